@@ -1,0 +1,238 @@
+"""ctypes binding of the plain FP64 CPU oracle (liboracle.so).
+
+TEST INFRASTRUCTURE ONLY: the tests, the smoke check and the benchmark's
+CPU-baseline leg import this package; the product library never does.
+The C source (ia_oracle.c) follows the paper's equations directly and
+shares no code with the HIP path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "ia_oracle.c")
+LIB = os.path.join(HERE, "liboracle.so")
+
+HIT_DTYPE = np.dtype([("x0", "f8"), ("y0", "f8"), ("z0", "f8"),
+                      ("x1", "f8"), ("y1", "f8"), ("z1", "f8"),
+                      ("drift", "f8"), ("band", "f8")])
+BOX_DTYPE = np.dtype([("lo", "f8", (5,)), ("hi", "f8", (5,))])
+PREP_DTYPE = np.dtype([("valid", "i4"), ("axial", "i4"), ("px", "f8"), ("py", "f8"),
+                       ("tant", "f8"), ("sphis", "f8"), ("cphis", "f8"), ("r", "f8"),
+                       ("phip", "f8"), ("r2lo", "f8"), ("r2hi", "f8"), ("d", "f8"),
+                       ("band", "f8")])
+SCHED_DTYPE = np.dtype([("range", BOX_DTYPE), ("bins", "i4", (5,)), ("n_refine", "i4"),
+                        ("top_k", "i4"), ("split", "i4", (5,)), ("v_min", "i4"),
+                        ("n_helix_max", "i4"), ("hitfind_scale", "f8")], align=True)
+HELIX_DTYPE = np.dtype([("p", "f8", (5,)), ("err", "f8", (5,)), ("votes", "i4"),
+                        ("n_assigned", "i4"), ("n_argmax", "i4"), ("pad", "i4")])
+MAX_LEVELS, MAX_K, MAX_PASSES = 8, 64, 16
+TRACE_DTYPE = np.dtype([("n_passes", "i4"),
+                        ("vmax", "i4", (MAX_PASSES, MAX_LEVELS)),
+                        ("n_argmax", "i4", (MAX_PASSES, MAX_LEVELS)),
+                        ("selected", BOX_DTYPE, (MAX_PASSES, MAX_LEVELS, MAX_K)),
+                        ("selected_index", "i8", (MAX_PASSES, MAX_LEVELS, MAX_K))], align=True)
+
+CFLAGS = ["-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
+          "-fopenmp", "-Wall", "-Wextra"]
+
+
+def build(force: bool = True) -> str:
+    """Compile liboracle.so with gcc (scalar, no FMA contraction)."""
+    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+        tmp = LIB + ".tmp"
+        subprocess.check_call(["gcc", *CFLAGS, "-o", tmp, SRC, "-lm"])
+        os.replace(tmp, LIB)
+    return LIB
+
+
+_lib = None
+_P = C.c_void_p
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+            build(force=True)
+        L = C.CDLL(LIB)
+        d, i32, i64 = C.c_double, C.c_int32, C.c_int64
+        L.or_sin.restype = d; L.or_sin.argtypes = [d]
+        L.or_cos.restype = d; L.or_cos.argtypes = [d]
+        L.or_atan2.restype = d; L.or_atan2.argtypes = [d, d]
+        L.or_wdn.restype = d; L.or_wdn.argtypes = [d]
+        L.or_wup.restype = d; L.or_wup.argtypes = [d]
+        L.or_sin_encl.restype = None; L.or_sin_encl.argtypes = [d, d, _P, _P]
+        L.or_imul.restype = None; L.or_imul.argtypes = [d, d, d, d, _P, _P]
+        L.or_isqr.restype = None; L.or_isqr.argtypes = [d, d, _P, _P]
+        L.or_prep_hit.restype = i32; L.or_prep_hit.argtypes = [_P, _P]
+        L.or_box_child.restype = None; L.or_box_child.argtypes = [_P, _P, i64, _P]
+        L.or_stereo_e.restype = i32; L.or_stereo_e.argtypes = [_P, _P, i32, _P, _P]
+        L.or_pair_vote.restype = i32; L.or_pair_vote.argtypes = [_P, _P, _P]
+        L.or_vote_level.restype = None
+        L.or_vote_level.argtypes = [_P, i32, _P, _P, i32, _P, _P, i32]
+        L.or_topk.restype = i32; L.or_topk.argtypes = [_P, i64, i32, _P, _P]
+        L.or_estimate.restype = i32
+        L.or_estimate.argtypes = [_P, i32, _P, _P, C.c_uint16, _P, _P]
+        L.or_find_helices.restype = i32
+        L.or_find_helices.argtypes = [_P, i32, _P, _P, i32, _P, _P, i32]
+        _lib = L
+    return _lib
+
+
+def _ptr(a):
+    return a.ctypes.data_as(_P) if a is not None else None
+
+
+def _c(a, dtype):
+    return np.ascontiguousarray(a, dtype=dtype)
+
+
+# ----------------------------------------------------------------------------
+# thin numpy wrappers
+# ----------------------------------------------------------------------------
+def sin(x):
+    return lib().or_sin(float(x))
+
+
+def cos(x):
+    return lib().or_cos(float(x))
+
+
+def atan2(y, x):
+    return lib().or_atan2(float(y), float(x))
+
+
+def wdn(x):
+    return lib().or_wdn(float(x))
+
+
+def wup(x):
+    return lib().or_wup(float(x))
+
+
+def sin_encl(a, b):
+    lo, hi = C.c_double(), C.c_double()
+    lib().or_sin_encl(float(a), float(b), C.byref(lo), C.byref(hi))
+    return lo.value, hi.value
+
+
+def imul(a, b):
+    lo, hi = C.c_double(), C.c_double()
+    lib().or_imul(float(a[0]), float(a[1]), float(b[0]), float(b[1]), C.byref(lo), C.byref(hi))
+    return lo.value, hi.value
+
+
+def isqr(a):
+    lo, hi = C.c_double(), C.c_double()
+    lib().or_isqr(float(a[0]), float(a[1]), C.byref(lo), C.byref(hi))
+    return lo.value, hi.value
+
+
+def prep_hits(hits):
+    hits = _c(hits, HIT_DTYPE)
+    out = np.zeros(hits.shape[0], dtype=PREP_DTYPE)
+    for i in range(hits.shape[0]):
+        lib().or_prep_hit(_ptr(hits[i:i + 1]), _ptr(out[i:i + 1]))
+    return out
+
+
+def make_box(lo, hi):
+    b = np.zeros((), dtype=BOX_DTYPE)
+    b["lo"] = lo
+    b["hi"] = hi
+    return b
+
+
+def box_child(parent, split, child):
+    parent = _c(np.atleast_1d(parent), BOX_DTYPE)
+    split = _c(split, np.int32)
+    out = np.zeros(1, dtype=BOX_DTYPE)
+    lib().or_box_child(_ptr(parent), _ptr(split), int(child), _ptr(out))
+    return out[0]
+
+
+def stereo_e(prep, c, s, debug=False):
+    prep = _c(np.atleast_1d(prep), PREP_DTYPE)
+    c = _c(c, np.float64)
+    e = np.zeros(1)
+    dbg = np.full(24, np.nan) if debug else None
+    ok = lib().or_stereo_e(_ptr(prep), _ptr(c), int(s), _ptr(e), _ptr(dbg))
+    if debug:
+        return bool(ok), float(e[0]), dbg
+    return bool(ok), float(e[0])
+
+
+STEREO_DEBUG_NAMES = ["R", "xc", "yc", "Dx", "Dy", "RAx", "cAx", "sAx", "sinA", "cosA", "dphi",
+                      "zA", "Phi1", "Phi2", "eps", "sinP", "cosP", "u", "delta", "sperp", "zS",
+                      "ctau", "Q", "dhat"]
+
+
+def pair_vote(prep, box, debug=False):
+    prep = _c(np.atleast_1d(prep), PREP_DTYPE)
+    box = _c(np.atleast_1d(box), BOX_DTYPE)
+    dbg = np.full(8, np.nan) if debug else None
+    v = lib().or_pair_vote(_ptr(prep), _ptr(box), _ptr(dbg))
+    return (int(v), dbg) if debug else int(v)
+
+
+def vote_level(hits, parents, split, active=None, n_threads=0):
+    hits = _c(hits, HIT_DTYPE)
+    parents = _c(np.atleast_1d(parents), BOX_DTYPE)
+    split = _c(split, np.int32)
+    nb = parents.shape[0] * int(np.prod(split.astype(np.int64)))
+    votes = np.zeros(nb, dtype=np.uint16)
+    act = None if active is None else _c(active, np.uint8)
+    lib().or_vote_level(_ptr(hits), hits.shape[0], _ptr(act), _ptr(parents), parents.shape[0],
+                        _ptr(split), _ptr(votes), int(n_threads))
+    return votes
+
+
+def topk(votes, k):
+    votes = _c(votes, np.uint16)
+    idx = np.zeros(max(k, 1), dtype=np.int64)
+    v = np.zeros(max(k, 1), dtype=np.uint16)
+    kk = lib().or_topk(_ptr(votes), votes.shape[0], int(k), _ptr(idx), _ptr(v))
+    return idx[:kk], v[:kk]
+
+
+def estimate(parents, split, votes, vmax):
+    parents = _c(np.atleast_1d(parents), BOX_DTYPE)
+    split = _c(split, np.int32)
+    votes = _c(votes, np.uint16)
+    p = np.zeros(5)
+    err = np.zeros(5)
+    n = lib().or_estimate(_ptr(parents), parents.shape[0], _ptr(split), _ptr(votes),
+                          int(vmax), _ptr(p), _ptr(err))
+    return p, err, int(n)
+
+
+def make_sched(lo, hi, bins, n_refine=4, top_k=32, split=(4, 4, 4, 4, 4), v_min=10,
+               n_helix_max=1, hitfind_scale=5.0):
+    s = np.zeros((), dtype=SCHED_DTYPE)
+    s["range"]["lo"] = lo
+    s["range"]["hi"] = hi
+    s["bins"] = bins
+    s["n_refine"] = n_refine
+    s["top_k"] = top_k
+    s["split"] = split
+    s["v_min"] = v_min
+    s["n_helix_max"] = n_helix_max
+    s["hitfind_scale"] = hitfind_scale
+    return s
+
+
+def find_helices(hits, sched, max_out=16, n_threads=0, want_trace=False):
+    hits = _c(hits, HIT_DTYPE)
+    sched = np.ascontiguousarray(np.atleast_1d(sched))
+    out = np.zeros(max_out, dtype=HELIX_DTYPE)
+    assigned = np.full(hits.shape[0], -1, dtype=np.int32)
+    trace = np.zeros(1, dtype=TRACE_DTYPE) if want_trace else None
+    n = lib().or_find_helices(_ptr(hits), hits.shape[0], _ptr(sched), _ptr(out), int(max_out),
+                              _ptr(assigned), _ptr(trace), int(n_threads))
+    res = (out[:n], assigned)
+    return res + (trace[0],) if want_trace else res

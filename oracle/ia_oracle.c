@@ -1,0 +1,547 @@
+/*
+ * ia_oracle.c -- plain FP64 CPU oracle of the interval-arithmetic helix vote.
+ *
+ * TEST INFRASTRUCTURE ONLY: loaded by the tests, the smoke check and the
+ * benchmark's CPU-baseline leg, never by the product path.  It shares no code
+ * with the HIP library.
+ *
+ * Build: -O2 -ffp-contract=off -fno-fast-math.  Every interval +, -, x result
+ * is computed round-to-nearest and then widened outward by
+ * |x| 2^-52 + 2^-1074 (at least one ulp), so enclosures are sound and the
+ * result is reproducible bit for bit; scaling by 2 or 1/2 and negation are
+ * exact and not widened.  sqrt and / are the IEEE correctly rounded ones.
+ * sin, cos and atan2 are written here (Cody-Waite reduction by pi/2 with a
+ * three-part constant, Taylor polynomials evaluated by Horner's rule with
+ * fused multiply-adds), so their results do not depend on the C library.
+ *
+ * Parity status of each function is stated at its definition.
+ */
+#include "ia_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* pi/2 split for Cody-Waite reduction: the first two parts carry 33
+ * significant bits, so k * part is exact for |k| < 2^20. */
+static const double TWO_OVER_PI = 0x1.45f306dc9c883p-1;
+static const double PIO2_1 = 0x1.921fb544p+0;
+static const double PIO2_2 = 0x1.0b4611a6p-34;
+static const double PIO2_3 = 0x1.3198a2e037073p-69;
+static const double PI_RN = 0x1.921fb54442d18p+1;      /* pi, rounded (below pi) */
+static const double TWO_PI_RN = 0x1.921fb54442d18p+2;  /* 2 pi, rounded (below 2 pi) */
+static const double PIO2_RN = 0x1.921fb54442d18p+0;
+static const double PIO6_RN = 0x1.0c152382d7366p-1;
+static const double SQRT3_RN = 0x1.bb67ae8584caap+0;
+static const double INV_TWO_PI = 0x1.45f306dc9c883p-3;
+static const double TAN_PI_12 = 0x1.126145e9ecd56p-2;  /* 2 - sqrt(3) */
+static const double SIN_MARGIN = 0x1p-50;  /* > 4x the measured error of or_sin */
+static const double EXT_FUZZ = 0x1p-40;    /* slack of the extremum test */
+
+/* ------------------------------------------------------------------------
+ * elementary functions (pinned against mpmath in the tests)
+ * ---------------------------------------------------------------------- */
+/* sin r on |r| <= pi/4: Taylor series to degree 17, coefficients 1/n! */
+static double sin_poly(double r) {
+  double z = r * r;
+  double p = 1.0 / 355687428096000.0;
+  p = fma(p, z, -1.0 / 1307674368000.0);
+  p = fma(p, z, 1.0 / 6227020800.0);
+  p = fma(p, z, -1.0 / 39916800.0);
+  p = fma(p, z, 1.0 / 362880.0);
+  p = fma(p, z, -1.0 / 5040.0);
+  p = fma(p, z, 1.0 / 120.0);
+  p = fma(p, z, -1.0 / 6.0);
+  return fma(r * z, p, r);
+}
+
+/* cos r on |r| <= pi/4: Taylor series to degree 16 */
+static double cos_poly(double r) {
+  double z = r * r;
+  double q = 1.0 / 20922789888000.0;
+  q = fma(q, z, -1.0 / 87178291200.0);
+  q = fma(q, z, 1.0 / 479001600.0);
+  q = fma(q, z, -1.0 / 3628800.0);
+  q = fma(q, z, 1.0 / 40320.0);
+  q = fma(q, z, -1.0 / 720.0);
+  q = fma(q, z, 1.0 / 24.0);
+  q = fma(q, z, -0.5);
+  return fma(z, q, 1.0);
+}
+
+/* x = k pi/2 + r with |r| <= pi/4 (plus rounding) */
+static double reduce_pio2(double x, int64_t *k_out) {
+  double k = rint(x * TWO_OVER_PI);
+  double r = ((x - k * PIO2_1) - k * PIO2_2) - k * PIO2_3;
+  *k_out = (int64_t)k;
+  return r;
+}
+
+double or_sin(double x) {
+  int64_t k;
+  double r = reduce_pio2(x, &k);
+  switch (k & 3) {
+    case 0: return sin_poly(r);
+    case 1: return cos_poly(r);
+    case 2: return -sin_poly(r);
+    default: return -cos_poly(r);
+  }
+}
+
+double or_cos(double x) {
+  int64_t k;
+  double r = reduce_pio2(x, &k);
+  switch (k & 3) {
+    case 0: return cos_poly(r);
+    case 1: return -sin_poly(r);
+    case 2: return -cos_poly(r);
+    default: return sin_poly(r);
+  }
+}
+
+/* atan u on |u| <= tan(pi/12): Taylor series to degree 29 */
+static double atan_poly(double u) {
+  double z = u * u;
+  double p = 1.0 / 29.0;
+  p = fma(p, z, -1.0 / 27.0);
+  p = fma(p, z, 1.0 / 25.0);
+  p = fma(p, z, -1.0 / 23.0);
+  p = fma(p, z, 1.0 / 21.0);
+  p = fma(p, z, -1.0 / 19.0);
+  p = fma(p, z, 1.0 / 17.0);
+  p = fma(p, z, -1.0 / 15.0);
+  p = fma(p, z, 1.0 / 13.0);
+  p = fma(p, z, -1.0 / 11.0);
+  p = fma(p, z, 1.0 / 9.0);
+  p = fma(p, z, -1.0 / 7.0);
+  p = fma(p, z, 1.0 / 5.0);
+  p = fma(p, z, -1.0 / 3.0);
+  return fma(u * z, p, u);
+}
+
+/* atan t on [0, 1]; above tan(pi/12) use atan t = pi/6 + atan((t sqrt3 - 1)/(t + sqrt3)) */
+static double atan_unit(double t) {
+  if (t > TAN_PI_12) return PIO6_RN + atan_poly((t * SQRT3_RN - 1.0) / (t + SQRT3_RN));
+  return atan_poly(t);
+}
+
+/* the angle of (x, y), in [-pi, pi]; 0 for the origin */
+double or_atan2(double y, double x) {
+  double ax = fabs(x), ay = fabs(y);
+  if (ax == 0.0 && ay == 0.0) return 0.0;
+  int swap = ay > ax;
+  double a = atan_unit(swap ? ax / ay : ay / ax);
+  if (swap) a = PIO2_RN - a;
+  if (x < 0.0) a = PI_RN - a;
+  if (y < 0.0) a = -a;
+  return a;
+}
+
+/* ------------------------------------------------------------------------
+ * interval arithmetic (Moore intervals, outward rounded)
+ * ---------------------------------------------------------------------- */
+double or_wdn(double x) { return x - fma(fabs(x), 0x1p-52, 0x1p-1074); }
+double or_wup(double x) { return x + fma(fabs(x), 0x1p-52, 0x1p-1074); }
+
+typedef struct { double lo, hi; } iv;
+
+static iv iv_add(iv a, iv b) { iv r = {or_wdn(a.lo + b.lo), or_wup(a.hi + b.hi)}; return r; }
+static iv iv_sub(iv a, iv b) { iv r = {or_wdn(a.lo - b.hi), or_wup(a.hi - b.lo)}; return r; }
+static iv iv_mul(iv a, iv b) {
+  double p1 = a.lo * b.lo, p2 = a.lo * b.hi, p3 = a.hi * b.lo, p4 = a.hi * b.hi;
+  iv r = {or_wdn(fmin(fmin(p1, p2), fmin(p3, p4))), or_wup(fmax(fmax(p1, p2), fmax(p3, p4)))};
+  return r;
+}
+static iv iv_sqr(iv a) {
+  double l2 = a.lo * a.lo, h2 = a.hi * a.hi;
+  iv r;
+  if (a.lo <= 0.0 && a.hi >= 0.0) { r.lo = 0.0; r.hi = or_wup(fmax(l2, h2)); }
+  else { r.lo = or_wdn(fmin(l2, h2)); r.hi = or_wup(fmax(l2, h2)); }
+  return r;
+}
+static iv iv_twice(iv a) { iv r = {2.0 * a.lo, 2.0 * a.hi}; return r; }
+static iv iv_point(double x) { iv r = {x, x}; return r; }
+
+void or_imul(double alo, double ahi, double blo, double bhi, double *lo, double *hi) {
+  iv a = {alo, ahi}, b = {blo, bhi}, r = iv_mul(a, b);
+  *lo = r.lo; *hi = r.hi;
+}
+void or_isqr(double alo, double ahi, double *lo, double *hi) {
+  iv a = {alo, ahi}, r = iv_sqr(a);
+  *lo = r.lo; *hi = r.hi;
+}
+
+/* Enclosure of sin over [a, b].  Between extrema sin is monotone, so the end
+ * values (less / plus a margin above the error of or_sin) bound it; an
+ * interval that may contain pi/2 + 2k pi (resp. -pi/2 + 2k pi) gets hi = 1
+ * (resp. lo = -1).  The membership test is fuzzed by 2^-40 so that rounding
+ * can only make it answer "contains". */
+void or_sin_encl(double a, double b, double *lo, double *hi) {
+  if (b - a >= TWO_PI_RN) { *lo = -1.0; *hi = 1.0; return; }
+  double va = or_sin(a), vb = or_sin(b);
+  double l = fmin(va, vb) - SIN_MARGIN, h = fmax(va, vb) + SIN_MARGIN;
+  if (floor((b - PIO2_RN) * INV_TWO_PI + EXT_FUZZ) >= ceil((a - PIO2_RN) * INV_TWO_PI - EXT_FUZZ)) h = 1.0;
+  if (floor((b + PIO2_RN) * INV_TWO_PI + EXT_FUZZ) >= ceil((a + PIO2_RN) * INV_TWO_PI - EXT_FUZZ)) l = -1.0;
+  if (l < -1.0) l = -1.0;
+  if (h > 1.0) h = 1.0;
+  *lo = l; *hi = h;
+}
+
+/* ------------------------------------------------------------------------
+ * hit preparation: the wire point at z = 0 and the stereo direction
+ * (Eqs. wirePar_a,b; Eqs. EQSinter_d,e with z_ref = 0)
+ * ---------------------------------------------------------------------- */
+int32_t or_prep_hit(const or_hit *h, or_prep *o) {
+  memset(o, 0, sizeof *o);
+  const double *f = &h->x0;
+  for (int i = 0; i < 8; i++) if (!isfinite(f[i])) return 0;
+  double dz = h->z1 - h->z0;
+  if (dz == 0.0 || h->drift < 0.0 || h->band < 0.0) return 0;
+  double tx = (h->x1 - h->x0) / dz, ty = (h->y1 - h->y0) / dz;
+  o->px = h->x0 - h->z0 * tx;
+  o->py = h->y0 - h->z0 * ty;
+  o->tant = sqrt(tx * tx + ty * ty);
+  if (!isfinite(o->px) || !isfinite(o->py) || !isfinite(o->tant)) return 0;
+  /* direction (sin phi_s, -cos phi_s) tan(tau) = (tx, ty) with tan(tau) >= 0 */
+  if (o->tant == 0.0) { o->sphis = 0.0; o->cphis = 1.0; o->axial = 1; }
+  else { o->sphis = tx / o->tant; o->cphis = -ty / o->tant; o->axial = 0; }
+  o->r = sqrt(o->px * o->px + o->py * o->py);
+  o->phip = or_atan2(o->py, o->px);
+  double r2 = o->r * o->r;
+  o->r2lo = or_wdn(r2);
+  o->r2hi = or_wup(r2);
+  o->d = h->drift;
+  o->band = h->band;
+  o->valid = 1;
+  return 1;
+}
+
+/* ------------------------------------------------------------------------
+ * boxes: regular split of a parent box (edges L + k w, last edge U)
+ * ---------------------------------------------------------------------- */
+void or_box_child(const or_box *par, const int32_t m[5], int64_t child, or_box *out) {
+  int64_t k[5], rem = child;
+  for (int j = 4; j >= 0; j--) { k[j] = rem % m[j]; rem /= m[j]; }
+  for (int j = 0; j < 5; j++) {
+    double L = par->lo[j], U = par->hi[j], w = (U - L) / (double)m[j];
+    out->lo[j] = L + (double)k[j] * w;
+    out->hi[j] = (k[j] + 1 == m[j]) ? U : L + (double)(k[j] + 1) * w;
+  }
+}
+
+/* ------------------------------------------------------------------------
+ * virtual drift distance d^Ax at a point of parameter space
+ * (Appendix A: Eqs. normudi, EQSinter_c, defdiAX_b, CSAXtoPHI_a's
+ * definitions and the second-order solution ApproxPhi, with z_ref = 0).
+ *
+ * Appendix A assumes R > 0.  A point with kappa < 0 is mirrored (y -> -y),
+ * which maps the helix to one with kappa > 0, d0 -> -d0, phi0 -> -phi0 and the
+ * wire to its mirror image; d^Ax is computed there and returned as
+ * e = sgn(kappa) d^Ax, the drift term of the kappa-scaled residual.
+ * ---------------------------------------------------------------------- */
+int32_t or_stereo_e(const or_prep *h, const double c[5], int32_t s, double *e, double *dbg) {
+  double kap = c[2], sig = 1.0;
+  if (kap < 0.0) sig = -1.0;
+  if (kap == 0.0) { kap = 0x1p-30; sig = 1.0; }
+  double dS = (double)s * h->d;               /* signed drift d^St */
+  if (h->axial) {                             /* tan(tau) = 0: d^Ax = d^St */
+    *e = sig * dS;
+    return 1;
+  }
+  double kp = sig * kap, d0p = sig * c[0];
+  double sp0 = sig * or_sin(c[1]), cp0 = or_cos(c[1]);
+  double R = 1.0 / kp;
+  double Rd = R + d0p;
+  double xc = -(Rd * sp0), yc = Rd * cp0;     /* circle centre (HelixEq_d) */
+  double py = sig * h->py, cps = sig * h->cphis, sps = h->sphis;
+  double Dx = h->px - xc, Dy = py - yc;
+  double RAx = sqrt(Dx * Dx + Dy * Dy);       /* R_i^Ax */
+  double cAx = Dx * sps - Dy * cps;           /* c_i^Ax */
+  double sAx = Dx * cps + Dy * sps;           /* s_i^Ax */
+  double sinA = sAx / RAx, cosA = cAx / RAx;  /* sin, cos of Phi_i^Ax */
+  /* phi_i^Ax - phi0, wrapped to [-pi, pi] */
+  double dphi = or_atan2(Dx * cp0 + Dy * sp0, Dx * sp0 - Dy * cp0);
+  double z0 = c[3], lam = c[4], tt = h->tant;
+  double sArc = R * dphi;                     /* transverse arc length to the axial point */
+  double zA = z0 + lam * sArc;                /* z_i^Ax (ApproxPhi_d) */
+  /* first- and second-order terms of Phi_i (ApproxPhi_b, ApproxPhi_c) */
+  double Phi1 = -(zA * sinA + (lam * dS) * cosA) / RAx;
+  double c2 = cosA * cosA - sinA * sinA;      /* cos 2 Phi^Ax */
+  double s2 = 2.0 * sinA * cosA;              /* sin 2 Phi^Ax */
+  double Phi2n = (lam * R) * zA - ((lam * zA) * (R - 2.0 * dS)) * c2
+               + (zA * zA + dS * (RAx + (lam * lam) * ((R + RAx) - dS))) * s2;
+  double Phi2 = Phi2n / (2.0 * (RAx * RAx));
+  double t2 = tt * tt;
+  double eps = Phi1 * tt + Phi2 * t2;         /* Phi_i - Phi_i^Ax (ApproxPhi) */
+  double se = or_sin(eps), ce = or_cos(eps);
+  double sinP = sinA * ce + cosA * se, cosP = cosA * ce - sinA * se;
+  /* norm of the drift direction (normudi) */
+  double u = sqrt(((1.0 + ((2.0 * lam) * sinP) * tt) + (lam * lam) * t2) + (cosP * cosP) * t2);
+  double delta = dS / u;
+  double sperp = R * (dphi + eps);            /* rho s_perp = Phi + phi_s - phi0 */
+  double zS = (z0 + lam * sperp) - (delta * cosP) * tt;   /* z_i^St (EQSinter_c) */
+  double ctau = zS * cAx - (lam * delta) * sAx;           /* c_i^tau */
+  double a1 = zS * tt, a2 = (lam * delta) * tt;
+  double Q = ((2.0 * ctau) * tt + a1 * a1) + a2 * a2;
+  double A = R + delta;
+  double disc = A * A - Q;
+  if (!(disc >= 0.0)) return 0;
+  /* d^Ax = sqrt((R + delta)^2 - Q) - R  (defdiAX_b), written without cancellation */
+  double dhat = delta - Q / (A + sqrt(disc));
+  if (dbg) {
+    double v[24] = {R, xc, yc, Dx, Dy, RAx, cAx, sAx, sinA, cosA, dphi, zA, Phi1, Phi2,
+                    eps, sinP, cosP, u, delta, sperp, zS, ctau, Q, dhat};
+    memcpy(dbg, v, sizeof v);
+  }
+  *e = sig * dhat;
+  return isfinite(*e) ? 1 : 0;
+}
+
+/* ------------------------------------------------------------------------
+ * the vote predicate, Eq. ApoVote, multiplied by kappa:
+ *   kappa F = 2 G - 2 e - kappa e^2,
+ *   G = (kappa/2)(r^2 + d0^2) + (1 + kappa d0) r sin(phi0 - phiP) + d0,
+ * which is kappa (|P - C|^2 - R^2) / 2 in perigee variables.  G is enclosed
+ * over the whole box; e is the point value at the middle of the box for each
+ * drift sign; one vote when zero is enclosed for either sign.
+ * ---------------------------------------------------------------------- */
+int32_t or_pair_vote(const or_prep *h, const or_box *b, double *dbg) {
+  if (!h->valid) return 0;
+  iv K = {b->lo[2], b->hi[2]}, Dd = {b->lo[0], b->hi[0]};
+  iv Ar = {or_wdn(b->lo[1] - h->phip), or_wup(b->hi[1] - h->phip)};
+  iv S;
+  or_sin_encl(Ar.lo, Ar.hi, &S.lo, &S.hi);
+  iv rS = iv_mul(S, iv_point(h->r));
+  iv D2 = iv_sqr(Dd);
+  iv T0 = iv_add(D2, (iv){h->r2lo, h->r2hi});
+  iv T = {0.5 * T0.lo, 0.5 * T0.hi};
+  iv KT = iv_mul(K, T);
+  iv KD1 = iv_add(iv_mul(K, Dd), iv_point(1.0));
+  iv G = iv_add(iv_add(KT, iv_mul(KD1, rS)), Dd);
+  double c[5];
+  for (int j = 0; j < 5; j++) c[j] = 0.5 * (b->lo[j] + b->hi[j]);
+  int32_t vote = 0;
+  if (dbg) { dbg[0] = G.lo; dbg[1] = G.hi; for (int j = 2; j < 8; j++) dbg[j] = NAN; }
+  for (int32_t si = 0; si < 2; si++) {
+    int32_t s = si == 0 ? 1 : -1;
+    double e;
+    if (!or_stereo_e(h, c, s, &e, NULL)) continue;
+    iv E = {or_wdn(e - h->band), or_wup(e + h->band)};
+    iv H = iv_sub(iv_twice(G), iv_add(iv_twice(E), iv_mul(K, iv_sqr(E))));
+    if (dbg) { dbg[2 + 2 * si] = H.lo; dbg[3 + 2 * si] = H.hi; dbg[6 + si] = e; }
+    if (H.lo <= 0.0 && 0.0 <= H.hi) vote = 1;
+  }
+  return vote;
+}
+
+/* ------------------------------------------------------------------------
+ * one accumulator level: votes of all active valid hits for every box
+ * ---------------------------------------------------------------------- */
+static int64_t prod5(const int32_t m[5]) {
+  int64_t p = 1;
+  for (int j = 0; j < 5; j++) p *= m[j];
+  return p;
+}
+
+static void vote_prepped(const or_prep *pr, const uint8_t *use, int32_t n_hits,
+                         const or_box *parents, int32_t n_parents, const int32_t split[5],
+                         uint16_t *votes, int32_t n_threads) {
+  int64_t nc = prod5(split), nb = (int64_t)n_parents * nc;
+#ifdef _OPENMP
+  int nt = n_threads > 0 ? n_threads : omp_get_max_threads();
+#pragma omp parallel for schedule(dynamic, 256) num_threads(nt)
+#endif
+  for (int64_t b = 0; b < nb; b++) {
+    or_box box;
+    or_box_child(&parents[b / nc], split, b % nc, &box);
+    int32_t v = 0;
+    for (int32_t i = 0; i < n_hits; i++)
+      if (use[i]) v += or_pair_vote(&pr[i], &box, NULL);
+    votes[b] = (uint16_t)v;
+  }
+  (void)n_threads;
+}
+
+void or_vote_level(const or_hit *hits, int32_t n_hits, const uint8_t *active,
+                   const or_box *parents, int32_t n_parents, const int32_t split[5],
+                   uint16_t *votes, int32_t n_threads) {
+  or_prep *pr = (or_prep *)calloc((size_t)(n_hits > 0 ? n_hits : 1), sizeof *pr);
+  uint8_t *use = (uint8_t *)calloc((size_t)(n_hits > 0 ? n_hits : 1), 1);
+  for (int32_t i = 0; i < n_hits; i++)
+    use[i] = (uint8_t)(or_prep_hit(&hits[i], &pr[i]) && (!active || active[i]));
+  vote_prepped(pr, use, n_hits, parents, n_parents, split, votes, n_threads);
+  free(pr);
+  free(use);
+}
+
+/* ------------------------------------------------------------------------
+ * selection of the max-vote boxes: full sort by (votes desc, index asc)
+ * ---------------------------------------------------------------------- */
+typedef struct { uint16_t v; int64_t idx; } vi_pair;
+
+static int cmp_vi(const void *a, const void *b) {
+  const vi_pair *x = (const vi_pair *)a, *y = (const vi_pair *)b;
+  if (x->v != y->v) return x->v > y->v ? -1 : 1;
+  return x->idx < y->idx ? -1 : (x->idx > y->idx ? 1 : 0);
+}
+
+int32_t or_topk(const uint16_t *votes, int64_t n_boxes, int32_t k, int64_t *out_index,
+                uint16_t *out_votes) {
+  if (n_boxes <= 0 || k <= 0) return 0;
+  vi_pair *a = (vi_pair *)malloc((size_t)n_boxes * sizeof *a);
+  for (int64_t b = 0; b < n_boxes; b++) { a[b].v = votes[b]; a[b].idx = b; }
+  qsort(a, (size_t)n_boxes, sizeof *a, cmp_vi);
+  int32_t kk = (int64_t)k < n_boxes ? k : (int32_t)n_boxes;
+  for (int32_t i = 0; i < kk; i++) { out_index[i] = a[i].idx; out_votes[i] = a[i].v; }
+  free(a);
+  return kk;
+}
+
+/* ------------------------------------------------------------------------
+ * estimate from the selected max-vote cells (Sec. 3.3): the mean of their
+ * centres (phi0 taken relative to the first cell's centre, in (-pi, pi]) and
+ * half the extent of their union as the error.  Sums run over the level's
+ * boxes in index order by pairwise summation on a zero-padded power-of-two
+ * array (cells that are not maximal contribute zero).
+ * ---------------------------------------------------------------------- */
+static double pairwise_sum(double *a, int64_t p2) {
+  for (int64_t n = p2; n > 1; n >>= 1)
+    for (int64_t i = 0; i < n / 2; i++) a[i] = a[2 * i] + a[2 * i + 1];
+  return a[0];
+}
+
+int32_t or_estimate(const or_box *parents, int32_t n_parents, const int32_t split[5],
+                    const uint16_t *votes, uint16_t vmax, double p[5], double err[5]) {
+  int64_t nc = prod5(split), nb = (int64_t)n_parents * nc, p2 = 1;
+  while (p2 < nb) p2 <<= 1;
+  double *acc[5];
+  for (int j = 0; j < 5; j++) acc[j] = (double *)calloc((size_t)p2, sizeof(double));
+  double lo_min[5], hi_max[5], c0 = 0.0;
+  for (int j = 0; j < 5; j++) { lo_min[j] = INFINITY; hi_max[j] = -INFINITY; }
+  int32_t count = 0;
+  for (int64_t b = 0; b < nb; b++) {
+    if (votes[b] != vmax) continue;
+    or_box box;
+    or_box_child(&parents[b / nc], split, b % nc, &box);
+    if (count == 0) c0 = 0.5 * (box.lo[1] + box.hi[1]);
+    for (int j = 0; j < 5; j++) {
+      double c = 0.5 * (box.lo[j] + box.hi[j]), lo = box.lo[j], hi = box.hi[j];
+      if (j == 1) {
+        double dv = c - c0, shift = 0.0;
+        if (dv > PI_RN) shift = -TWO_PI_RN;
+        else if (dv <= -PI_RN) shift = TWO_PI_RN;
+        acc[j][b] = dv + shift;
+        lo = lo + shift;
+        hi = hi + shift;
+      } else {
+        acc[j][b] = c;
+      }
+      lo_min[j] = fmin(lo_min[j], lo);
+      hi_max[j] = fmax(hi_max[j], hi);
+    }
+    count++;
+  }
+  for (int j = 0; j < 5; j++) {
+    double S = pairwise_sum(acc[j], p2);
+    if (count == 0) { p[j] = NAN; err[j] = NAN; continue; }
+    if (j == 1) {
+      double v = c0 + S / (double)count;
+      if (v < 0.0) v += TWO_PI_RN;
+      if (v >= TWO_PI_RN) v -= TWO_PI_RN;
+      p[j] = v;
+    } else {
+      p[j] = S / (double)count;
+    }
+    err[j] = 0.5 * (hi_max[j] - lo_min[j]);
+  }
+  for (int j = 0; j < 5; j++) free(acc[j]);
+  return count;
+}
+
+/* ------------------------------------------------------------------------
+ * the search for one event (Sec. 3.3): coarse vote, max-cell refinement,
+ * estimate, hit finding with the box estimate +- scale x error; repeated on
+ * the hits not yet assigned for several helices.
+ * ---------------------------------------------------------------------- */
+int32_t or_find_helices(const or_hit *hits, int32_t n_hits, const or_sched *sc,
+                        or_helix *out, int32_t max_out, int32_t *assigned,
+                        or_trace *trace, int32_t n_threads) {
+  int32_t nh1 = n_hits > 0 ? n_hits : 1;
+  or_prep *pr = (or_prep *)calloc((size_t)nh1, sizeof *pr);
+  uint8_t *act = (uint8_t *)calloc((size_t)nh1, 1);
+  for (int32_t i = 0; i < n_hits; i++) {
+    act[i] = (uint8_t)or_prep_hit(&hits[i], &pr[i]);
+    if (assigned) assigned[i] = -1;
+  }
+  int64_t nb0 = prod5(sc->bins), nbr = (int64_t)sc->top_k * prod5(sc->split);
+  int64_t nbmax = nb0 > nbr ? nb0 : nbr;
+  uint16_t *votes = (uint16_t *)malloc((size_t)nbmax * sizeof(uint16_t));
+  int32_t kmax = sc->top_k;
+  or_box *par = (or_box *)malloc((size_t)(kmax > 1 ? kmax : 1) * sizeof(or_box));
+  or_box *nxt = (or_box *)malloc((size_t)(kmax > 1 ? kmax : 1) * sizeof(or_box));
+  int64_t *tidx = (int64_t *)malloc((size_t)(kmax > 1 ? kmax : 1) * sizeof(int64_t));
+  uint16_t *tv = (uint16_t *)malloc((size_t)(kmax > 1 ? kmax : 1) * sizeof(uint16_t));
+  if (trace) memset(trace, 0, sizeof *trace);
+  int32_t nh = 0;
+  for (int32_t pass = 0; pass < sc->n_helix_max && nh < max_out; pass++) {
+    int32_t n_par = 1, split[5];
+    par[0] = sc->range;
+    memcpy(split, sc->bins, sizeof split);
+    uint16_t vmax = 0;
+    for (int32_t lev = 0; lev <= sc->n_refine; lev++) {
+      vote_prepped(pr, act, n_hits, par, n_par, split, votes, n_threads);
+      int64_t nb = (int64_t)n_par * prod5(split);
+      int32_t k = or_topk(votes, nb, sc->top_k, tidx, tv);
+      vmax = k > 0 ? tv[0] : 0;
+      if (trace && pass < OR_MAX_PASSES && lev < OR_MAX_LEVELS) {
+        trace->n_passes = pass + 1;
+        trace->vmax[pass][lev] = vmax;
+        int32_t na = 0;
+        for (int64_t b = 0; b < nb; b++) na += votes[b] == vmax;
+        trace->n_argmax[pass][lev] = na;
+        for (int32_t i = 0; i < k && i < OR_MAX_K; i++) {
+          trace->selected_index[pass][lev][i] = tidx[i];
+          or_box_child(&par[tidx[i] / prod5(split)], split, tidx[i] % prod5(split),
+                       &trace->selected[pass][lev][i]);
+        }
+      }
+      if (lev == 0 && vmax < sc->v_min) break;
+      if (lev == sc->n_refine) break;
+      /* the selected boxes become the parents of the next level */
+      int64_t nc = prod5(split);
+      for (int32_t i = 0; i < k; i++) or_box_child(&par[tidx[i] / nc], split, tidx[i] % nc, &nxt[i]);
+      for (int32_t i = 0; i < k; i++) par[i] = nxt[i];
+      n_par = k;
+      memcpy(split, sc->split, sizeof split);
+    }
+    if (vmax < sc->v_min) break;
+    or_helix hx;
+    memset(&hx, 0, sizeof hx);
+    hx.n_argmax = or_estimate(par, n_par, split, votes, vmax, hx.p, hx.err);
+    hx.votes = vmax;
+    /* hit finding: every still-active hit voting for estimate +- scale x error */
+    or_box E;
+    for (int j = 0; j < 5; j++) {
+      double w = sc->hitfind_scale * hx.err[j];
+      E.lo[j] = hx.p[j] - w;
+      E.hi[j] = hx.p[j] + w;
+    }
+    int32_t na = 0;
+    for (int32_t i = 0; i < n_hits; i++) {
+      if (!act[i]) continue;
+      if (or_pair_vote(&pr[i], &E, NULL)) {
+        act[i] = 0;
+        if (assigned) assigned[i] = nh;
+        na++;
+      }
+    }
+    hx.n_assigned = na;
+    out[nh++] = hx;
+    if (na == 0) break;
+  }
+  free(pr); free(act); free(votes); free(par); free(nxt); free(tidx); free(tv);
+  return nh;
+}

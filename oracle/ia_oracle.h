@@ -1,0 +1,115 @@
+/*
+ * ia_oracle.h -- plain FP64 CPU oracle of the interval-arithmetic helix vote.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test-suite, the smoke check and the
+ * benchmark's CPU-baseline leg may load this library.  The product path
+ * (libia, the HIP kernels) shares no code with it and never calls it.
+ *
+ * It follows "GPU-accelerated Interval Arithmetic to solve the Apollonius
+ * Problem applied to a Stereo Drift Chamber" (da Silva, Lebrun, Angelique,
+ * Del Buono):
+ *   - the helix model, Eqs. HelixEq_a-d (Sec. 2.2), in perigee form;
+ *   - the stereo wire and the virtual drift distance d^Ax, Appendix A
+ *     (Eqs. wirePar, normudi, EQSinter, defdiAX_b, ApproxPhi);
+ *   - the interval vote predicate, Eq. ApoVote (Sec. 3.1), with d^Ax taken
+ *     at the middle of the voxel (Sec. 3.1, last paragraph);
+ *   - the iterative max-cell refinement, the estimate from the selected
+ *     voxels and the hit finding (Sec. 3.3).
+ * Units: m, rad, 1/m.  Box dimension order: d0, phi0, kappa, z0, tanl.
+ */
+#ifndef IA_ORACLE_H
+#define IA_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct { double x0, y0, z0, x1, y1, z1, drift, band; } or_hit;
+typedef struct { double lo[5], hi[5]; } or_box;
+
+/* per-hit constants (Eqs. wirePar_a,b and EQSinter_d,e with z_ref = 0) */
+typedef struct {
+  int32_t valid, axial;
+  double px, py;        /* wire point at z = 0 */
+  double tant;          /* tan(tau) >= 0 */
+  double sphis, cphis;  /* sin, cos of the wire projection angle phi_s */
+  double r, phip;       /* polar form of (px, py); (r, phip) define the hit point */
+  double r2lo, r2hi;    /* outward enclosure of r*r */
+  double d, band;       /* drift radius and tolerance half-width */
+} or_prep;
+
+typedef struct {
+  or_box range; int32_t bins[5];          /* level-0 regular grid */
+  int32_t n_refine, top_k, split[5];      /* refinement schedule */
+  int32_t v_min, n_helix_max;             /* multi-helix stop rules */
+  double hitfind_scale;                   /* half-width of the hit-finding box in errors */
+} or_sched;
+
+typedef struct {
+  double p[5], err[5];
+  int32_t votes, n_assigned, n_argmax, pad;
+} or_helix;
+
+#define OR_MAX_LEVELS 8
+#define OR_MAX_K 64
+#define OR_MAX_PASSES 16
+typedef struct {
+  int32_t n_passes;
+  int32_t vmax[OR_MAX_PASSES][OR_MAX_LEVELS];
+  int32_t n_argmax[OR_MAX_PASSES][OR_MAX_LEVELS];
+  or_box selected[OR_MAX_PASSES][OR_MAX_LEVELS][OR_MAX_K];
+  int64_t selected_index[OR_MAX_PASSES][OR_MAX_LEVELS][OR_MAX_K];
+} or_trace;
+
+/* elementary functions written for the oracle (Cody-Waite + Taylor) */
+double or_sin(double x);
+double or_cos(double x);
+double or_atan2(double y, double x);
+/* outward widening of a round-to-nearest result */
+double or_wdn(double x);
+double or_wup(double x);
+/* interval enclosure of sin over [a, b] */
+void or_sin_encl(double a, double b, double *lo, double *hi);
+/* interval product (4-product rule) and square, for the tests */
+void or_imul(double alo, double ahi, double blo, double bhi, double *lo, double *hi);
+void or_isqr(double alo, double ahi, double *lo, double *hi);
+
+int32_t or_prep_hit(const or_hit *h, or_prep *out);
+void or_box_child(const or_box *parent, const int32_t split[5], int64_t child, or_box *out);
+
+/* d^Ax at the point c for drift sign s (+1 / -1).  Returns 1 and writes
+ * e = sgn(kappa) d^Ax (the signed-kappa frame), or 0 when the square root of
+ * Eq. defdiAX_b has a negative argument.  dbg (nullable, 24 doubles) receives
+ * intermediates: see the source. */
+int32_t or_stereo_e(const or_prep *h, const double c[5], int32_t s, double *e, double *dbg);
+
+/* Eq. ApoVote for one (box, hit): returns 1 when zero lies in the enclosure for
+ * either drift sign.  dbg (nullable, 8 doubles): G lo/hi, H+ lo/hi, H- lo/hi,
+ * e+, e-. */
+int32_t or_pair_vote(const or_prep *h, const or_box *b, double *dbg);
+
+/* votes[parent * prod(split) + child] for every child box of every parent.
+ * active (nullable) masks hits. */
+void or_vote_level(const or_hit *hits, int32_t n_hits, const uint8_t *active,
+                   const or_box *parents, int32_t n_parents, const int32_t split[5],
+                   uint16_t *votes, int32_t n_threads);
+
+/* the first k boxes by (votes desc, index asc); returns k actually taken */
+int32_t or_topk(const uint16_t *votes, int64_t n_boxes, int32_t k,
+                int64_t *out_index, uint16_t *out_votes);
+
+/* estimate from the max-vote boxes of a level (Sec. 3.3) */
+int32_t or_estimate(const or_box *parents, int32_t n_parents, const int32_t split[5],
+                    const uint16_t *votes, uint16_t vmax, double p[5], double err[5]);
+
+/* the whole search for one event; returns the number of helices written.
+ * assigned (nullable, n_hits) receives the helix index of each hit or -1. */
+int32_t or_find_helices(const or_hit *hits, int32_t n_hits, const or_sched *sched,
+                        or_helix *out, int32_t max_out, int32_t *assigned,
+                        or_trace *trace, int32_t n_threads);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
