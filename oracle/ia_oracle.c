@@ -491,6 +491,7 @@ int32_t or_find_helices(const or_hit *hits, int32_t n_hits, const or_sched *sc,
     par[0] = sc->range;
     memcpy(split, sc->bins, sizeof split);
     uint16_t vmax = 0;
+    int32_t stop = 0;
     for (int32_t lev = 0; lev <= sc->n_refine; lev++) {
       vote_prepped(pr, act, n_hits, par, n_par, split, votes, n_threads);
       int64_t nb = (int64_t)n_par * prod5(split);
@@ -508,7 +509,7 @@ int32_t or_find_helices(const or_hit *hits, int32_t n_hits, const or_sched *sc,
                        &trace->selected[pass][lev][i]);
         }
       }
-      if (lev == 0 && vmax < sc->v_min) break;
+      if (lev == 0 && vmax < sc->v_min) { stop = 1; break; }   /* too few votes for a helix */
       if (lev == sc->n_refine) break;
       /* the selected boxes become the parents of the next level */
       int64_t nc = prod5(split);
@@ -517,7 +518,7 @@ int32_t or_find_helices(const or_hit *hits, int32_t n_hits, const or_sched *sc,
       n_par = k;
       memcpy(split, sc->split, sizeof split);
     }
-    if (vmax < sc->v_min) break;
+    if (stop) break;
     or_helix hx;
     memset(&hx, 0, sizeof hx);
     hx.n_argmax = or_estimate(par, n_par, split, votes, vmax, hx.p, hx.err);

@@ -133,3 +133,17 @@ def test_invalid_hits_never_vote(orc):
     v2 = orc.vote_level(both, orc.make_box(H.LO, H.HI), [5] * 5)
     assert np.array_equal(v1, v2)
     assert orc.prep_hits(bad)["valid"].sum() == 0
+
+
+def test_driver_stop_rule_applies_to_level0(orc):
+    """The greedy loop stops only when the level-0 maximum is below v_min; a
+    lower maximum at a refinement level still records the helix."""
+    ev = toymc.config_event(1, 2)
+    kw = dict(bins=[6] * 5, n_refine=2, top_k=4, split=[2] * 5, n_helix_max=3)
+    hel, ass, tr = orc.find_helices(ev.hits, orc.make_sched(H.LO, H.HI, v_min=10, **kw), want_trace=True)
+    assert tr["vmax"][0][0] >= 10 and len(hel) >= 1
+    assert hel[0]["votes"] == tr["vmax"][0][2]
+    assert (ass >= 0).sum() == sum(h["n_assigned"] for h in hel)
+    # a level-0 maximum below v_min records nothing
+    hel2, ass2 = orc.find_helices(ev.hits, orc.make_sched(H.LO, H.HI, v_min=ev.n_hits + 1, **kw))
+    assert len(hel2) == 0 and (ass2 == -1).all()
