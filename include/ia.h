@@ -1,0 +1,181 @@
+/*
+ * ia.h -- C ABI of libia, the MI355X (gfx950) interval-arithmetic helix vote.
+ *
+ * Method: da Silva, Lebrun, Angelique, Del Buono, "GPU-accelerated Interval
+ * Arithmetic to solve the Apollonius Problem applied to a Stereo Drift
+ * Chamber".  Every hit -- a drift radius and the two end points of its wire
+ * (Sec. 3.2) -- votes for each box of helix-parameter space whose interval
+ * enclosure of the Apollonius tangency condition (Eq. ApoVote, with the
+ * stereo virtual drift distance d^Ax of Eq. defdiAX_b taken at the middle of
+ * the box, Sec. 3.1) contains zero, for either drift sign.  The max-vote
+ * boxes are selected, subdivided and voted again level by level (Sec. 3.3).
+ *
+ * Parameters (SI units: m, rad, 1/m), always in this order:
+ *   d0     signed distance of closest approach to the z axis
+ *   phi0   direction of travel at that point, [0, 2 pi)
+ *   kappa  signed curvature 1/R, > 0 for counter-clockwise seen from +z
+ *   z0     z at the point of closest approach
+ *   tanl   dz / ds_perp (the paper's lambda)
+ * The transverse circle has centre (1/kappa + d0)(-sin phi0, cos phi0).
+ *
+ * Box order: a level is n_parents parent boxes each split regularly by
+ * split[5]; box b = parent * prod(split) + child with the child index
+ * lexicographic (d0 slowest, tanl fastest).  Child edges along a dimension
+ * with range [L, U] and m parts are L + k (U - L)/m, and the last edge is U.
+ * A level-0 grid is the case n_parents = 1, parent = the search range.
+ *
+ * Conventions shared by every entry point:
+ *  - Pointers named d_* are device memory owned by the caller; the library
+ *    never frees them.  h_* and plain struct pointers are host memory, read
+ *    during the call.
+ *  - Work is enqueued on `stream` (a hipStream_t, passed as void *); the calls
+ *    return without waiting.  One context must be used by one stream at a
+ *    time: its scratch is reused by every call.
+ *  - The return value reports errors the host can see (null pointers, sizes,
+ *    scratch too small, HIP launch failures).  Problems found on the device
+ *    (malformed hits, a vote above the bound) are recorded in the context and
+ *    read with ia_ctx_status() after the stream has been synchronised.
+ *    Malformed hits (non-finite values, z0 == z1, drift < 0, band < 0) never
+ *    vote; they are counted, not fatal.
+ *  - No entry point allocates device memory except ia_ctx_create.
+ *  - Results are deterministic: integer votes and fixed reduction orders do
+ *    not depend on launch shapes or on other work on the device.
+ */
+#ifndef IA_H
+#define IA_H
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  IA_OK = 0,
+  IA_ERR_INVALID = 1,      /* bad argument */
+  IA_ERR_NOMEM = 2,        /* context scratch too small for the request */
+  IA_ERR_DEVICE = 3,       /* a HIP call failed */
+  IA_ERR_UNSUPPORTED = 4,  /* valid request this build does not implement */
+  IA_ERR_OVERFLOW = 5      /* a size does not fit the index types */
+} ia_status;
+
+typedef enum { IA_FP64 = 0, IA_FP32 = 1 } ia_precision;
+
+/* one hit: wire end points (z0 != z1), measured drift radius >= 0 and the
+ * tolerance half-width added on both sides of the drift (0 = exact) */
+typedef struct { double x0, y0, z0, x1, y1, z1, drift, band; } ia_hit;
+
+typedef struct { double lo[5], hi[5]; } ia_box;
+
+/* estimate from the max-vote boxes of a level (Sec. 3.3) */
+typedef struct {
+  double p[5];        /* mean of the box centres; phi0 taken relative to the
+                         first max-vote box's centre in (-pi, pi], wrapped to [0, 2 pi) */
+  double err[5];      /* half the extent of the union of the max-vote boxes */
+  int32_t vmax;       /* the maximum vote */
+  int32_t n_argmax;   /* number of boxes with vmax votes */
+} ia_estimate_t;
+
+typedef struct {
+  double p[5], err[5];  /* estimate at the last level */
+  int32_t votes;        /* max vote at the last level */
+  int32_t n_assigned;   /* hits assigned to this helix by hit finding */
+  int32_t n_argmax;     /* boxes sharing the max vote at the last level */
+  int32_t status;       /* 0 */
+} ia_helix;
+
+#define IA_MAX_LEVELS 8
+
+/* the search schedule of ia_find_helices */
+typedef struct {
+  ia_box range;           /* level-0 search range */
+  int32_t bins[5];        /* level-0 grid */
+  int32_t n_refine;       /* refinement levels after level 0 (< IA_MAX_LEVELS) */
+  int32_t top_k;          /* boxes kept per level, by (votes desc, index asc) */
+  int32_t split[5];       /* split of every kept box at the next level */
+  int32_t v_min;          /* stop when the level-0 max vote is below this */
+  int32_t n_helix_max;    /* helices searched per event (greedy, hits removed) */
+  double hitfind_scale;   /* hit-finding box = estimate +- scale x error (5 in Sec. 3.3) */
+  int32_t prec[IA_MAX_LEVELS];  /* arithmetic per level (IA_FP64 or IA_FP32) */
+  double fp32_slack;      /* extra tolerance added to the band at FP32 levels */
+} ia_schedule;
+
+typedef struct ia_ctx ia_ctx;
+
+/* Create a context on HIP device `device` owning `scratch_bytes` of device
+ * scratch, the only device allocation the library makes.  On error *out is
+ * NULL.  ia_ctx_scratch_needed() gives the size a workload needs. */
+ia_status ia_ctx_create(ia_ctx **out, int32_t device, size_t scratch_bytes);
+void ia_ctx_destroy(ia_ctx *ctx);
+
+/* Message of the last host-side error on this context ("" if none). */
+const char *ia_last_error(const ia_ctx *ctx);
+
+/* Device-detected conditions since the last clear: flags bit 0 = malformed
+ * hits seen (their number in *n_bad_hits), bit 1 = a vote above the bound
+ * given to ia_refine.  Synchronises the device.  Either pointer may be NULL. */
+ia_status ia_ctx_status(ia_ctx *ctx, uint32_t *flags, int64_t *n_bad_hits);
+ia_status ia_ctx_clear_status(ia_ctx *ctx);
+
+/* Kernel timing: while enabled, every launch of the vote kernel made through
+ * this context is bracketed by HIP events on its stream.
+ * ia_ctx_profile_read() synchronises the device, returns the number of
+ * bracketed launches and their summed duration in milliseconds, and clears
+ * the record.  Creating the events is the only host-side cost. */
+ia_status ia_ctx_set_profiling(ia_ctx *ctx, int32_t enable);
+ia_status ia_ctx_profile_read(ia_ctx *ctx, int64_t *n_launches, double *total_ms);
+
+/* Scratch bytes needed by ia_find_helices for events of at most max_hits
+ * hits under `sched`. */
+size_t ia_ctx_scratch_needed(const ia_schedule *sched, int32_t max_hits);
+
+/* One accumulator level (Eq. ApoVote over every box; Sec. 3.1).
+ *   d_hits    n_hits hits (n_hits in [0, 65535])
+ *   d_active  NULL or n_hits bytes; 0 excludes a hit
+ *   d_parents n_parents boxes (lo <= hi in every dimension)
+ *   split     host int32[5], each >= 1
+ *   prec      IA_FP64 (IA_FP32 returns IA_ERR_UNSUPPORTED in this build)
+ *   d_votes   n_parents * prod(split) uint16, written: number of active,
+ *             well-formed hits voting for each box
+ * Scratch: 96 bytes per hit. */
+ia_status ia_vote_level(ia_ctx *ctx, const ia_hit *d_hits, int32_t n_hits, const uint8_t *d_active,
+                        const ia_box *d_parents, int32_t n_parents, const int32_t split[5],
+                        ia_precision prec, uint16_t *d_votes, void *stream);
+
+/* Selection of the max-vote boxes of a level (Sec. 3.3): the first
+ * min(top_k, n_boxes) boxes by (votes desc, box index asc), in that order.
+ *   d_votes           n_boxes = n_parents * prod(split) votes, each <= vote_bound
+ *   d_selected        written: the selected boxes' extents (next level's parents)
+ *   d_selected_index  written: their box indices (int64)
+ *   d_selected_votes  written: their votes
+ * top_k in [1, 4096].  Votes above vote_bound set status bit 1 and are not
+ * counted by the threshold search. */
+ia_status ia_refine(ia_ctx *ctx, const ia_box *d_parents, int32_t n_parents, const int32_t split[5],
+                    const uint16_t *d_votes, int32_t vote_bound, int32_t top_k, ia_box *d_selected,
+                    int64_t *d_selected_index, uint16_t *d_selected_votes, void *stream);
+
+/* Estimate from the max-vote boxes of a level (Sec. 3.3), FP64.  Sums run
+ * over the level's boxes in index order by pairwise summation on a
+ * zero-padded power-of-two array (non-maximal boxes add zero). */
+ia_status ia_estimate(ia_ctx *ctx, const ia_box *d_parents, int32_t n_parents, const int32_t split[5],
+                      const uint16_t *d_votes, ia_estimate_t *d_out, void *stream);
+
+/* The whole search (Sec. 3.3) for n_events events.  Event e owns hits
+ * [h_hit_offsets[e], h_hit_offsets[e+1]) of d_hits (host array of
+ * n_events + 1 offsets, non-decreasing, each event <= 65535 hits).  Per
+ * helix pass: vote the level-0 grid; stop if its max vote is below v_min;
+ * n_refine times select top_k boxes and vote their children; estimate from
+ * the max-vote boxes; assign every still-active hit voting for the box
+ * estimate +- hitfind_scale x error; stop when none is assigned or
+ * n_helix_max / max_per_event helices are found.
+ *   d_out      n_events * max_per_event helices (event-major)
+ *   d_n_out    n_events counts
+ *   d_assigned NULL or one int32 per hit: helix index within its event, -1 if none */
+ia_status ia_find_helices(ia_ctx *ctx, const ia_hit *d_hits, const int32_t *h_hit_offsets,
+                          int32_t n_events, const ia_schedule *sched, ia_helix *d_out,
+                          int32_t max_per_event, int32_t *d_n_out, int32_t *d_assigned, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

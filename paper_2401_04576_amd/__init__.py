@@ -1,0 +1,275 @@
+"""MI355X interval-arithmetic helix vote: Python binding of libia.
+
+Thin ctypes marshalling over the C ABI of include/ia.h.  Every step of the
+search runs in the HIP kernels of libia.so; PyTorch only provides device
+memory and the stream.  Importing works without a GPU; calling anything
+that needs libia raises IAError when the library is missing (there is no
+fallback path).
+
+Tensor layouts (all on the context's CUDA/HIP device):
+  hits     float64 (N, 8)   x0 y0 z0 x1 y1 z1 drift band
+  boxes    float64 (B, 10)  lo[5] then hi[5], order d0 phi0 kappa z0 tanl
+  votes    uint16 (n_boxes,)
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+__all__ = ["IAError", "Context", "Schedule", "vote_level", "refine", "estimate", "find_helices",
+           "lib_path", "load", "FP64", "FP32", "HELIX_DTYPE", "ESTIMATE_DTYPE"]
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+FP64, FP32 = 0, 1
+MAX_LEVELS = 8
+
+_STATUS = {0: "IA_OK", 1: "IA_ERR_INVALID", 2: "IA_ERR_NOMEM", 3: "IA_ERR_DEVICE",
+           4: "IA_ERR_UNSUPPORTED", 5: "IA_ERR_OVERFLOW"}
+
+
+class IAError(RuntimeError):
+    def __init__(self, status, msg=""):
+        super().__init__(f"{_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Box(C.Structure):
+    _fields_ = [("lo", C.c_double * 5), ("hi", C.c_double * 5)]
+
+
+class Schedule(C.Structure):
+    _fields_ = [("range", Box), ("bins", C.c_int32 * 5), ("n_refine", C.c_int32), ("top_k", C.c_int32),
+                ("split", C.c_int32 * 5), ("v_min", C.c_int32), ("n_helix_max", C.c_int32),
+                ("hitfind_scale", C.c_double), ("prec", C.c_int32 * MAX_LEVELS),
+                ("fp32_slack", C.c_double)]
+
+    @classmethod
+    def make(cls, lo, hi, bins, n_refine=4, top_k=32, split=(4, 4, 4, 4, 4), v_min=10, n_helix_max=1,
+             hitfind_scale=5.0, prec=None, fp32_slack=1e-6):
+        s = cls()
+        for j in range(5):
+            s.range.lo[j] = float(lo[j])
+            s.range.hi[j] = float(hi[j])
+            s.bins[j] = int(bins[j])
+            s.split[j] = int(split[j])
+        s.n_refine = int(n_refine)
+        s.top_k = int(top_k)
+        s.v_min = int(v_min)
+        s.n_helix_max = int(n_helix_max)
+        s.hitfind_scale = float(hitfind_scale)
+        prec = [FP64] * MAX_LEVELS if prec is None else list(prec) + [FP64] * (MAX_LEVELS - len(prec))
+        for l in range(MAX_LEVELS):
+            s.prec[l] = int(prec[l])
+        s.fp32_slack = float(fp32_slack)
+        return s
+
+
+HELIX_DTYPE = np.dtype([("p", "f8", (5,)), ("err", "f8", (5,)), ("votes", "i4"), ("n_assigned", "i4"),
+                        ("n_argmax", "i4"), ("status", "i4")])
+ESTIMATE_DTYPE = np.dtype([("p", "f8", (5,)), ("err", "f8", (5,)), ("vmax", "i4"), ("n_argmax", "i4")])
+
+_lib = None
+
+
+def lib_path():
+    return os.path.join(HERE, "libia.so")
+
+
+def load():
+    """Load libia.so; raise IAError if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    path = lib_path()
+    if not os.path.exists(path):
+        raise IAError(4, f"{path} is missing: build it with __graft_entry__.build() "
+                         "or python -m paper_2401_04576_amd.build")
+    L = C.CDLL(path)
+    P, i32, i64, sz = C.c_void_p, C.c_int32, C.c_int64, C.c_size_t
+    L.ia_ctx_create.restype = i32
+    L.ia_ctx_create.argtypes = [C.POINTER(P), i32, sz]
+    L.ia_ctx_destroy.restype = None
+    L.ia_ctx_destroy.argtypes = [P]
+    L.ia_last_error.restype = C.c_char_p
+    L.ia_last_error.argtypes = [P]
+    L.ia_ctx_status.restype = i32
+    L.ia_ctx_status.argtypes = [P, C.POINTER(C.c_uint32), C.POINTER(i64)]
+    L.ia_ctx_clear_status.restype = i32
+    L.ia_ctx_clear_status.argtypes = [P]
+    L.ia_ctx_set_profiling.restype = i32
+    L.ia_ctx_set_profiling.argtypes = [P, i32]
+    L.ia_ctx_profile_read.restype = i32
+    L.ia_ctx_profile_read.argtypes = [P, C.POINTER(i64), C.POINTER(C.c_double)]
+    L.ia_ctx_scratch_needed.restype = sz
+    L.ia_ctx_scratch_needed.argtypes = [C.POINTER(Schedule), i32]
+    L.ia_vote_level.restype = i32
+    L.ia_vote_level.argtypes = [P, P, i32, P, P, i32, C.POINTER(i32), i32, P, P]
+    L.ia_refine.restype = i32
+    L.ia_refine.argtypes = [P, P, i32, C.POINTER(i32), P, i32, i32, P, P, P, P]
+    L.ia_estimate.restype = i32
+    L.ia_estimate.argtypes = [P, P, i32, C.POINTER(i32), P, P, P]
+    L.ia_find_helices.restype = i32
+    L.ia_find_helices.argtypes = [P, P, C.POINTER(i32), i32, C.POINTER(Schedule), P, i32, P, P, P]
+    _lib = L
+    return L
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_handle(stream):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _split(split):
+    arr = (C.c_int32 * 5)(*[int(v) for v in split])
+    return arr
+
+
+def _check_dev(t, dtype, name, device):
+    torch = _torch()
+    if t.dtype != dtype:
+        raise IAError(1, f"{name}: dtype {t.dtype}, expected {dtype}")
+    if not t.is_cuda or t.device.index != device:
+        raise IAError(1, f"{name}: must be on cuda:{device}")
+    if not t.is_contiguous():
+        raise IAError(1, f"{name}: must be contiguous")
+    return t
+
+
+class Context:
+    """Owns the library context (device scratch) for one device and stream."""
+
+    def __init__(self, device=0, scratch_bytes=64 << 20):
+        L = load()
+        self.device = int(device)
+        h = C.c_void_p()
+        st = L.ia_ctx_create(C.byref(h), self.device, int(scratch_bytes))
+        if st != 0:
+            raise IAError(st, "ia_ctx_create failed")
+        self._h = h
+        self._L = L
+
+    def _check(self, st):
+        if st != 0:
+            raise IAError(st, self._L.ia_last_error(self._h).decode())
+
+    def status(self):
+        flags, nbad = C.c_uint32(), C.c_int64()
+        self._check(self._L.ia_ctx_status(self._h, C.byref(flags), C.byref(nbad)))
+        return int(flags.value), int(nbad.value)
+
+    def clear_status(self):
+        self._check(self._L.ia_ctx_clear_status(self._h))
+
+    def set_profiling(self, enable=True):
+        self._check(self._L.ia_ctx_set_profiling(self._h, 1 if enable else 0))
+
+    def profile_read(self):
+        n, ms = C.c_int64(), C.c_double()
+        self._check(self._L.ia_ctx_profile_read(self._h, C.byref(n), C.byref(ms)))
+        return int(n.value), float(ms.value)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._L.ia_ctx_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @staticmethod
+    def scratch_needed(sched, max_hits):
+        return int(load().ia_ctx_scratch_needed(C.byref(sched), int(max_hits)))
+
+
+def vote_level(ctx, hits, parents, split, votes=None, active=None, prec=FP64, stream=None):
+    """Votes of `hits` for every child box of `parents` split by `split`."""
+    torch = _torch()
+    _check_dev(hits, torch.float64, "hits", ctx.device)
+    _check_dev(parents, torch.float64, "parents", ctx.device)
+    nb = parents.shape[0] * int(np.prod([int(s) for s in split]))
+    if votes is None:
+        votes = torch.empty(nb, dtype=torch.uint16, device=hits.device)
+    _check_dev(votes, torch.uint16, "votes", ctx.device)
+    if votes.numel() < nb:
+        raise IAError(1, "votes too small")
+    if active is not None:
+        _check_dev(active, torch.uint8, "active", ctx.device)
+    ctx._check(ctx._L.ia_vote_level(ctx._h, _ptr(hits), int(hits.shape[0]), _ptr(active), _ptr(parents),
+                                    int(parents.shape[0]), _split(split), int(prec), _ptr(votes),
+                                    _stream_handle(stream)))
+    return votes
+
+
+def refine(ctx, parents, split, votes, vote_bound, top_k, stream=None):
+    """Top-k boxes by (votes desc, index asc): (boxes (k, 10), index (k,), votes (k,))."""
+    torch = _torch()
+    _check_dev(parents, torch.float64, "parents", ctx.device)
+    _check_dev(votes, torch.uint16, "votes", ctx.device)
+    nb = parents.shape[0] * int(np.prod([int(s) for s in split]))
+    k = min(int(top_k), nb)
+    dev = votes.device
+    sel = torch.empty((k, 10), dtype=torch.float64, device=dev)
+    idx = torch.empty(k, dtype=torch.int64, device=dev)
+    sv = torch.empty(k, dtype=torch.uint16, device=dev)
+    ctx._check(ctx._L.ia_refine(ctx._h, _ptr(parents), int(parents.shape[0]), _split(split), _ptr(votes),
+                                int(vote_bound), int(top_k), _ptr(sel), _ptr(idx), _ptr(sv),
+                                _stream_handle(stream)))
+    return sel, idx, sv
+
+
+def estimate(ctx, parents, split, votes, stream=None):
+    """Estimate from the max-vote boxes; returns a uint8 device tensor holding one ESTIMATE_DTYPE record."""
+    torch = _torch()
+    _check_dev(parents, torch.float64, "parents", ctx.device)
+    _check_dev(votes, torch.uint16, "votes", ctx.device)
+    out = torch.zeros(ESTIMATE_DTYPE.itemsize, dtype=torch.uint8, device=votes.device)
+    ctx._check(ctx._L.ia_estimate(ctx._h, _ptr(parents), int(parents.shape[0]), _split(split), _ptr(votes),
+                                  _ptr(out), _stream_handle(stream)))
+    return out
+
+
+def decode(raw, dtype):
+    """Device bytes -> numpy structured array (synchronises)."""
+    return np.frombuffer(raw.cpu().numpy().tobytes(), dtype=dtype)
+
+
+def find_helices(ctx, hits, offsets, sched, max_per_event=16, want_assigned=True, stream=None,
+                 out=None, n_out=None, assigned=None):
+    """Run the whole search on the events of `hits` (CSR `offsets`, host ints).
+
+    Returns device tensors (helices as raw bytes, n_out int32, assigned int32 or None).
+    Output tensors may be passed in to avoid allocations."""
+    torch = _torch()
+    _check_dev(hits, torch.float64, "hits", ctx.device)
+    off = np.ascontiguousarray(np.asarray(offsets, dtype=np.int32))
+    n_events = off.shape[0] - 1
+    dev = hits.device
+    if out is None:
+        out = torch.zeros(max(1, n_events * max_per_event) * HELIX_DTYPE.itemsize, dtype=torch.uint8, device=dev)
+    if n_out is None:
+        n_out = torch.zeros(max(1, n_events), dtype=torch.int32, device=dev)
+    if assigned is None and want_assigned:
+        assigned = torch.full((max(1, hits.shape[0]),), -1, dtype=torch.int32, device=dev)
+    if out.numel() < n_events * max_per_event * HELIX_DTYPE.itemsize or n_out.numel() < n_events:
+        raise IAError(1, "output tensors too small")
+    if assigned is not None and assigned.numel() < hits.shape[0]:
+        raise IAError(1, "assigned too small")
+    ctx._check(ctx._L.ia_find_helices(ctx._h, _ptr(hits), off.ctypes.data_as(C.POINTER(C.c_int32)), int(n_events),
+                                      C.byref(sched), _ptr(out), int(max_per_event), _ptr(n_out), _ptr(assigned),
+                                      _stream_handle(stream)))
+    return out, n_out, assigned

@@ -1,0 +1,745 @@
+// ia_kernels.hpp -- HIP kernels of the interval-arithmetic helix vote (gfx950).
+//
+// Box order everywhere: a level is n_parents parent boxes, each split
+// regularly by m[5] (dimension order d0, phi0, kappa, z0, tanl; d0 slowest,
+// tanl fastest); box b = parent * prod(m) + child.  Child edges are
+// L + k (U - L)/m, the last edge U (Sec. 3.3 voxel grids).
+//
+// The vote of a hit for a box depends on the box's (d0, phi0, kappa)
+// intervals -- a "triple" -- through the interval residual G, and on its
+// (z0, tanl) centre only through the point-evaluated stereo drift d^Ax.  The
+// vote kernel therefore stages, per (triple, hit), everything that does not
+// depend on (z0, tanl) in LDS (computed cooperatively by the workgroup), and
+// each lane (one box) finishes the stereo term for its own (z0, tanl).  Axial
+// hits (tan tau = 0) are decided completely per (triple, hit).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "ia_math.hpp"
+
+namespace ia {
+
+constexpr int kWG = 256;        // lanes per workgroup (4 waves of 64)
+constexpr int kCap = 256;       // (triple, hit) records staged per chunk
+constexpr int kHistLds = 1024;  // vote histogram bins kept in LDS
+constexpr int kEstLevels = 15;  // estimate stack depth: levels of up to 2^22 boxes
+
+struct HitRec {                 // prepared hit, 96 bytes
+  double px, py, tant, sphis, cphis, r, phip, r2lo, r2hi, d, band;
+  int32_t use;                  // valid and active
+  int32_t axial;
+};
+
+struct BoxD { double lo[5], hi[5]; };
+
+struct Shape {                  // one level of boxes
+  int32_t m[5];
+  int32_t pad;
+  int64_t nc;                   // boxes per parent
+  int64_t m34;                  // (z0, tanl) boxes per triple
+  int64_t m012;                 // triples per parent
+  int64_t n_boxes;              // n_parents * nc
+};
+
+// per-event control block kept on the device
+struct EventState {
+  int32_t done;                 // 1: no further work for this event
+  int32_t n_out;                // helices written
+  int32_t vmax;                 // max votes of the last selection
+  int32_t k_sel;                // boxes selected by the last selection
+  int32_t n_assigned;           // hits assigned by the last hit finding
+  int32_t n_argmax;             // size of the max-vote set of the last level
+  int32_t pad[2];
+  double p[5], err[5];          // last estimate
+};
+
+// status word bits (device-detected problems, read after a stream sync)
+enum : uint32_t { kStBadHit = 1u, kStVoteOverflow = 2u };
+
+// ---------------------------------------------------------------------------
+// edges of child k of [L, U] split m ways
+__device__ __forceinline__ void child_edge(double L, double U, int32_t m, int64_t k,
+                                           double* lo, double* hi) {
+  double w = (U - L) / static_cast<double>(m);
+  *lo = L + static_cast<double>(k) * w;
+  *hi = (k + 1 == m) ? U : L + static_cast<double>(k + 1) * w;
+}
+
+__device__ __forceinline__ void child_box(const BoxD& P, const int32_t m[5], int64_t child, BoxD* out) {
+  int64_t k[5], rem = child;
+  for (int j = 4; j >= 0; --j) { k[j] = rem % m[j]; rem /= m[j]; }
+  for (int j = 0; j < 5; ++j) child_edge(P.lo[j], P.hi[j], m[j], k[j], &out->lo[j], &out->hi[j]);
+}
+
+// ---------------------------------------------------------------------------
+// hit preparation (Eqs. wirePar_a,b and EQSinter_d,e with z_ref = 0)
+__device__ __forceinline__ void prep_one(const double* h, bool active, HitRec* o, bool* bad) {
+  HitRec r{};
+  bool fin = true;
+  for (int i = 0; i < 8; ++i) fin = fin && isfinite(h[i]);
+  *bad = false;
+  r.use = 0;
+  r.axial = 0;
+  if (!fin) { *bad = true; *o = r; return; }
+  double x0 = h[0], y0 = h[1], z0 = h[2], x1 = h[3], y1 = h[4], z1 = h[5];
+  double dz = z1 - z0;
+  if (dz == 0.0 || h[6] < 0.0 || h[7] < 0.0) { *bad = true; *o = r; return; }
+  double tx = (x1 - x0) / dz, ty = (y1 - y0) / dz;
+  r.px = x0 - z0 * tx;
+  r.py = y0 - z0 * ty;
+  r.tant = sqrt(tx * tx + ty * ty);
+  if (!isfinite(r.px) || !isfinite(r.py) || !isfinite(r.tant)) { *bad = true; *o = HitRec{}; return; }
+  if (r.tant == 0.0) { r.sphis = 0.0; r.cphis = 1.0; r.axial = 1; }
+  else { r.sphis = tx / r.tant; r.cphis = -ty / r.tant; r.axial = 0; }
+  r.r = sqrt(r.px * r.px + r.py * r.py);
+  r.phip = atan2_p(r.py, r.px);
+  double r2 = r.r * r.r;
+  r.r2lo = wdn(r2);
+  r.r2hi = wup(r2);
+  r.d = h[6];
+  r.band = h[7];
+  r.use = active ? 1 : 0;
+  *o = r;
+}
+
+// one thread per hit; also clears the vote histogram of the first level
+__global__ void k_prep(const double* __restrict__ hits, const uint8_t* __restrict__ active,
+                       int32_t n_hits, HitRec* __restrict__ out, uint32_t* __restrict__ hist,
+                       int32_t n_bins, uint32_t* __restrict__ status, int64_t* __restrict__ n_bad) {
+  int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  for (int32_t b = i; b < n_bins && hist; b += gridDim.x * blockDim.x) hist[b] = 0u;
+  if (i >= n_hits) return;
+  bool bad;
+  prep_one(hits + 8 * static_cast<int64_t>(i), active ? active[i] != 0 : true, &out[i], &bad);
+  if (bad) {
+    atomicOr(status, kStBadHit);
+    atomicAdd(reinterpret_cast<unsigned long long*>(n_bad), 1ull);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// frame of a triple at its centre (mirrored to kappa > 0, Appendix A assumes R > 0)
+struct Frame {
+  Iv K, Dd, Fi;                 // kappa, d0, phi0 intervals
+  double sig, R, xc, yc, sp0, cp0;
+};
+
+__device__ __forceinline__ Frame triple_frame(const BoxD& P, const int32_t m[5], int64_t k0, int64_t k1,
+                                              int64_t k2) {
+  Frame f;
+  child_edge(P.lo[0], P.hi[0], m[0], k0, &f.Dd.lo, &f.Dd.hi);
+  child_edge(P.lo[1], P.hi[1], m[1], k1, &f.Fi.lo, &f.Fi.hi);
+  child_edge(P.lo[2], P.hi[2], m[2], k2, &f.K.lo, &f.K.hi);
+  double c0 = 0.5 * (f.Dd.lo + f.Dd.hi), c1 = 0.5 * (f.Fi.lo + f.Fi.hi), kap = 0.5 * (f.K.lo + f.K.hi);
+  double sig = 1.0;
+  if (kap < 0.0) sig = -1.0;
+  if (kap == 0.0) { kap = 0x1p-30; sig = 1.0; }
+  double kp = sig * kap, d0p = sig * c0;
+  double s1, c1v;
+  s1 = sin_p(c1);
+  c1v = cos_p(c1);
+  f.sp0 = sig * s1;
+  f.cp0 = c1v;
+  f.R = 1.0 / kp;
+  double Rd = f.R + d0p;
+  f.xc = -(Rd * f.sp0);
+  f.yc = Rd * f.cp0;
+  f.sig = sig;
+  return f;
+}
+
+// interval residual G over the triple (kappa-scaled Eq. ApoVote)
+__device__ __forceinline__ Iv residual_G(const Frame& f, const HitRec& h) {
+  Iv Ar = {wdn(f.Fi.lo - h.phip), wup(f.Fi.hi - h.phip)};
+  Iv S = sin_encl(Ar.lo, Ar.hi);
+  Iv rS = imul_pos(S, h.r);
+  Iv D2 = isqr(f.Dd);
+  Iv T0 = iadd(D2, Iv{h.r2lo, h.r2hi});
+  Iv T = {0.5 * T0.lo, 0.5 * T0.hi};
+  Iv KT = imul(f.K, T);
+  Iv KD1 = iadd(imul(f.K, f.Dd), Iv{1.0, 1.0});
+  return iadd(iadd(KT, imul(KD1, rS)), f.Dd);
+}
+
+__device__ __forceinline__ bool h_contains0(Iv G, Iv K, double e, double band) {
+  Iv E = {wdn(e - band), wup(e + band)};
+  Iv Hv = isub(itwice(G), iadd(itwice(E), imul(K, isqr(E))));
+  return Hv.lo <= 0.0 && 0.0 <= Hv.hi;
+}
+
+// per (triple, stereo hit) quantities that do not depend on (z0, tanl)
+struct PairQ {
+  double Glo, Ghi, sArc, dphi, RAx, sinA, cosA, sAx, cAx, c2, s2, twoRAx2, RpRAx;
+};
+
+__device__ __forceinline__ PairQ pair_quantities(const Frame& f, const HitRec& h, Iv G) {
+  PairQ q;
+  q.Glo = G.lo;
+  q.Ghi = G.hi;
+  double py = f.sig * h.py, cps = f.sig * h.cphis, sps = h.sphis;
+  double Dx = h.px - f.xc, Dy = py - f.yc;
+  q.RAx = sqrt(Dx * Dx + Dy * Dy);
+  q.cAx = Dx * sps - Dy * cps;
+  q.sAx = Dx * cps + Dy * sps;
+  q.sinA = q.sAx / q.RAx;
+  q.cosA = q.cAx / q.RAx;
+  q.dphi = atan2_p(Dx * f.cp0 + Dy * f.sp0, Dx * f.sp0 - Dy * f.cp0);
+  q.sArc = f.R * q.dphi;
+  q.c2 = q.cosA * q.cosA - q.sinA * q.sinA;
+  q.s2 = 2.0 * q.sinA * q.cosA;
+  q.twoRAx2 = 2.0 * (q.RAx * q.RAx);
+  q.RpRAx = f.R + q.RAx;
+  return q;
+}
+
+// stereo vote of one hit for one box centre (z0, lam); ApproxPhi, normudi,
+// EQSinter_c, defdiAX_b evaluated in the same operation order as the oracle
+__device__ __forceinline__ bool stereo_vote(const PairQ& q, double R, double sig, Iv K, double z0,
+                                            double lam, double lamR, double lam2, double tt, double t2,
+                                            double d, double band) {
+  double zA = z0 + lam * q.sArc;
+  double zAs = zA * q.sinA;
+  double zA2 = zA * zA;
+  double lzA = lam * zA;
+  Iv G = {q.Glo, q.Ghi};
+  bool vote = false;
+#pragma unroll
+  for (int si = 0; si < 2; ++si) {
+    double dS = si == 0 ? d : -d;
+    double Phi1 = -(zAs + (lam * dS) * q.cosA) / q.RAx;
+    double Phi2n = lamR * zA - (lzA * (R - 2.0 * dS)) * q.c2 + (zA2 + dS * (q.RAx + lam2 * (q.RpRAx - dS))) * q.s2;
+    double Phi2 = Phi2n / q.twoRAx2;
+    double eps = Phi1 * tt + Phi2 * t2;
+    double se, ce;
+    sincos_p(eps, &se, &ce);
+    double sinP = q.sinA * ce + q.cosA * se, cosP = q.cosA * ce - q.sinA * se;
+    double u = sqrt(((1.0 + ((2.0 * lam) * sinP) * tt) + lam2 * t2) + (cosP * cosP) * t2);
+    double delta = dS / u;
+    double sperp = R * (q.dphi + eps);
+    double zS = (z0 + lam * sperp) - (delta * cosP) * tt;
+    double ld = lam * delta;
+    double ctau = zS * q.cAx - ld * q.sAx;
+    double a1 = zS * tt, a2 = ld * tt;
+    double Q = ((2.0 * ctau) * tt + a1 * a1) + a2 * a2;
+    double A = R + delta;
+    double disc = A * A - Q;
+    if (disc >= 0.0) {
+      double dhat = delta - Q / (A + sqrt(disc));
+      double e = sig * dhat;
+      if (isfinite(e) && h_contains0(G, K, e, band)) vote = true;
+    }
+  }
+  return vote;
+}
+
+// ---------------------------------------------------------------------------
+// the vote kernel: one lane per box, 256 consecutive boxes per workgroup.
+// Grid: ceil(n_boxes / 256) workgroups.  hist (nullable) receives the vote
+// histogram (bins 0..n_bins-1; votes above are flagged in status).
+__global__ void __launch_bounds__(kWG) k_vote(const HitRec* __restrict__ hits, int32_t n_hits,
+                                              const BoxD* __restrict__ parents, Shape sh,
+                                              uint16_t* __restrict__ votes, uint32_t* __restrict__ hist,
+                                              int32_t n_bins, uint32_t* __restrict__ status,
+                                              const EventState* __restrict__ ev) {
+  if (ev && ev->done) return;
+  __shared__ double sq[13][kCap + 16];
+  __shared__ int8_t sflag[kCap + 16];
+  __shared__ uint32_t shist[kHistLds];
+
+  const int64_t b0 = static_cast<int64_t>(blockIdx.x) * kWG;
+  const int64_t b_last = min(b0 + kWG, sh.n_boxes) - 1;
+  const int64_t b = b0 + threadIdx.x;
+  const bool live = b < sh.n_boxes;
+  const int64_t bb = live ? b : b_last;
+
+  // global triple index of a box: parent * m012 + (child / m34)
+  auto triple_of = [&](int64_t x) { return (x / sh.nc) * sh.m012 + (x % sh.nc) / sh.m34; };
+  const int64_t t_first = triple_of(b0);
+  const int32_t nt = static_cast<int32_t>(triple_of(b_last) - t_first + 1);
+  const int32_t my_tl = static_cast<int32_t>(triple_of(bb) - t_first);
+  const int32_t hc = max(1, kCap / nt);          // hits per chunk
+  // LDS row pitch per triple: one padding slot when a few triples share a
+  // wave (avoids bank conflicts); nt * pitch <= kCap + 16 always holds.
+  const int32_t pitch = hc + ((nt > 1 && nt <= 16) ? 1 : 0);
+
+  // this lane's box: triple frame and (z0, tanl) centre
+  const int64_t par = bb / sh.nc, child = bb % sh.nc;
+  int64_t k[5], rem = child;
+  for (int j = 4; j >= 0; --j) { k[j] = rem % sh.m[j]; rem /= sh.m[j]; }
+  const BoxD P = parents[par];
+  const Frame f = triple_frame(P, sh.m, k[0], k[1], k[2]);
+  double zlo, zhi, llo, lhi;
+  child_edge(P.lo[3], P.hi[3], sh.m[3], k[3], &zlo, &zhi);
+  child_edge(P.lo[4], P.hi[4], sh.m[4], k[4], &llo, &lhi);
+  const double z0 = 0.5 * (zlo + zhi), lam = 0.5 * (llo + lhi);
+  const double lamR = lam * f.R, lam2 = lam * lam;
+
+  int32_t nv = 0;
+  for (int32_t h0 = 0; h0 < n_hits; h0 += hc) {
+    const int32_t nh = min(hc, n_hits - h0);
+    __syncthreads();
+    // stage (triple, hit) quantities: thread r -> (tl = r / hc, hl = r % hc)
+    for (int32_t r = threadIdx.x; r < nt * hc; r += kWG) {
+      const int32_t tl = r / hc, hl = r % hc;
+      const int32_t slot = tl * pitch + hl;
+      if (hl >= nh) continue;
+      const HitRec h = hits[h0 + hl];
+      if (!h.use) { sflag[slot] = -1; continue; }
+      const int64_t t = t_first + tl;
+      const int64_t tp = t / sh.m012, tc = t % sh.m012;
+      const int64_t t0 = tc / (static_cast<int64_t>(sh.m[1]) * sh.m[2]);
+      const int64_t t1 = (tc / sh.m[2]) % sh.m[1], t2 = tc % sh.m[2];
+      const Frame ft = triple_frame(parents[tp], sh.m, t0, t1, t2);
+      const Iv G = residual_G(ft, h);
+      if (h.axial) {
+        bool v = h_contains0(G, ft.K, ft.sig * h.d, h.band) || h_contains0(G, ft.K, ft.sig * (-h.d), h.band);
+        sflag[slot] = v ? 1 : 0;
+      } else {
+        const PairQ q = pair_quantities(ft, h, G);
+        sflag[slot] = 2;
+        sq[0][slot] = q.Glo; sq[1][slot] = q.Ghi; sq[2][slot] = q.sArc; sq[3][slot] = q.dphi;
+        sq[4][slot] = q.RAx; sq[5][slot] = q.sinA; sq[6][slot] = q.cosA; sq[7][slot] = q.sAx;
+        sq[8][slot] = q.cAx; sq[9][slot] = q.c2; sq[10][slot] = q.s2; sq[11][slot] = q.twoRAx2;
+        sq[12][slot] = q.RpRAx;
+      }
+    }
+    __syncthreads();
+    for (int32_t hl = 0; hl < nh; ++hl) {
+      const int32_t slot = my_tl * pitch + hl;
+      const int8_t fl = sflag[slot];
+      if (fl < 2) { nv += fl > 0 ? 1 : 0; continue; }
+      const HitRec& h = hits[h0 + hl];
+      PairQ q;
+      q.Glo = sq[0][slot]; q.Ghi = sq[1][slot]; q.sArc = sq[2][slot]; q.dphi = sq[3][slot];
+      q.RAx = sq[4][slot]; q.sinA = sq[5][slot]; q.cosA = sq[6][slot]; q.sAx = sq[7][slot];
+      q.cAx = sq[8][slot]; q.c2 = sq[9][slot]; q.s2 = sq[10][slot]; q.twoRAx2 = sq[11][slot];
+      q.RpRAx = sq[12][slot];
+      const double tt = h.tant;
+      if (stereo_vote(q, f.R, f.sig, f.K, z0, lam, lamR, lam2, tt, tt * tt, h.d, h.band)) ++nv;
+    }
+  }
+  if (live) votes[b] = static_cast<uint16_t>(nv);
+
+  if (hist) {
+    const bool in_lds = n_bins <= kHistLds;
+    if (in_lds) {
+      for (int32_t i = threadIdx.x; i < n_bins; i += kWG) shist[i] = 0u;
+      __syncthreads();
+    }
+    if (live) {
+      if (nv >= n_bins) atomicOr(status, kStVoteOverflow);
+      else if (in_lds) atomicAdd(&shist[nv], 1u);
+      else atomicAdd(&hist[nv], 1u);
+    }
+    if (in_lds) {
+      __syncthreads();
+      for (int32_t i = threadIdx.x; i < n_bins; i += kWG)
+        if (shist[i]) atomicAdd(&hist[i], shist[i]);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// histogram of an existing vote array (used when votes come from the caller)
+__global__ void __launch_bounds__(kWG) k_hist(const uint16_t* __restrict__ votes, int64_t n,
+                                              uint32_t* __restrict__ hist, int32_t n_bins,
+                                              uint32_t* __restrict__ status) {
+  __shared__ uint32_t shist[kHistLds];
+  const bool in_lds = n_bins <= kHistLds;
+  if (in_lds) {
+    for (int32_t i = threadIdx.x; i < n_bins; i += kWG) shist[i] = 0u;
+    __syncthreads();
+  }
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * kWG + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * kWG) {
+    const int32_t v = votes[i];
+    if (v >= n_bins) atomicOr(status, kStVoteOverflow);
+    else if (in_lds) atomicAdd(&shist[v], 1u);
+    else atomicAdd(&hist[v], 1u);
+  }
+  if (in_lds) {
+    __syncthreads();
+    for (int32_t i = threadIdx.x; i < n_bins; i += kWG)
+      if (shist[i]) atomicAdd(&hist[i], shist[i]);
+  }
+}
+
+__global__ void k_fill_u32(uint32_t* p, int64_t n, uint32_t v) {
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    p[i] = v;
+}
+
+// ---------------------------------------------------------------------------
+// top-k selection by (votes desc, index asc).
+// threshold v*: the largest v with count(votes >= v) >= k_eff; every box above
+// v* is taken, and the first (k_eff - count(votes > v*)) boxes at v* in index
+// order (prefix-sum compaction over the chunks of the grid).
+struct SelInfo { int32_t vstar, need_eq, n_gt, k_eff; };
+
+__device__ __forceinline__ SelInfo threshold(const uint32_t* hist, int32_t n_bins, int32_t k,
+                                             int64_t n_boxes) {
+  SelInfo s;
+  s.k_eff = static_cast<int32_t>(min(static_cast<int64_t>(k), n_boxes));
+  int64_t cum = 0;
+  s.vstar = 0;
+  s.need_eq = s.k_eff;
+  s.n_gt = 0;
+  for (int32_t v = n_bins - 1; v >= 0; --v) {
+    const int64_t c = hist[v];
+    if (cum + c >= s.k_eff) { s.vstar = v; s.need_eq = static_cast<int32_t>(s.k_eff - cum); break; }
+    cum += c;
+  }
+  s.n_gt = s.k_eff - s.need_eq;
+  return s;
+}
+
+// block-wide exclusive scan of 0/1 flags (256 lanes); returns the total
+__device__ __forceinline__ int32_t block_scan(int32_t flag, int32_t* excl, int32_t* sbuf) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const unsigned long long m = __ballot(flag != 0);
+  const int32_t before = __popcll(m & ((1ull << lane) - 1ull));
+  if (lane == 0) sbuf[wv] = __popcll(m);
+  __syncthreads();
+  int32_t off = 0, tot = 0;
+  for (int w = 0; w < kWG / 64; ++w) { if (w < wv) off += sbuf[w]; tot += sbuf[w]; }
+  __syncthreads();
+  *excl = off + before;
+  return tot;
+}
+
+__device__ __forceinline__ int32_t block_sum(int32_t v, int32_t* sbuf) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  if ((threadIdx.x & 63) == 0) sbuf[threadIdx.x >> 6] = v;
+  __syncthreads();
+  int32_t t = 0;
+  for (int w = 0; w < kWG / 64; ++w) t += sbuf[w];
+  __syncthreads();
+  return t;
+}
+
+__global__ void __launch_bounds__(kWG) k_select_count(const uint16_t* __restrict__ votes, int64_t n_boxes,
+                                                      int64_t chunk, const uint32_t* __restrict__ hist,
+                                                      int32_t n_bins, int32_t k, int32_t* __restrict__ cnt,
+                                                      const EventState* __restrict__ ev) {
+  if (ev && ev->done) return;
+  __shared__ SelInfo si;
+  __shared__ int32_t sbuf[kWG / 64];
+  if (threadIdx.x == 0) si = threshold(hist, n_bins, k, n_boxes);
+  __syncthreads();
+  const int64_t beg = blockIdx.x * chunk, end = min(beg + chunk, n_boxes);
+  int32_t gt = 0, eq = 0;
+  for (int64_t i = beg + threadIdx.x; i < end; i += kWG) {
+    const int32_t v = votes[i];
+    gt += v > si.vstar;
+    eq += v == si.vstar;
+  }
+  gt = block_sum(gt, sbuf);
+  eq = block_sum(eq, sbuf);
+  if (threadIdx.x == 0) { cnt[2 * blockIdx.x] = gt; cnt[2 * blockIdx.x + 1] = eq; }
+}
+
+// writes the selection; the last workgroup to finish orders it, writes the
+// selected boxes, clears the histogram and resets the completion counter.
+__global__ void __launch_bounds__(kWG) k_select_write(
+    const uint16_t* __restrict__ votes, int64_t n_boxes, int64_t chunk, uint32_t* __restrict__ hist,
+    int32_t n_bins, int32_t k, const int32_t* __restrict__ cnt, int64_t* __restrict__ tmp_idx,
+    uint32_t* __restrict__ done_counter, const BoxD* __restrict__ parents, Shape sh,
+    BoxD* __restrict__ out_boxes, int64_t* __restrict__ out_index, uint16_t* __restrict__ out_votes,
+    EventState* __restrict__ ev, int32_t v_min_stop) {
+  if (ev && ev->done) return;
+  __shared__ SelInfo si;
+  __shared__ int32_t sbuf[kWG / 64];
+  __shared__ int32_t base_gt, base_eq;
+  __shared__ int32_t is_last;
+  if (threadIdx.x == 0) si = threshold(hist, n_bins, k, n_boxes);
+  __syncthreads();
+  // prefix over earlier chunks
+  int32_t pg = 0, pe = 0;
+  for (int32_t w = threadIdx.x; w < static_cast<int32_t>(blockIdx.x); w += kWG) {
+    pg += cnt[2 * w];
+    pe += cnt[2 * w + 1];
+  }
+  pg = block_sum(pg, sbuf);
+  pe = block_sum(pe, sbuf);
+  if (threadIdx.x == 0) { base_gt = pg; base_eq = pe; }
+  __syncthreads();
+  const int64_t beg = blockIdx.x * chunk, end = min(beg + chunk, n_boxes);
+  int32_t run_gt = base_gt, run_eq = base_eq;
+  for (int64_t i0 = beg; i0 < end && (run_gt < si.n_gt || run_eq < si.need_eq); i0 += kWG) {
+    const int64_t i = i0 + threadIdx.x;
+    const int32_t v = i < end ? votes[i] : -1;
+    const int32_t fg = v > si.vstar, fe = v == si.vstar;
+    int32_t xg, xe;
+    const int32_t tg = block_scan(fg, &xg, sbuf);
+    const int32_t te = block_scan(fe, &xe, sbuf);
+    if (fg && run_gt + xg < si.n_gt) tmp_idx[run_gt + xg] = i;
+    if (fe && run_eq + xe < si.need_eq) tmp_idx[si.n_gt + run_eq + xe] = i;
+    run_gt += tg;
+    run_eq += te;
+  }
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) is_last = atomicAdd(done_counter, 1u) == gridDim.x - 1;
+  __syncthreads();
+  if (!is_last) return;
+  __threadfence();
+  __shared__ int32_t s_vmax;
+  __shared__ uint32_t s_nmax;
+  if (threadIdx.x == 0) {
+    int32_t vm = 0;
+    uint32_t nm = 0;
+    for (int32_t v = n_bins - 1; v >= 0; --v) {
+      const uint32_t c = hist[v];
+      if (c != 0u) { vm = v; nm = c; break; }
+    }
+    s_vmax = vm;
+    s_nmax = nm;
+  }
+  // order the k_eff entries by (votes desc, index asc)
+  const int32_t ke = si.k_eff;
+  for (int32_t a = threadIdx.x; a < ke; a += kWG) {
+    const int64_t ia = __atomic_load_n(&tmp_idx[a], __ATOMIC_RELAXED);
+    const int32_t va = votes[ia];
+    int32_t rank = 0;
+    for (int32_t c = 0; c < ke; ++c) {
+      const int64_t ic = __atomic_load_n(&tmp_idx[c], __ATOMIC_RELAXED);
+      const int32_t vc = votes[ic];
+      rank += (vc > va) || (vc == va && ic < ia);
+    }
+    out_index[rank] = ia;
+    out_votes[rank] = static_cast<uint16_t>(va);
+    if (out_boxes) child_box(parents[ia / sh.nc], sh.m, ia % sh.nc, &out_boxes[rank]);
+  }
+  __syncthreads();
+  for (int32_t i = threadIdx.x; i < n_bins; i += kWG) hist[i] = 0u;
+  if (threadIdx.x == 0) {
+    *done_counter = 0u;
+    if (ev) {
+      ev->vmax = s_vmax;
+      ev->n_argmax = static_cast<int32_t>(s_nmax);
+      ev->k_sel = ke;
+      if (v_min_stop > 0 && s_vmax < v_min_stop) ev->done = 1;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// estimate from the max-vote cells of a level (Sec. 3.3): mean of the cell
+// centres (phi0 relative to the first cell's centre, in (-pi, pi]) and half
+// the extent of their union.  Sums are pairwise over the level's boxes in
+// index order on a zero-padded power-of-two array: each lane reduces an
+// aligned power-of-two segment with a binary-counter stack (the same tree),
+// then adjacent lane sums are paired in LDS.  One workgroup.
+struct EstimateOut {
+  double p[5], err[5];
+  int32_t vmax, n_argmax;
+};
+
+__global__ void __launch_bounds__(kWG) k_estimate(const BoxD* __restrict__ parents, Shape sh,
+                                                  const uint16_t* __restrict__ votes,
+                                                  EstimateOut* __restrict__ out, EventState* __restrict__ ev) {
+  if (ev && ev->done) return;
+  __shared__ double stack[kWG][kEstLevels];
+  __shared__ double lsum[kWG];
+  __shared__ double smin[kWG], smax[kWG];
+  __shared__ int32_t sbuf[kWG / 64];
+  __shared__ int32_t s_vmax;
+  __shared__ double s_c0;
+  const int64_t n = sh.n_boxes;
+  // vmax and the first max-vote box
+  int32_t vm = 0;
+  for (int64_t i = threadIdx.x; i < n; i += kWG) vm = max(vm, static_cast<int32_t>(votes[i]));
+  for (int o = 32; o > 0; o >>= 1) vm = max(vm, __shfl_down(vm, o, 64));
+  if ((threadIdx.x & 63) == 0) sbuf[threadIdx.x >> 6] = vm;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int32_t t = 0;
+    for (int w = 0; w < kWG / 64; ++w) t = max(t, sbuf[w]);
+    s_vmax = t;
+  }
+  __syncthreads();
+  const int32_t vmax = s_vmax;
+  int64_t first = n;
+  for (int64_t i = threadIdx.x; i < n; i += kWG)
+    if (votes[i] == vmax) { first = i; break; }
+  // min over lanes (at most 256 candidates)
+  lsum[threadIdx.x] = static_cast<double>(first);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int64_t f = n;
+    for (int w = 0; w < kWG; ++w) f = min(f, static_cast<int64_t>(lsum[w]));
+    BoxD bx;
+    child_box(parents[f / sh.nc], sh.m, f % sh.nc, &bx);
+    s_c0 = 0.5 * (bx.lo[1] + bx.hi[1]);
+  }
+  __syncthreads();
+  const double c0 = s_c0;
+  int64_t p2 = 1;
+  while (p2 < n) p2 <<= 1;
+  const int32_t nthr = static_cast<int32_t>(min<int64_t>(kWG, p2));
+  const int64_t seg = p2 / nthr;
+  int32_t cnt = 0;
+  for (int64_t i = threadIdx.x; i < n; i += kWG) cnt += votes[i] == vmax;
+  for (int o = 32; o > 0; o >>= 1) cnt += __shfl_down(cnt, o, 64);
+  if ((threadIdx.x & 63) == 0) sbuf[threadIdx.x >> 6] = cnt;
+  __syncthreads();
+  int32_t count = 0;
+  for (int w = 0; w < kWG / 64; ++w) count += sbuf[w];
+  for (int j = 0; j < 5; ++j) {
+    double lo_min = INFINITY, hi_max = -INFINITY;
+    double total = 0.0;
+    if (static_cast<int32_t>(threadIdx.x) < nthr) {
+      const int64_t beg = threadIdx.x * seg;
+      for (int64_t s = 0; s < seg; ++s) {
+        const int64_t i = beg + s;
+        double v = 0.0;
+        if (i < n && votes[i] == vmax) {
+          BoxD bx;
+          child_box(parents[i / sh.nc], sh.m, i % sh.nc, &bx);
+          double lo = bx.lo[j], hi = bx.hi[j];
+          const double c = 0.5 * (lo + hi);
+          if (j == 1) {
+            const double dv = c - c0;
+            double shift = 0.0;
+            if (dv > kPi) shift = -kTwoPi;
+            else if (dv <= -kPi) shift = kTwoPi;
+            v = dv + shift;
+            lo = lo + shift;
+            hi = hi + shift;
+          } else {
+            v = c;
+          }
+          lo_min = fmin(lo_min, lo);
+          hi_max = fmax(hi_max, hi);
+        }
+        int64_t c = s;
+        int lvl = 0;
+        while (c & 1) { v = stack[threadIdx.x][lvl] + v; c >>= 1; ++lvl; }
+        stack[threadIdx.x][lvl] = v;
+      }
+      int lg = 0;
+      while ((static_cast<int64_t>(1) << lg) < seg) ++lg;
+      total = stack[threadIdx.x][lg];
+    }
+    lsum[threadIdx.x] = total;
+    smin[threadIdx.x] = lo_min;
+    smax[threadIdx.x] = hi_max;
+    __syncthreads();
+    for (int32_t w = nthr; w > 1; w >>= 1) {
+      double a = 0.0, mn = 0.0, mx = 0.0;
+      const bool act = static_cast<int32_t>(threadIdx.x) < w / 2;
+      if (act) {
+        a = lsum[2 * threadIdx.x] + lsum[2 * threadIdx.x + 1];
+        mn = fmin(smin[2 * threadIdx.x], smin[2 * threadIdx.x + 1]);
+        mx = fmax(smax[2 * threadIdx.x], smax[2 * threadIdx.x + 1]);
+      }
+      __syncthreads();
+      if (act) { lsum[threadIdx.x] = a; smin[threadIdx.x] = mn; smax[threadIdx.x] = mx; }
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+      const double S = lsum[0];
+      double pj;
+      if (j == 1) {
+        pj = c0 + S / static_cast<double>(count);
+        if (pj < 0.0) pj += kTwoPi;
+        if (pj >= kTwoPi) pj -= kTwoPi;
+      } else {
+        pj = S / static_cast<double>(count);
+      }
+      const double ej = 0.5 * (smax[0] - smin[0]);
+      if (out) { out->p[j] = pj; out->err[j] = ej; }
+      if (ev) { ev->p[j] = pj; ev->err[j] = ej; }
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    if (out) { out->vmax = vmax; out->n_argmax = count; }
+    if (ev) { ev->vmax = vmax; ev->n_argmax = count; ev->n_assigned = 0; }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// hit finding (Sec. 3.3): every active hit that votes for the box
+// estimate +- scale x error is assigned to the current helix
+__device__ __forceinline__ bool pair_vote_box(const BoxD& b, const HitRec& h) {
+  if (!h.use) return false;
+  Frame f;
+  f.Dd = {b.lo[0], b.hi[0]};
+  f.Fi = {b.lo[1], b.hi[1]};
+  f.K = {b.lo[2], b.hi[2]};
+  double c0 = 0.5 * (f.Dd.lo + f.Dd.hi), c1 = 0.5 * (f.Fi.lo + f.Fi.hi), kap = 0.5 * (f.K.lo + f.K.hi);
+  double sig = 1.0;
+  if (kap < 0.0) sig = -1.0;
+  if (kap == 0.0) { kap = 0x1p-30; sig = 1.0; }
+  const double kp = sig * kap, d0p = sig * c0;
+  f.sp0 = sig * sin_p(c1);
+  f.cp0 = cos_p(c1);
+  f.R = 1.0 / kp;
+  const double Rd = f.R + d0p;
+  f.xc = -(Rd * f.sp0);
+  f.yc = Rd * f.cp0;
+  f.sig = sig;
+  const Iv G = residual_G(f, h);
+  if (h.axial)
+    return h_contains0(G, f.K, f.sig * h.d, h.band) || h_contains0(G, f.K, f.sig * (-h.d), h.band);
+  const PairQ q = pair_quantities(f, h, G);
+  const double z0 = 0.5 * (b.lo[3] + b.hi[3]), lam = 0.5 * (b.lo[4] + b.hi[4]);
+  return stereo_vote(q, f.R, f.sig, f.K, z0, lam, lam * f.R, lam * lam, h.tant, h.tant * h.tant, h.d, h.band);
+}
+
+__global__ void __launch_bounds__(kWG) k_hitfind(HitRec* __restrict__ hits, int32_t n_hits,
+                                                 EventState* __restrict__ ev, double scale,
+                                                 int32_t* __restrict__ assigned) {
+  if (ev->done) return;
+  const int32_t i = blockIdx.x * kWG + threadIdx.x;
+  if (i >= n_hits) return;
+  BoxD E;
+  for (int j = 0; j < 5; ++j) {
+    const double w = scale * ev->err[j];
+    E.lo[j] = ev->p[j] - w;
+    E.hi[j] = ev->p[j] + w;
+  }
+  HitRec h = hits[i];
+  if (pair_vote_box(E, h)) {
+    hits[i].use = 0;
+    if (assigned) assigned[i] = ev->n_out;
+    atomicAdd(&ev->n_assigned, 1);
+  }
+}
+
+// helix record: {p[5], err[5], votes, n_assigned, n_argmax, status}
+struct HelixOut {
+  double p[5], err[5];
+  int32_t votes, n_assigned, n_argmax, status;
+};
+
+__global__ void k_record(EventState* __restrict__ ev, HelixOut* __restrict__ out, int32_t max_out,
+                         int32_t* __restrict__ n_out) {
+  if (threadIdx.x != 0 || ev->done) return;
+  const int32_t k = ev->n_out;
+  if (k < max_out) {
+    HelixOut h;
+    for (int j = 0; j < 5; ++j) { h.p[j] = ev->p[j]; h.err[j] = ev->err[j]; }
+    h.votes = ev->vmax;
+    h.n_assigned = ev->n_assigned;
+    h.n_argmax = ev->n_argmax;
+    h.status = 0;
+    out[k] = h;
+    ev->n_out = k + 1;
+  }
+  if (n_out) *n_out = ev->n_out;
+  if (ev->n_assigned == 0 || ev->n_out >= max_out) ev->done = 1;
+}
+
+__global__ void k_event_init(EventState* ev, int32_t* n_out) {
+  if (threadIdx.x == 0) {
+    EventState e{};
+    *ev = e;
+    if (n_out) *n_out = 0;
+  }
+}
+
+}  // namespace ia

@@ -1,0 +1,163 @@
+// ia_math.hpp -- device arithmetic of the interval vote (gfx950, FP64).
+//
+// Outward rounding: every interval +, -, x endpoint is computed in
+// round-to-nearest and moved outward by |x| 2^-52 + 2^-1074 (one fused
+// multiply-add and one add), which is at least one ulp, so each enclosure
+// contains the exact result.  Doubling, halving and negation are exact.
+//
+// sin, cos: Cody-Waite reduction by pi/2 with a three-part constant (parts of
+// 33, 33 and 53 significant bits of pi/2) and Taylor polynomials of degree
+// 17 (sin) and 16 (cos) on [-pi/4, pi/4], Horner with fused multiply-adds.
+// atan2: octant reduction, atan t = pi/6 + atan((t sqrt3 - 1)/(t + sqrt3))
+// above tan(pi/12), Taylor series of degree 29.  These are written here so
+// results are reproducible independently of the device math library.
+//
+// The whole file must be compiled with -ffp-contract=off: only the explicit
+// fma() calls may fuse.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ia {
+
+// pi/2 = P1 + P2 + P3 (+ 1e-37): P1, P2 carry 33 significant bits
+constexpr double kTwoOverPi = 0x1.45f306dc9c883p-1;
+constexpr double kPio2a = 0x1.921fb544p+0;
+constexpr double kPio2b = 0x1.0b4611a6p-34;
+constexpr double kPio2c = 0x1.3198a2e037073p-69;
+constexpr double kPi = 0x1.921fb54442d18p+1;      // below pi
+constexpr double kTwoPi = 0x1.921fb54442d18p+2;   // below 2 pi
+constexpr double kPio2 = 0x1.921fb54442d18p+0;
+constexpr double kPio6 = 0x1.0c152382d7366p-1;
+constexpr double kSqrt3 = 0x1.bb67ae8584caap+0;
+constexpr double kInvTwoPi = 0x1.45f306dc9c883p-3;
+constexpr double kTanPi12 = 0x1.126145e9ecd56p-2;
+constexpr double kSinMargin = 0x1p-50;   // > 4x the error of sin_p / cos_p
+constexpr double kExtFuzz = 0x1p-40;     // extremum-membership slack
+
+__device__ __forceinline__ double wdn(double x) { return x - fma(fabs(x), 0x1p-52, 0x1p-1074); }
+__device__ __forceinline__ double wup(double x) { return x + fma(fabs(x), 0x1p-52, 0x1p-1074); }
+
+__device__ __forceinline__ double poly_sin(double r) {
+  double z = r * r;
+  double p = 1.0 / 355687428096000.0;      // 1/17!
+  p = fma(p, z, -1.0 / 1307674368000.0);   // 1/15!
+  p = fma(p, z, 1.0 / 6227020800.0);       // 1/13!
+  p = fma(p, z, -1.0 / 39916800.0);        // 1/11!
+  p = fma(p, z, 1.0 / 362880.0);           // 1/9!
+  p = fma(p, z, -1.0 / 5040.0);            // 1/7!
+  p = fma(p, z, 1.0 / 120.0);              // 1/5!
+  p = fma(p, z, -1.0 / 6.0);               // 1/3!
+  return fma(r * z, p, r);
+}
+
+__device__ __forceinline__ double poly_cos(double r) {
+  double z = r * r;
+  double q = 1.0 / 20922789888000.0;       // 1/16!
+  q = fma(q, z, -1.0 / 87178291200.0);     // 1/14!
+  q = fma(q, z, 1.0 / 479001600.0);        // 1/12!
+  q = fma(q, z, -1.0 / 3628800.0);         // 1/10!
+  q = fma(q, z, 1.0 / 40320.0);            // 1/8!
+  q = fma(q, z, -1.0 / 720.0);             // 1/6!
+  q = fma(q, z, 1.0 / 24.0);               // 1/4!
+  q = fma(q, z, -0.5);                     // 1/2!
+  return fma(z, q, 1.0);
+}
+
+// x = k pi/2 + r
+__device__ __forceinline__ double reduce_quadrant(double x, int* quad) {
+  double k = rint(x * kTwoOverPi);
+  double r = ((x - k * kPio2a) - k * kPio2b) - k * kPio2c;
+  *quad = static_cast<int>(static_cast<int64_t>(k) & 3);
+  return r;
+}
+
+__device__ __forceinline__ double sin_p(double x) {
+  int q;
+  double r = reduce_quadrant(x, &q);
+  double v = (q & 1) ? poly_cos(r) : poly_sin(r);
+  return (q & 2) ? -v : v;
+}
+
+__device__ __forceinline__ double cos_p(double x) {
+  int q;
+  double r = reduce_quadrant(x, &q);
+  double v = (q & 1) ? poly_sin(r) : poly_cos(r);
+  return ((q + 1) & 2) ? -v : v;
+}
+
+// sin and cos of the same argument with one reduction
+__device__ __forceinline__ void sincos_p(double x, double* s, double* c) {
+  int q;
+  double r = reduce_quadrant(x, &q);
+  double ps = poly_sin(r), pc = poly_cos(r);
+  double sv = (q & 1) ? pc : ps;
+  double cv = (q & 1) ? ps : pc;
+  *s = (q & 2) ? -sv : sv;
+  *c = ((q + 1) & 2) ? -cv : cv;
+}
+
+__device__ __forceinline__ double poly_atan(double u) {
+  double z = u * u;
+  double p = 1.0 / 29.0;
+  p = fma(p, z, -1.0 / 27.0);
+  p = fma(p, z, 1.0 / 25.0);
+  p = fma(p, z, -1.0 / 23.0);
+  p = fma(p, z, 1.0 / 21.0);
+  p = fma(p, z, -1.0 / 19.0);
+  p = fma(p, z, 1.0 / 17.0);
+  p = fma(p, z, -1.0 / 15.0);
+  p = fma(p, z, 1.0 / 13.0);
+  p = fma(p, z, -1.0 / 11.0);
+  p = fma(p, z, 1.0 / 9.0);
+  p = fma(p, z, -1.0 / 7.0);
+  p = fma(p, z, 1.0 / 5.0);
+  p = fma(p, z, -1.0 / 3.0);
+  return fma(u * z, p, u);
+}
+
+// angle of (x, y) in [-pi, pi]; 0 at the origin
+__device__ __forceinline__ double atan2_p(double y, double x) {
+  double ax = fabs(x), ay = fabs(y);
+  if (ax == 0.0 && ay == 0.0) return 0.0;
+  bool swap = ay > ax;
+  double t = swap ? ax / ay : ay / ax;
+  double a;
+  if (t > kTanPi12) a = kPio6 + poly_atan((t * kSqrt3 - 1.0) / (t + kSqrt3));
+  else a = poly_atan(t);
+  if (swap) a = kPio2 - a;
+  if (x < 0.0) a = kPi - a;
+  if (y < 0.0) a = -a;
+  return a;
+}
+
+struct Iv { double lo, hi; };
+
+__device__ __forceinline__ Iv iadd(Iv a, Iv b) { return {wdn(a.lo + b.lo), wup(a.hi + b.hi)}; }
+__device__ __forceinline__ Iv isub(Iv a, Iv b) { return {wdn(a.lo - b.hi), wup(a.hi - b.lo)}; }
+__device__ __forceinline__ Iv imul(Iv a, Iv b) {
+  double p1 = a.lo * b.lo, p2 = a.lo * b.hi, p3 = a.hi * b.lo, p4 = a.hi * b.hi;
+  return {wdn(fmin(fmin(p1, p2), fmin(p3, p4))), wup(fmax(fmax(p1, p2), fmax(p3, p4)))};
+}
+// interval times a non-negative point: the 4-product rule reduces to two products
+__device__ __forceinline__ Iv imul_pos(Iv a, double s) { return {wdn(a.lo * s), wup(a.hi * s)}; }
+__device__ __forceinline__ Iv isqr(Iv a) {
+  double l2 = a.lo * a.lo, h2 = a.hi * a.hi;
+  if (a.lo <= 0.0 && a.hi >= 0.0) return {0.0, wup(fmax(l2, h2))};
+  return {wdn(fmin(l2, h2)), wup(fmax(l2, h2))};
+}
+__device__ __forceinline__ Iv itwice(Iv a) { return {2.0 * a.lo, 2.0 * a.hi}; }
+
+// enclosure of sin over [a, b]
+__device__ __forceinline__ Iv sin_encl(double a, double b) {
+  if (b - a >= kTwoPi) return {-1.0, 1.0};
+  double va = sin_p(a), vb = sin_p(b);
+  double l = fmin(va, vb) - kSinMargin, h = fmax(va, vb) + kSinMargin;
+  if (floor((b - kPio2) * kInvTwoPi + kExtFuzz) >= ceil((a - kPio2) * kInvTwoPi - kExtFuzz)) h = 1.0;
+  if (floor((b + kPio2) * kInvTwoPi + kExtFuzz) >= ceil((a + kPio2) * kInvTwoPi - kExtFuzz)) l = -1.0;
+  if (l < -1.0) l = -1.0;
+  if (h > 1.0) h = 1.0;
+  return {l, h};
+}
+
+}  // namespace ia

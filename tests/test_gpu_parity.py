@@ -1,0 +1,220 @@
+"""GPU parity: libia (HIP, gfx950) against the FP64 CPU oracle.
+
+FP64 arithmetic on both sides follows the same IEEE operation sequence, so
+votes, selections, estimates and helices must be identical bit for bit.
+Inputs are seeded synthetic events; nothing here reads stored GPU output.
+"""
+import ctypes as C
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_2401_04576_amd as ia
+from paper_2401_04576_amd import toymc
+from tests import _helpers as H
+
+pytestmark = pytest.mark.gpu
+
+
+def _torch():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    return torch
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    _torch()
+    c = ia.Context(0, scratch_bytes=256 << 20)
+    yield c
+    c.close()
+
+
+def _dev_hits(hits):
+    torch = _torch()
+    a = np.ascontiguousarray(hits).view(np.float64).reshape(-1, 8) if len(hits) else np.zeros((0, 8))
+    return torch.from_numpy(a.copy()).to("cuda:0")
+
+
+def _dev_boxes(boxes):
+    torch = _torch()
+    b = np.atleast_1d(boxes)
+    a = np.concatenate([b["lo"], b["hi"]], axis=1).astype(np.float64)
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+
+
+def _votes_np(t):
+    return t.cpu().numpy().astype(np.uint16)
+
+
+def _gpu_votes(ctx, hits, parents, split, active=None):
+    torch = _torch()
+    act = None if active is None else torch.from_numpy(np.asarray(active, np.uint8)).to("cuda:0")
+    v = ia.vote_level(ctx, _dev_hits(hits), _dev_boxes(parents), split, active=act)
+    torch.cuda.synchronize()
+    return _votes_np(v)
+
+
+def test_level0_votes_bit_exact_cfg1(ctx):
+    """Single event, 12^5 level-0 grid (the plain FP64 single-level workload)."""
+    for ev_i in range(2):
+        ev = toymc.config_event(1, ev_i)
+        print(f"cfg1 event {ev_i} N={ev.n_hits}", flush=True)
+        root = oracle.make_box(H.LO, H.HI)
+        ref = oracle.vote_level(ev.hits, root, [12] * 5)
+        got = _gpu_votes(ctx, ev.hits, root, [12] * 5)
+        assert got.shape == ref.shape
+        bad = np.flatnonzero(got != ref)
+        assert bad.size == 0, (bad[:10], got[bad[:10]], ref[bad[:10]])
+
+
+def test_refinement_shape_votes_bit_exact(ctx):
+    """32 parents split 4^5 (a refinement level) on a noisy event with bands."""
+    ev = toymc.config_event(2, 3)
+    root = oracle.make_box(H.LO, H.HI)
+    v0 = oracle.vote_level(ev.hits, root, [8] * 5)
+    idx, _ = oracle.topk(v0, 32)
+    parents = np.array([oracle.box_child(root, [8] * 5, i) for i in idx])
+    ref = oracle.vote_level(ev.hits, parents, [4] * 5)
+    got = _gpu_votes(ctx, ev.hits, parents, [4] * 5)
+    assert np.array_equal(got, ref)
+
+
+@pytest.mark.parametrize("split,n_par", [((3, 5, 2, 7, 3), 5), ((1, 1, 1, 1, 1), 300), ((2, 3, 1, 1, 1), 77),
+                                         ((5, 1, 4, 1, 2), 3)])
+def test_ragged_shapes_bit_exact(ctx, split, n_par):
+    """Shapes with ragged tiles: several triples per workgroup, partial last tile."""
+    ev = toymc.config_event(2, 5)
+    rng = np.random.default_rng(41)
+    t = ev.truth[0]
+    w = (H.HI - H.LO) * 0.02
+    parents = np.array([oracle.make_box(t - w * rng.uniform(0.2, 1, 5), t + w * rng.uniform(0.2, 1, 5))
+                        for _ in range(n_par)])
+    ref = oracle.vote_level(ev.hits, parents, split)
+    got = _gpu_votes(ctx, ev.hits, parents, split)
+    assert np.array_equal(got, ref)
+
+
+def test_edge_cases_hits(ctx):
+    torch = _torch()
+    root = oracle.make_box(H.LO, H.HI)
+    # no hits
+    got = _gpu_votes(ctx, np.zeros(0, dtype=toymc.HIT_DTYPE), root, [4] * 5)
+    assert got.shape == (4 ** 5,) and not got.any()
+    # malformed hits never vote and are counted
+    ev = toymc.config_event(1, 9)
+    hits = ev.hits.copy()
+    bad = hits[:4].copy()
+    bad[0]["drift"] = -1.0
+    bad[1]["z1"] = bad[1]["z0"]
+    bad[2]["x0"] = np.nan
+    bad[3]["band"] = -1.0
+    both = np.concatenate([hits, bad])
+    ctx.clear_status()
+    got = _gpu_votes(ctx, both, root, [6] * 5)
+    ref = oracle.vote_level(hits, root, [6] * 5)
+    assert np.array_equal(got, ref)
+    flags, nbad = ctx.status()
+    assert flags & 1 and nbad == 4
+    ctx.clear_status()
+    # active mask
+    act = np.ones(ev.n_hits, np.uint8)
+    act[::3] = 0
+    got = _gpu_votes(ctx, hits, root, [6] * 5, active=act)
+    ref = oracle.vote_level(hits, root, [6] * 5, active=act)
+    assert np.array_equal(got, ref)
+    # many hits (several chunks of the staging loop at level 0)
+    ev5 = toymc.config_event(5, 3)
+    many = np.concatenate([ev5.hits] * 4)[:700]
+    parents = np.array([oracle.make_box(H.LO, H.HI)])
+    got = _gpu_votes(ctx, many, parents, [3, 4, 3, 2, 2])
+    ref = oracle.vote_level(many, parents, [3, 4, 3, 2, 2])
+    assert np.array_equal(got, ref)
+    del torch
+
+
+@pytest.mark.parametrize("n,k,vmax", [(1, 1, 3), (7, 32, 2), (1000, 32, 3), (32768, 32, 20),
+                                      (1048576, 32, 24), (250000, 64, 1), (5000, 4096, 9)])
+def test_refine_topk_matches_oracle(ctx, n, k, vmax):
+    torch = _torch()
+    rng = np.random.default_rng(n + k)
+    v = rng.integers(0, vmax + 1, n).astype(np.uint16)
+    # one parent split n ways along d0: box index = child index
+    root = oracle.make_box(H.LO, H.HI)
+    parents = np.array([root])
+    split = [n, 1, 1, 1, 1]
+    sel, idx, sv = ia.refine(ctx, _dev_boxes(parents), split, torch.from_numpy(v).to("cuda:0"), vmax, k)
+    torch.cuda.synchronize()
+    ridx, rv = oracle.topk(v, k)
+    assert np.array_equal(idx.cpu().numpy(), ridx)
+    assert np.array_equal(sv.cpu().numpy().astype(np.uint16), rv)
+    selb = sel.cpu().numpy()
+    for r in range(min(len(ridx), 50)):
+        b = oracle.box_child(root, split, ridx[r])
+        assert np.array_equal(selb[r, :5], b["lo"]) and np.array_equal(selb[r, 5:], b["hi"])
+
+
+def test_estimate_bit_exact(ctx):
+    torch = _torch()
+    ev = toymc.config_event(2, 4)
+    root = oracle.make_box(H.LO, H.HI)
+    v0 = oracle.vote_level(ev.hits, root, [8] * 5)
+    idx, _ = oracle.topk(v0, 32)
+    parents = np.array([oracle.box_child(root, [8] * 5, i) for i in idx])
+    votes = oracle.vote_level(ev.hits, parents, [4] * 5)
+    p, err, n = oracle.estimate(parents, [4] * 5, votes, votes.max())
+    raw = ia.estimate(ctx, _dev_boxes(parents), [4] * 5, torch.from_numpy(votes).to("cuda:0"))
+    got = ia.decode(raw, ia.ESTIMATE_DTYPE)[0]
+    assert got["vmax"] == votes.max() and got["n_argmax"] == n
+    assert np.array_equal(got["p"], p) and np.array_equal(got["err"], err)
+    # level-0 estimate over a non-power-of-two grid
+    v12 = oracle.vote_level(ev.hits, root, [12] * 5)
+    p, err, n = oracle.estimate(np.array([root]), [12] * 5, v12, v12.max())
+    raw = ia.estimate(ctx, _dev_boxes(root), [12] * 5, torch.from_numpy(v12).to("cuda:0"))
+    got = ia.decode(raw, ia.ESTIMATE_DTYPE)[0]
+    assert got["n_argmax"] == n and np.array_equal(got["p"], p) and np.array_equal(got["err"], err)
+
+
+def _compare_find(ctx, events, sched_o, sched_g, max_out=4):
+    torch = _torch()
+    hits = np.concatenate([e.hits for e in events])
+    off = np.concatenate([[0], np.cumsum([e.n_hits for e in events])]).astype(np.int32)
+    raw, n_out, assigned = ia.find_helices(ctx, _dev_hits(hits), off, sched_g, max_per_event=max_out)
+    torch.cuda.synchronize()
+    hel = ia.decode(raw, ia.HELIX_DTYPE).reshape(len(events), max_out)
+    n_out = n_out.cpu().numpy()
+    assigned = assigned.cpu().numpy()
+    for e, ev in enumerate(events):
+        ref, ref_ass = oracle.find_helices(ev.hits, sched_o, max_out=max_out)
+        assert n_out[e] == len(ref), (e, n_out[e], len(ref))
+        for h in range(len(ref)):
+            g, r = hel[e, h], ref[h]
+            assert np.array_equal(g["p"], r["p"]) and np.array_equal(g["err"], r["err"]), (e, h, g, r)
+            assert (g["votes"], g["n_assigned"], g["n_argmax"]) == (r["votes"], r["n_assigned"], r["n_argmax"])
+        assert np.array_equal(assigned[off[e]:off[e + 1]], ref_ass)
+
+
+def test_find_helices_full_schedule_cfg2(ctx):
+    """The measured workload: 16^5 grid, 4 levels of top-32 split 4^5, FP64."""
+    events = [toymc.config_event(2, i) for i in range(2)]
+    so = H.full_sched(oracle)
+    sg = ia.Schedule.make(H.LO, H.HI, [16] * 5)
+    _compare_find(ctx, events, so, sg, max_out=1)
+
+
+def test_find_helices_multi_helix_small_grid(ctx):
+    """Greedy multi-helix passes with hit removal (smaller grids for the oracle)."""
+    events = [toymc.config_event(4, i) for i in range(3)]
+    kw = dict(bins=[8] * 5, n_refine=2, top_k=16, split=[2] * 5, v_min=10, n_helix_max=4)
+    so = oracle.make_sched(H.LO, H.HI, **kw)
+    sg = ia.Schedule.make(H.LO, H.HI, **kw)
+    _compare_find(ctx, events, so, sg, max_out=4)
+
+
+def test_deterministic_repeat(ctx):
+    ev = toymc.config_event(2, 6)
+    root = oracle.make_box(H.LO, H.HI)
+    a = _gpu_votes(ctx, ev.hits, root, [16] * 5)
+    b = _gpu_votes(ctx, ev.hits, root, [16] * 5)
+    assert np.array_equal(a, b)
