@@ -125,6 +125,11 @@ ia_status ia_ctx_clear_status(ia_ctx *ctx);
 ia_status ia_ctx_set_profiling(ia_ctx *ctx, int32_t enable);
 ia_status ia_ctx_profile_read(ia_ctx *ctx, int64_t *n_launches, double *total_ms);
 
+/* Boxes per workgroup of the vote kernel: 256, 128 or 64 (the workgroup's
+ * 256 lanes then split each hit chunk over 1, 2 or 4 waves), or 0 to choose
+ * by level size.  Results do not depend on it. */
+ia_status ia_ctx_set_vote_tile(ia_ctx *ctx, int32_t boxes_per_workgroup);
+
 /* Scratch bytes needed by ia_find_helices for events of at most max_hits
  * hits under `sched`. */
 size_t ia_ctx_scratch_needed(const ia_schedule *sched, int32_t max_hits);

@@ -98,6 +98,8 @@ def load():
     L.ia_ctx_status.argtypes = [P, C.POINTER(C.c_uint32), C.POINTER(i64)]
     L.ia_ctx_clear_status.restype = i32
     L.ia_ctx_clear_status.argtypes = [P]
+    L.ia_ctx_set_vote_tile.restype = i32
+    L.ia_ctx_set_vote_tile.argtypes = [P, i32]
     L.ia_ctx_set_profiling.restype = i32
     L.ia_ctx_set_profiling.argtypes = [P, i32]
     L.ia_ctx_profile_read.restype = i32
@@ -171,6 +173,10 @@ class Context:
 
     def clear_status(self):
         self._check(self._L.ia_ctx_clear_status(self._h))
+
+    def set_vote_tile(self, boxes_per_workgroup=0):
+        """Force the vote kernel's boxes per workgroup (256, 128, 64) or 0 for automatic."""
+        self._check(self._L.ia_ctx_set_vote_tile(self._h, int(boxes_per_workgroup)))
 
     def set_profiling(self, enable=True):
         self._check(self._L.ia_ctx_set_profiling(self._h, 1 if enable else 0))

@@ -23,7 +23,8 @@ namespace ia {
 constexpr int kWG = 256;        // lanes per workgroup (4 waves of 64)
 constexpr int kCap = 256;       // (triple, hit) records staged per chunk
 constexpr int kHistLds = 1024;  // vote histogram bins kept in LDS
-constexpr int kEstLevels = 15;  // estimate stack depth: levels of up to 2^22 boxes
+constexpr int kEstLevels = 15;  // estimate stack depth (partials of up to 2^22 boxes)
+constexpr int kMaxTopK = 4096;  // selection size limit
 
 struct HitRec {                 // prepared hit, 96 bytes
   double px, py, tant, sphis, cphis, r, phip, r2lo, r2hi, d, band;
@@ -33,13 +34,15 @@ struct HitRec {                 // prepared hit, 96 bytes
 
 struct BoxD { double lo[5], hi[5]; };
 
-struct Shape {                  // one level of boxes
-  int32_t m[5];
-  int32_t pad;
-  int64_t nc;                   // boxes per parent
-  int64_t m34;                  // (z0, tanl) boxes per triple
-  int64_t m012;                 // triples per parent
-  int64_t n_boxes;              // n_parents * nc
+struct Shape {                  // one level of boxes (n_boxes < 2^31)
+  uint32_t m[5];
+  uint32_t nc;                  // boxes per parent
+  uint32_t m34;                 // (z0, tanl) boxes per triple
+  uint32_t m012;                // triples per parent
+  uint32_t m12;                 // m[1] * m[2]
+  uint32_t n_boxes;             // n_parents * nc
+  uint32_t n_parents;
+  uint32_t pad;
 };
 
 // per-event control block kept on the device
@@ -59,17 +62,25 @@ enum : uint32_t { kStBadHit = 1u, kStVoteOverflow = 2u };
 
 // ---------------------------------------------------------------------------
 // edges of child k of [L, U] split m ways
-__device__ __forceinline__ void child_edge(double L, double U, int32_t m, int64_t k,
+__device__ __forceinline__ void child_edge(double L, double U, uint32_t m, uint32_t k,
                                            double* lo, double* hi) {
   double w = (U - L) / static_cast<double>(m);
   *lo = L + static_cast<double>(k) * w;
   *hi = (k + 1 == m) ? U : L + static_cast<double>(k + 1) * w;
 }
 
-__device__ __forceinline__ void child_box(const BoxD& P, const int32_t m[5], int64_t child, BoxD* out) {
-  int64_t k[5], rem = child;
-  for (int j = 4; j >= 0; --j) { k[j] = rem % m[j]; rem /= m[j]; }
+__device__ __forceinline__ void child_index(const uint32_t m[5], uint32_t child, uint32_t k[5]) {
+  for (int j = 4; j >= 0; --j) { k[j] = child % m[j]; child /= m[j]; }
+}
+
+__device__ __forceinline__ void child_box(const BoxD& P, const uint32_t m[5], uint32_t child, BoxD* out) {
+  uint32_t k[5];
+  child_index(m, child, k);
   for (int j = 0; j < 5; ++j) child_edge(P.lo[j], P.hi[j], m[j], k[j], &out->lo[j], &out->hi[j]);
+}
+
+__device__ __forceinline__ void level_box(const BoxD* parents, const Shape& sh, uint32_t b, BoxD* out) {
+  child_box(parents[b / sh.nc], sh.m, b % sh.nc, out);
 }
 
 // ---------------------------------------------------------------------------
@@ -103,21 +114,6 @@ __device__ __forceinline__ void prep_one(const double* h, bool active, HitRec* o
   *o = r;
 }
 
-// one thread per hit; also clears the vote histogram of the first level
-__global__ void k_prep(const double* __restrict__ hits, const uint8_t* __restrict__ active,
-                       int32_t n_hits, HitRec* __restrict__ out, uint32_t* __restrict__ hist,
-                       int32_t n_bins, uint32_t* __restrict__ status, int64_t* __restrict__ n_bad) {
-  int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  for (int32_t b = i; b < n_bins && hist; b += gridDim.x * blockDim.x) hist[b] = 0u;
-  if (i >= n_hits) return;
-  bool bad;
-  prep_one(hits + 8 * static_cast<int64_t>(i), active ? active[i] != 0 : true, &out[i], &bad);
-  if (bad) {
-    atomicOr(status, kStBadHit);
-    atomicAdd(reinterpret_cast<unsigned long long*>(n_bad), 1ull);
-  }
-}
-
 // ---------------------------------------------------------------------------
 // frame of a triple at its centre (mirrored to kappa > 0, Appendix A assumes R > 0)
 struct Frame {
@@ -125,8 +121,8 @@ struct Frame {
   double sig, R, xc, yc, sp0, cp0;
 };
 
-__device__ __forceinline__ Frame triple_frame(const BoxD& P, const int32_t m[5], int64_t k0, int64_t k1,
-                                              int64_t k2) {
+__device__ __forceinline__ Frame triple_frame(const BoxD& P, const uint32_t m[5], uint32_t k0, uint32_t k1,
+                                              uint32_t k2) {
   Frame f;
   child_edge(P.lo[0], P.hi[0], m[0], k0, &f.Dd.lo, &f.Dd.hi);
   child_edge(P.lo[1], P.hi[1], m[1], k1, &f.Fi.lo, &f.Fi.hi);
@@ -234,28 +230,65 @@ __device__ __forceinline__ bool stereo_vote(const PairQ& q, double R, double sig
 }
 
 // ---------------------------------------------------------------------------
-// the vote kernel: one lane per box, 256 consecutive boxes per workgroup.
-// Grid: ceil(n_boxes / 256) workgroups.  hist (nullable) receives the vote
-// histogram (bins 0..n_bins-1; votes above are flagged in status).
+// hit preparation.  One thread per hit; also clears the vote histogram.  With
+// `ev` set it starts an event: resets the event state, writes the search
+// range box and marks every hit unassigned.
+__global__ void k_prep(const double* __restrict__ hits, const uint8_t* __restrict__ active, int32_t n_hits,
+                       HitRec* __restrict__ out, uint32_t* __restrict__ hist, int32_t n_bins,
+                       uint32_t* __restrict__ status, int64_t* __restrict__ n_bad, EventState* __restrict__ ev,
+                       int32_t* __restrict__ n_out, BoxD* __restrict__ range_dst, BoxD range,
+                       int32_t* __restrict__ assigned) {
+  const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int32_t stride = gridDim.x * blockDim.x;
+  if (ev && i == 0) {
+    EventState e{};
+    *ev = e;
+    if (n_out) *n_out = 0;
+    *range_dst = range;
+  }
+  for (int32_t b = i; b < n_bins && hist; b += stride) hist[b] = 0u;
+  for (int32_t h = i; h < n_hits; h += stride) {
+    bool bad;
+    prep_one(hits + 8 * static_cast<int64_t>(h), active ? active[h] != 0 : true, &out[h], &bad);
+    if (assigned) assigned[h] = -1;
+    if (bad) {
+      atomicOr(status, kStBadHit);
+      atomicAdd(reinterpret_cast<unsigned long long*>(n_bad), 1ull);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// the vote kernel.  A workgroup owns BX consecutive boxes (one lane each) and
+// splits the hits of every chunk over kWG / BX slices (whole waves); the
+// slices' counts are summed in LDS.  Per chunk, the workgroup first stages
+// the (triple, hit) quantities of the triples its boxes span.
+// hist (nullable) receives the vote histogram of bins 0..n_bins-1.
+template <int BX>
 __global__ void __launch_bounds__(kWG) k_vote(const HitRec* __restrict__ hits, int32_t n_hits,
                                               const BoxD* __restrict__ parents, Shape sh,
                                               uint16_t* __restrict__ votes, uint32_t* __restrict__ hist,
                                               int32_t n_bins, uint32_t* __restrict__ status,
                                               const EventState* __restrict__ ev) {
+  constexpr int HS = kWG / BX;
+  static_assert(BX % 64 == 0 && HS * BX == kWG, "slices are whole waves");
   if (ev && ev->done) return;
   __shared__ double sq[13][kCap + 16];
   __shared__ int8_t sflag[kCap + 16];
   __shared__ uint32_t shist[kHistLds];
+  __shared__ int32_t sred[HS][BX];
 
-  const int64_t b0 = static_cast<int64_t>(blockIdx.x) * kWG;
-  const int64_t b_last = min(b0 + kWG, sh.n_boxes) - 1;
-  const int64_t b = b0 + threadIdx.x;
+  const uint32_t tid = threadIdx.x;
+  const uint32_t bl = tid % BX, sl = tid / BX;
+  const uint32_t b0 = blockIdx.x * BX;
+  const uint32_t b_last = min(b0 + BX, sh.n_boxes) - 1;
+  const uint32_t b = b0 + bl;
   const bool live = b < sh.n_boxes;
-  const int64_t bb = live ? b : b_last;
+  const uint32_t bb = live ? b : b_last;
 
   // global triple index of a box: parent * m012 + (child / m34)
-  auto triple_of = [&](int64_t x) { return (x / sh.nc) * sh.m012 + (x % sh.nc) / sh.m34; };
-  const int64_t t_first = triple_of(b0);
+  auto triple_of = [&](uint32_t x) { return (x / sh.nc) * sh.m012 + (x % sh.nc) / sh.m34; };
+  const uint32_t t_first = triple_of(b0);
   const int32_t nt = static_cast<int32_t>(triple_of(b_last) - t_first + 1);
   const int32_t my_tl = static_cast<int32_t>(triple_of(bb) - t_first);
   const int32_t hc = max(1, kCap / nt);          // hits per chunk
@@ -264,10 +297,9 @@ __global__ void __launch_bounds__(kWG) k_vote(const HitRec* __restrict__ hits, i
   const int32_t pitch = hc + ((nt > 1 && nt <= 16) ? 1 : 0);
 
   // this lane's box: triple frame and (z0, tanl) centre
-  const int64_t par = bb / sh.nc, child = bb % sh.nc;
-  int64_t k[5], rem = child;
-  for (int j = 4; j >= 0; --j) { k[j] = rem % sh.m[j]; rem /= sh.m[j]; }
-  const BoxD P = parents[par];
+  uint32_t k[5];
+  child_index(sh.m, bb % sh.nc, k);
+  const BoxD& P = parents[bb / sh.nc];
   const Frame f = triple_frame(P, sh.m, k[0], k[1], k[2]);
   double zlo, zhi, llo, lhi;
   child_edge(P.lo[3], P.hi[3], sh.m[3], k[3], &zlo, &zhi);
@@ -280,17 +312,16 @@ __global__ void __launch_bounds__(kWG) k_vote(const HitRec* __restrict__ hits, i
     const int32_t nh = min(hc, n_hits - h0);
     __syncthreads();
     // stage (triple, hit) quantities: thread r -> (tl = r / hc, hl = r % hc)
-    for (int32_t r = threadIdx.x; r < nt * hc; r += kWG) {
+    for (int32_t r = tid; r < nt * hc; r += kWG) {
       const int32_t tl = r / hc, hl = r % hc;
       const int32_t slot = tl * pitch + hl;
       if (hl >= nh) continue;
       const HitRec h = hits[h0 + hl];
       if (!h.use) { sflag[slot] = -1; continue; }
-      const int64_t t = t_first + tl;
-      const int64_t tp = t / sh.m012, tc = t % sh.m012;
-      const int64_t t0 = tc / (static_cast<int64_t>(sh.m[1]) * sh.m[2]);
-      const int64_t t1 = (tc / sh.m[2]) % sh.m[1], t2 = tc % sh.m[2];
-      const Frame ft = triple_frame(parents[tp], sh.m, t0, t1, t2);
+      const uint32_t t = t_first + tl;
+      const uint32_t tc = t % sh.m012;
+      const uint32_t t0 = tc / sh.m12, t1 = (tc / sh.m[2]) % sh.m[1], t2 = tc % sh.m[2];
+      const Frame ft = triple_frame(parents[t / sh.m012], sh.m, t0, t1, t2);
       const Iv G = residual_G(ft, h);
       if (h.axial) {
         bool v = h_contains0(G, ft.K, ft.sig * h.d, h.band) || h_contains0(G, ft.K, ft.sig * (-h.d), h.band);
@@ -305,7 +336,7 @@ __global__ void __launch_bounds__(kWG) k_vote(const HitRec* __restrict__ hits, i
       }
     }
     __syncthreads();
-    for (int32_t hl = 0; hl < nh; ++hl) {
+    for (int32_t hl = sl; hl < nh; hl += HS) {
       const int32_t slot = my_tl * pitch + hl;
       const int8_t fl = sflag[slot];
       if (fl < 2) { nv += fl > 0 ? 1 : 0; continue; }
@@ -319,22 +350,29 @@ __global__ void __launch_bounds__(kWG) k_vote(const HitRec* __restrict__ hits, i
       if (stereo_vote(q, f.R, f.sig, f.K, z0, lam, lamR, lam2, tt, tt * tt, h.d, h.band)) ++nv;
     }
   }
-  if (live) votes[b] = static_cast<uint16_t>(nv);
+  if (HS > 1) {
+    sred[sl][bl] = nv;
+    __syncthreads();
+    if (sl == 0)
+      for (int s = 1; s < HS; ++s) nv += sred[s][bl];
+  }
+  const bool owner = sl == 0 && live;
+  if (owner) votes[b] = static_cast<uint16_t>(nv);
 
   if (hist) {
     const bool in_lds = n_bins <= kHistLds;
     if (in_lds) {
-      for (int32_t i = threadIdx.x; i < n_bins; i += kWG) shist[i] = 0u;
+      for (int32_t i = tid; i < n_bins; i += kWG) shist[i] = 0u;
       __syncthreads();
     }
-    if (live) {
+    if (owner) {
       if (nv >= n_bins) atomicOr(status, kStVoteOverflow);
       else if (in_lds) atomicAdd(&shist[nv], 1u);
       else atomicAdd(&hist[nv], 1u);
     }
     if (in_lds) {
       __syncthreads();
-      for (int32_t i = threadIdx.x; i < n_bins; i += kWG)
+      for (int32_t i = tid; i < n_bins; i += kWG)
         if (shist[i]) atomicAdd(&hist[i], shist[i]);
     }
   }
@@ -342,7 +380,7 @@ __global__ void __launch_bounds__(kWG) k_vote(const HitRec* __restrict__ hits, i
 
 // ---------------------------------------------------------------------------
 // histogram of an existing vote array (used when votes come from the caller)
-__global__ void __launch_bounds__(kWG) k_hist(const uint16_t* __restrict__ votes, int64_t n,
+__global__ void __launch_bounds__(kWG) k_hist(const uint16_t* __restrict__ votes, uint32_t n,
                                               uint32_t* __restrict__ hist, int32_t n_bins,
                                               uint32_t* __restrict__ status) {
   __shared__ uint32_t shist[kHistLds];
@@ -351,8 +389,7 @@ __global__ void __launch_bounds__(kWG) k_hist(const uint16_t* __restrict__ votes
     for (int32_t i = threadIdx.x; i < n_bins; i += kWG) shist[i] = 0u;
     __syncthreads();
   }
-  for (int64_t i = static_cast<int64_t>(blockIdx.x) * kWG + threadIdx.x; i < n;
-       i += static_cast<int64_t>(gridDim.x) * kWG) {
+  for (uint32_t i = blockIdx.x * kWG + threadIdx.x; i < n; i += gridDim.x * kWG) {
     const int32_t v = votes[i];
     if (v >= n_bins) atomicOr(status, kStVoteOverflow);
     else if (in_lds) atomicAdd(&shist[v], 1u);
@@ -365,10 +402,8 @@ __global__ void __launch_bounds__(kWG) k_hist(const uint16_t* __restrict__ votes
   }
 }
 
-__global__ void k_fill_u32(uint32_t* p, int64_t n, uint32_t v) {
-  for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
-       i += static_cast<int64_t>(gridDim.x) * blockDim.x)
-    p[i] = v;
+__global__ void k_fill_u32(uint32_t* p, uint32_t n, uint32_t v) {
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = v;
 }
 
 // ---------------------------------------------------------------------------
@@ -378,14 +413,12 @@ __global__ void k_fill_u32(uint32_t* p, int64_t n, uint32_t v) {
 // order (prefix-sum compaction over the chunks of the grid).
 struct SelInfo { int32_t vstar, need_eq, n_gt, k_eff; };
 
-__device__ __forceinline__ SelInfo threshold(const uint32_t* hist, int32_t n_bins, int32_t k,
-                                             int64_t n_boxes) {
+__device__ __forceinline__ SelInfo threshold(const uint32_t* hist, int32_t n_bins, int32_t k, uint32_t n_boxes) {
   SelInfo s;
-  s.k_eff = static_cast<int32_t>(min(static_cast<int64_t>(k), n_boxes));
+  s.k_eff = static_cast<int32_t>(min(static_cast<uint32_t>(k), n_boxes));
   int64_t cum = 0;
   s.vstar = 0;
   s.need_eq = s.k_eff;
-  s.n_gt = 0;
   for (int32_t v = n_bins - 1; v >= 0; --v) {
     const int64_t c = hist[v];
     if (cum + c >= s.k_eff) { s.vstar = v; s.need_eq = static_cast<int32_t>(s.k_eff - cum); break; }
@@ -395,7 +428,7 @@ __device__ __forceinline__ SelInfo threshold(const uint32_t* hist, int32_t n_bin
   return s;
 }
 
-// block-wide exclusive scan of 0/1 flags (256 lanes); returns the total
+// block-wide exclusive scan of 0/1 flags (kWG lanes); returns the total
 __device__ __forceinline__ int32_t block_scan(int32_t flag, int32_t* excl, int32_t* sbuf) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const unsigned long long m = __ballot(flag != 0);
@@ -419,8 +452,8 @@ __device__ __forceinline__ int32_t block_sum(int32_t v, int32_t* sbuf) {
   return t;
 }
 
-__global__ void __launch_bounds__(kWG) k_select_count(const uint16_t* __restrict__ votes, int64_t n_boxes,
-                                                      int64_t chunk, const uint32_t* __restrict__ hist,
+__global__ void __launch_bounds__(kWG) k_select_count(const uint16_t* __restrict__ votes, uint32_t n_boxes,
+                                                      uint32_t chunk, const uint32_t* __restrict__ hist,
                                                       int32_t n_bins, int32_t k, int32_t* __restrict__ cnt,
                                                       const EventState* __restrict__ ev) {
   if (ev && ev->done) return;
@@ -428,9 +461,9 @@ __global__ void __launch_bounds__(kWG) k_select_count(const uint16_t* __restrict
   __shared__ int32_t sbuf[kWG / 64];
   if (threadIdx.x == 0) si = threshold(hist, n_bins, k, n_boxes);
   __syncthreads();
-  const int64_t beg = blockIdx.x * chunk, end = min(beg + chunk, n_boxes);
+  const uint32_t beg = blockIdx.x * chunk, end = min(beg + chunk, n_boxes);
   int32_t gt = 0, eq = 0;
-  for (int64_t i = beg + threadIdx.x; i < end; i += kWG) {
+  for (uint32_t i = beg + threadIdx.x; i < end; i += kWG) {
     const int32_t v = votes[i];
     gt += v > si.vstar;
     eq += v == si.vstar;
@@ -443,8 +476,8 @@ __global__ void __launch_bounds__(kWG) k_select_count(const uint16_t* __restrict
 // writes the selection; the last workgroup to finish orders it, writes the
 // selected boxes, clears the histogram and resets the completion counter.
 __global__ void __launch_bounds__(kWG) k_select_write(
-    const uint16_t* __restrict__ votes, int64_t n_boxes, int64_t chunk, uint32_t* __restrict__ hist,
-    int32_t n_bins, int32_t k, const int32_t* __restrict__ cnt, int64_t* __restrict__ tmp_idx,
+    const uint16_t* __restrict__ votes, uint32_t n_boxes, uint32_t chunk, uint32_t* __restrict__ hist,
+    int32_t n_bins, int32_t k, const int32_t* __restrict__ cnt, uint32_t* __restrict__ tmp_idx,
     uint32_t* __restrict__ done_counter, const BoxD* __restrict__ parents, Shape sh,
     BoxD* __restrict__ out_boxes, int64_t* __restrict__ out_index, uint16_t* __restrict__ out_votes,
     EventState* __restrict__ ev, int32_t v_min_stop) {
@@ -453,6 +486,8 @@ __global__ void __launch_bounds__(kWG) k_select_write(
   __shared__ int32_t sbuf[kWG / 64];
   __shared__ int32_t base_gt, base_eq;
   __shared__ int32_t is_last;
+  __shared__ uint32_t s_idx[kMaxTopK];
+  __shared__ uint16_t s_v[kMaxTopK];
   if (threadIdx.x == 0) si = threshold(hist, n_bins, k, n_boxes);
   __syncthreads();
   // prefix over earlier chunks
@@ -465,10 +500,14 @@ __global__ void __launch_bounds__(kWG) k_select_write(
   pe = block_sum(pe, sbuf);
   if (threadIdx.x == 0) { base_gt = pg; base_eq = pe; }
   __syncthreads();
-  const int64_t beg = blockIdx.x * chunk, end = min(beg + chunk, n_boxes);
+  const int32_t my_gt = cnt[2 * blockIdx.x], my_eq = cnt[2 * blockIdx.x + 1];
+  const bool need = (my_gt > 0) || (my_eq > 0 && base_eq < si.need_eq);
+  const uint32_t beg = blockIdx.x * chunk, end = min(beg + chunk, n_boxes);
   int32_t run_gt = base_gt, run_eq = base_eq;
-  for (int64_t i0 = beg; i0 < end && (run_gt < si.n_gt || run_eq < si.need_eq); i0 += kWG) {
-    const int64_t i = i0 + threadIdx.x;
+  const int32_t stop_gt = base_gt + my_gt;
+  const int32_t stop_eq = min(base_eq + my_eq, si.need_eq);
+  for (uint32_t i0 = beg; need && i0 < end && (run_gt < stop_gt || run_eq < stop_eq); i0 += kWG) {
+    const uint32_t i = i0 + threadIdx.x;
     const int32_t v = i < end ? votes[i] : -1;
     const int32_t fg = v > si.vstar, fe = v == si.vstar;
     int32_t xg, xe;
@@ -497,20 +536,25 @@ __global__ void __launch_bounds__(kWG) k_select_write(
     s_vmax = vm;
     s_nmax = nm;
   }
-  // order the k_eff entries by (votes desc, index asc)
   const int32_t ke = si.k_eff;
   for (int32_t a = threadIdx.x; a < ke; a += kWG) {
-    const int64_t ia = __atomic_load_n(&tmp_idx[a], __ATOMIC_RELAXED);
-    const int32_t va = votes[ia];
+    const uint32_t ia = __atomic_load_n(&tmp_idx[a], __ATOMIC_RELAXED);
+    s_idx[a] = ia;
+    s_v[a] = votes[ia];
+  }
+  __syncthreads();
+  // order the k_eff entries by (votes desc, index asc)
+  for (int32_t a = threadIdx.x; a < ke; a += kWG) {
+    const uint32_t ia = s_idx[a];
+    const int32_t va = s_v[a];
     int32_t rank = 0;
     for (int32_t c = 0; c < ke; ++c) {
-      const int64_t ic = __atomic_load_n(&tmp_idx[c], __ATOMIC_RELAXED);
-      const int32_t vc = votes[ic];
-      rank += (vc > va) || (vc == va && ic < ia);
+      const int32_t vc = s_v[c];
+      rank += (vc > va) || (vc == va && s_idx[c] < ia);
     }
     out_index[rank] = ia;
     out_votes[rank] = static_cast<uint16_t>(va);
-    if (out_boxes) child_box(parents[ia / sh.nc], sh.m, ia % sh.nc, &out_boxes[rank]);
+    if (out_boxes) level_box(parents, sh, ia, &out_boxes[rank]);
   }
   __syncthreads();
   for (int32_t i = threadIdx.x; i < n_bins; i += kWG) hist[i] = 0u;
@@ -529,141 +573,80 @@ __global__ void __launch_bounds__(kWG) k_select_write(
 // estimate from the max-vote cells of a level (Sec. 3.3): mean of the cell
 // centres (phi0 relative to the first cell's centre, in (-pi, pi]) and half
 // the extent of their union.  Sums are pairwise over the level's boxes in
-// index order on a zero-padded power-of-two array: each lane reduces an
-// aligned power-of-two segment with a binary-counter stack (the same tree),
-// then adjacent lane sums are paired in LDS.  One workgroup.
+// index order on a zero-padded power-of-two array: k_est_partial reduces
+// aligned 256-box chunks (one box per lane, adjacent pairs in LDS), and
+// k_est_final reduces the chunk sums on the same tree.  vmax and the first
+// max-vote box come from the level's selection (rank 0).
 struct EstimateOut {
   double p[5], err[5];
   int32_t vmax, n_argmax;
 };
 
-__global__ void __launch_bounds__(kWG) k_estimate(const BoxD* __restrict__ parents, Shape sh,
-                                                  const uint16_t* __restrict__ votes,
-                                                  EstimateOut* __restrict__ out, EventState* __restrict__ ev) {
-  if (ev && ev->done) return;
-  __shared__ double stack[kWG][kEstLevels];
-  __shared__ double lsum[kWG];
-  __shared__ double smin[kWG], smax[kWG];
-  __shared__ int32_t sbuf[kWG / 64];
-  __shared__ int32_t s_vmax;
-  __shared__ double s_c0;
-  const int64_t n = sh.n_boxes;
-  // vmax and the first max-vote box
-  int32_t vm = 0;
-  for (int64_t i = threadIdx.x; i < n; i += kWG) vm = max(vm, static_cast<int32_t>(votes[i]));
-  for (int o = 32; o > 0; o >>= 1) vm = max(vm, __shfl_down(vm, o, 64));
-  if ((threadIdx.x & 63) == 0) sbuf[threadIdx.x >> 6] = vm;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    int32_t t = 0;
-    for (int w = 0; w < kWG / 64; ++w) t = max(t, sbuf[w]);
-    s_vmax = t;
+constexpr int kEstQ = 16;        // 5 sums, 5 minima, 5 maxima, count
+
+__device__ __forceinline__ void tree_step(double (*s)[kWG], int w) {
+  // s[q][i] = combine(s[q][2i], s[q][2i + 1]) for i < w / 2
+  const int t = threadIdx.x;
+  double v[kEstQ];
+  const bool act = t < w / 2;
+  if (act) {
+#pragma unroll
+    for (int q = 0; q < 5; ++q) v[q] = s[q][2 * t] + s[q][2 * t + 1];
+#pragma unroll
+    for (int q = 5; q < 10; ++q) v[q] = fmin(s[q][2 * t], s[q][2 * t + 1]);
+#pragma unroll
+    for (int q = 10; q < 15; ++q) v[q] = fmax(s[q][2 * t], s[q][2 * t + 1]);
+    v[15] = s[15][2 * t] + s[15][2 * t + 1];
   }
   __syncthreads();
-  const int32_t vmax = s_vmax;
-  int64_t first = n;
-  for (int64_t i = threadIdx.x; i < n; i += kWG)
-    if (votes[i] == vmax) { first = i; break; }
-  // min over lanes (at most 256 candidates)
-  lsum[threadIdx.x] = static_cast<double>(first);
+  if (act)
+#pragma unroll
+    for (int q = 0; q < kEstQ; ++q) s[q][t] = v[q];
   __syncthreads();
-  if (threadIdx.x == 0) {
-    int64_t f = n;
-    for (int w = 0; w < kWG; ++w) f = min(f, static_cast<int64_t>(lsum[w]));
-    BoxD bx;
-    child_box(parents[f / sh.nc], sh.m, f % sh.nc, &bx);
-    s_c0 = 0.5 * (bx.lo[1] + bx.hi[1]);
-  }
-  __syncthreads();
-  const double c0 = s_c0;
-  int64_t p2 = 1;
-  while (p2 < n) p2 <<= 1;
-  const int32_t nthr = static_cast<int32_t>(min<int64_t>(kWG, p2));
-  const int64_t seg = p2 / nthr;
-  int32_t cnt = 0;
-  for (int64_t i = threadIdx.x; i < n; i += kWG) cnt += votes[i] == vmax;
-  for (int o = 32; o > 0; o >>= 1) cnt += __shfl_down(cnt, o, 64);
-  if ((threadIdx.x & 63) == 0) sbuf[threadIdx.x >> 6] = cnt;
-  __syncthreads();
-  int32_t count = 0;
-  for (int w = 0; w < kWG / 64; ++w) count += sbuf[w];
-  for (int j = 0; j < 5; ++j) {
-    double lo_min = INFINITY, hi_max = -INFINITY;
-    double total = 0.0;
-    if (static_cast<int32_t>(threadIdx.x) < nthr) {
-      const int64_t beg = threadIdx.x * seg;
-      for (int64_t s = 0; s < seg; ++s) {
-        const int64_t i = beg + s;
-        double v = 0.0;
-        if (i < n && votes[i] == vmax) {
-          BoxD bx;
-          child_box(parents[i / sh.nc], sh.m, i % sh.nc, &bx);
-          double lo = bx.lo[j], hi = bx.hi[j];
-          const double c = 0.5 * (lo + hi);
-          if (j == 1) {
-            const double dv = c - c0;
-            double shift = 0.0;
-            if (dv > kPi) shift = -kTwoPi;
-            else if (dv <= -kPi) shift = kTwoPi;
-            v = dv + shift;
-            lo = lo + shift;
-            hi = hi + shift;
-          } else {
-            v = c;
-          }
-          lo_min = fmin(lo_min, lo);
-          hi_max = fmax(hi_max, hi);
-        }
-        int64_t c = s;
-        int lvl = 0;
-        while (c & 1) { v = stack[threadIdx.x][lvl] + v; c >>= 1; ++lvl; }
-        stack[threadIdx.x][lvl] = v;
-      }
-      int lg = 0;
-      while ((static_cast<int64_t>(1) << lg) < seg) ++lg;
-      total = stack[threadIdx.x][lg];
-    }
-    lsum[threadIdx.x] = total;
-    smin[threadIdx.x] = lo_min;
-    smax[threadIdx.x] = hi_max;
-    __syncthreads();
-    for (int32_t w = nthr; w > 1; w >>= 1) {
-      double a = 0.0, mn = 0.0, mx = 0.0;
-      const bool act = static_cast<int32_t>(threadIdx.x) < w / 2;
-      if (act) {
-        a = lsum[2 * threadIdx.x] + lsum[2 * threadIdx.x + 1];
-        mn = fmin(smin[2 * threadIdx.x], smin[2 * threadIdx.x + 1]);
-        mx = fmax(smax[2 * threadIdx.x], smax[2 * threadIdx.x + 1]);
-      }
-      __syncthreads();
-      if (act) { lsum[threadIdx.x] = a; smin[threadIdx.x] = mn; smax[threadIdx.x] = mx; }
-      __syncthreads();
-    }
-    if (threadIdx.x == 0) {
-      const double S = lsum[0];
-      double pj;
-      if (j == 1) {
-        pj = c0 + S / static_cast<double>(count);
-        if (pj < 0.0) pj += kTwoPi;
-        if (pj >= kTwoPi) pj -= kTwoPi;
-      } else {
-        pj = S / static_cast<double>(count);
-      }
-      const double ej = 0.5 * (smax[0] - smin[0]);
-      if (out) { out->p[j] = pj; out->err[j] = ej; }
-      if (ev) { ev->p[j] = pj; ev->err[j] = ej; }
-    }
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) {
-    if (out) { out->vmax = vmax; out->n_argmax = count; }
-    if (ev) { ev->vmax = vmax; ev->n_argmax = count; ev->n_assigned = 0; }
-  }
 }
 
-// ---------------------------------------------------------------------------
-// hit finding (Sec. 3.3): every active hit that votes for the box
-// estimate +- scale x error is assigned to the current helix
+__global__ void __launch_bounds__(kWG) k_est_partial(const BoxD* __restrict__ parents, Shape sh,
+                                                     const uint16_t* __restrict__ votes,
+                                                     const BoxD* __restrict__ first_box,
+                                                     const uint16_t* __restrict__ first_votes,
+                                                     double* __restrict__ part, const EventState* __restrict__ ev) {
+  if (ev && ev->done) return;
+  __shared__ double s[kEstQ][kWG];
+  const int32_t vmax = first_votes[0];
+  const double c0 = 0.5 * (first_box->lo[1] + first_box->hi[1]);
+  const uint32_t i = blockIdx.x * kWG + threadIdx.x;
+  double v[kEstQ];
+  for (int q = 0; q < 5; ++q) { v[q] = 0.0; v[5 + q] = INFINITY; v[10 + q] = -INFINITY; }
+  v[15] = 0.0;
+  if (i < sh.n_boxes && votes[i] == vmax) {
+    BoxD bx;
+    level_box(parents, sh, i, &bx);
+    for (int j = 0; j < 5; ++j) {
+      double lo = bx.lo[j], hi = bx.hi[j];
+      const double c = 0.5 * (lo + hi);
+      if (j == 1) {
+        const double dv = c - c0;
+        double shift = 0.0;
+        if (dv > kPi) shift = -kTwoPi;
+        else if (dv <= -kPi) shift = kTwoPi;
+        v[j] = dv + shift;
+        lo = lo + shift;
+        hi = hi + shift;
+      } else {
+        v[j] = c;
+      }
+      v[5 + j] = lo;
+      v[10 + j] = hi;
+    }
+    v[15] = 1.0;
+  }
+  for (int q = 0; q < kEstQ; ++q) s[q][threadIdx.x] = v[q];
+  __syncthreads();
+  for (int w = kWG; w > 1; w >>= 1) tree_step(s, w);
+  if (threadIdx.x < kEstQ) part[blockIdx.x * kEstQ + threadIdx.x] = s[threadIdx.x][0];
+}
+
+// hit finding (Sec. 3.3): does an active hit vote for the box estimate +- scale x error
 __device__ __forceinline__ bool pair_vote_box(const BoxD& b, const HitRec& h) {
   if (!h.use) return false;
   Frame f;
@@ -690,55 +673,120 @@ __device__ __forceinline__ bool pair_vote_box(const BoxD& b, const HitRec& h) {
   return stereo_vote(q, f.R, f.sig, f.K, z0, lam, lam * f.R, lam * lam, h.tant, h.tant * h.tant, h.d, h.band);
 }
 
-__global__ void __launch_bounds__(kWG) k_hitfind(HitRec* __restrict__ hits, int32_t n_hits,
-                                                 EventState* __restrict__ ev, double scale,
-                                                 int32_t* __restrict__ assigned) {
-  if (ev->done) return;
-  const int32_t i = blockIdx.x * kWG + threadIdx.x;
-  if (i >= n_hits) return;
-  BoxD E;
-  for (int j = 0; j < 5; ++j) {
-    const double w = scale * ev->err[j];
-    E.lo[j] = ev->p[j] - w;
-    E.hi[j] = ev->p[j] + w;
-  }
-  HitRec h = hits[i];
-  if (pair_vote_box(E, h)) {
-    hits[i].use = 0;
-    if (assigned) assigned[i] = ev->n_out;
-    atomicAdd(&ev->n_assigned, 1);
-  }
-}
-
 // helix record: {p[5], err[5], votes, n_assigned, n_argmax, status}
 struct HelixOut {
   double p[5], err[5];
   int32_t votes, n_assigned, n_argmax, status;
 };
 
-__global__ void k_record(EventState* __restrict__ ev, HelixOut* __restrict__ out, int32_t max_out,
-                         int32_t* __restrict__ n_out) {
-  if (threadIdx.x != 0 || ev->done) return;
-  const int32_t k = ev->n_out;
-  if (k < max_out) {
-    HelixOut h;
-    for (int j = 0; j < 5; ++j) { h.p[j] = ev->p[j]; h.err[j] = ev->err[j]; }
-    h.votes = ev->vmax;
-    h.n_assigned = ev->n_assigned;
-    h.n_argmax = ev->n_argmax;
-    h.status = 0;
-    out[k] = h;
-    ev->n_out = k + 1;
+// One workgroup: combines the n_part chunk sums (n_part a power of two) on
+// the pairwise tree, writes the estimate; with `hits` set it then runs hit
+// finding for the event and records the helix.
+__global__ void __launch_bounds__(kWG) k_est_final(const double* __restrict__ part, int32_t n_part,
+                                                   const BoxD* __restrict__ first_box,
+                                                   const uint16_t* __restrict__ first_votes,
+                                                   EstimateOut* __restrict__ out, EventState* __restrict__ ev,
+                                                   HitRec* __restrict__ hits, int32_t n_hits, double scale,
+                                                   int32_t* __restrict__ assigned, HelixOut* __restrict__ hout,
+                                                   int32_t max_out, int32_t* __restrict__ n_out) {
+  if (ev && ev->done) return;
+  __shared__ double s[kEstQ][kWG];
+  __shared__ double stack[kWG][kEstLevels];
+  __shared__ double sp[5], se[5];
+  __shared__ int32_t s_count, s_assigned;
+  const int t = threadIdx.x;
+  // each lane reduces `seg` consecutive chunk sums with a binary-counter stack
+  const int32_t nthr = min(kWG, n_part);
+  const int32_t seg = n_part / nthr;
+  for (int q = 0; q < kEstQ; ++q) {
+    double acc = 0.0;
+    if (t < nthr) {
+      const int32_t beg = t * seg;
+      if (q < 5 || q == 15) {
+        for (int32_t i = 0; i < seg; ++i) {
+          double v = part[(beg + i) * kEstQ + q];
+          int32_t c = i, lvl = 0;
+          while (c & 1) { v = stack[t][lvl] + v; c >>= 1; ++lvl; }
+          stack[t][lvl] = v;
+        }
+        int lg = 0;
+        while ((1 << lg) < seg) ++lg;
+        acc = stack[t][lg];
+      } else {
+        acc = q < 10 ? INFINITY : -INFINITY;
+        for (int32_t i = 0; i < seg; ++i) {
+          const double v = part[(beg + i) * kEstQ + q];
+          acc = q < 10 ? fmin(acc, v) : fmax(acc, v);
+        }
+      }
+    } else {
+      acc = (q >= 5 && q < 10) ? INFINITY : ((q >= 10 && q < 15) ? -INFINITY : 0.0);
+    }
+    s[q][t] = acc;
   }
-  if (n_out) *n_out = ev->n_out;
-  if (ev->n_assigned == 0 || ev->n_out >= max_out) ev->done = 1;
-}
-
-__global__ void k_event_init(EventState* ev, int32_t* n_out) {
-  if (threadIdx.x == 0) {
-    EventState e{};
-    *ev = e;
-    if (n_out) *n_out = 0;
+  __syncthreads();
+  for (int w = kWG; w > 1; w >>= 1) tree_step(s, w);
+  if (t == 0) {
+    const double c0 = 0.5 * (first_box->lo[1] + first_box->hi[1]);
+    const int32_t count = static_cast<int32_t>(s[15][0]);
+    for (int j = 0; j < 5; ++j) {
+      const double S = s[j][0];
+      double pj;
+      if (j == 1) {
+        pj = c0 + S / static_cast<double>(count);
+        if (pj < 0.0) pj += kTwoPi;
+        if (pj >= kTwoPi) pj -= kTwoPi;
+      } else {
+        pj = S / static_cast<double>(count);
+      }
+      sp[j] = pj;
+      se[j] = 0.5 * (s[10 + j][0] - s[5 + j][0]);
+    }
+    s_count = count;
+    s_assigned = 0;
+    if (out) {
+      for (int j = 0; j < 5; ++j) { out->p[j] = sp[j]; out->err[j] = se[j]; }
+      out->vmax = first_votes[0];
+      out->n_argmax = count;
+    }
+  }
+  __syncthreads();
+  if (!ev) return;
+  // hit finding: every still-active hit voting for estimate +- scale x error
+  BoxD E;
+  for (int j = 0; j < 5; ++j) {
+    const double w = scale * se[j];
+    E.lo[j] = sp[j] - w;
+    E.hi[j] = sp[j] + w;
+  }
+  const int32_t k = ev->n_out;
+  int32_t mine = 0;
+  for (int32_t i = t; i < n_hits; i += kWG) {
+    if (pair_vote_box(E, hits[i])) {
+      hits[i].use = 0;
+      if (assigned) assigned[i] = k;
+      ++mine;
+    }
+  }
+  if (mine) atomicAdd(&s_assigned, mine);
+  __syncthreads();
+  if (t == 0) {
+    const int32_t na = s_assigned;
+    if (k < max_out) {
+      HelixOut h;
+      for (int j = 0; j < 5; ++j) { h.p[j] = sp[j]; h.err[j] = se[j]; }
+      h.votes = first_votes[0];
+      h.n_assigned = na;
+      h.n_argmax = s_count;
+      h.status = 0;
+      hout[k] = h;
+      ev->n_out = k + 1;
+    }
+    for (int j = 0; j < 5; ++j) { ev->p[j] = sp[j]; ev->err[j] = se[j]; }
+    ev->n_assigned = na;
+    ev->n_argmax = s_count;
+    if (n_out) *n_out = ev->n_out;
+    if (na == 0 || ev->n_out >= max_out) ev->done = 1;
   }
 }
 

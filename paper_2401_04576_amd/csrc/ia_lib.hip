@@ -28,7 +28,8 @@ namespace {
 
 constexpr size_t kAlign = 256;
 constexpr int32_t kMaxHits = 65535;
-constexpr int32_t kMaxTopK = 4096;
+constexpr int32_t kMaxTopK = ia::kMaxTopK;
+constexpr int64_t kMaxLevelBoxes = (int64_t(1) << 31) - 1;
 constexpr int64_t kSelChunkMin = 4096;
 constexpr int32_t kSelMaxGroups = 1024;
 // k_estimate: 256 lanes x segments of at most 2^(kEstLevels - 1) boxes
@@ -51,6 +52,7 @@ struct ia_ctx {
   size_t used = 0;
   std::string err;
   bool profiling = false;
+  int32_t tile_override = 0;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> marks;
 };
 
@@ -89,35 +91,45 @@ bool make_shape(const int32_t m[5], int64_t n_parents, Shape* sh) {
   int64_t nc = 1;
   for (int j = 0; j < 5; ++j) {
     if (m[j] < 1 || m[j] > (1 << 20)) return false;
-    sh->m[j] = m[j];
+    sh->m[j] = static_cast<uint32_t>(m[j]);
     nc *= m[j];
-    if (nc > (int64_t(1) << 40)) return false;
+    if (nc > kMaxLevelBoxes) return false;
   }
+  if (n_parents < 1 || nc * n_parents > kMaxLevelBoxes) return false;
+  sh->nc = static_cast<uint32_t>(nc);
+  sh->m34 = static_cast<uint32_t>(m[3]) * static_cast<uint32_t>(m[4]);
+  sh->m012 = static_cast<uint32_t>(m[0]) * static_cast<uint32_t>(m[1]) * static_cast<uint32_t>(m[2]);
+  sh->m12 = static_cast<uint32_t>(m[1]) * static_cast<uint32_t>(m[2]);
+  sh->n_boxes = static_cast<uint32_t>(nc * n_parents);
+  sh->n_parents = static_cast<uint32_t>(n_parents);
   sh->pad = 0;
-  sh->nc = nc;
-  sh->m34 = int64_t(m[3]) * m[4];
-  sh->m012 = int64_t(m[0]) * m[1] * m[2];
-  sh->n_boxes = nc * n_parents;
-  return sh->n_boxes <= (int64_t(1) << 38);
+  return true;
 }
 
 hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
 
-int32_t sel_groups(int64_t n_boxes, int64_t* chunk) {
+int32_t sel_groups(int64_t n_boxes, uint32_t* chunk) {
   int64_t g = (n_boxes + kSelChunkMin - 1) / kSelChunkMin;
   g = std::max<int64_t>(1, std::min<int64_t>(g, kSelMaxGroups));
   int64_t c = (n_boxes + g - 1) / g;
   c = (c + ia::kWG - 1) / ia::kWG * ia::kWG;
-  *chunk = c;
+  *chunk = static_cast<uint32_t>(c);
   return static_cast<int32_t>((n_boxes + c - 1) / c);
+}
+
+// chunks of 256 boxes of the zero-padded power-of-two array of a level
+int32_t est_parts(uint32_t n_boxes) {
+  uint32_t p2 = 256;
+  while (p2 < n_boxes) p2 <<= 1;
+  return static_cast<int32_t>(p2 / 256);
 }
 
 // launches the selection of one level: histogram already in `hist`
 ia_status launch_select(ia_ctx* c, const uint16_t* votes, const Shape& sh, const BoxD* parents,
-                        uint32_t* hist, int32_t n_bins, int32_t top_k, int32_t* cnt, int64_t* tmp_idx,
+                        uint32_t* hist, int32_t n_bins, int32_t top_k, int32_t* cnt, uint32_t* tmp_idx,
                         BoxD* out_boxes, int64_t* out_index, uint16_t* out_votes, EventState* ev,
                         int32_t v_min_stop, hipStream_t s) {
-  int64_t chunk;
+  uint32_t chunk;
   const int32_t g = sel_groups(sh.n_boxes, &chunk);
   hipLaunchKernelGGL(ia::k_select_count, dim3(g), dim3(ia::kWG), 0, s, votes, sh.n_boxes, chunk, hist, n_bins,
                      top_k, cnt, ev);
@@ -128,18 +140,39 @@ ia_status launch_select(ia_ctx* c, const uint16_t* votes, const Shape& sh, const
   return IA_OK;
 }
 
+// boxes per workgroup of the vote kernel for a level: large levels use one
+// lane per box; small levels split each chunk's hits over 2 or 4 waves so
+// that the device gets enough workgroups
+int32_t vote_tile(const ia_ctx* c, uint32_t n_boxes) {
+  if (c->tile_override) return c->tile_override;
+  if (n_boxes >= (1u << 19)) return 256;
+  if (n_boxes >= (1u << 17)) return 128;
+  return 64;
+}
+
 // launches the vote kernel, bracketed by events when profiling
 ia_status launch_vote(ia_ctx* c, const HitRec* recs, int32_t n, const BoxD* par, const Shape& sh, uint16_t* votes,
                       uint32_t* hist, int32_t n_bins, EventState* ev, hipStream_t s) {
-  const int64_t grid = (sh.n_boxes + ia::kWG - 1) / ia::kWG;
+  const int32_t bx = vote_tile(c, sh.n_boxes);
+  const uint32_t grid = (sh.n_boxes + bx - 1) / bx;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (c->profiling) {
     IA_HIP(c, hipEventCreate(&e0));
     IA_HIP(c, hipEventCreate(&e1));
     IA_HIP(c, hipEventRecord(e0, s));
   }
-  hipLaunchKernelGGL(ia::k_vote, dim3(static_cast<uint32_t>(grid)), dim3(ia::kWG), 0, s, recs, n, par, sh, votes, hist,
-                     n_bins, &persistent(c)->status, ev);
+  uint32_t* st = &persistent(c)->status;
+  switch (bx) {
+    case 256:
+      hipLaunchKernelGGL(ia::k_vote<256>, dim3(grid), dim3(ia::kWG), 0, s, recs, n, par, sh, votes, hist, n_bins, st, ev);
+      break;
+    case 128:
+      hipLaunchKernelGGL(ia::k_vote<128>, dim3(grid), dim3(ia::kWG), 0, s, recs, n, par, sh, votes, hist, n_bins, st, ev);
+      break;
+    default:
+      hipLaunchKernelGGL(ia::k_vote<64>, dim3(grid), dim3(ia::kWG), 0, s, recs, n, par, sh, votes, hist, n_bins, st, ev);
+      break;
+  }
   if (c->profiling) {
     IA_HIP(c, hipEventRecord(e1, s));
     c->marks.emplace_back(e0, e1);
@@ -148,8 +181,48 @@ ia_status launch_vote(ia_ctx* c, const HitRec* recs, int32_t n, const BoxD* par,
   return IA_OK;
 }
 
-__global__ void k_set_box(BoxD* dst, BoxD v) {
-  if (threadIdx.x == 0) *dst = v;
+// estimate of a level from its selection (rank 0 = first max-vote box)
+ia_status launch_estimate(ia_ctx* c, const BoxD* par, const Shape& sh, const uint16_t* votes, const BoxD* first_box,
+                          const uint16_t* first_votes, double* part, ia::EstimateOut* out, EventState* ev,
+                          HitRec* recs, int32_t n_hits, double scale, int32_t* assigned, ia::HelixOut* hout,
+                          int32_t max_out, int32_t* n_out, hipStream_t s) {
+  const int32_t n_part = est_parts(sh.n_boxes);
+  hipLaunchKernelGGL(ia::k_est_partial, dim3(n_part), dim3(ia::kWG), 0, s, par, sh, votes, first_box, first_votes,
+                     part, ev);
+  hipLaunchKernelGGL(ia::k_est_final, dim3(1), dim3(ia::kWG), 0, s, part, n_part, first_box, first_votes, out, ev,
+                     recs, n_hits, scale, assigned, hout, max_out, n_out);
+  IA_HIP(c, hipGetLastError());
+  return IA_OK;
+}
+
+// scratch layout of ia_find_helices (byte offsets into the arena)
+struct FindLayout {
+  size_t recs, votes, hist, cnt, tmp, selA, selB, range, sel_idx, sel_v, ev, part, total;
+};
+
+void layout_find(int64_t max_level_boxes, int32_t top_k, int32_t max_hits, FindLayout* L) {
+  uint32_t chunk;
+  const int32_t g = sel_groups(max_level_boxes, &chunk);
+  const int32_t n_part = est_parts(static_cast<uint32_t>(max_level_boxes));
+  size_t off = align_up(sizeof(Persistent));
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off += align_up(bytes + 1);
+    return o;
+  };
+  L->recs = take(sizeof(HitRec) * size_t(std::max(1, max_hits)));
+  L->votes = take(sizeof(uint16_t) * size_t(max_level_boxes));
+  L->hist = take(sizeof(uint32_t) * size_t(max_hits + 2));
+  L->cnt = take(sizeof(int32_t) * 2 * size_t(g));
+  L->tmp = take(sizeof(uint32_t) * size_t(top_k));
+  L->selA = take(sizeof(BoxD) * size_t(top_k));
+  L->selB = take(sizeof(BoxD) * size_t(top_k));
+  L->range = take(sizeof(BoxD));
+  L->sel_idx = take(sizeof(int64_t) * size_t(top_k));
+  L->sel_v = take(sizeof(uint16_t) * size_t(top_k));
+  L->ev = take(sizeof(EventState));
+  L->part = take(sizeof(double) * ia::kEstQ * size_t(n_part));
+  L->total = off;
 }
 
 }  // namespace
@@ -212,6 +285,14 @@ ia_status ia_ctx_clear_status(ia_ctx* c) {
   return IA_OK;
 }
 
+ia_status ia_ctx_set_vote_tile(ia_ctx* c, int32_t bx) {
+  if (!c) return IA_ERR_INVALID;
+  if (bx != 0 && bx != 64 && bx != 128 && bx != 256)
+    return fail(c, IA_ERR_INVALID, "vote tile %d not in {0, 64, 128, 256}", bx);
+  c->tile_override = bx;
+  return IA_OK;
+}
+
 ia_status ia_ctx_set_profiling(ia_ctx* c, int32_t enable) {
   if (!c) return IA_ERR_INVALID;
   c->profiling = enable != 0;
@@ -247,24 +328,10 @@ size_t ia_ctx_scratch_needed(const ia_schedule* sc, int32_t max_hits) {
   int64_t nb0 = 1, nc = 1;
   for (int j = 0; j < 5; ++j) { nb0 *= std::max(1, sc->bins[j]); nc *= std::max(1, sc->split[j]); }
   const int64_t nbr = int64_t(std::max(1, sc->top_k)) * nc;
-  const int64_t nb = std::max(nb0, nbr);
-  int64_t chunk;
-  const int32_t g = sel_groups(nb, &chunk);
-  size_t s = align_up(sizeof(Persistent));
-  auto add = [&](size_t bytes) { s += align_up(bytes + 1); };
-  add(sizeof(HitRec) * size_t(std::max(1, max_hits)));
-  add(sizeof(uint16_t) * size_t(nb));
-  add(sizeof(uint32_t) * size_t(max_hits + 2));
-  add(sizeof(int32_t) * 2 * size_t(g));
-  add(sizeof(int64_t) * size_t(std::max(1, sc->top_k)));
-  add(sizeof(BoxD) * size_t(std::max(1, sc->top_k)));
-  add(sizeof(BoxD) * size_t(std::max(1, sc->top_k)));
-  add(sizeof(BoxD));
-  add(sizeof(int64_t) * size_t(std::max(1, sc->top_k)));
-  add(sizeof(uint16_t) * size_t(std::max(1, sc->top_k)));
-  add(sizeof(EventState));
-  add(sizeof(ia::EstimateOut));
-  return s + 4096;
+  const int64_t nb = std::min<int64_t>(std::max(nb0, nbr), kMaxLevelBoxes);
+  FindLayout L;
+  layout_find(nb, std::max(1, sc->top_k), max_hits, &L);
+  return L.total;
 }
 
 ia_status ia_vote_level(ia_ctx* c, const ia_hit* d_hits, int32_t n_hits, const uint8_t* d_active,
@@ -277,7 +344,7 @@ ia_status ia_vote_level(ia_ctx* c, const ia_hit* d_hits, int32_t n_hits, const u
   if (n_parents < 1) return fail(c, IA_ERR_INVALID, "n_parents %d < 1", n_parents);
   if (prec != IA_FP64) return fail(c, IA_ERR_UNSUPPORTED, "precision %d not available", int(prec));
   Shape sh;
-  if (!make_shape(split, n_parents, &sh)) return fail(c, IA_ERR_OVERFLOW, "split / n_parents too large");
+  if (!make_shape(split, n_parents, &sh)) return fail(c, IA_ERR_OVERFLOW, "level exceeds 2^31 - 1 boxes");
   IA_HIP(c, hipSetDevice(c->device));
   reset_bump(c);
   HitRec* recs = bump<HitRec>(c, size_t(std::max(1, n_hits)));
@@ -286,8 +353,8 @@ ia_status ia_vote_level(ia_ctx* c, const ia_hit* d_hits, int32_t n_hits, const u
   Persistent* ps = persistent(c);
   if (n_hits > 0)
     hipLaunchKernelGGL(ia::k_prep, dim3((n_hits + 255) / 256), dim3(256), 0, s,
-                       reinterpret_cast<const double*>(d_hits), d_active, n_hits, recs, nullptr, 0,
-                       &ps->status, &ps->n_bad);
+                       reinterpret_cast<const double*>(d_hits), d_active, n_hits, recs, nullptr, 0, &ps->status,
+                       &ps->n_bad, nullptr, nullptr, nullptr, BoxD{}, nullptr);
   return launch_vote(c, recs, n_hits, reinterpret_cast<const BoxD*>(d_parents), sh, d_votes, nullptr, 0, nullptr, s);
 }
 
@@ -301,22 +368,21 @@ ia_status ia_refine(ia_ctx* c, const ia_box* d_parents, int32_t n_parents, const
   if (top_k < 1 || top_k > kMaxTopK) return fail(c, IA_ERR_INVALID, "top_k %d outside [1, %d]", top_k, kMaxTopK);
   if (vote_bound < 0 || vote_bound > 65535) return fail(c, IA_ERR_INVALID, "vote_bound %d", vote_bound);
   Shape sh;
-  if (!make_shape(split, n_parents, &sh)) return fail(c, IA_ERR_OVERFLOW, "split / n_parents too large");
+  if (!make_shape(split, n_parents, &sh)) return fail(c, IA_ERR_OVERFLOW, "level exceeds 2^31 - 1 boxes");
   IA_HIP(c, hipSetDevice(c->device));
   reset_bump(c);
   const int32_t n_bins = vote_bound + 1;
-  int64_t chunk;
+  uint32_t chunk;
   const int32_t g = sel_groups(sh.n_boxes, &chunk);
   uint32_t* hist = bump<uint32_t>(c, size_t(n_bins));
   int32_t* cnt = bump<int32_t>(c, 2 * size_t(g));
-  int64_t* tmp = bump<int64_t>(c, size_t(top_k));
+  uint32_t* tmp = bump<uint32_t>(c, size_t(top_k));
   if (!hist || !cnt || !tmp) return fail(c, IA_ERR_NOMEM, "scratch too small for the selection");
   hipStream_t s = as_stream(stream);
   Persistent* ps = persistent(c);
-  hipLaunchKernelGGL(ia::k_fill_u32, dim3((n_bins + 255) / 256), dim3(256), 0, s, hist, int64_t(n_bins), 0u);
-  const int64_t hg = std::min<int64_t>((sh.n_boxes + ia::kWG - 1) / ia::kWG, 2048);
-  hipLaunchKernelGGL(ia::k_hist, dim3(static_cast<uint32_t>(hg)), dim3(ia::kWG), 0, s, d_votes, sh.n_boxes, hist,
-                     n_bins, &ps->status);
+  hipLaunchKernelGGL(ia::k_fill_u32, dim3((n_bins + 255) / 256), dim3(256), 0, s, hist, uint32_t(n_bins), 0u);
+  const uint32_t hg = std::min<uint32_t>((sh.n_boxes + ia::kWG - 1) / ia::kWG, 2048);
+  hipLaunchKernelGGL(ia::k_hist, dim3(hg), dim3(ia::kWG), 0, s, d_votes, sh.n_boxes, hist, n_bins, &ps->status);
   return launch_select(c, d_votes, sh, reinterpret_cast<const BoxD*>(d_parents), hist, n_bins, top_k, cnt, tmp,
                        reinterpret_cast<BoxD*>(d_selected), d_selected_index, d_selected_votes, nullptr, 0, s);
 }
@@ -327,14 +393,35 @@ ia_status ia_estimate(ia_ctx* c, const ia_box* d_parents, int32_t n_parents, con
   if (!d_parents || !split || !d_votes || !d_out) return fail(c, IA_ERR_INVALID, "null pointer argument");
   if (n_parents < 1) return fail(c, IA_ERR_INVALID, "n_parents %d < 1", n_parents);
   Shape sh;
-  if (!make_shape(split, n_parents, &sh)) return fail(c, IA_ERR_OVERFLOW, "split / n_parents too large");
+  if (!make_shape(split, n_parents, &sh)) return fail(c, IA_ERR_OVERFLOW, "level exceeds 2^31 - 1 boxes");
   if (sh.n_boxes > kMaxEstimateBoxes) return fail(c, IA_ERR_OVERFLOW, "level too large for the estimate");
   IA_HIP(c, hipSetDevice(c->device));
+  reset_bump(c);
+  // the first max-vote box is the rank-0 entry of a top-1 selection
+  const int32_t n_bins = 65536;
+  uint32_t chunk;
+  const int32_t g = sel_groups(sh.n_boxes, &chunk);
+  const int32_t n_part = est_parts(sh.n_boxes);
+  uint32_t* hist = bump<uint32_t>(c, size_t(n_bins));
+  int32_t* cnt = bump<int32_t>(c, 2 * size_t(g));
+  uint32_t* tmp = bump<uint32_t>(c, 1);
+  BoxD* first = bump<BoxD>(c, 1);
+  int64_t* first_idx = bump<int64_t>(c, 1);
+  uint16_t* first_v = bump<uint16_t>(c, 1);
+  double* part = bump<double>(c, size_t(n_part) * ia::kEstQ);
+  if (!hist || !cnt || !tmp || !first || !first_idx || !first_v || !part)
+    return fail(c, IA_ERR_NOMEM, "scratch too small for the estimate");
   hipStream_t s = as_stream(stream);
-  hipLaunchKernelGGL(ia::k_estimate, dim3(1), dim3(ia::kWG), 0, s, reinterpret_cast<const BoxD*>(d_parents), sh,
-                     d_votes, reinterpret_cast<ia::EstimateOut*>(d_out), nullptr);
-  IA_HIP(c, hipGetLastError());
-  return IA_OK;
+  Persistent* ps = persistent(c);
+  const BoxD* par = reinterpret_cast<const BoxD*>(d_parents);
+  hipLaunchKernelGGL(ia::k_fill_u32, dim3((n_bins + 255) / 256), dim3(256), 0, s, hist, uint32_t(n_bins), 0u);
+  const uint32_t hg = std::min<uint32_t>((sh.n_boxes + ia::kWG - 1) / ia::kWG, 2048);
+  hipLaunchKernelGGL(ia::k_hist, dim3(hg), dim3(ia::kWG), 0, s, d_votes, sh.n_boxes, hist, n_bins, &ps->status);
+  ia_status st = launch_select(c, d_votes, sh, par, hist, n_bins, 1, cnt, tmp, first, first_idx, first_v, nullptr,
+                               0, s);
+  if (st != IA_OK) return st;
+  return launch_estimate(c, par, sh, d_votes, first, first_v, part, reinterpret_cast<ia::EstimateOut*>(d_out),
+                         nullptr, nullptr, 0, 0.0, nullptr, nullptr, 0, nullptr, s);
 }
 
 ia_status ia_find_helices(ia_ctx* c, const ia_hit* d_hits, const int32_t* h_off, int32_t n_events,
@@ -360,34 +447,33 @@ ia_status ia_find_helices(ia_ctx* c, const ia_hit* d_hits, const int32_t* h_off,
   }
   if (max_hits > 0 && !d_hits) return fail(c, IA_ERR_INVALID, "d_hits is NULL");
   Shape sh0, shr;
-  if (!make_shape(sc->bins, 1, &sh0)) return fail(c, IA_ERR_OVERFLOW, "bins too large");
-  if (!make_shape(sc->split, sc->top_k, &shr)) return fail(c, IA_ERR_OVERFLOW, "split too large");
+  if (!make_shape(sc->bins, 1, &sh0)) return fail(c, IA_ERR_OVERFLOW, "level-0 grid exceeds 2^31 - 1 boxes");
+  if (!make_shape(sc->split, sc->top_k, &shr)) return fail(c, IA_ERR_OVERFLOW, "refinement level too large");
   if (sh0.n_boxes > kMaxEstimateBoxes || shr.n_boxes > kMaxEstimateBoxes)
     return fail(c, IA_ERR_OVERFLOW, "a level exceeds %lld boxes", static_cast<long long>(kMaxEstimateBoxes));
   IA_HIP(c, hipSetDevice(c->device));
-  reset_bump(c);
-  const int64_t nbmax = std::max(sh0.n_boxes, shr.n_boxes);
-  int64_t chunk;
-  const int32_t gmax = sel_groups(nbmax, &chunk);
   const int32_t K = sc->top_k;
-  HitRec* recs = bump<HitRec>(c, size_t(std::max(1, max_hits)));
-  uint16_t* votes = bump<uint16_t>(c, size_t(nbmax));
-  uint32_t* hist = bump<uint32_t>(c, size_t(max_hits + 2));
-  int32_t* cnt = bump<int32_t>(c, 2 * size_t(gmax));
-  int64_t* tmp = bump<int64_t>(c, size_t(K));
-  BoxD* selA = bump<BoxD>(c, size_t(K));
-  BoxD* selB = bump<BoxD>(c, size_t(K));
-  BoxD* range = bump<BoxD>(c, 1);
-  int64_t* sel_idx = bump<int64_t>(c, size_t(K));
-  uint16_t* sel_v = bump<uint16_t>(c, size_t(K));
-  EventState* ev = bump<EventState>(c, 1);
-  if (!recs || !votes || !hist || !cnt || !tmp || !selA || !selB || !range || !sel_idx || !sel_v || !ev)
-    return fail(c, IA_ERR_NOMEM, "scratch too small: need %zu bytes", ia_ctx_scratch_needed(sc, max_hits));
+  FindLayout L;
+  layout_find(std::max<int64_t>(sh0.n_boxes, shr.n_boxes), K, max_hits, &L);
+  if (L.total > c->arena_bytes)
+    return fail(c, IA_ERR_NOMEM, "scratch too small: need %zu bytes, have %zu", L.total, c->arena_bytes);
+  char* a = c->arena;
+  HitRec* recs = reinterpret_cast<HitRec*>(a + L.recs);
+  uint16_t* votes = reinterpret_cast<uint16_t*>(a + L.votes);
+  uint32_t* hist = reinterpret_cast<uint32_t*>(a + L.hist);
+  int32_t* cnt = reinterpret_cast<int32_t*>(a + L.cnt);
+  uint32_t* tmp = reinterpret_cast<uint32_t*>(a + L.tmp);
+  BoxD* selA = reinterpret_cast<BoxD*>(a + L.selA);
+  BoxD* selB = reinterpret_cast<BoxD*>(a + L.selB);
+  BoxD* range = reinterpret_cast<BoxD*>(a + L.range);
+  int64_t* sel_idx = reinterpret_cast<int64_t*>(a + L.sel_idx);
+  uint16_t* sel_v = reinterpret_cast<uint16_t*>(a + L.sel_v);
+  EventState* ev = reinterpret_cast<EventState*>(a + L.ev);
+  double* part = reinterpret_cast<double*>(a + L.part);
   hipStream_t s = as_stream(stream);
   Persistent* ps = persistent(c);
   BoxD rb;
   std::memcpy(&rb, &sc->range, sizeof rb);
-  hipLaunchKernelGGL(k_set_box, dim3(1), dim3(64), 0, s, range, rb);
   for (int32_t e = 0; e < n_events; ++e) {
     const int32_t n = h_off[e + 1] - h_off[e];
     const int32_t n_bins = n + 1;
@@ -395,13 +481,9 @@ ia_status ia_find_helices(ia_ctx* c, const ia_hit* d_hits, const int32_t* h_off,
     int32_t* assigned = d_assigned ? d_assigned + h_off[e] : nullptr;
     ia::HelixOut* out = reinterpret_cast<ia::HelixOut*>(d_out) + int64_t(e) * max_per_event;
     int32_t* n_out = d_n_out + e;
-    hipLaunchKernelGGL(ia::k_event_init, dim3(1), dim3(64), 0, s, ev, n_out);
-    if (assigned && n > 0) {
-      hipLaunchKernelGGL(ia::k_fill_u32, dim3((n + 255) / 256), dim3(256), 0, s,
-                         reinterpret_cast<uint32_t*>(assigned), int64_t(n), 0xffffffffu);
-    }
-    hipLaunchKernelGGL(ia::k_prep, dim3(std::max(1, (std::max(n, n_bins) + 255) / 256)), dim3(256), 0, s, hits,
-                       nullptr, n, recs, hist, n_bins, &ps->status, &ps->n_bad);
+    const int32_t pg = std::max(1, (std::max(n, n_bins) + 255) / 256);
+    hipLaunchKernelGGL(ia::k_prep, dim3(pg), dim3(256), 0, s, hits, nullptr, n, recs, hist, n_bins, &ps->status,
+                       &ps->n_bad, ev, n_out, range, rb, assigned);
     for (int32_t pass = 0; pass < std::min(sc->n_helix_max, max_per_event); ++pass) {
       const BoxD* par = range;
       Shape sh = sh0;
@@ -410,7 +492,7 @@ ia_status ia_find_helices(ia_ctx* c, const ia_hit* d_hits, const int32_t* h_off,
         ia_status st = launch_vote(c, recs, n, par, sh, votes, hist, n_bins, ev, s);
         if (st != IA_OK) return st;
         st = launch_select(c, votes, sh, par, hist, n_bins, K, cnt, tmp, sel, sel_idx, sel_v, ev,
-                                     lev == 0 ? std::max(sc->v_min, 0) : 0, s);
+                           lev == 0 ? std::max(sc->v_min, 0) : 0, s);
         if (st != IA_OK) return st;
         if (lev == sc->n_refine) break;
         const int32_t k_eff = static_cast<int32_t>(std::min<int64_t>(K, sh.n_boxes));
@@ -418,14 +500,10 @@ ia_status ia_find_helices(ia_ctx* c, const ia_hit* d_hits, const int32_t* h_off,
         par = sel;
         sel = (sel == selA) ? selB : selA;
       }
-      hipLaunchKernelGGL(ia::k_estimate, dim3(1), dim3(ia::kWG), 0, s, par, sh, votes,
-                         static_cast<ia::EstimateOut*>(nullptr), ev);
-      if (n > 0)
-        hipLaunchKernelGGL(ia::k_hitfind, dim3((n + ia::kWG - 1) / ia::kWG), dim3(ia::kWG), 0, s, recs, n, ev,
-                           sc->hitfind_scale, assigned);
-      hipLaunchKernelGGL(ia::k_record, dim3(1), dim3(64), 0, s, ev, out, max_per_event, n_out);
+      ia_status st = launch_estimate(c, par, sh, votes, sel, sel_v, part, nullptr, ev, recs, n, sc->hitfind_scale,
+                                     assigned, out, max_per_event, n_out, s);
+      if (st != IA_OK) return st;
     }
-    IA_HIP(c, hipGetLastError());
   }
   return IA_OK;
 }

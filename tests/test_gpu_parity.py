@@ -81,10 +81,13 @@ def test_refinement_shape_votes_bit_exact(ctx):
     assert np.array_equal(got, ref)
 
 
+@pytest.mark.parametrize("tile", [64, 128, 256])
 @pytest.mark.parametrize("split,n_par", [((3, 5, 2, 7, 3), 5), ((1, 1, 1, 1, 1), 300), ((2, 3, 1, 1, 1), 77),
-                                         ((5, 1, 4, 1, 2), 3)])
-def test_ragged_shapes_bit_exact(ctx, split, n_par):
-    """Shapes with ragged tiles: several triples per workgroup, partial last tile."""
+                                         ((5, 1, 4, 1, 2), 3), ((4, 4, 4, 4, 4), 32)])
+def test_ragged_shapes_bit_exact(ctx, split, n_par, tile):
+    """Shapes with ragged tiles (several triples per workgroup, partial last
+    tile) under every vote-kernel tile: one box per lane, hits split over 2 or 4 waves."""
+    ctx.set_vote_tile(tile)
     ev = toymc.config_event(2, 5)
     rng = np.random.default_rng(41)
     t = ev.truth[0]
@@ -92,7 +95,10 @@ def test_ragged_shapes_bit_exact(ctx, split, n_par):
     parents = np.array([oracle.make_box(t - w * rng.uniform(0.2, 1, 5), t + w * rng.uniform(0.2, 1, 5))
                         for _ in range(n_par)])
     ref = oracle.vote_level(ev.hits, parents, split)
-    got = _gpu_votes(ctx, ev.hits, parents, split)
+    try:
+        got = _gpu_votes(ctx, ev.hits, parents, split)
+    finally:
+        ctx.set_vote_tile(0)
     assert np.array_equal(got, ref)
 
 
