@@ -130,6 +130,13 @@ ia_status ia_ctx_profile_read(ia_ctx *ctx, int64_t *n_launches, double *total_ms
  * by level size.  Results do not depend on it. */
 ia_status ia_ctx_set_vote_tile(ia_ctx *ctx, int32_t boxes_per_workgroup);
 
+/* The vote kernel's (triple, hit) pre-filter: an interval enclosure of the
+ * stereo drift over every box centre sharing (d0, phi0, kappa) proves that a
+ * hit cannot vote there, and its per-box evaluations are skipped.  mode -1
+ * chooses by level shape (the default), 0 disables, 1 enables.  Results do
+ * not depend on it. */
+ia_status ia_ctx_set_prefilter(ia_ctx *ctx, int32_t mode);
+
 /* Scratch bytes needed by ia_find_helices for events of at most max_hits
  * hits under `sched`. */
 size_t ia_ctx_scratch_needed(const ia_schedule *sched, int32_t max_hits);

@@ -98,6 +98,8 @@ def load():
     L.ia_ctx_status.argtypes = [P, C.POINTER(C.c_uint32), C.POINTER(i64)]
     L.ia_ctx_clear_status.restype = i32
     L.ia_ctx_clear_status.argtypes = [P]
+    L.ia_ctx_set_prefilter.restype = i32
+    L.ia_ctx_set_prefilter.argtypes = [P, i32]
     L.ia_ctx_set_vote_tile.restype = i32
     L.ia_ctx_set_vote_tile.argtypes = [P, i32]
     L.ia_ctx_set_profiling.restype = i32
@@ -177,6 +179,10 @@ class Context:
     def set_vote_tile(self, boxes_per_workgroup=0):
         """Force the vote kernel's boxes per workgroup (256, 128, 64) or 0 for automatic."""
         self._check(self._L.ia_ctx_set_vote_tile(self._h, int(boxes_per_workgroup)))
+
+    def set_prefilter(self, mode=-1):
+        """(triple, hit) pre-filter: -1 automatic, 0 off, 1 on."""
+        self._check(self._L.ia_ctx_set_prefilter(self._h, int(mode)))
 
     def set_profiling(self, enable=True):
         self._check(self._L.ia_ctx_set_profiling(self._h, 1 if enable else 0))

@@ -62,33 +62,33 @@ enum : uint32_t { kStBadHit = 1u, kStVoteOverflow = 2u };
 
 // ---------------------------------------------------------------------------
 // edges of child k of [L, U] split m ways
-__device__ __forceinline__ void child_edge(double L, double U, uint32_t m, uint32_t k,
+IA_HD void child_edge(double L, double U, uint32_t m, uint32_t k,
                                            double* lo, double* hi) {
   double w = (U - L) / static_cast<double>(m);
   *lo = L + static_cast<double>(k) * w;
   *hi = (k + 1 == m) ? U : L + static_cast<double>(k + 1) * w;
 }
 
-__device__ __forceinline__ void child_index(const uint32_t m[5], uint32_t child, uint32_t k[5]) {
+IA_HD void child_index(const uint32_t m[5], uint32_t child, uint32_t k[5]) {
   for (int j = 4; j >= 0; --j) { k[j] = child % m[j]; child /= m[j]; }
 }
 
-__device__ __forceinline__ void child_box(const BoxD& P, const uint32_t m[5], uint32_t child, BoxD* out) {
+IA_HD void child_box(const BoxD& P, const uint32_t m[5], uint32_t child, BoxD* out) {
   uint32_t k[5];
   child_index(m, child, k);
   for (int j = 0; j < 5; ++j) child_edge(P.lo[j], P.hi[j], m[j], k[j], &out->lo[j], &out->hi[j]);
 }
 
-__device__ __forceinline__ void level_box(const BoxD* parents, const Shape& sh, uint32_t b, BoxD* out) {
+IA_HD void level_box(const BoxD* parents, const Shape& sh, uint32_t b, BoxD* out) {
   child_box(parents[b / sh.nc], sh.m, b % sh.nc, out);
 }
 
 // ---------------------------------------------------------------------------
 // hit preparation (Eqs. wirePar_a,b and EQSinter_d,e with z_ref = 0)
-__device__ __forceinline__ void prep_one(const double* h, bool active, HitRec* o, bool* bad) {
+IA_HD void prep_one(const double* h, bool active, HitRec* o, bool* bad) {
   HitRec r{};
   bool fin = true;
-  for (int i = 0; i < 8; ++i) fin = fin && isfinite(h[i]);
+  for (int i = 0; i < 8; ++i) fin = fin && __builtin_isfinite(h[i]);
   *bad = false;
   r.use = 0;
   r.axial = 0;
@@ -100,7 +100,7 @@ __device__ __forceinline__ void prep_one(const double* h, bool active, HitRec* o
   r.px = x0 - z0 * tx;
   r.py = y0 - z0 * ty;
   r.tant = sqrt(tx * tx + ty * ty);
-  if (!isfinite(r.px) || !isfinite(r.py) || !isfinite(r.tant)) { *bad = true; *o = HitRec{}; return; }
+  if (!__builtin_isfinite(r.px) || !__builtin_isfinite(r.py) || !__builtin_isfinite(r.tant)) { *bad = true; *o = HitRec{}; return; }
   if (r.tant == 0.0) { r.sphis = 0.0; r.cphis = 1.0; r.axial = 1; }
   else { r.sphis = tx / r.tant; r.cphis = -ty / r.tant; r.axial = 0; }
   r.r = sqrt(r.px * r.px + r.py * r.py);
@@ -121,7 +121,7 @@ struct Frame {
   double sig, R, xc, yc, sp0, cp0;
 };
 
-__device__ __forceinline__ Frame triple_frame(const BoxD& P, const uint32_t m[5], uint32_t k0, uint32_t k1,
+IA_HD Frame triple_frame(const BoxD& P, const uint32_t m[5], uint32_t k0, uint32_t k1,
                                               uint32_t k2) {
   Frame f;
   child_edge(P.lo[0], P.hi[0], m[0], k0, &f.Dd.lo, &f.Dd.hi);
@@ -146,7 +146,7 @@ __device__ __forceinline__ Frame triple_frame(const BoxD& P, const uint32_t m[5]
 }
 
 // interval residual G over the triple (kappa-scaled Eq. ApoVote)
-__device__ __forceinline__ Iv residual_G(const Frame& f, const HitRec& h) {
+IA_HD Iv residual_G(const Frame& f, const HitRec& h) {
   Iv Ar = {wdn(f.Fi.lo - h.phip), wup(f.Fi.hi - h.phip)};
   Iv S = sin_encl(Ar.lo, Ar.hi);
   Iv rS = imul_pos(S, h.r);
@@ -158,7 +158,7 @@ __device__ __forceinline__ Iv residual_G(const Frame& f, const HitRec& h) {
   return iadd(iadd(KT, imul(KD1, rS)), f.Dd);
 }
 
-__device__ __forceinline__ bool h_contains0(Iv G, Iv K, double e, double band) {
+IA_HD bool h_contains0(Iv G, Iv K, double e, double band) {
   Iv E = {wdn(e - band), wup(e + band)};
   Iv Hv = isub(itwice(G), iadd(itwice(E), imul(K, isqr(E))));
   return Hv.lo <= 0.0 && 0.0 <= Hv.hi;
@@ -169,7 +169,7 @@ struct PairQ {
   double Glo, Ghi, sArc, dphi, RAx, sinA, cosA, sAx, cAx, c2, s2, twoRAx2, RpRAx;
 };
 
-__device__ __forceinline__ PairQ pair_quantities(const Frame& f, const HitRec& h, Iv G) {
+IA_HD PairQ pair_quantities(const Frame& f, const HitRec& h, Iv G) {
   PairQ q;
   q.Glo = G.lo;
   q.Ghi = G.hi;
@@ -191,7 +191,7 @@ __device__ __forceinline__ PairQ pair_quantities(const Frame& f, const HitRec& h
 
 // stereo vote of one hit for one box centre (z0, lam); ApproxPhi, normudi,
 // EQSinter_c, defdiAX_b evaluated in the same operation order as the oracle
-__device__ __forceinline__ bool stereo_vote(const PairQ& q, double R, double sig, Iv K, double z0,
+IA_HD bool stereo_vote(const PairQ& q, double R, double sig, Iv K, double z0,
                                             double lam, double lamR, double lam2, double tt, double t2,
                                             double d, double band) {
   double zA = z0 + lam * q.sArc;
@@ -223,10 +223,85 @@ __device__ __forceinline__ bool stereo_vote(const PairQ& q, double R, double sig
     if (disc >= 0.0) {
       double dhat = delta - Q / (A + sqrt(disc));
       double e = sig * dhat;
-      if (isfinite(e) && h_contains0(G, K, e, band)) vote = true;
+      if (__builtin_isfinite(e) && h_contains0(G, K, e, band)) vote = true;
     }
   }
   return vote;
+}
+
+// ---------------------------------------------------------------------------
+// Pre-filter of a (triple, stereo hit) pair.  The point value e of each box
+// depends on the box only through its (z0, tanl) centre.  e_enclosure runs
+// the operation sequence of stereo_vote in interval arithmetic over the
+// rectangle Z x L holding every centre of the triple's boxes, and widens the
+// result by 1e-9 |e| + 1e-12 m, far above the rounding error of the point
+// evaluation (about 100 ulps of the terms of d^Ax).  Every interval
+// operation is inclusion-monotone, so if the H test fails for the widened
+// enclosure it fails for every box: the pair casts no vote anywhere in the
+// triple.  Returns false when no finite enclosure is available.
+IA_HD bool e_enclosure(const PairQ& q, double R, double sig, double tt, double t2, double dS, Iv Z, Iv L, Iv* out) {
+  const Iv ZA = iadd(Z, imul(L, ipt(q.sArc)));
+  const Iv ZAs = imul(ZA, ipt(q.sinA));
+  const Iv ZA2 = isqr(ZA);
+  const Iv LZA = imul(L, ZA);
+  const Iv LR = imul(L, ipt(R));
+  const Iv L2 = isqr(L);
+  const Iv PHI1 = ineg(idivp(iadd(ZAs, imul(imul(L, ipt(dS)), ipt(q.cosA))), q.RAx));
+  const Iv P2a = imul(LR, ZA);
+  const Iv P2b = imul(imul(LZA, isub(ipt(R), ipt(2.0 * dS))), ipt(q.c2));
+  const Iv inner = iadd(ipt(q.RAx), imul(L2, isub(ipt(q.RpRAx), ipt(dS))));
+  const Iv P2c = imul(iadd(ZA2, imul(ipt(dS), inner)), ipt(q.s2));
+  const Iv PHI2 = idivp(iadd(isub(P2a, P2b), P2c), q.twoRAx2);
+  const Iv EPS = iadd(imul(PHI1, ipt(tt)), imul(PHI2, ipt(t2)));
+  if (!(fabs(EPS.lo) < 1e5 && fabs(EPS.hi) < 1e5)) return false;
+  const Iv SE = sin_encl(EPS.lo, EPS.hi), CE = cos_encl(EPS.lo, EPS.hi);
+  const Iv SINP = iadd(imul(ipt(q.sinA), CE), imul(ipt(q.cosA), SE));
+  const Iv COSP = isub(imul(ipt(q.cosA), CE), imul(ipt(q.sinA), SE));
+  const Iv U2 = iadd(iadd(iadd(ipt(1.0), imul(imul(itwice(L), SINP), ipt(tt))), imul(L2, ipt(t2))),
+                     imul(isqr(COSP), ipt(t2)));
+  if (!(U2.lo > 0.0)) return false;
+  const Iv DELTA = idiv_pos(ipt(dS), isqrt(U2));
+  const Iv SPERP = imul(ipt(R), iadd(ipt(q.dphi), EPS));
+  const Iv ZS = isub(iadd(Z, imul(L, SPERP)), imul(imul(DELTA, COSP), ipt(tt)));
+  const Iv LD = imul(L, DELTA);
+  const Iv CTAU = isub(imul(ZS, ipt(q.cAx)), imul(LD, ipt(q.sAx)));
+  const Iv Q = iadd(iadd(imul(itwice(CTAU), ipt(tt)), isqr(imul(ZS, ipt(tt)))), isqr(imul(LD, ipt(tt))));
+  const Iv A = iadd(ipt(R), DELTA);
+  const Iv DISC = isub(isqr(A), Q);
+  if (!(DISC.hi >= 0.0)) return false;
+  const Iv DEN = iadd(A, isqrt(DISC));
+  if (!(DEN.lo > 0.0)) return false;
+  const Iv DHAT = isub(DELTA, idiv_pos(Q, DEN));
+  const Iv E = sig > 0.0 ? DHAT : ineg(DHAT);
+  const double m = 1e-9 * fmax(fabs(E.lo), fabs(E.hi)) + 1e-12;
+  *out = {wdn(E.lo - m), wup(E.hi + m)};
+  return __builtin_isfinite(out->lo) && __builtin_isfinite(out->hi);
+}
+
+// false only when no box of the triple can get this stereo hit's vote
+IA_HD bool triple_may_vote(const PairQ& q, const Frame& f, const HitRec& h, Iv Z, Iv L) {
+  const Iv G = {q.Glo, q.Ghi};
+  const double tt = h.tant, t2 = tt * tt;
+  for (int si = 0; si < 2; ++si) {
+    const double dS = si == 0 ? h.d : -h.d;
+    Iv E;
+    if (!e_enclosure(q, f.R, f.sig, tt, t2, dS, Z, L, &E)) return true;
+    const Iv Eb = {wdn(E.lo - h.band), wup(E.hi + h.band)};
+    const Iv Hb = isub(itwice(G), iadd(itwice(Eb), imul(f.K, isqr(Eb))));
+    if (Hb.lo <= 0.0 && 0.0 <= Hb.hi) return true;
+  }
+  return false;
+}
+
+// (z0, tanl) centre ranges of the boxes of one parent
+IA_HD void centre_ranges(const BoxD& P, const uint32_t m[5], Iv* Z, Iv* L) {
+  double lo, hi, lo2, hi2;
+  child_edge(P.lo[3], P.hi[3], m[3], 0, &lo, &hi);
+  child_edge(P.lo[3], P.hi[3], m[3], m[3] - 1, &lo2, &hi2);
+  *Z = {0.5 * (lo + hi), 0.5 * (lo2 + hi2)};
+  child_edge(P.lo[4], P.hi[4], m[4], 0, &lo, &hi);
+  child_edge(P.lo[4], P.hi[4], m[4], m[4] - 1, &lo2, &hi2);
+  *L = {0.5 * (lo + hi), 0.5 * (lo2 + hi2)};
 }
 
 // ---------------------------------------------------------------------------
@@ -259,17 +334,193 @@ __global__ void k_prep(const double* __restrict__ hits, const uint8_t* __restric
 }
 
 // ---------------------------------------------------------------------------
+// top-k selection by (votes desc, index asc).
+// threshold v*: the largest v with count(votes >= v) >= k_eff; every box above
+// v* is taken, and the first (k_eff - count(votes > v*)) boxes at v* in index
+// order (prefix-sum compaction over the chunks of the grid).
+struct SelInfo { int32_t vstar, need_eq, n_gt, k_eff; };
+
+IA_HD SelInfo threshold(const uint32_t* hist, int32_t n_bins, int32_t k, uint32_t n_boxes) {
+  SelInfo s;
+  s.k_eff = static_cast<int32_t>(min(static_cast<uint32_t>(k), n_boxes));
+  int64_t cum = 0;
+  s.vstar = 0;
+  s.need_eq = s.k_eff;
+  for (int32_t v = n_bins - 1; v >= 0; --v) {
+    const int64_t c = hist[v];
+    if (cum + c >= s.k_eff) { s.vstar = v; s.need_eq = static_cast<int32_t>(s.k_eff - cum); break; }
+    cum += c;
+  }
+  s.n_gt = s.k_eff - s.need_eq;
+  return s;
+}
+
+// block-wide exclusive scan of 0/1 flags (kWG lanes); returns the total
+__device__ __forceinline__ int32_t block_scan(int32_t flag, int32_t* excl, int32_t* sbuf) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const unsigned long long m = __ballot(flag != 0);
+  const int32_t before = __popcll(m & ((1ull << lane) - 1ull));
+  if (lane == 0) sbuf[wv] = __popcll(m);
+  __syncthreads();
+  int32_t off = 0, tot = 0;
+  for (int w = 0; w < kWG / 64; ++w) { if (w < wv) off += sbuf[w]; tot += sbuf[w]; }
+  __syncthreads();
+  *excl = off + before;
+  return tot;
+}
+
+__device__ __forceinline__ int32_t block_sum(int32_t v, int32_t* sbuf) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  if ((threadIdx.x & 63) == 0) sbuf[threadIdx.x >> 6] = v;
+  __syncthreads();
+  int32_t t = 0;
+  for (int w = 0; w < kWG / 64; ++w) t += sbuf[w];
+  __syncthreads();
+  return t;
+}
+
+// ---------------------------------------------------------------------------
+// (triple, hit) pre-pass, one thread per pair: flags[t * n_hits + h] =
+// 0 no vote anywhere in the triple (or hit unused), 1 axial hit voting for
+// the whole triple, 2 stereo hit that may vote (decided per box).
+__global__ void __launch_bounds__(kWG) k_pair_filter(const HitRec* __restrict__ hits, int32_t n_hits,
+                                                     const BoxD* __restrict__ parents, Shape sh,
+                                                     uint8_t* __restrict__ flags, int32_t filter,
+                                                     const EventState* __restrict__ ev) {
+  if (ev && ev->done) return;
+  const uint32_t i = blockIdx.x * kWG + threadIdx.x;
+  const uint32_t n_tr = sh.n_parents * sh.m012;
+  if (n_hits <= 0 || i >= n_tr * static_cast<uint32_t>(n_hits)) return;
+  const uint32_t t = i / static_cast<uint32_t>(n_hits), hi = i % static_cast<uint32_t>(n_hits);
+  const HitRec h = hits[hi];
+  uint8_t fl = 0;
+  if (h.use) {
+    const uint32_t tc = t % sh.m012;
+    const BoxD& TP = parents[t / sh.m012];
+    const Frame f = triple_frame(TP, sh.m, tc / sh.m12, (tc / sh.m[2]) % sh.m[1], tc % sh.m[2]);
+    const Iv G = residual_G(f, h);
+    if (h.axial) {
+      fl = (h_contains0(G, f.K, f.sig * h.d, h.band) || h_contains0(G, f.K, f.sig * (-h.d), h.band)) ? 1 : 0;
+    } else if (!filter) {
+      fl = 2;
+    } else {
+      const PairQ q = pair_quantities(f, h, G);
+      Iv Zr, Lr;
+      centre_ranges(TP, sh.m, &Zr, &Lr);
+      fl = triple_may_vote(q, f, h, Zr, Lr) ? 2 : 0;
+    }
+  }
+  flags[i] = fl;
+}
+
+// Top-k by (votes desc, index asc) of one level, one workgroup, run after
+// the vote kernel has written the votes, the histogram and the maximum of
+// each of its n_wg workgroups (bx boxes each).  Boxes above the threshold v*
+// or at it can only sit in workgroups whose maximum reaches v*; those are
+// visited in index order, kWG / bx at a time, and compacted with block scans
+// until all count(> v*) boxes and the first (k - count(> v*)) boxes at v*
+// are collected (at most k workgroups hold boxes above v*).  Then the entries
+// are ordered, the selected boxes written, the histogram cleared and, for
+// level 0, the event stopped when its maximum is below v_min.
+__global__ void __launch_bounds__(kWG) k_select_wg(const uint16_t* __restrict__ votes, uint32_t n_boxes,
+                                                   uint32_t* __restrict__ hist, int32_t n_bins, int32_t k,
+                                                   const int32_t* __restrict__ wg_max, uint32_t n_wg, int32_t bx,
+                                                   const BoxD* __restrict__ parents, Shape sh,
+                                                   BoxD* __restrict__ out_boxes, int64_t* __restrict__ out_index,
+                                                   uint16_t* __restrict__ out_votes, EventState* __restrict__ ev,
+                                                   int32_t v_min_stop) {
+  if (ev && ev->done) return;
+  __shared__ SelInfo si;
+  __shared__ int32_t sbuf[kWG / 64];
+  __shared__ int32_t s_vmax, s_run_gt, s_run_eq;
+  __shared__ uint32_t s_nmax;
+  __shared__ uint32_t s_idx[kMaxTopK];
+  __shared__ uint16_t s_v[kMaxTopK];
+  __shared__ uint32_t s_list[kWG];
+  const int tid = threadIdx.x;
+  if (tid == 0) {
+    si = threshold(hist, n_bins, k, n_boxes);
+    int32_t vm = 0;
+    uint32_t nm = 0;
+    for (int32_t v = n_bins - 1; v >= 0; --v) {
+      const uint32_t c = hist[v];
+      if (c != 0u) { vm = v; nm = c; break; }
+    }
+    s_vmax = vm;
+    s_nmax = nm;
+    s_run_gt = 0;
+    s_run_eq = 0;
+  }
+  __syncthreads();
+  const int32_t per = max(1, kWG / bx);            // candidate workgroups per pass
+  for (uint32_t w0 = 0; w0 < n_wg; w0 += kWG) {
+    if (s_run_gt >= si.n_gt && s_run_eq >= si.need_eq) break;
+    const uint32_t w = w0 + tid;
+    const int32_t m = w < n_wg ? wg_max[w] : -1;
+    const int32_t cand = (m > si.vstar) || (m == si.vstar && s_run_eq < si.need_eq);
+    int32_t xc;
+    const int32_t nc = block_scan(cand, &xc, sbuf);
+    if (cand) s_list[xc] = w;
+    __syncthreads();
+    for (int32_t c0 = 0; c0 < nc; c0 += per) {
+      if (s_run_gt >= si.n_gt && s_run_eq >= si.need_eq) break;
+      // thread -> (candidate c0 + tid / bx, box tid % bx): index order is thread order
+      const int32_t ci = c0 + tid / bx;
+      const bool ok = tid < per * bx && ci < nc;
+      const uint32_t b = ok ? s_list[ci] * static_cast<uint32_t>(bx) + static_cast<uint32_t>(tid % bx) : 0u;
+      const int32_t v = (ok && b < n_boxes) ? static_cast<int32_t>(votes[b]) : -1;
+      const int32_t fg = v > si.vstar, fe = v == si.vstar;
+      int32_t xg, xe;
+      const int32_t run_gt = s_run_gt, run_eq = s_run_eq;
+      const int32_t tg = block_scan(fg, &xg, sbuf);
+      const int32_t te = block_scan(fe, &xe, sbuf);
+      if (fg && run_gt + xg < si.n_gt) s_idx[run_gt + xg] = b;
+      if (fe && run_eq + xe < si.need_eq) s_idx[si.n_gt + run_eq + xe] = b;
+      __syncthreads();
+      if (tid == 0) { s_run_gt = run_gt + tg; s_run_eq = run_eq + te; }
+      __syncthreads();
+    }
+  }
+  const int32_t ke = si.k_eff;
+  for (int32_t a = tid; a < ke; a += kWG) s_v[a] = votes[s_idx[a]];
+  __syncthreads();
+  for (int32_t a = tid; a < ke; a += kWG) {
+    const uint32_t ia = s_idx[a];
+    const int32_t va = s_v[a];
+    int32_t rank = 0;
+    for (int32_t c = 0; c < ke; ++c) {
+      const int32_t vc = s_v[c];
+      rank += (vc > va) || (vc == va && s_idx[c] < ia);
+    }
+    out_index[rank] = ia;
+    out_votes[rank] = static_cast<uint16_t>(va);
+    level_box(parents, sh, ia, &out_boxes[rank]);
+  }
+  __syncthreads();
+  for (int32_t i = tid; i < n_bins; i += kWG) hist[i] = 0u;
+  if (tid == 0 && ev) {
+    ev->vmax = s_vmax;
+    ev->n_argmax = static_cast<int32_t>(s_nmax);
+    ev->k_sel = ke;
+    if (v_min_stop > 0 && s_vmax < v_min_stop) ev->done = 1;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // the vote kernel.  A workgroup owns BX consecutive boxes (one lane each) and
 // splits the hits of every chunk over kWG / BX slices (whole waves); the
 // slices' counts are summed in LDS.  Per chunk, the workgroup first stages
-// the (triple, hit) quantities of the triples its boxes span.
-// hist (nullable) receives the vote histogram of bins 0..n_bins-1.
+// the (triple, hit) quantities of the triples its boxes span; with `flags`
+// from k_pair_filter it stages only the stereo pairs that may vote.
+// hist (nullable) receives the vote histogram of bins 0..n_bins-1 and
+// wg_max (nullable) each workgroup's maximum vote, for k_select_wg.
 template <int BX>
 __global__ void __launch_bounds__(kWG) k_vote(const HitRec* __restrict__ hits, int32_t n_hits,
                                               const BoxD* __restrict__ parents, Shape sh,
                                               uint16_t* __restrict__ votes, uint32_t* __restrict__ hist,
                                               int32_t n_bins, uint32_t* __restrict__ status,
-                                              const EventState* __restrict__ ev) {
+                                              const EventState* __restrict__ ev,
+                                              const uint8_t* __restrict__ flags, int32_t* __restrict__ wg_max) {
   constexpr int HS = kWG / BX;
   static_assert(BX % 64 == 0 && HS * BX == kWG, "slices are whole waves");
   if (ev && ev->done) return;
@@ -277,7 +528,7 @@ __global__ void __launch_bounds__(kWG) k_vote(const HitRec* __restrict__ hits, i
   __shared__ int8_t sflag[kCap + 16];
   __shared__ uint32_t shist[kHistLds];
   __shared__ int32_t sred[HS][BX];
-
+  __shared__ int32_t sbuf[kWG / 64];
   const uint32_t tid = threadIdx.x;
   const uint32_t bl = tid % BX, sl = tid / BX;
   const uint32_t b0 = blockIdx.x * BX;
@@ -316,9 +567,13 @@ __global__ void __launch_bounds__(kWG) k_vote(const HitRec* __restrict__ hits, i
       const int32_t tl = r / hc, hl = r % hc;
       const int32_t slot = tl * pitch + hl;
       if (hl >= nh) continue;
+      const uint32_t t = t_first + tl;
+      if (flags) {
+        const uint8_t fl = flags[t * static_cast<uint32_t>(n_hits) + static_cast<uint32_t>(h0 + hl)];
+        if (fl < 2) { sflag[slot] = static_cast<int8_t>(fl); continue; }
+      }
       const HitRec h = hits[h0 + hl];
       if (!h.use) { sflag[slot] = -1; continue; }
-      const uint32_t t = t_first + tl;
       const uint32_t tc = t % sh.m012;
       const uint32_t t0 = tc / sh.m12, t1 = (tc / sh.m[2]) % sh.m[1], t2 = tc % sh.m[2];
       const Frame ft = triple_frame(parents[t / sh.m012], sh.m, t0, t1, t2);
@@ -376,6 +631,17 @@ __global__ void __launch_bounds__(kWG) k_vote(const HitRec* __restrict__ hits, i
         if (shist[i]) atomicAdd(&hist[i], shist[i]);
     }
   }
+  if (!wg_max) return;
+  // workgroup maximum, read by the selection kernel
+  int32_t mv = owner ? nv : -1;
+  for (int o = 32; o > 0; o >>= 1) mv = max(mv, __shfl_down(mv, o, 64));
+  if ((tid & 63) == 0) sbuf[tid >> 6] = mv;
+  __syncthreads();
+  if (tid == 0) {
+    int32_t m = -1;
+    for (int w = 0; w < kWG / 64; ++w) m = max(m, sbuf[w]);
+    wg_max[blockIdx.x] = m;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -404,52 +670,6 @@ __global__ void __launch_bounds__(kWG) k_hist(const uint16_t* __restrict__ votes
 
 __global__ void k_fill_u32(uint32_t* p, uint32_t n, uint32_t v) {
   for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = v;
-}
-
-// ---------------------------------------------------------------------------
-// top-k selection by (votes desc, index asc).
-// threshold v*: the largest v with count(votes >= v) >= k_eff; every box above
-// v* is taken, and the first (k_eff - count(votes > v*)) boxes at v* in index
-// order (prefix-sum compaction over the chunks of the grid).
-struct SelInfo { int32_t vstar, need_eq, n_gt, k_eff; };
-
-__device__ __forceinline__ SelInfo threshold(const uint32_t* hist, int32_t n_bins, int32_t k, uint32_t n_boxes) {
-  SelInfo s;
-  s.k_eff = static_cast<int32_t>(min(static_cast<uint32_t>(k), n_boxes));
-  int64_t cum = 0;
-  s.vstar = 0;
-  s.need_eq = s.k_eff;
-  for (int32_t v = n_bins - 1; v >= 0; --v) {
-    const int64_t c = hist[v];
-    if (cum + c >= s.k_eff) { s.vstar = v; s.need_eq = static_cast<int32_t>(s.k_eff - cum); break; }
-    cum += c;
-  }
-  s.n_gt = s.k_eff - s.need_eq;
-  return s;
-}
-
-// block-wide exclusive scan of 0/1 flags (kWG lanes); returns the total
-__device__ __forceinline__ int32_t block_scan(int32_t flag, int32_t* excl, int32_t* sbuf) {
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const unsigned long long m = __ballot(flag != 0);
-  const int32_t before = __popcll(m & ((1ull << lane) - 1ull));
-  if (lane == 0) sbuf[wv] = __popcll(m);
-  __syncthreads();
-  int32_t off = 0, tot = 0;
-  for (int w = 0; w < kWG / 64; ++w) { if (w < wv) off += sbuf[w]; tot += sbuf[w]; }
-  __syncthreads();
-  *excl = off + before;
-  return tot;
-}
-
-__device__ __forceinline__ int32_t block_sum(int32_t v, int32_t* sbuf) {
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
-  if ((threadIdx.x & 63) == 0) sbuf[threadIdx.x >> 6] = v;
-  __syncthreads();
-  int32_t t = 0;
-  for (int w = 0; w < kWG / 64; ++w) t += sbuf[w];
-  __syncthreads();
-  return t;
 }
 
 __global__ void __launch_bounds__(kWG) k_select_count(const uint16_t* __restrict__ votes, uint32_t n_boxes,
@@ -647,7 +867,7 @@ __global__ void __launch_bounds__(kWG) k_est_partial(const BoxD* __restrict__ pa
 }
 
 // hit finding (Sec. 3.3): does an active hit vote for the box estimate +- scale x error
-__device__ __forceinline__ bool pair_vote_box(const BoxD& b, const HitRec& h) {
+IA_HD bool pair_vote_box(const BoxD& b, const HitRec& h) {
   if (!h.use) return false;
   Frame f;
   f.Dd = {b.lo[0], b.hi[0]};

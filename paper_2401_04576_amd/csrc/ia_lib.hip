@@ -53,6 +53,7 @@ struct ia_ctx {
   std::string err;
   bool profiling = false;
   int32_t tile_override = 0;
+  int32_t filter_mode = -1;       // -1: automatic, 0: off, 1: on
   std::vector<std::pair<hipEvent_t, hipEvent_t>> marks;
 };
 
@@ -146,15 +147,35 @@ ia_status launch_select(ia_ctx* c, const uint16_t* votes, const Shape& sh, const
 int32_t vote_tile(const ia_ctx* c, uint32_t n_boxes) {
   if (c->tile_override) return c->tile_override;
   if (n_boxes >= (1u << 19)) return 256;
-  if (n_boxes >= (1u << 17)) return 128;
-  return 64;
+  return 128;
 }
 
-// launches the vote kernel, bracketed by events when profiling
+// the (triple, hit) pre-pass pays when many boxes share a triple
+int32_t use_filter(const ia_ctx* c, const Shape& sh) {
+  if (c->filter_mode >= 0) return c->filter_mode;
+  return sh.m34 >= 64 ? 1 : 0;
+}
+
+// launches the (triple, hit) pre-pass when it pays and room allows; returns
+// the flags to hand to the vote kernel, or nullptr
+const uint8_t* launch_filter(ia_ctx* c, const HitRec* recs, int32_t n, const BoxD* par, const Shape& sh,
+                             uint8_t* flags, size_t flag_cap, EventState* ev, hipStream_t s) {
+  if (!flags || n <= 0 || !use_filter(c, sh)) return nullptr;
+  const uint64_t pairs = uint64_t(sh.n_parents) * sh.m012 * uint64_t(n);
+  if (pairs > flag_cap || pairs >= (uint64_t(1) << 31)) return nullptr;
+  const uint32_t grid = static_cast<uint32_t>((pairs + ia::kWG - 1) / ia::kWG);
+  hipLaunchKernelGGL(ia::k_pair_filter, dim3(grid), dim3(ia::kWG), 0, s, recs, n, par, sh, flags, 1, ev);
+  return flags;
+}
+
+// launches the vote kernel (with the fused selection when sel.k > 0),
+// bracketed by events when profiling
 ia_status launch_vote(ia_ctx* c, const HitRec* recs, int32_t n, const BoxD* par, const Shape& sh, uint16_t* votes,
-                      uint32_t* hist, int32_t n_bins, EventState* ev, hipStream_t s) {
+                      uint32_t* hist, int32_t n_bins, const EventState* ev, const uint8_t* flags, int32_t* wg_max,
+                      hipStream_t s, int32_t* tile_used = nullptr) {
   const int32_t bx = vote_tile(c, sh.n_boxes);
   const uint32_t grid = (sh.n_boxes + bx - 1) / bx;
+  if (tile_used) *tile_used = bx;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (c->profiling) {
     IA_HIP(c, hipEventCreate(&e0));
@@ -164,13 +185,16 @@ ia_status launch_vote(ia_ctx* c, const HitRec* recs, int32_t n, const BoxD* par,
   uint32_t* st = &persistent(c)->status;
   switch (bx) {
     case 256:
-      hipLaunchKernelGGL(ia::k_vote<256>, dim3(grid), dim3(ia::kWG), 0, s, recs, n, par, sh, votes, hist, n_bins, st, ev);
+      hipLaunchKernelGGL(ia::k_vote<256>, dim3(grid), dim3(ia::kWG), 0, s, recs, n, par, sh, votes, hist, n_bins, st, ev,
+                         flags, wg_max);
       break;
     case 128:
-      hipLaunchKernelGGL(ia::k_vote<128>, dim3(grid), dim3(ia::kWG), 0, s, recs, n, par, sh, votes, hist, n_bins, st, ev);
+      hipLaunchKernelGGL(ia::k_vote<128>, dim3(grid), dim3(ia::kWG), 0, s, recs, n, par, sh, votes, hist, n_bins, st, ev,
+                         flags, wg_max);
       break;
     default:
-      hipLaunchKernelGGL(ia::k_vote<64>, dim3(grid), dim3(ia::kWG), 0, s, recs, n, par, sh, votes, hist, n_bins, st, ev);
+      hipLaunchKernelGGL(ia::k_vote<64>, dim3(grid), dim3(ia::kWG), 0, s, recs, n, par, sh, votes, hist, n_bins, st, ev,
+                         flags, wg_max);
       break;
   }
   if (c->profiling) {
@@ -197,10 +221,11 @@ ia_status launch_estimate(ia_ctx* c, const BoxD* par, const Shape& sh, const uin
 
 // scratch layout of ia_find_helices (byte offsets into the arena)
 struct FindLayout {
-  size_t recs, votes, hist, cnt, tmp, selA, selB, range, sel_idx, sel_v, ev, part, total;
+  size_t recs, votes, hist, cnt, tmp, selA, selB, range, sel_idx, sel_v, ev, part, flags, wg_max, total;
+  size_t flag_cap;
 };
 
-void layout_find(int64_t max_level_boxes, int32_t top_k, int32_t max_hits, FindLayout* L) {
+void layout_find(int64_t max_level_boxes, int64_t max_triples, int32_t top_k, int32_t max_hits, FindLayout* L) {
   uint32_t chunk;
   const int32_t g = sel_groups(max_level_boxes, &chunk);
   const int32_t n_part = est_parts(static_cast<uint32_t>(max_level_boxes));
@@ -222,6 +247,9 @@ void layout_find(int64_t max_level_boxes, int32_t top_k, int32_t max_hits, FindL
   L->sel_v = take(sizeof(uint16_t) * size_t(top_k));
   L->ev = take(sizeof(EventState));
   L->part = take(sizeof(double) * ia::kEstQ * size_t(n_part));
+  L->flag_cap = size_t(max_triples) * size_t(std::max(0, max_hits));
+  L->flags = take(L->flag_cap);
+  L->wg_max = take(sizeof(int32_t) * size_t((max_level_boxes + 63) / 64));
   L->total = off;
 }
 
@@ -293,6 +321,13 @@ ia_status ia_ctx_set_vote_tile(ia_ctx* c, int32_t bx) {
   return IA_OK;
 }
 
+ia_status ia_ctx_set_prefilter(ia_ctx* c, int32_t mode) {
+  if (!c) return IA_ERR_INVALID;
+  if (mode < -1 || mode > 1) return fail(c, IA_ERR_INVALID, "prefilter mode %d not in {-1, 0, 1}", mode);
+  c->filter_mode = mode;
+  return IA_OK;
+}
+
 ia_status ia_ctx_set_profiling(ia_ctx* c, int32_t enable) {
   if (!c) return IA_ERR_INVALID;
   c->profiling = enable != 0;
@@ -329,8 +364,11 @@ size_t ia_ctx_scratch_needed(const ia_schedule* sc, int32_t max_hits) {
   for (int j = 0; j < 5; ++j) { nb0 *= std::max(1, sc->bins[j]); nc *= std::max(1, sc->split[j]); }
   const int64_t nbr = int64_t(std::max(1, sc->top_k)) * nc;
   const int64_t nb = std::min<int64_t>(std::max(nb0, nbr), kMaxLevelBoxes);
+  const int64_t nt0 = int64_t(std::max(1, sc->bins[0])) * std::max(1, sc->bins[1]) * std::max(1, sc->bins[2]);
+  const int64_t ntr = int64_t(std::max(1, sc->top_k)) * std::max(1, sc->split[0]) * std::max(1, sc->split[1]) *
+                      std::max(1, sc->split[2]);
   FindLayout L;
-  layout_find(nb, std::max(1, sc->top_k), max_hits, &L);
+  layout_find(nb, std::max(nt0, ntr), std::max(1, sc->top_k), max_hits, &L);
   return L.total;
 }
 
@@ -355,7 +393,12 @@ ia_status ia_vote_level(ia_ctx* c, const ia_hit* d_hits, int32_t n_hits, const u
     hipLaunchKernelGGL(ia::k_prep, dim3((n_hits + 255) / 256), dim3(256), 0, s,
                        reinterpret_cast<const double*>(d_hits), d_active, n_hits, recs, nullptr, 0, &ps->status,
                        &ps->n_bad, nullptr, nullptr, nullptr, BoxD{}, nullptr);
-  return launch_vote(c, recs, n_hits, reinterpret_cast<const BoxD*>(d_parents), sh, d_votes, nullptr, 0, nullptr, s);
+  // the pre-pass flags, when the remaining scratch holds them (results do not depend on it)
+  const size_t flag_cap = size_t(sh.n_parents) * sh.m012 * size_t(std::max(0, n_hits));
+  uint8_t* flags = (n_hits > 0 && use_filter(c, sh)) ? bump<uint8_t>(c, flag_cap) : nullptr;
+  const BoxD* par = reinterpret_cast<const BoxD*>(d_parents);
+  const uint8_t* fl = launch_filter(c, recs, n_hits, par, sh, flags, flags ? flag_cap : 0, nullptr, s);
+  return launch_vote(c, recs, n_hits, par, sh, d_votes, nullptr, 0, nullptr, fl, nullptr, s);
 }
 
 ia_status ia_refine(ia_ctx* c, const ia_box* d_parents, int32_t n_parents, const int32_t split[5],
@@ -453,16 +496,15 @@ ia_status ia_find_helices(ia_ctx* c, const ia_hit* d_hits, const int32_t* h_off,
     return fail(c, IA_ERR_OVERFLOW, "a level exceeds %lld boxes", static_cast<long long>(kMaxEstimateBoxes));
   IA_HIP(c, hipSetDevice(c->device));
   const int32_t K = sc->top_k;
+  const int64_t nt0 = int64_t(sh0.n_parents) * sh0.m012, ntr = int64_t(shr.n_parents) * shr.m012;
   FindLayout L;
-  layout_find(std::max<int64_t>(sh0.n_boxes, shr.n_boxes), K, max_hits, &L);
+  layout_find(std::max<int64_t>(sh0.n_boxes, shr.n_boxes), std::max(nt0, ntr), K, max_hits, &L);
   if (L.total > c->arena_bytes)
     return fail(c, IA_ERR_NOMEM, "scratch too small: need %zu bytes, have %zu", L.total, c->arena_bytes);
   char* a = c->arena;
   HitRec* recs = reinterpret_cast<HitRec*>(a + L.recs);
   uint16_t* votes = reinterpret_cast<uint16_t*>(a + L.votes);
   uint32_t* hist = reinterpret_cast<uint32_t*>(a + L.hist);
-  int32_t* cnt = reinterpret_cast<int32_t*>(a + L.cnt);
-  uint32_t* tmp = reinterpret_cast<uint32_t*>(a + L.tmp);
   BoxD* selA = reinterpret_cast<BoxD*>(a + L.selA);
   BoxD* selB = reinterpret_cast<BoxD*>(a + L.selB);
   BoxD* range = reinterpret_cast<BoxD*>(a + L.range);
@@ -470,6 +512,8 @@ ia_status ia_find_helices(ia_ctx* c, const ia_hit* d_hits, const int32_t* h_off,
   uint16_t* sel_v = reinterpret_cast<uint16_t*>(a + L.sel_v);
   EventState* ev = reinterpret_cast<EventState*>(a + L.ev);
   double* part = reinterpret_cast<double*>(a + L.part);
+  uint8_t* flags = reinterpret_cast<uint8_t*>(a + L.flags);
+  int32_t* wg_max = reinterpret_cast<int32_t*>(a + L.wg_max);
   hipStream_t s = as_stream(stream);
   Persistent* ps = persistent(c);
   BoxD rb;
@@ -489,11 +533,14 @@ ia_status ia_find_helices(ia_ctx* c, const ia_hit* d_hits, const int32_t* h_off,
       Shape sh = sh0;
       BoxD* sel = selA;
       for (int32_t lev = 0; lev <= sc->n_refine; ++lev) {
-        ia_status st = launch_vote(c, recs, n, par, sh, votes, hist, n_bins, ev, s);
+        const uint8_t* fl = launch_filter(c, recs, n, par, sh, flags, L.flag_cap, ev, s);
+        int32_t bx = 0;
+        ia_status st = launch_vote(c, recs, n, par, sh, votes, hist, n_bins, ev, fl, wg_max, s, &bx);
         if (st != IA_OK) return st;
-        st = launch_select(c, votes, sh, par, hist, n_bins, K, cnt, tmp, sel, sel_idx, sel_v, ev,
-                           lev == 0 ? std::max(sc->v_min, 0) : 0, s);
-        if (st != IA_OK) return st;
+        const uint32_t n_wg = (sh.n_boxes + bx - 1) / bx;
+        hipLaunchKernelGGL(ia::k_select_wg, dim3(1), dim3(ia::kWG), 0, s, votes, sh.n_boxes, hist, n_bins, K, wg_max,
+                           n_wg, bx, par, sh, sel, sel_idx, sel_v, ev, lev == 0 ? std::max(sc->v_min, 0) : 0);
+        IA_HIP(c, hipGetLastError());
         if (lev == sc->n_refine) break;
         const int32_t k_eff = static_cast<int32_t>(std::min<int64_t>(K, sh.n_boxes));
         if (!make_shape(sc->split, k_eff, &sh)) return fail(c, IA_ERR_OVERFLOW, "split too large");

@@ -18,6 +18,9 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+// IA_HD: compiled for the device and, for the host-side checks, for the host
+#define IA_HD __host__ __device__ __forceinline__
+
 namespace ia {
 
 // pi/2 = P1 + P2 + P3 (+ 1e-37): P1, P2 carry 33 significant bits
@@ -27,7 +30,8 @@ constexpr double kPio2b = 0x1.0b4611a6p-34;
 constexpr double kPio2c = 0x1.3198a2e037073p-69;
 constexpr double kPi = 0x1.921fb54442d18p+1;      // below pi
 constexpr double kTwoPi = 0x1.921fb54442d18p+2;   // below 2 pi
-constexpr double kPio2 = 0x1.921fb54442d18p+0;
+constexpr double kPio2 = 0x1.921fb54442d18p+0;    // below pi/2
+constexpr double kPio2Up = 0x1.921fb54442d19p+0;  // above pi/2
 constexpr double kPio6 = 0x1.0c152382d7366p-1;
 constexpr double kSqrt3 = 0x1.bb67ae8584caap+0;
 constexpr double kInvTwoPi = 0x1.45f306dc9c883p-3;
@@ -35,10 +39,10 @@ constexpr double kTanPi12 = 0x1.126145e9ecd56p-2;
 constexpr double kSinMargin = 0x1p-50;   // > 4x the error of sin_p / cos_p
 constexpr double kExtFuzz = 0x1p-40;     // extremum-membership slack
 
-__device__ __forceinline__ double wdn(double x) { return x - fma(fabs(x), 0x1p-52, 0x1p-1074); }
-__device__ __forceinline__ double wup(double x) { return x + fma(fabs(x), 0x1p-52, 0x1p-1074); }
+IA_HD double wdn(double x) { return x - fma(fabs(x), 0x1p-52, 0x1p-1074); }
+IA_HD double wup(double x) { return x + fma(fabs(x), 0x1p-52, 0x1p-1074); }
 
-__device__ __forceinline__ double poly_sin(double r) {
+IA_HD double poly_sin(double r) {
   double z = r * r;
   double p = 1.0 / 355687428096000.0;      // 1/17!
   p = fma(p, z, -1.0 / 1307674368000.0);   // 1/15!
@@ -51,7 +55,7 @@ __device__ __forceinline__ double poly_sin(double r) {
   return fma(r * z, p, r);
 }
 
-__device__ __forceinline__ double poly_cos(double r) {
+IA_HD double poly_cos(double r) {
   double z = r * r;
   double q = 1.0 / 20922789888000.0;       // 1/16!
   q = fma(q, z, -1.0 / 87178291200.0);     // 1/14!
@@ -65,21 +69,21 @@ __device__ __forceinline__ double poly_cos(double r) {
 }
 
 // x = k pi/2 + r
-__device__ __forceinline__ double reduce_quadrant(double x, int* quad) {
+IA_HD double reduce_quadrant(double x, int* quad) {
   double k = rint(x * kTwoOverPi);
   double r = ((x - k * kPio2a) - k * kPio2b) - k * kPio2c;
   *quad = static_cast<int>(static_cast<int64_t>(k) & 3);
   return r;
 }
 
-__device__ __forceinline__ double sin_p(double x) {
+IA_HD double sin_p(double x) {
   int q;
   double r = reduce_quadrant(x, &q);
   double v = (q & 1) ? poly_cos(r) : poly_sin(r);
   return (q & 2) ? -v : v;
 }
 
-__device__ __forceinline__ double cos_p(double x) {
+IA_HD double cos_p(double x) {
   int q;
   double r = reduce_quadrant(x, &q);
   double v = (q & 1) ? poly_sin(r) : poly_cos(r);
@@ -87,7 +91,7 @@ __device__ __forceinline__ double cos_p(double x) {
 }
 
 // sin and cos of the same argument with one reduction
-__device__ __forceinline__ void sincos_p(double x, double* s, double* c) {
+IA_HD void sincos_p(double x, double* s, double* c) {
   int q;
   double r = reduce_quadrant(x, &q);
   double ps = poly_sin(r), pc = poly_cos(r);
@@ -97,7 +101,7 @@ __device__ __forceinline__ void sincos_p(double x, double* s, double* c) {
   *c = ((q + 1) & 2) ? -cv : cv;
 }
 
-__device__ __forceinline__ double poly_atan(double u) {
+IA_HD double poly_atan(double u) {
   double z = u * u;
   double p = 1.0 / 29.0;
   p = fma(p, z, -1.0 / 27.0);
@@ -117,7 +121,7 @@ __device__ __forceinline__ double poly_atan(double u) {
 }
 
 // angle of (x, y) in [-pi, pi]; 0 at the origin
-__device__ __forceinline__ double atan2_p(double y, double x) {
+IA_HD double atan2_p(double y, double x) {
   double ax = fabs(x), ay = fabs(y);
   if (ax == 0.0 && ay == 0.0) return 0.0;
   bool swap = ay > ax;
@@ -133,23 +137,34 @@ __device__ __forceinline__ double atan2_p(double y, double x) {
 
 struct Iv { double lo, hi; };
 
-__device__ __forceinline__ Iv iadd(Iv a, Iv b) { return {wdn(a.lo + b.lo), wup(a.hi + b.hi)}; }
-__device__ __forceinline__ Iv isub(Iv a, Iv b) { return {wdn(a.lo - b.hi), wup(a.hi - b.lo)}; }
-__device__ __forceinline__ Iv imul(Iv a, Iv b) {
+IA_HD Iv iadd(Iv a, Iv b) { return {wdn(a.lo + b.lo), wup(a.hi + b.hi)}; }
+IA_HD Iv isub(Iv a, Iv b) { return {wdn(a.lo - b.hi), wup(a.hi - b.lo)}; }
+IA_HD Iv imul(Iv a, Iv b) {
   double p1 = a.lo * b.lo, p2 = a.lo * b.hi, p3 = a.hi * b.lo, p4 = a.hi * b.hi;
   return {wdn(fmin(fmin(p1, p2), fmin(p3, p4))), wup(fmax(fmax(p1, p2), fmax(p3, p4)))};
 }
 // interval times a non-negative point: the 4-product rule reduces to two products
-__device__ __forceinline__ Iv imul_pos(Iv a, double s) { return {wdn(a.lo * s), wup(a.hi * s)}; }
-__device__ __forceinline__ Iv isqr(Iv a) {
+IA_HD Iv imul_pos(Iv a, double s) { return {wdn(a.lo * s), wup(a.hi * s)}; }
+IA_HD Iv isqr(Iv a) {
   double l2 = a.lo * a.lo, h2 = a.hi * a.hi;
   if (a.lo <= 0.0 && a.hi >= 0.0) return {0.0, wup(fmax(l2, h2))};
   return {wdn(fmin(l2, h2)), wup(fmax(l2, h2))};
 }
-__device__ __forceinline__ Iv itwice(Iv a) { return {2.0 * a.lo, 2.0 * a.hi}; }
+IA_HD Iv itwice(Iv a) { return {2.0 * a.lo, 2.0 * a.hi}; }
+IA_HD Iv ipt(double x) { return {x, x}; }
+IA_HD Iv ineg(Iv a) { return {-a.hi, -a.lo}; }
+// a / p for a point p > 0
+IA_HD Iv idivp(Iv a, double p) { return {wdn(a.lo / p), wup(a.hi / p)}; }
+// a / b for b > 0: the quotient is monotone in each argument
+IA_HD Iv idiv_pos(Iv a, Iv b) {
+  double q1 = a.lo / b.lo, q2 = a.lo / b.hi, q3 = a.hi / b.lo, q4 = a.hi / b.hi;
+  return {wdn(fmin(fmin(q1, q2), fmin(q3, q4))), wup(fmax(fmax(q1, q2), fmax(q3, q4)))};
+}
+// square root of [lo, hi] with hi >= 0; negative parts are clipped
+IA_HD Iv isqrt(Iv a) { return {a.lo > 0.0 ? wdn(sqrt(a.lo)) : 0.0, wup(sqrt(a.hi))}; }
 
 // enclosure of sin over [a, b]
-__device__ __forceinline__ Iv sin_encl(double a, double b) {
+IA_HD Iv sin_encl(double a, double b) {
   if (b - a >= kTwoPi) return {-1.0, 1.0};
   double va = sin_p(a), vb = sin_p(b);
   double l = fmin(va, vb) - kSinMargin, h = fmax(va, vb) + kSinMargin;
@@ -159,5 +174,8 @@ __device__ __forceinline__ Iv sin_encl(double a, double b) {
   if (h > 1.0) h = 1.0;
   return {l, h};
 }
+
+// enclosure of cos over [a, b] as sin over [a + pi/2, b + pi/2]
+IA_HD Iv cos_encl(double a, double b) { return sin_encl(wdn(a + kPio2), wup(b + kPio2Up)); }
 
 }  // namespace ia

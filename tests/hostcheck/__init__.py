@@ -1,0 +1,54 @@
+"""Loader of the host-side check harness (the HIP library's vote arithmetic
+compiled for the CPU).  Test infrastructure only."""
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "ia_hostcheck.hip")
+LIB = os.path.join(HERE, "libia_hostcheck.so")
+ROOT = os.path.dirname(os.path.dirname(HERE))
+DEPS = [SRC] + [os.path.join(ROOT, "paper_2401_04576_amd", "csrc", f) for f in ("ia_math.hpp", "ia_kernels.hpp")]
+FLAGS = ["-O2", "-std=c++17", "-fPIC", "-shared", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
+         "--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+
+
+def build(force=True):
+    stale = not os.path.exists(LIB) or any(os.path.getmtime(d) > os.path.getmtime(LIB) for d in DEPS)
+    if force or stale:
+        tmp = LIB + ".tmp"
+        subprocess.check_call([os.environ.get("HIPCC", "/opt/rocm/bin/hipcc"), *FLAGS, "-o", tmp, SRC],
+                              stderr=subprocess.DEVNULL)
+        os.replace(tmp, LIB)
+    return LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build(force=False)
+        L = C.CDLL(LIB)
+        P = C.c_void_p
+        L.hc_vote_level.restype = C.c_int32
+        L.hc_vote_level.argtypes = [P, C.c_int32, P, C.c_int32, P, C.c_int32, P, P]
+        _lib = L
+    return _lib
+
+
+def vote_level(hits, parents, split, filter_on):
+    h = np.ascontiguousarray(hits).view(np.float64).reshape(-1, 8).copy() if len(hits) else np.zeros((0, 8))
+    p = np.atleast_1d(parents)
+    pa = np.ascontiguousarray(np.concatenate([p["lo"], p["hi"]], axis=1), dtype=np.float64)
+    sp = np.ascontiguousarray(split, dtype=np.int32)
+    nb = pa.shape[0] * int(np.prod(sp.astype(np.int64)))
+    votes = np.zeros(nb, dtype=np.uint16)
+    stats = np.zeros(3, dtype=np.int64)
+    rc = lib().hc_vote_level(h.ctypes.data, h.shape[0], pa.ctypes.data, pa.shape[0], sp.ctypes.data,
+                             1 if filter_on else 0, votes.ctypes.data, stats.ctypes.data)
+    assert rc == 0
+    return votes, stats

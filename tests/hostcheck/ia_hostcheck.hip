@@ -1,0 +1,85 @@
+// Host-side check harness: the vote arithmetic of libia (the same
+// __host__ __device__ functions the HIP kernels run), compiled for the CPU
+// and driven by a loop with the kernel's structure -- per (triple, hit)
+// staging, the (triple, hit) pre-filter, then the per-box stereo term.
+// Used only by the tests, to compare the device arithmetic with the oracle
+// on many events without a GPU.
+#include <cstdint>
+#include <vector>
+
+#include "../../paper_2401_04576_amd/csrc/ia_kernels.hpp"
+
+using namespace ia;
+
+static bool make_shape(const int32_t m[5], int64_t n_parents, Shape* sh) {
+  int64_t nc = 1;
+  for (int j = 0; j < 5; ++j) {
+    if (m[j] < 1) return false;
+    sh->m[j] = static_cast<uint32_t>(m[j]);
+    nc *= m[j];
+  }
+  sh->nc = static_cast<uint32_t>(nc);
+  sh->m34 = sh->m[3] * sh->m[4];
+  sh->m012 = sh->m[0] * sh->m[1] * sh->m[2];
+  sh->m12 = sh->m[1] * sh->m[2];
+  sh->n_boxes = static_cast<uint32_t>(nc * n_parents);
+  sh->n_parents = static_cast<uint32_t>(n_parents);
+  return true;
+}
+
+extern "C" {
+
+// votes of the boxes of a level; stats[0] = stereo (triple, hit) pairs,
+// stats[1] = pairs removed by the pre-filter, stats[2] = stereo (box, hit)
+// evaluations performed
+int32_t hc_vote_level(const double* hits, int32_t n_hits, const double* parents, int32_t n_parents,
+                      const int32_t split[5], int32_t filter, uint16_t* votes, int64_t* stats) {
+  Shape sh;
+  if (!make_shape(split, n_parents, &sh)) return 1;
+  std::vector<HitRec> rec(n_hits > 0 ? n_hits : 1);
+  for (int32_t i = 0; i < n_hits; ++i) {
+    bool bad;
+    prep_one(hits + 8 * i, true, &rec[i], &bad);
+  }
+  const BoxD* P = reinterpret_cast<const BoxD*>(parents);
+  const int64_t n_triples = int64_t(n_parents) * sh.m012;
+  int64_t n_pairs = 0, n_cut = 0, n_evals = 0;
+#pragma omp parallel for schedule(dynamic, 4) reduction(+ : n_pairs, n_cut, n_evals)
+  for (int64_t t = 0; t < n_triples; ++t) {
+    const uint32_t tp = static_cast<uint32_t>(t / sh.m012), tc = static_cast<uint32_t>(t % sh.m012);
+    const uint32_t t0 = tc / sh.m12, t1 = (tc / sh.m[2]) % sh.m[1], t2 = tc % sh.m[2];
+    const Frame f = triple_frame(P[tp], sh.m, t0, t1, t2);
+    Iv Zr, Lr;
+    centre_ranges(P[tp], sh.m, &Zr, &Lr);
+    std::vector<int32_t> nv(sh.m34, 0);
+    for (int32_t i = 0; i < n_hits; ++i) {
+      const HitRec& h = rec[i];
+      if (!h.use) continue;
+      const Iv G = residual_G(f, h);
+      if (h.axial) {
+        if (h_contains0(G, f.K, f.sig * h.d, h.band) || h_contains0(G, f.K, f.sig * (-h.d), h.band))
+          for (uint32_t l = 0; l < sh.m34; ++l) ++nv[l];
+        continue;
+      }
+      const PairQ q = pair_quantities(f, h, G);
+      ++n_pairs;
+      if (filter && !triple_may_vote(q, f, h, Zr, Lr)) { ++n_cut; continue; }
+      for (uint32_t l = 0; l < sh.m34; ++l) {
+        const uint32_t k3 = l / sh.m[4], k4 = l % sh.m[4];
+        double zlo, zhi, llo, lhi;
+        child_edge(P[tp].lo[3], P[tp].hi[3], sh.m[3], k3, &zlo, &zhi);
+        child_edge(P[tp].lo[4], P[tp].hi[4], sh.m[4], k4, &llo, &lhi);
+        const double z0 = 0.5 * (zlo + zhi), lam = 0.5 * (llo + lhi);
+        ++n_evals;
+        if (stereo_vote(q, f.R, f.sig, f.K, z0, lam, lam * f.R, lam * lam, h.tant, h.tant * h.tant, h.d, h.band))
+          ++nv[l];
+      }
+    }
+    const int64_t base = int64_t(tp) * sh.nc + int64_t(tc) * sh.m34;
+    for (uint32_t l = 0; l < sh.m34; ++l) votes[base + l] = static_cast<uint16_t>(nv[l]);
+  }
+  if (stats) { stats[0] = n_pairs; stats[1] = n_cut; stats[2] = n_evals; }
+  return 0;
+}
+
+}  // extern "C"

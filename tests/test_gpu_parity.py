@@ -56,8 +56,10 @@ def _gpu_votes(ctx, hits, parents, split, active=None):
     return _votes_np(v)
 
 
-def test_level0_votes_bit_exact_cfg1(ctx):
+@pytest.mark.parametrize("prefilter", [0, -1])
+def test_level0_votes_bit_exact_cfg1(ctx, prefilter):
     """Single event, 12^5 level-0 grid (the plain FP64 single-level workload)."""
+    ctx.set_prefilter(prefilter)
     for ev_i in range(2):
         ev = toymc.config_event(1, ev_i)
         print(f"cfg1 event {ev_i} N={ev.n_hits}", flush=True)
@@ -67,6 +69,7 @@ def test_level0_votes_bit_exact_cfg1(ctx):
         assert got.shape == ref.shape
         bad = np.flatnonzero(got != ref)
         assert bad.size == 0, (bad[:10], got[bad[:10]], ref[bad[:10]])
+    ctx.set_prefilter(-1)
 
 
 def test_refinement_shape_votes_bit_exact(ctx):
@@ -81,13 +84,16 @@ def test_refinement_shape_votes_bit_exact(ctx):
     assert np.array_equal(got, ref)
 
 
+@pytest.mark.parametrize("prefilter", [0, 1])
 @pytest.mark.parametrize("tile", [64, 128, 256])
 @pytest.mark.parametrize("split,n_par", [((3, 5, 2, 7, 3), 5), ((1, 1, 1, 1, 1), 300), ((2, 3, 1, 1, 1), 77),
                                          ((5, 1, 4, 1, 2), 3), ((4, 4, 4, 4, 4), 32)])
-def test_ragged_shapes_bit_exact(ctx, split, n_par, tile):
+def test_ragged_shapes_bit_exact(ctx, split, n_par, tile, prefilter):
     """Shapes with ragged tiles (several triples per workgroup, partial last
-    tile) under every vote-kernel tile: one box per lane, hits split over 2 or 4 waves."""
+    tile) under every vote-kernel tile (one box per lane, hits split over 2
+    or 4 waves), with the (triple, hit) pre-filter off and forced on."""
     ctx.set_vote_tile(tile)
+    ctx.set_prefilter(prefilter)
     ev = toymc.config_event(2, 5)
     rng = np.random.default_rng(41)
     t = ev.truth[0]
@@ -99,6 +105,7 @@ def test_ragged_shapes_bit_exact(ctx, split, n_par, tile):
         got = _gpu_votes(ctx, ev.hits, parents, split)
     finally:
         ctx.set_vote_tile(0)
+        ctx.set_prefilter(-1)
     assert np.array_equal(got, ref)
 
 
