@@ -27,7 +27,9 @@ PREP_DTYPE = np.dtype([("valid", "i4"), ("axial", "i4"), ("px", "f8"), ("py", "f
                        ("band", "f8")])
 SCHED_DTYPE = np.dtype([("range", BOX_DTYPE), ("bins", "i4", (5,)), ("n_refine", "i4"),
                         ("top_k", "i4"), ("split", "i4", (5,)), ("v_min", "i4"),
-                        ("n_helix_max", "i4"), ("hitfind_scale", "f8")], align=True)
+                        ("n_helix_max", "i4"), ("hitfind_scale", "f8"), ("prec", "i4", (8,)),
+                        ("fp32_slack", "f8")], align=True)
+FP64, FP32 = 0, 1
 HELIX_DTYPE = np.dtype([("p", "f8", (5,)), ("err", "f8", (5,)), ("votes", "i4"),
                         ("n_assigned", "i4"), ("n_argmax", "i4"), ("pad", "i4")])
 MAX_LEVELS, MAX_K, MAX_PASSES = 8, 64, 16
@@ -75,6 +77,17 @@ def lib():
         L.or_pair_vote.restype = i32; L.or_pair_vote.argtypes = [_P, _P, _P]
         L.or_vote_level.restype = None
         L.or_vote_level.argtypes = [_P, i32, _P, _P, i32, _P, _P, i32]
+        L.or_vote_level_prec.restype = None
+        L.or_vote_level_prec.argtypes = [_P, i32, _P, _P, i32, _P, i32, d, _P, i32]
+        f = C.c_float
+        L.or_rd32.restype = f; L.or_rd32.argtypes = [d]
+        L.or_ru32.restype = f; L.or_ru32.argtypes = [d]
+        L.or_wdn32.restype = f; L.or_wdn32.argtypes = [f]
+        L.or_wup32.restype = f; L.or_wup32.argtypes = [f]
+        L.or_sinf1.restype = f; L.or_sinf1.argtypes = [f]
+        L.or_cosf1.restype = f; L.or_cosf1.argtypes = [f]
+        L.or_stereo_e32.restype = i32; L.or_stereo_e32.argtypes = [_P, _P, i32, _P, _P]
+        L.or_pair_vote32.restype = i32; L.or_pair_vote32.argtypes = [_P, _P, d, _P]
         L.or_topk.restype = i32; L.or_topk.argtypes = [_P, i64, i32, _P, _P]
         L.or_estimate.restype = i32
         L.or_estimate.argtypes = [_P, i32, _P, _P, C.c_uint16, _P, _P]
@@ -180,16 +193,60 @@ def pair_vote(prep, box, debug=False):
     return (int(v), dbg) if debug else int(v)
 
 
-def vote_level(hits, parents, split, active=None, n_threads=0):
+def vote_level(hits, parents, split, active=None, n_threads=0, prec=FP64, slack=1e-6):
     hits = _c(hits, HIT_DTYPE)
     parents = _c(np.atleast_1d(parents), BOX_DTYPE)
     split = _c(split, np.int32)
     nb = parents.shape[0] * int(np.prod(split.astype(np.int64)))
     votes = np.zeros(nb, dtype=np.uint16)
     act = None if active is None else _c(active, np.uint8)
-    lib().or_vote_level(_ptr(hits), hits.shape[0], _ptr(act), _ptr(parents), parents.shape[0],
-                        _ptr(split), _ptr(votes), int(n_threads))
+    lib().or_vote_level_prec(_ptr(hits), hits.shape[0], _ptr(act), _ptr(parents), parents.shape[0],
+                             _ptr(split), int(prec), C.c_double(slack), _ptr(votes), int(n_threads))
     return votes
+
+
+def rd32(x):
+    return np.float32(lib().or_rd32(C.c_double(x)))
+
+
+def ru32(x):
+    return np.float32(lib().or_ru32(C.c_double(x)))
+
+
+def wdn32(x):
+    return np.float32(lib().or_wdn32(C.c_float(x)))
+
+
+def wup32(x):
+    return np.float32(lib().or_wup32(C.c_float(x)))
+
+
+def sinf1(x):
+    return np.float32(lib().or_sinf1(C.c_float(x)))
+
+
+def cosf1(x):
+    return np.float32(lib().or_cosf1(C.c_float(x)))
+
+
+def stereo_e32(prep, c, s, debug=False):
+    """FP32-level d^Ax: (valid, e32) or (valid, e32, 24 float intermediates)."""
+    prep = _c(np.atleast_1d(prep), PREP_DTYPE)
+    c = _c(c, np.float64)
+    e = np.zeros(1, dtype=np.float32)
+    dbg = np.full(24, np.nan, dtype=np.float32) if debug else None
+    ok = lib().or_stereo_e32(_ptr(prep), _ptr(c), int(s), _ptr(e), _ptr(dbg))
+    if debug:
+        return bool(ok), e[0], dbg
+    return bool(ok), e[0]
+
+
+def pair_vote32(prep, box, slack=1e-6, debug=False):
+    prep = _c(np.atleast_1d(prep), PREP_DTYPE)
+    box = _c(np.atleast_1d(box), BOX_DTYPE)
+    dbg = np.full(8, np.nan, dtype=np.float32) if debug else None
+    v = lib().or_pair_vote32(_ptr(prep), _ptr(box), C.c_double(slack), _ptr(dbg))
+    return (int(v), dbg) if debug else int(v)
 
 
 def topk(votes, k):
@@ -212,8 +269,12 @@ def estimate(parents, split, votes, vmax):
 
 
 def make_sched(lo, hi, bins, n_refine=4, top_k=32, split=(4, 4, 4, 4, 4), v_min=10,
-               n_helix_max=1, hitfind_scale=5.0):
+               n_helix_max=1, hitfind_scale=5.0, prec=None, fp32_slack=1e-6):
+    """prec: per-level FP64 / FP32 list (default all FP64)."""
     s = np.zeros((), dtype=SCHED_DTYPE)
+    if prec is not None:
+        s["prec"][:len(prec)] = prec
+    s["fp32_slack"] = fp32_slack
     s["range"]["lo"] = lo
     s["range"]["hi"] = hi
     s["bins"] = bins

@@ -14,6 +14,10 @@
  * three-part constant, Taylor polynomials evaluated by Horner's rule with
  * fused multiply-adds), so their results do not depend on the C library.
  *
+ * Levels of a mixed-precision schedule marked FP32 use or_pair_vote32, whose
+ * definition (FP32 arithmetic for the (z0, tanl) part of d^Ax, an FP32
+ * interval test with a widened band) is stated at its source below.
+ *
  * Parity status of each function is stated at its definition.
  */
 #include "ia_oracle.h"
@@ -308,8 +312,7 @@ int32_t or_stereo_e(const or_prep *h, const double c[5], int32_t s, double *e, d
  * over the whole box; e is the point value at the middle of the box for each
  * drift sign; one vote when zero is enclosed for either sign.
  * ---------------------------------------------------------------------- */
-int32_t or_pair_vote(const or_prep *h, const or_box *b, double *dbg) {
-  if (!h->valid) return 0;
+static iv pair_G(const or_prep *h, const or_box *b) {
   iv K = {b->lo[2], b->hi[2]}, Dd = {b->lo[0], b->hi[0]};
   iv Ar = {or_wdn(b->lo[1] - h->phip), or_wup(b->hi[1] - h->phip)};
   iv S;
@@ -320,7 +323,13 @@ int32_t or_pair_vote(const or_prep *h, const or_box *b, double *dbg) {
   iv T = {0.5 * T0.lo, 0.5 * T0.hi};
   iv KT = iv_mul(K, T);
   iv KD1 = iv_add(iv_mul(K, Dd), iv_point(1.0));
-  iv G = iv_add(iv_add(KT, iv_mul(KD1, rS)), Dd);
+  return iv_add(iv_add(KT, iv_mul(KD1, rS)), Dd);
+}
+
+int32_t or_pair_vote(const or_prep *h, const or_box *b, double *dbg) {
+  if (!h->valid) return 0;
+  iv K = {b->lo[2], b->hi[2]};
+  iv G = pair_G(h, b);
   double c[5];
   for (int j = 0; j < 5; j++) c[j] = 0.5 * (b->lo[j] + b->hi[j]);
   int32_t vote = 0;
@@ -338,6 +347,169 @@ int32_t or_pair_vote(const or_prep *h, const or_box *b, double *dbg) {
 }
 
 /* ------------------------------------------------------------------------
+ * FP32 levels of a mixed-precision schedule.
+ *
+ * The paper computes in FP64 throughout.  A level marked FP32 decides a
+ * (box, stereo hit) pair by the following definition:
+ *  - what depends on the box only through (d0, phi0, kappa) -- the
+ *    enclosure G of Eq. ApoVote and the transverse quantities of d^Ax
+ *    (R, R^Ax, c^Ax, s^Ax, sin and cos Phi^Ax, phi^Ax - phi0) -- is computed
+ *    in FP64 exactly as in or_pair_vote and or_stereo_e; G and the kappa
+ *    interval are then rounded outward to FP32, the point quantities to
+ *    nearest;
+ *  - the part of d^Ax that depends on the centre (z0, tanl) is evaluated in
+ *    FP32, in the operation order of or_stereo_e;
+ *  - the vote is the interval test of or_pair_vote in FP32, each result
+ *    widened by |x| 2^-23 + 2^-149 (at least one FP32 ulp), with the
+ *    tolerance band widened by `slack`, a bound on |e32 - e64|;
+ *  - the FP32 evaluation is used only inside the domain where that bound
+ *    holds (R <= 2048 m, |Phi - Phi^Ax| <= 1, a positive discriminant, a
+ *    finite result); outside it the pair votes.
+ * Axial hits are decided exactly as at FP64 levels.  If |e32 - e64| <= slack,
+ * every FP32 interval contains the matching FP64 one (the operations are
+ * inclusion-monotone and FP32 outward rounding is wider than FP64), so an
+ * FP32 level votes for every pair an FP64 level votes for.
+ * ---------------------------------------------------------------------- */
+static const double R32_MAX = 2048.0;
+
+/* the FP32 numbers next to x: largest <= x, smallest >= x */
+float or_rd32(double x) {
+  float f = (float)x;
+  if ((double)f > x) f = nextafterf(f, -INFINITY);
+  return f;
+}
+float or_ru32(double x) {
+  float f = (float)x;
+  if ((double)f < x) f = nextafterf(f, INFINITY);
+  return f;
+}
+float or_wdn32(float x) { return x - fmaf(fabsf(x), 0x1p-23f, 0x1p-149f); }
+float or_wup32(float x) { return x + fmaf(fabsf(x), 0x1p-23f, 0x1p-149f); }
+
+typedef struct { float lo, hi; } ivf;
+static ivf ivf_add(ivf a, ivf b) { ivf r = {or_wdn32(a.lo + b.lo), or_wup32(a.hi + b.hi)}; return r; }
+static ivf ivf_sub(ivf a, ivf b) { ivf r = {or_wdn32(a.lo - b.hi), or_wup32(a.hi - b.lo)}; return r; }
+static ivf ivf_mul(ivf a, ivf b) {
+  float p1 = a.lo * b.lo, p2 = a.lo * b.hi, p3 = a.hi * b.lo, p4 = a.hi * b.hi;
+  ivf r = {or_wdn32(fminf(fminf(p1, p2), fminf(p3, p4))), or_wup32(fmaxf(fmaxf(p1, p2), fmaxf(p3, p4)))};
+  return r;
+}
+static ivf ivf_sqr(ivf a) {
+  float l2 = a.lo * a.lo, h2 = a.hi * a.hi;
+  ivf r;
+  if (a.lo <= 0.0f && a.hi >= 0.0f) { r.lo = 0.0f; r.hi = or_wup32(fmaxf(l2, h2)); }
+  else { r.lo = or_wdn32(fminf(l2, h2)); r.hi = or_wup32(fmaxf(l2, h2)); }
+  return r;
+}
+static ivf ivf_twice(ivf a) { ivf r = {2.0f * a.lo, 2.0f * a.hi}; return r; }
+
+/* sin and cos on |x| <= 1: Taylor series to degree 11 and 12 (the first
+ * omitted terms are below 2e-10), Horner's rule with fused multiply-adds */
+float or_sinf1(float x) {
+  float z = x * x;
+  float p = 1.0f / 39916800.0f;            /* 1/11! */
+  p = fmaf(p, z, -1.0f / 362880.0f);       /* 1/9! */
+  p = fmaf(p, z, 1.0f / 5040.0f);          /* 1/7! */
+  p = fmaf(p, z, -1.0f / 120.0f);          /* 1/5! */
+  p = fmaf(p, z, 1.0f / 6.0f);             /* 1/3! */
+  return fmaf(-(x * z), p, x);
+}
+float or_cosf1(float x) {
+  float z = x * x;
+  float q = 1.0f / 479001600.0f;           /* 1/12! */
+  q = fmaf(q, z, -1.0f / 3628800.0f);      /* 1/10! */
+  q = fmaf(q, z, 1.0f / 40320.0f);         /* 1/8! */
+  q = fmaf(q, z, -1.0f / 720.0f);          /* 1/6! */
+  q = fmaf(q, z, 1.0f / 24.0f);            /* 1/4! */
+  q = fmaf(q, z, -0.5f);                   /* 1/2! */
+  return fmaf(z, q, 1.0f);
+}
+
+/* d^Ax at the point c for drift sign s, FP32 part as defined above.
+ * Returns 1 and writes e32 = sgn(kappa) d^Ax, or 0 outside the FP32 domain
+ * (then the caller votes).  dbg (nullable, 24 floats): as or_stereo_e. */
+int32_t or_stereo_e32(const or_prep *h, const double c[5], int32_t s, float *e, float *dbg) {
+  /* FP64: the transverse frame, as in or_stereo_e */
+  double kap = c[2], sig = 1.0;
+  if (kap < 0.0) sig = -1.0;
+  if (kap == 0.0) { kap = 0x1p-30; sig = 1.0; }
+  double kp = sig * kap, d0p = sig * c[0];
+  double sp0 = sig * or_sin(c[1]), cp0 = or_cos(c[1]);
+  double R = 1.0 / kp;
+  double Rd = R + d0p;
+  double xc = -(Rd * sp0), yc = Rd * cp0;
+  double py = sig * h->py, cps = sig * h->cphis, sps = h->sphis;
+  double Dx = h->px - xc, Dy = py - yc;
+  double RAx = sqrt(Dx * Dx + Dy * Dy);
+  double cAx = Dx * sps - Dy * cps;
+  double sAx = Dx * cps + Dy * sps;
+  double sinA = sAx / RAx, cosA = cAx / RAx;
+  double dphi = or_atan2(Dx * cp0 + Dy * sp0, Dx * sp0 - Dy * cp0);
+  if (!(R <= R32_MAX)) return 0;
+  /* round to FP32 */
+  const float fR = (float)R, fRAx = (float)RAx, fcAx = (float)cAx, fsAx = (float)sAx;
+  const float fsinA = (float)sinA, fcosA = (float)cosA, fdphi = (float)dphi;
+  const float fsArc = (float)(R * dphi);
+  const float fc2 = (float)(cosA * cosA - sinA * sinA), fs2 = (float)(2.0 * sinA * cosA);
+  const float ftwoRAx2 = (float)(2.0 * (RAx * RAx)), fRpRAx = (float)(R + RAx);
+  const float z0 = (float)c[3], lam = (float)c[4], tt = (float)h->tant;
+  const float dS = (float)s * (float)h->d;
+  /* FP32: the (z0, tanl) part, in the order of or_stereo_e */
+  float zA = z0 + lam * fsArc;
+  float Phi1 = -(zA * fsinA + (lam * dS) * fcosA) / fRAx;
+  float Phi2n = (lam * fR) * zA - ((lam * zA) * (fR - 2.0f * dS)) * fc2
+              + (zA * zA + dS * (fRAx + (lam * lam) * (fRpRAx - dS))) * fs2;
+  float Phi2 = Phi2n / ftwoRAx2;
+  float t2 = tt * tt;
+  float eps = Phi1 * tt + Phi2 * t2;
+  if (!(fabsf(eps) <= 1.0f)) return 0;
+  float se = or_sinf1(eps), ce = or_cosf1(eps);
+  float sinP = fsinA * ce + fcosA * se, cosP = fcosA * ce - fsinA * se;
+  float u = sqrtf(((1.0f + ((2.0f * lam) * sinP) * tt) + (lam * lam) * t2) + (cosP * cosP) * t2);
+  float delta = dS / u;
+  float sperp = fR * (fdphi + eps);
+  float zS = (z0 + lam * sperp) - (delta * cosP) * tt;
+  float ctau = zS * fcAx - (lam * delta) * fsAx;
+  float a1 = zS * tt, a2 = (lam * delta) * tt;
+  float Q = ((2.0f * ctau) * tt + a1 * a1) + a2 * a2;
+  float A = fR + delta;
+  float disc = A * A - Q;
+  if (!(disc > 0.0f)) return 0;
+  float dhat = delta - Q / (A + sqrtf(disc));
+  if (dbg) {
+    float v[24] = {fR, (float)xc, (float)yc, (float)Dx, (float)Dy, fRAx, fcAx, fsAx, fsinA, fcosA, fdphi,
+                   zA, Phi1, Phi2, eps, sinP, cosP, u, delta, sperp, zS, ctau, Q, dhat};
+    memcpy(dbg, v, sizeof v);
+  }
+  *e = (float)sig * dhat;
+  return isfinite(*e) ? 1 : 0;
+}
+
+/* the vote of one (box, hit) at an FP32 level; dbg (nullable, 8 floats):
+ * G lo/hi, H+ lo/hi, H- lo/hi, e+, e- */
+int32_t or_pair_vote32(const or_prep *h, const or_box *b, double slack, float *dbg) {
+  if (!h->valid) return 0;
+  if (h->axial) return or_pair_vote(h, b, NULL);
+  const iv G64 = pair_G(h, b);
+  ivf G = {or_rd32(G64.lo), or_ru32(G64.hi)};
+  ivf K = {or_rd32(b->lo[2]), or_ru32(b->hi[2])};
+  const float bs = or_wup32(or_ru32(h->band) + or_ru32(slack));
+  double c[5];
+  for (int j = 0; j < 5; j++) c[j] = 0.5 * (b->lo[j] + b->hi[j]);
+  int32_t vote = 0;
+  if (dbg) { dbg[0] = G.lo; dbg[1] = G.hi; for (int j = 2; j < 8; j++) dbg[j] = NAN; }
+  for (int32_t si = 0; si < 2; si++) {
+    float e;
+    if (!or_stereo_e32(h, c, si == 0 ? 1 : -1, &e, NULL)) { vote = 1; continue; }
+    ivf E = {or_wdn32(e - bs), or_wup32(e + bs)};
+    ivf H = ivf_sub(ivf_twice(G), ivf_add(ivf_twice(E), ivf_mul(K, ivf_sqr(E))));
+    if (dbg) { dbg[2 + 2 * si] = H.lo; dbg[3 + 2 * si] = H.hi; dbg[6 + si] = e; }
+    if (H.lo <= 0.0f && 0.0f <= H.hi) vote = 1;
+  }
+  return vote;
+}
+
+/* ------------------------------------------------------------------------
  * one accumulator level: votes of all active valid hits for every box
  * ---------------------------------------------------------------------- */
 static int64_t prod5(const int32_t m[5]) {
@@ -348,7 +520,7 @@ static int64_t prod5(const int32_t m[5]) {
 
 static void vote_prepped(const or_prep *pr, const uint8_t *use, int32_t n_hits,
                          const or_box *parents, int32_t n_parents, const int32_t split[5],
-                         uint16_t *votes, int32_t n_threads) {
+                         int32_t prec, double slack, uint16_t *votes, int32_t n_threads) {
   int64_t nc = prod5(split), nb = (int64_t)n_parents * nc;
 #ifdef _OPENMP
   int nt = n_threads > 0 ? n_threads : omp_get_max_threads();
@@ -359,7 +531,7 @@ static void vote_prepped(const or_prep *pr, const uint8_t *use, int32_t n_hits,
     or_box_child(&parents[b / nc], split, b % nc, &box);
     int32_t v = 0;
     for (int32_t i = 0; i < n_hits; i++)
-      if (use[i]) v += or_pair_vote(&pr[i], &box, NULL);
+      if (use[i]) v += prec == OR_FP32 ? or_pair_vote32(&pr[i], &box, slack, NULL) : or_pair_vote(&pr[i], &box, NULL);
     votes[b] = (uint16_t)v;
   }
   (void)n_threads;
@@ -368,11 +540,17 @@ static void vote_prepped(const or_prep *pr, const uint8_t *use, int32_t n_hits,
 void or_vote_level(const or_hit *hits, int32_t n_hits, const uint8_t *active,
                    const or_box *parents, int32_t n_parents, const int32_t split[5],
                    uint16_t *votes, int32_t n_threads) {
+  or_vote_level_prec(hits, n_hits, active, parents, n_parents, split, OR_FP64, 0.0, votes, n_threads);
+}
+
+void or_vote_level_prec(const or_hit *hits, int32_t n_hits, const uint8_t *active,
+                        const or_box *parents, int32_t n_parents, const int32_t split[5],
+                        int32_t prec, double slack, uint16_t *votes, int32_t n_threads) {
   or_prep *pr = (or_prep *)calloc((size_t)(n_hits > 0 ? n_hits : 1), sizeof *pr);
   uint8_t *use = (uint8_t *)calloc((size_t)(n_hits > 0 ? n_hits : 1), 1);
   for (int32_t i = 0; i < n_hits; i++)
     use[i] = (uint8_t)(or_prep_hit(&hits[i], &pr[i]) && (!active || active[i]));
-  vote_prepped(pr, use, n_hits, parents, n_parents, split, votes, n_threads);
+  vote_prepped(pr, use, n_hits, parents, n_parents, split, prec, slack, votes, n_threads);
   free(pr);
   free(use);
 }
@@ -493,7 +671,7 @@ int32_t or_find_helices(const or_hit *hits, int32_t n_hits, const or_sched *sc,
     uint16_t vmax = 0;
     int32_t stop = 0;
     for (int32_t lev = 0; lev <= sc->n_refine; lev++) {
-      vote_prepped(pr, act, n_hits, par, n_par, split, votes, n_threads);
+      vote_prepped(pr, act, n_hits, par, n_par, split, sc->prec[lev], sc->fp32_slack, votes, n_threads);
       int64_t nb = (int64_t)n_par * prod5(split);
       int32_t k = or_topk(votes, nb, sc->top_k, tidx, tv);
       vmax = k > 0 ? tv[0] : 0;

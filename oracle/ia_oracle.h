@@ -15,6 +15,8 @@
  *     at the middle of the voxel (Sec. 3.1, last paragraph);
  *   - the iterative max-cell refinement, the estimate from the selected
  *     voxels and the hit finding (Sec. 3.3).
+ * and, for levels of a mixed-precision schedule marked OR_FP32, the FP32
+ * vote or_pair_vote32 (a definition of this implementation, not the paper's).
  * Units: m, rad, 1/m.  Box dimension order: d0, phi0, kappa, z0, tanl.
  */
 #ifndef IA_ORACLE_H
@@ -39,11 +41,16 @@ typedef struct {
   double d, band;       /* drift radius and tolerance half-width */
 } or_prep;
 
+#define OR_MAX_LEVELS 8
+enum { OR_FP64 = 0, OR_FP32 = 1 };
+
 typedef struct {
   or_box range; int32_t bins[5];          /* level-0 regular grid */
   int32_t n_refine, top_k, split[5];      /* refinement schedule */
   int32_t v_min, n_helix_max;             /* multi-helix stop rules */
   double hitfind_scale;                   /* half-width of the hit-finding box in errors */
+  int32_t prec[OR_MAX_LEVELS];            /* OR_FP64 or OR_FP32 per level */
+  double fp32_slack;                      /* band widening at FP32 levels (m) */
 } or_sched;
 
 typedef struct {
@@ -51,7 +58,6 @@ typedef struct {
   int32_t votes, n_assigned, n_argmax, pad;
 } or_helix;
 
-#define OR_MAX_LEVELS 8
 #define OR_MAX_K 64
 #define OR_MAX_PASSES 16
 typedef struct {
@@ -89,11 +95,28 @@ int32_t or_stereo_e(const or_prep *h, const double c[5], int32_t s, double *e, d
  * e+, e-. */
 int32_t or_pair_vote(const or_prep *h, const or_box *b, double *dbg);
 
+/* FP32 levels (see the source for the definition): outward and nearest
+ * FP64 -> FP32 conversions, FP32 widening, sin/cos on |x| <= 1, d^Ax with
+ * its (z0, tanl) part in FP32 (returns 0 outside the FP32 domain), and the
+ * vote of one (box, hit) with the band widened by slack. */
+float or_rd32(double x);
+float or_ru32(double x);
+float or_wdn32(float x);
+float or_wup32(float x);
+float or_sinf1(float x);
+float or_cosf1(float x);
+int32_t or_stereo_e32(const or_prep *h, const double c[5], int32_t s, float *e, float *dbg);
+int32_t or_pair_vote32(const or_prep *h, const or_box *b, double slack, float *dbg);
+
 /* votes[parent * prod(split) + child] for every child box of every parent.
  * active (nullable) masks hits. */
 void or_vote_level(const or_hit *hits, int32_t n_hits, const uint8_t *active,
                    const or_box *parents, int32_t n_parents, const int32_t split[5],
                    uint16_t *votes, int32_t n_threads);
+/* the same at precision prec (OR_FP64 or OR_FP32, band widening slack) */
+void or_vote_level_prec(const or_hit *hits, int32_t n_hits, const uint8_t *active,
+                        const or_box *parents, int32_t n_parents, const int32_t split[5],
+                        int32_t prec, double slack, uint16_t *votes, int32_t n_threads);
 
 /* the first k boxes by (votes desc, index asc); returns k actually taken */
 int32_t or_topk(const uint16_t *votes, int64_t n_boxes, int32_t k,

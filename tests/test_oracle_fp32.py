@@ -1,0 +1,114 @@
+"""FP32 levels of a mixed-precision schedule: the oracle's FP32 predicate
+against facts fixed outside it.
+
+The FP32 level is a definition of this implementation (the paper computes in
+FP64): the stereo term's (z0, tanl) part in FP32 and an FP32 interval test
+with the band widened by a slack.  Its pins:
+  - the FP64 -> FP32 roundings and the FP32 widening against numpy float32
+    (nextafter), and the FP32 sin / cos against numpy's float64 ones;
+  - |e32 - e64| far below the slack on sampled points, large radii included
+    (the claim the slack rests on);
+  - every FP64 vote is an FP32 vote (superset), boxes with a different count
+    are rare, and the argmax of a level does not move;
+  - a mixed schedule finds the all-FP64 helix.
+"""
+import numpy as np
+import pytest
+
+from paper_2401_04576_amd import toymc
+from tests import _helpers as H
+
+SLACK = 1e-6
+
+
+def test_fp32_roundings(orc):
+    rng = np.random.default_rng(5)
+    xs = np.concatenate([rng.normal(0, 1, 2000), rng.normal(0, 1e-30, 200), 10.0 ** rng.uniform(-44, 38, 500),
+                         [0.0, 1.0, -1.0, 0.1, -0.1, 1e-45, 3e38]])
+    for x in xs:
+        lo, hi = orc.rd32(x), orc.ru32(x)
+        assert float(lo) <= x <= float(hi)
+        if float(lo) == x:
+            assert lo == hi
+        else:
+            assert np.nextafter(lo, np.float32(np.inf)) == hi
+    for x in np.float32(rng.normal(0, 1, 2000)).tolist() + [0.0, 1e-45, -1e-45, 1e-38]:
+        x = np.float32(x)
+        assert orc.wdn32(x) <= np.nextafter(x, np.float32(-np.inf))
+        assert orc.wup32(x) >= np.nextafter(x, np.float32(np.inf))
+
+
+def test_fp32_sin_cos_on_unit_interval(orc):
+    xs = np.float32(np.linspace(-1, 1, 4001))
+    for x in xs:
+        s, c = orc.sinf1(x), orc.cosf1(x)
+        ulp_s = np.spacing(np.float32(abs(np.sin(float(x))) or 1e-38))
+        assert abs(float(s) - np.sin(float(x))) <= 2 * ulp_s
+        assert abs(float(c) - np.cos(float(x))) <= 2 * np.spacing(np.float32(np.cos(float(x))))
+
+
+def test_e32_error_far_below_slack(orc):
+    """|e32 - e64| at random centres, a quarter of them with |kappa| in
+    [1/2048, 0.1] (radius up to the FP32 domain's 2048 m)."""
+    rng = np.random.default_rng(9)
+    worst, n = 0.0, 0
+    for ev_i in range(6):
+        ev = toymc.config_event(2, ev_i)
+        prep = orc.prep_hits(ev.hits)
+        st = prep[(prep["valid"] == 1) & (prep["axial"] == 0)][:8]
+        for trial in range(120):
+            c = H.LO + (H.HI - H.LO) * rng.random(5)
+            if trial % 4 == 0:
+                c[2] = rng.choice([-1.0, 1.0]) * 10 ** rng.uniform(np.log10(1 / 2048.0), -1)
+            for h in st:
+                for s in (1, -1):
+                    ok64, e64 = orc.stereo_e(h, c, s)
+                    ok32, e32 = orc.stereo_e32(h, c, s)
+                    if ok64 and ok32:
+                        worst = max(worst, abs(float(e32) - e64))
+                        n += 1
+    assert n > 5000
+    assert worst < SLACK / 10, worst
+
+
+def test_e32_domain(orc):
+    """Outside the FP32 domain (radius above 2048 m) the FP32 term is not
+    evaluated and the pair votes."""
+    ev = toymc.config_event(2, 0)
+    prep = orc.prep_hits(ev.hits)
+    h = prep[(prep["valid"] == 1) & (prep["axial"] == 0)][0]
+    c = np.array([0.0, 1.0, 1.0 / 4096, 0.0, 0.2])
+    ok, _ = orc.stereo_e32(h, c, 1)
+    assert not ok
+    box = orc.make_box(c - 1e-9, c + 1e-9)
+    assert orc.pair_vote32(h, box, SLACK) == 1
+    c[2] = 0.3
+    assert orc.stereo_e32(h, c, 1)[0]
+
+
+@pytest.mark.parametrize("cfg,ev_i", [(1, 0), (2, 3), (5, 2)])
+def test_fp32_votes_contain_fp64_votes(orc, cfg, ev_i):
+    ev = toymc.config_event(cfg, ev_i)
+    root = orc.make_box(H.LO, H.HI)
+    v64 = orc.vote_level(ev.hits, root, [10] * 5)
+    v32 = orc.vote_level(ev.hits, root, [10] * 5, prec=orc.FP32, slack=SLACK)
+    d = v32.astype(np.int64) - v64
+    assert d.min() >= 0
+    assert (d != 0).mean() < 1e-3
+    assert v32.max() == v64.max()
+    assert np.argmax(v32) == np.argmax(v64)
+
+
+def test_mixed_schedule_recovers_fp64_helix(orc):
+    """FP32 at levels 0-2 and FP64 at 3-4 find the same helix as all-FP64
+    on noiseless single-helix events, within the final box size."""
+    kw = dict(bins=[8] * 5, n_refine=4, top_k=16, split=[2] * 5, v_min=10, n_helix_max=1)
+    s64 = orc.make_sched(H.LO, H.HI, **kw)
+    s32 = orc.make_sched(H.LO, H.HI, prec=[orc.FP32] * 3 + [orc.FP64] * 2, fp32_slack=SLACK, **kw)
+    for ev_i in range(3):
+        ev = toymc.config_event(3, ev_i)
+        h64, a64 = orc.find_helices(ev.hits, s64, max_out=1)
+        h32, a32 = orc.find_helices(ev.hits, s32, max_out=1)
+        assert len(h64) == len(h32) == 1
+        assert np.all(np.abs(h32[0]["p"] - h64[0]["p"]) <= 2 * h64[0]["err"] + 1e-12)
+        assert abs(int(h32[0]["votes"]) - int(h64[0]["votes"])) <= 1
