@@ -11,8 +11,20 @@ Workload (one step = one event through the whole search, FP64):
 Each step uses a different seeded event; all hits are resident in HBM
 before the timed region.
 
+With --workload batch, one step is instead a batch of 4096 events (1-5
+helices, 20-200 hits, 0-30 % noise, the same schedule with up to 5 greedy
+helix passes) searched by one ia_find_helices call, whose kernels each cover
+every event of a batch.
+
+With --workload serve, events of the serving mix (1-10 helices, lognormal
+hit counts with median 120 clipped to [20, 1000], 0-40 % noise) arrive as a
+Poisson stream and are served by the continuous-batching loop; the line
+gives p50/p99 arrival-to-result latency and events/s, beside the plain
+one-event-per-call FP64 path timed on a sample of the same events.
+
 Prints one JSON line: box-hit evaluations/s (value), events/s, p50/p99 event
-latency, the vote kernel's roofline figures and the CPU oracle baseline.
+latency (per step), the vote kernel's roofline figures and the CPU oracle
+baseline.
 """
 from __future__ import annotations
 
@@ -30,16 +42,54 @@ sys.path.insert(0, ROOT)
 METRIC = "box-hit interval evals/s + events/s at 1 GPU; p50/p99 event latency"
 
 # Algorithmic FP64 work of the vote kernel (flops; an FMA counts 2, a division
-# or square root 1), counted from the operation sequence of the predicate:
-#  - per (box, stereo hit), both drift signs: the stereo virtual drift at the
-#    box centre (second-order Phi, sin/cos of its correction, drift-line norm,
-#    d^Ax) and the interval test of 2G - 2E - kappa E^2;
-#  - per (triple, hit) staged once for all boxes sharing (d0, phi0, kappa):
-#    the centre frame, the interval residual G (sin enclosure) and the
-#    transverse part of the stereo term (axial hits are decided here).
+# or square root 1), counted from the operation sequence of the predicate and
+# applied to the work counters the library reports:
+#  - per stereo (box, hit) evaluation, both drift signs: the stereo virtual
+#    drift at the box centre (second-order Phi, sin/cos of its correction,
+#    drift-line norm, d^Ax) and the interval test of 2G - 2E - kappa E^2;
+#  - per staged (triple, stereo hit) record, shared by the boxes of the
+#    triple: the centre frame, the interval residual G (sin enclosure) and
+#    the transverse part of the stereo term.
 FLOP_BOX_STEREO = 335
 FLOP_TRIPLE_HIT = 310
+# the same per-box evaluation at FP32 levels (smaller sin/cos polynomials, no
+# range reduction), FP32 flops; the staged (triple, hit) work stays FP64
+FLOP_BOX_STEREO32 = 278
 PEAK_FP64_TFLOPS = 78.6   # MI355X vector FP64: 256 CU x 128 FLOP/clk x 2.4 GHz
+PEAK_FP32_TFLOPS = 157.3  # MI355X vector FP32 (non-packed)
+
+
+def sched_prec(name, n_refine):
+    """Per-level precision: all FP64, or FP32 at levels 0-2 and FP64 after."""
+    import paper_2401_04576_amd as ia
+    if name == "fp64":
+        return [ia.FP64] * (n_refine + 1)
+    return [ia.FP32 if lev <= 2 else ia.FP64 for lev in range(n_refine + 1)]
+
+
+def roofline(prof, work, wall):
+    """Roofline object of the dominant vote kernel (the precision class with
+    the larger summed launch time), with both classes under by_precision."""
+    n64, ms64, n32, ms32 = prof
+    e64, s64, e32, s32 = work
+    parts = {}
+    if n64:
+        a = (e64 * FLOP_BOX_STEREO + s64 * FLOP_TRIPLE_HIT) / (ms64 * 1e-3) / 1e12
+        parts["fp64"] = {"achieved": a, "peak": PEAK_FP64_TFLOPS, "frac": a / PEAK_FP64_TFLOPS,
+                         "avg_launch_ms": ms64 / n64, "launches": n64, "total_ms": ms64,
+                         "stereo_box_evals": e64, "staged_pairs": s64}
+    if n32:
+        # FP32 flops of the per-box term only; the FP64 staging is left out
+        a = e32 * FLOP_BOX_STEREO32 / (ms32 * 1e-3) / 1e12
+        parts["fp32"] = {"achieved": a, "peak": PEAK_FP32_TFLOPS, "frac": a / PEAK_FP32_TFLOPS,
+                         "avg_launch_ms": ms32 / n32, "launches": n32, "total_ms": ms32,
+                         "stereo_box_evals": e32, "staged_pairs": s32,
+                         "staged_fp64_tflops": s32 * FLOP_TRIPLE_HIT / (ms32 * 1e-3) / 1e12}
+    dom = max(parts, key=lambda k: parts[k]["total_ms"])
+    d = parts[dom]
+    return {"bound": "alu", "achieved": d["achieved"], "peak": d["peak"], "unit": "TFLOP/s", "frac": d["frac"],
+            "traffic": None, "kernel": f"k_vote ({dom} levels)", "avg_launch_ms": d["avg_launch_ms"],
+            "launches": d["launches"], "vote_share_of_wall": (ms64 + ms32) * 1e-3 / wall, "by_precision": parts}
 
 
 def level_shapes(bins, top_k, split, n_refine):
@@ -55,16 +105,41 @@ def level_shapes(bins, top_k, split, n_refine):
     return out
 
 
-def vote_flops(n_boxes, n_triples, n_stereo, n_hits):
-    return float(n_boxes) * n_stereo * FLOP_BOX_STEREO + float(n_triples) * n_hits * FLOP_TRIPLE_HIT
-
-
 def hit_counts(hits):
     dz = hits["z1"] - hits["z0"]
     tx = (hits["x1"] - hits["x0"]) / dz
     ty = (hits["y1"] - hits["y0"]) / dz
     stereo = (tx * tx + ty * ty) > 0
     return int(hits.shape[0]), int(stereo.sum())
+
+
+def event_evals(n_valid, helices, n_out, shapes, n_helix_max):
+    """Box-hit evaluations of one event, from its recorded helices: every
+    recorded helix is a full pass over the hits still active; a pass that
+    stops at level 0 (maximum below v_min) adds level 0 only."""
+    full = sum(nb for nb, _ in shapes)
+    active, ev = n_valid, 0.0
+    for h in range(n_out):
+        ev += full * active
+        active -= int(helices[h]["n_assigned"])
+    if n_out < n_helix_max and (n_out == 0 or int(helices[n_out - 1]["n_assigned"]) > 0):
+        ev += shapes[0][0] * active
+    return ev
+
+
+def _gen(args):
+    cfg, i = args
+    from paper_2401_04576_amd import toymc
+    return toymc.config_event(cfg, i)
+
+
+def generate(cfg, indices):
+    indices = list(indices)
+    if len(indices) < 64:
+        return [_gen((cfg, i)) for i in indices]
+    import multiprocessing as mp
+    with mp.get_context("fork").Pool(min(16, os.cpu_count() or 1)) as pool:
+        return pool.map(_gen, [(cfg, i) for i in indices], chunksize=16)
 
 
 def cpu_baseline(events, sched_kw, lo, hi, budget_s=20.0):
@@ -75,11 +150,11 @@ def cpu_baseline(events, sched_kw, lo, hi, budget_s=20.0):
     evals = 0.0
     t0 = time.perf_counter()
     n_done = 0
+    nh = sched_kw["n_helix_max"]
     for ev in events:
-        hel, _ = oracle.find_helices(ev.hits, sched, max_out=1, n_threads=nt)
+        hel, _ = oracle.find_helices(ev.hits, sched, max_out=nh, n_threads=nt)
         n, _ = hit_counts(ev.hits)
-        levels = shapes if len(hel) else shapes[:1]
-        evals += sum(nb for nb, _ in levels) * n
+        evals += event_evals(n, hel, len(hel), shapes, nh)
         n_done += 1
         if time.perf_counter() - t0 > budget_s:
             break
@@ -97,6 +172,14 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--workload", choices=["event", "batch", "serve"], default="event")
+    ap.add_argument("--batch-events", type=int, default=4096)
+    ap.add_argument("--scratch-gb", type=float, default=8.0)
+    ap.add_argument("--serve-events", type=int, default=4096)
+    ap.add_argument("--rate", type=float, default=20000.0, help="serving: Poisson arrival rate, events/s")
+    ap.add_argument("--slots", type=int, default=4, help="serving: concurrent batches")
+    ap.add_argument("--prec", choices=["fp64", "mixed"], default="fp64",
+                    help="mixed: FP32 vote arithmetic at levels 0-2, FP64 at the finer levels and the fit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the search shards by event "
@@ -109,17 +192,22 @@ def main():
     from paper_2401_04576_amd import toymc
 
     assert torch.cuda.is_available(), "bench.py needs a HIP device"
+    if args.workload == "batch":
+        return run_batch(args)
+    if args.workload == "serve":
+        return run_serve(args)
     dev = torch.device("cuda:0")
     lo, hi = np.array(toymc.GRID_RANGE_LO), np.array(toymc.GRID_RANGE_HI)
     sched_kw = dict(bins=[16] * 5, n_refine=4, top_k=32, split=[4] * 5, v_min=10, n_helix_max=1)
+    prec = sched_prec(args.prec, sched_kw["n_refine"])
     n_ev = args.warmup + args.steps
     t_gen = time.perf_counter()
-    events = [toymc.config_event(2, i) for i in range(n_ev)]
+    events = generate(2, range(n_ev))
     t_gen = time.perf_counter() - t_gen
     hits_np = np.concatenate([e.hits for e in events])
     off = np.concatenate([[0], np.cumsum([e.n_hits for e in events])]).astype(np.int64)
     hits = torch.from_numpy(hits_np.view(np.float64).reshape(-1, 8).copy()).to(dev)
-    sched = ia.Schedule.make(lo, hi, **sched_kw)
+    sched = ia.Schedule.make(lo, hi, prec=prec, **sched_kw)
     max_hits = max(e.n_hits for e in events)
     ctx = ia.Context(0, scratch_bytes=ia.Context.scratch_needed(sched, max_hits) + (1 << 20))
     out = torch.zeros(n_ev * ia.HELIX_DTYPE.itemsize, dtype=torch.uint8, device=dev)
@@ -137,6 +225,7 @@ def main():
         step(i)
     torch.cuda.synchronize()
     ctx.profile_read()
+    ctx.clear_status()
     starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
     ends = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
     ctx.set_profiling(True)
@@ -149,47 +238,214 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ctx.set_profiling(False)
-    n_launch, vote_ms = ctx.profile_read()
+    prof = ctx.profile_read()
+    work = ctx.work()
+    n_launch = prof[0] + prof[2]
     lat = np.array([s.elapsed_time(e) for s, e in zip(starts, ends)])
     wall = t1 - t0
 
     # work actually done: a pass stops after level 0 when its max vote is below v_min
     nout = n_out.cpu().numpy()
     shapes = level_shapes(sched_kw["bins"], sched_kw["top_k"], sched_kw["split"], sched_kw["n_refine"])
-    evals, flops, launches = 0.0, 0.0, 0
+    evals, launches = 0.0, 0
     for k in range(args.steps):
         i = args.warmup + k
         n, n_st = hit_counts(events[i].hits)
         levels = shapes if nout[i] > 0 else shapes[:1]
         for nb, ntr in levels:
             evals += float(nb) * n
-            flops += vote_flops(nb, ntr, n_st, n)
             launches += 1
     assert launches == n_launch, (launches, n_launch)
     value = evals / wall
-    avg_launch_ms = vote_ms / n_launch
-    achieved = flops / n_launch / (avg_launch_ms * 1e-3) / 1e12
     res = {
         "metric": METRIC, "value": value, "unit": "box-hit evals/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": wall / args.steps * 1e3, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": "single event, hierarchical refinement, FP64: 1 helix, 150 um smearing, "
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64" if args.prec == "fp64" else "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": "single event, hierarchical refinement, "
+                               + ("FP64" if args.prec == "fp64" else "FP32 at levels 0-2, FP64 at 3-4 and the fit")
+                               + ": 1 helix, 150 um smearing, "
                                "20% noise hits, band 3 sigma; 16^5 level-0 grid then 4 levels of top-32 "
                                "boxes split 4^5; estimate and hit finding",
                    "events": args.steps, "mean_hits": float(np.mean([e.n_hits for e in events[args.warmup:]])),
                    "boxes_per_event": int(sum(nb for nb, _ in shapes))},
         "events_per_s": args.steps / wall,
         "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
-                     "kernel": "k_vote", "avg_launch_ms": avg_launch_ms, "launches": n_launch,
-                     "vote_share_of_wall": vote_ms * 1e-3 / wall},
+        "roofline": roofline(prof, work, wall),
     }
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(events[args.warmup:], sched_kw, lo, hi, args.cpu_budget)
     ctx.close()
-    print(f"[bench] generated {n_ev} events in {t_gen:.1f} s; vote kernel {vote_ms:.2f} ms of "
+    print(f"[bench] generated {n_ev} events in {t_gen:.1f} s; vote kernel {prof[1] + prof[3]:.2f} ms of "
           f"{wall * 1e3:.2f} ms", file=sys.stderr)
+    print(json.dumps(res), flush=True)
+
+
+def run_batch(args):
+    """Workload 4: batches of events through one ia_find_helices call each."""
+    import torch
+
+    import paper_2401_04576_amd as ia
+    from paper_2401_04576_amd import toymc
+
+    dev = torch.device("cuda:0")
+    lo, hi = np.array(toymc.GRID_RANGE_LO), np.array(toymc.GRID_RANGE_HI)
+    nh = 5
+    sched_kw = dict(bins=[16] * 5, n_refine=4, top_k=32, split=[4] * 5, v_min=10, n_helix_max=nh)
+    prec = sched_prec(args.prec, sched_kw["n_refine"])
+    E = args.batch_events
+    n_batches = args.warmup + args.steps
+    t_gen = time.perf_counter()
+    events = generate(4, range(E * n_batches))
+    t_gen = time.perf_counter() - t_gen
+    sched = ia.Schedule.make(lo, hi, prec=prec, **sched_kw)
+    ctx = ia.Context(0, scratch_bytes=int(args.scratch_gb * (1 << 30)))
+    batches = []
+    for b in range(n_batches):
+        evs = events[b * E:(b + 1) * E]
+        hits_np = np.concatenate([e.hits for e in evs])
+        off = np.concatenate([[0], np.cumsum([e.n_hits for e in evs])]).astype(np.int64)
+        hits = torch.from_numpy(hits_np.view(np.float64).reshape(-1, 8).copy()).to(dev)
+        out = torch.zeros(E * nh * ia.HELIX_DTYPE.itemsize, dtype=torch.uint8, device=dev)
+        n_out = torch.zeros(E, dtype=torch.int32, device=dev)
+        assigned = torch.full((hits.shape[0],), -1, dtype=torch.int32, device=dev)
+        batches.append((evs, hits, off, out, n_out, assigned))
+    stream = torch.cuda.current_stream()
+
+    def step(b):
+        evs, hits, off, out, n_out, assigned = batches[b]
+        ia.find_helices(ctx, hits, off, sched, max_per_event=nh, stream=stream, out=out, n_out=n_out,
+                        assigned=assigned)
+
+    for b in range(args.warmup):
+        step(b)
+    torch.cuda.synchronize()
+    ctx.profile_read()
+    ctx.clear_status()
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    ctx.set_profiling(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        starts[k].record(stream)
+        step(args.warmup + k)
+        ends[k].record(stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ctx.set_profiling(False)
+    prof = ctx.profile_read()
+    work = ctx.work()
+    lat = np.array([s.elapsed_time(e) for s, e in zip(starts, ends)])
+    wall = t1 - t0
+    shapes = level_shapes(sched_kw["bins"], sched_kw["top_k"], sched_kw["split"], sched_kw["n_refine"])
+    evals, found, truth = 0.0, 0, 0
+    for k in range(args.steps):
+        evs, hits, off, out, n_out, assigned = batches[args.warmup + k]
+        hel = ia.decode(out, ia.HELIX_DTYPE).reshape(E, nh)
+        nout = n_out.cpu().numpy()
+        for e, ev in enumerate(evs):
+            n, _ = hit_counts(ev.hits)
+            evals += event_evals(n, hel[e], int(nout[e]), shapes, nh)
+            found += int(nout[e])
+            truth += ev.truth.shape[0]
+    res = {
+        "metric": METRIC, "value": evals / wall, "unit": "box-hit evals/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": wall / args.steps * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64" if args.prec == "fp64" else "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": f"batched: {E} events per ia_find_helices call, 1-5 helices and 20-200 hits "
+                               "per event, 0-30% noise, 150 um smearing, band 3 sigma; 16^5 grid then 4 "
+                               "levels of top-32 split 4^5; up to 5 greedy helix passes; "
+                               + ("FP64" if args.prec == "fp64" else "FP32 at levels 0-2, FP64 at 3-4 and the fit"),
+                   "events_per_step": E, "helices_found_per_event": found / (E * args.steps),
+                   "helices_generated_per_event": truth / (E * args.steps)},
+        "events_per_s": E * args.steps / wall,
+        "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+        "roofline": roofline(prof, work, wall),
+    }
+    if not args.no_cpu_baseline:
+        res["cpu_baseline"] = cpu_baseline(batches[args.warmup][0], sched_kw, lo, hi, args.cpu_budget)
+    ctx.close()
+    print(f"[bench] generated {len(events)} events in {t_gen:.1f} s", file=sys.stderr)
+    print(json.dumps(res), flush=True)
+
+
+def run_serve(args):
+    """Workload 5: Poisson arrivals served by the continuous-batching loop."""
+    import torch
+
+    import paper_2401_04576_amd as ia
+    from paper_2401_04576_amd import serve, toymc
+
+    dev = torch.device("cuda:0")
+    lo, hi = np.array(toymc.GRID_RANGE_LO), np.array(toymc.GRID_RANGE_HI)
+    nh = 10
+    sched_kw = dict(bins=[16] * 5, n_refine=4, top_k=32, split=[4] * 5, v_min=10, n_helix_max=nh)
+    sched = ia.Schedule.make(lo, hi, prec=sched_prec(args.prec, sched_kw["n_refine"]), **sched_kw)
+    sched64 = ia.Schedule.make(lo, hi, **sched_kw)
+    n_warm = min(256, args.serve_events)
+    t_gen = time.perf_counter()
+    events = generate(5, range(args.serve_events + n_warm))
+    t_gen = time.perf_counter() - t_gen
+    warm, events = events[:n_warm], events[n_warm:]
+    loop = serve.ServeLoop(sched, max_per_event=nh, n_slots=args.slots,
+                           scratch_budget=int(args.scratch_gb * (1 << 30)), max_batch=args.batch_events)
+    # warm-up: every slot launches at least once
+    loop.run([serve.Request(i, e.hits, 0.0) for i, e in enumerate(warm)])
+    loop.finished = []
+    torch.cuda.synchronize()
+    arrivals = serve.poisson_arrivals(len(events), args.rate, seed=11)
+    reqs = [serve.Request(i, e.hits, float(t)) for i, (e, t) in enumerate(zip(events, arrivals))]
+    t0 = time.perf_counter()
+    done = loop.run(reqs)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    st = serve.latency_stats(done)
+    shapes = level_shapes(sched_kw["bins"], sched_kw["top_k"], sched_kw["split"], sched_kw["n_refine"])
+    evals, found, truth = 0.0, 0, 0
+    for r in done:
+        n, _ = hit_counts(r.hits)
+        evals += event_evals(n, r.helices, len(r.helices), shapes, nh)
+        found += len(r.helices)
+        truth += events[r.rid].truth.shape[0]
+    slots_used = loop.events_per_slot
+    loop.close()
+
+    # the plain FP64 one-event-per-call path on a sample of the same events
+    n_plain = min(len(events), 256)
+    ctx = ia.Context(0, scratch_bytes=ia.Context.scratch_needed(sched, 1000) + (1 << 20))
+    plain_hits = [torch.from_numpy(e.hits.view(np.float64).reshape(-1, 8).copy()).to(dev) for e in events[:n_plain]]
+    torch.cuda.synchronize()
+    for h in plain_hits[:8]:
+        ia.find_helices(ctx, h, [0, h.shape[0]], sched64, max_per_event=nh)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    lat_plain = []
+    for h in plain_hits:
+        ta = time.perf_counter()
+        ia.find_helices(ctx, h, [0, h.shape[0]], sched64, max_per_event=nh)
+        torch.cuda.synchronize()
+        lat_plain.append(time.perf_counter() - ta)
+    plain_wall = time.perf_counter() - t1
+    ctx.close()
+    res = {
+        "metric": METRIC, "value": evals / wall, "unit": "box-hit evals/s", "n_gpus": 1, "steps": 1,
+        "warmup": 1, "ms_per_step": wall * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64" if args.prec == "fp64" else "f32+f64", "data": "synthetic",
+        "config": {"workload": f"serving: {len(events)} events, Poisson arrivals at {args.rate:g}/s, 1-10 "
+                               "helices, lognormal hits (median 120, [20, 1000]), 0-40% noise; 16^5 grid then 4 "
+                               "levels of top-32 split 4^5; up to 10 greedy helix passes; FP64",
+                   "slots": args.slots, "events_per_slot": slots_used,
+                   "helices_found_per_event": found / len(done),
+                   "helices_generated_per_event": truth / len(done)},
+        "events_per_s": len(done) / wall,
+        "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"], "mean_ms": st["mean_ms"],
+        "plain_fp64_per_event": {"events_per_s": n_plain / plain_wall,
+                                 "p50_ms": float(np.percentile(lat_plain, 50) * 1e3),
+                                 "p99_ms": float(np.percentile(lat_plain, 99) * 1e3), "events": n_plain},
+    }
+    print(f"[bench] generated {len(events) + n_warm} events in {t_gen:.1f} s", file=sys.stderr)
     print(json.dumps(res), flush=True)
 
 

@@ -97,7 +97,9 @@ typedef struct {
   int32_t n_helix_max;    /* helices searched per event (greedy, hits removed) */
   double hitfind_scale;   /* hit-finding box = estimate +- scale x error (5 in Sec. 3.3) */
   int32_t prec[IA_MAX_LEVELS];  /* arithmetic per level (IA_FP64 or IA_FP32) */
-  double fp32_slack;      /* extra tolerance added to the band at FP32 levels */
+  double fp32_slack;      /* band widening at FP32 levels, m, in [0, 1e-3]; it must
+                           * bound the FP32 error of d^Ax (1e-6 is 100x the largest
+                           * error seen on the chamber geometry) */
 } ia_schedule;
 
 typedef struct ia_ctx ia_ctx;
@@ -117,13 +119,27 @@ const char *ia_last_error(const ia_ctx *ctx);
 ia_status ia_ctx_status(ia_ctx *ctx, uint32_t *flags, int64_t *n_bad_hits);
 ia_status ia_ctx_clear_status(ia_ctx *ctx);
 
+/* Work counters of the vote kernel since the last ia_ctx_clear_status():
+ * stereo (box, hit) evaluations performed and (triple, stereo hit) records
+ * staged, at FP64 levels and at FP32 levels (pairs the pre-pass proved
+ * unable to vote are in none of them).  Synchronises the device.  Any
+ * pointer may be NULL. */
+ia_status ia_ctx_work(ia_ctx *ctx, int64_t *stereo_box_evals, int64_t *staged_pairs,
+                      int64_t *stereo_box_evals_fp32, int64_t *staged_pairs_fp32);
+
 /* Kernel timing: while enabled, every launch of the vote kernel made through
  * this context is bracketed by HIP events on its stream.
  * ia_ctx_profile_read() synchronises the device, returns the number of
- * bracketed launches and their summed duration in milliseconds, and clears
- * the record.  Creating the events is the only host-side cost. */
+ * bracketed launches and their summed duration in milliseconds, separately
+ * for FP64 and FP32 levels, and clears the record.  Creating the events is
+ * the only host-side cost.  Any output pointer may be NULL. */
 ia_status ia_ctx_set_profiling(ia_ctx *ctx, int32_t enable);
-ia_status ia_ctx_profile_read(ia_ctx *ctx, int64_t *n_launches, double *total_ms);
+ia_status ia_ctx_profile_read(ia_ctx *ctx, int64_t *n_launches, double *total_ms,
+                              int64_t *n_launches_fp32, double *total_ms_fp32);
+
+/* Band widening used by ia_vote_level at IA_FP32 (default 1e-6 m; ia_find_helices
+ * takes it from the schedule).  IA_ERR_INVALID outside [0, 1e-3]. */
+ia_status ia_ctx_set_fp32_slack(ia_ctx *ctx, double slack);
 
 /* Boxes per workgroup of the vote kernel: 256, 128 or 64 (the workgroup's
  * 256 lanes then split each hit chunk over 1, 2 or 4 waves), or 0 to choose
@@ -137,8 +153,15 @@ ia_status ia_ctx_set_vote_tile(ia_ctx *ctx, int32_t boxes_per_workgroup);
  * not depend on it. */
 ia_status ia_ctx_set_prefilter(ia_ctx *ctx, int32_t mode);
 
-/* Scratch bytes needed by ia_find_helices for events of at most max_hits
- * hits under `sched`. */
+/* ia_find_helices launches its events in batches: every kernel of a level
+ * covers all events of a batch (one event per grid row).  A batch holds as
+ * many events as the scratch arena fits, at most max_events (default 65535).
+ * Results do not depend on it. */
+ia_status ia_ctx_set_batch(ia_ctx *ctx, int32_t max_events);
+
+/* Scratch bytes needed by ia_find_helices for a batch of one event of at most
+ * max_hits hits under `sched` (each further event of the batch needs about
+ * the same again). */
 size_t ia_ctx_scratch_needed(const ia_schedule *sched, int32_t max_hits);
 
 /* One accumulator level (Eq. ApoVote over every box; Sec. 3.1).
@@ -146,7 +169,9 @@ size_t ia_ctx_scratch_needed(const ia_schedule *sched, int32_t max_hits);
  *   d_active  NULL or n_hits bytes; 0 excludes a hit
  *   d_parents n_parents boxes (lo <= hi in every dimension)
  *   split     host int32[5], each >= 1
- *   prec      IA_FP64 (IA_FP32 returns IA_ERR_UNSUPPORTED in this build)
+ *   prec      IA_FP64, or IA_FP32: the stereo term of each (box, hit) pair in
+ *             FP32 and an FP32 interval test with the band widened by the
+ *             context's slack; its votes contain the IA_FP64 votes
  *   d_votes   n_parents * prod(split) uint16, written: number of active,
  *             well-formed hits voting for each box
  * Scratch: 96 bytes per hit. */

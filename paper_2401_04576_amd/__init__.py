@@ -96,8 +96,14 @@ def load():
     L.ia_last_error.argtypes = [P]
     L.ia_ctx_status.restype = i32
     L.ia_ctx_status.argtypes = [P, C.POINTER(C.c_uint32), C.POINTER(i64)]
+    L.ia_ctx_work.restype = i32
+    L.ia_ctx_work.argtypes = [P, C.POINTER(i64), C.POINTER(i64), C.POINTER(i64), C.POINTER(i64)]
+    L.ia_ctx_set_fp32_slack.restype = i32
+    L.ia_ctx_set_fp32_slack.argtypes = [P, C.c_double]
     L.ia_ctx_clear_status.restype = i32
     L.ia_ctx_clear_status.argtypes = [P]
+    L.ia_ctx_set_batch.restype = i32
+    L.ia_ctx_set_batch.argtypes = [P, i32]
     L.ia_ctx_set_prefilter.restype = i32
     L.ia_ctx_set_prefilter.argtypes = [P, i32]
     L.ia_ctx_set_vote_tile.restype = i32
@@ -105,7 +111,8 @@ def load():
     L.ia_ctx_set_profiling.restype = i32
     L.ia_ctx_set_profiling.argtypes = [P, i32]
     L.ia_ctx_profile_read.restype = i32
-    L.ia_ctx_profile_read.argtypes = [P, C.POINTER(i64), C.POINTER(C.c_double)]
+    L.ia_ctx_profile_read.argtypes = [P, C.POINTER(i64), C.POINTER(C.c_double), C.POINTER(i64),
+                                      C.POINTER(C.c_double)]
     L.ia_ctx_scratch_needed.restype = sz
     L.ia_ctx_scratch_needed.argtypes = [C.POINTER(Schedule), i32]
     L.ia_vote_level.restype = i32
@@ -173,12 +180,27 @@ class Context:
         self._check(self._L.ia_ctx_status(self._h, C.byref(flags), C.byref(nbad)))
         return int(flags.value), int(nbad.value)
 
+    def work(self):
+        """(stereo box evaluations, staged pairs) at FP64 levels, then the same
+        two at FP32 levels, since the last clear_status()."""
+        a, b, f, g = C.c_int64(), C.c_int64(), C.c_int64(), C.c_int64()
+        self._check(self._L.ia_ctx_work(self._h, C.byref(a), C.byref(b), C.byref(f), C.byref(g)))
+        return int(a.value), int(b.value), int(f.value), int(g.value)
+
+    def set_fp32_slack(self, slack=1e-6):
+        """Band widening of vote_level at FP32 (m)."""
+        self._check(self._L.ia_ctx_set_fp32_slack(self._h, float(slack)))
+
     def clear_status(self):
         self._check(self._L.ia_ctx_clear_status(self._h))
 
     def set_vote_tile(self, boxes_per_workgroup=0):
         """Force the vote kernel's boxes per workgroup (256, 128, 64) or 0 for automatic."""
         self._check(self._L.ia_ctx_set_vote_tile(self._h, int(boxes_per_workgroup)))
+
+    def set_batch(self, max_events=65535):
+        """Maximum events per batched launch of find_helices."""
+        self._check(self._L.ia_ctx_set_batch(self._h, int(max_events)))
 
     def set_prefilter(self, mode=-1):
         """(triple, hit) pre-filter: -1 automatic, 0 off, 1 on."""
@@ -188,9 +210,10 @@ class Context:
         self._check(self._L.ia_ctx_set_profiling(self._h, 1 if enable else 0))
 
     def profile_read(self):
-        n, ms = C.c_int64(), C.c_double()
-        self._check(self._L.ia_ctx_profile_read(self._h, C.byref(n), C.byref(ms)))
-        return int(n.value), float(ms.value)
+        """(FP64 vote launches, their ms, FP32 vote launches, their ms) since the last read."""
+        n, ms, n32, ms32 = C.c_int64(), C.c_double(), C.c_int64(), C.c_double()
+        self._check(self._L.ia_ctx_profile_read(self._h, C.byref(n), C.byref(ms), C.byref(n32), C.byref(ms32)))
+        return int(n.value), float(ms.value), int(n32.value), float(ms32.value)
 
     def close(self):
         if getattr(self, "_h", None):

@@ -57,8 +57,32 @@ struct EventState {
   double p[5], err[5];          // last estimate
 };
 
+// Per-event views of a batch of events launched together: blockIdx.y is the
+// event.  Event e owns hits [off[e], off[e+1]) of the prepared-hit array
+// (off == nullptr: one event of n_single hits) and the e-th slice of every
+// per-event array, at the strides below.
+struct EvView {
+  const int32_t* off;
+  int32_t n_single;
+  int32_t k;                    // selection size (stride of the selection arrays)
+  int64_t par_stride;           // parent boxes per event (0: one shared list)
+  int64_t flag_stride;          // pre-pass flags per event
+  int32_t hist_stride;          // histogram bins per event
+  int32_t wg_stride;            // workgroup maxima per event
+  int32_t part_stride;          // estimate chunk sums per event (doubles)
+  int32_t max_out;              // helices per event
+  __device__ int32_t beg(int e) const { return off ? off[e] : 0; }
+  __device__ int32_t count(int e) const { return off ? off[e + 1] - off[e] : n_single; }
+};
+
 // status word bits (device-detected problems, read after a stream sync)
 enum : uint32_t { kStBadHit = 1u, kStVoteOverflow = 2u };
+
+// vote-kernel work counters: kWorkSlots slots of 16 u64 (one 128-byte line
+// each); counters 0..3 of a slot: stereo (box, hit) evaluations and staged
+// (triple, hit) pairs at FP64 levels, the same two at FP32 levels
+constexpr uint32_t kWorkSlots = 64;
+constexpr uint32_t kWorkSlotU64 = 16;
 
 // ---------------------------------------------------------------------------
 // edges of child k of [L, U] split m ways
@@ -239,7 +263,8 @@ IA_HD bool stereo_vote(const PairQ& q, double R, double sig, Iv K, double z0,
 // operation is inclusion-monotone, so if the H test fails for the widened
 // enclosure it fails for every box: the pair casts no vote anywhere in the
 // triple.  Returns false when no finite enclosure is available.
-IA_HD bool e_enclosure(const PairQ& q, double R, double sig, double tt, double t2, double dS, Iv Z, Iv L, Iv* out) {
+IA_HD bool e_enclosure_dom(const PairQ& q, double R, double sig, double tt, double t2, double dS, Iv Z, Iv L,
+                           Iv* out, Iv* eps_out, Iv* disc_out, Iv* a_out) {
   const Iv ZA = iadd(Z, imul(L, ipt(q.sArc)));
   const Iv ZAs = imul(ZA, ipt(q.sinA));
   const Iv ZA2 = isqr(ZA);
@@ -253,6 +278,7 @@ IA_HD bool e_enclosure(const PairQ& q, double R, double sig, double tt, double t
   const Iv P2c = imul(iadd(ZA2, imul(ipt(dS), inner)), ipt(q.s2));
   const Iv PHI2 = idivp(iadd(isub(P2a, P2b), P2c), q.twoRAx2);
   const Iv EPS = iadd(imul(PHI1, ipt(tt)), imul(PHI2, ipt(t2)));
+  *eps_out = EPS;
   if (!(fabs(EPS.lo) < 1e5 && fabs(EPS.hi) < 1e5)) return false;
   const Iv SE = sin_encl(EPS.lo, EPS.hi), CE = cos_encl(EPS.lo, EPS.hi);
   const Iv SINP = iadd(imul(ipt(q.sinA), CE), imul(ipt(q.cosA), SE));
@@ -268,6 +294,8 @@ IA_HD bool e_enclosure(const PairQ& q, double R, double sig, double tt, double t
   const Iv Q = iadd(iadd(imul(itwice(CTAU), ipt(tt)), isqr(imul(ZS, ipt(tt)))), isqr(imul(LD, ipt(tt))));
   const Iv A = iadd(ipt(R), DELTA);
   const Iv DISC = isub(isqr(A), Q);
+  *disc_out = DISC;
+  *a_out = A;
   if (!(DISC.hi >= 0.0)) return false;
   const Iv DEN = iadd(A, isqrt(DISC));
   if (!(DEN.lo > 0.0)) return false;
@@ -276,6 +304,11 @@ IA_HD bool e_enclosure(const PairQ& q, double R, double sig, double tt, double t
   const double m = 1e-9 * fmax(fabs(E.lo), fabs(E.hi)) + 1e-12;
   *out = {wdn(E.lo - m), wup(E.hi + m)};
   return __builtin_isfinite(out->lo) && __builtin_isfinite(out->hi);
+}
+
+IA_HD bool e_enclosure(const PairQ& q, double R, double sig, double tt, double t2, double dS, Iv Z, Iv L, Iv* out) {
+  Iv eps, disc, a;
+  return e_enclosure_dom(q, R, sig, tt, t2, dS, Z, L, out, &eps, &disc, &a);
 }
 
 // false only when no box of the triple can get this stereo hit's vote
@@ -289,6 +322,98 @@ IA_HD bool triple_may_vote(const PairQ& q, const Frame& f, const HitRec& h, Iv Z
     const Iv Eb = {wdn(E.lo - h.band), wup(E.hi + h.band)};
     const Iv Hb = isub(itwice(G), iadd(itwice(Eb), imul(f.K, isqr(Eb))));
     if (Hb.lo <= 0.0 && 0.0 <= Hb.hi) return true;
+  }
+  return false;
+}
+
+// ---------------------------------------------------------------------------
+// FP32 levels.  A stereo pair's (triple, hit) quantities are the FP64 ones
+// above, rounded to FP32 (G outward, points to nearest); the (z0, tanl) part
+// of d^Ax runs in FP32 in the operation order of stereo_vote, and the vote
+// test is the FP32 interval test with the band widened by a slack that
+// bounds |e32 - e64|.  The FP32 evaluation is used only where that bound
+// holds (R <= kR32Max, |eps| <= 1, positive discriminant, finite result);
+// elsewhere the pair votes.  FP32 votes thus contain the FP64 votes.
+constexpr double kR32Max = 2048.0;
+
+struct PairQ32 {
+  float Glo, Ghi, sArc, dphi, RAx, sinA, cosA, sAx, cAx, c2, s2, twoRAx2, RpRAx, tt, d, bs;
+};
+
+IA_HD PairQ32 pair_q32(const PairQ& q, const HitRec& h, float slack32) {
+  PairQ32 r;
+  r.Glo = rd32(q.Glo); r.Ghi = ru32(q.Ghi);
+  r.sArc = static_cast<float>(q.sArc); r.dphi = static_cast<float>(q.dphi);
+  r.RAx = static_cast<float>(q.RAx); r.sinA = static_cast<float>(q.sinA);
+  r.cosA = static_cast<float>(q.cosA); r.sAx = static_cast<float>(q.sAx);
+  r.cAx = static_cast<float>(q.cAx); r.c2 = static_cast<float>(q.c2); r.s2 = static_cast<float>(q.s2);
+  r.twoRAx2 = static_cast<float>(q.twoRAx2); r.RpRAx = static_cast<float>(q.RpRAx);
+  r.tt = static_cast<float>(h.tant);
+  r.d = static_cast<float>(h.d);
+  r.bs = wup32(ru32(h.band) + slack32);
+  return r;
+}
+
+IA_HD bool stereo_vote32(const PairQ32& q, float R, float sig, Iv32 K, float z0, float lam, float lamR,
+                         float lam2) {
+  const float tt = q.tt, t2 = tt * tt;
+  const float zA = z0 + lam * q.sArc;
+  const float zAs = zA * q.sinA;
+  const float zA2 = zA * zA;
+  const float lzA = lam * zA;
+  const Iv32 G = {q.Glo, q.Ghi};
+  bool vote = false;
+#pragma unroll
+  for (int si = 0; si < 2; ++si) {
+    const float dS = si == 0 ? q.d : -q.d;
+    const float Phi1 = -(zAs + (lam * dS) * q.cosA) / q.RAx;
+    const float Phi2n = lamR * zA - (lzA * (R - 2.0f * dS)) * q.c2 + (zA2 + dS * (q.RAx + lam2 * (q.RpRAx - dS))) * q.s2;
+    const float Phi2 = Phi2n / q.twoRAx2;
+    const float eps = Phi1 * tt + Phi2 * t2;
+    if (!(fabsf(eps) <= 1.0f)) { vote = true; continue; }
+    const float se = sin1_32(eps), ce = cos1_32(eps);
+    const float sinP = q.sinA * ce + q.cosA * se, cosP = q.cosA * ce - q.sinA * se;
+    const float u = sqrtf(((1.0f + ((2.0f * lam) * sinP) * tt) + lam2 * t2) + (cosP * cosP) * t2);
+    const float delta = dS / u;
+    const float sperp = R * (q.dphi + eps);
+    const float zS = (z0 + lam * sperp) - (delta * cosP) * tt;
+    const float ld = lam * delta;
+    const float ctau = zS * q.cAx - ld * q.sAx;
+    const float a1 = zS * tt, a2 = ld * tt;
+    const float Q = ((2.0f * ctau) * tt + a1 * a1) + a2 * a2;
+    const float A = R + delta;
+    const float disc = A * A - Q;
+    if (!(disc > 0.0f)) { vote = true; continue; }
+    const float e = sig * (delta - Q / (A + sqrtf(disc)));
+    if (!__builtin_isfinite(e)) { vote = true; continue; }
+    const Iv32 E = {wdn32(e - q.bs), wup32(e + q.bs)};
+    const Iv32 Hv = isub32(itwice32(G), iadd32(itwice32(E), imul32(K, isqr32(E))));
+    if (Hv.lo <= 0.0f && 0.0f <= Hv.hi) vote = true;
+  }
+  return vote;
+}
+
+// Pre-filter of a (triple, stereo hit) pair at an FP32 level: false only
+// when no box of the triple can get the FP32 vote.  The enclosure of e over
+// the centre rectangle (e_enclosure) must also show that every box stays in
+// the FP32 domain (|eps| <= 0.99, a discriminant above 1e-3 A^2, far beyond
+// FP32 rounding); its FP32 image is widened by band + 2 slack (one slack for
+// |e32 - e64|, one to spare for FP32 rounding) before the same interval test.
+IA_HD bool triple_may_vote32(const PairQ& q, const Frame& f, const HitRec& h, Iv Z, Iv L, float slack32) {
+  if (!(f.R <= kR32Max)) return true;
+  const Iv32 G = to32(Iv{q.Glo, q.Ghi});
+  const Iv32 K = to32(f.K);
+  const float bs2 = wup32(ru32(h.band) + 2.0f * slack32);
+  const double tt = h.tant, t2 = tt * tt;
+  for (int si = 0; si < 2; ++si) {
+    const double dS = si == 0 ? h.d : -h.d;
+    Iv E, EPS, DISC, A;
+    if (!e_enclosure_dom(q, f.R, f.sig, tt, t2, dS, Z, L, &E, &EPS, &DISC, &A)) return true;
+    if (!(fabs(EPS.lo) <= 0.99 && fabs(EPS.hi) <= 0.99)) return true;
+    if (!(DISC.lo > 1e-3 * A.hi * A.hi)) return true;
+    const Iv32 Eb = {wdn32(rd32(E.lo) - bs2), wup32(ru32(E.hi) + bs2)};
+    const Iv32 Hb = isub32(itwice32(G), iadd32(itwice32(Eb), imul32(K, isqr32(Eb))));
+    if (Hb.lo <= 0.0f && 0.0f <= Hb.hi) return true;
   }
   return false;
 }
@@ -308,24 +433,26 @@ IA_HD void centre_ranges(const BoxD& P, const uint32_t m[5], Iv* Z, Iv* L) {
 // hit preparation.  One thread per hit; also clears the vote histogram.  With
 // `ev` set it starts an event: resets the event state, writes the search
 // range box and marks every hit unassigned.
-__global__ void k_prep(const double* __restrict__ hits, const uint8_t* __restrict__ active, int32_t n_hits,
-                       HitRec* __restrict__ out, uint32_t* __restrict__ hist, int32_t n_bins,
-                       uint32_t* __restrict__ status, int64_t* __restrict__ n_bad, EventState* __restrict__ ev,
-                       int32_t* __restrict__ n_out, BoxD* __restrict__ range_dst, BoxD range,
-                       int32_t* __restrict__ assigned) {
+__global__ void k_prep(const double* __restrict__ hits, const uint8_t* __restrict__ active, EvView vw,
+                       HitRec* __restrict__ out, uint32_t* __restrict__ hist, uint32_t* __restrict__ status,
+                       int64_t* __restrict__ n_bad, EventState* __restrict__ ev, int32_t* __restrict__ n_out,
+                       BoxD* __restrict__ range_dst, BoxD range, int32_t* __restrict__ assigned) {
+  const int e = blockIdx.y;
+  const int32_t beg = vw.beg(e), n_hits = vw.count(e), n_bins = n_hits + 1;
   const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   const int32_t stride = gridDim.x * blockDim.x;
   if (ev && i == 0) {
-    EventState e{};
-    *ev = e;
-    if (n_out) *n_out = 0;
-    *range_dst = range;
+    EventState es{};
+    ev[e] = es;
+    if (n_out) n_out[e] = 0;
+    if (e == 0) *range_dst = range;
   }
-  for (int32_t b = i; b < n_bins && hist; b += stride) hist[b] = 0u;
+  if (hist)
+    for (int32_t b = i; b < n_bins; b += stride) hist[int64_t(e) * vw.hist_stride + b] = 0u;
   for (int32_t h = i; h < n_hits; h += stride) {
     bool bad;
-    prep_one(hits + 8 * static_cast<int64_t>(h), active ? active[h] != 0 : true, &out[h], &bad);
-    if (assigned) assigned[h] = -1;
+    prep_one(hits + 8 * static_cast<int64_t>(beg + h), active ? active[beg + h] != 0 : true, &out[beg + h], &bad);
+    if (assigned) assigned[beg + h] = -1;
     if (bad) {
       atomicOr(status, kStBadHit);
       atomicAdd(reinterpret_cast<unsigned long long*>(n_bad), 1ull);
@@ -383,11 +510,16 @@ __device__ __forceinline__ int32_t block_sum(int32_t v, int32_t* sbuf) {
 // (triple, hit) pre-pass, one thread per pair: flags[t * n_hits + h] =
 // 0 no vote anywhere in the triple (or hit unused), 1 axial hit voting for
 // the whole triple, 2 stereo hit that may vote (decided per box).
-__global__ void __launch_bounds__(kWG) k_pair_filter(const HitRec* __restrict__ hits, int32_t n_hits,
+__global__ void __launch_bounds__(kWG) k_pair_filter(const HitRec* __restrict__ hits, EvView vw,
                                                      const BoxD* __restrict__ parents, Shape sh,
                                                      uint8_t* __restrict__ flags, int32_t filter,
-                                                     const EventState* __restrict__ ev) {
-  if (ev && ev->done) return;
+                                                     const EventState* __restrict__ ev, int32_t f32, float slack32) {
+  const int e = blockIdx.y;
+  if (ev && ev[e].done) return;
+  const int32_t n_hits = vw.count(e);
+  hits += vw.beg(e);
+  parents += e * vw.par_stride;
+  flags += e * vw.flag_stride;
   const uint32_t i = blockIdx.x * kWG + threadIdx.x;
   const uint32_t n_tr = sh.n_parents * sh.m012;
   if (n_hits <= 0 || i >= n_tr * static_cast<uint32_t>(n_hits)) return;
@@ -401,13 +533,16 @@ __global__ void __launch_bounds__(kWG) k_pair_filter(const HitRec* __restrict__ 
     const Iv G = residual_G(f, h);
     if (h.axial) {
       fl = (h_contains0(G, f.K, f.sig * h.d, h.band) || h_contains0(G, f.K, f.sig * (-h.d), h.band)) ? 1 : 0;
+    } else if (f32 && !(f.R <= kR32Max)) {
+      fl = 1;                                // outside the FP32 domain: the pair votes
     } else if (!filter) {
       fl = 2;
     } else {
       const PairQ q = pair_quantities(f, h, G);
       Iv Zr, Lr;
       centre_ranges(TP, sh.m, &Zr, &Lr);
-      fl = triple_may_vote(q, f, h, Zr, Lr) ? 2 : 0;
+      const bool may = f32 ? triple_may_vote32(q, f, h, Zr, Lr, slack32) : triple_may_vote(q, f, h, Zr, Lr);
+      fl = may ? 2 : 0;
     }
   }
   flags[i] = fl;
@@ -422,14 +557,24 @@ __global__ void __launch_bounds__(kWG) k_pair_filter(const HitRec* __restrict__ 
 // are collected (at most k workgroups hold boxes above v*).  Then the entries
 // are ordered, the selected boxes written, the histogram cleared and, for
 // level 0, the event stopped when its maximum is below v_min.
-__global__ void __launch_bounds__(kWG) k_select_wg(const uint16_t* __restrict__ votes, uint32_t n_boxes,
-                                                   uint32_t* __restrict__ hist, int32_t n_bins, int32_t k,
-                                                   const int32_t* __restrict__ wg_max, uint32_t n_wg, int32_t bx,
-                                                   const BoxD* __restrict__ parents, Shape sh,
-                                                   BoxD* __restrict__ out_boxes, int64_t* __restrict__ out_index,
-                                                   uint16_t* __restrict__ out_votes, EventState* __restrict__ ev,
-                                                   int32_t v_min_stop) {
-  if (ev && ev->done) return;
+__global__ void __launch_bounds__(kWG) k_select_wg(const uint16_t* __restrict__ votes, EvView vw,
+                                                   uint32_t* __restrict__ hist, const int32_t* __restrict__ wg_max,
+                                                   uint32_t n_wg, int32_t bx, const BoxD* __restrict__ parents,
+                                                   Shape sh, BoxD* __restrict__ out_boxes,
+                                                   int64_t* __restrict__ out_index, uint16_t* __restrict__ out_votes,
+                                                   EventState* __restrict__ ev, int32_t v_min_stop) {
+  const int e = blockIdx.y;
+  if (ev && ev[e].done) return;
+  const uint32_t n_boxes = sh.n_boxes;
+  const int32_t n_bins = vw.count(e) + 1, k = vw.k;
+  votes += int64_t(e) * n_boxes;
+  hist += int64_t(e) * vw.hist_stride;
+  wg_max += int64_t(e) * vw.wg_stride;
+  parents += e * vw.par_stride;
+  out_boxes += int64_t(e) * k;
+  out_index += int64_t(e) * k;
+  out_votes += int64_t(e) * k;
+  if (ev) ev += e;
   __shared__ SelInfo si;
   __shared__ int32_t sbuf[kWG / 64];
   __shared__ int32_t s_vmax, s_run_gt, s_run_eq;
@@ -514,17 +659,28 @@ __global__ void __launch_bounds__(kWG) k_select_wg(const uint16_t* __restrict__ 
 // from k_pair_filter it stages only the stereo pairs that may vote.
 // hist (nullable) receives the vote histogram of bins 0..n_bins-1 and
 // wg_max (nullable) each workgroup's maximum vote, for k_select_wg.
-template <int BX>
-__global__ void __launch_bounds__(kWG) k_vote(const HitRec* __restrict__ hits, int32_t n_hits,
+template <int BX, bool F32>
+__global__ void __launch_bounds__(kWG) k_vote(const HitRec* __restrict__ hits, EvView vw,
                                               const BoxD* __restrict__ parents, Shape sh,
                                               uint16_t* __restrict__ votes, uint32_t* __restrict__ hist,
-                                              int32_t n_bins, uint32_t* __restrict__ status,
-                                              const EventState* __restrict__ ev,
-                                              const uint8_t* __restrict__ flags, int32_t* __restrict__ wg_max) {
+                                              uint32_t* __restrict__ status, const EventState* __restrict__ ev,
+                                              const uint8_t* __restrict__ flags, int32_t* __restrict__ wg_max,
+                                              unsigned long long* __restrict__ work, float slack32) {
   constexpr int HS = kWG / BX;
   static_assert(BX % 64 == 0 && HS * BX == kWG, "slices are whole waves");
-  if (ev && ev->done) return;
+  const int e = blockIdx.y;
+  if (ev && ev[e].done) return;
+  const int32_t n_hits = vw.count(e), n_bins = n_hits + 1;
+  hits += vw.beg(e);
+  parents += e * vw.par_stride;
+  votes += int64_t(e) * sh.n_boxes;
+  if (hist) hist += int64_t(e) * vw.hist_stride;
+  if (flags) flags += e * vw.flag_stride;
+  if (wg_max) wg_max += int64_t(e) * vw.wg_stride;
   __shared__ double sq[13][kCap + 16];
+  // FP32 levels stage 16 floats per pair in the same storage
+  static_assert(sizeof(PairQ32) == 16 * sizeof(float) && 16 * 4 <= 13 * 8, "FP32 staging fits");
+  float(*sq32)[kCap + 16] = reinterpret_cast<float(*)[kCap + 16]>(&sq[0][0]);
   __shared__ int8_t sflag[kCap + 16];
   __shared__ uint32_t shist[kHistLds];
   __shared__ int32_t sred[HS][BX];
@@ -557,8 +713,13 @@ __global__ void __launch_bounds__(kWG) k_vote(const HitRec* __restrict__ hits, i
   child_edge(P.lo[4], P.hi[4], sh.m[4], k[4], &llo, &lhi);
   const double z0 = 0.5 * (zlo + zhi), lam = 0.5 * (llo + lhi);
   const double lamR = lam * f.R, lam2 = lam * lam;
+  // FP32 images of the lane's box (used at FP32 levels only)
+  const float R32 = static_cast<float>(f.R), sig32 = static_cast<float>(f.sig);
+  const Iv32 K32 = to32(f.K);
+  const float z032 = static_cast<float>(z0), lam32 = static_cast<float>(lam);
+  const float lamR32 = lam32 * R32, lam232 = lam32 * lam32;
 
-  int32_t nv = 0;
+  int32_t nv = 0, n_eval = 0, n_staged = 0;
   for (int32_t h0 = 0; h0 < n_hits; h0 += hc) {
     const int32_t nh = min(hc, n_hits - h0);
     __syncthreads();
@@ -581,13 +742,24 @@ __global__ void __launch_bounds__(kWG) k_vote(const HitRec* __restrict__ hits, i
       if (h.axial) {
         bool v = h_contains0(G, ft.K, ft.sig * h.d, h.band) || h_contains0(G, ft.K, ft.sig * (-h.d), h.band);
         sflag[slot] = v ? 1 : 0;
+      } else if (F32 && !(ft.R <= kR32Max)) {
+        sflag[slot] = 1;                     // outside the FP32 domain: the pair votes
       } else {
         const PairQ q = pair_quantities(ft, h, G);
+        ++n_staged;
         sflag[slot] = 2;
-        sq[0][slot] = q.Glo; sq[1][slot] = q.Ghi; sq[2][slot] = q.sArc; sq[3][slot] = q.dphi;
-        sq[4][slot] = q.RAx; sq[5][slot] = q.sinA; sq[6][slot] = q.cosA; sq[7][slot] = q.sAx;
-        sq[8][slot] = q.cAx; sq[9][slot] = q.c2; sq[10][slot] = q.s2; sq[11][slot] = q.twoRAx2;
-        sq[12][slot] = q.RpRAx;
+        if constexpr (F32) {
+          const PairQ32 r = pair_q32(q, h, slack32);
+          sq32[0][slot] = r.Glo; sq32[1][slot] = r.Ghi; sq32[2][slot] = r.sArc; sq32[3][slot] = r.dphi;
+          sq32[4][slot] = r.RAx; sq32[5][slot] = r.sinA; sq32[6][slot] = r.cosA; sq32[7][slot] = r.sAx;
+          sq32[8][slot] = r.cAx; sq32[9][slot] = r.c2; sq32[10][slot] = r.s2; sq32[11][slot] = r.twoRAx2;
+          sq32[12][slot] = r.RpRAx; sq32[13][slot] = r.tt; sq32[14][slot] = r.d; sq32[15][slot] = r.bs;
+        } else {
+          sq[0][slot] = q.Glo; sq[1][slot] = q.Ghi; sq[2][slot] = q.sArc; sq[3][slot] = q.dphi;
+          sq[4][slot] = q.RAx; sq[5][slot] = q.sinA; sq[6][slot] = q.cosA; sq[7][slot] = q.sAx;
+          sq[8][slot] = q.cAx; sq[9][slot] = q.c2; sq[10][slot] = q.s2; sq[11][slot] = q.twoRAx2;
+          sq[12][slot] = q.RpRAx;
+        }
       }
     }
     __syncthreads();
@@ -595,14 +767,40 @@ __global__ void __launch_bounds__(kWG) k_vote(const HitRec* __restrict__ hits, i
       const int32_t slot = my_tl * pitch + hl;
       const int8_t fl = sflag[slot];
       if (fl < 2) { nv += fl > 0 ? 1 : 0; continue; }
-      const HitRec& h = hits[h0 + hl];
-      PairQ q;
-      q.Glo = sq[0][slot]; q.Ghi = sq[1][slot]; q.sArc = sq[2][slot]; q.dphi = sq[3][slot];
-      q.RAx = sq[4][slot]; q.sinA = sq[5][slot]; q.cosA = sq[6][slot]; q.sAx = sq[7][slot];
-      q.cAx = sq[8][slot]; q.c2 = sq[9][slot]; q.s2 = sq[10][slot]; q.twoRAx2 = sq[11][slot];
-      q.RpRAx = sq[12][slot];
-      const double tt = h.tant;
-      if (stereo_vote(q, f.R, f.sig, f.K, z0, lam, lamR, lam2, tt, tt * tt, h.d, h.band)) ++nv;
+      n_eval += live ? 1 : 0;
+      if constexpr (F32) {
+        PairQ32 r;
+        r.Glo = sq32[0][slot]; r.Ghi = sq32[1][slot]; r.sArc = sq32[2][slot]; r.dphi = sq32[3][slot];
+        r.RAx = sq32[4][slot]; r.sinA = sq32[5][slot]; r.cosA = sq32[6][slot]; r.sAx = sq32[7][slot];
+        r.cAx = sq32[8][slot]; r.c2 = sq32[9][slot]; r.s2 = sq32[10][slot]; r.twoRAx2 = sq32[11][slot];
+        r.RpRAx = sq32[12][slot]; r.tt = sq32[13][slot]; r.d = sq32[14][slot]; r.bs = sq32[15][slot];
+        if (stereo_vote32(r, R32, sig32, K32, z032, lam32, lamR32, lam232)) ++nv;
+      } else {
+        const HitRec& h = hits[h0 + hl];
+        PairQ q;
+        q.Glo = sq[0][slot]; q.Ghi = sq[1][slot]; q.sArc = sq[2][slot]; q.dphi = sq[3][slot];
+        q.RAx = sq[4][slot]; q.sinA = sq[5][slot]; q.cosA = sq[6][slot]; q.sAx = sq[7][slot];
+        q.cAx = sq[8][slot]; q.c2 = sq[9][slot]; q.s2 = sq[10][slot]; q.twoRAx2 = sq[11][slot];
+        q.RpRAx = sq[12][slot];
+        const double tt = h.tant;
+        if (stereo_vote(q, f.R, f.sig, f.K, z0, lam, lamR, lam2, tt, tt * tt, h.d, h.band)) ++nv;
+      }
+    }
+  }
+  if (work) {
+    // work done by this workgroup: summed over its waves in LDS, then one
+    // atomic per counter into one of kWorkSlots cache-line-sized slots
+    int32_t a = n_eval, b2 = n_staged;
+    for (int o = 32; o > 0; o >>= 1) { a += __shfl_down(a, o, 64); b2 += __shfl_down(b2, o, 64); }
+    __shared__ int32_t swork[2][kWG / 64];
+    if ((tid & 63) == 0) { swork[0][tid >> 6] = a; swork[1][tid >> 6] = b2; }
+    __syncthreads();
+    if (tid == 0) {
+      int32_t sa = 0, sb = 0;
+      for (int w = 0; w < kWG / 64; ++w) { sa += swork[0][w]; sb += swork[1][w]; }
+      unsigned long long* slot = work + kWorkSlotU64 * ((blockIdx.x + blockIdx.y * 7u) % kWorkSlots);
+      if (sa) atomicAdd(&slot[F32 ? 2 : 0], static_cast<unsigned long long>(sa));
+      if (sb) atomicAdd(&slot[F32 ? 3 : 1], static_cast<unsigned long long>(sb));
     }
   }
   if (HS > 1) {
@@ -829,8 +1027,15 @@ __global__ void __launch_bounds__(kWG) k_est_partial(const BoxD* __restrict__ pa
                                                      const uint16_t* __restrict__ votes,
                                                      const BoxD* __restrict__ first_box,
                                                      const uint16_t* __restrict__ first_votes,
-                                                     double* __restrict__ part, const EventState* __restrict__ ev) {
-  if (ev && ev->done) return;
+                                                     double* __restrict__ part, EvView vw,
+                                                     const EventState* __restrict__ ev) {
+  const int e = blockIdx.y;
+  if (ev && ev[e].done) return;
+  parents += e * vw.par_stride;
+  votes += int64_t(e) * sh.n_boxes;
+  first_box += int64_t(e) * vw.k;
+  first_votes += int64_t(e) * vw.k;
+  part += int64_t(e) * vw.part_stride;
   __shared__ double s[kEstQ][kWG];
   const int32_t vmax = first_votes[0];
   const double c0 = 0.5 * (first_box->lo[1] + first_box->hi[1]);
@@ -906,10 +1111,20 @@ __global__ void __launch_bounds__(kWG) k_est_final(const double* __restrict__ pa
                                                    const BoxD* __restrict__ first_box,
                                                    const uint16_t* __restrict__ first_votes,
                                                    EstimateOut* __restrict__ out, EventState* __restrict__ ev,
-                                                   HitRec* __restrict__ hits, int32_t n_hits, double scale,
+                                                   HitRec* __restrict__ hits, EvView vw, double scale,
                                                    int32_t* __restrict__ assigned, HelixOut* __restrict__ hout,
-                                                   int32_t max_out, int32_t* __restrict__ n_out) {
-  if (ev && ev->done) return;
+                                                   int32_t* __restrict__ n_out) {
+  const int e = blockIdx.y;
+  if (ev && ev[e].done) return;
+  part += int64_t(e) * vw.part_stride;
+  first_box += int64_t(e) * vw.k;
+  first_votes += int64_t(e) * vw.k;
+  if (ev) ev += e;
+  const int32_t n_hits = vw.count(e), max_out = vw.max_out;
+  if (hits) hits += vw.beg(e);
+  if (assigned) assigned += vw.beg(e);
+  if (hout) hout += int64_t(e) * max_out;
+  if (n_out) n_out += e;
   __shared__ double s[kEstQ][kWG];
   __shared__ double stack[kWG][kEstLevels];
   __shared__ double sp[5], se[5];

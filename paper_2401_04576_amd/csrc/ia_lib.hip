@@ -32,6 +32,8 @@ constexpr int32_t kMaxTopK = ia::kMaxTopK;
 constexpr int64_t kMaxLevelBoxes = (int64_t(1) << 31) - 1;
 constexpr int64_t kSelChunkMin = 4096;
 constexpr int32_t kSelMaxGroups = 1024;
+constexpr int kOffSlots = 8;             // pinned offset-staging slots
+constexpr int32_t kOffSlotInts = 65536;  // events + 1 per slot
 // k_estimate: 256 lanes x segments of at most 2^(kEstLevels - 1) boxes
 constexpr int64_t kMaxEstimateBoxes = int64_t(ia::kWG) << (ia::kEstLevels - 1);
 
@@ -41,6 +43,8 @@ struct Persistent {        // fixed region at the start of the arena
   uint32_t status;
   uint32_t done_counter;
   int64_t n_bad;
+  // vote-kernel work counters (ia::kWorkSlots slots, summed on read)
+  alignas(128) unsigned long long work[ia::kWorkSlots * ia::kWorkSlotU64];
 };
 
 }  // namespace
@@ -54,7 +58,16 @@ struct ia_ctx {
   bool profiling = false;
   int32_t tile_override = 0;
   int32_t filter_mode = -1;       // -1: automatic, 0: off, 1: on
-  std::vector<std::pair<hipEvent_t, hipEvent_t>> marks;
+  int32_t max_chunk = 65535;      // events per batched launch
+  float slack32 = ia::ru32(1e-6);  // band widening of ia_vote_level at FP32
+  // pinned staging ring for the chunk-relative hit offsets copied to the
+  // device; a slot is rewritten only after its previous copy has completed
+  int32_t* pinned = nullptr;
+  hipEvent_t slot_done[kOffSlots] = {};
+  bool slot_used[kOffSlots] = {};
+  uint32_t slot_next = 0;
+  struct Mark { hipEvent_t e0, e1; bool f32; };
+  std::vector<Mark> marks;
 };
 
 namespace {
@@ -156,23 +169,51 @@ int32_t use_filter(const ia_ctx* c, const Shape& sh) {
   return sh.m34 >= 64 ? 1 : 0;
 }
 
-// launches the (triple, hit) pre-pass when it pays and room allows; returns
-// the flags to hand to the vote kernel, or nullptr
-const uint8_t* launch_filter(ia_ctx* c, const HitRec* recs, int32_t n, const BoxD* par, const Shape& sh,
-                             uint8_t* flags, size_t flag_cap, EventState* ev, hipStream_t s) {
-  if (!flags || n <= 0 || !use_filter(c, sh)) return nullptr;
-  const uint64_t pairs = uint64_t(sh.n_parents) * sh.m012 * uint64_t(n);
-  if (pairs > flag_cap || pairs >= (uint64_t(1) << 31)) return nullptr;
+ia::EvView single_view(int32_t n_hits) {
+  ia::EvView v{};
+  v.off = nullptr;
+  v.n_single = n_hits;
+  return v;
+}
+
+// launches the (triple, hit) pre-pass for n_ev events when it pays and the
+// flag buffer holds it; returns the flags for the vote kernel, or nullptr
+const uint8_t* launch_filter(ia_ctx* c, const HitRec* recs, const ia::EvView& vw, int32_t n_ev, int32_t max_hits,
+                             const BoxD* par, const Shape& sh, uint8_t* flags, const EventState* ev, hipStream_t s,
+                             bool f32, float slack32) {
+  if (!flags || max_hits <= 0 || !use_filter(c, sh)) return nullptr;
+  const uint64_t pairs = uint64_t(sh.n_parents) * sh.m012 * uint64_t(max_hits);
+  if (pairs > uint64_t(vw.flag_stride) || pairs >= (uint64_t(1) << 31)) return nullptr;
   const uint32_t grid = static_cast<uint32_t>((pairs + ia::kWG - 1) / ia::kWG);
-  hipLaunchKernelGGL(ia::k_pair_filter, dim3(grid), dim3(ia::kWG), 0, s, recs, n, par, sh, flags, 1, ev);
+  hipLaunchKernelGGL(ia::k_pair_filter, dim3(grid, n_ev), dim3(ia::kWG), 0, s, recs, vw, par, sh, flags, 1, ev,
+                     f32 ? 1 : 0, slack32);
   return flags;
 }
 
-// launches the vote kernel (with the fused selection when sel.k > 0),
-// bracketed by events when profiling
-ia_status launch_vote(ia_ctx* c, const HitRec* recs, int32_t n, const BoxD* par, const Shape& sh, uint16_t* votes,
-                      uint32_t* hist, int32_t n_bins, const EventState* ev, const uint8_t* flags, int32_t* wg_max,
-                      hipStream_t s, int32_t* tile_used = nullptr) {
+// launches the vote kernel for n_ev events, bracketed by events when profiling
+template <bool F32>
+void launch_vote_tile(int32_t bx, dim3 g, hipStream_t s, const HitRec* recs, const ia::EvView& vw, const BoxD* par,
+                      const Shape& sh, uint16_t* votes, uint32_t* hist, uint32_t* st, const EventState* ev,
+                      const uint8_t* flags, int32_t* wg_max, unsigned long long* wk, float slack32) {
+  switch (bx) {
+    case 256:
+      hipLaunchKernelGGL((ia::k_vote<256, F32>), g, dim3(ia::kWG), 0, s, recs, vw, par, sh, votes, hist, st, ev, flags,
+                         wg_max, wk, slack32);
+      break;
+    case 128:
+      hipLaunchKernelGGL((ia::k_vote<128, F32>), g, dim3(ia::kWG), 0, s, recs, vw, par, sh, votes, hist, st, ev, flags,
+                         wg_max, wk, slack32);
+      break;
+    default:
+      hipLaunchKernelGGL((ia::k_vote<64, F32>), g, dim3(ia::kWG), 0, s, recs, vw, par, sh, votes, hist, st, ev, flags,
+                         wg_max, wk, slack32);
+      break;
+  }
+}
+
+ia_status launch_vote(ia_ctx* c, const HitRec* recs, const ia::EvView& vw, int32_t n_ev, const BoxD* par,
+                      const Shape& sh, uint16_t* votes, uint32_t* hist, const EventState* ev, const uint8_t* flags,
+                      int32_t* wg_max, hipStream_t s, bool f32, float slack32, int32_t* tile_used = nullptr) {
   const int32_t bx = vote_tile(c, sh.n_boxes);
   const uint32_t grid = (sh.n_boxes + bx - 1) / bx;
   if (tile_used) *tile_used = bx;
@@ -183,74 +224,68 @@ ia_status launch_vote(ia_ctx* c, const HitRec* recs, int32_t n, const BoxD* par,
     IA_HIP(c, hipEventRecord(e0, s));
   }
   uint32_t* st = &persistent(c)->status;
-  switch (bx) {
-    case 256:
-      hipLaunchKernelGGL(ia::k_vote<256>, dim3(grid), dim3(ia::kWG), 0, s, recs, n, par, sh, votes, hist, n_bins, st, ev,
-                         flags, wg_max);
-      break;
-    case 128:
-      hipLaunchKernelGGL(ia::k_vote<128>, dim3(grid), dim3(ia::kWG), 0, s, recs, n, par, sh, votes, hist, n_bins, st, ev,
-                         flags, wg_max);
-      break;
-    default:
-      hipLaunchKernelGGL(ia::k_vote<64>, dim3(grid), dim3(ia::kWG), 0, s, recs, n, par, sh, votes, hist, n_bins, st, ev,
-                         flags, wg_max);
-      break;
-  }
+  unsigned long long* wk = persistent(c)->work;
+  const dim3 g(grid, n_ev);
+  if (f32) launch_vote_tile<true>(bx, g, s, recs, vw, par, sh, votes, hist, st, ev, flags, wg_max, wk, slack32);
+  else launch_vote_tile<false>(bx, g, s, recs, vw, par, sh, votes, hist, st, ev, flags, wg_max, wk, slack32);
   if (c->profiling) {
     IA_HIP(c, hipEventRecord(e1, s));
-    c->marks.emplace_back(e0, e1);
+    c->marks.push_back({e0, e1, f32});
   }
   IA_HIP(c, hipGetLastError());
   return IA_OK;
 }
 
-// estimate of a level from its selection (rank 0 = first max-vote box)
-ia_status launch_estimate(ia_ctx* c, const BoxD* par, const Shape& sh, const uint16_t* votes, const BoxD* first_box,
-                          const uint16_t* first_votes, double* part, ia::EstimateOut* out, EventState* ev,
-                          HitRec* recs, int32_t n_hits, double scale, int32_t* assigned, ia::HelixOut* hout,
-                          int32_t max_out, int32_t* n_out, hipStream_t s) {
-  const int32_t n_part = est_parts(sh.n_boxes);
-  hipLaunchKernelGGL(ia::k_est_partial, dim3(n_part), dim3(ia::kWG), 0, s, par, sh, votes, first_box, first_votes,
-                     part, ev);
-  hipLaunchKernelGGL(ia::k_est_final, dim3(1), dim3(ia::kWG), 0, s, part, n_part, first_box, first_votes, out, ev,
-                     recs, n_hits, scale, assigned, hout, max_out, n_out);
-  IA_HIP(c, hipGetLastError());
-  return IA_OK;
-}
-
-// scratch layout of ia_find_helices (byte offsets into the arena)
+// scratch layout of one chunk of ia_find_helices (byte offsets into the
+// arena): per-event slices of every array, sized for events of max_hits hits
 struct FindLayout {
-  size_t recs, votes, hist, cnt, tmp, selA, selB, range, sel_idx, sel_v, ev, part, flags, wg_max, total;
-  size_t flag_cap;
+  size_t off, recs, votes, hist, selA, selB, range, sel_idx, sel_v, ev, part, flags, wg_max, total;
+  int64_t flag_stride, votes_stride;
+  int32_t hist_stride, wg_stride, part_stride, n_part;
 };
 
-void layout_find(int64_t max_level_boxes, int64_t max_triples, int32_t top_k, int32_t max_hits, FindLayout* L) {
-  uint32_t chunk;
-  const int32_t g = sel_groups(max_level_boxes, &chunk);
-  const int32_t n_part = est_parts(static_cast<uint32_t>(max_level_boxes));
+void layout_find(int64_t max_level_boxes, int64_t max_triples, int32_t top_k, int32_t max_hits, int32_t n_ev,
+                 int64_t n_hits_total, FindLayout* L) {
+  L->n_part = est_parts(static_cast<uint32_t>(max_level_boxes));
+  L->votes_stride = max_level_boxes;
+  L->hist_stride = max_hits + 2;
+  L->flag_stride = max_triples * int64_t(std::max(0, max_hits));
+  L->wg_stride = static_cast<int32_t>((max_level_boxes + 63) / 64);
+  L->part_stride = ia::kEstQ * L->n_part;
+  const size_t E = size_t(std::max(1, n_ev));
   size_t off = align_up(sizeof(Persistent));
   auto take = [&](size_t bytes) {
     const size_t o = off;
     off += align_up(bytes + 1);
     return o;
   };
-  L->recs = take(sizeof(HitRec) * size_t(std::max(1, max_hits)));
-  L->votes = take(sizeof(uint16_t) * size_t(max_level_boxes));
-  L->hist = take(sizeof(uint32_t) * size_t(max_hits + 2));
-  L->cnt = take(sizeof(int32_t) * 2 * size_t(g));
-  L->tmp = take(sizeof(uint32_t) * size_t(top_k));
-  L->selA = take(sizeof(BoxD) * size_t(top_k));
-  L->selB = take(sizeof(BoxD) * size_t(top_k));
+  L->off = take(sizeof(int32_t) * (E + 1));
+  L->recs = take(sizeof(HitRec) * size_t(std::max<int64_t>(1, n_hits_total)));
+  L->votes = take(sizeof(uint16_t) * size_t(L->votes_stride) * E);
+  L->hist = take(sizeof(uint32_t) * size_t(L->hist_stride) * E);
+  L->selA = take(sizeof(BoxD) * size_t(top_k) * E);
+  L->selB = take(sizeof(BoxD) * size_t(top_k) * E);
   L->range = take(sizeof(BoxD));
-  L->sel_idx = take(sizeof(int64_t) * size_t(top_k));
-  L->sel_v = take(sizeof(uint16_t) * size_t(top_k));
-  L->ev = take(sizeof(EventState));
-  L->part = take(sizeof(double) * ia::kEstQ * size_t(n_part));
-  L->flag_cap = size_t(max_triples) * size_t(std::max(0, max_hits));
-  L->flags = take(L->flag_cap);
-  L->wg_max = take(sizeof(int32_t) * size_t((max_level_boxes + 63) / 64));
+  L->sel_idx = take(sizeof(int64_t) * size_t(top_k) * E);
+  L->sel_v = take(sizeof(uint16_t) * size_t(top_k) * E);
+  L->ev = take(sizeof(EventState) * E);
+  L->part = take(sizeof(double) * size_t(L->part_stride) * E);
+  L->flags = take(size_t(L->flag_stride) * E);
+  L->wg_max = take(sizeof(int32_t) * size_t(L->wg_stride) * E);
   L->total = off;
+}
+
+struct SchedShapes {
+  Shape sh0, shr;
+  int64_t max_boxes, max_triples;
+};
+
+bool sched_shapes(const ia_schedule* sc, SchedShapes* S) {
+  if (!make_shape(sc->bins, 1, &S->sh0)) return false;
+  if (!make_shape(sc->split, std::max(1, sc->top_k), &S->shr)) return false;
+  S->max_boxes = std::max<int64_t>(S->sh0.n_boxes, S->shr.n_boxes);
+  S->max_triples = std::max<int64_t>(int64_t(S->sh0.n_parents) * S->sh0.m012, int64_t(S->shr.n_parents) * S->shr.m012);
+  return true;
 }
 
 }  // namespace
@@ -272,6 +307,14 @@ ia_status ia_ctx_create(ia_ctx** out, int32_t device, size_t scratch_bytes) {
   if (e != hipSuccess) { (void)hipFree(p); delete c; return IA_ERR_DEVICE; }
   c->arena = static_cast<char*>(p);
   c->arena_bytes = scratch_bytes;
+  void* hp = nullptr;
+  e = hipHostMalloc(&hp, sizeof(int32_t) * size_t(kOffSlots) * kOffSlotInts, hipHostMallocDefault);
+  if (e != hipSuccess) { (void)hipFree(p); delete c; return IA_ERR_NOMEM; }
+  c->pinned = static_cast<int32_t*>(hp);
+  for (int i = 0; i < kOffSlots; ++i) {
+    e = hipEventCreateWithFlags(&c->slot_done[i], hipEventDisableTiming);
+    if (e != hipSuccess) { ia_ctx_destroy(c); return IA_ERR_DEVICE; }
+  }
   reset_bump(c);
   *out = c;
   return IA_OK;
@@ -280,14 +323,15 @@ ia_status ia_ctx_create(ia_ctx** out, int32_t device, size_t scratch_bytes) {
 void ia_ctx_destroy(ia_ctx* c) {
   if (!c) return;
   for (auto& m : c->marks) {
-    (void)hipEventDestroy(m.first);
-    (void)hipEventDestroy(m.second);
+    (void)hipEventDestroy(m.e0);
+    (void)hipEventDestroy(m.e1);
   }
-  if (c->arena) {
-    (void)hipSetDevice(c->device);
-    (void)hipDeviceSynchronize();
-    (void)hipFree(c->arena);
-  }
+  (void)hipSetDevice(c->device);
+  (void)hipDeviceSynchronize();
+  if (c->arena) (void)hipFree(c->arena);
+  if (c->pinned) (void)hipHostFree(c->pinned);
+  for (int i = 0; i < kOffSlots; ++i)
+    if (c->slot_done[i]) (void)hipEventDestroy(c->slot_done[i]);
   delete c;
 }
 
@@ -301,6 +345,23 @@ ia_status ia_ctx_status(ia_ctx* c, uint32_t* flags, int64_t* n_bad) {
   IA_HIP(c, hipMemcpy(&p, c->arena, sizeof p, hipMemcpyDeviceToHost));
   if (flags) *flags = p.status;
   if (n_bad) *n_bad = p.n_bad;
+  return IA_OK;
+}
+
+ia_status ia_ctx_work(ia_ctx* c, int64_t* stereo_box_evals, int64_t* staged_pairs, int64_t* stereo_box_evals_fp32,
+                      int64_t* staged_pairs_fp32) {
+  if (!c) return IA_ERR_INVALID;
+  IA_HIP(c, hipSetDevice(c->device));
+  IA_HIP(c, hipDeviceSynchronize());
+  Persistent p;
+  IA_HIP(c, hipMemcpy(&p, c->arena, sizeof p, hipMemcpyDeviceToHost));
+  unsigned long long w[4] = {0, 0, 0, 0};
+  for (uint32_t i = 0; i < ia::kWorkSlots; ++i)
+    for (int k = 0; k < 4; ++k) w[k] += p.work[i * ia::kWorkSlotU64 + k];
+  if (stereo_box_evals) *stereo_box_evals = static_cast<int64_t>(w[0]);
+  if (staged_pairs) *staged_pairs = static_cast<int64_t>(w[1]);
+  if (stereo_box_evals_fp32) *stereo_box_evals_fp32 = static_cast<int64_t>(w[2]);
+  if (staged_pairs_fp32) *staged_pairs_fp32 = static_cast<int64_t>(w[3]);
   return IA_OK;
 }
 
@@ -321,6 +382,13 @@ ia_status ia_ctx_set_vote_tile(ia_ctx* c, int32_t bx) {
   return IA_OK;
 }
 
+ia_status ia_ctx_set_batch(ia_ctx* c, int32_t max_events) {
+  if (!c) return IA_ERR_INVALID;
+  if (max_events < 1) return fail(c, IA_ERR_INVALID, "max_events %d < 1", max_events);
+  c->max_chunk = std::min(max_events, kOffSlotInts - 1);
+  return IA_OK;
+}
+
 ia_status ia_ctx_set_prefilter(ia_ctx* c, int32_t mode) {
   if (!c) return IA_ERR_INVALID;
   if (mode < -1 || mode > 1) return fail(c, IA_ERR_INVALID, "prefilter mode %d not in {-1, 0, 1}", mode);
@@ -334,41 +402,46 @@ ia_status ia_ctx_set_profiling(ia_ctx* c, int32_t enable) {
   return IA_OK;
 }
 
-ia_status ia_ctx_profile_read(ia_ctx* c, int64_t* n_launches, double* total_ms) {
+ia_status ia_ctx_profile_read(ia_ctx* c, int64_t* n_launches, double* total_ms, int64_t* n_launches_fp32,
+                              double* total_ms_fp32) {
   if (!c) return IA_ERR_INVALID;
   IA_HIP(c, hipSetDevice(c->device));
-  double tot = 0.0;
-  int64_t n = 0;
+  double tot[2] = {0.0, 0.0};
+  int64_t n[2] = {0, 0};
   ia_status st = IA_OK;
   for (auto& m : c->marks) {
     if (st == IA_OK) {
-      hipError_t e = hipEventSynchronize(m.second);
+      hipError_t e = hipEventSynchronize(m.e1);
       float ms = 0.f;
-      if (e == hipSuccess) e = hipEventElapsedTime(&ms, m.first, m.second);
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, m.e0, m.e1);
       if (e != hipSuccess) st = fail(c, IA_ERR_DEVICE, "profile events: %s", hipGetErrorString(e));
-      tot += ms;
-      ++n;
+      tot[m.f32] += ms;
+      ++n[m.f32];
     }
-    (void)hipEventDestroy(m.first);
-    (void)hipEventDestroy(m.second);
+    (void)hipEventDestroy(m.e0);
+    (void)hipEventDestroy(m.e1);
   }
   c->marks.clear();
-  if (n_launches) *n_launches = n;
-  if (total_ms) *total_ms = tot;
+  if (n_launches) *n_launches = n[0];
+  if (total_ms) *total_ms = tot[0];
+  if (n_launches_fp32) *n_launches_fp32 = n[1];
+  if (total_ms_fp32) *total_ms_fp32 = tot[1];
   return st;
+}
+
+ia_status ia_ctx_set_fp32_slack(ia_ctx* c, double slack) {
+  if (!c) return IA_ERR_INVALID;
+  if (!(slack >= 0.0 && slack <= 1e-3)) return fail(c, IA_ERR_INVALID, "fp32 slack %g outside [0, 1e-3]", slack);
+  c->slack32 = ia::ru32(slack);
+  return IA_OK;
 }
 
 size_t ia_ctx_scratch_needed(const ia_schedule* sc, int32_t max_hits) {
   if (!sc || max_hits < 0) return 0;
-  int64_t nb0 = 1, nc = 1;
-  for (int j = 0; j < 5; ++j) { nb0 *= std::max(1, sc->bins[j]); nc *= std::max(1, sc->split[j]); }
-  const int64_t nbr = int64_t(std::max(1, sc->top_k)) * nc;
-  const int64_t nb = std::min<int64_t>(std::max(nb0, nbr), kMaxLevelBoxes);
-  const int64_t nt0 = int64_t(std::max(1, sc->bins[0])) * std::max(1, sc->bins[1]) * std::max(1, sc->bins[2]);
-  const int64_t ntr = int64_t(std::max(1, sc->top_k)) * std::max(1, sc->split[0]) * std::max(1, sc->split[1]) *
-                      std::max(1, sc->split[2]);
+  SchedShapes S;
+  if (!sched_shapes(sc, &S)) return 0;
   FindLayout L;
-  layout_find(nb, std::max(nt0, ntr), std::max(1, sc->top_k), max_hits, &L);
+  layout_find(S.max_boxes, S.max_triples, std::max(1, sc->top_k), max_hits, 1, max_hits, &L);
   return L.total;
 }
 
@@ -380,7 +453,7 @@ ia_status ia_vote_level(ia_ctx* c, const ia_hit* d_hits, int32_t n_hits, const u
   if (n_hits > 0 && !d_hits) return fail(c, IA_ERR_INVALID, "d_hits is NULL");
   if (!d_parents || !split || !d_votes) return fail(c, IA_ERR_INVALID, "null pointer argument");
   if (n_parents < 1) return fail(c, IA_ERR_INVALID, "n_parents %d < 1", n_parents);
-  if (prec != IA_FP64) return fail(c, IA_ERR_UNSUPPORTED, "precision %d not available", int(prec));
+  if (prec != IA_FP64 && prec != IA_FP32) return fail(c, IA_ERR_INVALID, "precision %d unknown", int(prec));
   Shape sh;
   if (!make_shape(split, n_parents, &sh)) return fail(c, IA_ERR_OVERFLOW, "level exceeds 2^31 - 1 boxes");
   IA_HIP(c, hipSetDevice(c->device));
@@ -389,16 +462,19 @@ ia_status ia_vote_level(ia_ctx* c, const ia_hit* d_hits, int32_t n_hits, const u
   if (!recs) return fail(c, IA_ERR_NOMEM, "scratch too small for %d hits", n_hits);
   hipStream_t s = as_stream(stream);
   Persistent* ps = persistent(c);
+  ia::EvView vw = single_view(n_hits);
   if (n_hits > 0)
-    hipLaunchKernelGGL(ia::k_prep, dim3((n_hits + 255) / 256), dim3(256), 0, s,
-                       reinterpret_cast<const double*>(d_hits), d_active, n_hits, recs, nullptr, 0, &ps->status,
+    hipLaunchKernelGGL(ia::k_prep, dim3((n_hits + 255) / 256, 1), dim3(256), 0, s,
+                       reinterpret_cast<const double*>(d_hits), d_active, vw, recs, nullptr, &ps->status,
                        &ps->n_bad, nullptr, nullptr, nullptr, BoxD{}, nullptr);
   // the pre-pass flags, when the remaining scratch holds them (results do not depend on it)
-  const size_t flag_cap = size_t(sh.n_parents) * sh.m012 * size_t(std::max(0, n_hits));
-  uint8_t* flags = (n_hits > 0 && use_filter(c, sh)) ? bump<uint8_t>(c, flag_cap) : nullptr;
+  const int64_t flag_cap = int64_t(sh.n_parents) * sh.m012 * int64_t(std::max(0, n_hits));
+  uint8_t* flags = (n_hits > 0 && use_filter(c, sh)) ? bump<uint8_t>(c, size_t(flag_cap)) : nullptr;
+  vw.flag_stride = flags ? flag_cap : 0;
   const BoxD* par = reinterpret_cast<const BoxD*>(d_parents);
-  const uint8_t* fl = launch_filter(c, recs, n_hits, par, sh, flags, flags ? flag_cap : 0, nullptr, s);
-  return launch_vote(c, recs, n_hits, par, sh, d_votes, nullptr, 0, nullptr, fl, nullptr, s);
+  const bool f32 = prec == IA_FP32;
+  const uint8_t* fl = launch_filter(c, recs, vw, 1, n_hits, par, sh, flags, nullptr, s, f32, c->slack32);
+  return launch_vote(c, recs, vw, 1, par, sh, d_votes, nullptr, nullptr, fl, nullptr, s, f32, c->slack32);
 }
 
 ia_status ia_refine(ia_ctx* c, const ia_box* d_parents, int32_t n_parents, const int32_t split[5],
@@ -463,8 +539,15 @@ ia_status ia_estimate(ia_ctx* c, const ia_box* d_parents, int32_t n_parents, con
   ia_status st = launch_select(c, d_votes, sh, par, hist, n_bins, 1, cnt, tmp, first, first_idx, first_v, nullptr,
                                0, s);
   if (st != IA_OK) return st;
-  return launch_estimate(c, par, sh, d_votes, first, first_v, part, reinterpret_cast<ia::EstimateOut*>(d_out),
-                         nullptr, nullptr, 0, 0.0, nullptr, nullptr, 0, nullptr, s);
+  ia::EvView vw = single_view(0);
+  vw.k = 1;
+  vw.part_stride = n_part * ia::kEstQ;
+  hipLaunchKernelGGL(ia::k_est_partial, dim3(n_part, 1), dim3(ia::kWG), 0, s, par, sh, d_votes, first, first_v, part,
+                     vw, nullptr);
+  hipLaunchKernelGGL(ia::k_est_final, dim3(1, 1), dim3(ia::kWG), 0, s, part, n_part, first, first_v,
+                     reinterpret_cast<ia::EstimateOut*>(d_out), nullptr, nullptr, vw, 0.0, nullptr, nullptr, nullptr);
+  IA_HIP(c, hipGetLastError());
+  return IA_OK;
 }
 
 ia_status ia_find_helices(ia_ctx* c, const ia_hit* d_hits, const int32_t* h_off, int32_t n_events,
@@ -481,7 +564,11 @@ ia_status ia_find_helices(ia_ctx* c, const ia_hit* d_hits, const int32_t* h_off,
   for (int j = 0; j < 5; ++j)
     if (!(sc->range.lo[j] <= sc->range.hi[j])) return fail(c, IA_ERR_INVALID, "range dimension %d: lo > hi", j);
   for (int l = 0; l <= sc->n_refine; ++l)
-    if (sc->prec[l] != IA_FP64) return fail(c, IA_ERR_UNSUPPORTED, "precision %d at level %d", sc->prec[l], l);
+    if (sc->prec[l] != IA_FP64 && sc->prec[l] != IA_FP32)
+      return fail(c, IA_ERR_INVALID, "precision %d at level %d", sc->prec[l], l);
+  if (!(sc->fp32_slack >= 0.0 && sc->fp32_slack <= 1e-3))
+    return fail(c, IA_ERR_INVALID, "fp32_slack %g outside [0, 1e-3]", sc->fp32_slack);
+  const float slack32 = ia::ru32(sc->fp32_slack);
   int32_t max_hits = 0;
   for (int32_t e = 0; e < n_events; ++e) {
     const int32_t n = h_off[e + 1] - h_off[e];
@@ -489,67 +576,101 @@ ia_status ia_find_helices(ia_ctx* c, const ia_hit* d_hits, const int32_t* h_off,
     max_hits = std::max(max_hits, n);
   }
   if (max_hits > 0 && !d_hits) return fail(c, IA_ERR_INVALID, "d_hits is NULL");
-  Shape sh0, shr;
-  if (!make_shape(sc->bins, 1, &sh0)) return fail(c, IA_ERR_OVERFLOW, "level-0 grid exceeds 2^31 - 1 boxes");
-  if (!make_shape(sc->split, sc->top_k, &shr)) return fail(c, IA_ERR_OVERFLOW, "refinement level too large");
-  if (sh0.n_boxes > kMaxEstimateBoxes || shr.n_boxes > kMaxEstimateBoxes)
+  SchedShapes S;
+  if (!sched_shapes(sc, &S)) return fail(c, IA_ERR_OVERFLOW, "a level exceeds 2^31 - 1 boxes");
+  if (S.max_boxes > kMaxEstimateBoxes)
     return fail(c, IA_ERR_OVERFLOW, "a level exceeds %lld boxes", static_cast<long long>(kMaxEstimateBoxes));
   IA_HIP(c, hipSetDevice(c->device));
   const int32_t K = sc->top_k;
-  const int64_t nt0 = int64_t(sh0.n_parents) * sh0.m012, ntr = int64_t(shr.n_parents) * shr.m012;
-  FindLayout L;
-  layout_find(std::max<int64_t>(sh0.n_boxes, shr.n_boxes), std::max(nt0, ntr), K, max_hits, &L);
-  if (L.total > c->arena_bytes)
-    return fail(c, IA_ERR_NOMEM, "scratch too small: need %zu bytes, have %zu", L.total, c->arena_bytes);
-  char* a = c->arena;
-  HitRec* recs = reinterpret_cast<HitRec*>(a + L.recs);
-  uint16_t* votes = reinterpret_cast<uint16_t*>(a + L.votes);
-  uint32_t* hist = reinterpret_cast<uint32_t*>(a + L.hist);
-  BoxD* selA = reinterpret_cast<BoxD*>(a + L.selA);
-  BoxD* selB = reinterpret_cast<BoxD*>(a + L.selB);
-  BoxD* range = reinterpret_cast<BoxD*>(a + L.range);
-  int64_t* sel_idx = reinterpret_cast<int64_t*>(a + L.sel_idx);
-  uint16_t* sel_v = reinterpret_cast<uint16_t*>(a + L.sel_v);
-  EventState* ev = reinterpret_cast<EventState*>(a + L.ev);
-  double* part = reinterpret_cast<double*>(a + L.part);
-  uint8_t* flags = reinterpret_cast<uint8_t*>(a + L.flags);
-  int32_t* wg_max = reinterpret_cast<int32_t*>(a + L.wg_max);
+  // events per chunk: as many as the arena holds
+  FindLayout L1;
+  layout_find(S.max_boxes, S.max_triples, K, max_hits, 1, max_hits, &L1);
+  if (L1.total > c->arena_bytes)
+    return fail(c, IA_ERR_NOMEM, "scratch too small: need %zu bytes, have %zu", L1.total, c->arena_bytes);
+  FindLayout L2;
+  layout_find(S.max_boxes, S.max_triples, K, max_hits, 2, 2 * int64_t(max_hits), &L2);
+  const size_t per_event = L2.total - L1.total;
+  int32_t chunk = static_cast<int32_t>(std::min<size_t>(
+      std::max(1, n_events), 1 + (c->arena_bytes - L1.total) / std::max<size_t>(per_event, 1)));
+  chunk = std::max(1, std::min(chunk, std::min(c->max_chunk, 65535)));
   hipStream_t s = as_stream(stream);
   Persistent* ps = persistent(c);
   BoxD rb;
   std::memcpy(&rb, &sc->range, sizeof rb);
-  for (int32_t e = 0; e < n_events; ++e) {
-    const int32_t n = h_off[e + 1] - h_off[e];
-    const int32_t n_bins = n + 1;
-    const double* hits = reinterpret_cast<const double*>(d_hits) + 8 * int64_t(h_off[e]);
-    int32_t* assigned = d_assigned ? d_assigned + h_off[e] : nullptr;
-    ia::HelixOut* out = reinterpret_cast<ia::HelixOut*>(d_out) + int64_t(e) * max_per_event;
-    int32_t* n_out = d_n_out + e;
-    const int32_t pg = std::max(1, (std::max(n, n_bins) + 255) / 256);
-    hipLaunchKernelGGL(ia::k_prep, dim3(pg), dim3(256), 0, s, hits, nullptr, n, recs, hist, n_bins, &ps->status,
+  chunk = std::min(chunk, kOffSlotInts - 1);
+  for (int32_t e0 = 0; e0 < n_events; e0 += chunk) {
+    const int32_t E = std::min(chunk, n_events - e0);
+    int32_t cmax = 0;
+    for (int32_t e = e0; e < e0 + E; ++e) cmax = std::max(cmax, h_off[e + 1] - h_off[e]);
+    const int64_t n_tot = int64_t(h_off[e0 + E]) - h_off[e0];
+    FindLayout L;
+    layout_find(S.max_boxes, S.max_triples, K, cmax, E, n_tot, &L);
+    if (L.total > c->arena_bytes) return fail(c, IA_ERR_NOMEM, "chunk layout exceeds scratch");
+    char* a = c->arena;
+    int32_t* d_off = reinterpret_cast<int32_t*>(a + L.off);
+    HitRec* recs = reinterpret_cast<HitRec*>(a + L.recs);
+    uint16_t* votes = reinterpret_cast<uint16_t*>(a + L.votes);
+    uint32_t* hist = reinterpret_cast<uint32_t*>(a + L.hist);
+    BoxD* selA = reinterpret_cast<BoxD*>(a + L.selA);
+    BoxD* selB = reinterpret_cast<BoxD*>(a + L.selB);
+    BoxD* range = reinterpret_cast<BoxD*>(a + L.range);
+    int64_t* sel_idx = reinterpret_cast<int64_t*>(a + L.sel_idx);
+    uint16_t* sel_v = reinterpret_cast<uint16_t*>(a + L.sel_v);
+    EventState* ev = reinterpret_cast<EventState*>(a + L.ev);
+    double* part = reinterpret_cast<double*>(a + L.part);
+    uint8_t* flags = reinterpret_cast<uint8_t*>(a + L.flags);
+    int32_t* wg_max = reinterpret_cast<int32_t*>(a + L.wg_max);
+    // chunk-relative hit offsets through a pinned slot whose last copy is done
+    const uint32_t slot = c->slot_next++ % kOffSlots;
+    if (c->slot_used[slot]) IA_HIP(c, hipEventSynchronize(c->slot_done[slot]));
+    int32_t* ho = c->pinned + size_t(slot) * kOffSlotInts;
+    for (int32_t e = 0; e <= E; ++e) ho[e] = h_off[e0 + e] - h_off[e0];
+    IA_HIP(c, hipMemcpyAsync(d_off, ho, sizeof(int32_t) * (size_t(E) + 1), hipMemcpyHostToDevice, s));
+    IA_HIP(c, hipEventRecord(c->slot_done[slot], s));
+    c->slot_used[slot] = true;
+    ia::EvView vw{};
+    vw.off = d_off;
+    vw.k = K;
+    vw.flag_stride = L.flag_stride;
+    vw.hist_stride = L.hist_stride;
+    vw.wg_stride = L.wg_stride;
+    vw.part_stride = L.part_stride;
+    vw.max_out = max_per_event;
+    const double* hits = reinterpret_cast<const double*>(d_hits) + 8 * int64_t(h_off[e0]);
+    int32_t* assigned = d_assigned ? d_assigned + h_off[e0] : nullptr;
+    ia::HelixOut* out = reinterpret_cast<ia::HelixOut*>(d_out) + int64_t(e0) * max_per_event;
+    int32_t* n_out = d_n_out + e0;
+    const int32_t pg = std::max(1, (cmax + 2 + 255) / 256);
+    hipLaunchKernelGGL(ia::k_prep, dim3(pg, E), dim3(256), 0, s, hits, nullptr, vw, recs, hist, &ps->status,
                        &ps->n_bad, ev, n_out, range, rb, assigned);
     for (int32_t pass = 0; pass < std::min(sc->n_helix_max, max_per_event); ++pass) {
       const BoxD* par = range;
-      Shape sh = sh0;
+      Shape sh = S.sh0;
       BoxD* sel = selA;
+      vw.par_stride = 0;
       for (int32_t lev = 0; lev <= sc->n_refine; ++lev) {
-        const uint8_t* fl = launch_filter(c, recs, n, par, sh, flags, L.flag_cap, ev, s);
+        const bool f32 = sc->prec[lev] == IA_FP32;
+        const uint8_t* fl = launch_filter(c, recs, vw, E, cmax, par, sh, flags, ev, s, f32, slack32);
         int32_t bx = 0;
-        ia_status st = launch_vote(c, recs, n, par, sh, votes, hist, n_bins, ev, fl, wg_max, s, &bx);
+        ia_status st = launch_vote(c, recs, vw, E, par, sh, votes, hist, ev, fl, wg_max, s, f32, slack32, &bx);
         if (st != IA_OK) return st;
         const uint32_t n_wg = (sh.n_boxes + bx - 1) / bx;
-        hipLaunchKernelGGL(ia::k_select_wg, dim3(1), dim3(ia::kWG), 0, s, votes, sh.n_boxes, hist, n_bins, K, wg_max,
-                           n_wg, bx, par, sh, sel, sel_idx, sel_v, ev, lev == 0 ? std::max(sc->v_min, 0) : 0);
+        hipLaunchKernelGGL(ia::k_select_wg, dim3(1, E), dim3(ia::kWG), 0, s, votes, vw, hist, wg_max, n_wg, bx, par,
+                           sh, sel, sel_idx, sel_v, ev, lev == 0 ? std::max(sc->v_min, 0) : 0);
         IA_HIP(c, hipGetLastError());
         if (lev == sc->n_refine) break;
         const int32_t k_eff = static_cast<int32_t>(std::min<int64_t>(K, sh.n_boxes));
         if (!make_shape(sc->split, k_eff, &sh)) return fail(c, IA_ERR_OVERFLOW, "split too large");
         par = sel;
+        vw.par_stride = K;
         sel = (sel == selA) ? selB : selA;
       }
-      ia_status st = launch_estimate(c, par, sh, votes, sel, sel_v, part, nullptr, ev, recs, n, sc->hitfind_scale,
-                                     assigned, out, max_per_event, n_out, s);
-      if (st != IA_OK) return st;
+      const int32_t n_part = est_parts(sh.n_boxes);
+      hipLaunchKernelGGL(ia::k_est_partial, dim3(n_part, E), dim3(ia::kWG), 0, s, par, sh, votes, sel, sel_v, part, vw,
+                         ev);
+      hipLaunchKernelGGL(ia::k_est_final, dim3(1, E), dim3(ia::kWG), 0, s, part, n_part, sel, sel_v,
+                         static_cast<ia::EstimateOut*>(nullptr), ev, recs, vw, sc->hitfind_scale, assigned, out, n_out);
+      IA_HIP(c, hipGetLastError());
     }
   }
   return IA_OK;

@@ -178,4 +178,65 @@ IA_HD Iv sin_encl(double a, double b) {
 // enclosure of cos over [a, b] as sin over [a + pi/2, b + pi/2]
 IA_HD Iv cos_encl(double a, double b) { return sin_encl(wdn(a + kPio2), wup(b + kPio2Up)); }
 
+// ---------------------------------------------------------------------------
+// FP32 levels.  Outward FP32 rounding widens by |x| 2^-23 + 2^-149 (at least
+// one FP32 ulp); FP64 values enter FP32 intervals rounded outward
+// (rd32 / ru32) and FP32 point arithmetic rounded to nearest.
+struct Iv32 { float lo, hi; };
+
+IA_HD float next_down32(float f) {
+  if (f == 0.0f) return -0x1p-149f;
+  uint32_t u = __builtin_bit_cast(uint32_t, f);
+  u = f > 0.0f ? u - 1u : u + 1u;
+  return __builtin_bit_cast(float, u);
+}
+IA_HD float next_up32(float f) { return -next_down32(-f); }
+// largest FP32 <= x, smallest FP32 >= x
+IA_HD float rd32(double x) {
+  float f = static_cast<float>(x);
+  return static_cast<double>(f) > x ? next_down32(f) : f;
+}
+IA_HD float ru32(double x) {
+  float f = static_cast<float>(x);
+  return static_cast<double>(f) < x ? next_up32(f) : f;
+}
+IA_HD float wdn32(float x) { return x - fmaf(fabsf(x), 0x1p-23f, 0x1p-149f); }
+IA_HD float wup32(float x) { return x + fmaf(fabsf(x), 0x1p-23f, 0x1p-149f); }
+
+IA_HD Iv32 iadd32(Iv32 a, Iv32 b) { return {wdn32(a.lo + b.lo), wup32(a.hi + b.hi)}; }
+IA_HD Iv32 isub32(Iv32 a, Iv32 b) { return {wdn32(a.lo - b.hi), wup32(a.hi - b.lo)}; }
+IA_HD Iv32 imul32(Iv32 a, Iv32 b) {
+  float p1 = a.lo * b.lo, p2 = a.lo * b.hi, p3 = a.hi * b.lo, p4 = a.hi * b.hi;
+  return {wdn32(fminf(fminf(p1, p2), fminf(p3, p4))), wup32(fmaxf(fmaxf(p1, p2), fmaxf(p3, p4)))};
+}
+IA_HD Iv32 isqr32(Iv32 a) {
+  float l2 = a.lo * a.lo, h2 = a.hi * a.hi;
+  if (a.lo <= 0.0f && a.hi >= 0.0f) return {0.0f, wup32(fmaxf(l2, h2))};
+  return {wdn32(fminf(l2, h2)), wup32(fmaxf(l2, h2))};
+}
+IA_HD Iv32 itwice32(Iv32 a) { return {2.0f * a.lo, 2.0f * a.hi}; }
+IA_HD Iv32 to32(Iv a) { return {rd32(a.lo), ru32(a.hi)}; }
+
+// sin and cos for |x| <= 1: Taylor polynomials of degree 11 and 12 (first
+// omitted terms below 2e-10), Horner with fused multiply-adds
+IA_HD float sin1_32(float x) {
+  float z = x * x;
+  float p = 1.0f / 39916800.0f;
+  p = fmaf(p, z, -1.0f / 362880.0f);
+  p = fmaf(p, z, 1.0f / 5040.0f);
+  p = fmaf(p, z, -1.0f / 120.0f);
+  p = fmaf(p, z, 1.0f / 6.0f);
+  return fmaf(-(x * z), p, x);
+}
+IA_HD float cos1_32(float x) {
+  float z = x * x;
+  float q = 1.0f / 479001600.0f;
+  q = fmaf(q, z, -1.0f / 3628800.0f);
+  q = fmaf(q, z, 1.0f / 40320.0f);
+  q = fmaf(q, z, -1.0f / 720.0f);
+  q = fmaf(q, z, 1.0f / 24.0f);
+  q = fmaf(q, z, -0.5f);
+  return fmaf(z, q, 1.0f);
+}
+
 }  // namespace ia

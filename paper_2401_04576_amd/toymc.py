@@ -249,6 +249,113 @@ def helix_hits(p, chamber=CHAMBER, second=False):
     return hits
 
 
+# --------------------------------------------------------------------------
+# vectorised closest approach: all layers and candidate wires of a helix
+# --------------------------------------------------------------------------
+def _xyz(p, s):
+    d0, phi0, kappa, z0, tanl = p
+    R = 1.0 / kappa
+    th = phi0 + kappa * s
+    return (-(R + d0) * np.sin(phi0) + R * np.sin(th), (R + d0) * np.cos(phi0) - R * np.cos(th),
+            z0 + tanl * s)
+
+
+def crossing_arcs(p, radii):
+    """Smallest s > 0 reaching each radius (NaN if never); bisection, 200 steps."""
+    radii = np.asarray(radii, dtype=float)
+    R = 1.0 / p[2]
+    s_hi = np.full(radii.shape, np.pi * abs(R))
+    x, y, _ = _xyz(p, s_hi)
+    ok = (np.hypot(x, y) >= radii) & (abs(p[0]) <= radii)
+    lo, hi = np.zeros(radii.shape), s_hi.copy()
+    for _ in range(200):
+        mid = 0.5 * (lo + hi)
+        x, y, _ = _xyz(p, mid)
+        inside = np.hypot(x, y) < radii
+        lo = np.where(inside, mid, lo)
+        hi = np.where(inside, hi, mid)
+    return np.where(ok, 0.5 * (lo + hi), np.nan)
+
+
+def _perp(p, s, px, py, tx, ty):
+    x, y, z = _xyz(p, s)
+    n = np.sqrt(tx * tx + ty * ty + 1.0)
+    wx, wy, wz = tx / n, ty / n, 1.0 / n
+    gx, gy, gz = x - px, y - py, z
+    gw = gx * wx + gy * wy + gz * wz
+    qx, qy, qz = gx - gw * wx, gy - gw * wy, gz - gw * wz
+    return np.sqrt(qx * qx + qy * qy + qz * qz), gw * wz, (gx, gy, gz), (wx, wy, wz), gw
+
+
+def closest_approach_vec(p, px, py, tx, ty, s_guess, window=0.25):
+    """Vectorised golden-section search (100 steps) on the squared helix-line
+    distance over [s_guess - window, s_guess + window], then Newton steps on
+    its derivative; returns (s*, d*, wire z*)."""
+    kappa = p[2]
+    a = np.maximum(0.0, s_guess - window)
+    b = s_guess + window
+    g = (np.sqrt(5.0) - 1.0) / 2.0
+    c, d = b - g * (b - a), a + g * (b - a)
+    fc = _perp(p, c, px, py, tx, ty)[0] ** 2
+    fd = _perp(p, d, px, py, tx, ty)[0] ** 2
+    for _ in range(100):
+        left = fc < fd                      # the minimum lies in [a, d]
+        a, b = np.where(left, a, c), np.where(left, d, b)
+        c_new = np.where(left, b - g * (b - a), d)
+        d_new = np.where(left, c, a + g * (b - a))
+        f_new = _perp(p, np.where(left, c_new, d_new), px, py, tx, ty)[0] ** 2
+        fc, fd = np.where(left, f_new, fd), np.where(left, fc, f_new)
+        c, d = c_new, d_new
+    s = 0.5 * (a + b)
+    for _ in range(8):
+        _, _, (gx, gy, gz), (wx, wy, wz), gw = _perp(p, s, px, py, tx, ty)
+        th = p[1] + kappa * s
+        T0, T1, T2 = np.cos(th), np.sin(th), p[4]
+        A0, A1 = -kappa * np.sin(th), kappa * np.cos(th)
+        Tw = T0 * wx + T1 * wy + T2 * wz
+        A2w = A0 * wx + A1 * wy
+        d1 = 2.0 * (gx * T0 + gy * T1 + gz * T2) - 2.0 * gw * Tw
+        d2 = 2.0 * (T0 * T0 + T1 * T1 + T2 * T2 + gx * A0 + gy * A1) - 2.0 * (Tw * Tw + gw * A2w)
+        good = d2 > 0.0
+        s = s - np.where(good, d1 / np.where(good, d2, 1.0), 0.0)
+    dist, zw = _perp(p, s, px, py, tx, ty)[:2]
+    return s, dist, zw
+
+
+def helix_hits_fast(p, chamber=CHAMBER, second=False, n_near=2):
+    """helix_hits with the closest approaches of all layers and candidate
+    wires computed together."""
+    layers = np.arange(chamber.n_layers)
+    r = chamber.radius(layers)
+    s_c = crossing_arcs(p, r)
+    ok = np.isfinite(s_c)
+    if not ok.any():
+        return []
+    s0 = np.where(ok, s_c, 0.0)
+    x, y, z = _xyz(p, s0)
+    nw = chamber.n_wires(layers)
+    tt = chamber.tan_tau(layers)
+    phc = np.arctan2(y, x) - z * tt / r
+    j0 = np.round(phc * nw / (2.0 * np.pi) - 0.5 * (layers % 2)).astype(np.int64)
+    dj = np.arange(-n_near, n_near + 1)
+    k = dj.size
+    L = np.repeat(layers, k)
+    J = (np.repeat(j0, k) + np.tile(dj, layers.size)) % np.repeat(nw, k)
+    px, py, tx, ty = chamber.wire_geometry(L, J)
+    s_star, d_star, z_star = closest_approach_vec(p, px, py, tx, ty, np.repeat(s0, k))
+    hits = []
+    for layer in layers:
+        if not ok[layer]:
+            continue
+        cands = [(int(J[i]), float(s_star[i]), float(d_star[i]), float(z_star[i]))
+                 for i in range(layer * k, (layer + 1) * k) if abs(z_star[i]) <= chamber.half_length]
+        cands.sort(key=lambda t: t[2])
+        picks = cands[:2] if second else cands[:1]
+        for rank, (j, s, d, zw) in enumerate(picks):
+            hits.append((int(layer), j, d, s, zw, rank))
+    return hits
+
+
 @dataclasses.dataclass
 class Event:
     hits: np.ndarray            # HIT_DTYPE, shape (N,)
@@ -304,7 +411,7 @@ def make_event(rng, n_helix=1, sigma=0.0, noise_frac=0.0, n_hits=None, chamber=C
         hc = float(chamber.half_cell(layer))
         return float(np.clip(d + rng.normal(0.0, sigma), 0.0, hc))
 
-    per_helix = [helix_hits(truth[h], chamber, second=n_hits is not None) for h in range(n_helix)]
+    per_helix = [helix_hits_fast(truth[h], chamber, second=n_hits is not None) for h in range(n_helix)]
     if n_hits is None:
         for h in range(n_helix):
             for (layer, j, d, s, zw, rank) in per_helix[h]:

@@ -29,11 +29,14 @@ static bool make_shape(const int32_t m[5], int64_t n_parents, Shape* sh) {
 
 extern "C" {
 
-// votes of the boxes of a level; stats[0] = stereo (triple, hit) pairs,
-// stats[1] = pairs removed by the pre-filter, stats[2] = stereo (box, hit)
-// evaluations performed
+// votes of the boxes of a level at precision f32 (0: FP64, 1: FP32 with
+// band widening slack); stats[0] = stereo (triple, hit) pairs, stats[1] =
+// pairs removed by the pre-filter, stats[2] = stereo (box, hit) evaluations
+// performed
 int32_t hc_vote_level(const double* hits, int32_t n_hits, const double* parents, int32_t n_parents,
-                      const int32_t split[5], int32_t filter, uint16_t* votes, int64_t* stats) {
+                      const int32_t split[5], int32_t filter, int32_t f32, double slack, uint16_t* votes,
+                      int64_t* stats) {
+  const float slack32 = ru32(slack);
   Shape sh;
   if (!make_shape(split, n_parents, &sh)) return 1;
   std::vector<HitRec> rec(n_hits > 0 ? n_hits : 1);
@@ -61,9 +64,17 @@ int32_t hc_vote_level(const double* hits, int32_t n_hits, const double* parents,
           for (uint32_t l = 0; l < sh.m34; ++l) ++nv[l];
         continue;
       }
+      if (f32 && !(f.R <= kR32Max)) {
+        for (uint32_t l = 0; l < sh.m34; ++l) ++nv[l];
+        continue;
+      }
       const PairQ q = pair_quantities(f, h, G);
       ++n_pairs;
-      if (filter && !triple_may_vote(q, f, h, Zr, Lr)) { ++n_cut; continue; }
+      const bool may = f32 ? triple_may_vote32(q, f, h, Zr, Lr, slack32) : triple_may_vote(q, f, h, Zr, Lr);
+      if (filter && !may) { ++n_cut; continue; }
+      const PairQ32 q32 = pair_q32(q, h, slack32);
+      const float R32 = static_cast<float>(f.R), sig32 = static_cast<float>(f.sig);
+      const Iv32 K32 = to32(f.K);
       for (uint32_t l = 0; l < sh.m34; ++l) {
         const uint32_t k3 = l / sh.m[4], k4 = l % sh.m[4];
         double zlo, zhi, llo, lhi;
@@ -71,8 +82,14 @@ int32_t hc_vote_level(const double* hits, int32_t n_hits, const double* parents,
         child_edge(P[tp].lo[4], P[tp].hi[4], sh.m[4], k4, &llo, &lhi);
         const double z0 = 0.5 * (zlo + zhi), lam = 0.5 * (llo + lhi);
         ++n_evals;
-        if (stereo_vote(q, f.R, f.sig, f.K, z0, lam, lam * f.R, lam * lam, h.tant, h.tant * h.tant, h.d, h.band))
-          ++nv[l];
+        bool v;
+        if (f32) {
+          const float z032 = static_cast<float>(z0), lam32 = static_cast<float>(lam);
+          v = stereo_vote32(q32, R32, sig32, K32, z032, lam32, lam32 * R32, lam32 * lam32);
+        } else {
+          v = stereo_vote(q, f.R, f.sig, f.K, z0, lam, lam * f.R, lam * lam, h.tant, h.tant * h.tant, h.d, h.band);
+        }
+        if (v) ++nv[l];
       }
     }
     const int64_t base = int64_t(tp) * sh.nc + int64_t(tc) * sh.m34;

@@ -231,3 +231,55 @@ def test_deterministic_repeat(ctx):
     a = _gpu_votes(ctx, ev.hits, root, [16] * 5)
     b = _gpu_votes(ctx, ev.hits, root, [16] * 5)
     assert np.array_equal(a, b)
+
+
+def _run_gpu(ctx, events, sched, max_out):
+    torch = _torch()
+    hits = np.concatenate([e.hits for e in events]) if events else np.zeros(0, dtype=toymc.HIT_DTYPE)
+    off = np.concatenate([[0], np.cumsum([e.n_hits for e in events])]).astype(np.int32)
+    raw, n_out, assigned = ia.find_helices(ctx, _dev_hits(hits), off, sched, max_per_event=max_out)
+    torch.cuda.synchronize()
+    hel = ia.decode(raw, ia.HELIX_DTYPE).reshape(max(1, len(events)), max_out)
+    return hel, n_out.cpu().numpy(), assigned.cpu().numpy(), off
+
+
+def test_batch_mix_invariance(ctx):
+    """Each event's result is the same alone, in one batch, and in small
+    batches (uneven hit counts, multi-helix passes, full 16^5 schedule)."""
+    events = [toymc.config_event(4, i) for i in range(10)]
+    sched = ia.Schedule.make(H.LO, H.HI, [16] * 5, n_helix_max=5)
+    hel_b, n_b, ass_b, off = _run_gpu(ctx, events, sched, 5)
+    ctx.set_batch(3)
+    try:
+        hel_c, n_c, ass_c, _ = _run_gpu(ctx, events, sched, 5)
+    finally:
+        ctx.set_batch(65535)
+    assert np.array_equal(n_b, n_c) and np.array_equal(ass_b, ass_c)
+    assert hel_b.tobytes() == hel_c.tobytes()
+    for e, ev in enumerate(events):
+        hel_1, n_1, ass_1, _ = _run_gpu(ctx, [ev], sched, 5)
+        assert n_1[0] == n_b[e]
+        assert hel_1[0, :n_1[0]].tobytes() == hel_b[e, :n_b[e]].tobytes()
+        assert np.array_equal(ass_1[:ev.n_hits], ass_b[off[e]:off[e + 1]])
+
+
+def test_batch_edge_events(ctx):
+    """Empty events, a one-hit event and a large event in one batch match the oracle."""
+    big = toymc.config_event(5, 7)
+    one = toymc.config_event(1, 3)
+    one_hit = type(one)(hits=one.hits[:1], truth=one.truth, owner=one.owner[:1], layer=one.layer[:1],
+                        wire=one.wire[:1], sigma=0.0)
+    empty = type(one)(hits=one.hits[:0], truth=one.truth, owner=one.owner[:0], layer=one.layer[:0],
+                      wire=one.wire[:0], sigma=0.0)
+    events = [empty, one_hit, big, empty, toymc.config_event(2, 9)]
+    kw = dict(bins=[6] * 5, n_refine=2, top_k=8, split=[2] * 5, v_min=10, n_helix_max=3)
+    so = oracle.make_sched(H.LO, H.HI, **kw)
+    sg = ia.Schedule.make(H.LO, H.HI, **kw)
+    hel, n_out, ass, off = _run_gpu(ctx, events, sg, 3)
+    for e, ev in enumerate(events):
+        ref, ref_ass = oracle.find_helices(ev.hits, so, max_out=3)
+        assert n_out[e] == len(ref)
+        for h in range(len(ref)):
+            assert np.array_equal(hel[e, h]["p"], ref[h]["p"]) and np.array_equal(hel[e, h]["err"], ref[h]["err"])
+            assert hel[e, h]["n_assigned"] == ref[h]["n_assigned"]
+        assert np.array_equal(ass[off[e]:off[e + 1]], ref_ass)

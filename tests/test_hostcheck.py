@@ -45,3 +45,23 @@ def test_prefilter_effect_level0():
     print(f"pre-filter removes {frac:.1%} of stereo (triple, hit) pairs; "
           f"stereo box evaluations {s_on[2]} vs {s_off[2]}")
     assert frac > 0.3
+
+
+SLACK = 1e-6
+
+
+@pytest.mark.parametrize("cfg,ev_i", [(1, 1), (2, 0), (5, 4)])
+def test_device_fp32_arithmetic_matches_oracle(orc, cfg, ev_i):
+    """The library's FP32 vote arithmetic (CPU build) equals the oracle's FP32
+    votes on a level-0 grid and a refinement level, pre-filter on and off."""
+    ev = toymc.config_event(cfg, ev_i)
+    root = orc.make_box(H.LO, H.HI)
+    ref = orc.vote_level(ev.hits, root, [10] * 5, prec=orc.FP32, slack=SLACK)
+    for filt in (False, True):
+        got, _ = hostcheck.vote_level(ev.hits, root, [10] * 5, filt, f32=True, slack=SLACK)
+        assert np.array_equal(got, ref), (filt, np.flatnonzero(got != ref)[:10])
+    top = np.argsort(-ref.astype(np.int64), kind="stable")[:6]
+    parents = np.array([orc.box_child(root, [10] * 5, int(b)) for b in top])
+    ref1 = orc.vote_level(ev.hits, parents, [4] * 5, prec=orc.FP32, slack=SLACK)
+    got1, stats = hostcheck.vote_level(ev.hits, parents, [4] * 5, True, f32=True, slack=SLACK)
+    assert np.array_equal(got1, ref1)
