@@ -311,19 +311,53 @@ IA_HD bool e_enclosure(const PairQ& q, double R, double sig, double tt, double t
   return e_enclosure_dom(q, R, sig, tt, t2, dS, Z, L, out, &eps, &disc, &a);
 }
 
-// false only when no box of the triple can get this stereo hit's vote
-IA_HD bool triple_may_vote(const PairQ& q, const Frame& f, const HitRec& h, Iv Z, Iv L) {
+// Inclusion: a proof that the per-box test votes for every point value e
+// in [E1, E2].  The per-box test (h_contains0, or its FP32 form) votes when
+// its interval T = 2E + K E^2, E = [e - b, e + b] rounded outward, has
+// T.hi >= 2 G.lo and T.lo <= 2 G.hi.  Outward rounding only widens, so
+// T.hi >= 2(e + b) + K.hi s1(e) and T.lo <= 2(e - b) + K.lo s2(e), where s1
+// (s2) is the largest square over E when K.hi >= 0 (K.lo < 0) and the
+// smallest otherwise.  Both bounds increase with e when
+// max|K| (max|e| + b) < 1/2, so checking the first at E1 and the second at
+// E2, with outward-rounded arithmetic, covers the whole range.
+IA_HD bool votes_everywhere(Iv G, Iv K, double E1, double E2, double b) {
+  const double emax = fmax(fabs(E1), fabs(E2));
+  if (!(fmax(fabs(K.lo), fabs(K.hi)) * (emax + b) < 0.5)) return false;
+  auto sq_big = [&](double e) { return isqr(iadd(ipt(fabs(e)), ipt(b))); };
+  auto sq_small = [&](double e) {
+    const Iv d = isub(ipt(fabs(e)), ipt(b));
+    return isqr(Iv{fmax(d.lo, 0.0), fmax(d.hi, 0.0)});
+  };
+  const Iv f = iadd(itwice(iadd(ipt(E1), ipt(b))), imul(ipt(K.hi), K.hi >= 0.0 ? sq_big(E1) : sq_small(E1)));
+  const Iv g = iadd(itwice(isub(ipt(E2), ipt(b))), imul(ipt(K.lo), K.lo >= 0.0 ? sq_small(E2) : sq_big(E2)));
+  return f.lo >= 2.0 * G.lo && g.hi <= 2.0 * G.hi;
+}
+
+// Class of a (triple, stereo hit) pair at an FP64 level: 0 when no box of
+// the triple can get the hit's vote, 1 when every box gets it, 2 when the
+// boxes must be evaluated one by one.  Class 1 needs, for one drift sign,
+// a well-conditioned point evaluation everywhere on the rectangle (the
+// discriminant of d^Ax above A^2 / 4) and the inclusion proof above over
+// the enclosure of e.
+IA_HD int triple_vote_class(const PairQ& q, const Frame& f, const HitRec& h, Iv Z, Iv L) {
   const Iv G = {q.Glo, q.Ghi};
   const double tt = h.tant, t2 = tt * tt;
+  bool may = false;
   for (int si = 0; si < 2; ++si) {
     const double dS = si == 0 ? h.d : -h.d;
-    Iv E;
-    if (!e_enclosure(q, f.R, f.sig, tt, t2, dS, Z, L, &E)) return true;
+    Iv E, EPS, DISC, A;
+    if (!e_enclosure_dom(q, f.R, f.sig, tt, t2, dS, Z, L, &E, &EPS, &DISC, &A)) { may = true; continue; }
+    if (DISC.lo > 0.25 * A.lo * A.lo && A.lo > 0.0 && votes_everywhere(G, f.K, E.lo, E.hi, h.band)) return 1;
     const Iv Eb = {wdn(E.lo - h.band), wup(E.hi + h.band)};
     const Iv Hb = isub(itwice(G), iadd(itwice(Eb), imul(f.K, isqr(Eb))));
-    if (Hb.lo <= 0.0 && 0.0 <= Hb.hi) return true;
+    if (Hb.lo <= 0.0 && 0.0 <= Hb.hi) may = true;
   }
-  return false;
+  return may ? 2 : 0;
+}
+
+// false only when no box of the triple can get this stereo hit's vote
+IA_HD bool triple_may_vote(const PairQ& q, const Frame& f, const HitRec& h, Iv Z, Iv L) {
+  return triple_vote_class(q, f, h, Z, L) != 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -393,29 +427,37 @@ IA_HD bool stereo_vote32(const PairQ32& q, float R, float sig, Iv32 K, float z0,
   return vote;
 }
 
-// Pre-filter of a (triple, stereo hit) pair at an FP32 level: false only
-// when no box of the triple can get the FP32 vote.  The enclosure of e over
-// the centre rectangle (e_enclosure) must also show that every box stays in
-// the FP32 domain (|eps| <= 0.99, a discriminant above 1e-3 A^2, far beyond
-// FP32 rounding); its FP32 image is widened by band + 2 slack (one slack for
-// |e32 - e64|, one to spare for FP32 rounding) before the same interval test.
-IA_HD bool triple_may_vote32(const PairQ& q, const Frame& f, const HitRec& h, Iv Z, Iv L, float slack32) {
-  if (!(f.R <= kR32Max)) return true;
+// Class (0, 1, 2 as in triple_vote_class) of a (triple, stereo hit) pair at
+// an FP32 level.  Exclusion: the enclosure of e over the centre rectangle
+// must show that every box stays in the FP32 domain (|eps| <= 0.99, a
+// discriminant above 1e-3 A^2, far beyond FP32 rounding); its FP32 image is
+// widened by band + 2 slack (one slack for |e32 - e64|, one to spare for
+// FP32 rounding) before the FP32 interval test.  Inclusion: the proof of
+// votes_everywhere holds for FP32 outward rounding as well; it is applied to
+// the FP32 G, K and band (exact in FP64) over [E1 - slack, E2 + slack],
+// which holds every box's e32 (a box outside the FP32 domain votes anyway).
+IA_HD int triple_vote_class32(const PairQ& q, const Frame& f, const HitRec& h, Iv Z, Iv L, float slack32) {
+  if (!(f.R <= kR32Max)) return 1;
   const Iv32 G = to32(Iv{q.Glo, q.Ghi});
   const Iv32 K = to32(f.K);
+  const float bs = wup32(ru32(h.band) + slack32);
   const float bs2 = wup32(ru32(h.band) + 2.0f * slack32);
   const double tt = h.tant, t2 = tt * tt;
+  bool may = false;
   for (int si = 0; si < 2; ++si) {
     const double dS = si == 0 ? h.d : -h.d;
     Iv E, EPS, DISC, A;
-    if (!e_enclosure_dom(q, f.R, f.sig, tt, t2, dS, Z, L, &E, &EPS, &DISC, &A)) return true;
-    if (!(fabs(EPS.lo) <= 0.99 && fabs(EPS.hi) <= 0.99)) return true;
-    if (!(DISC.lo > 1e-3 * A.hi * A.hi)) return true;
+    if (!e_enclosure_dom(q, f.R, f.sig, tt, t2, dS, Z, L, &E, &EPS, &DISC, &A)) { may = true; continue; }
+    if (DISC.lo > 0.25 * A.lo * A.lo && A.lo > 0.0 &&
+        votes_everywhere(Iv{G.lo, G.hi}, Iv{K.lo, K.hi}, wdn(E.lo - slack32), wup(E.hi + slack32), bs))
+      return 1;
+    if (!(fabs(EPS.lo) <= 0.99 && fabs(EPS.hi) <= 0.99)) { may = true; continue; }
+    if (!(DISC.lo > 1e-3 * A.hi * A.hi)) { may = true; continue; }
     const Iv32 Eb = {wdn32(rd32(E.lo) - bs2), wup32(ru32(E.hi) + bs2)};
     const Iv32 Hb = isub32(itwice32(G), iadd32(itwice32(Eb), imul32(K, isqr32(Eb))));
-    if (Hb.lo <= 0.0f && 0.0f <= Hb.hi) return true;
+    if (Hb.lo <= 0.0f && 0.0f <= Hb.hi) may = true;
   }
-  return false;
+  return may ? 2 : 0;
 }
 
 // (z0, tanl) centre ranges of the boxes of one parent
@@ -541,8 +583,8 @@ __global__ void __launch_bounds__(kWG) k_pair_filter(const HitRec* __restrict__ 
       const PairQ q = pair_quantities(f, h, G);
       Iv Zr, Lr;
       centre_ranges(TP, sh.m, &Zr, &Lr);
-      const bool may = f32 ? triple_may_vote32(q, f, h, Zr, Lr, slack32) : triple_may_vote(q, f, h, Zr, Lr);
-      fl = may ? 2 : 0;
+      fl = static_cast<uint8_t>(f32 ? triple_vote_class32(q, f, h, Zr, Lr, slack32)
+                                    : triple_vote_class(q, f, h, Zr, Lr));
     }
   }
   flags[i] = fl;

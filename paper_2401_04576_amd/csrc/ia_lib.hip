@@ -163,10 +163,11 @@ int32_t vote_tile(const ia_ctx* c, uint32_t n_boxes) {
   return 128;
 }
 
-// the (triple, hit) pre-pass pays when many boxes share a triple
+// the (triple, hit) pre-pass pays when several boxes share a triple: its
+// classes remove the pairs that vote nowhere or everywhere in the triple
 int32_t use_filter(const ia_ctx* c, const Shape& sh) {
   if (c->filter_mode >= 0) return c->filter_mode;
-  return sh.m34 >= 64 ? 1 : 0;
+  return sh.m34 >= 8 ? 1 : 0;
 }
 
 ia::EvView single_view(int32_t n_hits) {

@@ -47,7 +47,7 @@ def vote_level(hits, parents, split, filter_on, f32=False, slack=1e-6):
     sp = np.ascontiguousarray(split, dtype=np.int32)
     nb = pa.shape[0] * int(np.prod(sp.astype(np.int64)))
     votes = np.zeros(nb, dtype=np.uint16)
-    stats = np.zeros(3, dtype=np.int64)
+    stats = np.zeros(6, dtype=np.int64)
     rc = lib().hc_vote_level(h.ctypes.data, h.shape[0], pa.ctypes.data, pa.shape[0], sp.ctypes.data,
                              1 if filter_on else 0, 1 if f32 else 0, float(slack), votes.ctypes.data,
                              stats.ctypes.data)

@@ -32,7 +32,9 @@ extern "C" {
 // votes of the boxes of a level at precision f32 (0: FP64, 1: FP32 with
 // band widening slack); stats[0] = stereo (triple, hit) pairs, stats[1] =
 // pairs removed by the pre-filter, stats[2] = stereo (box, hit) evaluations
-// performed
+// performed, stats[3] = those that voted, stats[4] = evaluated pairs voting
+// in every box of their triple, stats[5] = pairs the pre-filter proved to
+// vote in every box (no evaluation)
 int32_t hc_vote_level(const double* hits, int32_t n_hits, const double* parents, int32_t n_parents,
                       const int32_t split[5], int32_t filter, int32_t f32, double slack, uint16_t* votes,
                       int64_t* stats) {
@@ -46,8 +48,8 @@ int32_t hc_vote_level(const double* hits, int32_t n_hits, const double* parents,
   }
   const BoxD* P = reinterpret_cast<const BoxD*>(parents);
   const int64_t n_triples = int64_t(n_parents) * sh.m012;
-  int64_t n_pairs = 0, n_cut = 0, n_evals = 0;
-#pragma omp parallel for schedule(dynamic, 4) reduction(+ : n_pairs, n_cut, n_evals)
+  int64_t n_pairs = 0, n_cut = 0, n_evals = 0, n_yes = 0, n_full = 0, n_incl = 0;
+#pragma omp parallel for schedule(dynamic, 4) reduction(+ : n_pairs, n_cut, n_evals, n_yes, n_full, n_incl)
   for (int64_t t = 0; t < n_triples; ++t) {
     const uint32_t tp = static_cast<uint32_t>(t / sh.m012), tc = static_cast<uint32_t>(t % sh.m012);
     const uint32_t t0 = tc / sh.m12, t1 = (tc / sh.m[2]) % sh.m[1], t2 = tc % sh.m[2];
@@ -70,11 +72,17 @@ int32_t hc_vote_level(const double* hits, int32_t n_hits, const double* parents,
       }
       const PairQ q = pair_quantities(f, h, G);
       ++n_pairs;
-      const bool may = f32 ? triple_may_vote32(q, f, h, Zr, Lr, slack32) : triple_may_vote(q, f, h, Zr, Lr);
-      if (filter && !may) { ++n_cut; continue; }
+      const int cls = f32 ? triple_vote_class32(q, f, h, Zr, Lr, slack32) : triple_vote_class(q, f, h, Zr, Lr);
+      if (filter && cls == 0) { ++n_cut; continue; }
+      if (filter && cls == 1) {
+        ++n_incl;
+        for (uint32_t l = 0; l < sh.m34; ++l) ++nv[l];
+        continue;
+      }
       const PairQ32 q32 = pair_q32(q, h, slack32);
       const float R32 = static_cast<float>(f.R), sig32 = static_cast<float>(f.sig);
       const Iv32 K32 = to32(f.K);
+      int64_t yes_here = 0;
       for (uint32_t l = 0; l < sh.m34; ++l) {
         const uint32_t k3 = l / sh.m[4], k4 = l % sh.m[4];
         double zlo, zhi, llo, lhi;
@@ -89,13 +97,17 @@ int32_t hc_vote_level(const double* hits, int32_t n_hits, const double* parents,
         } else {
           v = stereo_vote(q, f.R, f.sig, f.K, z0, lam, lam * f.R, lam * lam, h.tant, h.tant * h.tant, h.d, h.band);
         }
-        if (v) ++nv[l];
+        if (v) { ++nv[l]; ++n_yes; ++yes_here; }
       }
+      if (yes_here == int64_t(sh.m34)) ++n_full;
     }
     const int64_t base = int64_t(tp) * sh.nc + int64_t(tc) * sh.m34;
     for (uint32_t l = 0; l < sh.m34; ++l) votes[base + l] = static_cast<uint16_t>(nv[l]);
   }
-  if (stats) { stats[0] = n_pairs; stats[1] = n_cut; stats[2] = n_evals; }
+  if (stats) {
+    stats[0] = n_pairs; stats[1] = n_cut; stats[2] = n_evals; stats[3] = n_yes; stats[4] = n_full;
+    stats[5] = n_incl;
+  }
   return 0;
 }
 

@@ -1,6 +1,8 @@
 """The HIP library's vote arithmetic, compiled for the CPU (tests/hostcheck),
 against the oracle: identical votes with and without the (triple, hit)
-pre-filter.  A missed vote would show the pre-filter is unsound."""
+pre-filter, whose classes skip the per-box evaluation of pairs proved to
+vote nowhere or everywhere in a triple.  A missed or extra vote would show
+a class proof is unsound."""
 import numpy as np
 import pytest
 
@@ -65,3 +67,21 @@ def test_device_fp32_arithmetic_matches_oracle(orc, cfg, ev_i):
     ref1 = orc.vote_level(ev.hits, parents, [4] * 5, prec=orc.FP32, slack=SLACK)
     got1, stats = hostcheck.vote_level(ev.hits, parents, [4] * 5, True, f32=True, slack=SLACK)
     assert np.array_equal(got1, ref1)
+
+
+@pytest.mark.parametrize("f32", [False, True])
+def test_inclusion_proof_catches_full_vote_pairs(orc, f32):
+    """On the measured workload's level 0 and first refinement level, the
+    pairs left for evaluation that still vote in every box are a small
+    fraction of those the inclusion proof classified."""
+    ev = toymc.config_event(2, 0)
+    root = orc.make_box(H.LO, H.HI)
+    prec = orc.FP32 if f32 else orc.FP64
+    v, st = hostcheck.vote_level(ev.hits, root, [16] * 5, True, f32=f32, slack=SLACK)
+    assert np.array_equal(v, orc.vote_level(ev.hits, root, [16] * 5, prec=prec, slack=SLACK))
+    assert st[5] > 0 and st[4] < 0.05 * st[5]
+    top = np.argsort(-v.astype(np.int64), kind="stable")[:32]
+    parents = np.array([orc.box_child(root, [16] * 5, int(b)) for b in top])
+    v1, st1 = hostcheck.vote_level(ev.hits, parents, [4] * 5, True, f32=f32, slack=SLACK)
+    assert np.array_equal(v1, orc.vote_level(ev.hits, parents, [4] * 5, prec=prec, slack=SLACK))
+    assert st1[5] > 10 * st1[2] / 16
