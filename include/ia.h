@@ -146,12 +146,22 @@ ia_status ia_ctx_set_fp32_slack(ia_ctx *ctx, double slack);
  * by level size.  Results do not depend on it. */
 ia_status ia_ctx_set_vote_tile(ia_ctx *ctx, int32_t boxes_per_workgroup);
 
-/* The vote kernel's (triple, hit) pre-filter: an interval enclosure of the
+/* The (triple, hit) classification's proofs: an interval enclosure of the
  * stereo drift over every box centre sharing (d0, phi0, kappa) proves that a
- * hit cannot vote there, and its per-box evaluations are skipped.  mode -1
- * chooses by level shape (the default), 0 disables, 1 enables.  Results do
- * not depend on it. */
+ * stereo hit votes in none or in all of those boxes, and their per-box
+ * evaluations are skipped.  mode -1 (the default) and 1 enable, 0 disables
+ * (every stereo pair is then evaluated per box).  Results do not depend on
+ * it. */
 ia_status ia_ctx_set_prefilter(ia_ctx *ctx, int32_t mode);
+
+/* Pruning in ia_find_helices (enabled by default): per level, each triple's
+ * votes are bounded from below by its pairs proved to vote everywhere and
+ * from above by adding the pairs left undecided; a triple whose upper bound
+ * is below the k-th largest lower bound over boxes holds no box the
+ * selection can take, so its boxes are not evaluated.  Selections,
+ * estimates and helices do not depend on it; only the internal vote array of
+ * a level differs (pruned boxes hold their lower bound). */
+ia_status ia_ctx_set_pruning(ia_ctx *ctx, int32_t enable);
 
 /* ia_find_helices launches its events in batches: every kernel of a level
  * covers all events of a batch (one event per grid row).  A batch holds as
@@ -174,7 +184,9 @@ size_t ia_ctx_scratch_needed(const ia_schedule *sched, int32_t max_hits);
  *             context's slack; its votes contain the IA_FP64 votes
  *   d_votes   n_parents * prod(split) uint16, written: number of active,
  *             well-formed hits voting for each box
- * Scratch: 96 bytes per hit. */
+ * Scratch: 96 bytes per hit, and n_parents * prod(split[0..2]) * (n_hits + 8)
+ * bytes of (triple, hit) classes and per-triple bounds (IA_ERR_NOMEM when the
+ * context's scratch cannot hold them). */
 ia_status ia_vote_level(ia_ctx *ctx, const ia_hit *d_hits, int32_t n_hits, const uint8_t *d_active,
                         const ia_box *d_parents, int32_t n_parents, const int32_t split[5],
                         ia_precision prec, uint16_t *d_votes, void *stream);

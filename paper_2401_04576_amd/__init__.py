@@ -104,6 +104,8 @@ def load():
     L.ia_ctx_clear_status.argtypes = [P]
     L.ia_ctx_set_batch.restype = i32
     L.ia_ctx_set_batch.argtypes = [P, i32]
+    L.ia_ctx_set_pruning.restype = i32
+    L.ia_ctx_set_pruning.argtypes = [P, i32]
     L.ia_ctx_set_prefilter.restype = i32
     L.ia_ctx_set_prefilter.argtypes = [P, i32]
     L.ia_ctx_set_vote_tile.restype = i32
@@ -202,8 +204,12 @@ class Context:
         """Maximum events per batched launch of find_helices."""
         self._check(self._L.ia_ctx_set_batch(self._h, int(max_events)))
 
+    def set_pruning(self, enable=True):
+        """find_helices: skip triples whose vote upper bound cannot reach the selection."""
+        self._check(self._L.ia_ctx_set_pruning(self._h, 1 if enable else 0))
+
     def set_prefilter(self, mode=-1):
-        """(triple, hit) pre-filter: -1 automatic, 0 off, 1 on."""
+        """(triple, hit) classification proofs: -1 or 1 on, 0 off."""
         self._check(self._L.ia_ctx_set_prefilter(self._h, int(mode)))
 
     def set_profiling(self, enable=True):

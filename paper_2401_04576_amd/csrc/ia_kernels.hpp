@@ -53,7 +53,8 @@ struct EventState {
   int32_t k_sel;                // boxes selected by the last selection
   int32_t n_assigned;           // hits assigned by the last hit finding
   int32_t n_argmax;             // size of the max-vote set of the last level
-  int32_t pad[2];
+  int32_t t_prune;              // vote threshold of the current level's pruning (0: none)
+  int32_t pad;
   double p[5], err[5];          // last estimate
 };
 
@@ -67,6 +68,7 @@ struct EvView {
   int32_t k;                    // selection size (stride of the selection arrays)
   int64_t par_stride;           // parent boxes per event (0: one shared list)
   int64_t flag_stride;          // pre-pass flags per event
+  int64_t tri_stride;           // per-triple vote bounds per event
   int32_t hist_stride;          // histogram bins per event
   int32_t wg_stride;            // workgroup maxima per event
   int32_t part_stride;          // estimate chunk sums per event (doubles)
@@ -472,11 +474,13 @@ IA_HD void centre_ranges(const BoxD& P, const uint32_t m[5], Iv* Z, Iv* L) {
 }
 
 // ---------------------------------------------------------------------------
-// hit preparation.  One thread per hit; also clears the vote histogram.  With
-// `ev` set it starts an event: resets the event state, writes the search
-// range box and marks every hit unassigned.
+// hit preparation.  One thread per hit; also clears the vote and lower-bound
+// histograms and the per-triple bounds.  With `ev` set it starts an event:
+// resets the event state, writes the search range box and marks every hit
+// unassigned.
 __global__ void k_prep(const double* __restrict__ hits, const uint8_t* __restrict__ active, EvView vw,
-                       HitRec* __restrict__ out, uint32_t* __restrict__ hist, uint32_t* __restrict__ status,
+                       HitRec* __restrict__ out, uint32_t* __restrict__ hist, uint32_t* __restrict__ lbh,
+                       int32_t* __restrict__ tlb, int32_t* __restrict__ tn2, uint32_t* __restrict__ status,
                        int64_t* __restrict__ n_bad, EventState* __restrict__ ev, int32_t* __restrict__ n_out,
                        BoxD* __restrict__ range_dst, BoxD range, int32_t* __restrict__ assigned) {
   const int e = blockIdx.y;
@@ -491,6 +495,13 @@ __global__ void k_prep(const double* __restrict__ hits, const uint8_t* __restric
   }
   if (hist)
     for (int32_t b = i; b < n_bins; b += stride) hist[int64_t(e) * vw.hist_stride + b] = 0u;
+  if (lbh)
+    for (int32_t b = i; b < n_bins; b += stride) lbh[int64_t(e) * vw.hist_stride + b] = 0u;
+  if (tlb)
+    for (int64_t t = i; t < vw.tri_stride; t += stride) {
+      tlb[int64_t(e) * vw.tri_stride + t] = 0;
+      tn2[int64_t(e) * vw.tri_stride + t] = 0;
+    }
   for (int32_t h = i; h < n_hits; h += stride) {
     bool bad;
     prep_one(hits + 8 * static_cast<int64_t>(beg + h), active ? active[beg + h] != 0 : true, &out[beg + h], &bad);
@@ -549,45 +560,114 @@ __device__ __forceinline__ int32_t block_sum(int32_t v, int32_t* sbuf) {
 }
 
 // ---------------------------------------------------------------------------
-// (triple, hit) pre-pass, one thread per pair: flags[t * n_hits + h] =
-// 0 no vote anywhere in the triple (or hit unused), 1 axial hit voting for
-// the whole triple, 2 stereo hit that may vote (decided per box).
-__global__ void __launch_bounds__(kWG) k_pair_filter(const HitRec* __restrict__ hits, EvView vw,
-                                                     const BoxD* __restrict__ parents, Shape sh,
-                                                     uint8_t* __restrict__ flags, int32_t filter,
-                                                     const EventState* __restrict__ ev, int32_t f32, float slack32) {
+// Classes of every (triple, hit) pair of a level, and vote bounds per triple.
+// class 0: no box of the triple gets the hit's vote; 1: every box does;
+// 2: the boxes must be evaluated (stereo hits only).  Axial pairs are decided
+// here completely.  With `filter` off every well-formed stereo pair is class
+// 2.  Per triple: tlb = number of class-1 pairs (a lower bound of each of
+// its boxes' votes, exact for a triple without class-2 pairs), tn2 = number
+// of class-2 pairs (tlb + tn2 bounds the votes from above); both are added
+// to (they start at zero).
+// Thread = triple: a workgroup takes 64 consecutive triples; its four waves
+// and the gridDim.z workgroups of a triple group share the hits (wave w of
+// group z takes hits 4 z + w, 4 z + w + 4 gridDim.z, ...), so the hit of a
+// wave is uniform (axial and stereo work do not diverge) and each thread
+// computes its triple frame once.  flags are hit-major: flags[h * n_tr + t].
+template <bool F32>
+__global__ void __launch_bounds__(kWG) k_classify(const HitRec* __restrict__ hits, EvView vw,
+                                                  const BoxD* __restrict__ parents, Shape sh,
+                                                  uint8_t* __restrict__ flags, int32_t* __restrict__ tlb,
+                                                  int32_t* __restrict__ tn2, int32_t filter,
+                                                  const EventState* __restrict__ ev, float slack32) {
   const int e = blockIdx.y;
   if (ev && ev[e].done) return;
   const int32_t n_hits = vw.count(e);
   hits += vw.beg(e);
   parents += e * vw.par_stride;
   flags += e * vw.flag_stride;
-  const uint32_t i = blockIdx.x * kWG + threadIdx.x;
+  tlb += e * vw.tri_stride;
+  tn2 += e * vw.tri_stride;
   const uint32_t n_tr = sh.n_parents * sh.m012;
-  if (n_hits <= 0 || i >= n_tr * static_cast<uint32_t>(n_hits)) return;
-  const uint32_t t = i / static_cast<uint32_t>(n_hits), hi = i % static_cast<uint32_t>(n_hits);
-  const HitRec h = hits[hi];
-  uint8_t fl = 0;
-  if (h.use) {
-    const uint32_t tc = t % sh.m012;
-    const BoxD& TP = parents[t / sh.m012];
-    const Frame f = triple_frame(TP, sh.m, tc / sh.m12, (tc / sh.m[2]) % sh.m[1], tc % sh.m[2]);
-    const Iv G = residual_G(f, h);
-    if (h.axial) {
-      fl = (h_contains0(G, f.K, f.sig * h.d, h.band) || h_contains0(G, f.K, f.sig * (-h.d), h.band)) ? 1 : 0;
-    } else if (f32 && !(f.R <= kR32Max)) {
-      fl = 1;                                // outside the FP32 domain: the pair votes
-    } else if (!filter) {
-      fl = 2;
-    } else {
-      const PairQ q = pair_quantities(f, h, G);
-      Iv Zr, Lr;
-      centre_ranges(TP, sh.m, &Zr, &Lr);
-      fl = static_cast<uint8_t>(f32 ? triple_vote_class32(q, f, h, Zr, Lr, slack32)
-                                    : triple_vote_class(q, f, h, Zr, Lr));
+  const uint32_t lane = threadIdx.x & 63u;
+  const int32_t wave = __builtin_amdgcn_readfirstlane(static_cast<int32_t>(threadIdx.x >> 6));
+  const uint32_t t = blockIdx.x * 64u + lane;
+  const bool live = t < n_tr;
+  const uint32_t tq = live ? t : n_tr - 1;
+  const uint32_t tc = tq % sh.m012;
+  const BoxD& TP = parents[tq / sh.m012];
+  const Frame f = triple_frame(TP, sh.m, tc / sh.m12, (tc / sh.m[2]) % sh.m[1], tc % sh.m[2]);
+  Iv Zr, Lr;
+  centre_ranges(TP, sh.m, &Zr, &Lr);
+  int32_t lb = 0, n2 = 0;
+  const int32_t h_step = static_cast<int32_t>(gridDim.z) * (kWG / 64);
+  for (int32_t h = static_cast<int32_t>(blockIdx.z) * (kWG / 64) + wave; h < n_hits; h += h_step) {
+    const HitRec hr = hits[h];
+    uint8_t fl = 0;
+    if (hr.use) {
+      const Iv G = residual_G(f, hr);
+      if (hr.axial) {
+        fl = (h_contains0(G, f.K, f.sig * hr.d, hr.band) || h_contains0(G, f.K, f.sig * (-hr.d), hr.band)) ? 1 : 0;
+      } else if (F32 && !(f.R <= kR32Max)) {
+        fl = 1;                              // outside the FP32 domain: the pair votes
+      } else if (!filter) {
+        fl = 2;
+      } else {
+        const PairQ q = pair_quantities(f, hr, G);
+        fl = static_cast<uint8_t>(F32 ? triple_vote_class32(q, f, hr, Zr, Lr, slack32)
+                                      : triple_vote_class(q, f, hr, Zr, Lr));
+      }
     }
+    if (live) flags[int64_t(h) * n_tr + t] = fl;
+    lb += fl == 1 ? 1 : 0;
+    n2 += fl == 2 ? 1 : 0;
   }
-  flags[i] = fl;
+  __shared__ int32_t s_lb[kWG / 64][64], s_n2[kWG / 64][64];
+  s_lb[wave][lane] = lb;
+  s_n2[wave][lane] = n2;
+  __syncthreads();
+  if (wave == 0 && live) {
+    int32_t a = 0, b = 0;
+    for (int w = 0; w < kWG / 64; ++w) { a += s_lb[w][lane]; b += s_n2[w][lane]; }
+    if (a) atomicAdd(&tlb[t], a);
+    if (b) atomicAdd(&tn2[t], b);
+  }
+}
+
+// Pruning threshold of a level, one workgroup per event: T = the largest v
+// such that at least k_eff = min(k, n_boxes) boxes have a lower bound >= v
+// (each triple holds m34 boxes), from the histogram of the triples' lower
+// bounds (in LDS, or in lbh -- zero on entry, cleared on exit -- when it has
+// more than kHistLds bins).  The k_eff-th box of the selection has at least
+// T votes, so a triple whose upper bound is below T holds no selected box
+// and no box of the maximum.
+__global__ void __launch_bounds__(kWG) k_threshold(const int32_t* __restrict__ tlb, uint32_t* __restrict__ lbh,
+                                                   EvView vw, Shape sh, int32_t k, EventState* __restrict__ ev) {
+  const int e = blockIdx.y;
+  if (ev[e].done) return;
+  const int32_t n_bins = vw.count(e) + 1;
+  const uint32_t n_tr = sh.n_parents * sh.m012;
+  tlb += e * vw.tri_stride;
+  __shared__ uint32_t sh_h[kHistLds];
+  uint32_t* hh = sh_h;
+  if (n_bins > kHistLds) hh = lbh + int64_t(e) * vw.hist_stride;
+  else
+    for (int32_t b = threadIdx.x; b < n_bins; b += kWG) sh_h[b] = 0u;
+  __syncthreads();
+  for (uint32_t t = threadIdx.x; t < n_tr; t += kWG) atomicAdd(&hh[min(tlb[t], n_bins - 1)], 1u);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int64_t k_eff = min(static_cast<int64_t>(k), static_cast<int64_t>(sh.n_boxes));
+    int64_t cum = 0;
+    int32_t T = 0;
+    for (int32_t v = n_bins - 1; v >= 0; --v) {
+      cum += static_cast<int64_t>(hh[v]) * sh.m34;
+      if (cum >= k_eff) { T = v; break; }
+    }
+    ev[e].t_prune = T;
+  }
+  __syncthreads();
+  if (n_bins > kHistLds)
+    for (int32_t b = threadIdx.x; b < n_bins; b += kWG) hh[b] = 0u;
 }
 
 // Top-k by (votes desc, index asc) of one level, one workgroup, run after
@@ -604,7 +684,8 @@ __global__ void __launch_bounds__(kWG) k_select_wg(const uint16_t* __restrict__ 
                                                    uint32_t n_wg, int32_t bx, const BoxD* __restrict__ parents,
                                                    Shape sh, BoxD* __restrict__ out_boxes,
                                                    int64_t* __restrict__ out_index, uint16_t* __restrict__ out_votes,
-                                                   EventState* __restrict__ ev, int32_t v_min_stop) {
+                                                   EventState* __restrict__ ev, int32_t v_min_stop,
+                                                   int32_t* __restrict__ tlb, int32_t* __restrict__ tn2) {
   const int e = blockIdx.y;
   if (ev && ev[e].done) return;
   const uint32_t n_boxes = sh.n_boxes;
@@ -685,6 +766,13 @@ __global__ void __launch_bounds__(kWG) k_select_wg(const uint16_t* __restrict__ 
   }
   __syncthreads();
   for (int32_t i = tid; i < n_bins; i += kWG) hist[i] = 0u;
+  if (tlb) {
+    // the level's triple bounds start at zero for the next classification
+    const uint32_t n_tr = sh.n_parents * sh.m012;
+    tlb += e * vw.tri_stride;
+    tn2 += e * vw.tri_stride;
+    for (uint32_t t = tid; t < n_tr; t += kWG) { tlb[t] = 0; tn2[t] = 0; }
+  }
   if (tid == 0 && ev) {
     ev->vmax = s_vmax;
     ev->n_argmax = static_cast<int32_t>(s_nmax);
@@ -696,9 +784,13 @@ __global__ void __launch_bounds__(kWG) k_select_wg(const uint16_t* __restrict__ 
 // ---------------------------------------------------------------------------
 // the vote kernel.  A workgroup owns BX consecutive boxes (one lane each) and
 // splits the hits of every chunk over kWG / BX slices (whole waves); the
-// slices' counts are summed in LDS.  Per chunk, the workgroup first stages
-// the (triple, hit) quantities of the triples its boxes span; with `flags`
-// from k_pair_filter it stages only the stereo pairs that may vote.
+// slices' counts are summed in LDS.  Each box starts from its triple's lower
+// bound tlb (its class-1 pairs from k_classify, axial ones included); only
+// class-2 pairs are evaluated per box, and only in triples whose upper bound
+// tlb + tn2 reaches the event's pruning threshold (ev->t_prune with `prune`,
+// else 0).  A box of a pruned triple keeps its lower bound, which is below
+// the threshold.  Per chunk of hits, the workgroup stages the (triple, hit)
+// quantities of the class-2 pairs of its live triples in LDS.
 // hist (nullable) receives the vote histogram of bins 0..n_bins-1 and
 // wg_max (nullable) each workgroup's maximum vote, for k_select_wg.
 template <int BX, bool F32>
@@ -706,8 +798,10 @@ __global__ void __launch_bounds__(kWG) k_vote(const HitRec* __restrict__ hits, E
                                               const BoxD* __restrict__ parents, Shape sh,
                                               uint16_t* __restrict__ votes, uint32_t* __restrict__ hist,
                                               uint32_t* __restrict__ status, const EventState* __restrict__ ev,
-                                              const uint8_t* __restrict__ flags, int32_t* __restrict__ wg_max,
-                                              unsigned long long* __restrict__ work, float slack32) {
+                                              const uint8_t* __restrict__ flags, const int32_t* __restrict__ tlb,
+                                              const int32_t* __restrict__ tn2, int32_t prune,
+                                              int32_t* __restrict__ wg_max, unsigned long long* __restrict__ work,
+                                              float slack32) {
   constexpr int HS = kWG / BX;
   static_assert(BX % 64 == 0 && HS * BX == kWG, "slices are whole waves");
   const int e = blockIdx.y;
@@ -717,13 +811,18 @@ __global__ void __launch_bounds__(kWG) k_vote(const HitRec* __restrict__ hits, E
   parents += e * vw.par_stride;
   votes += int64_t(e) * sh.n_boxes;
   if (hist) hist += int64_t(e) * vw.hist_stride;
-  if (flags) flags += e * vw.flag_stride;
+  flags += e * vw.flag_stride;
+  tlb += e * vw.tri_stride;
+  tn2 += e * vw.tri_stride;
   if (wg_max) wg_max += int64_t(e) * vw.wg_stride;
+  const int32_t T = (prune && ev) ? ev[e].t_prune : 0;
+  const uint32_t n_tr = sh.n_parents * sh.m012;
   __shared__ double sq[13][kCap + 16];
   // FP32 levels stage 16 floats per pair in the same storage
   static_assert(sizeof(PairQ32) == 16 * sizeof(float) && 16 * 4 <= 13 * 8, "FP32 staging fits");
   float(*sq32)[kCap + 16] = reinterpret_cast<float(*)[kCap + 16]>(&sq[0][0]);
   __shared__ int8_t sflag[kCap + 16];
+  __shared__ int8_t stlive[kWG];
   __shared__ uint32_t shist[kHistLds];
   __shared__ int32_t sred[HS][BX];
   __shared__ int32_t sbuf[kWG / 64];
@@ -745,57 +844,58 @@ __global__ void __launch_bounds__(kWG) k_vote(const HitRec* __restrict__ hits, E
   // wave (avoids bank conflicts); nt * pitch <= kCap + 16 always holds.
   const int32_t pitch = hc + ((nt > 1 && nt <= 16) ? 1 : 0);
 
-  // this lane's box: triple frame and (z0, tanl) centre
-  uint32_t k[5];
-  child_index(sh.m, bb % sh.nc, k);
-  const BoxD& P = parents[bb / sh.nc];
-  const Frame f = triple_frame(P, sh.m, k[0], k[1], k[2]);
-  double zlo, zhi, llo, lhi;
-  child_edge(P.lo[3], P.hi[3], sh.m[3], k[3], &zlo, &zhi);
-  child_edge(P.lo[4], P.hi[4], sh.m[4], k[4], &llo, &lhi);
-  const double z0 = 0.5 * (zlo + zhi), lam = 0.5 * (llo + lhi);
-  const double lamR = lam * f.R, lam2 = lam * lam;
-  // FP32 images of the lane's box (used at FP32 levels only)
-  const float R32 = static_cast<float>(f.R), sig32 = static_cast<float>(f.sig);
-  const Iv32 K32 = to32(f.K);
-  const float z032 = static_cast<float>(z0), lam32 = static_cast<float>(lam);
-  const float lamR32 = lam32 * R32, lam232 = lam32 * lam32;
+  // triples of this workgroup that need per-box evaluation
+  int32_t any_live = 0;
+  for (int32_t i = tid; i < nt; i += kWG) {
+    const int32_t a = tlb[t_first + i], c = tn2[t_first + i];
+    const bool lv = c > 0 && a + c >= T;
+    stlive[i] = lv ? 1 : 0;
+    any_live |= lv ? 1 : 0;
+  }
+  any_live = __syncthreads_or(any_live);
 
-  int32_t nv = 0, n_eval = 0, n_staged = 0;
-  for (int32_t h0 = 0; h0 < n_hits; h0 += hc) {
-    const int32_t nh = min(hc, n_hits - h0);
-    __syncthreads();
-    // stage (triple, hit) quantities: thread r -> (tl = r / hc, hl = r % hc)
-    for (int32_t r = tid; r < nt * hc; r += kWG) {
-      const int32_t tl = r / hc, hl = r % hc;
-      const int32_t slot = tl * pitch + hl;
-      if (hl >= nh) continue;
-      const uint32_t t = t_first + tl;
-      if (flags) {
-        const uint8_t fl = flags[t * static_cast<uint32_t>(n_hits) + static_cast<uint32_t>(h0 + hl)];
-        if (fl < 2) { sflag[slot] = static_cast<int8_t>(fl); continue; }
-      }
-      const HitRec h = hits[h0 + hl];
-      if (!h.use) { sflag[slot] = -1; continue; }
-      const uint32_t tc = t % sh.m012;
-      const uint32_t t0 = tc / sh.m12, t1 = (tc / sh.m[2]) % sh.m[1], t2 = tc % sh.m[2];
-      const Frame ft = triple_frame(parents[t / sh.m012], sh.m, t0, t1, t2);
-      const Iv G = residual_G(ft, h);
-      if (h.axial) {
-        bool v = h_contains0(G, ft.K, ft.sig * h.d, h.band) || h_contains0(G, ft.K, ft.sig * (-h.d), h.band);
-        sflag[slot] = v ? 1 : 0;
-      } else if (F32 && !(ft.R <= kR32Max)) {
-        sflag[slot] = 1;                     // outside the FP32 domain: the pair votes
-      } else {
+  int32_t nv = sl == 0 ? tlb[t_first + my_tl] : 0, n_eval = 0, n_staged = 0;
+  if (any_live) {                      // uniform over the workgroup (barriers below)
+    // this lane's box: triple frame and (z0, tanl) centre
+    uint32_t k[5];
+    child_index(sh.m, bb % sh.nc, k);
+    const BoxD& P = parents[bb / sh.nc];
+    const Frame f = triple_frame(P, sh.m, k[0], k[1], k[2]);
+    double zlo, zhi, llo, lhi;
+    child_edge(P.lo[3], P.hi[3], sh.m[3], k[3], &zlo, &zhi);
+    child_edge(P.lo[4], P.hi[4], sh.m[4], k[4], &llo, &lhi);
+    const double z0 = 0.5 * (zlo + zhi), lam = 0.5 * (llo + lhi);
+    const double lamR = lam * f.R, lam2 = lam * lam;
+    // FP32 images of the lane's box (used at FP32 levels only)
+    const float R32 = static_cast<float>(f.R), sig32 = static_cast<float>(f.sig);
+    const Iv32 K32 = to32(f.K);
+    const float z032 = static_cast<float>(z0), lam32 = static_cast<float>(lam);
+    const float lamR32 = lam32 * R32, lam232 = lam32 * lam32;
+
+    for (int32_t h0 = 0; h0 < n_hits; h0 += hc) {
+      const int32_t nh = min(hc, n_hits - h0);
+      __syncthreads();
+      // stage the class-2 pairs of live triples: thread r -> (tl = r / hc, hl = r % hc)
+      for (int32_t r = tid; r < nt * hc; r += kWG) {
+        const int32_t tl = r / hc, hl = r % hc;
+        const int32_t slot = tl * pitch + hl;
+        if (hl >= nh) continue;
+        const uint32_t t = t_first + tl;
+        if (!stlive[tl] || flags[int64_t(h0 + hl) * n_tr + t] != 2) { sflag[slot] = 0; continue; }
+        const HitRec h = hits[h0 + hl];
+        const uint32_t tc = t % sh.m012;
+        const uint32_t t0 = tc / sh.m12, t1 = (tc / sh.m[2]) % sh.m[1], t2 = tc % sh.m[2];
+        const Frame ft = triple_frame(parents[t / sh.m012], sh.m, t0, t1, t2);
+        const Iv G = residual_G(ft, h);
         const PairQ q = pair_quantities(ft, h, G);
         ++n_staged;
         sflag[slot] = 2;
         if constexpr (F32) {
-          const PairQ32 r = pair_q32(q, h, slack32);
-          sq32[0][slot] = r.Glo; sq32[1][slot] = r.Ghi; sq32[2][slot] = r.sArc; sq32[3][slot] = r.dphi;
-          sq32[4][slot] = r.RAx; sq32[5][slot] = r.sinA; sq32[6][slot] = r.cosA; sq32[7][slot] = r.sAx;
-          sq32[8][slot] = r.cAx; sq32[9][slot] = r.c2; sq32[10][slot] = r.s2; sq32[11][slot] = r.twoRAx2;
-          sq32[12][slot] = r.RpRAx; sq32[13][slot] = r.tt; sq32[14][slot] = r.d; sq32[15][slot] = r.bs;
+          const PairQ32 rq = pair_q32(q, h, slack32);
+          sq32[0][slot] = rq.Glo; sq32[1][slot] = rq.Ghi; sq32[2][slot] = rq.sArc; sq32[3][slot] = rq.dphi;
+          sq32[4][slot] = rq.RAx; sq32[5][slot] = rq.sinA; sq32[6][slot] = rq.cosA; sq32[7][slot] = rq.sAx;
+          sq32[8][slot] = rq.cAx; sq32[9][slot] = rq.c2; sq32[10][slot] = rq.s2; sq32[11][slot] = rq.twoRAx2;
+          sq32[12][slot] = rq.RpRAx; sq32[13][slot] = rq.tt; sq32[14][slot] = rq.d; sq32[15][slot] = rq.bs;
         } else {
           sq[0][slot] = q.Glo; sq[1][slot] = q.Ghi; sq[2][slot] = q.sArc; sq[3][slot] = q.dphi;
           sq[4][slot] = q.RAx; sq[5][slot] = q.sinA; sq[6][slot] = q.cosA; sq[7][slot] = q.sAx;
@@ -803,29 +903,29 @@ __global__ void __launch_bounds__(kWG) k_vote(const HitRec* __restrict__ hits, E
           sq[12][slot] = q.RpRAx;
         }
       }
-    }
-    __syncthreads();
-    for (int32_t hl = sl; hl < nh; hl += HS) {
-      const int32_t slot = my_tl * pitch + hl;
-      const int8_t fl = sflag[slot];
-      if (fl < 2) { nv += fl > 0 ? 1 : 0; continue; }
-      n_eval += live ? 1 : 0;
-      if constexpr (F32) {
-        PairQ32 r;
-        r.Glo = sq32[0][slot]; r.Ghi = sq32[1][slot]; r.sArc = sq32[2][slot]; r.dphi = sq32[3][slot];
-        r.RAx = sq32[4][slot]; r.sinA = sq32[5][slot]; r.cosA = sq32[6][slot]; r.sAx = sq32[7][slot];
-        r.cAx = sq32[8][slot]; r.c2 = sq32[9][slot]; r.s2 = sq32[10][slot]; r.twoRAx2 = sq32[11][slot];
-        r.RpRAx = sq32[12][slot]; r.tt = sq32[13][slot]; r.d = sq32[14][slot]; r.bs = sq32[15][slot];
-        if (stereo_vote32(r, R32, sig32, K32, z032, lam32, lamR32, lam232)) ++nv;
-      } else {
-        const HitRec& h = hits[h0 + hl];
-        PairQ q;
-        q.Glo = sq[0][slot]; q.Ghi = sq[1][slot]; q.sArc = sq[2][slot]; q.dphi = sq[3][slot];
-        q.RAx = sq[4][slot]; q.sinA = sq[5][slot]; q.cosA = sq[6][slot]; q.sAx = sq[7][slot];
-        q.cAx = sq[8][slot]; q.c2 = sq[9][slot]; q.s2 = sq[10][slot]; q.twoRAx2 = sq[11][slot];
-        q.RpRAx = sq[12][slot];
-        const double tt = h.tant;
-        if (stereo_vote(q, f.R, f.sig, f.K, z0, lam, lamR, lam2, tt, tt * tt, h.d, h.band)) ++nv;
+      __syncthreads();
+      if (!stlive[my_tl]) continue;
+      for (int32_t hl = sl; hl < nh; hl += HS) {
+        const int32_t slot = my_tl * pitch + hl;
+        if (sflag[slot] != 2) continue;
+        n_eval += live ? 1 : 0;
+        if constexpr (F32) {
+          PairQ32 r;
+          r.Glo = sq32[0][slot]; r.Ghi = sq32[1][slot]; r.sArc = sq32[2][slot]; r.dphi = sq32[3][slot];
+          r.RAx = sq32[4][slot]; r.sinA = sq32[5][slot]; r.cosA = sq32[6][slot]; r.sAx = sq32[7][slot];
+          r.cAx = sq32[8][slot]; r.c2 = sq32[9][slot]; r.s2 = sq32[10][slot]; r.twoRAx2 = sq32[11][slot];
+          r.RpRAx = sq32[12][slot]; r.tt = sq32[13][slot]; r.d = sq32[14][slot]; r.bs = sq32[15][slot];
+          if (stereo_vote32(r, R32, sig32, K32, z032, lam32, lamR32, lam232)) ++nv;
+        } else {
+          const HitRec& h = hits[h0 + hl];
+          PairQ q;
+          q.Glo = sq[0][slot]; q.Ghi = sq[1][slot]; q.sArc = sq[2][slot]; q.dphi = sq[3][slot];
+          q.RAx = sq[4][slot]; q.sinA = sq[5][slot]; q.cosA = sq[6][slot]; q.sAx = sq[7][slot];
+          q.cAx = sq[8][slot]; q.c2 = sq[9][slot]; q.s2 = sq[10][slot]; q.twoRAx2 = sq[11][slot];
+          q.RpRAx = sq[12][slot];
+          const double tt = h.tant;
+          if (stereo_vote(q, f.R, f.sig, f.K, z0, lam, lamR, lam2, tt, tt * tt, h.d, h.band)) ++nv;
+        }
       }
     }
   }
@@ -853,14 +953,23 @@ __global__ void __launch_bounds__(kWG) k_vote(const HitRec* __restrict__ hits, E
   }
   const bool owner = sl == 0 && live;
   if (owner) votes[b] = static_cast<uint16_t>(nv);
-
-  if (hist) {
+  // workgroup maximum (read by the selection kernel and used below)
+  int32_t mv = owner ? nv : -1;
+  for (int o = 32; o > 0; o >>= 1) mv = max(mv, __shfl_down(mv, o, 64));
+  if ((tid & 63) == 0) sbuf[tid >> 6] = mv;
+  __syncthreads();
+  int32_t wmax = -1;
+  for (int w = 0; w < kWG / 64; ++w) wmax = max(wmax, sbuf[w]);
+  if (wg_max && tid == 0) wg_max[blockIdx.x] = wmax;
+  // vote histogram of the bins >= T (the selection threshold is never below
+  // T, so lower bins are never read); nothing to add when the maximum is below
+  if (hist && wmax >= T) {
     const bool in_lds = n_bins <= kHistLds;
     if (in_lds) {
       for (int32_t i = tid; i < n_bins; i += kWG) shist[i] = 0u;
       __syncthreads();
     }
-    if (owner) {
+    if (owner && nv >= T) {
       if (nv >= n_bins) atomicOr(status, kStVoteOverflow);
       else if (in_lds) atomicAdd(&shist[nv], 1u);
       else atomicAdd(&hist[nv], 1u);
@@ -870,17 +979,6 @@ __global__ void __launch_bounds__(kWG) k_vote(const HitRec* __restrict__ hits, E
       for (int32_t i = tid; i < n_bins; i += kWG)
         if (shist[i]) atomicAdd(&hist[i], shist[i]);
     }
-  }
-  if (!wg_max) return;
-  // workgroup maximum, read by the selection kernel
-  int32_t mv = owner ? nv : -1;
-  for (int o = 32; o > 0; o >>= 1) mv = max(mv, __shfl_down(mv, o, 64));
-  if ((tid & 63) == 0) sbuf[tid >> 6] = mv;
-  __syncthreads();
-  if (tid == 0) {
-    int32_t m = -1;
-    for (int w = 0; w < kWG / 64; ++w) m = max(m, sbuf[w]);
-    wg_max[blockIdx.x] = m;
   }
 }
 

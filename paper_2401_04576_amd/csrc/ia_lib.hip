@@ -58,6 +58,7 @@ struct ia_ctx {
   bool profiling = false;
   int32_t tile_override = 0;
   int32_t filter_mode = -1;       // -1: automatic, 0: off, 1: on
+  int32_t prune = 1;              // ia_find_helices: skip triples that cannot reach the selection
   int32_t max_chunk = 65535;      // events per batched launch
   float slack32 = ia::ru32(1e-6);  // band widening of ia_vote_level at FP32
   // pinned staging ring for the chunk-relative hit offsets copied to the
@@ -163,12 +164,9 @@ int32_t vote_tile(const ia_ctx* c, uint32_t n_boxes) {
   return 128;
 }
 
-// the (triple, hit) pre-pass pays when several boxes share a triple: its
-// classes remove the pairs that vote nowhere or everywhere in the triple
-int32_t use_filter(const ia_ctx* c, const Shape& sh) {
-  if (c->filter_mode >= 0) return c->filter_mode;
-  return sh.m34 >= 8 ? 1 : 0;
-}
+// the exclusion and inclusion proofs of the (triple, hit) classification:
+// on unless switched off (then every stereo pair is evaluated per box)
+int32_t use_filter(const ia_ctx* c) { return c->filter_mode >= 0 ? c->filter_mode : 1; }
 
 ia::EvView single_view(int32_t n_hits) {
   ia::EvView v{};
@@ -177,43 +175,58 @@ ia::EvView single_view(int32_t n_hits) {
   return v;
 }
 
-// launches the (triple, hit) pre-pass for n_ev events when it pays and the
-// flag buffer holds it; returns the flags for the vote kernel, or nullptr
-const uint8_t* launch_filter(ia_ctx* c, const HitRec* recs, const ia::EvView& vw, int32_t n_ev, int32_t max_hits,
-                             const BoxD* par, const Shape& sh, uint8_t* flags, const EventState* ev, hipStream_t s,
-                             bool f32, float slack32) {
-  if (!flags || max_hits <= 0 || !use_filter(c, sh)) return nullptr;
-  const uint64_t pairs = uint64_t(sh.n_parents) * sh.m012 * uint64_t(max_hits);
-  if (pairs > uint64_t(vw.flag_stride) || pairs >= (uint64_t(1) << 31)) return nullptr;
-  const uint32_t grid = static_cast<uint32_t>((pairs + ia::kWG - 1) / ia::kWG);
-  hipLaunchKernelGGL(ia::k_pair_filter, dim3(grid, n_ev), dim3(ia::kWG), 0, s, recs, vw, par, sh, flags, 1, ev,
-                     f32 ? 1 : 0, slack32);
-  return flags;
+// launches the (triple, hit) classification of a level for n_ev events
+// (tlb and tn2 must be zero on entry; the kernel adds to them).  The hits
+// are split over enough groups (grid z) to give the device about 2048
+// workgroups when the triples alone do not.
+void launch_classify(ia_ctx* c, const HitRec* recs, const ia::EvView& vw, int32_t n_ev, int32_t max_hits,
+                     const BoxD* par, const Shape& sh, uint8_t* flags, int32_t* tlb, int32_t* tn2,
+                     const EventState* ev, hipStream_t s, bool f32, float slack32) {
+  const uint32_t n_tr = sh.n_parents * sh.m012;
+  const uint32_t gx = (n_tr + 63) / 64;
+  const int64_t base = int64_t(gx) * std::max(1, n_ev);
+  const int32_t max_groups = std::max(1, (max_hits + ia::kWG / 64 - 1) / (ia::kWG / 64));
+  const int32_t hg = static_cast<int32_t>(std::min<int64_t>(std::max<int64_t>(1, 2048 / base), std::min(max_groups, 64)));
+  const dim3 g(gx, n_ev, hg);
+  const int32_t filt = use_filter(c);
+  if (f32)
+    hipLaunchKernelGGL((ia::k_classify<true>), g, dim3(ia::kWG), 0, s, recs, vw, par, sh, flags, tlb, tn2, filt, ev,
+                       slack32);
+  else
+    hipLaunchKernelGGL((ia::k_classify<false>), g, dim3(ia::kWG), 0, s, recs, vw, par, sh, flags, tlb, tn2, filt, ev,
+                       slack32);
 }
 
 // launches the vote kernel for n_ev events, bracketed by events when profiling
+struct VoteIn {                   // per-level inputs of the vote kernel
+  const uint8_t* flags;
+  const int32_t* tlb;
+  const int32_t* tn2;
+  int32_t prune;
+};
+
 template <bool F32>
 void launch_vote_tile(int32_t bx, dim3 g, hipStream_t s, const HitRec* recs, const ia::EvView& vw, const BoxD* par,
                       const Shape& sh, uint16_t* votes, uint32_t* hist, uint32_t* st, const EventState* ev,
-                      const uint8_t* flags, int32_t* wg_max, unsigned long long* wk, float slack32) {
+                      const VoteIn& in, int32_t* wg_max, unsigned long long* wk, float slack32) {
   switch (bx) {
     case 256:
-      hipLaunchKernelGGL((ia::k_vote<256, F32>), g, dim3(ia::kWG), 0, s, recs, vw, par, sh, votes, hist, st, ev, flags,
-                         wg_max, wk, slack32);
+      hipLaunchKernelGGL((ia::k_vote<256, F32>), g, dim3(ia::kWG), 0, s, recs, vw, par, sh, votes, hist, st, ev,
+                         in.flags, in.tlb, in.tn2, in.prune, wg_max, wk, slack32);
       break;
     case 128:
-      hipLaunchKernelGGL((ia::k_vote<128, F32>), g, dim3(ia::kWG), 0, s, recs, vw, par, sh, votes, hist, st, ev, flags,
-                         wg_max, wk, slack32);
+      hipLaunchKernelGGL((ia::k_vote<128, F32>), g, dim3(ia::kWG), 0, s, recs, vw, par, sh, votes, hist, st, ev,
+                         in.flags, in.tlb, in.tn2, in.prune, wg_max, wk, slack32);
       break;
     default:
-      hipLaunchKernelGGL((ia::k_vote<64, F32>), g, dim3(ia::kWG), 0, s, recs, vw, par, sh, votes, hist, st, ev, flags,
-                         wg_max, wk, slack32);
+      hipLaunchKernelGGL((ia::k_vote<64, F32>), g, dim3(ia::kWG), 0, s, recs, vw, par, sh, votes, hist, st, ev,
+                         in.flags, in.tlb, in.tn2, in.prune, wg_max, wk, slack32);
       break;
   }
 }
 
 ia_status launch_vote(ia_ctx* c, const HitRec* recs, const ia::EvView& vw, int32_t n_ev, const BoxD* par,
-                      const Shape& sh, uint16_t* votes, uint32_t* hist, const EventState* ev, const uint8_t* flags,
+                      const Shape& sh, uint16_t* votes, uint32_t* hist, const EventState* ev, const VoteIn& in,
                       int32_t* wg_max, hipStream_t s, bool f32, float slack32, int32_t* tile_used = nullptr) {
   const int32_t bx = vote_tile(c, sh.n_boxes);
   const uint32_t grid = (sh.n_boxes + bx - 1) / bx;
@@ -227,8 +240,8 @@ ia_status launch_vote(ia_ctx* c, const HitRec* recs, const ia::EvView& vw, int32
   uint32_t* st = &persistent(c)->status;
   unsigned long long* wk = persistent(c)->work;
   const dim3 g(grid, n_ev);
-  if (f32) launch_vote_tile<true>(bx, g, s, recs, vw, par, sh, votes, hist, st, ev, flags, wg_max, wk, slack32);
-  else launch_vote_tile<false>(bx, g, s, recs, vw, par, sh, votes, hist, st, ev, flags, wg_max, wk, slack32);
+  if (f32) launch_vote_tile<true>(bx, g, s, recs, vw, par, sh, votes, hist, st, ev, in, wg_max, wk, slack32);
+  else launch_vote_tile<false>(bx, g, s, recs, vw, par, sh, votes, hist, st, ev, in, wg_max, wk, slack32);
   if (c->profiling) {
     IA_HIP(c, hipEventRecord(e1, s));
     c->marks.push_back({e0, e1, f32});
@@ -240,8 +253,8 @@ ia_status launch_vote(ia_ctx* c, const HitRec* recs, const ia::EvView& vw, int32
 // scratch layout of one chunk of ia_find_helices (byte offsets into the
 // arena): per-event slices of every array, sized for events of max_hits hits
 struct FindLayout {
-  size_t off, recs, votes, hist, selA, selB, range, sel_idx, sel_v, ev, part, flags, wg_max, total;
-  int64_t flag_stride, votes_stride;
+  size_t off, recs, votes, hist, lbh, selA, selB, range, sel_idx, sel_v, ev, part, flags, tlb, tn2, wg_max, total;
+  int64_t flag_stride, tri_stride, votes_stride;
   int32_t hist_stride, wg_stride, part_stride, n_part;
 };
 
@@ -251,6 +264,7 @@ void layout_find(int64_t max_level_boxes, int64_t max_triples, int32_t top_k, in
   L->votes_stride = max_level_boxes;
   L->hist_stride = max_hits + 2;
   L->flag_stride = max_triples * int64_t(std::max(0, max_hits));
+  L->tri_stride = max_triples;
   L->wg_stride = static_cast<int32_t>((max_level_boxes + 63) / 64);
   L->part_stride = ia::kEstQ * L->n_part;
   const size_t E = size_t(std::max(1, n_ev));
@@ -264,6 +278,7 @@ void layout_find(int64_t max_level_boxes, int64_t max_triples, int32_t top_k, in
   L->recs = take(sizeof(HitRec) * size_t(std::max<int64_t>(1, n_hits_total)));
   L->votes = take(sizeof(uint16_t) * size_t(L->votes_stride) * E);
   L->hist = take(sizeof(uint32_t) * size_t(L->hist_stride) * E);
+  L->lbh = take(sizeof(uint32_t) * size_t(L->hist_stride) * E);
   L->selA = take(sizeof(BoxD) * size_t(top_k) * E);
   L->selB = take(sizeof(BoxD) * size_t(top_k) * E);
   L->range = take(sizeof(BoxD));
@@ -272,6 +287,8 @@ void layout_find(int64_t max_level_boxes, int64_t max_triples, int32_t top_k, in
   L->ev = take(sizeof(EventState) * E);
   L->part = take(sizeof(double) * size_t(L->part_stride) * E);
   L->flags = take(size_t(L->flag_stride) * E);
+  L->tlb = take(sizeof(int32_t) * size_t(L->tri_stride) * E);
+  L->tn2 = take(sizeof(int32_t) * size_t(L->tri_stride) * E);
   L->wg_max = take(sizeof(int32_t) * size_t(L->wg_stride) * E);
   L->total = off;
 }
@@ -397,6 +414,12 @@ ia_status ia_ctx_set_prefilter(ia_ctx* c, int32_t mode) {
   return IA_OK;
 }
 
+ia_status ia_ctx_set_pruning(ia_ctx* c, int32_t enable) {
+  if (!c) return IA_ERR_INVALID;
+  c->prune = enable != 0 ? 1 : 0;
+  return IA_OK;
+}
+
 ia_status ia_ctx_set_profiling(ia_ctx* c, int32_t enable) {
   if (!c) return IA_ERR_INVALID;
   c->profiling = enable != 0;
@@ -466,16 +489,29 @@ ia_status ia_vote_level(ia_ctx* c, const ia_hit* d_hits, int32_t n_hits, const u
   ia::EvView vw = single_view(n_hits);
   if (n_hits > 0)
     hipLaunchKernelGGL(ia::k_prep, dim3((n_hits + 255) / 256, 1), dim3(256), 0, s,
-                       reinterpret_cast<const double*>(d_hits), d_active, vw, recs, nullptr, &ps->status,
+                       reinterpret_cast<const double*>(d_hits), d_active, vw, recs, nullptr, nullptr, nullptr, nullptr,
+                       &ps->status,
                        &ps->n_bad, nullptr, nullptr, nullptr, BoxD{}, nullptr);
-  // the pre-pass flags, when the remaining scratch holds them (results do not depend on it)
-  const int64_t flag_cap = int64_t(sh.n_parents) * sh.m012 * int64_t(std::max(0, n_hits));
-  uint8_t* flags = (n_hits > 0 && use_filter(c, sh)) ? bump<uint8_t>(c, size_t(flag_cap)) : nullptr;
-  vw.flag_stride = flags ? flag_cap : 0;
+  // classes of the (triple, hit) pairs and per-triple vote bounds
+  const int64_t n_tr = int64_t(sh.n_parents) * sh.m012;
+  uint8_t* flags = bump<uint8_t>(c, size_t(std::max<int64_t>(1, n_tr * int64_t(n_hits))));
+  int32_t* tlb = bump<int32_t>(c, size_t(n_tr));
+  int32_t* tn2 = bump<int32_t>(c, size_t(n_tr));
+  if (!flags || !tlb || !tn2)
+    return fail(c, IA_ERR_NOMEM, "scratch too small: the level needs %lld bytes of pair classes",
+                static_cast<long long>(n_tr * (int64_t(n_hits) + 8)));
+  vw.flag_stride = 0;
+  vw.tri_stride = 0;
   const BoxD* par = reinterpret_cast<const BoxD*>(d_parents);
   const bool f32 = prec == IA_FP32;
-  const uint8_t* fl = launch_filter(c, recs, vw, 1, n_hits, par, sh, flags, nullptr, s, f32, c->slack32);
-  return launch_vote(c, recs, vw, 1, par, sh, d_votes, nullptr, nullptr, fl, nullptr, s, f32, c->slack32);
+  const uint32_t fill_n = static_cast<uint32_t>(std::min<int64_t>(n_tr, 0x7fffffff));
+  hipLaunchKernelGGL(ia::k_fill_u32, dim3(std::min<uint32_t>((fill_n + 255) / 256, 65535)), dim3(256), 0, s,
+                     reinterpret_cast<uint32_t*>(tlb), fill_n, 0u);
+  hipLaunchKernelGGL(ia::k_fill_u32, dim3(std::min<uint32_t>((fill_n + 255) / 256, 65535)), dim3(256), 0, s,
+                     reinterpret_cast<uint32_t*>(tn2), fill_n, 0u);
+  launch_classify(c, recs, vw, 1, n_hits, par, sh, flags, tlb, tn2, nullptr, s, f32, c->slack32);
+  const VoteIn in{flags, tlb, tn2, 0};
+  return launch_vote(c, recs, vw, 1, par, sh, d_votes, nullptr, nullptr, in, nullptr, s, f32, c->slack32);
 }
 
 ia_status ia_refine(ia_ctx* c, const ia_box* d_parents, int32_t n_parents, const int32_t split[5],
@@ -620,6 +656,9 @@ ia_status ia_find_helices(ia_ctx* c, const ia_hit* d_hits, const int32_t* h_off,
     EventState* ev = reinterpret_cast<EventState*>(a + L.ev);
     double* part = reinterpret_cast<double*>(a + L.part);
     uint8_t* flags = reinterpret_cast<uint8_t*>(a + L.flags);
+    int32_t* tlb = reinterpret_cast<int32_t*>(a + L.tlb);
+    int32_t* tn2 = reinterpret_cast<int32_t*>(a + L.tn2);
+    uint32_t* lbh = reinterpret_cast<uint32_t*>(a + L.lbh);
     int32_t* wg_max = reinterpret_cast<int32_t*>(a + L.wg_max);
     // chunk-relative hit offsets through a pinned slot whose last copy is done
     const uint32_t slot = c->slot_next++ % kOffSlots;
@@ -633,6 +672,7 @@ ia_status ia_find_helices(ia_ctx* c, const ia_hit* d_hits, const int32_t* h_off,
     vw.off = d_off;
     vw.k = K;
     vw.flag_stride = L.flag_stride;
+    vw.tri_stride = L.tri_stride;
     vw.hist_stride = L.hist_stride;
     vw.wg_stride = L.wg_stride;
     vw.part_stride = L.part_stride;
@@ -642,8 +682,8 @@ ia_status ia_find_helices(ia_ctx* c, const ia_hit* d_hits, const int32_t* h_off,
     ia::HelixOut* out = reinterpret_cast<ia::HelixOut*>(d_out) + int64_t(e0) * max_per_event;
     int32_t* n_out = d_n_out + e0;
     const int32_t pg = std::max(1, (cmax + 2 + 255) / 256);
-    hipLaunchKernelGGL(ia::k_prep, dim3(pg, E), dim3(256), 0, s, hits, nullptr, vw, recs, hist, &ps->status,
-                       &ps->n_bad, ev, n_out, range, rb, assigned);
+    hipLaunchKernelGGL(ia::k_prep, dim3(pg, E), dim3(256), 0, s, hits, nullptr, vw, recs, hist, lbh, tlb, tn2,
+                       &ps->status, &ps->n_bad, ev, n_out, range, rb, assigned);
     for (int32_t pass = 0; pass < std::min(sc->n_helix_max, max_per_event); ++pass) {
       const BoxD* par = range;
       Shape sh = S.sh0;
@@ -651,13 +691,15 @@ ia_status ia_find_helices(ia_ctx* c, const ia_hit* d_hits, const int32_t* h_off,
       vw.par_stride = 0;
       for (int32_t lev = 0; lev <= sc->n_refine; ++lev) {
         const bool f32 = sc->prec[lev] == IA_FP32;
-        const uint8_t* fl = launch_filter(c, recs, vw, E, cmax, par, sh, flags, ev, s, f32, slack32);
+        launch_classify(c, recs, vw, E, cmax, par, sh, flags, tlb, tn2, ev, s, f32, slack32);
+        hipLaunchKernelGGL(ia::k_threshold, dim3(1, E), dim3(ia::kWG), 0, s, tlb, lbh, vw, sh, K, ev);
         int32_t bx = 0;
-        ia_status st = launch_vote(c, recs, vw, E, par, sh, votes, hist, ev, fl, wg_max, s, f32, slack32, &bx);
+        const VoteIn in{flags, tlb, tn2, c->prune};
+        ia_status st = launch_vote(c, recs, vw, E, par, sh, votes, hist, ev, in, wg_max, s, f32, slack32, &bx);
         if (st != IA_OK) return st;
         const uint32_t n_wg = (sh.n_boxes + bx - 1) / bx;
         hipLaunchKernelGGL(ia::k_select_wg, dim3(1, E), dim3(ia::kWG), 0, s, votes, vw, hist, wg_max, n_wg, bx, par,
-                           sh, sel, sel_idx, sel_v, ev, lev == 0 ? std::max(sc->v_min, 0) : 0);
+                           sh, sel, sel_idx, sel_v, ev, lev == 0 ? std::max(sc->v_min, 0) : 0, tlb, tn2);
         IA_HIP(c, hipGetLastError());
         if (lev == sc->n_refine) break;
         const int32_t k_eff = static_cast<int32_t>(std::min<int64_t>(K, sh.n_boxes));

@@ -1,7 +1,8 @@
 // Host-side check harness: the vote arithmetic of libia (the same
 // __host__ __device__ functions the HIP kernels run), compiled for the CPU
-// and driven by a loop with the kernel's structure -- per (triple, hit)
-// staging, the (triple, hit) pre-filter, then the per-box stereo term.
+// and driven by a loop with the kernels' structure -- the (triple, hit)
+// classification and per-triple bounds, the pruning threshold, then the
+// per-box stereo term of the pairs left undecided.
 // Used only by the tests, to compare the device arithmetic with the oracle
 // on many events without a GPU.
 #include <cstdint>
@@ -30,14 +31,18 @@ static bool make_shape(const int32_t m[5], int64_t n_parents, Shape* sh) {
 extern "C" {
 
 // votes of the boxes of a level at precision f32 (0: FP64, 1: FP32 with
-// band widening slack); stats[0] = stereo (triple, hit) pairs, stats[1] =
-// pairs removed by the pre-filter, stats[2] = stereo (box, hit) evaluations
-// performed, stats[3] = those that voted, stats[4] = evaluated pairs voting
-// in every box of their triple, stats[5] = pairs the pre-filter proved to
-// vote in every box (no evaluation)
+// band widening slack), following the library's structure: classes of every
+// (triple, hit) pair (with the exclusion / inclusion proofs when `filter`),
+// per-triple bounds tlb (class-1 pairs) and tn2 (class-2 pairs), then the
+// per-box evaluation of class-2 pairs.  With prune_k > 0 only triples whose
+// upper bound reaches T (the prune_k-th largest lower bound over boxes) are
+// evaluated; the boxes of the others keep their lower bound.
+// stats: [0] stereo (triple, hit) pairs, [1] class 0, [2] stereo (box, hit)
+// evaluations, [3] of those that voted, [4] evaluated pairs voting in every
+// box of their triple, [5] class 1, [6] triples evaluated, [7] T
 int32_t hc_vote_level(const double* hits, int32_t n_hits, const double* parents, int32_t n_parents,
-                      const int32_t split[5], int32_t filter, int32_t f32, double slack, uint16_t* votes,
-                      int64_t* stats) {
+                      const int32_t split[5], int32_t filter, int32_t f32, double slack, int32_t prune_k,
+                      uint16_t* votes, int64_t* stats) {
   const float slack32 = ru32(slack);
   Shape sh;
   if (!make_shape(split, n_parents, &sh)) return 1;
@@ -48,65 +53,96 @@ int32_t hc_vote_level(const double* hits, int32_t n_hits, const double* parents,
   }
   const BoxD* P = reinterpret_cast<const BoxD*>(parents);
   const int64_t n_triples = int64_t(n_parents) * sh.m012;
-  int64_t n_pairs = 0, n_cut = 0, n_evals = 0, n_yes = 0, n_full = 0, n_incl = 0;
-#pragma omp parallel for schedule(dynamic, 4) reduction(+ : n_pairs, n_cut, n_evals, n_yes, n_full, n_incl)
+  std::vector<uint8_t> cls(size_t(n_triples) * size_t(n_hits > 0 ? n_hits : 1));
+  std::vector<int32_t> tlb(n_triples), tn2(n_triples);
+  int64_t n_pairs = 0, n_cut = 0, n_incl = 0;
+#pragma omp parallel for schedule(dynamic, 4) reduction(+ : n_pairs, n_cut, n_incl)
   for (int64_t t = 0; t < n_triples; ++t) {
     const uint32_t tp = static_cast<uint32_t>(t / sh.m012), tc = static_cast<uint32_t>(t % sh.m012);
-    const uint32_t t0 = tc / sh.m12, t1 = (tc / sh.m[2]) % sh.m[1], t2 = tc % sh.m[2];
-    const Frame f = triple_frame(P[tp], sh.m, t0, t1, t2);
+    const Frame f = triple_frame(P[tp], sh.m, tc / sh.m12, (tc / sh.m[2]) % sh.m[1], tc % sh.m[2]);
     Iv Zr, Lr;
     centre_ranges(P[tp], sh.m, &Zr, &Lr);
-    std::vector<int32_t> nv(sh.m34, 0);
+    int32_t a = 0, c2 = 0;
     for (int32_t i = 0; i < n_hits; ++i) {
       const HitRec& h = rec[i];
-      if (!h.use) continue;
-      const Iv G = residual_G(f, h);
-      if (h.axial) {
-        if (h_contains0(G, f.K, f.sig * h.d, h.band) || h_contains0(G, f.K, f.sig * (-h.d), h.band))
-          for (uint32_t l = 0; l < sh.m34; ++l) ++nv[l];
-        continue;
+      uint8_t fl = 0;
+      if (h.use) {
+        const Iv G = residual_G(f, h);
+        if (h.axial) {
+          fl = (h_contains0(G, f.K, f.sig * h.d, h.band) || h_contains0(G, f.K, f.sig * (-h.d), h.band)) ? 1 : 0;
+        } else {
+          ++n_pairs;
+          if (f32 && !(f.R <= kR32Max)) fl = 1;
+          else if (!filter) fl = 2;
+          else {
+            const PairQ q = pair_quantities(f, h, G);
+            fl = static_cast<uint8_t>(f32 ? triple_vote_class32(q, f, h, Zr, Lr, slack32)
+                                          : triple_vote_class(q, f, h, Zr, Lr));
+          }
+          n_cut += fl == 0;
+          n_incl += fl == 1;
+        }
       }
-      if (f32 && !(f.R <= kR32Max)) {
-        for (uint32_t l = 0; l < sh.m34; ++l) ++nv[l];
-        continue;
-      }
-      const PairQ q = pair_quantities(f, h, G);
-      ++n_pairs;
-      const int cls = f32 ? triple_vote_class32(q, f, h, Zr, Lr, slack32) : triple_vote_class(q, f, h, Zr, Lr);
-      if (filter && cls == 0) { ++n_cut; continue; }
-      if (filter && cls == 1) {
-        ++n_incl;
-        for (uint32_t l = 0; l < sh.m34; ++l) ++nv[l];
-        continue;
-      }
-      const PairQ32 q32 = pair_q32(q, h, slack32);
+      cls[size_t(t) * n_hits + i] = fl;
+      a += fl == 1;
+      c2 += fl == 2;
+    }
+    tlb[t] = a;
+    tn2[t] = c2;
+  }
+  int32_t T = 0;
+  if (prune_k > 0) {
+    std::vector<int64_t> h(n_hits + 1, 0);
+    for (int64_t t = 0; t < n_triples; ++t) h[std::min(tlb[t], n_hits)] += 1;
+    const int64_t k_eff = std::min<int64_t>(prune_k, int64_t(sh.n_boxes));
+    int64_t cum = 0;
+    for (int32_t v = n_hits; v >= 0; --v) {
+      cum += h[v] * sh.m34;
+      if (cum >= k_eff) { T = v; break; }
+    }
+  }
+  int64_t n_evals = 0, n_yes = 0, n_full = 0, n_live = 0;
+#pragma omp parallel for schedule(dynamic, 4) reduction(+ : n_evals, n_yes, n_full, n_live)
+  for (int64_t t = 0; t < n_triples; ++t) {
+    const uint32_t tp = static_cast<uint32_t>(t / sh.m012), tc = static_cast<uint32_t>(t % sh.m012);
+    const int64_t base = int64_t(tp) * sh.nc + int64_t(tc) * sh.m34;
+    std::vector<int32_t> nv(sh.m34, tlb[t]);
+    if (tn2[t] > 0 && tlb[t] + tn2[t] >= T) {
+      ++n_live;
+      const Frame f = triple_frame(P[tp], sh.m, tc / sh.m12, (tc / sh.m[2]) % sh.m[1], tc % sh.m[2]);
       const float R32 = static_cast<float>(f.R), sig32 = static_cast<float>(f.sig);
       const Iv32 K32 = to32(f.K);
-      int64_t yes_here = 0;
-      for (uint32_t l = 0; l < sh.m34; ++l) {
-        const uint32_t k3 = l / sh.m[4], k4 = l % sh.m[4];
-        double zlo, zhi, llo, lhi;
-        child_edge(P[tp].lo[3], P[tp].hi[3], sh.m[3], k3, &zlo, &zhi);
-        child_edge(P[tp].lo[4], P[tp].hi[4], sh.m[4], k4, &llo, &lhi);
-        const double z0 = 0.5 * (zlo + zhi), lam = 0.5 * (llo + lhi);
-        ++n_evals;
-        bool v;
-        if (f32) {
-          const float z032 = static_cast<float>(z0), lam32 = static_cast<float>(lam);
-          v = stereo_vote32(q32, R32, sig32, K32, z032, lam32, lam32 * R32, lam32 * lam32);
-        } else {
-          v = stereo_vote(q, f.R, f.sig, f.K, z0, lam, lam * f.R, lam * lam, h.tant, h.tant * h.tant, h.d, h.band);
+      for (int32_t i = 0; i < n_hits; ++i) {
+        if (cls[size_t(t) * n_hits + i] != 2) continue;
+        const HitRec& h = rec[i];
+        const Iv G = residual_G(f, h);
+        const PairQ q = pair_quantities(f, h, G);
+        const PairQ32 q32 = pair_q32(q, h, slack32);
+        int64_t yes_here = 0;
+        for (uint32_t l = 0; l < sh.m34; ++l) {
+          const uint32_t k3 = l / sh.m[4], k4 = l % sh.m[4];
+          double zlo, zhi, llo, lhi;
+          child_edge(P[tp].lo[3], P[tp].hi[3], sh.m[3], k3, &zlo, &zhi);
+          child_edge(P[tp].lo[4], P[tp].hi[4], sh.m[4], k4, &llo, &lhi);
+          const double z0 = 0.5 * (zlo + zhi), lam = 0.5 * (llo + lhi);
+          ++n_evals;
+          bool v;
+          if (f32) {
+            const float z032 = static_cast<float>(z0), lam32 = static_cast<float>(lam);
+            v = stereo_vote32(q32, R32, sig32, K32, z032, lam32, lam32 * R32, lam32 * lam32);
+          } else {
+            v = stereo_vote(q, f.R, f.sig, f.K, z0, lam, lam * f.R, lam * lam, h.tant, h.tant * h.tant, h.d, h.band);
+          }
+          if (v) { ++nv[l]; ++n_yes; ++yes_here; }
         }
-        if (v) { ++nv[l]; ++n_yes; ++yes_here; }
+        if (yes_here == int64_t(sh.m34)) ++n_full;
       }
-      if (yes_here == int64_t(sh.m34)) ++n_full;
     }
-    const int64_t base = int64_t(tp) * sh.nc + int64_t(tc) * sh.m34;
     for (uint32_t l = 0; l < sh.m34; ++l) votes[base + l] = static_cast<uint16_t>(nv[l]);
   }
   if (stats) {
     stats[0] = n_pairs; stats[1] = n_cut; stats[2] = n_evals; stats[3] = n_yes; stats[4] = n_full;
-    stats[5] = n_incl;
+    stats[5] = n_incl; stats[6] = n_live; stats[7] = T;
   }
   return 0;
 }

@@ -283,3 +283,19 @@ def test_batch_edge_events(ctx):
             assert np.array_equal(hel[e, h]["p"], ref[h]["p"]) and np.array_equal(hel[e, h]["err"], ref[h]["err"])
             assert hel[e, h]["n_assigned"] == ref[h]["n_assigned"]
         assert np.array_equal(ass[off[e]:off[e + 1]], ref_ass)
+
+
+def test_pruning_does_not_change_helices(ctx):
+    """find_helices with and without triple pruning: identical helices,
+    votes, hit assignments (multi-helix events, full schedule)."""
+    events = [toymc.config_event(4, i) for i in range(20, 26)]
+    sched = ia.Schedule.make(H.LO, H.HI, [16] * 5, n_helix_max=5)
+    hel_p, n_p, ass_p, _ = _run_gpu(ctx, events, sched, 5)
+    ctx.set_pruning(False)
+    try:
+        hel_f, n_f, ass_f, _ = _run_gpu(ctx, events, sched, 5)
+    finally:
+        ctx.set_pruning(True)
+    assert np.array_equal(n_p, n_f) and np.array_equal(ass_p, ass_f)
+    for e in range(len(events)):
+        assert hel_p[e, :n_p[e]].tobytes() == hel_f[e, :n_f[e]].tobytes()

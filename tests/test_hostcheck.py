@@ -85,3 +85,37 @@ def test_inclusion_proof_catches_full_vote_pairs(orc, f32):
     v1, st1 = hostcheck.vote_level(ev.hits, parents, [4] * 5, True, f32=f32, slack=SLACK)
     assert np.array_equal(v1, orc.vote_level(ev.hits, parents, [4] * 5, prec=prec, slack=SLACK))
     assert st1[5] > 10 * st1[2] / 16
+
+
+def _topk(votes, k):
+    order = np.lexsort((np.arange(votes.size), -votes.astype(np.int64)))
+    return order[:k], votes[order[:k]]
+
+
+@pytest.mark.parametrize("f32", [False, True])
+@pytest.mark.parametrize("cfg,ev_i", [(2, 0), (4, 3), (5, 4)])
+def test_pruning_keeps_selection(orc, cfg, ev_i, f32):
+    """With triples pruned by their vote bounds, the top-32 boxes (votes
+    desc, index asc), their votes, the maximum and the max-vote set equal the
+    oracle's exhaustive level; every box holds at most its exact vote; few
+    triples are evaluated."""
+    ev = toymc.config_event(cfg, ev_i)
+    root = orc.make_box(H.LO, H.HI)
+    prec = orc.FP32 if f32 else orc.FP64
+    k = 32
+    levels = [(np.atleast_1d(root), [10] * 5)]
+    ref0 = orc.vote_level(ev.hits, root, [10] * 5, prec=prec, slack=SLACK)
+    top0, _ = _topk(ref0, k)
+    levels.append((np.array([orc.box_child(root, [10] * 5, int(b)) for b in top0]), [4] * 5))
+    for parents, split in levels:
+        ref = orc.vote_level(ev.hits, parents, split, prec=prec, slack=SLACK)
+        got, st = hostcheck.vote_level(ev.hits, parents, split, True, f32=f32, slack=SLACK, prune_k=k)
+        assert np.all(got <= ref)
+        ti_r, tv_r = _topk(ref, k)
+        ti_g, tv_g = _topk(got, k)
+        assert np.array_equal(ti_r, ti_g) and np.array_equal(tv_r, tv_g)
+        vmax = ref.max()
+        assert got.max() == vmax
+        assert np.array_equal(np.flatnonzero(got == vmax), np.flatnonzero(ref == vmax))
+        n_tr = parents.size * int(np.prod(split[:3]))
+        assert st[6] < 0.5 * n_tr, (st[6], n_tr)
