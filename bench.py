@@ -1,15 +1,17 @@
 #!/usr/bin/env python3
 """Benchmark of the interval-arithmetic helix vote on one MI355X.
 
-Workload (one step = one event through the whole search, FP64):
-  a single-helix event of the synthetic stereo chamber (20 layers, 0/+60/-60
-  mrad superlayers, B = 1 T), drift radii smeared by 150 um, 20 % extra noise
-  hits, tolerance band 3 sigma; level-0 grid 16^5 over d0 [-5, 5] mm,
-  phi0 [0, 2 pi], kappa [-0.6, 0.6] 1/m, z0 [-5, 5] cm, tanl [-0.8, 0.8];
-  four refinement levels, each keeping the 32 max-vote boxes and splitting
-  them 4^5; estimate from the max-vote boxes; hit finding.
-Each step uses a different seeded event; all hits are resident in HBM
-before the timed region.
+Workload (one step = one ia_find_helices call over --event-batch events,
+default 1024, through the whole search, FP64):
+  single-helix events of the synthetic stereo chamber (20 layers,
+  0/+60/-60 mrad superlayers, B = 1 T), drift radii smeared by 150 um, 20 %
+  extra noise hits, tolerance band 3 sigma; level-0 grid 16^5 over d0
+  [-5, 5] mm, phi0 [0, 2 pi], kappa [-0.6, 0.6] 1/m, z0 [-5, 5] cm, tanl
+  [-0.8, 0.8]; four refinement levels, each keeping the 32 max-vote boxes
+  and splitting them 4^5; estimate from the max-vote boxes; hit finding.
+Each step uses different seeded events; all hits are resident in HBM
+before the timed region.  p50/p99 are per-event latencies of single-event
+calls made after the timed steps.
 
 With --workload batch, one step is instead a batch of 4096 events (1-5
 helices, 20-200 hits, 0-30 % noise, the same schedule with up to 5 greedy
@@ -168,12 +170,16 @@ def cpu_baseline(events, sched_kw, lo, hi, budget_s=20.0):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--workload", choices=["event", "batch", "serve"], default="event")
     ap.add_argument("--batch-events", type=int, default=4096)
+    ap.add_argument("--event-batch", type=int, default=1024,
+                    help="single-helix workload: events per ia_find_helices call (one step)")
+    ap.add_argument("--latency-events", type=int, default=40,
+                    help="single-helix workload: single-event calls timed for p50/p99 latency")
     ap.add_argument("--scratch-gb", type=float, default=8.0)
     ap.add_argument("--serve-events", type=int, default=4096)
     ap.add_argument("--rate", type=float, default=20000.0, help="serving: Poisson arrival rate, events/s")
@@ -196,85 +202,115 @@ def main():
         return run_batch(args)
     if args.workload == "serve":
         return run_serve(args)
+    return run_event(args)
+
+
+def run_event(args):
+    """The single-helix workload (16^5 grid, 4 refinement levels, FP64 or
+    mixed): each step is one ia_find_helices call over --event-batch events;
+    then single-event calls give the per-event latency."""
+    import torch
+
+    import paper_2401_04576_amd as ia
+    from paper_2401_04576_amd import toymc
+
     dev = torch.device("cuda:0")
     lo, hi = np.array(toymc.GRID_RANGE_LO), np.array(toymc.GRID_RANGE_HI)
     sched_kw = dict(bins=[16] * 5, n_refine=4, top_k=32, split=[4] * 5, v_min=10, n_helix_max=1)
     prec = sched_prec(args.prec, sched_kw["n_refine"])
-    n_ev = args.warmup + args.steps
+    B = max(1, args.event_batch)
+    n_lat = args.latency_events
+    n_ev = (args.warmup + args.steps) * B + n_lat
     t_gen = time.perf_counter()
     events = generate(2, range(n_ev))
     t_gen = time.perf_counter() - t_gen
-    hits_np = np.concatenate([e.hits for e in events])
-    off = np.concatenate([[0], np.cumsum([e.n_hits for e in events])]).astype(np.int64)
-    hits = torch.from_numpy(hits_np.view(np.float64).reshape(-1, 8).copy()).to(dev)
     sched = ia.Schedule.make(lo, hi, prec=prec, **sched_kw)
     max_hits = max(e.n_hits for e in events)
-    ctx = ia.Context(0, scratch_bytes=ia.Context.scratch_needed(sched, max_hits) + (1 << 20))
-    out = torch.zeros(n_ev * ia.HELIX_DTYPE.itemsize, dtype=torch.uint8, device=dev)
-    n_out = torch.zeros(n_ev, dtype=torch.int32, device=dev)
-    assigned = torch.full((hits.shape[0],), -1, dtype=torch.int32, device=dev)
-    stream = torch.cuda.current_stream()
+    per_event = ia.Context.scratch_needed(sched, max_hits)
+    ctx = ia.Context(0, scratch_bytes=min(int(args.scratch_gb * (1 << 30)), per_event * B * 2) + (16 << 20))
     HB = ia.HELIX_DTYPE.itemsize
+    stream = torch.cuda.current_stream()
+    batches = []
+    for k in range(args.warmup + args.steps):
+        evs = events[k * B:(k + 1) * B]
+        h = np.concatenate([e.hits for e in evs])
+        off = np.concatenate([[0], np.cumsum([e.n_hits for e in evs])]).astype(np.int64)
+        batches.append((evs, torch.from_numpy(h.view(np.float64).reshape(-1, 8).copy()).to(dev), off,
+                        torch.zeros(B * HB, dtype=torch.uint8, device=dev),
+                        torch.zeros(B, dtype=torch.int32, device=dev),
+                        torch.full((h.shape[0],), -1, dtype=torch.int32, device=dev)))
 
-    def step(i):
-        a, b = int(off[i]), int(off[i + 1])
-        ia.find_helices(ctx, hits[a:b], [0, b - a], sched, max_per_event=1, stream=stream,
-                        out=out[i * HB:(i + 1) * HB], n_out=n_out[i:i + 1], assigned=assigned[a:b])
+    def step(k):
+        evs, hits, off, out, n_out, assigned = batches[k]
+        ia.find_helices(ctx, hits, off, sched, max_per_event=1, stream=stream, out=out, n_out=n_out,
+                        assigned=assigned)
 
-    for i in range(args.warmup):
-        step(i)
+    for k in range(args.warmup):
+        step(k)
     torch.cuda.synchronize()
     ctx.profile_read()
     ctx.clear_status()
-    starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
-    ends = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
     ctx.set_profiling(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for k in range(args.steps):
-        starts[k].record(stream)
-        step(args.warmup + k)
-        ends[k].record(stream)
+    for k in range(args.warmup, args.warmup + args.steps):
+        step(k)
     torch.cuda.synchronize()
-    t1 = time.perf_counter()
+    wall = time.perf_counter() - t0
     ctx.set_profiling(False)
     prof = ctx.profile_read()
     work = ctx.work()
-    n_launch = prof[0] + prof[2]
-    lat = np.array([s.elapsed_time(e) for s, e in zip(starts, ends)])
-    wall = t1 - t0
 
-    # work actually done: a pass stops after level 0 when its max vote is below v_min
-    nout = n_out.cpu().numpy()
+    # work of the schedule: a pass that stops at level 0 (maximum below
+    # v_min) has level 0 only
     shapes = level_shapes(sched_kw["bins"], sched_kw["top_k"], sched_kw["split"], sched_kw["n_refine"])
-    evals, launches = 0.0, 0
-    for k in range(args.steps):
-        i = args.warmup + k
-        n, n_st = hit_counts(events[i].hits)
-        levels = shapes if nout[i] > 0 else shapes[:1]
-        for nb, ntr in levels:
-            evals += float(nb) * n
-            launches += 1
-    assert launches == n_launch, (launches, n_launch)
-    value = evals / wall
+    evals, found = 0.0, 0
+    for k in range(args.warmup, args.warmup + args.steps):
+        evs, _, _, _, n_out, _ = batches[k]
+        nout = n_out.cpu().numpy()
+        for e, ev in enumerate(evs):
+            n, _ = hit_counts(ev.hits)
+            levels = shapes if nout[e] > 0 else shapes[:1]
+            evals += sum(float(nb) * n for nb, _ in levels)
+            found += int(nout[e])
+
+    # per-event latency: single-event calls, each timed on its own
+    lat = []
+    if n_lat:
+        lat_evs = events[(args.warmup + args.steps) * B:]
+        hl = [torch.from_numpy(e.hits.view(np.float64).reshape(-1, 8).copy()).to(dev) for e in lat_evs]
+        o1 = torch.zeros(HB, dtype=torch.uint8, device=dev)
+        n1 = torch.zeros(1, dtype=torch.int32, device=dev)
+        for i, h in enumerate(hl):
+            a1 = torch.full((h.shape[0],), -1, dtype=torch.int32, device=dev)
+            torch.cuda.synchronize()
+            ts = time.perf_counter()
+            ia.find_helices(ctx, h, [0, h.shape[0]], sched, max_per_event=1, stream=stream, out=o1, n_out=n1,
+                            assigned=a1)
+            torch.cuda.synchronize()
+            if i >= 3:
+                lat.append((time.perf_counter() - ts) * 1e3)
+    n_done = B * args.steps
     res = {
-        "metric": METRIC, "value": value, "unit": "box-hit evals/s", "n_gpus": 1, "steps": args.steps,
+        "metric": METRIC, "value": evals / wall, "unit": "box-hit evals/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": wall / args.steps * 1e3, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64" if args.prec == "fp64" else "f32+f64",
         "data": "synthetic",
-        "config": {"workload": "single event, hierarchical refinement, "
+        "config": {"workload": f"single-helix events, {B} per ia_find_helices call, hierarchical refinement, "
                                + ("FP64" if args.prec == "fp64" else "FP32 at levels 0-2, FP64 at 3-4 and the fit")
-                               + ": 1 helix, 150 um smearing, "
-                               "20% noise hits, band 3 sigma; 16^5 level-0 grid then 4 levels of top-32 "
-                               "boxes split 4^5; estimate and hit finding",
-                   "events": args.steps, "mean_hits": float(np.mean([e.n_hits for e in events[args.warmup:]])),
-                   "boxes_per_event": int(sum(nb for nb, _ in shapes))},
-        "events_per_s": args.steps / wall,
-        "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+                               + ": 20 layers, 150 um smearing, 20% noise hits, band 3 sigma; 16^5 level-0 grid "
+                               "then 4 levels of top-32 boxes split 4^5; estimate and hit finding",
+                   "events_per_step": B, "mean_hits": float(np.mean([e.n_hits for e in events])),
+                   "boxes_per_event": int(sum(nb for nb, _ in shapes)),
+                   "helices_found_per_event": found / n_done},
+        "events_per_s": n_done / wall,
+        "p50_ms": float(np.percentile(lat, 50)) if lat else None,
+        "p99_ms": float(np.percentile(lat, 99)) if lat else None,
+        "latency": "p50/p99: one event per call, arrival of resident hits to its recorded helix",
         "roofline": roofline(prof, work, wall),
     }
     if not args.no_cpu_baseline:
-        res["cpu_baseline"] = cpu_baseline(events[args.warmup:], sched_kw, lo, hi, args.cpu_budget)
+        res["cpu_baseline"] = cpu_baseline(batches[args.warmup][0], sched_kw, lo, hi, args.cpu_budget)
     ctx.close()
     print(f"[bench] generated {n_ev} events in {t_gen:.1f} s; vote kernel {prof[1] + prof[3]:.2f} ms of "
           f"{wall * 1e3:.2f} ms", file=sys.stderr)

@@ -54,7 +54,7 @@ struct EventState {
   int32_t n_assigned;           // hits assigned by the last hit finding
   int32_t n_argmax;             // size of the max-vote set of the last level
   int32_t t_prune;              // vote threshold of the current level's pruning (0: none)
-  int32_t pad;
+  int32_t n_live;               // vote tiles of the current level holding a box that can be selected
   double p[5], err[5];          // last estimate
 };
 
@@ -265,35 +265,41 @@ IA_HD bool stereo_vote(const PairQ& q, double R, double sig, Iv K, double z0,
 // operation is inclusion-monotone, so if the H test fails for the widened
 // enclosure it fails for every box: the pair casts no vote anywhere in the
 // triple.  Returns false when no finite enclosure is available.
-IA_HD bool e_enclosure_dom(const PairQ& q, double R, double sig, double tt, double t2, double dS, Iv Z, Iv L,
+IA_HD bool e_enclosure_dom(const PairQ& q, double R, double sig, double tt, double t2, Iv DS, Iv Z, Iv L,
                            Iv* out, Iv* eps_out, Iv* disc_out, Iv* a_out) {
-  const Iv ZA = iadd(Z, imul(L, ipt(q.sArc)));
-  const Iv ZAs = imul(ZA, ipt(q.sinA));
+  const Iv ZA = iadd(Z, imul_pt(L, q.sArc));
+  const Iv ZAs = imul_pt(ZA, q.sinA);
   const Iv ZA2 = isqr(ZA);
   const Iv LZA = imul(L, ZA);
-  const Iv LR = imul(L, ipt(R));
+  const Iv LR = imul_pt(L, R);
   const Iv L2 = isqr(L);
-  const Iv PHI1 = ineg(idivp(iadd(ZAs, imul(imul(L, ipt(dS)), ipt(q.cosA))), q.RAx));
+  const Iv PHI1 = ineg(idivp(iadd(ZAs, imul_pt(imul(L, DS), q.cosA)), q.RAx));
   const Iv P2a = imul(LR, ZA);
-  const Iv P2b = imul(imul(LZA, isub(ipt(R), ipt(2.0 * dS))), ipt(q.c2));
-  const Iv inner = iadd(ipt(q.RAx), imul(L2, isub(ipt(q.RpRAx), ipt(dS))));
-  const Iv P2c = imul(iadd(ZA2, imul(ipt(dS), inner)), ipt(q.s2));
+  const Iv P2b = imul_pt(imul(LZA, isub(ipt(R), itwice(DS))), q.c2);
+  const Iv inner = iadd(ipt(q.RAx), imul(L2, isub(ipt(q.RpRAx), DS)));
+  const Iv P2c = imul_pt(iadd(ZA2, imul(DS, inner)), q.s2);
   const Iv PHI2 = idivp(iadd(isub(P2a, P2b), P2c), q.twoRAx2);
-  const Iv EPS = iadd(imul(PHI1, ipt(tt)), imul(PHI2, ipt(t2)));
+  const Iv EPS = iadd(imul_pt(PHI1, tt), imul_pt(PHI2, t2));
   *eps_out = EPS;
   if (!(fabs(EPS.lo) < 1e5 && fabs(EPS.hi) < 1e5)) return false;
-  const Iv SE = sin_encl(EPS.lo, EPS.hi), CE = cos_encl(EPS.lo, EPS.hi);
-  const Iv SINP = iadd(imul(ipt(q.sinA), CE), imul(ipt(q.cosA), SE));
-  const Iv COSP = isub(imul(ipt(q.cosA), CE), imul(ipt(q.sinA), SE));
-  const Iv U2 = iadd(iadd(iadd(ipt(1.0), imul(imul(itwice(L), SINP), ipt(tt))), imul(L2, ipt(t2))),
-                     imul(isqr(COSP), ipt(t2)));
+  Iv SE, CE;
+  if (fabs(EPS.lo) <= kSmallTrig && fabs(EPS.hi) <= kSmallTrig) {
+    sincos_encl_small(EPS, &SE, &CE);
+  } else {
+    SE = sin_encl(EPS.lo, EPS.hi);
+    CE = cos_encl(EPS.lo, EPS.hi);
+  }
+  const Iv SINP = iadd(imul_pt(CE, q.sinA), imul_pt(SE, q.cosA));
+  const Iv COSP = isub(imul_pt(CE, q.cosA), imul_pt(SE, q.sinA));
+  const Iv U2 = iadd(iadd(iadd(ipt(1.0), imul_pt(imul(itwice(L), SINP), tt)), imul_pt(L2, t2)),
+                     imul_pt(isqr(COSP), t2));
   if (!(U2.lo > 0.0)) return false;
-  const Iv DELTA = idiv_pos(ipt(dS), isqrt(U2));
-  const Iv SPERP = imul(ipt(R), iadd(ipt(q.dphi), EPS));
-  const Iv ZS = isub(iadd(Z, imul(L, SPERP)), imul(imul(DELTA, COSP), ipt(tt)));
+  const Iv DELTA = idiv_pos2(DS, isqrt(U2));
+  const Iv SPERP = imul_pt(iadd(ipt(q.dphi), EPS), R);
+  const Iv ZS = isub(iadd(Z, imul(L, SPERP)), imul_pt(imul(DELTA, COSP), tt));
   const Iv LD = imul(L, DELTA);
-  const Iv CTAU = isub(imul(ZS, ipt(q.cAx)), imul(LD, ipt(q.sAx)));
-  const Iv Q = iadd(iadd(imul(itwice(CTAU), ipt(tt)), isqr(imul(ZS, ipt(tt)))), isqr(imul(LD, ipt(tt))));
+  const Iv CTAU = isub(imul_pt(ZS, q.cAx), imul_pt(LD, q.sAx));
+  const Iv Q = iadd(iadd(imul_pt(itwice(CTAU), tt), isqr(imul_pt(ZS, tt))), isqr(imul_pt(LD, tt)));
   const Iv A = iadd(ipt(R), DELTA);
   const Iv DISC = isub(isqr(A), Q);
   *disc_out = DISC;
@@ -301,7 +307,7 @@ IA_HD bool e_enclosure_dom(const PairQ& q, double R, double sig, double tt, doub
   if (!(DISC.hi >= 0.0)) return false;
   const Iv DEN = iadd(A, isqrt(DISC));
   if (!(DEN.lo > 0.0)) return false;
-  const Iv DHAT = isub(DELTA, idiv_pos(Q, DEN));
+  const Iv DHAT = isub(DELTA, idiv_pos2(Q, DEN));
   const Iv E = sig > 0.0 ? DHAT : ineg(DHAT);
   const double m = 1e-9 * fmax(fabs(E.lo), fabs(E.hi)) + 1e-12;
   *out = {wdn(E.lo - m), wup(E.hi + m)};
@@ -310,7 +316,7 @@ IA_HD bool e_enclosure_dom(const PairQ& q, double R, double sig, double tt, doub
 
 IA_HD bool e_enclosure(const PairQ& q, double R, double sig, double tt, double t2, double dS, Iv Z, Iv L, Iv* out) {
   Iv eps, disc, a;
-  return e_enclosure_dom(q, R, sig, tt, t2, dS, Z, L, out, &eps, &disc, &a);
+  return e_enclosure_dom(q, R, sig, tt, t2, ipt(dS), Z, L, out, &eps, &disc, &a);
 }
 
 // Inclusion: a proof that the per-box test votes for every point value e
@@ -345,14 +351,28 @@ IA_HD int triple_vote_class(const PairQ& q, const Frame& f, const HitRec& h, Iv 
   const Iv G = {q.Glo, q.Ghi};
   const double tt = h.tant, t2 = tt * tt;
   bool may = false;
-  for (int si = 0; si < 2; ++si) {
-    const double dS = si == 0 ? h.d : -h.d;
+  // pass -1: both drift signs at once (drift in [-d, d]), where most
+  // excluded pairs end; passes 0 and 1: each sign.  One loop body, kept
+  // rolled, holds the enclosure's registers once.
+#pragma unroll 1
+  for (int si = -1; si < 2; ++si) {
+    const Iv DS = si < 0 ? Iv{-h.d, h.d} : ipt(si == 0 ? h.d : -h.d);
     Iv E, EPS, DISC, A;
-    if (!e_enclosure_dom(q, f.R, f.sig, tt, t2, dS, Z, L, &E, &EPS, &DISC, &A)) { may = true; continue; }
-    if (DISC.lo > 0.25 * A.lo * A.lo && A.lo > 0.0 && votes_everywhere(G, f.K, E.lo, E.hi, h.band)) return 1;
-    const Iv Eb = {wdn(E.lo - h.band), wup(E.hi + h.band)};
-    const Iv Hb = isub(itwice(G), iadd(itwice(Eb), imul(f.K, isqr(Eb))));
-    if (Hb.lo <= 0.0 && 0.0 <= Hb.hi) may = true;
+    const bool ok = e_enclosure_dom(q, f.R, f.sig, tt, t2, DS, Z, L, &E, &EPS, &DISC, &A);
+    if (si >= 0 && ok && DISC.lo > 0.25 * A.lo * A.lo && A.lo > 0.0 &&
+        votes_everywhere(G, f.K, E.lo, E.hi, h.band))
+      return 1;
+    bool in = true;                      // the test cannot be excluded on this pass
+    if (ok) {
+      const Iv Eb = {wdn(E.lo - h.band), wup(E.hi + h.band)};
+      const Iv Hb = isub(itwice(G), iadd(itwice(Eb), imul(f.K, isqr(Eb))));
+      in = Hb.lo <= 0.0 && 0.0 <= Hb.hi;
+    }
+    if (si < 0) {
+      if (!in) return 0;
+    } else if (in) {
+      may = true;
+    }
   }
   return may ? 2 : 0;
 }
@@ -446,18 +466,29 @@ IA_HD int triple_vote_class32(const PairQ& q, const Frame& f, const HitRec& h, I
   const float bs2 = wup32(ru32(h.band) + 2.0f * slack32);
   const double tt = h.tant, t2 = tt * tt;
   bool may = false;
-  for (int si = 0; si < 2; ++si) {
-    const double dS = si == 0 ? h.d : -h.d;
+  // pass -1: both drift signs at once; passes 0 and 1: each sign (one
+  // rolled loop body, as in triple_vote_class)
+#pragma unroll 1
+  for (int si = -1; si < 2; ++si) {
+    const Iv DS = si < 0 ? Iv{-h.d, h.d} : ipt(si == 0 ? h.d : -h.d);
     Iv E, EPS, DISC, A;
-    if (!e_enclosure_dom(q, f.R, f.sig, tt, t2, dS, Z, L, &E, &EPS, &DISC, &A)) { may = true; continue; }
-    if (DISC.lo > 0.25 * A.lo * A.lo && A.lo > 0.0 &&
+    const bool ok = e_enclosure_dom(q, f.R, f.sig, tt, t2, DS, Z, L, &E, &EPS, &DISC, &A);
+    if (si >= 0 && ok && DISC.lo > 0.25 * A.lo * A.lo && A.lo > 0.0 &&
         votes_everywhere(Iv{G.lo, G.hi}, Iv{K.lo, K.hi}, wdn(E.lo - slack32), wup(E.hi + slack32), bs))
       return 1;
-    if (!(fabs(EPS.lo) <= 0.99 && fabs(EPS.hi) <= 0.99)) { may = true; continue; }
-    if (!(DISC.lo > 1e-3 * A.hi * A.hi)) { may = true; continue; }
-    const Iv32 Eb = {wdn32(rd32(E.lo) - bs2), wup32(ru32(E.hi) + bs2)};
-    const Iv32 Hb = isub32(itwice32(G), iadd32(itwice32(Eb), imul32(K, isqr32(Eb))));
-    if (Hb.lo <= 0.0f && 0.0f <= Hb.hi) may = true;
+    // excluded only when every box stays in the FP32 domain and the widened
+    // FP32 test fails over the whole enclosure
+    bool in = true;
+    if (ok && fabs(EPS.lo) <= 0.99 && fabs(EPS.hi) <= 0.99 && DISC.lo > 1e-3 * A.hi * A.hi) {
+      const Iv32 Eb = {wdn32(rd32(E.lo) - bs2), wup32(ru32(E.hi) + bs2)};
+      const Iv32 Hb = isub32(itwice32(G), iadd32(itwice32(Eb), imul32(K, isqr32(Eb))));
+      in = Hb.lo <= 0.0f && 0.0f <= Hb.hi;
+    }
+    if (si < 0) {
+      if (!in) return 0;
+    } else if (in) {
+      may = true;
+    }
   }
   return may ? 2 : 0;
 }
@@ -549,6 +580,23 @@ __device__ __forceinline__ int32_t block_scan(int32_t flag, int32_t* excl, int32
   return tot;
 }
 
+// block-wide exclusive scan of non-negative counts (kWG lanes); returns the total
+__device__ __forceinline__ int32_t block_scan_count(int32_t v, int32_t* excl, int32_t* sbuf) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  int32_t x = v;
+  for (int o = 1; o < 64; o <<= 1) {
+    const int32_t y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) sbuf[wv] = x;
+  __syncthreads();
+  int32_t off = 0, tot = 0;
+  for (int w = 0; w < kWG / 64; ++w) { if (w < wv) off += sbuf[w]; tot += sbuf[w]; }
+  __syncthreads();
+  *excl = off + x - v;
+  return tot;
+}
+
 __device__ __forceinline__ int32_t block_sum(int32_t v, int32_t* sbuf) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
   if ((threadIdx.x & 63) == 0) sbuf[threadIdx.x >> 6] = v;
@@ -637,37 +685,79 @@ __global__ void __launch_bounds__(kWG) k_classify(const HitRec* __restrict__ hit
 // such that at least k_eff = min(k, n_boxes) boxes have a lower bound >= v
 // (each triple holds m34 boxes), from the histogram of the triples' lower
 // bounds (in LDS, or in lbh -- zero on entry, cleared on exit -- when it has
-// more than kHistLds bins).  The k_eff-th box of the selection has at least
-// T votes, so a triple whose upper bound is below T holds no selected box
-// and no box of the maximum.
-__global__ void __launch_bounds__(kWG) k_threshold(const int32_t* __restrict__ tlb, uint32_t* __restrict__ lbh,
-                                                   EvView vw, Shape sh, int32_t k, EventState* __restrict__ ev) {
+// more than kHistLds bins); T = 0 without `prune`.  The k_eff-th box of the
+// selection has at least T votes, so a triple whose upper bound is below T
+// holds no selected box and no box of the maximum.  Then the vote tiles of
+// bx boxes holding a triple with upper bound >= T are listed in index order
+// (live_list, ev->n_live); the others get wg_max = -1 and are not voted.
+__global__ void __launch_bounds__(kWG) k_threshold(const int32_t* __restrict__ tlb, const int32_t* __restrict__ tn2,
+                                                   uint32_t* __restrict__ lbh, EvView vw, Shape sh, int32_t k,
+                                                   int32_t prune, int32_t bx, EventState* __restrict__ ev,
+                                                   int32_t* __restrict__ live_list, int32_t* __restrict__ wg_max) {
   const int e = blockIdx.y;
   if (ev[e].done) return;
   const int32_t n_bins = vw.count(e) + 1;
   const uint32_t n_tr = sh.n_parents * sh.m012;
   tlb += e * vw.tri_stride;
+  tn2 += e * vw.tri_stride;
+  live_list += int64_t(e) * vw.wg_stride;
+  wg_max += int64_t(e) * vw.wg_stride;
   __shared__ uint32_t sh_h[kHistLds];
-  uint32_t* hh = sh_h;
-  if (n_bins > kHistLds) hh = lbh + int64_t(e) * vw.hist_stride;
-  else
-    for (int32_t b = threadIdx.x; b < n_bins; b += kWG) sh_h[b] = 0u;
-  __syncthreads();
-  for (uint32_t t = threadIdx.x; t < n_tr; t += kWG) atomicAdd(&hh[min(tlb[t], n_bins - 1)], 1u);
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const int64_t k_eff = min(static_cast<int64_t>(k), static_cast<int64_t>(sh.n_boxes));
-    int64_t cum = 0;
-    int32_t T = 0;
-    for (int32_t v = n_bins - 1; v >= 0; --v) {
-      cum += static_cast<int64_t>(hh[v]) * sh.m34;
-      if (cum >= k_eff) { T = v; break; }
+  __shared__ int32_t s_T;
+  __shared__ int32_t sbuf[kWG / 64];
+  const uint32_t tid = threadIdx.x;
+  if (prune) {
+    uint32_t* hh = sh_h;
+    if (n_bins > kHistLds) hh = lbh + int64_t(e) * vw.hist_stride;
+    else
+      for (int32_t b = tid; b < n_bins; b += kWG) sh_h[b] = 0u;
+    __syncthreads();
+    for (uint32_t t = tid; t < n_tr; t += kWG) atomicAdd(&hh[min(tlb[t], n_bins - 1)], 1u);
+    __syncthreads();
+    if (tid == 0) {
+      const int64_t k_eff = min(static_cast<int64_t>(k), static_cast<int64_t>(sh.n_boxes));
+      int64_t cum = 0;
+      int32_t T = 0;
+      for (int32_t v = n_bins - 1; v >= 0; --v) {
+        cum += static_cast<int64_t>(hh[v]) * sh.m34;
+        if (cum >= k_eff) { T = v; break; }
+      }
+      s_T = T;
     }
-    ev[e].t_prune = T;
+    __syncthreads();
+    if (n_bins > kHistLds)
+      for (int32_t b = tid; b < n_bins; b += kWG) hh[b] = 0u;
+  } else if (tid == 0) {
+    s_T = 0;
   }
   __syncthreads();
-  if (n_bins > kHistLds)
-    for (int32_t b = threadIdx.x; b < n_bins; b += kWG) hh[b] = 0u;
+  const int32_t T = s_T;
+  // live tiles, compacted in index order: each thread takes a contiguous run
+  // of tiles, counts its live ones, and one block scan places them
+  auto triple_of = [&](uint32_t x) { return (x / sh.nc) * sh.m012 + (x % sh.nc) / sh.m34; };
+  const uint32_t n_tiles = (sh.n_boxes + static_cast<uint32_t>(bx) - 1) / static_cast<uint32_t>(bx);
+  const uint32_t per = (n_tiles + kWG - 1) / kWG;
+  const uint32_t ta = min(tid * per, n_tiles), tb = min(ta + per, n_tiles);
+  auto tile_live = [&](uint32_t tile) {
+    const uint32_t b0 = tile * static_cast<uint32_t>(bx);
+    const uint32_t b1 = min(b0 + static_cast<uint32_t>(bx), sh.n_boxes) - 1;
+    bool lv = false;
+    for (uint32_t t = triple_of(b0); t <= triple_of(b1) && !lv; ++t) lv = tlb[t] + tn2[t] >= T;
+    return lv;
+  };
+  int32_t mine = 0;
+  for (uint32_t tile = ta; tile < tb; ++tile) {
+    if (tile_live(tile)) ++mine;
+    else wg_max[tile] = -1;
+  }
+  int32_t pos;
+  const int32_t total = block_scan_count(mine, &pos, sbuf);
+  for (uint32_t tile = ta; tile < tb; ++tile)
+    if (tile_live(tile)) live_list[pos++] = static_cast<int32_t>(tile);
+  if (tid == 0) {
+    ev[e].t_prune = T;
+    ev[e].n_live = total;
+  }
 }
 
 // Top-k by (votes desc, index asc) of one level, one workgroup, run after
@@ -782,24 +872,26 @@ __global__ void __launch_bounds__(kWG) k_select_wg(const uint16_t* __restrict__ 
 }
 
 // ---------------------------------------------------------------------------
-// the vote kernel.  A workgroup owns BX consecutive boxes (one lane each) and
-// splits the hits of every chunk over kWG / BX slices (whole waves); the
-// slices' counts are summed in LDS.  Each box starts from its triple's lower
-// bound tlb (its class-1 pairs from k_classify, axial ones included); only
-// class-2 pairs are evaluated per box, and only in triples whose upper bound
-// tlb + tn2 reaches the event's pruning threshold (ev->t_prune with `prune`,
-// else 0).  A box of a pruned triple keeps its lower bound, which is below
-// the threshold.  Per chunk of hits, the workgroup stages the (triple, hit)
-// quantities of the class-2 pairs of its live triples in LDS.
-// hist (nullable) receives the vote histogram of bins 0..n_bins-1 and
-// wg_max (nullable) each workgroup's maximum vote, for k_select_wg.
+// the vote kernel.  The boxes of a level form tiles of BX consecutive boxes;
+// a workgroup takes one tile at a time (one box per lane), striding over the
+// event's live tiles (live_list[0 .. ev->n_live), from k_threshold) or, with
+// live_list null, over every tile.  Within a tile it splits each hit chunk
+// over kWG / BX slices (whole waves) whose counts are summed in LDS.  Each
+// box starts from its triple's lower bound tlb (its class-1 pairs from
+// k_classify, axial ones included); class-2 pairs are evaluated per box only
+// in triples whose upper bound tlb + tn2 reaches the event's pruning
+// threshold T (ev->t_prune, 0 without ev).  Per chunk of hits, the workgroup
+// stages the (triple, hit) quantities of those pairs in LDS.
+// Writes the votes of its tiles, each tile's maximum (wg_max) and, with
+// hist, the histogram of the votes >= T (the selection threshold is never
+// below T).  Tiles that are not live are neither written nor counted.
 template <int BX, bool F32>
 __global__ void __launch_bounds__(kWG) k_vote(const HitRec* __restrict__ hits, EvView vw,
                                               const BoxD* __restrict__ parents, Shape sh,
                                               uint16_t* __restrict__ votes, uint32_t* __restrict__ hist,
                                               uint32_t* __restrict__ status, const EventState* __restrict__ ev,
                                               const uint8_t* __restrict__ flags, const int32_t* __restrict__ tlb,
-                                              const int32_t* __restrict__ tn2, int32_t prune,
+                                              const int32_t* __restrict__ tn2, const int32_t* __restrict__ live_list,
                                               int32_t* __restrict__ wg_max, unsigned long long* __restrict__ work,
                                               float slack32) {
   constexpr int HS = kWG / BX;
@@ -815,8 +907,11 @@ __global__ void __launch_bounds__(kWG) k_vote(const HitRec* __restrict__ hits, E
   tlb += e * vw.tri_stride;
   tn2 += e * vw.tri_stride;
   if (wg_max) wg_max += int64_t(e) * vw.wg_stride;
-  const int32_t T = (prune && ev) ? ev[e].t_prune : 0;
+  if (live_list) live_list += int64_t(e) * vw.wg_stride;
+  const int32_t T = ev ? ev[e].t_prune : 0;
   const uint32_t n_tr = sh.n_parents * sh.m012;
+  const uint32_t n_tiles = (sh.n_boxes + BX - 1) / BX;
+  const uint32_t n_items = live_list ? static_cast<uint32_t>(ev[e].n_live) : n_tiles;
   __shared__ double sq[13][kCap + 16];
   // FP32 levels stage 16 floats per pair in the same storage
   static_assert(sizeof(PairQ32) == 16 * sizeof(float) && 16 * 4 <= 13 * 8, "FP32 staging fits");
@@ -828,104 +923,145 @@ __global__ void __launch_bounds__(kWG) k_vote(const HitRec* __restrict__ hits, E
   __shared__ int32_t sbuf[kWG / 64];
   const uint32_t tid = threadIdx.x;
   const uint32_t bl = tid % BX, sl = tid / BX;
-  const uint32_t b0 = blockIdx.x * BX;
-  const uint32_t b_last = min(b0 + BX, sh.n_boxes) - 1;
-  const uint32_t b = b0 + bl;
-  const bool live = b < sh.n_boxes;
-  const uint32_t bb = live ? b : b_last;
-
   // global triple index of a box: parent * m012 + (child / m34)
   auto triple_of = [&](uint32_t x) { return (x / sh.nc) * sh.m012 + (x % sh.nc) / sh.m34; };
-  const uint32_t t_first = triple_of(b0);
-  const int32_t nt = static_cast<int32_t>(triple_of(b_last) - t_first + 1);
-  const int32_t my_tl = static_cast<int32_t>(triple_of(bb) - t_first);
-  const int32_t hc = max(1, kCap / nt);          // hits per chunk
-  // LDS row pitch per triple: one padding slot when a few triples share a
-  // wave (avoids bank conflicts); nt * pitch <= kCap + 16 always holds.
-  const int32_t pitch = hc + ((nt > 1 && nt <= 16) ? 1 : 0);
+  int32_t n_eval = 0, n_staged = 0;
 
-  // triples of this workgroup that need per-box evaluation
-  int32_t any_live = 0;
-  for (int32_t i = tid; i < nt; i += kWG) {
-    const int32_t a = tlb[t_first + i], c = tn2[t_first + i];
-    const bool lv = c > 0 && a + c >= T;
-    stlive[i] = lv ? 1 : 0;
-    any_live |= lv ? 1 : 0;
-  }
-  any_live = __syncthreads_or(any_live);
+  for (uint32_t item = blockIdx.x; item < n_items; item += gridDim.x) {
+    const uint32_t tile = live_list ? static_cast<uint32_t>(live_list[item]) : item;
+    const uint32_t b0 = tile * BX;
+    const uint32_t b_last = min(b0 + BX, sh.n_boxes) - 1;
+    const uint32_t b = b0 + bl;
+    const bool live = b < sh.n_boxes;
+    const uint32_t bb = live ? b : b_last;
+    const uint32_t t_first = triple_of(b0);
+    const int32_t nt = static_cast<int32_t>(triple_of(b_last) - t_first + 1);
+    const int32_t my_tl = static_cast<int32_t>(triple_of(bb) - t_first);
+    const int32_t hc = max(1, kCap / nt);          // hits per chunk
+    // LDS row pitch per triple: one padding slot when a few triples share a
+    // wave (avoids bank conflicts); nt * pitch <= kCap + 16 always holds.
+    const int32_t pitch = hc + ((nt > 1 && nt <= 16) ? 1 : 0);
 
-  int32_t nv = sl == 0 ? tlb[t_first + my_tl] : 0, n_eval = 0, n_staged = 0;
-  if (any_live) {                      // uniform over the workgroup (barriers below)
-    // this lane's box: triple frame and (z0, tanl) centre
-    uint32_t k[5];
-    child_index(sh.m, bb % sh.nc, k);
-    const BoxD& P = parents[bb / sh.nc];
-    const Frame f = triple_frame(P, sh.m, k[0], k[1], k[2]);
-    double zlo, zhi, llo, lhi;
-    child_edge(P.lo[3], P.hi[3], sh.m[3], k[3], &zlo, &zhi);
-    child_edge(P.lo[4], P.hi[4], sh.m[4], k[4], &llo, &lhi);
-    const double z0 = 0.5 * (zlo + zhi), lam = 0.5 * (llo + lhi);
-    const double lamR = lam * f.R, lam2 = lam * lam;
-    // FP32 images of the lane's box (used at FP32 levels only)
-    const float R32 = static_cast<float>(f.R), sig32 = static_cast<float>(f.sig);
-    const Iv32 K32 = to32(f.K);
-    const float z032 = static_cast<float>(z0), lam32 = static_cast<float>(lam);
-    const float lamR32 = lam32 * R32, lam232 = lam32 * lam32;
+    __syncthreads();                     // LDS of the previous tile is free
+    // triples of this tile that need per-box evaluation
+    int32_t any_live = 0;
+    for (int32_t i = tid; i < nt; i += kWG) {
+      const int32_t a = tlb[t_first + i], c = tn2[t_first + i];
+      const bool lv = c > 0 && a + c >= T;
+      stlive[i] = lv ? 1 : 0;
+      any_live |= lv ? 1 : 0;
+    }
+    any_live = __syncthreads_or(any_live);
 
-    for (int32_t h0 = 0; h0 < n_hits; h0 += hc) {
-      const int32_t nh = min(hc, n_hits - h0);
-      __syncthreads();
-      // stage the class-2 pairs of live triples: thread r -> (tl = r / hc, hl = r % hc)
-      for (int32_t r = tid; r < nt * hc; r += kWG) {
-        const int32_t tl = r / hc, hl = r % hc;
-        const int32_t slot = tl * pitch + hl;
-        if (hl >= nh) continue;
-        const uint32_t t = t_first + tl;
-        if (!stlive[tl] || flags[int64_t(h0 + hl) * n_tr + t] != 2) { sflag[slot] = 0; continue; }
-        const HitRec h = hits[h0 + hl];
-        const uint32_t tc = t % sh.m012;
-        const uint32_t t0 = tc / sh.m12, t1 = (tc / sh.m[2]) % sh.m[1], t2 = tc % sh.m[2];
-        const Frame ft = triple_frame(parents[t / sh.m012], sh.m, t0, t1, t2);
-        const Iv G = residual_G(ft, h);
-        const PairQ q = pair_quantities(ft, h, G);
-        ++n_staged;
-        sflag[slot] = 2;
-        if constexpr (F32) {
-          const PairQ32 rq = pair_q32(q, h, slack32);
-          sq32[0][slot] = rq.Glo; sq32[1][slot] = rq.Ghi; sq32[2][slot] = rq.sArc; sq32[3][slot] = rq.dphi;
-          sq32[4][slot] = rq.RAx; sq32[5][slot] = rq.sinA; sq32[6][slot] = rq.cosA; sq32[7][slot] = rq.sAx;
-          sq32[8][slot] = rq.cAx; sq32[9][slot] = rq.c2; sq32[10][slot] = rq.s2; sq32[11][slot] = rq.twoRAx2;
-          sq32[12][slot] = rq.RpRAx; sq32[13][slot] = rq.tt; sq32[14][slot] = rq.d; sq32[15][slot] = rq.bs;
-        } else {
-          sq[0][slot] = q.Glo; sq[1][slot] = q.Ghi; sq[2][slot] = q.sArc; sq[3][slot] = q.dphi;
-          sq[4][slot] = q.RAx; sq[5][slot] = q.sinA; sq[6][slot] = q.cosA; sq[7][slot] = q.sAx;
-          sq[8][slot] = q.cAx; sq[9][slot] = q.c2; sq[10][slot] = q.s2; sq[11][slot] = q.twoRAx2;
-          sq[12][slot] = q.RpRAx;
+    int32_t nv = sl == 0 ? tlb[t_first + my_tl] : 0;
+    if (any_live) {                      // uniform over the workgroup (barriers below)
+      // this lane's box: triple frame and (z0, tanl) centre
+      uint32_t k[5];
+      child_index(sh.m, bb % sh.nc, k);
+      const BoxD& P = parents[bb / sh.nc];
+      const Frame f = triple_frame(P, sh.m, k[0], k[1], k[2]);
+      double zlo, zhi, llo, lhi;
+      child_edge(P.lo[3], P.hi[3], sh.m[3], k[3], &zlo, &zhi);
+      child_edge(P.lo[4], P.hi[4], sh.m[4], k[4], &llo, &lhi);
+      const double z0 = 0.5 * (zlo + zhi), lam = 0.5 * (llo + lhi);
+      const double lamR = lam * f.R, lam2 = lam * lam;
+      // FP32 images of the lane's box (used at FP32 levels only)
+      const float R32 = static_cast<float>(f.R), sig32 = static_cast<float>(f.sig);
+      const Iv32 K32 = to32(f.K);
+      const float z032 = static_cast<float>(z0), lam32 = static_cast<float>(lam);
+      const float lamR32 = lam32 * R32, lam232 = lam32 * lam32;
+
+      for (int32_t h0 = 0; h0 < n_hits; h0 += hc) {
+        const int32_t nh = min(hc, n_hits - h0);
+        __syncthreads();
+        // stage the class-2 pairs of live triples: thread r -> (tl = r / hc, hl = r % hc)
+        for (int32_t r = tid; r < nt * hc; r += kWG) {
+          const int32_t tl = r / hc, hl = r % hc;
+          const int32_t slot = tl * pitch + hl;
+          if (hl >= nh) continue;
+          const uint32_t t = t_first + tl;
+          if (!stlive[tl] || flags[int64_t(h0 + hl) * n_tr + t] != 2) { sflag[slot] = 0; continue; }
+          const HitRec h = hits[h0 + hl];
+          const uint32_t tc = t % sh.m012;
+          const uint32_t t0 = tc / sh.m12, t1 = (tc / sh.m[2]) % sh.m[1], t2 = tc % sh.m[2];
+          const Frame ft = triple_frame(parents[t / sh.m012], sh.m, t0, t1, t2);
+          const Iv G = residual_G(ft, h);
+          const PairQ q = pair_quantities(ft, h, G);
+          ++n_staged;
+          sflag[slot] = 2;
+          if constexpr (F32) {
+            const PairQ32 rq = pair_q32(q, h, slack32);
+            sq32[0][slot] = rq.Glo; sq32[1][slot] = rq.Ghi; sq32[2][slot] = rq.sArc; sq32[3][slot] = rq.dphi;
+            sq32[4][slot] = rq.RAx; sq32[5][slot] = rq.sinA; sq32[6][slot] = rq.cosA; sq32[7][slot] = rq.sAx;
+            sq32[8][slot] = rq.cAx; sq32[9][slot] = rq.c2; sq32[10][slot] = rq.s2; sq32[11][slot] = rq.twoRAx2;
+            sq32[12][slot] = rq.RpRAx; sq32[13][slot] = rq.tt; sq32[14][slot] = rq.d; sq32[15][slot] = rq.bs;
+          } else {
+            sq[0][slot] = q.Glo; sq[1][slot] = q.Ghi; sq[2][slot] = q.sArc; sq[3][slot] = q.dphi;
+            sq[4][slot] = q.RAx; sq[5][slot] = q.sinA; sq[6][slot] = q.cosA; sq[7][slot] = q.sAx;
+            sq[8][slot] = q.cAx; sq[9][slot] = q.c2; sq[10][slot] = q.s2; sq[11][slot] = q.twoRAx2;
+            sq[12][slot] = q.RpRAx;
+          }
+        }
+        __syncthreads();
+        if (!stlive[my_tl]) continue;
+        for (int32_t hl = sl; hl < nh; hl += HS) {
+          const int32_t slot = my_tl * pitch + hl;
+          if (sflag[slot] != 2) continue;
+          n_eval += live ? 1 : 0;
+          if constexpr (F32) {
+            PairQ32 r;
+            r.Glo = sq32[0][slot]; r.Ghi = sq32[1][slot]; r.sArc = sq32[2][slot]; r.dphi = sq32[3][slot];
+            r.RAx = sq32[4][slot]; r.sinA = sq32[5][slot]; r.cosA = sq32[6][slot]; r.sAx = sq32[7][slot];
+            r.cAx = sq32[8][slot]; r.c2 = sq32[9][slot]; r.s2 = sq32[10][slot]; r.twoRAx2 = sq32[11][slot];
+            r.RpRAx = sq32[12][slot]; r.tt = sq32[13][slot]; r.d = sq32[14][slot]; r.bs = sq32[15][slot];
+            if (stereo_vote32(r, R32, sig32, K32, z032, lam32, lamR32, lam232)) ++nv;
+          } else {
+            const HitRec& h = hits[h0 + hl];
+            PairQ q;
+            q.Glo = sq[0][slot]; q.Ghi = sq[1][slot]; q.sArc = sq[2][slot]; q.dphi = sq[3][slot];
+            q.RAx = sq[4][slot]; q.sinA = sq[5][slot]; q.cosA = sq[6][slot]; q.sAx = sq[7][slot];
+            q.cAx = sq[8][slot]; q.c2 = sq[9][slot]; q.s2 = sq[10][slot]; q.twoRAx2 = sq[11][slot];
+            q.RpRAx = sq[12][slot];
+            const double tt = h.tant;
+            if (stereo_vote(q, f.R, f.sig, f.K, z0, lam, lamR, lam2, tt, tt * tt, h.d, h.band)) ++nv;
+          }
         }
       }
+    }
+    if (HS > 1) {
       __syncthreads();
-      if (!stlive[my_tl]) continue;
-      for (int32_t hl = sl; hl < nh; hl += HS) {
-        const int32_t slot = my_tl * pitch + hl;
-        if (sflag[slot] != 2) continue;
-        n_eval += live ? 1 : 0;
-        if constexpr (F32) {
-          PairQ32 r;
-          r.Glo = sq32[0][slot]; r.Ghi = sq32[1][slot]; r.sArc = sq32[2][slot]; r.dphi = sq32[3][slot];
-          r.RAx = sq32[4][slot]; r.sinA = sq32[5][slot]; r.cosA = sq32[6][slot]; r.sAx = sq32[7][slot];
-          r.cAx = sq32[8][slot]; r.c2 = sq32[9][slot]; r.s2 = sq32[10][slot]; r.twoRAx2 = sq32[11][slot];
-          r.RpRAx = sq32[12][slot]; r.tt = sq32[13][slot]; r.d = sq32[14][slot]; r.bs = sq32[15][slot];
-          if (stereo_vote32(r, R32, sig32, K32, z032, lam32, lamR32, lam232)) ++nv;
-        } else {
-          const HitRec& h = hits[h0 + hl];
-          PairQ q;
-          q.Glo = sq[0][slot]; q.Ghi = sq[1][slot]; q.sArc = sq[2][slot]; q.dphi = sq[3][slot];
-          q.RAx = sq[4][slot]; q.sinA = sq[5][slot]; q.cosA = sq[6][slot]; q.sAx = sq[7][slot];
-          q.cAx = sq[8][slot]; q.c2 = sq[9][slot]; q.s2 = sq[10][slot]; q.twoRAx2 = sq[11][slot];
-          q.RpRAx = sq[12][slot];
-          const double tt = h.tant;
-          if (stereo_vote(q, f.R, f.sig, f.K, z0, lam, lamR, lam2, tt, tt * tt, h.d, h.band)) ++nv;
-        }
+      sred[sl][bl] = nv;
+      __syncthreads();
+      if (sl == 0)
+        for (int s = 1; s < HS; ++s) nv += sred[s][bl];
+    }
+    const bool owner = sl == 0 && live;
+    if (owner) votes[b] = static_cast<uint16_t>(nv);
+    // tile maximum (read by the selection kernel and used below)
+    int32_t mv = owner ? nv : -1;
+    for (int o = 32; o > 0; o >>= 1) mv = max(mv, __shfl_down(mv, o, 64));
+    __syncthreads();
+    if ((tid & 63) == 0) sbuf[tid >> 6] = mv;
+    __syncthreads();
+    int32_t wmax = -1;
+    for (int w = 0; w < kWG / 64; ++w) wmax = max(wmax, sbuf[w]);
+    if (wg_max && tid == 0) wg_max[tile] = wmax;
+    // vote histogram of the bins >= T; nothing to add when the maximum is below
+    if (hist && wmax >= T) {
+      const bool in_lds = n_bins <= kHistLds;
+      if (in_lds) {
+        for (int32_t i = tid; i < n_bins; i += kWG) shist[i] = 0u;
+        __syncthreads();
+      }
+      if (owner && nv >= T) {
+        if (nv >= n_bins) atomicOr(status, kStVoteOverflow);
+        else if (in_lds) atomicAdd(&shist[nv], 1u);
+        else atomicAdd(&hist[nv], 1u);
+      }
+      if (in_lds) {
+        __syncthreads();
+        for (int32_t i = tid; i < n_bins; i += kWG)
+          if (shist[i]) atomicAdd(&hist[i], shist[i]);
       }
     }
   }
@@ -935,6 +1071,7 @@ __global__ void __launch_bounds__(kWG) k_vote(const HitRec* __restrict__ hits, E
     int32_t a = n_eval, b2 = n_staged;
     for (int o = 32; o > 0; o >>= 1) { a += __shfl_down(a, o, 64); b2 += __shfl_down(b2, o, 64); }
     __shared__ int32_t swork[2][kWG / 64];
+    __syncthreads();
     if ((tid & 63) == 0) { swork[0][tid >> 6] = a; swork[1][tid >> 6] = b2; }
     __syncthreads();
     if (tid == 0) {
@@ -943,41 +1080,6 @@ __global__ void __launch_bounds__(kWG) k_vote(const HitRec* __restrict__ hits, E
       unsigned long long* slot = work + kWorkSlotU64 * ((blockIdx.x + blockIdx.y * 7u) % kWorkSlots);
       if (sa) atomicAdd(&slot[F32 ? 2 : 0], static_cast<unsigned long long>(sa));
       if (sb) atomicAdd(&slot[F32 ? 3 : 1], static_cast<unsigned long long>(sb));
-    }
-  }
-  if (HS > 1) {
-    sred[sl][bl] = nv;
-    __syncthreads();
-    if (sl == 0)
-      for (int s = 1; s < HS; ++s) nv += sred[s][bl];
-  }
-  const bool owner = sl == 0 && live;
-  if (owner) votes[b] = static_cast<uint16_t>(nv);
-  // workgroup maximum (read by the selection kernel and used below)
-  int32_t mv = owner ? nv : -1;
-  for (int o = 32; o > 0; o >>= 1) mv = max(mv, __shfl_down(mv, o, 64));
-  if ((tid & 63) == 0) sbuf[tid >> 6] = mv;
-  __syncthreads();
-  int32_t wmax = -1;
-  for (int w = 0; w < kWG / 64; ++w) wmax = max(wmax, sbuf[w]);
-  if (wg_max && tid == 0) wg_max[blockIdx.x] = wmax;
-  // vote histogram of the bins >= T (the selection threshold is never below
-  // T, so lower bins are never read); nothing to add when the maximum is below
-  if (hist && wmax >= T) {
-    const bool in_lds = n_bins <= kHistLds;
-    if (in_lds) {
-      for (int32_t i = tid; i < n_bins; i += kWG) shist[i] = 0u;
-      __syncthreads();
-    }
-    if (owner && nv >= T) {
-      if (nv >= n_bins) atomicOr(status, kStVoteOverflow);
-      else if (in_lds) atomicAdd(&shist[nv], 1u);
-      else atomicAdd(&hist[nv], 1u);
-    }
-    if (in_lds) {
-      __syncthreads();
-      for (int32_t i = tid; i < n_bins; i += kWG)
-        if (shist[i]) atomicAdd(&hist[i], shist[i]);
     }
   }
 }
@@ -1168,11 +1270,13 @@ __global__ void __launch_bounds__(kWG) k_est_partial(const BoxD* __restrict__ pa
                                                      const BoxD* __restrict__ first_box,
                                                      const uint16_t* __restrict__ first_votes,
                                                      double* __restrict__ part, EvView vw,
-                                                     const EventState* __restrict__ ev) {
+                                                     const EventState* __restrict__ ev,
+                                                     const int32_t* __restrict__ wg_max, int32_t bx) {
   const int e = blockIdx.y;
   if (ev && ev[e].done) return;
   parents += e * vw.par_stride;
   votes += int64_t(e) * sh.n_boxes;
+  if (wg_max) wg_max += int64_t(e) * vw.wg_stride;
   first_box += int64_t(e) * vw.k;
   first_votes += int64_t(e) * vw.k;
   part += int64_t(e) * vw.part_stride;
@@ -1183,11 +1287,12 @@ __global__ void __launch_bounds__(kWG) k_est_partial(const BoxD* __restrict__ pa
   double v[kEstQ];
   for (int q = 0; q < 5; ++q) { v[q] = 0.0; v[5 + q] = INFINITY; v[10 + q] = -INFINITY; }
   v[15] = 0.0;
-  if (i < sh.n_boxes && votes[i] == vmax) {
-    BoxD bx;
-    level_box(parents, sh, i, &bx);
+  // with wg_max, only tiles whose maximum reaches vmax hold written votes
+  if (i < sh.n_boxes && (!wg_max || wg_max[i / static_cast<uint32_t>(bx)] >= vmax) && votes[i] == vmax) {
+    BoxD box;
+    level_box(parents, sh, i, &box);
     for (int j = 0; j < 5; ++j) {
-      double lo = bx.lo[j], hi = bx.hi[j];
+      double lo = box.lo[j], hi = box.hi[j];
       const double c = 0.5 * (lo + hi);
       if (j == 1) {
         const double dv = c - c0;

@@ -34,6 +34,7 @@ constexpr int64_t kSelChunkMin = 4096;
 constexpr int32_t kSelMaxGroups = 1024;
 constexpr int kOffSlots = 8;             // pinned offset-staging slots
 constexpr int32_t kOffSlotInts = 65536;  // events + 1 per slot
+constexpr uint32_t kVoteGroups = 2048;   // vote workgroups per launch over live tiles
 // k_estimate: 256 lanes x segments of at most 2^(kEstLevels - 1) boxes
 constexpr int64_t kMaxEstimateBoxes = int64_t(ia::kWG) << (ia::kEstLevels - 1);
 
@@ -202,7 +203,7 @@ struct VoteIn {                   // per-level inputs of the vote kernel
   const uint8_t* flags;
   const int32_t* tlb;
   const int32_t* tn2;
-  int32_t prune;
+  const int32_t* live_list;       // null: every tile of the level
 };
 
 template <bool F32>
@@ -212,15 +213,15 @@ void launch_vote_tile(int32_t bx, dim3 g, hipStream_t s, const HitRec* recs, con
   switch (bx) {
     case 256:
       hipLaunchKernelGGL((ia::k_vote<256, F32>), g, dim3(ia::kWG), 0, s, recs, vw, par, sh, votes, hist, st, ev,
-                         in.flags, in.tlb, in.tn2, in.prune, wg_max, wk, slack32);
+                         in.flags, in.tlb, in.tn2, in.live_list, wg_max, wk, slack32);
       break;
     case 128:
       hipLaunchKernelGGL((ia::k_vote<128, F32>), g, dim3(ia::kWG), 0, s, recs, vw, par, sh, votes, hist, st, ev,
-                         in.flags, in.tlb, in.tn2, in.prune, wg_max, wk, slack32);
+                         in.flags, in.tlb, in.tn2, in.live_list, wg_max, wk, slack32);
       break;
     default:
       hipLaunchKernelGGL((ia::k_vote<64, F32>), g, dim3(ia::kWG), 0, s, recs, vw, par, sh, votes, hist, st, ev,
-                         in.flags, in.tlb, in.tn2, in.prune, wg_max, wk, slack32);
+                         in.flags, in.tlb, in.tn2, in.live_list, wg_max, wk, slack32);
       break;
   }
 }
@@ -229,7 +230,13 @@ ia_status launch_vote(ia_ctx* c, const HitRec* recs, const ia::EvView& vw, int32
                       const Shape& sh, uint16_t* votes, uint32_t* hist, const EventState* ev, const VoteIn& in,
                       int32_t* wg_max, hipStream_t s, bool f32, float slack32, int32_t* tile_used = nullptr) {
   const int32_t bx = vote_tile(c, sh.n_boxes);
-  const uint32_t grid = (sh.n_boxes + bx - 1) / bx;
+  // workgroups stride over the tiles: with a live list, about kVoteGroups in
+  // all (most tiles of a pruned level are not live); otherwise one per tile
+  // up to a cap
+  const uint32_t n_tiles = (sh.n_boxes + bx - 1) / bx;
+  uint32_t grid = std::min<uint32_t>(n_tiles, 16384u);
+  if (in.live_list)
+    grid = std::max<uint32_t>(1, std::min<uint32_t>(n_tiles, (kVoteGroups + n_ev - 1) / std::max(1, n_ev)));
   if (tile_used) *tile_used = bx;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (c->profiling) {
@@ -253,7 +260,8 @@ ia_status launch_vote(ia_ctx* c, const HitRec* recs, const ia::EvView& vw, int32
 // scratch layout of one chunk of ia_find_helices (byte offsets into the
 // arena): per-event slices of every array, sized for events of max_hits hits
 struct FindLayout {
-  size_t off, recs, votes, hist, lbh, selA, selB, range, sel_idx, sel_v, ev, part, flags, tlb, tn2, wg_max, total;
+  size_t off, recs, votes, hist, lbh, selA, selB, range, sel_idx, sel_v, ev, part, flags, tlb, tn2, wg_max, live,
+      total;
   int64_t flag_stride, tri_stride, votes_stride;
   int32_t hist_stride, wg_stride, part_stride, n_part;
 };
@@ -290,6 +298,7 @@ void layout_find(int64_t max_level_boxes, int64_t max_triples, int32_t top_k, in
   L->tlb = take(sizeof(int32_t) * size_t(L->tri_stride) * E);
   L->tn2 = take(sizeof(int32_t) * size_t(L->tri_stride) * E);
   L->wg_max = take(sizeof(int32_t) * size_t(L->wg_stride) * E);
+  L->live = take(sizeof(int32_t) * size_t(L->wg_stride) * E);
   L->total = off;
 }
 
@@ -510,7 +519,7 @@ ia_status ia_vote_level(ia_ctx* c, const ia_hit* d_hits, int32_t n_hits, const u
   hipLaunchKernelGGL(ia::k_fill_u32, dim3(std::min<uint32_t>((fill_n + 255) / 256, 65535)), dim3(256), 0, s,
                      reinterpret_cast<uint32_t*>(tn2), fill_n, 0u);
   launch_classify(c, recs, vw, 1, n_hits, par, sh, flags, tlb, tn2, nullptr, s, f32, c->slack32);
-  const VoteIn in{flags, tlb, tn2, 0};
+  const VoteIn in{flags, tlb, tn2, nullptr};
   return launch_vote(c, recs, vw, 1, par, sh, d_votes, nullptr, nullptr, in, nullptr, s, f32, c->slack32);
 }
 
@@ -580,7 +589,7 @@ ia_status ia_estimate(ia_ctx* c, const ia_box* d_parents, int32_t n_parents, con
   vw.k = 1;
   vw.part_stride = n_part * ia::kEstQ;
   hipLaunchKernelGGL(ia::k_est_partial, dim3(n_part, 1), dim3(ia::kWG), 0, s, par, sh, d_votes, first, first_v, part,
-                     vw, nullptr);
+                     vw, nullptr, nullptr, 1);
   hipLaunchKernelGGL(ia::k_est_final, dim3(1, 1), dim3(ia::kWG), 0, s, part, n_part, first, first_v,
                      reinterpret_cast<ia::EstimateOut*>(d_out), nullptr, nullptr, vw, 0.0, nullptr, nullptr, nullptr);
   IA_HIP(c, hipGetLastError());
@@ -660,6 +669,7 @@ ia_status ia_find_helices(ia_ctx* c, const ia_hit* d_hits, const int32_t* h_off,
     int32_t* tn2 = reinterpret_cast<int32_t*>(a + L.tn2);
     uint32_t* lbh = reinterpret_cast<uint32_t*>(a + L.lbh);
     int32_t* wg_max = reinterpret_cast<int32_t*>(a + L.wg_max);
+    int32_t* live = reinterpret_cast<int32_t*>(a + L.live);
     // chunk-relative hit offsets through a pinned slot whose last copy is done
     const uint32_t slot = c->slot_next++ % kOffSlots;
     if (c->slot_used[slot]) IA_HIP(c, hipEventSynchronize(c->slot_done[slot]));
@@ -689,14 +699,18 @@ ia_status ia_find_helices(ia_ctx* c, const ia_hit* d_hits, const int32_t* h_off,
       Shape sh = S.sh0;
       BoxD* sel = selA;
       vw.par_stride = 0;
+      int32_t last_bx = 1;
       for (int32_t lev = 0; lev <= sc->n_refine; ++lev) {
         const bool f32 = sc->prec[lev] == IA_FP32;
         launch_classify(c, recs, vw, E, cmax, par, sh, flags, tlb, tn2, ev, s, f32, slack32);
-        hipLaunchKernelGGL(ia::k_threshold, dim3(1, E), dim3(ia::kWG), 0, s, tlb, lbh, vw, sh, K, ev);
+        const int32_t vt = vote_tile(c, sh.n_boxes);
+        hipLaunchKernelGGL(ia::k_threshold, dim3(1, E), dim3(ia::kWG), 0, s, tlb, tn2, lbh, vw, sh, K, c->prune, vt,
+                           ev, live, wg_max);
         int32_t bx = 0;
-        const VoteIn in{flags, tlb, tn2, c->prune};
+        const VoteIn in{flags, tlb, tn2, live};
         ia_status st = launch_vote(c, recs, vw, E, par, sh, votes, hist, ev, in, wg_max, s, f32, slack32, &bx);
         if (st != IA_OK) return st;
+        last_bx = bx;
         const uint32_t n_wg = (sh.n_boxes + bx - 1) / bx;
         hipLaunchKernelGGL(ia::k_select_wg, dim3(1, E), dim3(ia::kWG), 0, s, votes, vw, hist, wg_max, n_wg, bx, par,
                            sh, sel, sel_idx, sel_v, ev, lev == 0 ? std::max(sc->v_min, 0) : 0, tlb, tn2);
@@ -710,7 +724,7 @@ ia_status ia_find_helices(ia_ctx* c, const ia_hit* d_hits, const int32_t* h_off,
       }
       const int32_t n_part = est_parts(sh.n_boxes);
       hipLaunchKernelGGL(ia::k_est_partial, dim3(n_part, E), dim3(ia::kWG), 0, s, par, sh, votes, sel, sel_v, part, vw,
-                         ev);
+                         ev, wg_max, last_bx);
       hipLaunchKernelGGL(ia::k_est_final, dim3(1, E), dim3(ia::kWG), 0, s, part, n_part, sel, sel_v,
                          static_cast<ia::EstimateOut*>(nullptr), ev, recs, vw, sc->hitfind_scale, assigned, out, n_out);
       IA_HIP(c, hipGetLastError());

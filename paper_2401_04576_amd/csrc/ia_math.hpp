@@ -163,6 +163,52 @@ IA_HD Iv idiv_pos(Iv a, Iv b) {
 // square root of [lo, hi] with hi >= 0; negative parts are clipped
 IA_HD Iv isqrt(Iv a) { return {a.lo > 0.0 ? wdn(sqrt(a.lo)) : 0.0, wup(sqrt(a.hi))}; }
 
+// interval times a point of either sign: two products
+IA_HD Iv imul_pt(Iv a, double x) {
+  const double p = a.lo * x, q = a.hi * x;
+  return x >= 0.0 ? Iv{wdn(p), wup(q)} : Iv{wdn(q), wup(p)};
+}
+// a / b for b.lo > 0: the extreme quotients, chosen by the signs of a's ends
+IA_HD Iv idiv_pos2(Iv a, Iv b) {
+  const double lo = a.lo / (a.lo >= 0.0 ? b.hi : b.lo);
+  const double hi = a.hi / (a.hi >= 0.0 ? b.lo : b.hi);
+  return {wdn(lo), wup(hi)};
+}
+
+// sin and cos enclosures for intervals inside [-kSmallTrig, kSmallTrig]:
+// there sin increases and cos decreases with |x|; Taylor polynomials of
+// degree 13 and 14 are within 1e-14 of them, far below the 2^-40 margin
+constexpr double kSmallTrig = 0.75;
+constexpr double kSmallMargin = 0x1p-40;
+IA_HD double sin_small(double x) {
+  const double z = x * x;
+  double p = 1.0 / 6227020800.0;
+  p = fma(p, z, -1.0 / 39916800.0);
+  p = fma(p, z, 1.0 / 362880.0);
+  p = fma(p, z, -1.0 / 5040.0);
+  p = fma(p, z, 1.0 / 120.0);
+  p = fma(p, z, -1.0 / 6.0);
+  return fma(x * z, p, x);
+}
+IA_HD double cos_small(double x) {
+  const double z = x * x;
+  double q = -1.0 / 87178291200.0;
+  q = fma(q, z, 1.0 / 479001600.0);
+  q = fma(q, z, -1.0 / 3628800.0);
+  q = fma(q, z, 1.0 / 40320.0);
+  q = fma(q, z, -1.0 / 720.0);
+  q = fma(q, z, 1.0 / 24.0);
+  q = fma(q, z, -0.5);
+  return fma(z, q, 1.0);
+}
+IA_HD void sincos_encl_small(Iv x, Iv* S, Iv* C) {
+  *S = {fmax(sin_small(x.lo) - kSmallMargin, -1.0), fmin(sin_small(x.hi) + kSmallMargin, 1.0)};
+  const double alo = fabs(x.lo), ahi = fabs(x.hi);
+  const bool has0 = x.lo <= 0.0 && x.hi >= 0.0;
+  const double amin = has0 ? 0.0 : fmin(alo, ahi), amax = fmax(alo, ahi);
+  *C = {cos_small(amax) - kSmallMargin, has0 ? 1.0 : fmin(cos_small(amin) + kSmallMargin, 1.0)};
+}
+
 // enclosure of sin over [a, b]
 IA_HD Iv sin_encl(double a, double b) {
   if (b - a >= kTwoPi) return {-1.0, 1.0};
