@@ -55,6 +55,10 @@ struct EventState {
   int32_t n_argmax;             // size of the max-vote set of the last level
   int32_t t_prune;              // vote threshold of the current level's pruning (0: none)
   int32_t n_live;               // vote tiles of the current level holding a box that can be selected
+  int32_t n_live_tri;           // triples of the current level whose class-2 pairs are evaluated
+  int32_t n_rec;                // their class-2 pairs (staged records)
+  int32_t rec_ok;               // 1: the records fit the record buffer (else the in-kernel staging runs)
+  int32_t pad;
   double p[5], err[5];          // last estimate
 };
 
@@ -69,6 +73,7 @@ struct EvView {
   int64_t par_stride;           // parent boxes per event (0: one shared list)
   int64_t flag_stride;          // pre-pass flags per event
   int64_t tri_stride;           // per-triple vote bounds per event
+  int64_t rec_stride;           // staged pair records per event
   int32_t hist_stride;          // histogram bins per event
   int32_t wg_stride;            // workgroup maxima per event
   int32_t part_stride;          // estimate chunk sums per event (doubles)
@@ -410,6 +415,15 @@ IA_HD PairQ32 pair_q32(const PairQ& q, const HitRec& h, float slack32) {
   return r;
 }
 
+// a staged (triple, stereo hit) record at FP64 levels: the pair quantities
+// and the hit's tan(tau), drift and band (128 bytes)
+struct RecD {
+  double q[13];
+  double tt, d, band;
+};
+// per-triple frame values the per-box evaluation needs: R, sign, kappa interval
+struct TriFrame { double R, sig, Klo, Khi; };
+
 IA_HD bool stereo_vote32(const PairQ32& q, float R, float sig, Iv32 K, float z0, float lam, float lamR,
                          float lam2) {
   const float tt = q.tt, t2 = tt * tt;
@@ -690,10 +704,16 @@ __global__ void __launch_bounds__(kWG) k_classify(const HitRec* __restrict__ hit
 // holds no selected box and no box of the maximum.  Then the vote tiles of
 // bx boxes holding a triple with upper bound >= T are listed in index order
 // (live_list, ev->n_live); the others get wg_max = -1 and are not voted.
+// With live_tri, the triples whose class-2 pairs are evaluated (tn2 > 0 and
+// upper bound >= T) are listed too (ev->n_live_tri), each with the offset of
+// its records (rec_off, in index order; rec_fill cleared); ev->rec_ok tells
+// whether all ev->n_rec records fit rec_cap.
 __global__ void __launch_bounds__(kWG) k_threshold(const int32_t* __restrict__ tlb, const int32_t* __restrict__ tn2,
                                                    uint32_t* __restrict__ lbh, EvView vw, Shape sh, int32_t k,
                                                    int32_t prune, int32_t bx, EventState* __restrict__ ev,
-                                                   int32_t* __restrict__ live_list, int32_t* __restrict__ wg_max) {
+                                                   int32_t* __restrict__ live_list, int32_t* __restrict__ wg_max,
+                                                   int32_t* __restrict__ live_tri, int32_t* __restrict__ rec_off,
+                                                   int32_t* __restrict__ rec_fill, int64_t rec_cap) {
   const int e = blockIdx.y;
   if (ev[e].done) return;
   const int32_t n_bins = vw.count(e) + 1;
@@ -754,9 +774,86 @@ __global__ void __launch_bounds__(kWG) k_threshold(const int32_t* __restrict__ t
   const int32_t total = block_scan_count(mine, &pos, sbuf);
   for (uint32_t tile = ta; tile < tb; ++tile)
     if (tile_live(tile)) live_list[pos++] = static_cast<int32_t>(tile);
+  int32_t n_lt = 0, n_rec = 0;
+  if (live_tri) {
+    // triples whose class-2 pairs are evaluated, and their record offsets
+    live_tri += e * vw.tri_stride;
+    rec_off += e * vw.tri_stride;
+    rec_fill += e * vw.tri_stride;
+    const uint32_t pt = (n_tr + kWG - 1) / kWG;
+    const uint32_t ra = min(tid * pt, n_tr), rb = min(ra + pt, n_tr);
+    int32_t c1 = 0, c2 = 0;
+    for (uint32_t t = ra; t < rb; ++t)
+      if (tn2[t] > 0 && tlb[t] + tn2[t] >= T) { ++c1; c2 += tn2[t]; }
+    int32_t p1, p2;
+    n_lt = block_scan_count(c1, &p1, sbuf);
+    n_rec = block_scan_count(c2, &p2, sbuf);
+    for (uint32_t t = ra; t < rb; ++t)
+      if (tn2[t] > 0 && tlb[t] + tn2[t] >= T) {
+        live_tri[p1++] = static_cast<int32_t>(t);
+        rec_off[t] = p2;
+        rec_fill[t] = 0;
+        p2 += tn2[t];
+      }
+  }
   if (tid == 0) {
     ev[e].t_prune = T;
     ev[e].n_live = total;
+    ev[e].n_live_tri = n_lt;
+    ev[e].n_rec = n_rec;
+    ev[e].rec_ok = live_tri != nullptr && static_cast<int64_t>(n_rec) <= rec_cap ? 1 : 0;
+  }
+}
+
+// Staged records of a level: one thread per (listed triple, hit); each
+// class-2 pair computes its triple's frame, G and the pair quantities
+// (FP64, or their FP32 images at FP32 levels) and writes them, with the
+// hit's tan(tau), drift and band, to a slot of its triple's record range
+// (slots taken in any order: votes do not depend on it).  Every writer of a
+// triple also writes the same TriFrame.  Events with rec_ok == 0 are skipped.
+template <bool F32>
+__global__ void __launch_bounds__(kWG) k_stage(const HitRec* __restrict__ hits, EvView vw,
+                                               const BoxD* __restrict__ parents, Shape sh,
+                                               const uint8_t* __restrict__ flags, const int32_t* __restrict__ live_tri,
+                                               const int32_t* __restrict__ rec_off, int32_t* __restrict__ rec_fill,
+                                               void* __restrict__ rec, TriFrame* __restrict__ tfr,
+                                               const EventState* __restrict__ ev, float slack32) {
+  const int e = blockIdx.y;
+  if (ev[e].done || !ev[e].rec_ok) return;
+  const int32_t n_hits = vw.count(e);
+  if (n_hits <= 0) return;
+  hits += vw.beg(e);
+  parents += e * vw.par_stride;
+  flags += e * vw.flag_stride;
+  live_tri += e * vw.tri_stride;
+  rec_off += e * vw.tri_stride;
+  rec_fill += e * vw.tri_stride;
+  tfr += e * vw.tri_stride;
+  const uint32_t n_tr = sh.n_parents * sh.m012;
+  const int64_t n_items = static_cast<int64_t>(ev[e].n_live_tri) * n_hits;
+  for (int64_t i = int64_t(blockIdx.x) * kWG + threadIdx.x; i < n_items; i += int64_t(gridDim.x) * kWG) {
+    const uint32_t t = static_cast<uint32_t>(live_tri[i / n_hits]);
+    const int32_t h = static_cast<int32_t>(i % n_hits);
+    if (flags[int64_t(h) * n_tr + t] != 2) continue;
+    const HitRec hr = hits[h];
+    const uint32_t tc = t % sh.m012;
+    const Frame f = triple_frame(parents[t / sh.m012], sh.m, tc / sh.m12, (tc / sh.m[2]) % sh.m[1], tc % sh.m[2]);
+    const Iv G = residual_G(f, hr);
+    const PairQ q = pair_quantities(f, hr, G);
+    const int64_t slot = int64_t(e) * vw.rec_stride + rec_off[t] + atomicAdd(&rec_fill[t], 1);
+    if constexpr (F32) {
+      reinterpret_cast<PairQ32*>(rec)[slot] = pair_q32(q, hr, slack32);
+    } else {
+      RecD r;
+      r.q[0] = q.Glo; r.q[1] = q.Ghi; r.q[2] = q.sArc; r.q[3] = q.dphi; r.q[4] = q.RAx; r.q[5] = q.sinA;
+      r.q[6] = q.cosA; r.q[7] = q.sAx; r.q[8] = q.cAx; r.q[9] = q.c2; r.q[10] = q.s2; r.q[11] = q.twoRAx2;
+      r.q[12] = q.RpRAx;
+      r.tt = hr.tant;
+      r.d = hr.d;
+      r.band = hr.band;
+      reinterpret_cast<RecD*>(rec)[slot] = r;
+    }
+    tfr[t] = TriFrame{f.R, f.sig, f.K.lo, f.K.hi};
   }
 }
 
@@ -885,6 +982,8 @@ __global__ void __launch_bounds__(kWG) k_select_wg(const uint16_t* __restrict__ 
 // Writes the votes of its tiles, each tile's maximum (wg_max) and, with
 // hist, the histogram of the votes >= T (the selection threshold is never
 // below T).  Tiles that are not live are neither written nor counted.
+// With only_unstaged, it votes only the events whose records did not fit
+// (k_vote_rec votes the others).
 template <int BX, bool F32>
 __global__ void __launch_bounds__(kWG) k_vote(const HitRec* __restrict__ hits, EvView vw,
                                               const BoxD* __restrict__ parents, Shape sh,
@@ -893,11 +992,12 @@ __global__ void __launch_bounds__(kWG) k_vote(const HitRec* __restrict__ hits, E
                                               const uint8_t* __restrict__ flags, const int32_t* __restrict__ tlb,
                                               const int32_t* __restrict__ tn2, const int32_t* __restrict__ live_list,
                                               int32_t* __restrict__ wg_max, unsigned long long* __restrict__ work,
-                                              float slack32) {
+                                              float slack32, int32_t only_unstaged) {
   constexpr int HS = kWG / BX;
   static_assert(BX % 64 == 0 && HS * BX == kWG, "slices are whole waves");
   const int e = blockIdx.y;
   if (ev && ev[e].done) return;
+  if (only_unstaged && ev[e].rec_ok) return;   // k_vote_rec covers this event
   const int32_t n_hits = vw.count(e), n_bins = n_hits + 1;
   hits += vw.beg(e);
   parents += e * vw.par_stride;
@@ -1080,6 +1180,194 @@ __global__ void __launch_bounds__(kWG) k_vote(const HitRec* __restrict__ hits, E
       unsigned long long* slot = work + kWorkSlotU64 * ((blockIdx.x + blockIdx.y * 7u) % kWorkSlots);
       if (sa) atomicAdd(&slot[F32 ? 2 : 0], static_cast<unsigned long long>(sa));
       if (sb) atomicAdd(&slot[F32 ? 3 : 1], static_cast<unsigned long long>(sb));
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// The vote kernel on staged records (ia_find_helices).  The same tiles,
+// slices, lower bounds and outputs as k_vote, for events whose records fit
+// (ev->rec_ok); the class-2 pairs of each evaluated triple are its records
+// from k_stage, copied to LDS a chunk at a time, and the triple's frame
+// comes from its TriFrame, so the kernel holds only the per-box arithmetic.
+template <int BX, bool F32>
+__global__ void __launch_bounds__(kWG) k_vote_rec(EvView vw, const BoxD* __restrict__ parents, Shape sh,
+                                                  uint16_t* __restrict__ votes, uint32_t* __restrict__ hist,
+                                                  uint32_t* __restrict__ status, const EventState* __restrict__ ev,
+                                                  const int32_t* __restrict__ tlb, const int32_t* __restrict__ tn2,
+                                                  const int32_t* __restrict__ live_list,
+                                                  const int32_t* __restrict__ rec_off, const void* __restrict__ rec,
+                                                  const TriFrame* __restrict__ tfr, int32_t* __restrict__ wg_max,
+                                                  unsigned long long* __restrict__ work) {
+  constexpr int HS = kWG / BX;
+  constexpr int NQ = F32 ? 8 : 16;               // doubles of LDS per staged record
+  static_assert(BX % 64 == 0 && HS * BX == kWG, "slices are whole waves");
+  const int e = blockIdx.y;
+  if (ev[e].done || !ev[e].rec_ok) return;
+  const int32_t n_hits = vw.count(e), n_bins = n_hits + 1;
+  parents += e * vw.par_stride;
+  votes += int64_t(e) * sh.n_boxes;
+  if (hist) hist += int64_t(e) * vw.hist_stride;
+  tlb += e * vw.tri_stride;
+  tn2 += e * vw.tri_stride;
+  rec_off += e * vw.tri_stride;
+  tfr += e * vw.tri_stride;
+  wg_max += int64_t(e) * vw.wg_stride;
+  live_list += int64_t(e) * vw.wg_stride;
+  const RecD* recd = reinterpret_cast<const RecD*>(rec) + int64_t(e) * vw.rec_stride;
+  const PairQ32* recf = reinterpret_cast<const PairQ32*>(rec) + int64_t(e) * vw.rec_stride;
+  const int32_t T = ev[e].t_prune;
+  const uint32_t n_items = static_cast<uint32_t>(ev[e].n_live);
+  __shared__ double sq[NQ][kCap + 16];
+  float(*sq32)[kCap + 16] = reinterpret_cast<float(*)[kCap + 16]>(&sq[0][0]);
+  __shared__ int8_t sflag[kCap + 16];
+  __shared__ int8_t stlive[kWG];
+  __shared__ uint32_t shist[kHistLds];
+  __shared__ int32_t sred[HS][BX];
+  __shared__ int32_t sbuf[kWG / 64];
+  const uint32_t tid = threadIdx.x;
+  const uint32_t bl = tid % BX, sl = tid / BX;
+  auto triple_of = [&](uint32_t x) { return (x / sh.nc) * sh.m012 + (x % sh.nc) / sh.m34; };
+  int32_t n_eval = 0;
+
+  for (uint32_t item = blockIdx.x; item < n_items; item += gridDim.x) {
+    const uint32_t tile = static_cast<uint32_t>(live_list[item]);
+    const uint32_t b0 = tile * BX;
+    const uint32_t b_last = min(b0 + BX, sh.n_boxes) - 1;
+    const uint32_t b = b0 + bl;
+    const bool live = b < sh.n_boxes;
+    const uint32_t bb = live ? b : b_last;
+    const uint32_t t_first = triple_of(b0);
+    const int32_t nt = static_cast<int32_t>(triple_of(b_last) - t_first + 1);
+    const int32_t my_tl = static_cast<int32_t>(triple_of(bb) - t_first);
+    const int32_t hc = max(1, kCap / nt);          // records per triple per chunk
+    const int32_t pitch = hc + ((nt > 1 && nt <= 16) ? 1 : 0);
+
+    __syncthreads();                     // LDS of the previous tile is free
+    int32_t n2max = 0;
+    for (int32_t i = tid; i < nt; i += kWG) {
+      const int32_t a = tlb[t_first + i], c = tn2[t_first + i];
+      const bool lv = c > 0 && a + c >= T;
+      stlive[i] = lv ? 1 : 0;
+      if (lv) n2max = max(n2max, c);
+    }
+    for (int o = 32; o > 0; o >>= 1) n2max = max(n2max, __shfl_down(n2max, o, 64));
+    if ((tid & 63) == 0) sbuf[tid >> 6] = n2max;
+    __syncthreads();
+    n2max = 0;
+    for (int w = 0; w < kWG / 64; ++w) n2max = max(n2max, sbuf[w]);
+
+    const uint32_t my_t = t_first + my_tl;
+    int32_t nv = sl == 0 ? tlb[my_t] : 0;
+    if (n2max > 0) {                     // uniform over the workgroup (barriers below)
+      const TriFrame fr = tfr[my_t];
+      const Iv K = {fr.Klo, fr.Khi};
+      uint32_t k[5];
+      child_index(sh.m, bb % sh.nc, k);
+      const BoxD& P = parents[bb / sh.nc];
+      double zlo, zhi, llo, lhi;
+      child_edge(P.lo[3], P.hi[3], sh.m[3], k[3], &zlo, &zhi);
+      child_edge(P.lo[4], P.hi[4], sh.m[4], k[4], &llo, &lhi);
+      const double z0 = 0.5 * (zlo + zhi), lam = 0.5 * (llo + lhi);
+      const double lamR = lam * fr.R, lam2 = lam * lam;
+      const float R32 = static_cast<float>(fr.R), sig32 = static_cast<float>(fr.sig);
+      const Iv32 K32 = to32(K);
+      const float z032 = static_cast<float>(z0), lam32 = static_cast<float>(lam);
+      const float lamR32 = lam32 * R32, lam232 = lam32 * lam32;
+      const int32_t my_n2 = stlive[my_tl] ? tn2[my_t] : 0;
+
+      for (int32_t j0 = 0; j0 < n2max; j0 += hc) {
+        __syncthreads();
+        // copy records j0 .. j0 + hc - 1 of every evaluated triple to LDS
+        for (int32_t r = tid; r < nt * hc; r += kWG) {
+          const int32_t tl = r / hc, jl = r % hc;
+          const int32_t slot = tl * pitch + jl;
+          const uint32_t t = t_first + tl;
+          if (!stlive[tl] || j0 + jl >= tn2[t]) { sflag[slot] = 0; continue; }
+          const int64_t ri = int64_t(rec_off[t]) + j0 + jl;
+          sflag[slot] = 2;
+          if constexpr (F32) {
+            const PairQ32 q = recf[ri];
+            sq32[0][slot] = q.Glo; sq32[1][slot] = q.Ghi; sq32[2][slot] = q.sArc; sq32[3][slot] = q.dphi;
+            sq32[4][slot] = q.RAx; sq32[5][slot] = q.sinA; sq32[6][slot] = q.cosA; sq32[7][slot] = q.sAx;
+            sq32[8][slot] = q.cAx; sq32[9][slot] = q.c2; sq32[10][slot] = q.s2; sq32[11][slot] = q.twoRAx2;
+            sq32[12][slot] = q.RpRAx; sq32[13][slot] = q.tt; sq32[14][slot] = q.d; sq32[15][slot] = q.bs;
+          } else {
+            const RecD& q = recd[ri];
+            for (int c = 0; c < 13; ++c) sq[c][slot] = q.q[c];
+            sq[13][slot] = q.tt; sq[14][slot] = q.d; sq[15][slot] = q.band;
+          }
+        }
+        __syncthreads();
+        const int32_t nj = min(hc, my_n2 - j0);
+        for (int32_t jl = sl; jl < nj; jl += HS) {
+          const int32_t slot = my_tl * pitch + jl;
+          n_eval += live ? 1 : 0;
+          if constexpr (F32) {
+            PairQ32 r;
+            r.Glo = sq32[0][slot]; r.Ghi = sq32[1][slot]; r.sArc = sq32[2][slot]; r.dphi = sq32[3][slot];
+            r.RAx = sq32[4][slot]; r.sinA = sq32[5][slot]; r.cosA = sq32[6][slot]; r.sAx = sq32[7][slot];
+            r.cAx = sq32[8][slot]; r.c2 = sq32[9][slot]; r.s2 = sq32[10][slot]; r.twoRAx2 = sq32[11][slot];
+            r.RpRAx = sq32[12][slot]; r.tt = sq32[13][slot]; r.d = sq32[14][slot]; r.bs = sq32[15][slot];
+            if (stereo_vote32(r, R32, sig32, K32, z032, lam32, lamR32, lam232)) ++nv;
+          } else {
+            PairQ q;
+            q.Glo = sq[0][slot]; q.Ghi = sq[1][slot]; q.sArc = sq[2][slot]; q.dphi = sq[3][slot];
+            q.RAx = sq[4][slot]; q.sinA = sq[5][slot]; q.cosA = sq[6][slot]; q.sAx = sq[7][slot];
+            q.cAx = sq[8][slot]; q.c2 = sq[9][slot]; q.s2 = sq[10][slot]; q.twoRAx2 = sq[11][slot];
+            q.RpRAx = sq[12][slot];
+            const double tt = sq[13][slot];
+            if (stereo_vote(q, fr.R, fr.sig, K, z0, lam, lamR, lam2, tt, tt * tt, sq[14][slot], sq[15][slot])) ++nv;
+          }
+        }
+      }
+    }
+    if (HS > 1) {
+      __syncthreads();
+      sred[sl][bl] = nv;
+      __syncthreads();
+      if (sl == 0)
+        for (int s2 = 1; s2 < HS; ++s2) nv += sred[s2][bl];
+    }
+    const bool owner = sl == 0 && live;
+    if (owner) votes[b] = static_cast<uint16_t>(nv);
+    int32_t mv = owner ? nv : -1;
+    for (int o = 32; o > 0; o >>= 1) mv = max(mv, __shfl_down(mv, o, 64));
+    __syncthreads();
+    if ((tid & 63) == 0) sbuf[tid >> 6] = mv;
+    __syncthreads();
+    int32_t wmax = -1;
+    for (int w = 0; w < kWG / 64; ++w) wmax = max(wmax, sbuf[w]);
+    if (tid == 0) wg_max[tile] = wmax;
+    if (hist && wmax >= T) {
+      const bool in_lds = n_bins <= kHistLds;
+      if (in_lds) {
+        for (int32_t i = tid; i < n_bins; i += kWG) shist[i] = 0u;
+        __syncthreads();
+      }
+      if (owner && nv >= T) {
+        if (nv >= n_bins) atomicOr(status, kStVoteOverflow);
+        else if (in_lds) atomicAdd(&shist[nv], 1u);
+        else atomicAdd(&hist[nv], 1u);
+      }
+      if (in_lds) {
+        __syncthreads();
+        for (int32_t i = tid; i < n_bins; i += kWG)
+          if (shist[i]) atomicAdd(&hist[i], shist[i]);
+      }
+    }
+  }
+  if (work) {
+    int32_t a = n_eval;
+    for (int o = 32; o > 0; o >>= 1) a += __shfl_down(a, o, 64);
+    __syncthreads();
+    if ((tid & 63) == 0) sbuf[tid >> 6] = a;
+    __syncthreads();
+    if (tid == 0) {
+      int32_t sa = 0;
+      for (int w = 0; w < kWG / 64; ++w) sa += sbuf[w];
+      unsigned long long* slot = work + kWorkSlotU64 * ((blockIdx.x + blockIdx.y * 7u) % kWorkSlots);
+      if (sa) atomicAdd(&slot[F32 ? 2 : 0], static_cast<unsigned long long>(sa));
     }
   }
 }

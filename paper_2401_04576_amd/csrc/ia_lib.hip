@@ -35,6 +35,7 @@ constexpr int32_t kSelMaxGroups = 1024;
 constexpr int kOffSlots = 8;             // pinned offset-staging slots
 constexpr int32_t kOffSlotInts = 65536;  // events + 1 per slot
 constexpr uint32_t kVoteGroups = 2048;   // vote workgroups per launch over live tiles
+constexpr int64_t kRecCap = 32768;       // staged records per event when the arena cannot hold all pairs
 // k_estimate: 256 lanes x segments of at most 2^(kEstLevels - 1) boxes
 constexpr int64_t kMaxEstimateBoxes = int64_t(ia::kWG) << (ia::kEstLevels - 1);
 
@@ -204,6 +205,7 @@ struct VoteIn {                   // per-level inputs of the vote kernel
   const int32_t* tlb;
   const int32_t* tn2;
   const int32_t* live_list;       // null: every tile of the level
+  int32_t only_unstaged;          // vote only events whose records did not fit
 };
 
 template <bool F32>
@@ -213,15 +215,15 @@ void launch_vote_tile(int32_t bx, dim3 g, hipStream_t s, const HitRec* recs, con
   switch (bx) {
     case 256:
       hipLaunchKernelGGL((ia::k_vote<256, F32>), g, dim3(ia::kWG), 0, s, recs, vw, par, sh, votes, hist, st, ev,
-                         in.flags, in.tlb, in.tn2, in.live_list, wg_max, wk, slack32);
+                         in.flags, in.tlb, in.tn2, in.live_list, wg_max, wk, slack32, in.only_unstaged);
       break;
     case 128:
       hipLaunchKernelGGL((ia::k_vote<128, F32>), g, dim3(ia::kWG), 0, s, recs, vw, par, sh, votes, hist, st, ev,
-                         in.flags, in.tlb, in.tn2, in.live_list, wg_max, wk, slack32);
+                         in.flags, in.tlb, in.tn2, in.live_list, wg_max, wk, slack32, in.only_unstaged);
       break;
     default:
       hipLaunchKernelGGL((ia::k_vote<64, F32>), g, dim3(ia::kWG), 0, s, recs, vw, par, sh, votes, hist, st, ev,
-                         in.flags, in.tlb, in.tn2, in.live_list, wg_max, wk, slack32);
+                         in.flags, in.tlb, in.tn2, in.live_list, wg_max, wk, slack32, in.only_unstaged);
       break;
   }
 }
@@ -257,22 +259,90 @@ ia_status launch_vote(ia_ctx* c, const HitRec* recs, const ia::EvView& vw, int32
   return IA_OK;
 }
 
+struct RecIn {                    // per-level staged-record buffers
+  int32_t* live_tri;
+  int32_t* rec_off;
+  int32_t* rec_fill;
+  void* rec;
+  ia::TriFrame* tfr;
+};
+
+void launch_stage(const HitRec* recs, const ia::EvView& vw, int32_t n_ev, const BoxD* par, const Shape& sh,
+                  const uint8_t* flags, const RecIn& r, const EventState* ev, hipStream_t s, bool f32,
+                  float slack32) {
+  const dim3 g(std::max<uint32_t>(1, (kVoteGroups + n_ev - 1) / std::max(1, n_ev)), n_ev);
+  if (f32)
+    hipLaunchKernelGGL((ia::k_stage<true>), g, dim3(ia::kWG), 0, s, recs, vw, par, sh, flags, r.live_tri, r.rec_off,
+                       r.rec_fill, r.rec, r.tfr, ev, slack32);
+  else
+    hipLaunchKernelGGL((ia::k_stage<false>), g, dim3(ia::kWG), 0, s, recs, vw, par, sh, flags, r.live_tri, r.rec_off,
+                       r.rec_fill, r.rec, r.tfr, ev, slack32);
+}
+
+template <bool F32>
+void launch_vote_rec_tile(int32_t bx, dim3 g, hipStream_t s, const ia::EvView& vw, const BoxD* par, const Shape& sh,
+                          uint16_t* votes, uint32_t* hist, uint32_t* st, const EventState* ev, const VoteIn& in,
+                          const RecIn& r, int32_t* wg_max, unsigned long long* wk) {
+  switch (bx) {
+    case 256:
+      hipLaunchKernelGGL((ia::k_vote_rec<256, F32>), g, dim3(ia::kWG), 0, s, vw, par, sh, votes, hist, st, ev, in.tlb,
+                         in.tn2, in.live_list, r.rec_off, r.rec, r.tfr, wg_max, wk);
+      break;
+    case 128:
+      hipLaunchKernelGGL((ia::k_vote_rec<128, F32>), g, dim3(ia::kWG), 0, s, vw, par, sh, votes, hist, st, ev, in.tlb,
+                         in.tn2, in.live_list, r.rec_off, r.rec, r.tfr, wg_max, wk);
+      break;
+    default:
+      hipLaunchKernelGGL((ia::k_vote_rec<64, F32>), g, dim3(ia::kWG), 0, s, vw, par, sh, votes, hist, st, ev, in.tlb,
+                         in.tn2, in.live_list, r.rec_off, r.rec, r.tfr, wg_max, wk);
+      break;
+  }
+}
+
+// the record-based vote for n_ev events (bracketed by events when profiling)
+ia_status launch_vote_rec(ia_ctx* c, const ia::EvView& vw, int32_t n_ev, const BoxD* par, const Shape& sh,
+                          uint16_t* votes, uint32_t* hist, const EventState* ev, const VoteIn& in, const RecIn& r,
+                          int32_t* wg_max, hipStream_t s, bool f32) {
+  const int32_t bx = vote_tile(c, sh.n_boxes);
+  const uint32_t n_tiles = (sh.n_boxes + bx - 1) / bx;
+  const uint32_t grid = std::max<uint32_t>(1, std::min<uint32_t>(n_tiles, (kVoteGroups + n_ev - 1) / std::max(1, n_ev)));
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (c->profiling) {
+    IA_HIP(c, hipEventCreate(&e0));
+    IA_HIP(c, hipEventCreate(&e1));
+    IA_HIP(c, hipEventRecord(e0, s));
+  }
+  uint32_t* st = &persistent(c)->status;
+  unsigned long long* wk = persistent(c)->work;
+  const dim3 g(grid, n_ev);
+  if (f32) launch_vote_rec_tile<true>(bx, g, s, vw, par, sh, votes, hist, st, ev, in, r, wg_max, wk);
+  else launch_vote_rec_tile<false>(bx, g, s, vw, par, sh, votes, hist, st, ev, in, r, wg_max, wk);
+  if (c->profiling) {
+    IA_HIP(c, hipEventRecord(e1, s));
+    c->marks.push_back({e0, e1, f32});
+  }
+  IA_HIP(c, hipGetLastError());
+  return IA_OK;
+}
+
 // scratch layout of one chunk of ia_find_helices (byte offsets into the
 // arena): per-event slices of every array, sized for events of max_hits hits
 struct FindLayout {
   size_t off, recs, votes, hist, lbh, selA, selB, range, sel_idx, sel_v, ev, part, flags, tlb, tn2, wg_max, live,
-      total;
-  int64_t flag_stride, tri_stride, votes_stride;
+      live_tri, rec_off, rec_fill, tfr, rec, total;
+  int64_t flag_stride, tri_stride, votes_stride, rec_stride;
   int32_t hist_stride, wg_stride, part_stride, n_part;
 };
 
+// rec_per_event: staged records per event (0: every (triple, hit) pair)
 void layout_find(int64_t max_level_boxes, int64_t max_triples, int32_t top_k, int32_t max_hits, int32_t n_ev,
-                 int64_t n_hits_total, FindLayout* L) {
+                 int64_t n_hits_total, FindLayout* L, int64_t rec_per_event = 0) {
   L->n_part = est_parts(static_cast<uint32_t>(max_level_boxes));
   L->votes_stride = max_level_boxes;
   L->hist_stride = max_hits + 2;
   L->flag_stride = max_triples * int64_t(std::max(0, max_hits));
   L->tri_stride = max_triples;
+  L->rec_stride = rec_per_event > 0 ? rec_per_event : std::max<int64_t>(1, max_triples * int64_t(std::max(0, max_hits)));
   L->wg_stride = static_cast<int32_t>((max_level_boxes + 63) / 64);
   L->part_stride = ia::kEstQ * L->n_part;
   const size_t E = size_t(std::max(1, n_ev));
@@ -299,6 +369,11 @@ void layout_find(int64_t max_level_boxes, int64_t max_triples, int32_t top_k, in
   L->tn2 = take(sizeof(int32_t) * size_t(L->tri_stride) * E);
   L->wg_max = take(sizeof(int32_t) * size_t(L->wg_stride) * E);
   L->live = take(sizeof(int32_t) * size_t(L->wg_stride) * E);
+  L->live_tri = take(sizeof(int32_t) * size_t(L->tri_stride) * E);
+  L->rec_off = take(sizeof(int32_t) * size_t(L->tri_stride) * E);
+  L->rec_fill = take(sizeof(int32_t) * size_t(L->tri_stride) * E);
+  L->tfr = take(sizeof(ia::TriFrame) * size_t(L->tri_stride) * E);
+  L->rec = take(sizeof(ia::RecD) * size_t(L->rec_stride) * E);
   L->total = off;
 }
 
@@ -519,7 +594,7 @@ ia_status ia_vote_level(ia_ctx* c, const ia_hit* d_hits, int32_t n_hits, const u
   hipLaunchKernelGGL(ia::k_fill_u32, dim3(std::min<uint32_t>((fill_n + 255) / 256, 65535)), dim3(256), 0, s,
                      reinterpret_cast<uint32_t*>(tn2), fill_n, 0u);
   launch_classify(c, recs, vw, 1, n_hits, par, sh, flags, tlb, tn2, nullptr, s, f32, c->slack32);
-  const VoteIn in{flags, tlb, tn2, nullptr};
+  const VoteIn in{flags, tlb, tn2, nullptr, 0};
   return launch_vote(c, recs, vw, 1, par, sh, d_votes, nullptr, nullptr, in, nullptr, s, f32, c->slack32);
 }
 
@@ -628,17 +703,38 @@ ia_status ia_find_helices(ia_ctx* c, const ia_hit* d_hits, const int32_t* h_off,
     return fail(c, IA_ERR_OVERFLOW, "a level exceeds %lld boxes", static_cast<long long>(kMaxEstimateBoxes));
   IA_HIP(c, hipSetDevice(c->device));
   const int32_t K = sc->top_k;
-  // events per chunk: as many as the arena holds
-  FindLayout L1;
-  layout_find(S.max_boxes, S.max_triples, K, max_hits, 1, max_hits, &L1);
-  if (L1.total > c->arena_bytes)
+  // events per chunk: as many as the arena holds.  Staged records: room for
+  // every (triple, hit) pair when a full chunk fits that way, else kRecCap
+  // per event (an event needing more is voted with in-kernel staging)
+  const int64_t worst_rec = std::max<int64_t>(1, S.max_triples * int64_t(max_hits));
+  auto chunk_for = [&](int64_t rpe, int32_t* out) {
+    FindLayout L1, L2;
+    layout_find(S.max_boxes, S.max_triples, K, max_hits, 1, max_hits, &L1, rpe);
+    if (L1.total > c->arena_bytes) return false;
+    layout_find(S.max_boxes, S.max_triples, K, max_hits, 2, 2 * int64_t(max_hits), &L2, rpe);
+    const size_t per_event = L2.total - L1.total;
+    int32_t ch = static_cast<int32_t>(std::min<size_t>(
+        std::max(1, n_events), 1 + (c->arena_bytes - L1.total) / std::max<size_t>(per_event, 1)));
+    *out = std::max(1, std::min(ch, std::min(c->max_chunk, 65535)));
+    return true;
+  };
+  const int32_t want = std::max(1, std::min(n_events, std::min(c->max_chunk, 65535)));
+  int64_t rpe = worst_rec;
+  int32_t chunk = 0;
+  const bool fits_worst = chunk_for(rpe, &chunk);
+  if ((!fits_worst || chunk < want) && kRecCap < worst_rec) {
+    int32_t chunk_cap = 0;
+    if (chunk_for(kRecCap, &chunk_cap) && (!fits_worst || chunk_cap > chunk)) {
+      rpe = kRecCap;
+      chunk = chunk_cap;
+    }
+  }
+  if (chunk == 0) {
+    FindLayout L1;
+    layout_find(S.max_boxes, S.max_triples, K, max_hits, 1, max_hits, &L1, rpe);
     return fail(c, IA_ERR_NOMEM, "scratch too small: need %zu bytes, have %zu", L1.total, c->arena_bytes);
-  FindLayout L2;
-  layout_find(S.max_boxes, S.max_triples, K, max_hits, 2, 2 * int64_t(max_hits), &L2);
-  const size_t per_event = L2.total - L1.total;
-  int32_t chunk = static_cast<int32_t>(std::min<size_t>(
-      std::max(1, n_events), 1 + (c->arena_bytes - L1.total) / std::max<size_t>(per_event, 1)));
-  chunk = std::max(1, std::min(chunk, std::min(c->max_chunk, 65535)));
+  }
+  const bool may_overflow = rpe < worst_rec;
   hipStream_t s = as_stream(stream);
   Persistent* ps = persistent(c);
   BoxD rb;
@@ -650,7 +746,7 @@ ia_status ia_find_helices(ia_ctx* c, const ia_hit* d_hits, const int32_t* h_off,
     for (int32_t e = e0; e < e0 + E; ++e) cmax = std::max(cmax, h_off[e + 1] - h_off[e]);
     const int64_t n_tot = int64_t(h_off[e0 + E]) - h_off[e0];
     FindLayout L;
-    layout_find(S.max_boxes, S.max_triples, K, cmax, E, n_tot, &L);
+    layout_find(S.max_boxes, S.max_triples, K, cmax, E, n_tot, &L, rpe);
     if (L.total > c->arena_bytes) return fail(c, IA_ERR_NOMEM, "chunk layout exceeds scratch");
     char* a = c->arena;
     int32_t* d_off = reinterpret_cast<int32_t*>(a + L.off);
@@ -670,6 +766,9 @@ ia_status ia_find_helices(ia_ctx* c, const ia_hit* d_hits, const int32_t* h_off,
     uint32_t* lbh = reinterpret_cast<uint32_t*>(a + L.lbh);
     int32_t* wg_max = reinterpret_cast<int32_t*>(a + L.wg_max);
     int32_t* live = reinterpret_cast<int32_t*>(a + L.live);
+    const RecIn rin{reinterpret_cast<int32_t*>(a + L.live_tri), reinterpret_cast<int32_t*>(a + L.rec_off),
+                    reinterpret_cast<int32_t*>(a + L.rec_fill), a + L.rec,
+                    reinterpret_cast<ia::TriFrame*>(a + L.tfr)};
     // chunk-relative hit offsets through a pinned slot whose last copy is done
     const uint32_t slot = c->slot_next++ % kOffSlots;
     if (c->slot_used[slot]) IA_HIP(c, hipEventSynchronize(c->slot_done[slot]));
@@ -683,6 +782,7 @@ ia_status ia_find_helices(ia_ctx* c, const ia_hit* d_hits, const int32_t* h_off,
     vw.k = K;
     vw.flag_stride = L.flag_stride;
     vw.tri_stride = L.tri_stride;
+    vw.rec_stride = L.rec_stride;
     vw.hist_stride = L.hist_stride;
     vw.wg_stride = L.wg_stride;
     vw.part_stride = L.part_stride;
@@ -705,11 +805,16 @@ ia_status ia_find_helices(ia_ctx* c, const ia_hit* d_hits, const int32_t* h_off,
         launch_classify(c, recs, vw, E, cmax, par, sh, flags, tlb, tn2, ev, s, f32, slack32);
         const int32_t vt = vote_tile(c, sh.n_boxes);
         hipLaunchKernelGGL(ia::k_threshold, dim3(1, E), dim3(ia::kWG), 0, s, tlb, tn2, lbh, vw, sh, K, c->prune, vt,
-                           ev, live, wg_max);
-        int32_t bx = 0;
-        const VoteIn in{flags, tlb, tn2, live};
-        ia_status st = launch_vote(c, recs, vw, E, par, sh, votes, hist, ev, in, wg_max, s, f32, slack32, &bx);
+                           ev, live, wg_max, rin.live_tri, rin.rec_off, rin.rec_fill, L.rec_stride);
+        launch_stage(recs, vw, E, par, sh, flags, rin, ev, s, f32, slack32);
+        const VoteIn in{flags, tlb, tn2, live, 1};
+        ia_status st = launch_vote_rec(c, vw, E, par, sh, votes, hist, ev, in, rin, wg_max, s, f32);
         if (st != IA_OK) return st;
+        int32_t bx = vt;
+        if (may_overflow) {
+          st = launch_vote(c, recs, vw, E, par, sh, votes, hist, ev, in, wg_max, s, f32, slack32, &bx);
+          if (st != IA_OK) return st;
+        }
         last_bx = bx;
         const uint32_t n_wg = (sh.n_boxes + bx - 1) / bx;
         hipLaunchKernelGGL(ia::k_select_wg, dim3(1, E), dim3(ia::kWG), 0, s, votes, vw, hist, wg_max, n_wg, bx, par,
