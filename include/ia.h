@@ -114,7 +114,8 @@ void ia_ctx_destroy(ia_ctx *ctx);
 const char *ia_last_error(const ia_ctx *ctx);
 
 /* Device-detected conditions since the last clear: flags bit 0 = malformed
- * hits seen (their number in *n_bad_hits), bit 1 = a vote above the bound
+ * hits seen (their number in *n_bad_hits), bit 2 = an event of
+ * ia_find_helices_dev outside its declared bounds, bit 1 = a vote above the bound
  * given to ia_refine.  Synchronises the device.  Either pointer may be NULL. */
 ia_status ia_ctx_status(ia_ctx *ctx, uint32_t *flags, int64_t *n_bad_hits);
 ia_status ia_ctx_clear_status(ia_ctx *ctx);
@@ -223,6 +224,24 @@ ia_status ia_estimate(ia_ctx *ctx, const ia_box *d_parents, int32_t n_parents, c
 ia_status ia_find_helices(ia_ctx *ctx, const ia_hit *d_hits, const int32_t *h_hit_offsets,
                           int32_t n_events, const ia_schedule *sched, ia_helix *d_out,
                           int32_t max_per_event, int32_t *d_n_out, int32_t *d_assigned, void *stream);
+
+/* The same search with the offsets on the device, for callers that capture
+ * the call into a HIP graph and replay it (a persistent batch form): it
+ * enqueues kernels only -- no host read of offsets, no copy, no
+ * synchronisation, no allocation -- so the work depends on the host only
+ * through n_events, max_hits and n_hits_total, which a replay keeps.
+ *   d_off         device, n_events + 1 non-decreasing offsets into d_hits
+ *   n_events      [1, 65535], all in one launch sequence (no chunking)
+ *   max_hits      hits of the largest event, in [1, 65535]
+ *   n_hits_total  hits addressable from d_hits (>= d_off[n_events])
+ * An event with more than max_hits hits or outside [0, n_hits_total) is not
+ * searched (0 helices) and sets status bit 2.  IA_ERR_NOMEM when the context
+ * scratch cannot hold n_events events of max_hits hits (see
+ * ia_ctx_scratch_needed).  Profiling must be off while capturing. */
+ia_status ia_find_helices_dev(ia_ctx *ctx, const ia_hit *d_hits, const int32_t *d_off, int32_t n_events,
+                              int32_t max_hits, int64_t n_hits_total, const ia_schedule *sched,
+                              ia_helix *d_out, int32_t max_per_event, int32_t *d_n_out,
+                              int32_t *d_assigned, void *stream);
 
 #ifdef __cplusplus
 }

@@ -125,6 +125,8 @@ def load():
     L.ia_estimate.argtypes = [P, P, i32, C.POINTER(i32), P, P, P]
     L.ia_find_helices.restype = i32
     L.ia_find_helices.argtypes = [P, P, C.POINTER(i32), i32, C.POINTER(Schedule), P, i32, P, P, P]
+    L.ia_find_helices_dev.restype = i32
+    L.ia_find_helices_dev.argtypes = [P, P, P, i32, i32, i64, C.POINTER(Schedule), P, i32, P, P, P]
     _lib = L
     return L
 
@@ -313,4 +315,22 @@ def find_helices(ctx, hits, offsets, sched, max_per_event=16, want_assigned=True
     ctx._check(ctx._L.ia_find_helices(ctx._h, _ptr(hits), off.ctypes.data_as(C.POINTER(C.c_int32)), int(n_events),
                                       C.byref(sched), _ptr(out), int(max_per_event), _ptr(n_out), _ptr(assigned),
                                       _stream_handle(stream)))
+    return out, n_out, assigned
+
+
+def find_helices_dev(ctx, hits, d_off, max_hits, sched, out, n_out, assigned=None, max_per_event=16, stream=None):
+    """The search with device offsets (int32 tensor of n_events + 1), enqueuing
+    kernels only, so it can be captured in a HIP graph (torch.cuda.graph) and
+    replayed on new contents of the same buffers."""
+    torch = _torch()
+    _check_dev(hits, torch.float64, "hits", ctx.device)
+    _check_dev(d_off, torch.int32, "d_off", ctx.device)
+    n_events = d_off.numel() - 1
+    if out.numel() < n_events * max_per_event * HELIX_DTYPE.itemsize or n_out.numel() < n_events:
+        raise IAError(1, "output tensors too small")
+    if assigned is not None and assigned.numel() < hits.shape[0]:
+        raise IAError(1, "assigned too small")
+    ctx._check(ctx._L.ia_find_helices_dev(ctx._h, _ptr(hits), _ptr(d_off), int(n_events), int(max_hits),
+                                          int(hits.shape[0]), C.byref(sched), _ptr(out), int(max_per_event),
+                                          _ptr(n_out), _ptr(assigned), _stream_handle(stream)))
     return out, n_out, assigned

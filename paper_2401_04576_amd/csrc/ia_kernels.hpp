@@ -78,12 +78,14 @@ struct EvView {
   int32_t wg_stride;            // workgroup maxima per event
   int32_t part_stride;          // estimate chunk sums per event (doubles)
   int32_t max_out;              // helices per event
+  int32_t max_hits;             // hits per event the strides are sized for (0: unchecked)
+  int64_t n_total;              // hits addressable from the batch's first hit
   __device__ int32_t beg(int e) const { return off ? off[e] : 0; }
   __device__ int32_t count(int e) const { return off ? off[e + 1] - off[e] : n_single; }
 };
 
 // status word bits (device-detected problems, read after a stream sync)
-enum : uint32_t { kStBadHit = 1u, kStVoteOverflow = 2u };
+enum : uint32_t { kStBadHit = 1u, kStVoteOverflow = 2u, kStBadOffsets = 4u };
 
 // vote-kernel work counters: kWorkSlots slots of 16 u64 (one 128-byte line
 // each); counters 0..3 of a slot: stereo (box, hit) evaluations and staged
@@ -532,12 +534,21 @@ __global__ void k_prep(const double* __restrict__ hits, const uint8_t* __restric
   const int32_t beg = vw.beg(e), n_hits = vw.count(e), n_bins = n_hits + 1;
   const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   const int32_t stride = gridDim.x * blockDim.x;
+  // offsets are checked against the sizes the strides were laid out for; an
+  // event outside them is stopped (no kernel touches it) and flagged
+  const bool bad_ev = vw.max_hits > 0 && (n_hits < 0 || n_hits > vw.max_hits || beg < 0 ||
+                                          static_cast<int64_t>(beg) + n_hits > vw.n_total);
   if (ev && i == 0) {
     EventState es{};
+    if (bad_ev) {
+      es.done = 1;
+      atomicOr(status, kStBadOffsets);
+    }
     ev[e] = es;
     if (n_out) n_out[e] = 0;
     if (e == 0) *range_dst = range;
   }
+  if (bad_ev) return;
   if (hist)
     for (int32_t b = i; b < n_bins; b += stride) hist[int64_t(e) * vw.hist_stride + b] = 0u;
   if (lbh)

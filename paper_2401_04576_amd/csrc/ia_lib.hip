@@ -390,6 +390,129 @@ bool sched_shapes(const ia_schedule* sc, SchedShapes* S) {
   return true;
 }
 
+ia_status check_sched(ia_ctx* c, const ia_schedule* sc) {
+  if (sc->n_refine < 0 || sc->n_refine >= IA_MAX_LEVELS) return fail(c, IA_ERR_INVALID, "n_refine %d", sc->n_refine);
+  if (sc->top_k < 1 || sc->top_k > kMaxTopK) return fail(c, IA_ERR_INVALID, "top_k %d", sc->top_k);
+  if (sc->n_helix_max < 0) return fail(c, IA_ERR_INVALID, "n_helix_max %d", sc->n_helix_max);
+  if (!(sc->hitfind_scale >= 0.0)) return fail(c, IA_ERR_INVALID, "hitfind_scale");
+  for (int j = 0; j < 5; ++j)
+    if (!(sc->range.lo[j] <= sc->range.hi[j])) return fail(c, IA_ERR_INVALID, "range dimension %d: lo > hi", j);
+  for (int l = 0; l <= sc->n_refine; ++l)
+    if (sc->prec[l] != IA_FP64 && sc->prec[l] != IA_FP32)
+      return fail(c, IA_ERR_INVALID, "precision %d at level %d", sc->prec[l], l);
+  if (!(sc->fp32_slack >= 0.0 && sc->fp32_slack <= 1e-3))
+    return fail(c, IA_ERR_INVALID, "fp32_slack %g outside [0, 1e-3]", sc->fp32_slack);
+  return IA_OK;
+}
+
+// One chunk of E events through every pass and level.  The chunk's CSR
+// offsets (relative to hits_chunk) come from the host (h_off_chunk, copied
+// through the pinned ring) or are already on the device (dev_off, then no
+// host synchronisation or copy happens: the launches can be captured).
+ia_status run_chunk(ia_ctx* c, const double* hits_chunk, const int32_t* h_off_chunk, const int32_t* dev_off,
+                    int32_t E, int32_t cmax, int64_t n_tot, const SchedShapes& S, const ia_schedule* sc,
+                    float slack32, int64_t rpe, bool may_overflow, ia::HelixOut* out_chunk, int32_t max_per_event,
+                    int32_t* n_out_chunk, int32_t* assigned_chunk, hipStream_t s) {
+  const int32_t K = sc->top_k;
+  Persistent* ps = persistent(c);
+  BoxD rb;
+  std::memcpy(&rb, &sc->range, sizeof rb);
+  FindLayout L;
+  layout_find(S.max_boxes, S.max_triples, K, cmax, E, n_tot, &L, rpe);
+  if (L.total > c->arena_bytes) return fail(c, IA_ERR_NOMEM, "chunk layout exceeds scratch");
+  char* a = c->arena;
+  int32_t* d_off = dev_off ? const_cast<int32_t*>(dev_off) : reinterpret_cast<int32_t*>(a + L.off);
+  HitRec* recs = reinterpret_cast<HitRec*>(a + L.recs);
+  uint16_t* votes = reinterpret_cast<uint16_t*>(a + L.votes);
+  uint32_t* hist = reinterpret_cast<uint32_t*>(a + L.hist);
+  BoxD* selA = reinterpret_cast<BoxD*>(a + L.selA);
+  BoxD* selB = reinterpret_cast<BoxD*>(a + L.selB);
+  BoxD* range = reinterpret_cast<BoxD*>(a + L.range);
+  int64_t* sel_idx = reinterpret_cast<int64_t*>(a + L.sel_idx);
+  uint16_t* sel_v = reinterpret_cast<uint16_t*>(a + L.sel_v);
+  EventState* ev = reinterpret_cast<EventState*>(a + L.ev);
+  double* part = reinterpret_cast<double*>(a + L.part);
+  uint8_t* flags = reinterpret_cast<uint8_t*>(a + L.flags);
+  int32_t* tlb = reinterpret_cast<int32_t*>(a + L.tlb);
+  int32_t* tn2 = reinterpret_cast<int32_t*>(a + L.tn2);
+  uint32_t* lbh = reinterpret_cast<uint32_t*>(a + L.lbh);
+  int32_t* wg_max = reinterpret_cast<int32_t*>(a + L.wg_max);
+  int32_t* live = reinterpret_cast<int32_t*>(a + L.live);
+  const RecIn rin{reinterpret_cast<int32_t*>(a + L.live_tri), reinterpret_cast<int32_t*>(a + L.rec_off),
+                  reinterpret_cast<int32_t*>(a + L.rec_fill), a + L.rec,
+                  reinterpret_cast<ia::TriFrame*>(a + L.tfr)};
+  if (!dev_off) {
+    // chunk-relative hit offsets through a pinned slot whose last copy is done
+    const uint32_t slot = c->slot_next++ % kOffSlots;
+    if (c->slot_used[slot]) IA_HIP(c, hipEventSynchronize(c->slot_done[slot]));
+    int32_t* ho = c->pinned + size_t(slot) * kOffSlotInts;
+    for (int32_t e = 0; e <= E; ++e) ho[e] = h_off_chunk[e] - h_off_chunk[0];
+    IA_HIP(c, hipMemcpyAsync(d_off, ho, sizeof(int32_t) * (size_t(E) + 1), hipMemcpyHostToDevice, s));
+    IA_HIP(c, hipEventRecord(c->slot_done[slot], s));
+    c->slot_used[slot] = true;
+  }
+  ia::EvView vw{};
+  vw.off = d_off;
+  vw.k = K;
+  vw.flag_stride = L.flag_stride;
+  vw.tri_stride = L.tri_stride;
+  vw.rec_stride = L.rec_stride;
+  vw.hist_stride = L.hist_stride;
+  vw.wg_stride = L.wg_stride;
+  vw.part_stride = L.part_stride;
+  vw.max_out = max_per_event;
+  vw.max_hits = std::max(1, cmax);
+  vw.n_total = n_tot;
+  const double* hits = hits_chunk;
+  int32_t* assigned = assigned_chunk;
+  ia::HelixOut* out = out_chunk;
+  int32_t* n_out = n_out_chunk;
+  const int32_t pg = std::max(1, (cmax + 2 + 255) / 256);
+  hipLaunchKernelGGL(ia::k_prep, dim3(pg, E), dim3(256), 0, s, hits, nullptr, vw, recs, hist, lbh, tlb, tn2,
+                     &ps->status, &ps->n_bad, ev, n_out, range, rb, assigned);
+  for (int32_t pass = 0; pass < std::min(sc->n_helix_max, max_per_event); ++pass) {
+    const BoxD* par = range;
+    Shape sh = S.sh0;
+    BoxD* sel = selA;
+    vw.par_stride = 0;
+    int32_t last_bx = 1;
+    for (int32_t lev = 0; lev <= sc->n_refine; ++lev) {
+      const bool f32 = sc->prec[lev] == IA_FP32;
+      launch_classify(c, recs, vw, E, cmax, par, sh, flags, tlb, tn2, ev, s, f32, slack32);
+      const int32_t vt = vote_tile(c, sh.n_boxes);
+      hipLaunchKernelGGL(ia::k_threshold, dim3(1, E), dim3(ia::kWG), 0, s, tlb, tn2, lbh, vw, sh, K, c->prune, vt,
+                         ev, live, wg_max, rin.live_tri, rin.rec_off, rin.rec_fill, L.rec_stride);
+      launch_stage(recs, vw, E, par, sh, flags, rin, ev, s, f32, slack32);
+      const VoteIn in{flags, tlb, tn2, live, 1};
+      ia_status st = launch_vote_rec(c, vw, E, par, sh, votes, hist, ev, in, rin, wg_max, s, f32);
+      if (st != IA_OK) return st;
+      int32_t bx = vt;
+      if (may_overflow) {
+        st = launch_vote(c, recs, vw, E, par, sh, votes, hist, ev, in, wg_max, s, f32, slack32, &bx);
+        if (st != IA_OK) return st;
+      }
+      last_bx = bx;
+      const uint32_t n_wg = (sh.n_boxes + bx - 1) / bx;
+      hipLaunchKernelGGL(ia::k_select_wg, dim3(1, E), dim3(ia::kWG), 0, s, votes, vw, hist, wg_max, n_wg, bx, par,
+                         sh, sel, sel_idx, sel_v, ev, lev == 0 ? std::max(sc->v_min, 0) : 0, tlb, tn2);
+      IA_HIP(c, hipGetLastError());
+      if (lev == sc->n_refine) break;
+      const int32_t k_eff = static_cast<int32_t>(std::min<int64_t>(K, sh.n_boxes));
+      if (!make_shape(sc->split, k_eff, &sh)) return fail(c, IA_ERR_OVERFLOW, "split too large");
+      par = sel;
+      vw.par_stride = K;
+      sel = (sel == selA) ? selB : selA;
+    }
+    const int32_t n_part = est_parts(sh.n_boxes);
+    hipLaunchKernelGGL(ia::k_est_partial, dim3(n_part, E), dim3(ia::kWG), 0, s, par, sh, votes, sel, sel_v, part, vw,
+                       ev, wg_max, last_bx);
+    hipLaunchKernelGGL(ia::k_est_final, dim3(1, E), dim3(ia::kWG), 0, s, part, n_part, sel, sel_v,
+                       static_cast<ia::EstimateOut*>(nullptr), ev, recs, vw, sc->hitfind_scale, assigned, out, n_out);
+    IA_HIP(c, hipGetLastError());
+  }
+  return IA_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -678,17 +801,8 @@ ia_status ia_find_helices(ia_ctx* c, const ia_hit* d_hits, const int32_t* h_off,
   if (!h_off || !sc || !d_out || !d_n_out) return fail(c, IA_ERR_INVALID, "null pointer argument");
   if (n_events < 0) return fail(c, IA_ERR_INVALID, "n_events %d < 0", n_events);
   if (max_per_event < 1) return fail(c, IA_ERR_INVALID, "max_per_event %d < 1", max_per_event);
-  if (sc->n_refine < 0 || sc->n_refine >= IA_MAX_LEVELS) return fail(c, IA_ERR_INVALID, "n_refine %d", sc->n_refine);
-  if (sc->top_k < 1 || sc->top_k > kMaxTopK) return fail(c, IA_ERR_INVALID, "top_k %d", sc->top_k);
-  if (sc->n_helix_max < 0) return fail(c, IA_ERR_INVALID, "n_helix_max %d", sc->n_helix_max);
-  if (!(sc->hitfind_scale >= 0.0)) return fail(c, IA_ERR_INVALID, "hitfind_scale");
-  for (int j = 0; j < 5; ++j)
-    if (!(sc->range.lo[j] <= sc->range.hi[j])) return fail(c, IA_ERR_INVALID, "range dimension %d: lo > hi", j);
-  for (int l = 0; l <= sc->n_refine; ++l)
-    if (sc->prec[l] != IA_FP64 && sc->prec[l] != IA_FP32)
-      return fail(c, IA_ERR_INVALID, "precision %d at level %d", sc->prec[l], l);
-  if (!(sc->fp32_slack >= 0.0 && sc->fp32_slack <= 1e-3))
-    return fail(c, IA_ERR_INVALID, "fp32_slack %g outside [0, 1e-3]", sc->fp32_slack);
+  const ia_status sv = check_sched(c, sc);
+  if (sv != IA_OK) return sv;
   const float slack32 = ia::ru32(sc->fp32_slack);
   int32_t max_hits = 0;
   for (int32_t e = 0; e < n_events; ++e) {
@@ -736,106 +850,53 @@ ia_status ia_find_helices(ia_ctx* c, const ia_hit* d_hits, const int32_t* h_off,
   }
   const bool may_overflow = rpe < worst_rec;
   hipStream_t s = as_stream(stream);
-  Persistent* ps = persistent(c);
-  BoxD rb;
-  std::memcpy(&rb, &sc->range, sizeof rb);
   chunk = std::min(chunk, kOffSlotInts - 1);
   for (int32_t e0 = 0; e0 < n_events; e0 += chunk) {
     const int32_t E = std::min(chunk, n_events - e0);
     int32_t cmax = 0;
     for (int32_t e = e0; e < e0 + E; ++e) cmax = std::max(cmax, h_off[e + 1] - h_off[e]);
     const int64_t n_tot = int64_t(h_off[e0 + E]) - h_off[e0];
-    FindLayout L;
-    layout_find(S.max_boxes, S.max_triples, K, cmax, E, n_tot, &L, rpe);
-    if (L.total > c->arena_bytes) return fail(c, IA_ERR_NOMEM, "chunk layout exceeds scratch");
-    char* a = c->arena;
-    int32_t* d_off = reinterpret_cast<int32_t*>(a + L.off);
-    HitRec* recs = reinterpret_cast<HitRec*>(a + L.recs);
-    uint16_t* votes = reinterpret_cast<uint16_t*>(a + L.votes);
-    uint32_t* hist = reinterpret_cast<uint32_t*>(a + L.hist);
-    BoxD* selA = reinterpret_cast<BoxD*>(a + L.selA);
-    BoxD* selB = reinterpret_cast<BoxD*>(a + L.selB);
-    BoxD* range = reinterpret_cast<BoxD*>(a + L.range);
-    int64_t* sel_idx = reinterpret_cast<int64_t*>(a + L.sel_idx);
-    uint16_t* sel_v = reinterpret_cast<uint16_t*>(a + L.sel_v);
-    EventState* ev = reinterpret_cast<EventState*>(a + L.ev);
-    double* part = reinterpret_cast<double*>(a + L.part);
-    uint8_t* flags = reinterpret_cast<uint8_t*>(a + L.flags);
-    int32_t* tlb = reinterpret_cast<int32_t*>(a + L.tlb);
-    int32_t* tn2 = reinterpret_cast<int32_t*>(a + L.tn2);
-    uint32_t* lbh = reinterpret_cast<uint32_t*>(a + L.lbh);
-    int32_t* wg_max = reinterpret_cast<int32_t*>(a + L.wg_max);
-    int32_t* live = reinterpret_cast<int32_t*>(a + L.live);
-    const RecIn rin{reinterpret_cast<int32_t*>(a + L.live_tri), reinterpret_cast<int32_t*>(a + L.rec_off),
-                    reinterpret_cast<int32_t*>(a + L.rec_fill), a + L.rec,
-                    reinterpret_cast<ia::TriFrame*>(a + L.tfr)};
-    // chunk-relative hit offsets through a pinned slot whose last copy is done
-    const uint32_t slot = c->slot_next++ % kOffSlots;
-    if (c->slot_used[slot]) IA_HIP(c, hipEventSynchronize(c->slot_done[slot]));
-    int32_t* ho = c->pinned + size_t(slot) * kOffSlotInts;
-    for (int32_t e = 0; e <= E; ++e) ho[e] = h_off[e0 + e] - h_off[e0];
-    IA_HIP(c, hipMemcpyAsync(d_off, ho, sizeof(int32_t) * (size_t(E) + 1), hipMemcpyHostToDevice, s));
-    IA_HIP(c, hipEventRecord(c->slot_done[slot], s));
-    c->slot_used[slot] = true;
-    ia::EvView vw{};
-    vw.off = d_off;
-    vw.k = K;
-    vw.flag_stride = L.flag_stride;
-    vw.tri_stride = L.tri_stride;
-    vw.rec_stride = L.rec_stride;
-    vw.hist_stride = L.hist_stride;
-    vw.wg_stride = L.wg_stride;
-    vw.part_stride = L.part_stride;
-    vw.max_out = max_per_event;
-    const double* hits = reinterpret_cast<const double*>(d_hits) + 8 * int64_t(h_off[e0]);
-    int32_t* assigned = d_assigned ? d_assigned + h_off[e0] : nullptr;
-    ia::HelixOut* out = reinterpret_cast<ia::HelixOut*>(d_out) + int64_t(e0) * max_per_event;
-    int32_t* n_out = d_n_out + e0;
-    const int32_t pg = std::max(1, (cmax + 2 + 255) / 256);
-    hipLaunchKernelGGL(ia::k_prep, dim3(pg, E), dim3(256), 0, s, hits, nullptr, vw, recs, hist, lbh, tlb, tn2,
-                       &ps->status, &ps->n_bad, ev, n_out, range, rb, assigned);
-    for (int32_t pass = 0; pass < std::min(sc->n_helix_max, max_per_event); ++pass) {
-      const BoxD* par = range;
-      Shape sh = S.sh0;
-      BoxD* sel = selA;
-      vw.par_stride = 0;
-      int32_t last_bx = 1;
-      for (int32_t lev = 0; lev <= sc->n_refine; ++lev) {
-        const bool f32 = sc->prec[lev] == IA_FP32;
-        launch_classify(c, recs, vw, E, cmax, par, sh, flags, tlb, tn2, ev, s, f32, slack32);
-        const int32_t vt = vote_tile(c, sh.n_boxes);
-        hipLaunchKernelGGL(ia::k_threshold, dim3(1, E), dim3(ia::kWG), 0, s, tlb, tn2, lbh, vw, sh, K, c->prune, vt,
-                           ev, live, wg_max, rin.live_tri, rin.rec_off, rin.rec_fill, L.rec_stride);
-        launch_stage(recs, vw, E, par, sh, flags, rin, ev, s, f32, slack32);
-        const VoteIn in{flags, tlb, tn2, live, 1};
-        ia_status st = launch_vote_rec(c, vw, E, par, sh, votes, hist, ev, in, rin, wg_max, s, f32);
-        if (st != IA_OK) return st;
-        int32_t bx = vt;
-        if (may_overflow) {
-          st = launch_vote(c, recs, vw, E, par, sh, votes, hist, ev, in, wg_max, s, f32, slack32, &bx);
-          if (st != IA_OK) return st;
-        }
-        last_bx = bx;
-        const uint32_t n_wg = (sh.n_boxes + bx - 1) / bx;
-        hipLaunchKernelGGL(ia::k_select_wg, dim3(1, E), dim3(ia::kWG), 0, s, votes, vw, hist, wg_max, n_wg, bx, par,
-                           sh, sel, sel_idx, sel_v, ev, lev == 0 ? std::max(sc->v_min, 0) : 0, tlb, tn2);
-        IA_HIP(c, hipGetLastError());
-        if (lev == sc->n_refine) break;
-        const int32_t k_eff = static_cast<int32_t>(std::min<int64_t>(K, sh.n_boxes));
-        if (!make_shape(sc->split, k_eff, &sh)) return fail(c, IA_ERR_OVERFLOW, "split too large");
-        par = sel;
-        vw.par_stride = K;
-        sel = (sel == selA) ? selB : selA;
-      }
-      const int32_t n_part = est_parts(sh.n_boxes);
-      hipLaunchKernelGGL(ia::k_est_partial, dim3(n_part, E), dim3(ia::kWG), 0, s, par, sh, votes, sel, sel_v, part, vw,
-                         ev, wg_max, last_bx);
-      hipLaunchKernelGGL(ia::k_est_final, dim3(1, E), dim3(ia::kWG), 0, s, part, n_part, sel, sel_v,
-                         static_cast<ia::EstimateOut*>(nullptr), ev, recs, vw, sc->hitfind_scale, assigned, out, n_out);
-      IA_HIP(c, hipGetLastError());
-    }
+    const ia_status st = run_chunk(c, reinterpret_cast<const double*>(d_hits) + 8 * int64_t(h_off[e0]), h_off + e0,
+                                   nullptr, E, cmax, n_tot, S, sc, slack32, rpe, may_overflow,
+                                   reinterpret_cast<ia::HelixOut*>(d_out) + int64_t(e0) * max_per_event,
+                                   max_per_event, d_n_out + e0, d_assigned ? d_assigned + h_off[e0] : nullptr, s);
+    if (st != IA_OK) return st;
   }
   return IA_OK;
+}
+
+ia_status ia_find_helices_dev(ia_ctx* c, const ia_hit* d_hits, const int32_t* d_off, int32_t n_events,
+                              int32_t max_hits, int64_t n_hits_total, const ia_schedule* sc, ia_helix* d_out,
+                              int32_t max_per_event, int32_t* d_n_out, int32_t* d_assigned, void* stream) {
+  if (!c) return IA_ERR_INVALID;
+  if (!d_off || !sc || !d_out || !d_n_out) return fail(c, IA_ERR_INVALID, "null pointer argument");
+  if (n_events < 1 || n_events > 65535) return fail(c, IA_ERR_INVALID, "n_events %d outside [1, 65535]", n_events);
+  if (max_per_event < 1) return fail(c, IA_ERR_INVALID, "max_per_event %d < 1", max_per_event);
+  if (max_hits < 1 || max_hits > kMaxHits) return fail(c, IA_ERR_INVALID, "max_hits %d outside [1, %d]", max_hits, kMaxHits);
+  if (n_hits_total < 0) return fail(c, IA_ERR_INVALID, "n_hits_total < 0");
+  if (n_hits_total > 0 && !d_hits) return fail(c, IA_ERR_INVALID, "d_hits is NULL");
+  const ia_status sv = check_sched(c, sc);
+  if (sv != IA_OK) return sv;
+  const float slack32 = ia::ru32(sc->fp32_slack);
+  SchedShapes S;
+  if (!sched_shapes(sc, &S)) return fail(c, IA_ERR_OVERFLOW, "a level exceeds 2^31 - 1 boxes");
+  if (S.max_boxes > kMaxEstimateBoxes)
+    return fail(c, IA_ERR_OVERFLOW, "a level exceeds %lld boxes", static_cast<long long>(kMaxEstimateBoxes));
+  IA_HIP(c, hipSetDevice(c->device));
+  // records for every (triple, hit) pair when they fit, else kRecCap per event
+  const int64_t worst_rec = std::max<int64_t>(1, S.max_triples * int64_t(max_hits));
+  int64_t rpe = worst_rec;
+  FindLayout L;
+  layout_find(S.max_boxes, S.max_triples, sc->top_k, max_hits, n_events, n_hits_total, &L, rpe);
+  if (L.total > c->arena_bytes && kRecCap < worst_rec) {
+    rpe = kRecCap;
+    layout_find(S.max_boxes, S.max_triples, sc->top_k, max_hits, n_events, n_hits_total, &L, rpe);
+  }
+  if (L.total > c->arena_bytes)
+    return fail(c, IA_ERR_NOMEM, "scratch too small: need %zu bytes, have %zu", L.total, c->arena_bytes);
+  return run_chunk(c, reinterpret_cast<const double*>(d_hits), nullptr, d_off, n_events, max_hits, n_hits_total, S, sc,
+                   slack32, rpe, rpe < worst_rec, reinterpret_cast<ia::HelixOut*>(d_out), max_per_event, d_n_out,
+                   d_assigned, as_stream(stream));
 }
 
 }  // extern "C"
