@@ -191,6 +191,7 @@ def main():
     ap.add_argument("--rate", type=float, default=20000.0, help="serving: Poisson arrival rate, events/s")
     ap.add_argument("--slots", type=int, default=4, help="serving: concurrent batches")
     ap.add_argument("--report-events", type=int, default=1000, help="mixed-report: noiseless single-helix events")
+    ap.add_argument("--no-autotune", action="store_true", help="skip the vote-tile autotuner")
     ap.add_argument("--no-graph", action="store_true",
                     help="batch: call ia_find_helices per step instead of replaying a captured graph")
     ap.add_argument("--prec", choices=["fp64", "mixed"], default="fp64",
@@ -250,6 +251,8 @@ def run_event(args):
                         torch.zeros(B * HB, dtype=torch.uint8, device=dev),
                         torch.zeros(B, dtype=torch.int32, device=dev),
                         torch.full((h.shape[0],), -1, dtype=torch.int32, device=dev)))
+
+    tuned = {} if args.no_autotune else ctx.autotune(batches[0][1], batches[0][2], sched, max_per_event=1)
 
     def step(k):
         evs, hits, off, out, n_out, assigned = batches[k]
@@ -313,15 +316,14 @@ def run_event(args):
                                "then 4 levels of top-32 boxes split 4^5; estimate and hit finding",
                    "events_per_step": B, "mean_hits": float(np.mean([e.n_hits for e in events])),
                    "boxes_per_event": int(sum(nb for nb, _ in shapes)),
-                   "helices_found_per_event": found / n_done},
+                   "helices_found_per_event": found / n_done,
+                   "vote_tiles": {str(k): v for k, v in tuned.items()}},
         "events_per_s": n_done / wall,
         "p50_ms": float(np.percentile(lat, 50)) if lat else None,
         "p99_ms": float(np.percentile(lat, 99)) if lat else None,
         "latency": "p50/p99: one event per call, arrival of resident hits to its recorded helix",
-        "roofline": roofline(prof, work, wall * rep_steps / args.steps),
+        "roofline": roofline(prof, work, wall),
     }
-    if use_graph:
-        res["roofline"]["measured_on"] = "eager profiled repeat of the last timed batch"
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(batches[args.warmup][0], sched_kw, lo, hi, args.cpu_budget)
     ctx.close()
@@ -360,6 +362,7 @@ def run_batch(args):
         assigned = torch.full((hits.shape[0],), -1, dtype=torch.int32, device=dev)
         batches.append((evs, hits, off, out, n_out, assigned))
     stream = torch.cuda.current_stream()
+    tuned = {} if args.no_autotune else ctx.autotune(batches[0][1], batches[0][2], sched, max_per_event=nh)
     use_graph = not args.no_graph
     if use_graph:
         # one capture of the device-offset search over static buffers sized for
@@ -455,6 +458,7 @@ def run_batch(args):
                                "levels of top-32 split 4^5; up to 5 greedy helix passes; "
                                + ("FP64" if args.prec == "fp64" else "FP32 at levels 0-2, FP64 at 3-4 and the fit"),
                    "events_per_step": E, "helices_found_per_event": found / (E * args.steps),
+                   "vote_tiles": {str(k): v for k, v in tuned.items()},
                    "helices_generated_per_event": truth / (E * args.steps)},
         "events_per_s": E * args.steps / wall,
         "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),

@@ -164,6 +164,13 @@ ia_status ia_ctx_set_prefilter(ia_ctx *ctx, int32_t mode);
  * a level differs (pruned boxes hold their lower bound). */
 ia_status ia_ctx_set_pruning(ia_ctx *ctx, int32_t enable);
 
+/* Parent-level exclusion in ia_find_helices (enabled by default): at each
+ * refinement level, an interval enclosure over all of a parent's children
+ * (their frames, pair quantities and stereo drifts) proves that a hit votes
+ * for none of them, and its per-triple classification is skipped.  Results
+ * do not depend on it. */
+ia_status ia_ctx_set_parent_filter(ia_ctx *ctx, int32_t enable);
+
 /* ia_find_helices launches its events in batches: every kernel of a level
  * covers all events of a batch (one event per grid row).  A batch holds as
  * many events as the scratch arena fits, at most max_events (default 65535).
@@ -224,6 +231,19 @@ ia_status ia_estimate(ia_ctx *ctx, const ia_box *d_parents, int32_t n_parents, c
 ia_status ia_find_helices(ia_ctx *ctx, const ia_hit *d_hits, const int32_t *h_hit_offsets,
                           int32_t n_events, const ia_schedule *sched, ia_helix *d_out,
                           int32_t max_per_event, int32_t *d_n_out, int32_t *d_assigned, void *stream);
+
+/* Vote-tile autotuner: runs the search on a sample batch (as ia_find_helices,
+ * writing d_out and d_n_out) once per tile size 256, 128 and 64 boxes per
+ * workgroup, times the vote kernel per level size (boxes per event), and
+ * keeps the fastest tile for each size; the context's automatic tile choice
+ * uses that table afterwards (ia_ctx_set_vote_tile still overrides it).
+ * Synchronises the stream.  Results never depend on the tile. */
+ia_status ia_ctx_autotune(ia_ctx *ctx, const ia_hit *d_hits, const int32_t *h_hit_offsets, int32_t n_events,
+                          const ia_schedule *sched, ia_helix *d_out, int32_t max_per_event, int32_t *d_n_out,
+                          void *stream);
+/* The autotuned table: writes up to max_entries (level size, tile) pairs and
+ * returns the number of entries. */
+int32_t ia_ctx_tuned(const ia_ctx *ctx, uint32_t *n_boxes, int32_t *tiles, int32_t max_entries);
 
 /* The same search with the offsets on the device, for callers that capture
  * the call into a HIP graph and replay it (a persistent batch form): it

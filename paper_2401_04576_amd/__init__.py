@@ -104,6 +104,8 @@ def load():
     L.ia_ctx_clear_status.argtypes = [P]
     L.ia_ctx_set_batch.restype = i32
     L.ia_ctx_set_batch.argtypes = [P, i32]
+    L.ia_ctx_set_parent_filter.restype = i32
+    L.ia_ctx_set_parent_filter.argtypes = [P, i32]
     L.ia_ctx_set_pruning.restype = i32
     L.ia_ctx_set_pruning.argtypes = [P, i32]
     L.ia_ctx_set_prefilter.restype = i32
@@ -125,6 +127,10 @@ def load():
     L.ia_estimate.argtypes = [P, P, i32, C.POINTER(i32), P, P, P]
     L.ia_find_helices.restype = i32
     L.ia_find_helices.argtypes = [P, P, C.POINTER(i32), i32, C.POINTER(Schedule), P, i32, P, P, P]
+    L.ia_ctx_autotune.restype = i32
+    L.ia_ctx_autotune.argtypes = [P, P, C.POINTER(i32), i32, C.POINTER(Schedule), P, i32, P, P]
+    L.ia_ctx_tuned.restype = i32
+    L.ia_ctx_tuned.argtypes = [P, P, P, i32]
     L.ia_find_helices_dev.restype = i32
     L.ia_find_helices_dev.argtypes = [P, P, P, i32, i32, i64, C.POINTER(Schedule), P, i32, P, P, P]
     _lib = L
@@ -209,6 +215,27 @@ class Context:
     def set_pruning(self, enable=True):
         """find_helices: skip triples whose vote upper bound cannot reach the selection."""
         self._check(self._L.ia_ctx_set_pruning(self._h, 1 if enable else 0))
+
+    def autotune(self, hits, offsets, sched, max_per_event=16, stream=None):
+        """Pick the vote tile per level size by timing a sample batch; returns {level boxes: tile}."""
+        torch = _torch()
+        _check_dev(hits, torch.float64, "hits", self.device)
+        off = np.ascontiguousarray(np.asarray(offsets, dtype=np.int32))
+        n_events = off.shape[0] - 1
+        out = torch.zeros(max(1, n_events * max_per_event) * HELIX_DTYPE.itemsize, dtype=torch.uint8,
+                          device=hits.device)
+        n_out = torch.zeros(max(1, n_events), dtype=torch.int32, device=hits.device)
+        self._check(self._L.ia_ctx_autotune(self._h, _ptr(hits), off.ctypes.data_as(C.POINTER(C.c_int32)),
+                                            int(n_events), C.byref(sched), _ptr(out), int(max_per_event),
+                                            _ptr(n_out), _stream_handle(stream)))
+        nb = np.zeros(64, dtype=np.uint32)
+        tl = np.zeros(64, dtype=np.int32)
+        n = self._L.ia_ctx_tuned(self._h, nb.ctypes.data, tl.ctypes.data, 64)
+        return {int(nb[i]): int(tl[i]) for i in range(min(n, 64))}
+
+    def set_parent_filter(self, enable=True):
+        """find_helices: parent-level exclusion of hits at refinement levels."""
+        self._check(self._L.ia_ctx_set_parent_filter(self._h, 1 if enable else 0))
 
     def set_prefilter(self, mode=-1):
         """(triple, hit) classification proofs: -1 or 1 on, 0 off."""

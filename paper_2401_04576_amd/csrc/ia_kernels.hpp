@@ -74,6 +74,7 @@ struct EvView {
   int64_t flag_stride;          // pre-pass flags per event
   int64_t tri_stride;           // per-triple vote bounds per event
   int64_t rec_stride;           // staged pair records per event
+  int64_t pflag_stride;         // parent-level exclusion flags per event
   int32_t hist_stride;          // histogram bins per event
   int32_t wg_stride;            // workgroup maxima per event
   int32_t part_stride;          // estimate chunk sums per event (doubles)
@@ -521,6 +522,165 @@ IA_HD void centre_ranges(const BoxD& P, const uint32_t m[5], Iv* Z, Iv* L) {
 }
 
 // ---------------------------------------------------------------------------
+// Parent-level exclusion (refinement levels): can a hit vote for any box of
+// a parent at all?  Every point operation of triple_frame and
+// pair_quantities is mirrored by the same interval operation over the
+// parent's child-triple centres (whose end points are the first and last
+// child centre of each dimension, exactly as the children compute them).
+// Round-to-nearest is monotone and every interval end point is rounded
+// outward by at least one ulp, so each interval contains the floating-point
+// value every child triple computes; the sin and cos enclosures carry their
+// margin, and atan2 is enclosed by its values at the corners of its argument
+// box plus 1e-13 (the whole [-pi, pi] when that box meets the negative x axis).
+struct FrameIv {
+  Iv K, Dd, Fi;                 // the parent's kappa, d0, phi0 ranges (for G)
+  double sig;
+  Iv R, XC, YC, SP0, CP0;
+};
+struct PairQIv { Iv sArc, dphi, RAx, sinA, cosA, sAx, cAx, c2, s2, twoRAx2, RpRAx; };
+
+IA_HD Iv atan2_encl(Iv Y, Iv X) {
+  if (X.lo <= 0.0 && Y.lo <= 0.0 && Y.hi >= 0.0) return {-kPio2Up * 2.0, kPio2Up * 2.0};
+  const double a = atan2_p(Y.lo, X.lo), b = atan2_p(Y.lo, X.hi), c = atan2_p(Y.hi, X.lo), d = atan2_p(Y.hi, X.hi);
+  return {fmin(fmin(a, b), fmin(c, d)) - 1e-13, fmax(fmax(a, b), fmax(c, d)) + 1e-13};
+}
+
+// false when the children's kappa centres are not all of one sign (no frame)
+IA_HD bool parent_frame(const BoxD& P, const uint32_t m[5], FrameIv* f) {
+  double c[3][2];
+  for (int j = 0; j < 3; ++j) {
+    double lo, hi, lo2, hi2;
+    child_edge(P.lo[j], P.hi[j], m[j], 0, &lo, &hi);
+    child_edge(P.lo[j], P.hi[j], m[j], m[j] - 1, &lo2, &hi2);
+    c[j][0] = 0.5 * (lo + hi);
+    c[j][1] = 0.5 * (lo2 + hi2);
+  }
+  f->Dd = {P.lo[0], P.hi[0]};
+  f->Fi = {P.lo[1], P.hi[1]};
+  f->K = {P.lo[2], P.hi[2]};
+  double sig;
+  if (c[2][0] > 0.0) sig = 1.0;
+  else if (c[2][1] < 0.0) sig = -1.0;
+  else return false;
+  const Iv KP = sig > 0.0 ? Iv{c[2][0], c[2][1]} : Iv{-c[2][1], -c[2][0]};
+  const Iv D0P = sig > 0.0 ? Iv{c[0][0], c[0][1]} : Iv{-c[0][1], -c[0][0]};
+  const Iv R = {wdn(1.0 / KP.hi), wup(1.0 / KP.lo)};
+  const Iv S1 = sin_encl(c[1][0], c[1][1]), C1 = cos_encl(c[1][0], c[1][1]);
+  f->SP0 = sig > 0.0 ? S1 : ineg(S1);
+  f->CP0 = C1;
+  const Iv RD = iadd(R, D0P);
+  f->XC = ineg(imul(RD, f->SP0));
+  f->YC = imul(RD, f->CP0);
+  f->R = R;
+  f->sig = sig;
+  return true;
+}
+
+IA_HD bool parent_pairq(const FrameIv& f, const HitRec& h, PairQIv* q) {
+  const double py = f.sig * h.py, cps = f.sig * h.cphis, sps = h.sphis;
+  const Iv Dx = isub(ipt(h.px), f.XC), Dy = isub(ipt(py), f.YC);
+  q->RAx = isqrt(iadd(isqr(Dx), isqr(Dy)));
+  if (!(q->RAx.lo > 0.0)) return false;
+  q->cAx = isub(imul_pt(Dx, sps), imul_pt(Dy, cps));
+  q->sAx = iadd(imul_pt(Dx, cps), imul_pt(Dy, sps));
+  q->sinA = idiv_pos2(q->sAx, q->RAx);
+  q->cosA = idiv_pos2(q->cAx, q->RAx);
+  q->dphi = atan2_encl(iadd(imul(Dx, f.CP0), imul(Dy, f.SP0)), isub(imul(Dx, f.SP0), imul(Dy, f.CP0)));
+  q->sArc = imul(f.R, q->dphi);
+  q->c2 = isub(isqr(q->cosA), isqr(q->sinA));
+  q->s2 = itwice(imul(q->sinA, q->cosA));
+  q->twoRAx2 = itwice(isqr(q->RAx));
+  q->RpRAx = iadd(f.R, q->RAx);
+  return true;
+}
+
+// e_enclosure_dom with interval pair quantities and radius
+IA_HD bool e_enclosure_iq(const PairQIv& q, Iv R, double sig, double tt, double t2, Iv DS, Iv Z, Iv L, Iv* out,
+                          Iv* eps_out, Iv* disc_out, Iv* a_out) {
+  const Iv ZA = iadd(Z, imul(L, q.sArc));
+  const Iv ZAs = imul(ZA, q.sinA);
+  const Iv ZA2 = isqr(ZA);
+  const Iv LZA = imul(L, ZA);
+  const Iv LR = imul(L, R);
+  const Iv L2 = isqr(L);
+  const Iv PHI1 = ineg(idiv_pos2(iadd(ZAs, imul(imul(L, DS), q.cosA)), q.RAx));
+  const Iv P2a = imul(LR, ZA);
+  const Iv P2b = imul(imul(LZA, isub(R, itwice(DS))), q.c2);
+  const Iv inner = iadd(q.RAx, imul(L2, isub(q.RpRAx, DS)));
+  const Iv P2c = imul(iadd(ZA2, imul(DS, inner)), q.s2);
+  const Iv PHI2 = idiv_pos2(iadd(isub(P2a, P2b), P2c), q.twoRAx2);
+  const Iv EPS = iadd(imul_pt(PHI1, tt), imul_pt(PHI2, t2));
+  *eps_out = EPS;
+  if (!(fabs(EPS.lo) < 1e5 && fabs(EPS.hi) < 1e5)) return false;
+  Iv SE, CE;
+  if (fabs(EPS.lo) <= kSmallTrig && fabs(EPS.hi) <= kSmallTrig) {
+    sincos_encl_small(EPS, &SE, &CE);
+  } else {
+    SE = sin_encl(EPS.lo, EPS.hi);
+    CE = cos_encl(EPS.lo, EPS.hi);
+  }
+  const Iv SINP = iadd(imul(CE, q.sinA), imul(SE, q.cosA));
+  const Iv COSP = isub(imul(CE, q.cosA), imul(SE, q.sinA));
+  const Iv U2 = iadd(iadd(iadd(ipt(1.0), imul_pt(imul(itwice(L), SINP), tt)), imul_pt(L2, t2)),
+                     imul_pt(isqr(COSP), t2));
+  if (!(U2.lo > 0.0)) return false;
+  const Iv DELTA = idiv_pos2(DS, isqrt(U2));
+  const Iv SPERP = imul(iadd(q.dphi, EPS), R);
+  const Iv ZS = isub(iadd(Z, imul(L, SPERP)), imul_pt(imul(DELTA, COSP), tt));
+  const Iv LD = imul(L, DELTA);
+  const Iv CTAU = isub(imul(ZS, q.cAx), imul(LD, q.sAx));
+  const Iv Q = iadd(iadd(imul_pt(itwice(CTAU), tt), isqr(imul_pt(ZS, tt))), isqr(imul_pt(LD, tt)));
+  const Iv A = iadd(R, DELTA);
+  const Iv DISC = isub(isqr(A), Q);
+  *disc_out = DISC;
+  *a_out = A;
+  if (!(DISC.hi >= 0.0)) return false;
+  const Iv DEN = iadd(A, isqrt(DISC));
+  if (!(DEN.lo > 0.0)) return false;
+  const Iv DHAT = isub(DELTA, idiv_pos2(Q, DEN));
+  const Iv E = sig > 0.0 ? DHAT : ineg(DHAT);
+  const double mg = 1e-9 * fmax(fabs(E.lo), fabs(E.hi)) + 1e-12;
+  *out = {wdn(E.lo - mg), wup(E.hi + mg)};
+  return __builtin_isfinite(out->lo) && __builtin_isfinite(out->hi);
+}
+
+// false only when the hit can vote for no box of the parent's children
+// (at FP32 levels, under the FP32 definition: out-of-domain boxes vote)
+template <bool F32>
+IA_HD bool parent_may_vote(const BoxD& P, const uint32_t m[5], const HitRec& h, float slack32) {
+  if (!h.use) return false;
+  FrameIv f;
+  if (!parent_frame(P, m, &f)) return true;
+  Frame fg;                                     // the parent box's ranges for G
+  fg.K = f.K;
+  fg.Dd = f.Dd;
+  fg.Fi = f.Fi;
+  const Iv G = residual_G(fg, h);
+  if (h.axial)
+    return h_contains0(G, f.K, f.sig * h.d, h.band) || h_contains0(G, f.K, f.sig * (-h.d), h.band);
+  if (F32 && !(f.R.hi <= kR32Max)) return true;
+  PairQIv q;
+  if (!parent_pairq(f, h, &q)) return true;
+  Iv Z, L;
+  centre_ranges(P, m, &Z, &L);
+  const double tt = h.tant, t2 = tt * tt;
+  Iv E, EPS, DISC, A;
+  if (!e_enclosure_iq(q, f.R, f.sig, tt, t2, Iv{-h.d, h.d}, Z, L, &E, &EPS, &DISC, &A)) return true;
+  if constexpr (F32) {
+    if (!(fabs(EPS.lo) <= 0.99 && fabs(EPS.hi) <= 0.99 && DISC.lo > 1e-3 * A.hi * A.hi)) return true;
+    const Iv32 G32 = to32(G), K32 = to32(f.K);
+    const float bs2 = wup32(ru32(h.band) + 2.0f * slack32);
+    const Iv32 Eb = {wdn32(rd32(E.lo) - bs2), wup32(ru32(E.hi) + bs2)};
+    const Iv32 Hb = isub32(itwice32(G32), iadd32(itwice32(Eb), imul32(K32, isqr32(Eb))));
+    return Hb.lo <= 0.0f && 0.0f <= Hb.hi;
+  } else {
+    const Iv Eb = {wdn(E.lo - h.band), wup(E.hi + h.band)};
+    const Iv Hb = isub(itwice(G), iadd(itwice(Eb), imul(f.K, isqr(Eb))));
+    return Hb.lo <= 0.0 && 0.0 <= Hb.hi;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // hit preparation.  One thread per hit; also clears the vote and lower-bound
 // histograms and the per-triple bounds.  With `ev` set it starts an event:
 // resets the event state, writes the search range box and marks every hit
@@ -637,7 +797,8 @@ __device__ __forceinline__ int32_t block_sum(int32_t v, int32_t* sbuf) {
 // class 0: no box of the triple gets the hit's vote; 1: every box does;
 // 2: the boxes must be evaluated (stereo hits only).  Axial pairs are decided
 // here completely.  With `filter` off every well-formed stereo pair is class
-// 2.  Per triple: tlb = number of class-1 pairs (a lower bound of each of
+// 2.  With pflags (refinement levels), a hit the parent-level test excluded
+// is class 0 for every triple of that parent.  Per triple: tlb = number of class-1 pairs (a lower bound of each of
 // its boxes' votes, exact for a triple without class-2 pairs), tn2 = number
 // of class-2 pairs (tlb + tn2 bounds the votes from above); both are added
 // to (they start at zero).
@@ -651,7 +812,8 @@ __global__ void __launch_bounds__(kWG) k_classify(const HitRec* __restrict__ hit
                                                   const BoxD* __restrict__ parents, Shape sh,
                                                   uint8_t* __restrict__ flags, int32_t* __restrict__ tlb,
                                                   int32_t* __restrict__ tn2, int32_t filter,
-                                                  const EventState* __restrict__ ev, float slack32) {
+                                                  const EventState* __restrict__ ev, float slack32,
+                                                  const uint8_t* __restrict__ pflags) {
   const int e = blockIdx.y;
   if (ev && ev[e].done) return;
   const int32_t n_hits = vw.count(e);
@@ -668,6 +830,7 @@ __global__ void __launch_bounds__(kWG) k_classify(const HitRec* __restrict__ hit
   const uint32_t tq = live ? t : n_tr - 1;
   const uint32_t tc = tq % sh.m012;
   const BoxD& TP = parents[tq / sh.m012];
+  const uint8_t* pf = pflags ? pflags + e * vw.pflag_stride + int64_t(tq / sh.m012) * n_hits : nullptr;
   const Frame f = triple_frame(TP, sh.m, tc / sh.m12, (tc / sh.m[2]) % sh.m[1], tc % sh.m[2]);
   Iv Zr, Lr;
   centre_ranges(TP, sh.m, &Zr, &Lr);
@@ -676,7 +839,7 @@ __global__ void __launch_bounds__(kWG) k_classify(const HitRec* __restrict__ hit
   for (int32_t h = static_cast<int32_t>(blockIdx.z) * (kWG / 64) + wave; h < n_hits; h += h_step) {
     const HitRec hr = hits[h];
     uint8_t fl = 0;
-    if (hr.use) {
+    if (hr.use && (!pf || pf[h])) {
       const Iv G = residual_G(f, hr);
       if (hr.axial) {
         fl = (h_contains0(G, f.K, f.sig * hr.d, hr.band) || h_contains0(G, f.K, f.sig * (-hr.d), hr.band)) ? 1 : 0;
@@ -703,6 +866,28 @@ __global__ void __launch_bounds__(kWG) k_classify(const HitRec* __restrict__ hit
     for (int w = 0; w < kWG / 64; ++w) { a += s_lb[w][lane]; b += s_n2[w][lane]; }
     if (a) atomicAdd(&tlb[t], a);
     if (b) atomicAdd(&tn2[t], b);
+  }
+}
+
+// Parent-level exclusion of a refinement level: pflags[p * n_hits + h] = 0
+// when hit h can vote for no child box of parent p (parent_may_vote), else 1.
+template <bool F32>
+__global__ void __launch_bounds__(kWG) k_parent_filter(const HitRec* __restrict__ hits, EvView vw,
+                                                       const BoxD* __restrict__ parents, Shape sh,
+                                                       uint8_t* __restrict__ pflags, const EventState* __restrict__ ev,
+                                                       float slack32) {
+  const int e = blockIdx.y;
+  if (ev[e].done) return;
+  const int32_t n_hits = vw.count(e);
+  if (n_hits <= 0) return;
+  hits += vw.beg(e);
+  parents += e * vw.par_stride;
+  pflags += e * vw.pflag_stride;
+  const int64_t n = static_cast<int64_t>(sh.n_parents) * n_hits;
+  for (int64_t i = int64_t(blockIdx.x) * kWG + threadIdx.x; i < n; i += int64_t(gridDim.x) * kWG) {
+    const uint32_t p = static_cast<uint32_t>(i / n_hits);
+    const int32_t h = static_cast<int32_t>(i % n_hits);
+    pflags[i] = parent_may_vote<F32>(parents[p], sh.m, hits[h], slack32) ? 1 : 0;
   }
 }
 

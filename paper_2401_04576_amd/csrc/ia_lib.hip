@@ -61,6 +61,7 @@ struct ia_ctx {
   int32_t tile_override = 0;
   int32_t filter_mode = -1;       // -1: automatic, 0: off, 1: on
   int32_t prune = 1;              // ia_find_helices: skip triples that cannot reach the selection
+  int32_t parent_filter = 1;      // ia_find_helices: parent-level exclusion at refinement levels
   int32_t max_chunk = 65535;      // events per batched launch
   float slack32 = ia::ru32(1e-6);  // band widening of ia_vote_level at FP32
   // pinned staging ring for the chunk-relative hit offsets copied to the
@@ -69,8 +70,10 @@ struct ia_ctx {
   hipEvent_t slot_done[kOffSlots] = {};
   bool slot_used[kOffSlots] = {};
   uint32_t slot_next = 0;
-  struct Mark { hipEvent_t e0, e1; bool f32; };
+  struct Mark { hipEvent_t e0, e1; bool f32; uint32_t n_boxes; };
   std::vector<Mark> marks;
+  // autotuned vote tile per level size (boxes per event), from ia_ctx_autotune
+  std::vector<std::pair<uint32_t, int32_t>> tuned;
 };
 
 namespace {
@@ -162,6 +165,8 @@ ia_status launch_select(ia_ctx* c, const uint16_t* votes, const Shape& sh, const
 // that the device gets enough workgroups
 int32_t vote_tile(const ia_ctx* c, uint32_t n_boxes) {
   if (c->tile_override) return c->tile_override;
+  for (const auto& t : c->tuned)
+    if (t.first == n_boxes) return t.second;
   if (n_boxes >= (1u << 19)) return 256;
   return 128;
 }
@@ -183,7 +188,8 @@ ia::EvView single_view(int32_t n_hits) {
 // workgroups when the triples alone do not.
 void launch_classify(ia_ctx* c, const HitRec* recs, const ia::EvView& vw, int32_t n_ev, int32_t max_hits,
                      const BoxD* par, const Shape& sh, uint8_t* flags, int32_t* tlb, int32_t* tn2,
-                     const EventState* ev, hipStream_t s, bool f32, float slack32) {
+                     const EventState* ev, hipStream_t s, bool f32, float slack32,
+                     const uint8_t* pflags = nullptr) {
   const uint32_t n_tr = sh.n_parents * sh.m012;
   const uint32_t gx = (n_tr + 63) / 64;
   const int64_t base = int64_t(gx) * std::max(1, n_ev);
@@ -193,10 +199,10 @@ void launch_classify(ia_ctx* c, const HitRec* recs, const ia::EvView& vw, int32_
   const int32_t filt = use_filter(c);
   if (f32)
     hipLaunchKernelGGL((ia::k_classify<true>), g, dim3(ia::kWG), 0, s, recs, vw, par, sh, flags, tlb, tn2, filt, ev,
-                       slack32);
+                       slack32, pflags);
   else
     hipLaunchKernelGGL((ia::k_classify<false>), g, dim3(ia::kWG), 0, s, recs, vw, par, sh, flags, tlb, tn2, filt, ev,
-                       slack32);
+                       slack32, pflags);
 }
 
 // launches the vote kernel for n_ev events, bracketed by events when profiling
@@ -253,7 +259,7 @@ ia_status launch_vote(ia_ctx* c, const HitRec* recs, const ia::EvView& vw, int32
   else launch_vote_tile<false>(bx, g, s, recs, vw, par, sh, votes, hist, st, ev, in, wg_max, wk, slack32);
   if (c->profiling) {
     IA_HIP(c, hipEventRecord(e1, s));
-    c->marks.push_back({e0, e1, f32});
+    c->marks.push_back({e0, e1, f32, sh.n_boxes});
   }
   IA_HIP(c, hipGetLastError());
   return IA_OK;
@@ -319,7 +325,7 @@ ia_status launch_vote_rec(ia_ctx* c, const ia::EvView& vw, int32_t n_ev, const B
   else launch_vote_rec_tile<false>(bx, g, s, vw, par, sh, votes, hist, st, ev, in, r, wg_max, wk);
   if (c->profiling) {
     IA_HIP(c, hipEventRecord(e1, s));
-    c->marks.push_back({e0, e1, f32});
+    c->marks.push_back({e0, e1, f32, sh.n_boxes});
   }
   IA_HIP(c, hipGetLastError());
   return IA_OK;
@@ -329,8 +335,8 @@ ia_status launch_vote_rec(ia_ctx* c, const ia::EvView& vw, int32_t n_ev, const B
 // arena): per-event slices of every array, sized for events of max_hits hits
 struct FindLayout {
   size_t off, recs, votes, hist, lbh, selA, selB, range, sel_idx, sel_v, ev, part, flags, tlb, tn2, wg_max, live,
-      live_tri, rec_off, rec_fill, tfr, rec, total;
-  int64_t flag_stride, tri_stride, votes_stride, rec_stride;
+      live_tri, rec_off, rec_fill, tfr, rec, pflags, total;
+  int64_t flag_stride, tri_stride, votes_stride, rec_stride, pflag_stride;
   int32_t hist_stride, wg_stride, part_stride, n_part;
 };
 
@@ -342,6 +348,7 @@ void layout_find(int64_t max_level_boxes, int64_t max_triples, int32_t top_k, in
   L->hist_stride = max_hits + 2;
   L->flag_stride = max_triples * int64_t(std::max(0, max_hits));
   L->tri_stride = max_triples;
+  L->pflag_stride = int64_t(std::max(1, top_k)) * int64_t(std::max(0, max_hits));
   L->rec_stride = rec_per_event > 0 ? rec_per_event : std::max<int64_t>(1, max_triples * int64_t(std::max(0, max_hits)));
   L->wg_stride = static_cast<int32_t>((max_level_boxes + 63) / 64);
   L->part_stride = ia::kEstQ * L->n_part;
@@ -374,6 +381,7 @@ void layout_find(int64_t max_level_boxes, int64_t max_triples, int32_t top_k, in
   L->rec_fill = take(sizeof(int32_t) * size_t(L->tri_stride) * E);
   L->tfr = take(sizeof(ia::TriFrame) * size_t(L->tri_stride) * E);
   L->rec = take(sizeof(ia::RecD) * size_t(L->rec_stride) * E);
+  L->pflags = take(size_t(L->pflag_stride) * E);
   L->total = off;
 }
 
@@ -433,6 +441,7 @@ ia_status run_chunk(ia_ctx* c, const double* hits_chunk, const int32_t* h_off_ch
   EventState* ev = reinterpret_cast<EventState*>(a + L.ev);
   double* part = reinterpret_cast<double*>(a + L.part);
   uint8_t* flags = reinterpret_cast<uint8_t*>(a + L.flags);
+  uint8_t* pflags = reinterpret_cast<uint8_t*>(a + L.pflags);
   int32_t* tlb = reinterpret_cast<int32_t*>(a + L.tlb);
   int32_t* tn2 = reinterpret_cast<int32_t*>(a + L.tn2);
   uint32_t* lbh = reinterpret_cast<uint32_t*>(a + L.lbh);
@@ -457,6 +466,7 @@ ia_status run_chunk(ia_ctx* c, const double* hits_chunk, const int32_t* h_off_ch
   vw.flag_stride = L.flag_stride;
   vw.tri_stride = L.tri_stride;
   vw.rec_stride = L.rec_stride;
+  vw.pflag_stride = L.pflag_stride;
   vw.hist_stride = L.hist_stride;
   vw.wg_stride = L.wg_stride;
   vw.part_stride = L.part_stride;
@@ -478,7 +488,21 @@ ia_status run_chunk(ia_ctx* c, const double* hits_chunk, const int32_t* h_off_ch
     int32_t last_bx = 1;
     for (int32_t lev = 0; lev <= sc->n_refine; ++lev) {
       const bool f32 = sc->prec[lev] == IA_FP32;
-      launch_classify(c, recs, vw, E, cmax, par, sh, flags, tlb, tn2, ev, s, f32, slack32);
+      // refinement levels: the parent-level test first (a hit it excludes
+      // is class 0 for all of that parent's triples)
+      const bool use_pf = lev > 0 && use_filter(c) && c->parent_filter;
+      if (use_pf) {
+        const int64_t n_pairs = int64_t(sh.n_parents) * std::max(1, cmax);
+        const dim3 gp(static_cast<uint32_t>(std::min<int64_t>((n_pairs + ia::kWG - 1) / ia::kWG, 65535)), E);
+        if (f32)
+          hipLaunchKernelGGL((ia::k_parent_filter<true>), gp, dim3(ia::kWG), 0, s, recs, vw, par, sh, pflags, ev,
+                             slack32);
+        else
+          hipLaunchKernelGGL((ia::k_parent_filter<false>), gp, dim3(ia::kWG), 0, s, recs, vw, par, sh, pflags, ev,
+                             slack32);
+      }
+      launch_classify(c, recs, vw, E, cmax, par, sh, flags, tlb, tn2, ev, s, f32, slack32,
+                      use_pf ? pflags : nullptr);
       const int32_t vt = vote_tile(c, sh.n_boxes);
       hipLaunchKernelGGL(ia::k_threshold, dim3(1, E), dim3(ia::kWG), 0, s, tlb, tn2, lbh, vw, sh, K, c->prune, vt,
                          ev, live, wg_max, rin.live_tri, rin.rec_off, rin.rec_fill, L.rec_stride);
@@ -624,6 +648,12 @@ ia_status ia_ctx_set_prefilter(ia_ctx* c, int32_t mode) {
 ia_status ia_ctx_set_pruning(ia_ctx* c, int32_t enable) {
   if (!c) return IA_ERR_INVALID;
   c->prune = enable != 0 ? 1 : 0;
+  return IA_OK;
+}
+
+ia_status ia_ctx_set_parent_filter(ia_ctx* c, int32_t enable) {
+  if (!c) return IA_ERR_INVALID;
+  c->parent_filter = enable != 0 ? 1 : 0;
   return IA_OK;
 }
 
@@ -863,6 +893,67 @@ ia_status ia_find_helices(ia_ctx* c, const ia_hit* d_hits, const int32_t* h_off,
     if (st != IA_OK) return st;
   }
   return IA_OK;
+}
+
+ia_status ia_ctx_autotune(ia_ctx* c, const ia_hit* d_hits, const int32_t* h_off, int32_t n_events,
+                          const ia_schedule* sc, ia_helix* d_out, int32_t max_per_event, int32_t* d_n_out,
+                          void* stream) {
+  if (!c) return IA_ERR_INVALID;
+  static const int32_t kTiles[3] = {256, 128, 64};
+  const int32_t saved = c->tile_override;
+  const bool saved_prof = c->profiling;
+  // summed vote-kernel milliseconds per (level size, candidate)
+  std::vector<std::pair<uint32_t, double>> ms[3];
+  for (int ci = 0; ci < 3; ++ci) {
+    c->tile_override = kTiles[ci];
+    c->profiling = false;
+    ia_status st = ia_find_helices(c, d_hits, h_off, n_events, sc, d_out, max_per_event, d_n_out, nullptr, stream);
+    if (st == IA_OK) {
+      c->profiling = true;
+      st = ia_find_helices(c, d_hits, h_off, n_events, sc, d_out, max_per_event, d_n_out, nullptr, stream);
+    }
+    c->profiling = false;
+    if (st == IA_OK) IA_HIP(c, hipStreamSynchronize(as_stream(stream)));
+    for (auto& m : c->marks) {
+      float t = 0.f;
+      if (st == IA_OK && hipEventElapsedTime(&t, m.e0, m.e1) == hipSuccess) {
+        bool found = false;
+        for (auto& x : ms[ci])
+          if (x.first == m.n_boxes) { x.second += t; found = true; }
+        if (!found) ms[ci].push_back({m.n_boxes, double(t)});
+      }
+      (void)hipEventDestroy(m.e0);
+      (void)hipEventDestroy(m.e1);
+    }
+    c->marks.clear();
+    if (st != IA_OK) {
+      c->tile_override = saved;
+      c->profiling = saved_prof;
+      return st;
+    }
+  }
+  c->tile_override = saved;
+  c->profiling = saved_prof;
+  c->tuned.clear();
+  for (const auto& x : ms[0]) {
+    int32_t best = kTiles[0];
+    double best_ms = x.second;
+    for (int ci = 1; ci < 3; ++ci)
+      for (const auto& y : ms[ci])
+        if (y.first == x.first && y.second < best_ms) { best_ms = y.second; best = kTiles[ci]; }
+    c->tuned.push_back({x.first, best});
+  }
+  return IA_OK;
+}
+
+int32_t ia_ctx_tuned(const ia_ctx* c, uint32_t* n_boxes, int32_t* tiles, int32_t max_entries) {
+  if (!c) return 0;
+  const int32_t n = static_cast<int32_t>(c->tuned.size());
+  for (int32_t i = 0; i < n && i < max_entries; ++i) {
+    if (n_boxes) n_boxes[i] = c->tuned[i].first;
+    if (tiles) tiles[i] = c->tuned[i].second;
+  }
+  return n;
 }
 
 ia_status ia_find_helices_dev(ia_ctx* c, const ia_hit* d_hits, const int32_t* d_off, int32_t n_events,

@@ -36,21 +36,21 @@ def lib():
         P = C.c_void_p
         L.hc_vote_level.restype = C.c_int32
         L.hc_vote_level.argtypes = [P, C.c_int32, P, C.c_int32, P, C.c_int32, C.c_int32, C.c_double, C.c_int32,
-                                    P, P]
+                                    C.c_int32, P, P]
         _lib = L
     return _lib
 
 
-def vote_level(hits, parents, split, filter_on, f32=False, slack=1e-6, prune_k=0):
+def vote_level(hits, parents, split, filter_on, f32=False, slack=1e-6, prune_k=0, parent_filter=False):
     h = np.ascontiguousarray(hits).view(np.float64).reshape(-1, 8).copy() if len(hits) else np.zeros((0, 8))
     p = np.atleast_1d(parents)
     pa = np.ascontiguousarray(np.concatenate([p["lo"], p["hi"]], axis=1), dtype=np.float64)
     sp = np.ascontiguousarray(split, dtype=np.int32)
     nb = pa.shape[0] * int(np.prod(sp.astype(np.int64)))
     votes = np.zeros(nb, dtype=np.uint16)
-    stats = np.zeros(8, dtype=np.int64)
+    stats = np.zeros(9, dtype=np.int64)
     rc = lib().hc_vote_level(h.ctypes.data, h.shape[0], pa.ctypes.data, pa.shape[0], sp.ctypes.data,
                              1 if filter_on else 0, 1 if f32 else 0, float(slack), int(prune_k),
-                             votes.ctypes.data, stats.ctypes.data)
+                             1 if parent_filter else 0, votes.ctypes.data, stats.ctypes.data)
     assert rc == 0
     return votes, stats

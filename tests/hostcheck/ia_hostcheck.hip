@@ -39,10 +39,11 @@ extern "C" {
 // evaluated; the boxes of the others keep their lower bound.
 // stats: [0] stereo (triple, hit) pairs, [1] class 0, [2] stereo (box, hit)
 // evaluations, [3] of those that voted, [4] evaluated pairs voting in every
-// box of their triple, [5] class 1, [6] triples evaluated, [7] T
+// box of their triple, [5] class 1, [6] triples evaluated, [7] T,
+// [8] (parent, hit) pairs the parent-level test excluded (with parent_filter)
 int32_t hc_vote_level(const double* hits, int32_t n_hits, const double* parents, int32_t n_parents,
                       const int32_t split[5], int32_t filter, int32_t f32, double slack, int32_t prune_k,
-                      uint16_t* votes, int64_t* stats) {
+                      int32_t parent_filter, uint16_t* votes, int64_t* stats) {
   const float slack32 = ru32(slack);
   Shape sh;
   if (!make_shape(split, n_parents, &sh)) return 1;
@@ -53,6 +54,19 @@ int32_t hc_vote_level(const double* hits, int32_t n_hits, const double* parents,
   }
   const BoxD* P = reinterpret_cast<const BoxD*>(parents);
   const int64_t n_triples = int64_t(n_parents) * sh.m012;
+  // parent-level exclusion per (parent, hit)
+  std::vector<uint8_t> pmay(size_t(n_parents) * size_t(n_hits > 0 ? n_hits : 1), 1);
+  int64_t n_pexcl = 0;
+  if (parent_filter && filter) {
+#pragma omp parallel for schedule(dynamic, 1) reduction(+ : n_pexcl)
+    for (int32_t p = 0; p < n_parents; ++p)
+      for (int32_t i = 0; i < n_hits; ++i) {
+        const bool may = f32 ? parent_may_vote<true>(P[p], sh.m, rec[i], slack32)
+                             : parent_may_vote<false>(P[p], sh.m, rec[i], slack32);
+        pmay[size_t(p) * n_hits + i] = may ? 1 : 0;
+        n_pexcl += (!may && rec[i].use) ? 1 : 0;
+      }
+  }
   std::vector<uint8_t> cls(size_t(n_triples) * size_t(n_hits > 0 ? n_hits : 1));
   std::vector<int32_t> tlb(n_triples), tn2(n_triples);
   int64_t n_pairs = 0, n_cut = 0, n_incl = 0;
@@ -66,7 +80,7 @@ int32_t hc_vote_level(const double* hits, int32_t n_hits, const double* parents,
     for (int32_t i = 0; i < n_hits; ++i) {
       const HitRec& h = rec[i];
       uint8_t fl = 0;
-      if (h.use) {
+      if (h.use && pmay[size_t(tp) * n_hits + i]) {
         const Iv G = residual_G(f, h);
         if (h.axial) {
           fl = (h_contains0(G, f.K, f.sig * h.d, h.band) || h_contains0(G, f.K, f.sig * (-h.d), h.band)) ? 1 : 0;
@@ -142,7 +156,7 @@ int32_t hc_vote_level(const double* hits, int32_t n_hits, const double* parents,
   }
   if (stats) {
     stats[0] = n_pairs; stats[1] = n_cut; stats[2] = n_evals; stats[3] = n_yes; stats[4] = n_full;
-    stats[5] = n_incl; stats[6] = n_live; stats[7] = T;
+    stats[5] = n_incl; stats[6] = n_live; stats[7] = T; stats[8] = n_pexcl;
   }
   return 0;
 }

@@ -299,3 +299,36 @@ def test_pruning_does_not_change_helices(ctx):
     assert np.array_equal(n_p, n_f) and np.array_equal(ass_p, ass_f)
     for e in range(len(events)):
         assert hel_p[e, :n_p[e]].tobytes() == hel_f[e, :n_f[e]].tobytes()
+
+
+def test_autotune_keeps_results(ctx):
+    """The autotuner's tile table (one entry per level size, tiles of 64, 128
+    or 256 boxes) does not change the search's results."""
+    events = [toymc.config_event(4, i) for i in range(30, 36)]
+    sched = ia.Schedule.make(H.LO, H.HI, [16] * 5, n_helix_max=5)
+    hel_a, n_a, ass_a, off = _run_gpu(ctx, events, sched, 5)
+    hits = _dev_hits(np.concatenate([e.hits for e in events]))
+    table = ctx.autotune(hits, off, sched, max_per_event=5)
+    assert set(table) == {16 ** 5, 32 * 4 ** 5} and set(table.values()) <= {64, 128, 256}
+    hel_b, n_b, ass_b, _ = _run_gpu(ctx, events, sched, 5)
+    assert np.array_equal(n_a, n_b) and np.array_equal(ass_a, ass_b)
+    for e in range(len(events)):
+        assert hel_a[e, :n_a[e]].tobytes() == hel_b[e, :n_b[e]].tobytes()
+
+
+def test_parent_filter_does_not_change_results(ctx):
+    """find_helices with and without the parent-level exclusion at the
+    refinement levels: identical helices, votes and hit assignments, in FP64
+    and in the mixed schedule."""
+    events = [toymc.config_event(4, i) for i in range(40, 46)] + [toymc.config_event(5, i) for i in range(3)]
+    for prec in (None, [ia.FP32] * 3 + [ia.FP64] * 2):
+        sched = ia.Schedule.make(H.LO, H.HI, [16] * 5, n_helix_max=5, prec=prec)
+        hel_a, n_a, ass_a, _ = _run_gpu(ctx, events, sched, 5)
+        ctx.set_parent_filter(False)
+        try:
+            hel_b, n_b, ass_b, _ = _run_gpu(ctx, events, sched, 5)
+        finally:
+            ctx.set_parent_filter(True)
+        assert np.array_equal(n_a, n_b) and np.array_equal(ass_a, ass_b)
+        for e in range(len(events)):
+            assert hel_a[e, :n_a[e]].tobytes() == hel_b[e, :n_b[e]].tobytes()

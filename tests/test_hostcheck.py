@@ -119,3 +119,30 @@ def test_pruning_keeps_selection(orc, cfg, ev_i, f32):
         assert np.array_equal(np.flatnonzero(got == vmax), np.flatnonzero(ref == vmax))
         n_tr = parents.size * int(np.prod(split[:3]))
         assert st[6] < 0.5 * n_tr, (st[6], n_tr)
+
+
+@pytest.mark.parametrize("f32", [False, True])
+@pytest.mark.parametrize("cfg,ev_i,split", [(4, 7, [4] * 5), (5, 9, [3, 4, 2, 5, 3]), (2, 0, [4] * 5)])
+def test_parent_exclusion_sound(orc, cfg, ev_i, split, f32):
+    """The parent-level test (the frame and pair quantities taken as
+    intervals over every child triple of a refinement parent) only drops
+    (parent, hit) pairs that vote in none of the parent's child boxes: the
+    level's votes equal the oracle's, with and without pruning, and the test
+    drops a share of the pairs on multi-helix events."""
+    ev = toymc.config_event(cfg, ev_i)
+    root = orc.make_box(H.LO, H.HI)
+    prec = orc.FP32 if f32 else orc.FP64
+    v0 = orc.vote_level(ev.hits, root, [12] * 5, prec=prec, slack=SLACK)
+    top, _ = _topk(v0, 32)
+    parents = np.array([orc.box_child(root, [12] * 5, int(b)) for b in top])
+    ref = orc.vote_level(ev.hits, parents, split, prec=prec, slack=SLACK)
+    got, st = hostcheck.vote_level(ev.hits, parents, split, True, f32=f32, slack=SLACK, parent_filter=True)
+    assert np.array_equal(got, ref), np.flatnonzero(got != ref)[:10]
+    if cfg != 2:
+        assert st[8] > 0.1 * parents.size * ev.n_hits
+    got_p, st_p = hostcheck.vote_level(ev.hits, parents, split, True, f32=f32, slack=SLACK, prune_k=32,
+                                       parent_filter=True)
+    assert np.all(got_p <= ref)
+    ti_r, tv_r = _topk(ref, 32)
+    ti_g, tv_g = _topk(got_p, 32)
+    assert np.array_equal(ti_r, ti_g) and np.array_equal(tv_r, tv_g)
