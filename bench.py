@@ -24,6 +24,10 @@ level, the fraction of boxes whose FP32 and FP64 votes differ on the FP64
 frontier's parents, whether the FP32 selection equals the FP64 one, and per
 parameter |FP32 - FP64| and |estimate - truth| of the final helices.
 
+With --workload copy, a plain elementwise copy of 1 GiB (torch, float32)
+runs a few times: under rocprofv3 --pmc its FETCH_SIZE and WRITE_SIZE per
+dispatch against the 1 GiB it moves give the scale of those counters.
+
 With --workload serve, events of the serving mix (1-10 helices, lognormal
 hit counts with median 120 clipped to [20, 1000], 0-40 % noise) arrive as a
 Poisson stream and are served by the continuous-batching loop; the line
@@ -63,7 +67,25 @@ FLOP_TRIPLE_HIT = 310
 # the same per-box evaluation at FP32 levels (smaller sin/cos polynomials, no
 # range reduction), FP32 flops; the staged (triple, hit) work stays FP64
 FLOP_BOX_STEREO32 = 278
+# (triple, hit) classification, FP64 flops per unit (add, sub, mul, div,
+# sqrt 1, fma 2; min, max, abs 0; outward rounding of an end point 3):
+#  - residual interval G of a pair (two sin evaluations of the phi0
+#    enclosure, the kappa-scaled terms): 157;
+#  - axial test, both drift signs (two interval tests of 2G - 2E - kappa E^2): 92;
+#  - stereo pair quantities (RAx, its sin / cos, atan2 of the arc, sArc, ...): 69;
+#  - one interval enclosure of d^Ax over the triple's (z0, tanl) centres with
+#    its exclusion test (the FP32 levels' test counted as FP64 too): 688;
+#  - one inclusion proof (bounds at the enclosure's ends): 94.
+FLOP_CLS_G, FLOP_CLS_AXIAL, FLOP_CLS_PAIRQ, FLOP_CLS_ENCL, FLOP_CLS_INCL = 157, 92, 69, 688, 94
 PEAK_FP64_TFLOPS = 78.6   # MI355X vector FP64: 256 CU x 128 FLOP/clk x 2.4 GHz
+# HBM bytes per launch of the FP64 classification over 1024-event batches of
+# the default workload: rocprofv3 --pmc FETCH_SIZE, then WRITE_SIZE, averaged
+# over those launches and scaled by 2.0 and 1.0 (what the two counters read
+# for a copy of 1 GiB, bench.py --workload copy).  Valid only for the kernel
+# sources they were measured on (SHA-256 of ia_math.hpp + ia_kernels.hpp).
+TRAFFIC_CLASSIFY = {"workload": "event", "events_per_step": 1024,
+                    "sources_sha256": "475d5b67480e54ed519bebede6c0ce0b52e998e6286b4025a67a637df2594b11",
+                    "fetch_bytes": 44199347, "write_bytes": 75287949}
 PEAK_FP32_TFLOPS = 157.3  # MI355X vector FP32 (non-packed)
 
 
@@ -75,29 +97,96 @@ def sched_prec(name, n_refine):
     return [ia.FP32 if lev <= 2 else ia.FP64 for lev in range(n_refine + 1)]
 
 
-def roofline(prof, work, wall):
-    """Roofline object of the dominant vote kernel (the precision class with
-    the larger summed launch time), with both classes under by_precision."""
-    n64, ms64, n32, ms32 = prof
+def kernel_sources_sha256():
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("ia_math.hpp", "ia_kernels.hpp"):
+        with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2401_04576_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def classify_traffic(workload, events_per_step):
+    """Measured HBM bytes per classification launch, or None when the
+    workload or the kernel sources differ from those of the measurement."""
+    t = TRAFFIC_CLASSIFY
+    if workload != t["workload"] or events_per_step != t["events_per_step"]:
+        return None
+    if kernel_sources_sha256() != t["sources_sha256"]:
+        return None
+    return t["fetch_bytes"] + t["write_bytes"]
+
+
+def classify_flops(cw):
+    return (cw["G"] * FLOP_CLS_G + cw["axial"] * FLOP_CLS_AXIAL + cw["pairq"] * FLOP_CLS_PAIRQ
+            + cw["enclosures"] * FLOP_CLS_ENCL + cw["inclusions"] * FLOP_CLS_INCL)
+
+
+def roofline(kprof, work, cwork, wall, measured_on, traffic_classify=None):
+    """Roofline object of the dominant kernel: of the vote kernel and the
+    (triple, hit) classification at FP64 and FP32 levels, the one with the
+    largest summed launch time (HIP events around each launch).  Achieved =
+    algorithmic flops of the launches / their summed duration; every entry
+    is listed under by_kernel."""
     e64, s64, e32, s32 = work
     parts = {}
-    if n64:
-        a = (e64 * FLOP_BOX_STEREO + s64 * FLOP_TRIPLE_HIT) / (ms64 * 1e-3) / 1e12
-        parts["fp64"] = {"achieved": a, "peak": PEAK_FP64_TFLOPS, "frac": a / PEAK_FP64_TFLOPS,
-                         "avg_launch_ms": ms64 / n64, "launches": n64, "total_ms": ms64,
-                         "stereo_box_evals": e64, "staged_pairs": s64}
-    if n32:
+    n, ms = kprof[("vote", "fp64")]
+    if n:
+        a = (e64 * FLOP_BOX_STEREO + s64 * FLOP_TRIPLE_HIT) / (ms * 1e-3) / 1e12
+        parts["k_vote (fp64 levels)"] = {
+            "achieved": a, "peak": PEAK_FP64_TFLOPS, "frac": a / PEAK_FP64_TFLOPS, "avg_launch_ms": ms / n,
+            "launches": n, "total_ms": ms, "stereo_box_evals": e64, "staged_pairs": s64}
+    n, ms = kprof[("vote", "fp32")]
+    if n:
         # FP32 flops of the per-box term only; the FP64 staging is left out
-        a = e32 * FLOP_BOX_STEREO32 / (ms32 * 1e-3) / 1e12
-        parts["fp32"] = {"achieved": a, "peak": PEAK_FP32_TFLOPS, "frac": a / PEAK_FP32_TFLOPS,
-                         "avg_launch_ms": ms32 / n32, "launches": n32, "total_ms": ms32,
-                         "stereo_box_evals": e32, "staged_pairs": s32,
-                         "staged_fp64_tflops": s32 * FLOP_TRIPLE_HIT / (ms32 * 1e-3) / 1e12}
+        a = e32 * FLOP_BOX_STEREO32 / (ms * 1e-3) / 1e12
+        parts["k_vote (fp32 levels)"] = {
+            "achieved": a, "peak": PEAK_FP32_TFLOPS, "frac": a / PEAK_FP32_TFLOPS, "avg_launch_ms": ms / n,
+            "launches": n, "total_ms": ms, "stereo_box_evals": e32, "staged_pairs": s32,
+            "staged_fp64_tflops": s32 * FLOP_TRIPLE_HIT / (ms * 1e-3) / 1e12}
+    for p in ("fp64", "fp32"):
+        n, ms = kprof[("classify", p)]
+        if n:
+            a = classify_flops(cwork[p]) / (ms * 1e-3) / 1e12
+            parts[f"k_classify ({p} levels)"] = {
+                "achieved": a, "peak": PEAK_FP64_TFLOPS, "frac": a / PEAK_FP64_TFLOPS, "avg_launch_ms": ms / n,
+                "launches": n, "total_ms": ms, **cwork[p]}
     dom = max(parts, key=lambda k: parts[k]["total_ms"])
     d = parts[dom]
+    traffic = traffic_classify if dom == "k_classify (fp64 levels)" else None
     return {"bound": "alu", "achieved": d["achieved"], "peak": d["peak"], "unit": "TFLOP/s", "frac": d["frac"],
-            "traffic": None, "kernel": f"k_vote ({dom} levels)", "avg_launch_ms": d["avg_launch_ms"],
-            "launches": d["launches"], "vote_share_of_wall": (ms64 + ms32) * 1e-3 / wall, "by_precision": parts}
+            "traffic": traffic, "traffic_unit": "bytes per launch (HBM, rocprofv3 FETCH_SIZE + WRITE_SIZE, scaled)",
+            "kernel": dom, "avg_launch_ms": d["avg_launch_ms"], "launches": d["launches"],
+            "share_of_wall": d["total_ms"] * 1e-3 / wall, "measured_on": measured_on,
+            "by_kernel": parts}
+
+
+def kernel_measure(ctx, run):
+    """Per-kernel launch durations (HIP events on the launch stream around
+    every vote and classification launch) over one run of `run`, the vote
+    kernel's work counters of that run, then the classification's work over
+    a second, counting run of the same work (the search is deterministic).
+    Both runs follow the timed region, which carries no events or counters."""
+    import torch
+    torch.cuda.synchronize()
+    ctx.profile_kernels()
+    ctx.clear_status()
+    ctx.set_profiling(True)
+    try:
+        run()
+        torch.cuda.synchronize()
+    finally:
+        ctx.set_profiling(False)
+    kprof = ctx.profile_kernels()
+    work = ctx.work()
+    ctx.clear_status()
+    ctx.set_work_counting(True)
+    try:
+        run()
+        torch.cuda.synchronize()
+    finally:
+        ctx.set_work_counting(False)
+    return kprof, work, ctx.classify_work()
 
 
 def level_shapes(bins, top_k, split, n_refine):
@@ -180,7 +269,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
-    ap.add_argument("--workload", choices=["event", "batch", "serve", "mixed-report"], default="event")
+    ap.add_argument("--workload", choices=["event", "batch", "serve", "mixed-report", "copy"], default="event")
     ap.add_argument("--batch-events", type=int, default=4096)
     ap.add_argument("--event-batch", type=int, default=1024,
                     help="single-helix workload: events per ia_find_helices call (one step)")
@@ -214,7 +303,28 @@ def main():
         return run_serve(args)
     if args.workload == "mixed-report":
         return run_mixed_report(args)
+    if args.workload == "copy":
+        return run_copy(args)
     return run_event(args)
+
+
+def run_copy(args):
+    """Calibration of the HBM traffic counters: an elementwise copy that
+    reads and writes exactly 1 GiB per dispatch."""
+    import torch
+    n = (1 << 30) // 4
+    x = torch.rand(n, device="cuda:0", dtype=torch.float32)
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    reps = 5
+    for _ in range(reps):
+        torch.mul(x, 1.0, out=y)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    assert torch.equal(x, y)
+    print(json.dumps({"workload": "copy", "bytes_read_per_dispatch": n * 4, "bytes_written_per_dispatch": n * 4,
+                      "dispatches": reps, "ms_per_dispatch": dt * 1e3, "GBps": 2 * n * 4 / dt / 1e9}), flush=True)
 
 
 def run_event(args):
@@ -262,18 +372,12 @@ def run_event(args):
     for k in range(args.warmup):
         step(k)
     torch.cuda.synchronize()
-    ctx.profile_read()
-    ctx.clear_status()
-    ctx.set_profiling(True)
-    torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(args.warmup, args.warmup + args.steps):
         step(k)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    ctx.set_profiling(False)
-    prof = ctx.profile_read()
-    work = ctx.work()
+    kprof, work, cwork = kernel_measure(ctx, lambda: [step(k) for k in range(args.warmup, args.warmup + args.steps)])
 
     # work of the schedule: a pass that stops at level 0 (maximum below
     # v_min) has level 0 only
@@ -322,13 +426,17 @@ def run_event(args):
         "p50_ms": float(np.percentile(lat, 50)) if lat else None,
         "p99_ms": float(np.percentile(lat, 99)) if lat else None,
         "latency": "p50/p99: one event per call, arrival of resident hits to its recorded helix",
-        "roofline": roofline(prof, work, wall),
+        "roofline": roofline(kprof, work, cwork, wall,
+                             "repeat of the timed steps: HIP events around each launch, then a work-counting run",
+                             classify_traffic("event", B)),
     }
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(batches[args.warmup][0], sched_kw, lo, hi, args.cpu_budget)
     ctx.close()
-    print(f"[bench] generated {n_ev} events in {t_gen:.1f} s; vote kernel {prof[1] + prof[3]:.2f} ms of "
-          f"{wall * 1e3:.2f} ms", file=sys.stderr)
+    print(f"[bench] generated {n_ev} events in {t_gen:.1f} s; vote kernel "
+          f"{kprof[('vote', 'fp64')][1] + kprof[('vote', 'fp32')][1]:.2f} ms, classification "
+          f"{kprof[('classify', 'fp64')][1] + kprof[('classify', 'fp32')][1]:.2f} ms of {wall * 1e3:.2f} ms",
+          file=sys.stderr)
     print(json.dumps(res), flush=True)
 
 
@@ -401,11 +509,8 @@ def run_batch(args):
     for b in range(args.warmup):
         step(b)
     torch.cuda.synchronize()
-    ctx.profile_read()
-    ctx.clear_status()
     starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
     ends = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
-    ctx.set_profiling(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(args.steps):
@@ -414,27 +519,24 @@ def run_batch(args):
         ends[k].record(stream)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    ctx.set_profiling(False)
-    prof = ctx.profile_read()
-    work = ctx.work()
     lat = np.array([s.elapsed_time(e) for s, e in zip(starts, ends)])
     wall = t1 - t0
     if use_graph:
-        # a captured graph holds no per-launch timing events: the vote kernel's
-        # launch durations and work come from one eager, profiled repeat of the
-        # last timed batch (the same kernels on the same events)
+        # a captured graph holds no per-launch timing events: launch durations
+        # and work come from an eager repeat of the last timed batch (the same
+        # kernels on the same events)
         evs, hits, off, out, n_out, assigned = batches[args.warmup + args.steps - 1]
-        ctx.clear_status()
-        ctx.set_profiling(True)
-        ia.find_helices(ctx, hits, off, sched, max_per_event=nh, stream=stream, out=torch.empty_like(out),
-                        n_out=torch.empty_like(n_out), assigned=torch.empty_like(assigned))
-        torch.cuda.synchronize()
-        ctx.set_profiling(False)
-        prof = ctx.profile_read()
-        work = ctx.work()
+
+        def rerun():
+            ia.find_helices(ctx, hits, off, sched, max_per_event=nh, stream=stream, out=torch.empty_like(out),
+                            n_out=torch.empty_like(n_out), assigned=torch.empty_like(assigned))
         rep_steps = 1
     else:
+        def rerun():
+            for k in range(args.steps):
+                step(args.warmup + k)
         rep_steps = args.steps
+    kprof, work, cwork = kernel_measure(ctx, rerun)
     shapes = level_shapes(sched_kw["bins"], sched_kw["top_k"], sched_kw["split"], sched_kw["n_refine"])
     evals, found, truth = 0.0, 0, 0
     for k in range(args.steps):
@@ -462,7 +564,9 @@ def run_batch(args):
                    "helices_generated_per_event": truth / (E * args.steps)},
         "events_per_s": E * args.steps / wall,
         "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
-        "roofline": roofline(prof, work, wall * rep_steps / args.steps),
+        "roofline": roofline(kprof, work, cwork, wall * rep_steps / args.steps,
+                             ("eager repeat of the last timed batch" if use_graph else "repeat of the timed steps")
+                             + ": HIP events around each launch, then a work-counting run"),
     }
     if use_graph:
         res["roofline"]["measured_on"] = "eager profiled repeat of the last timed batch"

@@ -138,6 +138,35 @@ ia_status ia_ctx_set_profiling(ia_ctx *ctx, int32_t enable);
 ia_status ia_ctx_profile_read(ia_ctx *ctx, int64_t *n_launches, double *total_ms,
                               int64_t *n_launches_fp32, double *total_ms_fp32);
 
+/* Kernels bracketed while profiling is enabled: the vote kernel and the
+ * (triple, hit) classification (Sec. 3.3's exclusion test over a triple's
+ * boxes, run before the per-box vote). */
+enum { IA_KERNEL_VOTE = 0, IA_KERNEL_CLASSIFY = 1 };
+
+/* Every bracketed launch: n_launches[2 k + p] and total_ms[2 k + p] for
+ * kernel k (IA_KERNEL_*) at precision p (0 FP64 levels, 1 FP32 levels).
+ * Synchronises on the recorded events and clears the record (as
+ * ia_ctx_profile_read, which returns the vote kernel's entries of it).
+ * Both arrays are host memory of 4 entries; IA_ERR_INVALID if either is
+ * NULL. */
+ia_status ia_ctx_profile_kernels(ia_ctx *ctx, int64_t n_launches[4], double total_ms[4]);
+
+/* Counting of the classification kernel's work (off by default): while
+ * enabled, the classification runs a variant that adds its work to the
+ * counters ia_ctx_classify_work reads, a few per cent slower.  Results do
+ * not depend on it. */
+ia_status ia_ctx_set_work_counting(ia_ctx *ctx, int32_t enable);
+
+/* Work of the classification kernel, counted while work counting was
+ * enabled, since the last ia_ctx_clear_status:
+ * counts[5 p + c] at precision p (0 FP64 levels, 1 FP32 levels) for
+ * c = 0 residual intervals G (Eq. ApoVote over a triple), 1 axial tests,
+ * 2 stereo pair quantities, 3 interval enclosures of d^Ax (each with its
+ * exclusion test), 4 inclusion proofs.  Only pairs of live triples are
+ * counted; pairs the parent-level test excluded are not.  Synchronises the
+ * device.  counts is host memory of 10 entries. */
+ia_status ia_ctx_classify_work(ia_ctx *ctx, int64_t counts[10]);
+
 /* Band widening used by ia_vote_level at IA_FP32 (default 1e-6 m; ia_find_helices
  * takes it from the schedule).  IA_ERR_INVALID outside [0, 1e-3]. */
 ia_status ia_ctx_set_fp32_slack(ia_ctx *ctx, double slack);

@@ -98,6 +98,12 @@ def load():
     L.ia_ctx_status.argtypes = [P, C.POINTER(C.c_uint32), C.POINTER(i64)]
     L.ia_ctx_work.restype = i32
     L.ia_ctx_work.argtypes = [P, C.POINTER(i64), C.POINTER(i64), C.POINTER(i64), C.POINTER(i64)]
+    L.ia_ctx_set_work_counting.restype = i32
+    L.ia_ctx_set_work_counting.argtypes = [P, i32]
+    L.ia_ctx_classify_work.restype = i32
+    L.ia_ctx_classify_work.argtypes = [P, C.POINTER(i64)]
+    L.ia_ctx_profile_kernels.restype = i32
+    L.ia_ctx_profile_kernels.argtypes = [P, C.POINTER(i64), C.POINTER(C.c_double)]
     L.ia_ctx_set_fp32_slack.restype = i32
     L.ia_ctx_set_fp32_slack.argtypes = [P, C.c_double]
     L.ia_ctx_clear_status.restype = i32
@@ -197,6 +203,19 @@ class Context:
         self._check(self._L.ia_ctx_work(self._h, C.byref(a), C.byref(b), C.byref(f), C.byref(g)))
         return int(a.value), int(b.value), int(f.value), int(g.value)
 
+    def set_work_counting(self, enable=True):
+        """Classification launches count their work (a slower variant) while enabled."""
+        self._check(self._L.ia_ctx_set_work_counting(self._h, 1 if enable else 0))
+
+    def classify_work(self):
+        """Classification work counted (set_work_counting) since the last clear_status(): {"fp64": {...},
+        "fp32": {...}} with counts of residuals G, axial tests, stereo pair
+        quantities, d^Ax enclosures and inclusion proofs."""
+        a = (C.c_int64 * 10)()
+        self._check(self._L.ia_ctx_classify_work(self._h, a))
+        keys = ("G", "axial", "pairq", "enclosures", "inclusions")
+        return {p: {k: int(a[5 * i + j]) for j, k in enumerate(keys)} for i, p in enumerate(("fp64", "fp32"))}
+
     def set_fp32_slack(self, slack=1e-6):
         """Band widening of vote_level at FP32 (m)."""
         self._check(self._L.ia_ctx_set_fp32_slack(self._h, float(slack)))
@@ -249,6 +268,15 @@ class Context:
         n, ms, n32, ms32 = C.c_int64(), C.c_double(), C.c_int64(), C.c_double()
         self._check(self._L.ia_ctx_profile_read(self._h, C.byref(n), C.byref(ms), C.byref(n32), C.byref(ms32)))
         return int(n.value), float(ms.value), int(n32.value), float(ms32.value)
+
+    def profile_kernels(self):
+        """{(kernel, prec): (launches, ms)} for kernel in ("vote", "classify")
+        and prec in ("fp64", "fp32"), since the last read (clears the record)."""
+        n = (C.c_int64 * 4)()
+        ms = (C.c_double * 4)()
+        self._check(self._L.ia_ctx_profile_kernels(self._h, n, ms))
+        return {(k, p): (int(n[2 * i + j]), float(ms[2 * i + j]))
+                for i, k in enumerate(("vote", "classify")) for j, p in enumerate(("fp64", "fp32"))}
 
     def close(self):
         if getattr(self, "_h", None):

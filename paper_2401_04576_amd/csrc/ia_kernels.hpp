@@ -88,11 +88,15 @@ struct EvView {
 // status word bits (device-detected problems, read after a stream sync)
 enum : uint32_t { kStBadHit = 1u, kStVoteOverflow = 2u, kStBadOffsets = 4u };
 
-// vote-kernel work counters: kWorkSlots slots of 16 u64 (one 128-byte line
-// each); counters 0..3 of a slot: stereo (box, hit) evaluations and staged
-// (triple, hit) pairs at FP64 levels, the same two at FP32 levels
+// work counters: kWorkSlots slots of 16 u64 (one 128-byte line each);
+// counters 0..3 of a slot: stereo (box, hit) evaluations and staged (triple,
+// hit) pairs at FP64 levels, the same two at FP32 levels (vote kernels);
+// counters kWorkClassify + 5 p + c: classification work at precision p
+// (0 FP64, 1 FP32), c = kCw* below
 constexpr uint32_t kWorkSlots = 64;
 constexpr uint32_t kWorkSlotU64 = 16;
+constexpr uint32_t kWorkClassify = 4;
+enum : uint32_t { kCwG = 0, kCwAxial = 1, kCwPairQ = 2, kCwPass = 3, kCwIncl = 4, kCwN = 5 };
 
 // ---------------------------------------------------------------------------
 // edges of child k of [L, U] split m ways
@@ -355,7 +359,9 @@ IA_HD bool votes_everywhere(Iv G, Iv K, double E1, double E2, double b) {
 // a well-conditioned point evaluation everywhere on the rectangle (the
 // discriminant of d^Ax above A^2 / 4) and the inclusion proof above over
 // the enclosure of e.
-IA_HD int triple_vote_class(const PairQ& q, const Frame& f, const HitRec& h, Iv Z, Iv L) {
+// With `cnt` set, cnt[0] counts the enclosure passes and cnt[1] the
+// inclusion proofs evaluated.
+IA_HD int triple_vote_class(const PairQ& q, const Frame& f, const HitRec& h, Iv Z, Iv L, int32_t* cnt = nullptr) {
   const Iv G = {q.Glo, q.Ghi};
   const double tt = h.tant, t2 = tt * tt;
   bool may = false;
@@ -367,9 +373,10 @@ IA_HD int triple_vote_class(const PairQ& q, const Frame& f, const HitRec& h, Iv 
     const Iv DS = si < 0 ? Iv{-h.d, h.d} : ipt(si == 0 ? h.d : -h.d);
     Iv E, EPS, DISC, A;
     const bool ok = e_enclosure_dom(q, f.R, f.sig, tt, t2, DS, Z, L, &E, &EPS, &DISC, &A);
-    if (si >= 0 && ok && DISC.lo > 0.25 * A.lo * A.lo && A.lo > 0.0 &&
-        votes_everywhere(G, f.K, E.lo, E.hi, h.band))
-      return 1;
+    if (cnt) ++cnt[0];
+    const bool try_incl = si >= 0 && ok && DISC.lo > 0.25 * A.lo * A.lo && A.lo > 0.0;
+    if (cnt && try_incl) ++cnt[1];
+    if (try_incl && votes_everywhere(G, f.K, E.lo, E.hi, h.band)) return 1;
     bool in = true;                      // the test cannot be excluded on this pass
     if (ok) {
       const Iv Eb = {wdn(E.lo - h.band), wup(E.hi + h.band)};
@@ -475,7 +482,8 @@ IA_HD bool stereo_vote32(const PairQ32& q, float R, float sig, Iv32 K, float z0,
 // votes_everywhere holds for FP32 outward rounding as well; it is applied to
 // the FP32 G, K and band (exact in FP64) over [E1 - slack, E2 + slack],
 // which holds every box's e32 (a box outside the FP32 domain votes anyway).
-IA_HD int triple_vote_class32(const PairQ& q, const Frame& f, const HitRec& h, Iv Z, Iv L, float slack32) {
+IA_HD int triple_vote_class32(const PairQ& q, const Frame& f, const HitRec& h, Iv Z, Iv L, float slack32,
+                              int32_t* cnt = nullptr) {
   if (!(f.R <= kR32Max)) return 1;
   const Iv32 G = to32(Iv{q.Glo, q.Ghi});
   const Iv32 K = to32(f.K);
@@ -490,8 +498,10 @@ IA_HD int triple_vote_class32(const PairQ& q, const Frame& f, const HitRec& h, I
     const Iv DS = si < 0 ? Iv{-h.d, h.d} : ipt(si == 0 ? h.d : -h.d);
     Iv E, EPS, DISC, A;
     const bool ok = e_enclosure_dom(q, f.R, f.sig, tt, t2, DS, Z, L, &E, &EPS, &DISC, &A);
-    if (si >= 0 && ok && DISC.lo > 0.25 * A.lo * A.lo && A.lo > 0.0 &&
-        votes_everywhere(Iv{G.lo, G.hi}, Iv{K.lo, K.hi}, wdn(E.lo - slack32), wup(E.hi + slack32), bs))
+    if (cnt) ++cnt[0];
+    const bool try_incl = si >= 0 && ok && DISC.lo > 0.25 * A.lo * A.lo && A.lo > 0.0;
+    if (cnt && try_incl) ++cnt[1];
+    if (try_incl && votes_everywhere(Iv{G.lo, G.hi}, Iv{K.lo, K.hi}, wdn(E.lo - slack32), wup(E.hi + slack32), bs))
       return 1;
     // excluded only when every box stays in the FP32 domain and the widened
     // FP32 test fails over the whole enclosure
@@ -807,13 +817,18 @@ __device__ __forceinline__ int32_t block_sum(int32_t v, int32_t* sbuf) {
 // group z takes hits 4 z + w, 4 z + w + 4 gridDim.z, ...), so the hit of a
 // wave is uniform (axial and stereo work do not diverge) and each thread
 // computes its triple frame once.  flags are hit-major: flags[h * n_tr + t].
-template <bool F32>
+// With COUNT, the work done (residuals G, axial tests, pair quantities,
+// enclosure passes, inclusion proofs; live triples only) is added to `work`
+// with one atomic per counter per workgroup (a separate instantiation: the
+// counting costs the search a few per cent).
+template <bool F32, bool COUNT>
 __global__ void __launch_bounds__(kWG) k_classify(const HitRec* __restrict__ hits, EvView vw,
                                                   const BoxD* __restrict__ parents, Shape sh,
                                                   uint8_t* __restrict__ flags, int32_t* __restrict__ tlb,
                                                   int32_t* __restrict__ tn2, int32_t filter,
                                                   const EventState* __restrict__ ev, float slack32,
-                                                  const uint8_t* __restrict__ pflags) {
+                                                  const uint8_t* __restrict__ pflags,
+                                                  unsigned long long* __restrict__ work) {
   const int e = blockIdx.y;
   if (ev && ev[e].done) return;
   const int32_t n_hits = vw.count(e);
@@ -835,22 +850,27 @@ __global__ void __launch_bounds__(kWG) k_classify(const HitRec* __restrict__ hit
   Iv Zr, Lr;
   centre_ranges(TP, sh.m, &Zr, &Lr);
   int32_t lb = 0, n2 = 0;
+  int32_t cw[kCwN] = {0, 0, 0, 0, 0};
   const int32_t h_step = static_cast<int32_t>(gridDim.z) * (kWG / 64);
   for (int32_t h = static_cast<int32_t>(blockIdx.z) * (kWG / 64) + wave; h < n_hits; h += h_step) {
     const HitRec hr = hits[h];
     uint8_t fl = 0;
     if (hr.use && (!pf || pf[h])) {
       const Iv G = residual_G(f, hr);
+      if constexpr (COUNT) ++cw[kCwG];
       if (hr.axial) {
         fl = (h_contains0(G, f.K, f.sig * hr.d, hr.band) || h_contains0(G, f.K, f.sig * (-hr.d), hr.band)) ? 1 : 0;
+        if constexpr (COUNT) ++cw[kCwAxial];
       } else if (F32 && !(f.R <= kR32Max)) {
         fl = 1;                              // outside the FP32 domain: the pair votes
       } else if (!filter) {
         fl = 2;
       } else {
         const PairQ q = pair_quantities(f, hr, G);
-        fl = static_cast<uint8_t>(F32 ? triple_vote_class32(q, f, hr, Zr, Lr, slack32)
-                                      : triple_vote_class(q, f, hr, Zr, Lr));
+        if constexpr (COUNT) ++cw[kCwPairQ];
+        int32_t* pc = COUNT ? &cw[kCwPass] : nullptr;
+        fl = static_cast<uint8_t>(F32 ? triple_vote_class32(q, f, hr, Zr, Lr, slack32, pc)
+                                      : triple_vote_class(q, f, hr, Zr, Lr, pc));
       }
     }
     if (live) flags[int64_t(h) * n_tr + t] = fl;
@@ -858,14 +878,27 @@ __global__ void __launch_bounds__(kWG) k_classify(const HitRec* __restrict__ hit
     n2 += fl == 2 ? 1 : 0;
   }
   __shared__ int32_t s_lb[kWG / 64][64], s_n2[kWG / 64][64];
+  __shared__ unsigned long long s_cw[kCwN];
+  if (COUNT && threadIdx.x < kCwN) s_cw[threadIdx.x] = 0;
   s_lb[wave][lane] = lb;
   s_n2[wave][lane] = n2;
   __syncthreads();
+  if (COUNT && live)
+    for (uint32_t k = 0; k < kCwN; ++k)
+      if (cw[k]) atomicAdd(&s_cw[k], static_cast<unsigned long long>(cw[k]));
   if (wave == 0 && live) {
     int32_t a = 0, b = 0;
     for (int w = 0; w < kWG / 64; ++w) { a += s_lb[w][lane]; b += s_n2[w][lane]; }
     if (a) atomicAdd(&tlb[t], a);
     if (b) atomicAdd(&tn2[t], b);
+  }
+  if constexpr (COUNT) {
+    __syncthreads();
+    if (threadIdx.x < kCwN && s_cw[threadIdx.x]) {
+      unsigned long long* slot =
+          work + kWorkSlotU64 * ((blockIdx.x + blockIdx.y * 7u + blockIdx.z * 13u) % kWorkSlots);
+      atomicAdd(&slot[kWorkClassify + (F32 ? kCwN : 0) + threadIdx.x], s_cw[threadIdx.x]);
+    }
   }
 }
 

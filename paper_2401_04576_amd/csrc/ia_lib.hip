@@ -62,6 +62,7 @@ struct ia_ctx {
   int32_t filter_mode = -1;       // -1: automatic, 0: off, 1: on
   int32_t prune = 1;              // ia_find_helices: skip triples that cannot reach the selection
   int32_t parent_filter = 1;      // ia_find_helices: parent-level exclusion at refinement levels
+  int32_t count_work = 0;         // classification launches count their work
   int32_t max_chunk = 65535;      // events per batched launch
   float slack32 = ia::ru32(1e-6);  // band widening of ia_vote_level at FP32
   // pinned staging ring for the chunk-relative hit offsets copied to the
@@ -70,7 +71,7 @@ struct ia_ctx {
   hipEvent_t slot_done[kOffSlots] = {};
   bool slot_used[kOffSlots] = {};
   uint32_t slot_next = 0;
-  struct Mark { hipEvent_t e0, e1; bool f32; uint32_t n_boxes; };
+  struct Mark { hipEvent_t e0, e1; bool f32; uint32_t n_boxes; int32_t kind; };   // kind: IA_KERNEL_*
   std::vector<Mark> marks;
   // autotuned vote tile per level size (boxes per event), from ia_ctx_autotune
   std::vector<std::pair<uint32_t, int32_t>> tuned;
@@ -186,10 +187,10 @@ ia::EvView single_view(int32_t n_hits) {
 // (tlb and tn2 must be zero on entry; the kernel adds to them).  The hits
 // are split over enough groups (grid z) to give the device about 2048
 // workgroups when the triples alone do not.
-void launch_classify(ia_ctx* c, const HitRec* recs, const ia::EvView& vw, int32_t n_ev, int32_t max_hits,
-                     const BoxD* par, const Shape& sh, uint8_t* flags, int32_t* tlb, int32_t* tn2,
-                     const EventState* ev, hipStream_t s, bool f32, float slack32,
-                     const uint8_t* pflags = nullptr) {
+ia_status launch_classify(ia_ctx* c, const HitRec* recs, const ia::EvView& vw, int32_t n_ev, int32_t max_hits,
+                          const BoxD* par, const Shape& sh, uint8_t* flags, int32_t* tlb, int32_t* tn2,
+                          const EventState* ev, hipStream_t s, bool f32, float slack32,
+                          const uint8_t* pflags = nullptr) {
   const uint32_t n_tr = sh.n_parents * sh.m012;
   const uint32_t gx = (n_tr + 63) / 64;
   const int64_t base = int64_t(gx) * std::max(1, n_ev);
@@ -197,12 +198,34 @@ void launch_classify(ia_ctx* c, const HitRec* recs, const ia::EvView& vw, int32_
   const int32_t hg = static_cast<int32_t>(std::min<int64_t>(std::max<int64_t>(1, 2048 / base), std::min(max_groups, 64)));
   const dim3 g(gx, n_ev, hg);
   const int32_t filt = use_filter(c);
-  if (f32)
-    hipLaunchKernelGGL((ia::k_classify<true>), g, dim3(ia::kWG), 0, s, recs, vw, par, sh, flags, tlb, tn2, filt, ev,
-                       slack32, pflags);
-  else
-    hipLaunchKernelGGL((ia::k_classify<false>), g, dim3(ia::kWG), 0, s, recs, vw, par, sh, flags, tlb, tn2, filt, ev,
-                       slack32, pflags);
+  unsigned long long* wk = persistent(c)->work;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (c->profiling) {
+    IA_HIP(c, hipEventCreate(&e0));
+    IA_HIP(c, hipEventCreate(&e1));
+    IA_HIP(c, hipEventRecord(e0, s));
+  }
+  const dim3 b(ia::kWG);
+  if (c->count_work) {
+    if (f32)
+      hipLaunchKernelGGL((ia::k_classify<true, true>), g, b, 0, s, recs, vw, par, sh, flags, tlb, tn2, filt, ev,
+                         slack32, pflags, wk);
+    else
+      hipLaunchKernelGGL((ia::k_classify<false, true>), g, b, 0, s, recs, vw, par, sh, flags, tlb, tn2, filt, ev,
+                         slack32, pflags, wk);
+  } else if (f32) {
+    hipLaunchKernelGGL((ia::k_classify<true, false>), g, b, 0, s, recs, vw, par, sh, flags, tlb, tn2, filt, ev,
+                       slack32, pflags, nullptr);
+  } else {
+    hipLaunchKernelGGL((ia::k_classify<false, false>), g, b, 0, s, recs, vw, par, sh, flags, tlb, tn2, filt, ev,
+                       slack32, pflags, nullptr);
+  }
+  if (c->profiling) {
+    IA_HIP(c, hipEventRecord(e1, s));
+    c->marks.push_back({e0, e1, f32, sh.n_boxes, IA_KERNEL_CLASSIFY});
+  }
+  IA_HIP(c, hipGetLastError());
+  return IA_OK;
 }
 
 // launches the vote kernel for n_ev events, bracketed by events when profiling
@@ -259,7 +282,7 @@ ia_status launch_vote(ia_ctx* c, const HitRec* recs, const ia::EvView& vw, int32
   else launch_vote_tile<false>(bx, g, s, recs, vw, par, sh, votes, hist, st, ev, in, wg_max, wk, slack32);
   if (c->profiling) {
     IA_HIP(c, hipEventRecord(e1, s));
-    c->marks.push_back({e0, e1, f32, sh.n_boxes});
+    c->marks.push_back({e0, e1, f32, sh.n_boxes, IA_KERNEL_VOTE});
   }
   IA_HIP(c, hipGetLastError());
   return IA_OK;
@@ -325,7 +348,7 @@ ia_status launch_vote_rec(ia_ctx* c, const ia::EvView& vw, int32_t n_ev, const B
   else launch_vote_rec_tile<false>(bx, g, s, vw, par, sh, votes, hist, st, ev, in, r, wg_max, wk);
   if (c->profiling) {
     IA_HIP(c, hipEventRecord(e1, s));
-    c->marks.push_back({e0, e1, f32, sh.n_boxes});
+    c->marks.push_back({e0, e1, f32, sh.n_boxes, IA_KERNEL_VOTE});
   }
   IA_HIP(c, hipGetLastError());
   return IA_OK;
@@ -501,8 +524,11 @@ ia_status run_chunk(ia_ctx* c, const double* hits_chunk, const int32_t* h_off_ch
           hipLaunchKernelGGL((ia::k_parent_filter<false>), gp, dim3(ia::kWG), 0, s, recs, vw, par, sh, pflags, ev,
                              slack32);
       }
-      launch_classify(c, recs, vw, E, cmax, par, sh, flags, tlb, tn2, ev, s, f32, slack32,
-                      use_pf ? pflags : nullptr);
+      {
+        const ia_status cs = launch_classify(c, recs, vw, E, cmax, par, sh, flags, tlb, tn2, ev, s, f32, slack32,
+                                             use_pf ? pflags : nullptr);
+        if (cs != IA_OK) return cs;
+      }
       const int32_t vt = vote_tile(c, sh.n_boxes);
       hipLaunchKernelGGL(ia::k_threshold, dim3(1, E), dim3(ia::kWG), 0, s, tlb, tn2, lbh, vw, sh, K, c->prune, vt,
                          ev, live, wg_max, rin.live_tri, rin.rec_off, rin.rec_fill, L.rec_stride);
@@ -614,6 +640,20 @@ ia_status ia_ctx_work(ia_ctx* c, int64_t* stereo_box_evals, int64_t* staged_pair
   return IA_OK;
 }
 
+ia_status ia_ctx_classify_work(ia_ctx* c, int64_t counts[10]) {
+  if (!c || !counts) return IA_ERR_INVALID;
+  IA_HIP(c, hipSetDevice(c->device));
+  IA_HIP(c, hipDeviceSynchronize());
+  Persistent p;
+  IA_HIP(c, hipMemcpy(&p, c->arena, sizeof p, hipMemcpyDeviceToHost));
+  for (uint32_t k = 0; k < 2 * ia::kCwN; ++k) {
+    unsigned long long w = 0;
+    for (uint32_t i = 0; i < ia::kWorkSlots; ++i) w += p.work[i * ia::kWorkSlotU64 + ia::kWorkClassify + k];
+    counts[k] = static_cast<int64_t>(w);
+  }
+  return IA_OK;
+}
+
 ia_status ia_ctx_clear_status(ia_ctx* c) {
   if (!c) return IA_ERR_INVALID;
   IA_HIP(c, hipSetDevice(c->device));
@@ -657,18 +697,22 @@ ia_status ia_ctx_set_parent_filter(ia_ctx* c, int32_t enable) {
   return IA_OK;
 }
 
+ia_status ia_ctx_set_work_counting(ia_ctx* c, int32_t enable) {
+  if (!c) return IA_ERR_INVALID;
+  c->count_work = enable != 0 ? 1 : 0;
+  return IA_OK;
+}
+
 ia_status ia_ctx_set_profiling(ia_ctx* c, int32_t enable) {
   if (!c) return IA_ERR_INVALID;
   c->profiling = enable != 0;
   return IA_OK;
 }
 
-ia_status ia_ctx_profile_read(ia_ctx* c, int64_t* n_launches, double* total_ms, int64_t* n_launches_fp32,
-                              double* total_ms_fp32) {
-  if (!c) return IA_ERR_INVALID;
+ia_status ia_ctx_profile_kernels(ia_ctx* c, int64_t n_launches[4], double total_ms[4]) {
+  if (!c || !n_launches || !total_ms) return IA_ERR_INVALID;
   IA_HIP(c, hipSetDevice(c->device));
-  double tot[2] = {0.0, 0.0};
-  int64_t n[2] = {0, 0};
+  for (int i = 0; i < 4; ++i) { n_launches[i] = 0; total_ms[i] = 0.0; }
   ia_status st = IA_OK;
   for (auto& m : c->marks) {
     if (st == IA_OK) {
@@ -676,17 +720,26 @@ ia_status ia_ctx_profile_read(ia_ctx* c, int64_t* n_launches, double* total_ms, 
       float ms = 0.f;
       if (e == hipSuccess) e = hipEventElapsedTime(&ms, m.e0, m.e1);
       if (e != hipSuccess) st = fail(c, IA_ERR_DEVICE, "profile events: %s", hipGetErrorString(e));
-      tot[m.f32] += ms;
-      ++n[m.f32];
+      const int i = 2 * m.kind + (m.f32 ? 1 : 0);
+      total_ms[i] += ms;
+      ++n_launches[i];
     }
     (void)hipEventDestroy(m.e0);
     (void)hipEventDestroy(m.e1);
   }
   c->marks.clear();
-  if (n_launches) *n_launches = n[0];
-  if (total_ms) *total_ms = tot[0];
-  if (n_launches_fp32) *n_launches_fp32 = n[1];
-  if (total_ms_fp32) *total_ms_fp32 = tot[1];
+  return st;
+}
+
+ia_status ia_ctx_profile_read(ia_ctx* c, int64_t* n_launches, double* total_ms, int64_t* n_launches_fp32,
+                              double* total_ms_fp32) {
+  int64_t n[4];
+  double ms[4];
+  const ia_status st = ia_ctx_profile_kernels(c, n, ms);
+  if (n_launches) *n_launches = n[2 * IA_KERNEL_VOTE];
+  if (total_ms) *total_ms = ms[2 * IA_KERNEL_VOTE];
+  if (n_launches_fp32) *n_launches_fp32 = n[2 * IA_KERNEL_VOTE + 1];
+  if (total_ms_fp32) *total_ms_fp32 = ms[2 * IA_KERNEL_VOTE + 1];
   return st;
 }
 
@@ -746,7 +799,8 @@ ia_status ia_vote_level(ia_ctx* c, const ia_hit* d_hits, int32_t n_hits, const u
                      reinterpret_cast<uint32_t*>(tlb), fill_n, 0u);
   hipLaunchKernelGGL(ia::k_fill_u32, dim3(std::min<uint32_t>((fill_n + 255) / 256, 65535)), dim3(256), 0, s,
                      reinterpret_cast<uint32_t*>(tn2), fill_n, 0u);
-  launch_classify(c, recs, vw, 1, n_hits, par, sh, flags, tlb, tn2, nullptr, s, f32, c->slack32);
+  const ia_status cs = launch_classify(c, recs, vw, 1, n_hits, par, sh, flags, tlb, tn2, nullptr, s, f32, c->slack32);
+  if (cs != IA_OK) return cs;
   const VoteIn in{flags, tlb, tn2, nullptr, 0};
   return launch_vote(c, recs, vw, 1, par, sh, d_votes, nullptr, nullptr, in, nullptr, s, f32, c->slack32);
 }
@@ -916,7 +970,7 @@ ia_status ia_ctx_autotune(ia_ctx* c, const ia_hit* d_hits, const int32_t* h_off,
     if (st == IA_OK) IA_HIP(c, hipStreamSynchronize(as_stream(stream)));
     for (auto& m : c->marks) {
       float t = 0.f;
-      if (st == IA_OK && hipEventElapsedTime(&t, m.e0, m.e1) == hipSuccess) {
+      if (st == IA_OK && m.kind == IA_KERNEL_VOTE && hipEventElapsedTime(&t, m.e0, m.e1) == hipSuccess) {
         bool found = false;
         for (auto& x : ms[ci])
           if (x.first == m.n_boxes) { x.second += t; found = true; }

@@ -332,3 +332,40 @@ def test_parent_filter_does_not_change_results(ctx):
         assert np.array_equal(n_a, n_b) and np.array_equal(ass_a, ass_b)
         for e in range(len(events)):
             assert hel_a[e, :n_a[e]].tobytes() == hel_b[e, :n_b[e]].tobytes()
+
+
+def test_classification_counters_and_timing(ctx):
+    """The classification's work counters and the per-kernel timing record
+    of one ia_vote_level call: one residual G per (triple, used hit), one
+    axial test per axial pair, one set of pair quantities per stereo pair,
+    one to three enclosures per stereo pair and at most two inclusion
+    proofs; one timed launch each of the classification and the vote."""
+    torch = _torch()
+    ev = toymc.config_event(2, 3)
+    prep = oracle.prep_hits(ev.hits)
+    used = prep["valid"] == 1
+    n_ax, n_st = int((used & (prep["axial"] == 1)).sum()), int((used & (prep["axial"] == 0)).sum())
+    root = oracle.make_box(H.LO, H.HI)
+    split = [9, 10, 11, 4, 4]
+    n_tr = 9 * 10 * 11
+    ctx.clear_status()
+    ctx.profile_kernels()
+    ctx.set_profiling(True)
+    ctx.set_work_counting(True)
+    try:
+        v = ia.vote_level(ctx, _dev_hits(ev.hits), _dev_boxes(root), split)
+        torch.cuda.synchronize()
+    finally:
+        ctx.set_profiling(False)
+        ctx.set_work_counting(False)
+    kp = ctx.profile_kernels()
+    cw = ctx.classify_work()["fp64"]
+    assert kp[("classify", "fp64")][0] == 1 and kp[("vote", "fp64")][0] == 1
+    assert kp[("classify", "fp32")][0] == 0 and kp[("classify", "fp64")][1] > 0
+    assert cw["G"] == n_tr * (n_ax + n_st)
+    assert cw["axial"] == n_tr * n_ax
+    assert cw["pairq"] == n_tr * n_st
+    assert cw["pairq"] <= cw["enclosures"] <= 3 * cw["pairq"]
+    assert cw["inclusions"] <= 2 * cw["pairq"]
+    assert np.array_equal(v.cpu().numpy().astype(np.uint16),
+                          oracle.vote_level(ev.hits, root, split))
