@@ -641,7 +641,8 @@ def run_serve(args):
         "vs_baseline": None, "dtype": "f64" if args.prec == "fp64" else "f32+f64", "data": "synthetic",
         "config": {"workload": f"serving: {len(events)} events, Poisson arrivals at {args.rate:g}/s, 1-10 "
                                "helices, lognormal hits (median 120, [20, 1000]), 0-40% noise; 16^5 grid then 4 "
-                               "levels of top-32 split 4^5; up to 10 greedy helix passes; FP64",
+                               "levels of top-32 split 4^5; up to 10 greedy helix passes; "
+                               + ("FP64" if args.prec == "fp64" else "FP32 at levels 0-2, FP64 at 3-4 and the fit"),
                    "slots": args.slots, "events_per_slot": slots_used,
                    "helices_found_per_event": found / len(done),
                    "helices_generated_per_event": truth / len(done)},
