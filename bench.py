@@ -75,8 +75,9 @@ FLOP_BOX_STEREO32 = 278
 #  - stereo pair quantities (RAx, its sin / cos, atan2 of the arc, sArc, ...): 69;
 #  - one interval enclosure of d^Ax over the triple's (z0, tanl) centres with
 #    its exclusion test (the FP32 levels' test counted as FP64 too): 688;
-#  - one inclusion proof (bounds at the enclosure's ends): 94.
-FLOP_CLS_G, FLOP_CLS_AXIAL, FLOP_CLS_PAIRQ, FLOP_CLS_ENCL, FLOP_CLS_INCL = 157, 92, 69, 688, 94
+#  - one inclusion proof (bounds at the enclosure's ends): 94;
+#  - one magnitude bound of d^Ax over the triple (67) with its exclusion test (46): 113.
+FLOP_CLS_G, FLOP_CLS_AXIAL, FLOP_CLS_PAIRQ, FLOP_CLS_ENCL, FLOP_CLS_INCL, FLOP_CLS_MAG = 157, 92, 69, 688, 94, 113
 PEAK_FP64_TFLOPS = 78.6   # MI355X vector FP64: 256 CU x 128 FLOP/clk x 2.4 GHz
 # HBM bytes per launch of the FP64 classification over 1024-event batches of
 # the default workload: rocprofv3 --pmc FETCH_SIZE, then WRITE_SIZE, averaged
@@ -119,7 +120,8 @@ def classify_traffic(workload, events_per_step):
 
 def classify_flops(cw):
     return (cw["G"] * FLOP_CLS_G + cw["axial"] * FLOP_CLS_AXIAL + cw["pairq"] * FLOP_CLS_PAIRQ
-            + cw["enclosures"] * FLOP_CLS_ENCL + cw["inclusions"] * FLOP_CLS_INCL)
+            + cw["enclosures"] * FLOP_CLS_ENCL + cw["inclusions"] * FLOP_CLS_INCL
+            + cw["magnitudes"] * FLOP_CLS_MAG)
 
 
 def roofline(kprof, work, cwork, wall, measured_on, traffic_classify=None):

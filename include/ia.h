@@ -159,13 +159,14 @@ ia_status ia_ctx_set_work_counting(ia_ctx *ctx, int32_t enable);
 
 /* Work of the classification kernel, counted while work counting was
  * enabled, since the last ia_ctx_clear_status:
- * counts[5 p + c] at precision p (0 FP64 levels, 1 FP32 levels) for
+ * counts[6 p + c] at precision p (0 FP64 levels, 1 FP32 levels) for
  * c = 0 residual intervals G (Eq. ApoVote over a triple), 1 axial tests,
  * 2 stereo pair quantities, 3 interval enclosures of d^Ax (each with its
- * exclusion test), 4 inclusion proofs.  Only pairs of live triples are
- * counted; pairs the parent-level test excluded are not.  Synchronises the
- * device.  counts is host memory of 10 entries. */
-ia_status ia_ctx_classify_work(ia_ctx *ctx, int64_t counts[10]);
+ * exclusion test), 4 inclusion proofs, 5 magnitude bounds of d^Ax (each
+ * with its exclusion test).  Only pairs of live triples are counted; pairs
+ * the parent-level test excluded are not.  Synchronises the device.
+ * counts is host memory of 12 entries. */
+ia_status ia_ctx_classify_work(ia_ctx *ctx, int64_t counts[12]);
 
 /* Band widening used by ia_vote_level at IA_FP32 (default 1e-6 m; ia_find_helices
  * takes it from the schedule).  IA_ERR_INVALID outside [0, 1e-3]. */

@@ -210,11 +210,11 @@ class Context:
     def classify_work(self):
         """Classification work counted (set_work_counting) since the last clear_status(): {"fp64": {...},
         "fp32": {...}} with counts of residuals G, axial tests, stereo pair
-        quantities, d^Ax enclosures and inclusion proofs."""
-        a = (C.c_int64 * 10)()
+        quantities, d^Ax enclosures, inclusion proofs and magnitude bounds."""
+        a = (C.c_int64 * 12)()
         self._check(self._L.ia_ctx_classify_work(self._h, a))
-        keys = ("G", "axial", "pairq", "enclosures", "inclusions")
-        return {p: {k: int(a[5 * i + j]) for j, k in enumerate(keys)} for i, p in enumerate(("fp64", "fp32"))}
+        keys = ("G", "axial", "pairq", "enclosures", "inclusions", "magnitudes")
+        return {p: {k: int(a[6 * i + j]) for j, k in enumerate(keys)} for i, p in enumerate(("fp64", "fp32"))}
 
     def set_fp32_slack(self, slack=1e-6):
         """Band widening of vote_level at FP32 (m)."""

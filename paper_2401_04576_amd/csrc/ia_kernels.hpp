@@ -91,12 +91,12 @@ enum : uint32_t { kStBadHit = 1u, kStVoteOverflow = 2u, kStBadOffsets = 4u };
 // work counters: kWorkSlots slots of 16 u64 (one 128-byte line each);
 // counters 0..3 of a slot: stereo (box, hit) evaluations and staged (triple,
 // hit) pairs at FP64 levels, the same two at FP32 levels (vote kernels);
-// counters kWorkClassify + 5 p + c: classification work at precision p
+// counters kWorkClassify + 6 p + c: classification work at precision p
 // (0 FP64, 1 FP32), c = kCw* below
 constexpr uint32_t kWorkSlots = 64;
 constexpr uint32_t kWorkSlotU64 = 16;
 constexpr uint32_t kWorkClassify = 4;
-enum : uint32_t { kCwG = 0, kCwAxial = 1, kCwPairQ = 2, kCwPass = 3, kCwIncl = 4, kCwN = 5 };
+enum : uint32_t { kCwG = 0, kCwAxial = 1, kCwPairQ = 2, kCwPass = 3, kCwIncl = 4, kCwMag = 5, kCwN = 6 };
 
 // ---------------------------------------------------------------------------
 // edges of child k of [L, U] split m ways
@@ -353,28 +353,87 @@ IA_HD bool votes_everywhere(Iv G, Iv K, double E1, double E2, double b) {
   return f.lo >= 2.0 * G.lo && g.hi <= 2.0 * G.hi;
 }
 
+// Magnitude bound of d^Ax over a triple.  Every term of the point evaluation
+// (stereo_vote) is replaced by an upper bound of its absolute value over all
+// (z0, tanl) centres of the triple and both drift signs: |z0| <= z, |tanl| <=
+// l, |dS| = d, |sinP|, |cosP| <= |sinA| + |cosA| (each is a rotation of
+// (sinA, cosA)), u^2 >= 1 - 2 l (|sinA| + |cosA|) tan(tau), A >= R - |delta|,
+// and A + sqrt(A^2 - Q) >= alo + sqrt(alo^2 - |Q|) when the root is real
+// (a negative discriminant casts no vote).  Only sums, products, quotients
+// and roots of non-negative numbers remain, except three subtractions held
+// far from cancellation by the checks (u^2 >= 1/4, alo^2 - |Q| >= alo^2 / 4),
+// so the bound's own rounding stays below a few hundred ulps; the result is
+// widened by 2^-29 relative + 1e-12 m, which also covers the point
+// evaluation's rounding (the margin of e_enclosure_dom).  Returns false when
+// a check fails (no bound).  `eps` bounds |eps|, `disc_lo` bounds the
+// discriminant from below and `a_hi` bounds A from above.
+struct EMag { double M, eps, disc_lo, a_hi; };
+
+IA_HD bool e_magnitude(const PairQ& q, double R, double tt, double d, Iv Z, Iv L, EMag* out) {
+  const double at = fabs(tt), t2 = at * at;
+  const double z = fmax(fabs(Z.lo), fabs(Z.hi)), l = fmax(fabs(L.lo), fabs(L.hi));
+  const double sa = fabs(q.sinA), ca = fabs(q.cosA), S = sa + ca;
+  const double za = z + l * fabs(q.sArc);
+  const double phi1 = (za * sa + (l * d) * ca) / q.RAx;
+  const double phi2 = ((l * R) * za + ((l * za) * (R + 2.0 * d)) * fabs(q.c2) +
+                       (za * za + d * (q.RAx + (l * l) * (q.RpRAx + d))) * fabs(q.s2)) / q.twoRAx2;
+  const double eps = phi1 * at + phi2 * t2;
+  const double u2 = 1.0 - ((2.0 * l) * S) * at;
+  if (!(u2 >= 0.25)) return false;
+  const double delta = d / sqrt(u2);
+  const double zs = (z + l * (R * (fabs(q.dphi) + eps))) + (delta * S) * at;
+  const double ld = l * delta;
+  const double ctau = zs * fabs(q.cAx) + ld * fabs(q.sAx);
+  const double Qm = ((2.0 * ctau) * at + (zs * at) * (zs * at)) + (ld * at) * (ld * at);
+  const double alo = R - delta;
+  if (!(alo > 0.0)) return false;
+  const double r = alo * alo - Qm;
+  if (!(r >= 0.25 * (alo * alo))) return false;
+  const double M = delta + Qm / (alo + sqrt(r));
+  out->M = M * (1.0 + 0x1p-29) + 1e-12;
+  out->eps = eps * (1.0 + 0x1p-29);
+  out->disc_lo = r * (1.0 - 0x1p-29);
+  out->a_hi = (R + delta) * (1.0 + 0x1p-29);
+  return __builtin_isfinite(out->M) && __builtin_isfinite(out->eps);
+}
+
+// H test of reading 8 over E = [-M, M] widened by the band: false when the
+// pair can vote in no box whose |e| is at most M
+IA_HD bool h_may_vote_mag(Iv G, Iv K, double M, double band) {
+  const double b = wup(M + band);
+  const Iv Eb = {-b, b};
+  const Iv Hb = isub(itwice(G), iadd(itwice(Eb), imul(K, isqr(Eb))));
+  return Hb.lo <= 0.0 && 0.0 <= Hb.hi;
+}
+
 // Class of a (triple, stereo hit) pair at an FP64 level: 0 when no box of
 // the triple can get the hit's vote, 1 when every box gets it, 2 when the
 // boxes must be evaluated one by one.  Class 1 needs, for one drift sign,
 // a well-conditioned point evaluation everywhere on the rectangle (the
 // discriminant of d^Ax above A^2 / 4) and the inclusion proof above over
 // the enclosure of e.
-// With `cnt` set, cnt[0] counts the enclosure passes and cnt[1] the
-// inclusion proofs evaluated.
+// With `cnt` set, cnt[0] counts the enclosure passes, cnt[1] the inclusion
+// proofs and cnt[2] the magnitude bounds evaluated.
 IA_HD int triple_vote_class(const PairQ& q, const Frame& f, const HitRec& h, Iv Z, Iv L, int32_t* cnt = nullptr) {
   const Iv G = {q.Glo, q.Ghi};
   const double tt = h.tant, t2 = tt * tt;
+  // the magnitude bound of e excludes most pairs that can be excluded, at a
+  // small part of an enclosure's cost
+  {
+    EMag em;
+    if (cnt) ++cnt[2];
+    if (e_magnitude(q, f.R, tt, h.d, Z, L, &em) && !h_may_vote_mag(G, f.K, em.M, h.band)) return 0;
+  }
   bool may = false;
-  // pass -1: both drift signs at once (drift in [-d, d]), where most
-  // excluded pairs end; passes 0 and 1: each sign.  One loop body, kept
-  // rolled, holds the enclosure's registers once.
+  // passes 0 and 1: each drift sign.  One loop body, kept rolled, holds the
+  // enclosure's registers once.
 #pragma unroll 1
-  for (int si = -1; si < 2; ++si) {
-    const Iv DS = si < 0 ? Iv{-h.d, h.d} : ipt(si == 0 ? h.d : -h.d);
+  for (int si = 0; si < 2; ++si) {
+    const Iv DS = ipt(si == 0 ? h.d : -h.d);
     Iv E, EPS, DISC, A;
     const bool ok = e_enclosure_dom(q, f.R, f.sig, tt, t2, DS, Z, L, &E, &EPS, &DISC, &A);
     if (cnt) ++cnt[0];
-    const bool try_incl = si >= 0 && ok && DISC.lo > 0.25 * A.lo * A.lo && A.lo > 0.0;
+    const bool try_incl = ok && DISC.lo > 0.25 * A.lo * A.lo && A.lo > 0.0;
     if (cnt && try_incl) ++cnt[1];
     if (try_incl && votes_everywhere(G, f.K, E.lo, E.hi, h.band)) return 1;
     bool in = true;                      // the test cannot be excluded on this pass
@@ -383,11 +442,7 @@ IA_HD int triple_vote_class(const PairQ& q, const Frame& f, const HitRec& h, Iv 
       const Iv Hb = isub(itwice(G), iadd(itwice(Eb), imul(f.K, isqr(Eb))));
       in = Hb.lo <= 0.0 && 0.0 <= Hb.hi;
     }
-    if (si < 0) {
-      if (!in) return 0;
-    } else if (in) {
-      may = true;
-    }
+    may = may || in;
   }
   return may ? 2 : 0;
 }
@@ -490,16 +545,28 @@ IA_HD int triple_vote_class32(const PairQ& q, const Frame& f, const HitRec& h, I
   const float bs = wup32(ru32(h.band) + slack32);
   const float bs2 = wup32(ru32(h.band) + 2.0f * slack32);
   const double tt = h.tant, t2 = tt * tt;
+  // magnitude bound first (as in triple_vote_class); the exclusion also needs
+  // every box inside the FP32 domain
+  {
+    EMag em;
+    if (cnt) ++cnt[2];
+    if (e_magnitude(q, f.R, tt, h.d, Z, L, &em) && em.eps <= 0.99 && em.disc_lo > 1e-3 * em.a_hi * em.a_hi) {
+      const float m32 = ru32(em.M);
+      const Iv32 Eb = {wdn32(-m32 - bs2), wup32(m32 + bs2)};
+      const Iv32 Hb = isub32(itwice32(G), iadd32(itwice32(Eb), imul32(K, isqr32(Eb))));
+      if (!(Hb.lo <= 0.0f && 0.0f <= Hb.hi)) return 0;
+    }
+  }
   bool may = false;
-  // pass -1: both drift signs at once; passes 0 and 1: each sign (one
-  // rolled loop body, as in triple_vote_class)
+  // passes 0 and 1: each drift sign (one rolled loop body, as in
+  // triple_vote_class)
 #pragma unroll 1
-  for (int si = -1; si < 2; ++si) {
-    const Iv DS = si < 0 ? Iv{-h.d, h.d} : ipt(si == 0 ? h.d : -h.d);
+  for (int si = 0; si < 2; ++si) {
+    const Iv DS = ipt(si == 0 ? h.d : -h.d);
     Iv E, EPS, DISC, A;
     const bool ok = e_enclosure_dom(q, f.R, f.sig, tt, t2, DS, Z, L, &E, &EPS, &DISC, &A);
     if (cnt) ++cnt[0];
-    const bool try_incl = si >= 0 && ok && DISC.lo > 0.25 * A.lo * A.lo && A.lo > 0.0;
+    const bool try_incl = ok && DISC.lo > 0.25 * A.lo * A.lo && A.lo > 0.0;
     if (cnt && try_incl) ++cnt[1];
     if (try_incl && votes_everywhere(Iv{G.lo, G.hi}, Iv{K.lo, K.hi}, wdn(E.lo - slack32), wup(E.hi + slack32), bs))
       return 1;
@@ -511,11 +578,7 @@ IA_HD int triple_vote_class32(const PairQ& q, const Frame& f, const HitRec& h, I
       const Iv32 Hb = isub32(itwice32(G), iadd32(itwice32(Eb), imul32(K, isqr32(Eb))));
       in = Hb.lo <= 0.0f && 0.0f <= Hb.hi;
     }
-    if (si < 0) {
-      if (!in) return 0;
-    } else if (in) {
-      may = true;
-    }
+    may = may || in;
   }
   return may ? 2 : 0;
 }

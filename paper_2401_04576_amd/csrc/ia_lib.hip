@@ -640,7 +640,7 @@ ia_status ia_ctx_work(ia_ctx* c, int64_t* stereo_box_evals, int64_t* staged_pair
   return IA_OK;
 }
 
-ia_status ia_ctx_classify_work(ia_ctx* c, int64_t counts[10]) {
+ia_status ia_ctx_classify_work(ia_ctx* c, int64_t counts[12]) {
   if (!c || !counts) return IA_ERR_INVALID;
   IA_HIP(c, hipSetDevice(c->device));
   IA_HIP(c, hipDeviceSynchronize());

@@ -37,8 +37,22 @@ def lib():
         L.hc_vote_level.restype = C.c_int32
         L.hc_vote_level.argtypes = [P, C.c_int32, P, C.c_int32, P, C.c_int32, C.c_int32, C.c_double, C.c_int32,
                                     C.c_int32, P, P]
+        L.hc_e_magnitude.restype = C.c_int32
+        L.hc_e_magnitude.argtypes = [P, P, P, C.c_uint32, P]
         _lib = L
     return _lib
+
+
+def e_magnitude(hit, parent, split, tc):
+    """(status, M, eps bound, discriminant bound) of the magnitude bound of
+    d^Ax for one stereo hit over triple tc of `parent` split by `split`."""
+    h = np.ascontiguousarray(np.atleast_1d(hit)).view(np.float64).reshape(-1, 8)[0].copy()
+    p = np.atleast_1d(parent)
+    pa = np.ascontiguousarray(np.concatenate([p["lo"], p["hi"]], axis=1)[0], dtype=np.float64)
+    sp = np.ascontiguousarray(split, dtype=np.int32)
+    out = np.zeros(3)
+    rc = lib().hc_e_magnitude(h.ctypes.data, pa.ctypes.data, sp.ctypes.data, int(tc), out.ctypes.data)
+    return int(rc), float(out[0]), float(out[1]), float(out[2])
 
 
 def vote_level(hits, parents, split, filter_on, f32=False, slack=1e-6, prune_k=0, parent_filter=False):

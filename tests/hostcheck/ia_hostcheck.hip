@@ -162,3 +162,32 @@ int32_t hc_vote_level(const double* hits, int32_t n_hits, const double* parents,
 }
 
 }  // extern "C"
+
+extern "C" {
+
+// magnitude bound of d^Ax (e_magnitude) for stereo hit `hit` over triple tc
+// of parent `parent` split by `split`: returns 1 and writes M, the eps bound
+// and the discriminant lower bound to out[0..2]; 0 when no bound exists;
+// -1 for an axial or invalid hit
+int32_t hc_e_magnitude(const double* hit, const double* parent, const int32_t split[5], uint32_t tc,
+                       double* out) {
+  Shape sh;
+  if (!make_shape(split, 1, &sh)) return -1;
+  HitRec h;
+  bool bad;
+  prep_one(hit, true, &h, &bad);
+  if (!h.use || h.axial) return -1;
+  const BoxD& P = *reinterpret_cast<const BoxD*>(parent);
+  const Frame f = triple_frame(P, sh.m, tc / sh.m12, (tc / sh.m[2]) % sh.m[1], tc % sh.m[2]);
+  Iv Z, L;
+  centre_ranges(P, sh.m, &Z, &L);
+  const PairQ q = pair_quantities(f, h, residual_G(f, h));
+  EMag em;
+  if (!e_magnitude(q, f.R, h.tant, h.d, Z, L, &em)) return 0;
+  out[0] = em.M;
+  out[1] = em.eps;
+  out[2] = em.disc_lo;
+  return 1;
+}
+
+}  // extern "C"

@@ -337,9 +337,10 @@ def test_parent_filter_does_not_change_results(ctx):
 def test_classification_counters_and_timing(ctx):
     """The classification's work counters and the per-kernel timing record
     of one ia_vote_level call: one residual G per (triple, used hit), one
-    axial test per axial pair, one set of pair quantities per stereo pair,
-    one to three enclosures per stereo pair and at most two inclusion
-    proofs; one timed launch each of the classification and the vote."""
+    axial test per axial pair, one set of pair quantities and one magnitude
+    bound per stereo pair, at most two enclosures and as many inclusion
+    proofs per stereo pair; one timed launch each of the classification and
+    the vote."""
     torch = _torch()
     ev = toymc.config_event(2, 3)
     prep = oracle.prep_hits(ev.hits)
@@ -365,7 +366,7 @@ def test_classification_counters_and_timing(ctx):
     assert cw["G"] == n_tr * (n_ax + n_st)
     assert cw["axial"] == n_tr * n_ax
     assert cw["pairq"] == n_tr * n_st
-    assert cw["pairq"] <= cw["enclosures"] <= 3 * cw["pairq"]
-    assert cw["inclusions"] <= 2 * cw["pairq"]
+    assert cw["magnitudes"] == cw["pairq"]
+    assert cw["enclosures"] <= 2 * cw["pairq"] and cw["inclusions"] <= cw["enclosures"]
     assert np.array_equal(v.cpu().numpy().astype(np.uint16),
                           oracle.vote_level(ev.hits, root, split))

@@ -146,3 +146,42 @@ def test_parent_exclusion_sound(orc, cfg, ev_i, split, f32):
     ti_r, tv_r = _topk(ref, 32)
     ti_g, tv_g = _topk(got_p, 32)
     assert np.array_equal(ti_r, ti_g) and np.array_equal(tv_r, tv_g)
+
+
+@pytest.mark.parametrize("cfg,ev_i", [(2, 1), (4, 7), (5, 4)])
+def test_magnitude_bound_contains_point_drift(orc, cfg, ev_i):
+    """The magnitude bound M of d^Ax over a triple (the classification's
+    cheap exclusion) holds the oracle's own point evaluation: |e| <= M at the
+    box centres of sampled triples (corners of the (z0, tanl) grid and random
+    boxes), both drift signs, at level 0 and on refinement parents; the bound
+    exists for almost every pair."""
+    ev = toymc.config_event(cfg, ev_i)
+    prep = orc.prep_hits(ev.hits)
+    stereo = np.flatnonzero((prep["valid"] == 1) & (prep["axial"] == 0))
+    root = orc.make_box(H.LO, H.HI)
+    rng = np.random.default_rng(cfg * 100 + ev_i)
+    v0 = orc.vote_level(ev.hits, root, [12] * 5)
+    top, _ = _topk(v0, 8)
+    cases = [(root, [12] * 5)] + [(orc.box_child(root, [12] * 5, int(b)), [4, 3, 5, 4, 4]) for b in top[:3]]
+    n_pairs = n_bound = n_checked = 0
+    for parent, split in cases:
+        m012, m34 = int(np.prod(split[:3])), split[3] * split[4]
+        corners = [0, split[4] - 1, m34 - split[4], m34 - 1]
+        for tc in rng.choice(m012, size=min(m012, 12), replace=False):
+            for hi in stereo:
+                rc, M, _, _ = hostcheck.e_magnitude(ev.hits[hi], parent, split, tc)
+                assert rc >= 0
+                n_pairs += 1
+                if rc == 0:
+                    continue
+                n_bound += 1
+                for j in corners + list(rng.integers(0, m34, size=4)):
+                    box = orc.box_child(parent, split, int(tc) * m34 + int(j))
+                    c = 0.5 * (box["lo"] + box["hi"]).ravel()
+                    for s in (1, -1):
+                        ok, e = orc.stereo_e(prep[hi], c, s)
+                        if ok:
+                            n_checked += 1
+                            assert abs(e) <= M, (tc, hi, j, s, e, M)
+    assert n_bound >= 0.95 * n_pairs
+    assert n_checked > 1000
