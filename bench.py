@@ -76,8 +76,10 @@ FLOP_BOX_STEREO32 = 278
 #  - one interval enclosure of d^Ax over the triple's (z0, tanl) centres with
 #    its exclusion test (the FP32 levels' test counted as FP64 too): 688;
 #  - one inclusion proof (bounds at the enclosure's ends): 94;
-#  - one magnitude bound of d^Ax over the triple (67) with its exclusion test (46): 113.
+#  - one magnitude bound of d^Ax over the triple (67) with its exclusion test (46): 113;
+#  - a deferred pair's triple frame and (z0, tanl) centre ranges: 130.
 FLOP_CLS_G, FLOP_CLS_AXIAL, FLOP_CLS_PAIRQ, FLOP_CLS_ENCL, FLOP_CLS_INCL, FLOP_CLS_MAG = 157, 92, 69, 688, 94, 113
+FLOP_CLS_FRAME = 130
 PEAK_FP64_TFLOPS = 78.6   # MI355X vector FP64: 256 CU x 128 FLOP/clk x 2.4 GHz
 # HBM bytes per launch of the FP64 classification over 1024-event batches of
 # the default workload: rocprofv3 --pmc FETCH_SIZE, then WRITE_SIZE, averaged
@@ -119,9 +121,15 @@ def classify_traffic(workload, events_per_step):
 
 
 def classify_flops(cw):
+    """FP64 flops of the first classification stage."""
     return (cw["G"] * FLOP_CLS_G + cw["axial"] * FLOP_CLS_AXIAL + cw["pairq"] * FLOP_CLS_PAIRQ
-            + cw["enclosures"] * FLOP_CLS_ENCL + cw["inclusions"] * FLOP_CLS_INCL
             + cw["magnitudes"] * FLOP_CLS_MAG)
+
+
+def defer_flops(cw):
+    """FP64 flops of the second classification stage."""
+    return (cw["deferred"] * (FLOP_CLS_FRAME + FLOP_CLS_G + FLOP_CLS_PAIRQ)
+            + cw["enclosures"] * FLOP_CLS_ENCL + cw["inclusions"] * FLOP_CLS_INCL)
 
 
 def roofline(kprof, work, cwork, wall, measured_on, traffic_classify=None):
@@ -147,12 +155,13 @@ def roofline(kprof, work, cwork, wall, measured_on, traffic_classify=None):
             "launches": n, "total_ms": ms, "stereo_box_evals": e32, "staged_pairs": s32,
             "staged_fp64_tflops": s32 * FLOP_TRIPLE_HIT / (ms * 1e-3) / 1e12}
     for p in ("fp64", "fp32"):
-        n, ms = kprof[("classify", p)]
-        if n:
-            a = classify_flops(cwork[p]) / (ms * 1e-3) / 1e12
-            parts[f"k_classify ({p} levels)"] = {
-                "achieved": a, "peak": PEAK_FP64_TFLOPS, "frac": a / PEAK_FP64_TFLOPS, "avg_launch_ms": ms / n,
-                "launches": n, "total_ms": ms, **cwork[p]}
+        for kern, fl in (("classify", classify_flops), ("classify_defer", defer_flops)):
+            n, ms = kprof[(kern, p)]
+            if n:
+                a = fl(cwork[p]) / (ms * 1e-3) / 1e12
+                parts[f"k_{kern} ({p} levels)"] = {
+                    "achieved": a, "peak": PEAK_FP64_TFLOPS, "frac": a / PEAK_FP64_TFLOPS, "avg_launch_ms": ms / n,
+                    "launches": n, "total_ms": ms, **cwork[p]}
     dom = max(parts, key=lambda k: parts[k]["total_ms"])
     d = parts[dom]
     traffic = traffic_classify if dom == "k_classify (fp64 levels)" else None

@@ -138,18 +138,20 @@ ia_status ia_ctx_set_profiling(ia_ctx *ctx, int32_t enable);
 ia_status ia_ctx_profile_read(ia_ctx *ctx, int64_t *n_launches, double *total_ms,
                               int64_t *n_launches_fp32, double *total_ms_fp32);
 
-/* Kernels bracketed while profiling is enabled: the vote kernel and the
- * (triple, hit) classification (Sec. 3.3's exclusion test over a triple's
- * boxes, run before the per-box vote). */
-enum { IA_KERNEL_VOTE = 0, IA_KERNEL_CLASSIFY = 1 };
+/* Kernels bracketed while profiling is enabled: the vote kernel and the two
+ * stages of the (triple, hit) classification run before it (the interval
+ * test of Eq. ApoVote over all boxes of a triple): the first decides the
+ * pairs its cheap tests can, the second runs the per-sign enclosures of
+ * d^Ax on the stereo pairs left over. */
+enum { IA_KERNEL_VOTE = 0, IA_KERNEL_CLASSIFY = 1, IA_KERNEL_CLASSIFY_DEFER = 2 };
 
 /* Every bracketed launch: n_launches[2 k + p] and total_ms[2 k + p] for
  * kernel k (IA_KERNEL_*) at precision p (0 FP64 levels, 1 FP32 levels).
  * Synchronises on the recorded events and clears the record (as
  * ia_ctx_profile_read, which returns the vote kernel's entries of it).
- * Both arrays are host memory of 4 entries; IA_ERR_INVALID if either is
+ * Both arrays are host memory of 6 entries; IA_ERR_INVALID if either is
  * NULL. */
-ia_status ia_ctx_profile_kernels(ia_ctx *ctx, int64_t n_launches[4], double total_ms[4]);
+ia_status ia_ctx_profile_kernels(ia_ctx *ctx, int64_t n_launches[6], double total_ms[6]);
 
 /* Counting of the classification kernel's work (off by default): while
  * enabled, the classification runs a variant that adds its work to the
@@ -157,16 +159,17 @@ ia_status ia_ctx_profile_kernels(ia_ctx *ctx, int64_t n_launches[4], double tota
  * not depend on it. */
 ia_status ia_ctx_set_work_counting(ia_ctx *ctx, int32_t enable);
 
-/* Work of the classification kernel, counted while work counting was
- * enabled, since the last ia_ctx_clear_status:
- * counts[6 p + c] at precision p (0 FP64 levels, 1 FP32 levels) for
- * c = 0 residual intervals G (Eq. ApoVote over a triple), 1 axial tests,
- * 2 stereo pair quantities, 3 interval enclosures of d^Ax (each with its
- * exclusion test), 4 inclusion proofs, 5 magnitude bounds of d^Ax (each
- * with its exclusion test).  Only pairs of live triples are counted; pairs
- * the parent-level test excluded are not.  Synchronises the device.
- * counts is host memory of 12 entries. */
-ia_status ia_ctx_classify_work(ia_ctx *ctx, int64_t counts[12]);
+/* Work of the two classification stages, counted while work counting was
+ * enabled, since the last ia_ctx_clear_status: counts[7 p + c] at precision
+ * p (0 FP64 levels, 1 FP32 levels).  First stage: c = 0 residual intervals
+ * G (Eq. ApoVote over a triple), 1 axial tests, 2 stereo pair quantities,
+ * 3 magnitude bounds of d^Ax (each with its exclusion test).  Second stage:
+ * c = 4 deferred pairs (each with its triple's frame, G and pair quantities
+ * again), 5 interval enclosures of d^Ax (each with its exclusion test),
+ * 6 inclusion proofs.  Only pairs of live triples are counted; pairs the
+ * parent-level test excluded are not.  Synchronises the device.  counts is
+ * host memory of 14 entries. */
+ia_status ia_ctx_classify_work(ia_ctx *ctx, int64_t counts[14]);
 
 /* Band widening used by ia_vote_level at IA_FP32 (default 1e-6 m; ia_find_helices
  * takes it from the schedule).  IA_ERR_INVALID outside [0, 1e-3]. */

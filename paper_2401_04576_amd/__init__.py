@@ -210,11 +210,12 @@ class Context:
     def classify_work(self):
         """Classification work counted (set_work_counting) since the last clear_status(): {"fp64": {...},
         "fp32": {...}} with counts of residuals G, axial tests, stereo pair
-        quantities, d^Ax enclosures, inclusion proofs and magnitude bounds."""
-        a = (C.c_int64 * 12)()
+        quantities and magnitude bounds (first stage), and deferred pairs,
+        d^Ax enclosures and inclusion proofs (second stage)."""
+        a = (C.c_int64 * 14)()
         self._check(self._L.ia_ctx_classify_work(self._h, a))
-        keys = ("G", "axial", "pairq", "enclosures", "inclusions", "magnitudes")
-        return {p: {k: int(a[6 * i + j]) for j, k in enumerate(keys)} for i, p in enumerate(("fp64", "fp32"))}
+        keys = ("G", "axial", "pairq", "magnitudes", "deferred", "enclosures", "inclusions")
+        return {p: {k: int(a[7 * i + j]) for j, k in enumerate(keys)} for i, p in enumerate(("fp64", "fp32"))}
 
     def set_fp32_slack(self, slack=1e-6):
         """Band widening of vote_level at FP32 (m)."""
@@ -270,13 +271,14 @@ class Context:
         return int(n.value), float(ms.value), int(n32.value), float(ms32.value)
 
     def profile_kernels(self):
-        """{(kernel, prec): (launches, ms)} for kernel in ("vote", "classify")
-        and prec in ("fp64", "fp32"), since the last read (clears the record)."""
-        n = (C.c_int64 * 4)()
-        ms = (C.c_double * 4)()
+        """{(kernel, prec): (launches, ms)} for kernel in ("vote", "classify",
+        "classify_defer") and prec in ("fp64", "fp32"), since the last read
+        (clears the record)."""
+        n = (C.c_int64 * 6)()
+        ms = (C.c_double * 6)()
         self._check(self._L.ia_ctx_profile_kernels(self._h, n, ms))
         return {(k, p): (int(n[2 * i + j]), float(ms[2 * i + j]))
-                for i, k in enumerate(("vote", "classify")) for j, p in enumerate(("fp64", "fp32"))}
+                for i, k in enumerate(("vote", "classify", "classify_defer")) for j, p in enumerate(("fp64", "fp32"))}
 
     def close(self):
         if getattr(self, "_h", None):

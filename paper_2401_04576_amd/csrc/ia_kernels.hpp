@@ -58,7 +58,7 @@ struct EventState {
   int32_t n_live_tri;           // triples of the current level whose class-2 pairs are evaluated
   int32_t n_rec;                // their class-2 pairs (staged records)
   int32_t rec_ok;               // 1: the records fit the record buffer (else the in-kernel staging runs)
-  int32_t pad;
+  int32_t t_cut;                // triples after this one with upper bound == t_prune are pruned too
   double p[5], err[5];          // last estimate
 };
 
@@ -91,12 +91,15 @@ enum : uint32_t { kStBadHit = 1u, kStVoteOverflow = 2u, kStBadOffsets = 4u };
 // work counters: kWorkSlots slots of 16 u64 (one 128-byte line each);
 // counters 0..3 of a slot: stereo (box, hit) evaluations and staged (triple,
 // hit) pairs at FP64 levels, the same two at FP32 levels (vote kernels);
-// counters kWorkClassify + 6 p + c: classification work at precision p
-// (0 FP64, 1 FP32), c = kCw* below
+// counters kWorkClassify + kCwN p + c: classification work at precision p
+// (0 FP64, 1 FP32), c = kCw* below (the first four from k_classify, the
+// last three from k_classify_defer)
 constexpr uint32_t kWorkSlots = 64;
-constexpr uint32_t kWorkSlotU64 = 16;
+constexpr uint32_t kWorkSlotU64 = 32;
 constexpr uint32_t kWorkClassify = 4;
-enum : uint32_t { kCwG = 0, kCwAxial = 1, kCwPairQ = 2, kCwPass = 3, kCwIncl = 4, kCwMag = 5, kCwN = 6 };
+enum : uint32_t { kCwG = 0, kCwAxial = 1, kCwPairQ = 2, kCwMag = 3, kCwDefer = 4, kCwPass = 5, kCwIncl = 6, kCwN = 7 };
+// class flag of a stereo pair whose class k_classify left to k_classify_defer
+constexpr uint8_t kFlagDeferred = 3;
 
 // ---------------------------------------------------------------------------
 // edges of child k of [L, U] split m ways
@@ -412,18 +415,21 @@ IA_HD bool h_may_vote_mag(Iv G, Iv K, double M, double band) {
 // a well-conditioned point evaluation everywhere on the rectangle (the
 // discriminant of d^Ax above A^2 / 4) and the inclusion proof above over
 // the enclosure of e.
-// With `cnt` set, cnt[0] counts the enclosure passes, cnt[1] the inclusion
-// proofs and cnt[2] the magnitude bounds evaluated.
-IA_HD int triple_vote_class(const PairQ& q, const Frame& f, const HitRec& h, Iv Z, Iv L, int32_t* cnt = nullptr) {
+// The class is decided in two stages: stereo_quick_class (the magnitude
+// bound of e, which excludes most pairs that can be excluded at a small part
+// of an enclosure's cost; 0 or -1 for undecided) and stereo_pass_class (the
+// enclosure per drift sign).  With `cnt` set, cnt[0] counts the enclosure
+// passes and cnt[1] the inclusion proofs evaluated.
+IA_HD int stereo_quick_class(const PairQ& q, const Frame& f, const HitRec& h, Iv Z, Iv L) {
+  EMag em;
+  if (e_magnitude(q, f.R, h.tant, h.d, Z, L, &em) && !h_may_vote_mag(Iv{q.Glo, q.Ghi}, f.K, em.M, h.band))
+    return 0;
+  return -1;
+}
+
+IA_HD int stereo_pass_class(const PairQ& q, const Frame& f, const HitRec& h, Iv Z, Iv L, int32_t* cnt = nullptr) {
   const Iv G = {q.Glo, q.Ghi};
   const double tt = h.tant, t2 = tt * tt;
-  // the magnitude bound of e excludes most pairs that can be excluded, at a
-  // small part of an enclosure's cost
-  {
-    EMag em;
-    if (cnt) ++cnt[2];
-    if (e_magnitude(q, f.R, tt, h.d, Z, L, &em) && !h_may_vote_mag(G, f.K, em.M, h.band)) return 0;
-  }
   bool may = false;
   // passes 0 and 1: each drift sign.  One loop body, kept rolled, holds the
   // enclosure's registers once.
@@ -445,6 +451,11 @@ IA_HD int triple_vote_class(const PairQ& q, const Frame& f, const HitRec& h, Iv 
     may = may || in;
   }
   return may ? 2 : 0;
+}
+
+IA_HD int triple_vote_class(const PairQ& q, const Frame& f, const HitRec& h, Iv Z, Iv L, int32_t* cnt = nullptr) {
+  const int c = stereo_quick_class(q, f, h, Z, L);
+  return c >= 0 ? c : stereo_pass_class(q, f, h, Z, L, cnt);
 }
 
 // false only when no box of the triple can get this stereo hit's vote
@@ -537,26 +548,31 @@ IA_HD bool stereo_vote32(const PairQ32& q, float R, float sig, Iv32 K, float z0,
 // votes_everywhere holds for FP32 outward rounding as well; it is applied to
 // the FP32 G, K and band (exact in FP64) over [E1 - slack, E2 + slack],
 // which holds every box's e32 (a box outside the FP32 domain votes anyway).
-IA_HD int triple_vote_class32(const PairQ& q, const Frame& f, const HitRec& h, Iv Z, Iv L, float slack32,
-                              int32_t* cnt = nullptr) {
+// Two stages as at FP64 levels; the quick stage also gives class 1 to a
+// triple outside the FP32 domain, and its exclusion needs every box inside
+// the domain.
+IA_HD int stereo_quick_class32(const PairQ& q, const Frame& f, const HitRec& h, Iv Z, Iv L, float slack32) {
   if (!(f.R <= kR32Max)) return 1;
+  EMag em;
+  if (e_magnitude(q, f.R, h.tant, h.d, Z, L, &em) && em.eps <= 0.99 && em.disc_lo > 1e-3 * em.a_hi * em.a_hi) {
+    const Iv32 G = to32(Iv{q.Glo, q.Ghi});
+    const Iv32 K = to32(f.K);
+    const float bs2 = wup32(ru32(h.band) + 2.0f * slack32);
+    const float m32 = ru32(em.M);
+    const Iv32 Eb = {wdn32(-m32 - bs2), wup32(m32 + bs2)};
+    const Iv32 Hb = isub32(itwice32(G), iadd32(itwice32(Eb), imul32(K, isqr32(Eb))));
+    if (!(Hb.lo <= 0.0f && 0.0f <= Hb.hi)) return 0;
+  }
+  return -1;
+}
+
+IA_HD int stereo_pass_class32(const PairQ& q, const Frame& f, const HitRec& h, Iv Z, Iv L, float slack32,
+                              int32_t* cnt = nullptr) {
   const Iv32 G = to32(Iv{q.Glo, q.Ghi});
   const Iv32 K = to32(f.K);
   const float bs = wup32(ru32(h.band) + slack32);
   const float bs2 = wup32(ru32(h.band) + 2.0f * slack32);
   const double tt = h.tant, t2 = tt * tt;
-  // magnitude bound first (as in triple_vote_class); the exclusion also needs
-  // every box inside the FP32 domain
-  {
-    EMag em;
-    if (cnt) ++cnt[2];
-    if (e_magnitude(q, f.R, tt, h.d, Z, L, &em) && em.eps <= 0.99 && em.disc_lo > 1e-3 * em.a_hi * em.a_hi) {
-      const float m32 = ru32(em.M);
-      const Iv32 Eb = {wdn32(-m32 - bs2), wup32(m32 + bs2)};
-      const Iv32 Hb = isub32(itwice32(G), iadd32(itwice32(Eb), imul32(K, isqr32(Eb))));
-      if (!(Hb.lo <= 0.0f && 0.0f <= Hb.hi)) return 0;
-    }
-  }
   bool may = false;
   // passes 0 and 1: each drift sign (one rolled loop body, as in
   // triple_vote_class)
@@ -581,6 +597,12 @@ IA_HD int triple_vote_class32(const PairQ& q, const Frame& f, const HitRec& h, I
     may = may || in;
   }
   return may ? 2 : 0;
+}
+
+IA_HD int triple_vote_class32(const PairQ& q, const Frame& f, const HitRec& h, Iv Z, Iv L, float slack32,
+                              int32_t* cnt = nullptr) {
+  const int c = stereo_quick_class32(q, f, h, Z, L, slack32);
+  return c >= 0 ? c : stereo_pass_class32(q, f, h, Z, L, slack32, cnt);
 }
 
 // (z0, tanl) centre ranges of the boxes of one parent
@@ -773,6 +795,7 @@ __global__ void k_prep(const double* __restrict__ hits, const uint8_t* __restric
                                           static_cast<int64_t>(beg) + n_hits > vw.n_total);
   if (ev && i == 0) {
     EventState es{};
+    es.t_cut = INT32_MAX;
     if (bad_ev) {
       es.done = 1;
       atomicOr(status, kStBadOffsets);
@@ -880,10 +903,14 @@ __device__ __forceinline__ int32_t block_sum(int32_t v, int32_t* sbuf) {
 // group z takes hits 4 z + w, 4 z + w + 4 gridDim.z, ...), so the hit of a
 // wave is uniform (axial and stereo work do not diverge) and each thread
 // computes its triple frame once.  flags are hit-major: flags[h * n_tr + t].
+// A stereo pair the quick stage leaves undecided gets kFlagDeferred and is
+// classified by k_classify_defer, which must run next: the enclosure passes
+// run there on compacted pairs, so that the lanes of a wave whose pairs were
+// decided here do not wait for them.
 // With COUNT, the work done (residuals G, axial tests, pair quantities,
-// enclosure passes, inclusion proofs; live triples only) is added to `work`
-// with one atomic per counter per workgroup (a separate instantiation: the
-// counting costs the search a few per cent).
+// magnitude bounds; live triples only) is added to `work` with one atomic
+// per counter per workgroup (a separate instantiation: the counting costs
+// the search a few per cent).
 template <bool F32, bool COUNT>
 __global__ void __launch_bounds__(kWG) k_classify(const HitRec* __restrict__ hits, EvView vw,
                                                   const BoxD* __restrict__ parents, Shape sh,
@@ -913,7 +940,7 @@ __global__ void __launch_bounds__(kWG) k_classify(const HitRec* __restrict__ hit
   Iv Zr, Lr;
   centre_ranges(TP, sh.m, &Zr, &Lr);
   int32_t lb = 0, n2 = 0;
-  int32_t cw[kCwN] = {0, 0, 0, 0, 0};
+  int32_t cw[kCwDefer] = {0, 0, 0, 0};
   const int32_t h_step = static_cast<int32_t>(gridDim.z) * (kWG / 64);
   for (int32_t h = static_cast<int32_t>(blockIdx.z) * (kWG / 64) + wave; h < n_hits; h += h_step) {
     const HitRec hr = hits[h];
@@ -930,10 +957,9 @@ __global__ void __launch_bounds__(kWG) k_classify(const HitRec* __restrict__ hit
         fl = 2;
       } else {
         const PairQ q = pair_quantities(f, hr, G);
-        if constexpr (COUNT) ++cw[kCwPairQ];
-        int32_t* pc = COUNT ? &cw[kCwPass] : nullptr;
-        fl = static_cast<uint8_t>(F32 ? triple_vote_class32(q, f, hr, Zr, Lr, slack32, pc)
-                                      : triple_vote_class(q, f, hr, Zr, Lr, pc));
+        if constexpr (COUNT) { ++cw[kCwPairQ]; ++cw[kCwMag]; }
+        const int c = F32 ? stereo_quick_class32(q, f, hr, Zr, Lr, slack32) : stereo_quick_class(q, f, hr, Zr, Lr);
+        fl = c >= 0 ? static_cast<uint8_t>(c) : kFlagDeferred;
       }
     }
     if (live) flags[int64_t(h) * n_tr + t] = fl;
@@ -941,13 +967,13 @@ __global__ void __launch_bounds__(kWG) k_classify(const HitRec* __restrict__ hit
     n2 += fl == 2 ? 1 : 0;
   }
   __shared__ int32_t s_lb[kWG / 64][64], s_n2[kWG / 64][64];
-  __shared__ unsigned long long s_cw[kCwN];
-  if (COUNT && threadIdx.x < kCwN) s_cw[threadIdx.x] = 0;
+  __shared__ unsigned long long s_cw[kCwDefer];
+  if (COUNT && threadIdx.x < kCwDefer) s_cw[threadIdx.x] = 0;
   s_lb[wave][lane] = lb;
   s_n2[wave][lane] = n2;
   __syncthreads();
   if (COUNT && live)
-    for (uint32_t k = 0; k < kCwN; ++k)
+    for (uint32_t k = 0; k < kCwDefer; ++k)
       if (cw[k]) atomicAdd(&s_cw[k], static_cast<unsigned long long>(cw[k]));
   if (wave == 0 && live) {
     int32_t a = 0, b = 0;
@@ -957,10 +983,90 @@ __global__ void __launch_bounds__(kWG) k_classify(const HitRec* __restrict__ hit
   }
   if constexpr (COUNT) {
     __syncthreads();
-    if (threadIdx.x < kCwN && s_cw[threadIdx.x]) {
+    if (threadIdx.x < kCwDefer && s_cw[threadIdx.x]) {
       unsigned long long* slot =
           work + kWorkSlotU64 * ((blockIdx.x + blockIdx.y * 7u + blockIdx.z * 13u) % kWorkSlots);
       atomicAdd(&slot[kWorkClassify + (F32 ? kCwN : 0) + threadIdx.x], s_cw[threadIdx.x]);
+    }
+  }
+}
+
+// Second stage of the classification: the stereo pairs k_classify deferred.
+// A workgroup takes kDeferChunk consecutive flags of one event (thread i
+// reads flags i, i + kWG, ...), lists the deferred ones in LDS with a block
+// scan, and the whole workgroup then works through the list, one pair per
+// lane: the triple's frame, G and the pair quantities (the same functions
+// and inputs as in k_classify, hence the same values), then the per-sign
+// enclosure passes; it writes the class and adds class-1 and class-2 pairs
+// to the triple's bounds.
+constexpr int32_t kDeferChunk = 4096;
+
+template <bool F32, bool COUNT>
+__global__ void __launch_bounds__(kWG) k_classify_defer(const HitRec* __restrict__ hits, EvView vw,
+                                                        const BoxD* __restrict__ parents, Shape sh,
+                                                        uint8_t* __restrict__ flags, int32_t* __restrict__ tlb,
+                                                        int32_t* __restrict__ tn2,
+                                                        const EventState* __restrict__ ev, float slack32,
+                                                        unsigned long long* __restrict__ work) {
+  const int e = blockIdx.y;
+  if (ev && ev[e].done) return;
+  const int32_t n_hits = vw.count(e);
+  const uint32_t n_tr = sh.n_parents * sh.m012;
+  const int64_t n_pairs = static_cast<int64_t>(n_tr) * (n_hits > 0 ? n_hits : 0);
+  const int64_t c0 = static_cast<int64_t>(blockIdx.x) * kDeferChunk;
+  if (c0 >= n_pairs) return;
+  hits += vw.beg(e);
+  parents += e * vw.par_stride;
+  flags += e * vw.flag_stride;
+  tlb += e * vw.tri_stride;
+  tn2 += e * vw.tri_stride;
+  __shared__ uint16_t s_list[kDeferChunk];
+  __shared__ int32_t s_scan[kWG];
+  constexpr int kPer = kDeferChunk / kWG;
+  uint32_t mask = 0;
+  int32_t mine = 0;
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) {
+    const int64_t p = c0 + k * kWG + threadIdx.x;
+    const bool d = p < n_pairs && flags[p] == kFlagDeferred;
+    mask |= d ? (1u << k) : 0u;
+    mine += d ? 1 : 0;
+  }
+  int32_t pos;
+  const int32_t total = block_scan_count(mine, &pos, s_scan);
+#pragma unroll
+  for (int k = 0; k < kPer; ++k)
+    if (mask & (1u << k)) s_list[pos++] = static_cast<uint16_t>(k * kWG + threadIdx.x);
+  __syncthreads();
+  int32_t cw[3] = {0, 0, 0};                  // deferred pairs, enclosure passes, inclusion proofs
+  for (int32_t i = threadIdx.x; i < total; i += kWG) {
+    const int64_t p = c0 + s_list[i];
+    const uint32_t h = static_cast<uint32_t>(p / n_tr), t = static_cast<uint32_t>(p % n_tr);
+    const uint32_t tc = t % sh.m012;
+    const BoxD& TP = parents[t / sh.m012];
+    const Frame f = triple_frame(TP, sh.m, tc / sh.m12, (tc / sh.m[2]) % sh.m[1], tc % sh.m[2]);
+    Iv Zr, Lr;
+    centre_ranges(TP, sh.m, &Zr, &Lr);
+    const HitRec hr = hits[h];
+    const PairQ q = pair_quantities(f, hr, residual_G(f, hr));
+    if constexpr (COUNT) ++cw[0];
+    int32_t* pc = COUNT ? &cw[1] : nullptr;
+    const int c = F32 ? stereo_pass_class32(q, f, hr, Zr, Lr, slack32, pc) : stereo_pass_class(q, f, hr, Zr, Lr, pc);
+    flags[p] = static_cast<uint8_t>(c);
+    if (c == 1) atomicAdd(&tlb[t], 1);
+    else if (c == 2) atomicAdd(&tn2[t], 1);
+  }
+  if constexpr (COUNT) {
+    __shared__ unsigned long long s_cw[3];
+    __syncthreads();
+    if (threadIdx.x < 3) s_cw[threadIdx.x] = 0;
+    __syncthreads();
+    for (int k = 0; k < 3; ++k)
+      if (cw[k]) atomicAdd(&s_cw[k], static_cast<unsigned long long>(cw[k]));
+    __syncthreads();
+    if (threadIdx.x < 3 && s_cw[threadIdx.x]) {
+      unsigned long long* slot = work + kWorkSlotU64 * ((blockIdx.x + blockIdx.y * 7u) % kWorkSlots);
+      atomicAdd(&slot[kWorkClassify + (F32 ? kCwN : 0) + kCwDefer + threadIdx.x], s_cw[threadIdx.x]);
     }
   }
 }
@@ -987,6 +1093,14 @@ __global__ void __launch_bounds__(kWG) k_parent_filter(const HitRec* __restrict_
   }
 }
 
+// Is a triple evaluated at a level with pruning threshold T and tie cut
+// tcut?  Its upper bound must reach T; at T exactly, only triples up to tcut
+// (see k_threshold) can hold a selected box.
+IA_HD bool triple_live(int32_t lb, int32_t n2, int32_t T, uint32_t t, int32_t tcut) {
+  const int32_t ub = lb + n2;
+  return ub > T || (ub == T && static_cast<int64_t>(t) <= tcut);
+}
+
 // Pruning threshold of a level, one workgroup per event: T = the largest v
 // such that at least k_eff = min(k, n_boxes) boxes have a lower bound >= v
 // (each triple holds m34 boxes), from the histogram of the triples' lower
@@ -1000,9 +1114,17 @@ __global__ void __launch_bounds__(kWG) k_parent_filter(const HitRec* __restrict_
 // upper bound >= T) are listed too (ev->n_live_tri), each with the offset of
 // its records (rec_off, in index order; rec_fill cleared); ev->rec_ok tells
 // whether all ev->n_rec records fit rec_cap.
+// With `ties` (levels whose only use is the top-k selection and the
+// maximum, not the estimate's max-vote set): let t_cut be the triple, in
+// index order, at which the triples with lower bound >= T first hold k_eff
+// boxes.  Those k_eff boxes have at least T votes and lower indices than any
+// box after t_cut, so a box after t_cut with at most T votes ranks after all
+// of them (votes desc, index asc); a triple after t_cut whose upper bound is
+// T is pruned too.  The maximum is unchanged (it is at least T).
+// ev->t_cut = INT32_MAX without ties.
 __global__ void __launch_bounds__(kWG) k_threshold(const int32_t* __restrict__ tlb, const int32_t* __restrict__ tn2,
                                                    uint32_t* __restrict__ lbh, EvView vw, Shape sh, int32_t k,
-                                                   int32_t prune, int32_t bx, EventState* __restrict__ ev,
+                                                   int32_t prune, int32_t ties, int32_t bx, EventState* __restrict__ ev,
                                                    int32_t* __restrict__ live_list, int32_t* __restrict__ wg_max,
                                                    int32_t* __restrict__ live_tri, int32_t* __restrict__ rec_off,
                                                    int32_t* __restrict__ rec_fill, int64_t rec_cap) {
@@ -1044,6 +1166,30 @@ __global__ void __launch_bounds__(kWG) k_threshold(const int32_t* __restrict__ t
   }
   __syncthreads();
   const int32_t T = s_T;
+  __shared__ int32_t s_cut;
+  if (tid == 0) s_cut = INT32_MAX;
+  __syncthreads();
+  if (prune && ties) {
+    // t_cut: the triple at which the boxes of triples with lower bound >= T
+    // reach k_eff, in index order (contiguous runs of triples per thread)
+    const int64_t k_eff = min(static_cast<int64_t>(k), static_cast<int64_t>(sh.n_boxes));
+    const uint32_t pt = (n_tr + kWG - 1) / kWG;
+    const uint32_t ra = min(tid * pt, n_tr), rb = min(ra + pt, n_tr);
+    int32_t c = 0;
+    for (uint32_t t = ra; t < rb; ++t) c += tlb[t] >= T ? 1 : 0;
+    int32_t before;
+    block_scan_count(c, &before, sbuf);
+    int64_t cum = static_cast<int64_t>(before) * sh.m34;
+    if (cum < k_eff && cum + static_cast<int64_t>(c) * sh.m34 >= k_eff) {
+      for (uint32_t t = ra; t < rb; ++t) {
+        if (tlb[t] < T) continue;
+        cum += sh.m34;
+        if (cum >= k_eff) { s_cut = static_cast<int32_t>(t); break; }
+      }
+    }
+    __syncthreads();
+  }
+  const int32_t tcut = s_cut;
   // live tiles, compacted in index order: each thread takes a contiguous run
   // of tiles, counts its live ones, and one block scan places them
   auto triple_of = [&](uint32_t x) { return (x / sh.nc) * sh.m012 + (x % sh.nc) / sh.m34; };
@@ -1054,7 +1200,7 @@ __global__ void __launch_bounds__(kWG) k_threshold(const int32_t* __restrict__ t
     const uint32_t b0 = tile * static_cast<uint32_t>(bx);
     const uint32_t b1 = min(b0 + static_cast<uint32_t>(bx), sh.n_boxes) - 1;
     bool lv = false;
-    for (uint32_t t = triple_of(b0); t <= triple_of(b1) && !lv; ++t) lv = tlb[t] + tn2[t] >= T;
+    for (uint32_t t = triple_of(b0); t <= triple_of(b1) && !lv; ++t) lv = triple_live(tlb[t], tn2[t], T, t, tcut);
     return lv;
   };
   int32_t mine = 0;
@@ -1076,12 +1222,12 @@ __global__ void __launch_bounds__(kWG) k_threshold(const int32_t* __restrict__ t
     const uint32_t ra = min(tid * pt, n_tr), rb = min(ra + pt, n_tr);
     int32_t c1 = 0, c2 = 0;
     for (uint32_t t = ra; t < rb; ++t)
-      if (tn2[t] > 0 && tlb[t] + tn2[t] >= T) { ++c1; c2 += tn2[t]; }
+      if (tn2[t] > 0 && triple_live(tlb[t], tn2[t], T, t, tcut)) { ++c1; c2 += tn2[t]; }
     int32_t p1, p2;
     n_lt = block_scan_count(c1, &p1, sbuf);
     n_rec = block_scan_count(c2, &p2, sbuf);
     for (uint32_t t = ra; t < rb; ++t)
-      if (tn2[t] > 0 && tlb[t] + tn2[t] >= T) {
+      if (tn2[t] > 0 && triple_live(tlb[t], tn2[t], T, t, tcut)) {
         live_tri[p1++] = static_cast<int32_t>(t);
         rec_off[t] = p2;
         rec_fill[t] = 0;
@@ -1090,6 +1236,7 @@ __global__ void __launch_bounds__(kWG) k_threshold(const int32_t* __restrict__ t
   }
   if (tid == 0) {
     ev[e].t_prune = T;
+    ev[e].t_cut = tcut;
     ev[e].n_live = total;
     ev[e].n_live_tri = n_lt;
     ev[e].n_rec = n_rec;
@@ -1301,6 +1448,7 @@ __global__ void __launch_bounds__(kWG) k_vote(const HitRec* __restrict__ hits, E
   if (wg_max) wg_max += int64_t(e) * vw.wg_stride;
   if (live_list) live_list += int64_t(e) * vw.wg_stride;
   const int32_t T = ev ? ev[e].t_prune : 0;
+  const int32_t tcut = ev ? ev[e].t_cut : INT32_MAX;
   const uint32_t n_tr = sh.n_parents * sh.m012;
   const uint32_t n_tiles = (sh.n_boxes + BX - 1) / BX;
   const uint32_t n_items = live_list ? static_cast<uint32_t>(ev[e].n_live) : n_tiles;
@@ -1339,7 +1487,7 @@ __global__ void __launch_bounds__(kWG) k_vote(const HitRec* __restrict__ hits, E
     int32_t any_live = 0;
     for (int32_t i = tid; i < nt; i += kWG) {
       const int32_t a = tlb[t_first + i], c = tn2[t_first + i];
-      const bool lv = c > 0 && a + c >= T;
+      const bool lv = c > 0 && triple_live(a, c, T, t_first + i, tcut);
       stlive[i] = lv ? 1 : 0;
       any_live |= lv ? 1 : 0;
     }
@@ -1509,6 +1657,7 @@ __global__ void __launch_bounds__(kWG) k_vote_rec(EvView vw, const BoxD* __restr
   const RecD* recd = reinterpret_cast<const RecD*>(rec) + int64_t(e) * vw.rec_stride;
   const PairQ32* recf = reinterpret_cast<const PairQ32*>(rec) + int64_t(e) * vw.rec_stride;
   const int32_t T = ev[e].t_prune;
+  const int32_t tcut = ev[e].t_cut;
   const uint32_t n_items = static_cast<uint32_t>(ev[e].n_live);
   __shared__ double sq[NQ][kCap + 16];
   float(*sq32)[kCap + 16] = reinterpret_cast<float(*)[kCap + 16]>(&sq[0][0]);
@@ -1539,7 +1688,7 @@ __global__ void __launch_bounds__(kWG) k_vote_rec(EvView vw, const BoxD* __restr
     int32_t n2max = 0;
     for (int32_t i = tid; i < nt; i += kWG) {
       const int32_t a = tlb[t_first + i], c = tn2[t_first + i];
-      const bool lv = c > 0 && a + c >= T;
+      const bool lv = c > 0 && triple_live(a, c, T, t_first + i, tcut);
       stlive[i] = lv ? 1 : 0;
       if (lv) n2max = max(n2max, c);
     }

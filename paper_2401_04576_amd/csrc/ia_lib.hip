@@ -225,6 +225,36 @@ ia_status launch_classify(ia_ctx* c, const HitRec* recs, const ia::EvView& vw, i
     c->marks.push_back({e0, e1, f32, sh.n_boxes, IA_KERNEL_CLASSIFY});
   }
   IA_HIP(c, hipGetLastError());
+  // the pairs left to the enclosure passes, compacted per chunk of flags
+  const int64_t n_pairs = int64_t(n_tr) * std::max(0, max_hits);
+  if (filt && n_pairs > 0) {
+    const dim3 gd(static_cast<uint32_t>((n_pairs + ia::kDeferChunk - 1) / ia::kDeferChunk), n_ev);
+    hipEvent_t d0 = nullptr, d1 = nullptr;
+    if (c->profiling) {
+      IA_HIP(c, hipEventCreate(&d0));
+      IA_HIP(c, hipEventCreate(&d1));
+      IA_HIP(c, hipEventRecord(d0, s));
+    }
+    if (c->count_work) {
+      if (f32)
+        hipLaunchKernelGGL((ia::k_classify_defer<true, true>), gd, b, 0, s, recs, vw, par, sh, flags, tlb, tn2, ev,
+                           slack32, wk);
+      else
+        hipLaunchKernelGGL((ia::k_classify_defer<false, true>), gd, b, 0, s, recs, vw, par, sh, flags, tlb, tn2, ev,
+                           slack32, wk);
+    } else if (f32) {
+      hipLaunchKernelGGL((ia::k_classify_defer<true, false>), gd, b, 0, s, recs, vw, par, sh, flags, tlb, tn2, ev,
+                         slack32, nullptr);
+    } else {
+      hipLaunchKernelGGL((ia::k_classify_defer<false, false>), gd, b, 0, s, recs, vw, par, sh, flags, tlb, tn2, ev,
+                         slack32, nullptr);
+    }
+    if (c->profiling) {
+      IA_HIP(c, hipEventRecord(d1, s));
+      c->marks.push_back({d0, d1, f32, sh.n_boxes, IA_KERNEL_CLASSIFY_DEFER});
+    }
+    IA_HIP(c, hipGetLastError());
+  }
   return IA_OK;
 }
 
@@ -530,8 +560,10 @@ ia_status run_chunk(ia_ctx* c, const double* hits_chunk, const int32_t* h_off_ch
         if (cs != IA_OK) return cs;
       }
       const int32_t vt = vote_tile(c, sh.n_boxes);
-      hipLaunchKernelGGL(ia::k_threshold, dim3(1, E), dim3(ia::kWG), 0, s, tlb, tn2, lbh, vw, sh, K, c->prune, vt,
-                         ev, live, wg_max, rin.live_tri, rin.rec_off, rin.rec_fill, L.rec_stride);
+      // the last level's max-vote set feeds the estimate: no tie cut there
+      const int32_t ties = lev < sc->n_refine ? 1 : 0;
+      hipLaunchKernelGGL(ia::k_threshold, dim3(1, E), dim3(ia::kWG), 0, s, tlb, tn2, lbh, vw, sh, K, c->prune, ties,
+                         vt, ev, live, wg_max, rin.live_tri, rin.rec_off, rin.rec_fill, L.rec_stride);
       launch_stage(recs, vw, E, par, sh, flags, rin, ev, s, f32, slack32);
       const VoteIn in{flags, tlb, tn2, live, 1};
       ia_status st = launch_vote_rec(c, vw, E, par, sh, votes, hist, ev, in, rin, wg_max, s, f32);
@@ -640,7 +672,7 @@ ia_status ia_ctx_work(ia_ctx* c, int64_t* stereo_box_evals, int64_t* staged_pair
   return IA_OK;
 }
 
-ia_status ia_ctx_classify_work(ia_ctx* c, int64_t counts[12]) {
+ia_status ia_ctx_classify_work(ia_ctx* c, int64_t counts[14]) {
   if (!c || !counts) return IA_ERR_INVALID;
   IA_HIP(c, hipSetDevice(c->device));
   IA_HIP(c, hipDeviceSynchronize());
@@ -709,10 +741,10 @@ ia_status ia_ctx_set_profiling(ia_ctx* c, int32_t enable) {
   return IA_OK;
 }
 
-ia_status ia_ctx_profile_kernels(ia_ctx* c, int64_t n_launches[4], double total_ms[4]) {
+ia_status ia_ctx_profile_kernels(ia_ctx* c, int64_t n_launches[6], double total_ms[6]) {
   if (!c || !n_launches || !total_ms) return IA_ERR_INVALID;
   IA_HIP(c, hipSetDevice(c->device));
-  for (int i = 0; i < 4; ++i) { n_launches[i] = 0; total_ms[i] = 0.0; }
+  for (int i = 0; i < 6; ++i) { n_launches[i] = 0; total_ms[i] = 0.0; }
   ia_status st = IA_OK;
   for (auto& m : c->marks) {
     if (st == IA_OK) {
@@ -733,8 +765,8 @@ ia_status ia_ctx_profile_kernels(ia_ctx* c, int64_t n_launches[4], double total_
 
 ia_status ia_ctx_profile_read(ia_ctx* c, int64_t* n_launches, double* total_ms, int64_t* n_launches_fp32,
                               double* total_ms_fp32) {
-  int64_t n[4];
-  double ms[4];
+  int64_t n[6];
+  double ms[6];
   const ia_status st = ia_ctx_profile_kernels(c, n, ms);
   if (n_launches) *n_launches = n[2 * IA_KERNEL_VOTE];
   if (total_ms) *total_ms = ms[2 * IA_KERNEL_VOTE];

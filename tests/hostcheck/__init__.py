@@ -36,7 +36,7 @@ def lib():
         P = C.c_void_p
         L.hc_vote_level.restype = C.c_int32
         L.hc_vote_level.argtypes = [P, C.c_int32, P, C.c_int32, P, C.c_int32, C.c_int32, C.c_double, C.c_int32,
-                                    C.c_int32, P, P]
+                                    C.c_int32, C.c_int32, P, P]
         L.hc_e_magnitude.restype = C.c_int32
         L.hc_e_magnitude.argtypes = [P, P, P, C.c_uint32, P]
         _lib = L
@@ -55,7 +55,7 @@ def e_magnitude(hit, parent, split, tc):
     return int(rc), float(out[0]), float(out[1]), float(out[2])
 
 
-def vote_level(hits, parents, split, filter_on, f32=False, slack=1e-6, prune_k=0, parent_filter=False):
+def vote_level(hits, parents, split, filter_on, f32=False, slack=1e-6, prune_k=0, parent_filter=False, ties=False):
     h = np.ascontiguousarray(hits).view(np.float64).reshape(-1, 8).copy() if len(hits) else np.zeros((0, 8))
     p = np.atleast_1d(parents)
     pa = np.ascontiguousarray(np.concatenate([p["lo"], p["hi"]], axis=1), dtype=np.float64)
@@ -65,6 +65,6 @@ def vote_level(hits, parents, split, filter_on, f32=False, slack=1e-6, prune_k=0
     stats = np.zeros(9, dtype=np.int64)
     rc = lib().hc_vote_level(h.ctypes.data, h.shape[0], pa.ctypes.data, pa.shape[0], sp.ctypes.data,
                              1 if filter_on else 0, 1 if f32 else 0, float(slack), int(prune_k),
-                             1 if parent_filter else 0, votes.ctypes.data, stats.ctypes.data)
+                             1 if ties else 0, 1 if parent_filter else 0, votes.ctypes.data, stats.ctypes.data)
     assert rc == 0
     return votes, stats

@@ -36,14 +36,15 @@ extern "C" {
 // per-triple bounds tlb (class-1 pairs) and tn2 (class-2 pairs), then the
 // per-box evaluation of class-2 pairs.  With prune_k > 0 only triples whose
 // upper bound reaches T (the prune_k-th largest lower bound over boxes) are
-// evaluated; the boxes of the others keep their lower bound.
+// evaluated, and with `ties` those whose upper bound is exactly T only up to
+// the tie cut; the boxes of the others keep their lower bound.
 // stats: [0] stereo (triple, hit) pairs, [1] class 0, [2] stereo (box, hit)
 // evaluations, [3] of those that voted, [4] evaluated pairs voting in every
 // box of their triple, [5] class 1, [6] triples evaluated, [7] T,
 // [8] (parent, hit) pairs the parent-level test excluded (with parent_filter)
 int32_t hc_vote_level(const double* hits, int32_t n_hits, const double* parents, int32_t n_parents,
                       const int32_t split[5], int32_t filter, int32_t f32, double slack, int32_t prune_k,
-                      int32_t parent_filter, uint16_t* votes, int64_t* stats) {
+                      int32_t ties, int32_t parent_filter, uint16_t* votes, int64_t* stats) {
   const float slack32 = ru32(slack);
   Shape sh;
   if (!make_shape(split, n_parents, &sh)) return 1;
@@ -115,13 +116,25 @@ int32_t hc_vote_level(const double* hits, int32_t n_hits, const double* parents,
       if (cum >= k_eff) { T = v; break; }
     }
   }
+  // tie cut (k_threshold with ties): the triple at which the triples with
+  // lower bound >= T first hold k_eff boxes, in index order
+  int32_t tcut = INT32_MAX;
+  if (prune_k > 0 && ties) {
+    const int64_t k_eff = std::min<int64_t>(prune_k, int64_t(sh.n_boxes));
+    int64_t cum = 0;
+    for (int64_t t = 0; t < n_triples; ++t) {
+      if (tlb[t] < T) continue;
+      cum += sh.m34;
+      if (cum >= k_eff) { tcut = static_cast<int32_t>(t); break; }
+    }
+  }
   int64_t n_evals = 0, n_yes = 0, n_full = 0, n_live = 0;
 #pragma omp parallel for schedule(dynamic, 4) reduction(+ : n_evals, n_yes, n_full, n_live)
   for (int64_t t = 0; t < n_triples; ++t) {
     const uint32_t tp = static_cast<uint32_t>(t / sh.m012), tc = static_cast<uint32_t>(t % sh.m012);
     const int64_t base = int64_t(tp) * sh.nc + int64_t(tc) * sh.m34;
     std::vector<int32_t> nv(sh.m34, tlb[t]);
-    if (tn2[t] > 0 && tlb[t] + tn2[t] >= T) {
+    if (tn2[t] > 0 && triple_live(tlb[t], tn2[t], T, static_cast<uint32_t>(t), tcut)) {
       ++n_live;
       const Frame f = triple_frame(P[tp], sh.m, tc / sh.m12, (tc / sh.m[2]) % sh.m[1], tc % sh.m[2]);
       const float R32 = static_cast<float>(f.R), sig32 = static_cast<float>(f.sig);

@@ -338,9 +338,9 @@ def test_classification_counters_and_timing(ctx):
     """The classification's work counters and the per-kernel timing record
     of one ia_vote_level call: one residual G per (triple, used hit), one
     axial test per axial pair, one set of pair quantities and one magnitude
-    bound per stereo pair, at most two enclosures and as many inclusion
-    proofs per stereo pair; one timed launch each of the classification and
-    the vote."""
+    bound per stereo pair in the first stage; in the second, at most two
+    enclosures and as many inclusion proofs per deferred pair; one timed
+    launch each of the two stages and of the vote."""
     torch = _torch()
     ev = toymc.config_event(2, 3)
     prep = oracle.prep_hits(ev.hits)
@@ -362,11 +362,13 @@ def test_classification_counters_and_timing(ctx):
     kp = ctx.profile_kernels()
     cw = ctx.classify_work()["fp64"]
     assert kp[("classify", "fp64")][0] == 1 and kp[("vote", "fp64")][0] == 1
+    assert kp[("classify_defer", "fp64")][0] == 1
     assert kp[("classify", "fp32")][0] == 0 and kp[("classify", "fp64")][1] > 0
     assert cw["G"] == n_tr * (n_ax + n_st)
     assert cw["axial"] == n_tr * n_ax
     assert cw["pairq"] == n_tr * n_st
     assert cw["magnitudes"] == cw["pairq"]
-    assert cw["enclosures"] <= 2 * cw["pairq"] and cw["inclusions"] <= cw["enclosures"]
+    assert 0 < cw["deferred"] < cw["pairq"]
+    assert cw["deferred"] <= cw["enclosures"] <= 2 * cw["deferred"] and cw["inclusions"] <= cw["enclosures"]
     assert np.array_equal(v.cpu().numpy().astype(np.uint16),
                           oracle.vote_level(ev.hits, root, split))

@@ -185,3 +185,32 @@ def test_magnitude_bound_contains_point_drift(orc, cfg, ev_i):
                             assert abs(e) <= M, (tc, hi, j, s, e, M)
     assert n_bound >= 0.95 * n_pairs
     assert n_checked > 1000
+
+
+@pytest.mark.parametrize("f32", [False, True])
+@pytest.mark.parametrize("cfg,ev_i", [(2, 0), (2, 3), (4, 3), (5, 4)])
+def test_tie_cut_keeps_selection(orc, cfg, ev_i, f32):
+    """With the tie cut (triples after the one at which the lower bounds >= T
+    first cover k boxes, and whose upper bound is exactly T, are pruned too):
+    the top-32 boxes and their votes and the maximum equal the oracle's
+    exhaustive level, every box holds at most its exact vote, and no more
+    triples are evaluated than without the cut.  (The max-vote set is not
+    kept; the cut is used only where the selection and the maximum are.)"""
+    ev = toymc.config_event(cfg, ev_i)
+    root = orc.make_box(H.LO, H.HI)
+    prec = orc.FP32 if f32 else orc.FP64
+    k = 32
+    ref0 = orc.vote_level(ev.hits, root, [10] * 5, prec=prec, slack=SLACK)
+    top0, _ = _topk(ref0, k)
+    levels = [(np.atleast_1d(root), [10] * 5),
+              (np.array([orc.box_child(root, [10] * 5, int(b)) for b in top0]), [4] * 5)]
+    for li, (parents, split) in enumerate(levels):
+        ref = ref0 if li == 0 else orc.vote_level(ev.hits, parents, split, prec=prec, slack=SLACK)
+        got, st = hostcheck.vote_level(ev.hits, parents, split, True, f32=f32, slack=SLACK, prune_k=k, ties=True)
+        _, st0 = hostcheck.vote_level(ev.hits, parents, split, True, f32=f32, slack=SLACK, prune_k=k)
+        assert np.all(got <= ref)
+        ti_r, tv_r = _topk(ref, k)
+        ti_g, tv_g = _topk(got, k)
+        assert np.array_equal(ti_r, ti_g) and np.array_equal(tv_r, tv_g)
+        assert got.max() == ref.max()
+        assert st[6] <= st0[6]
