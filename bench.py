@@ -286,7 +286,7 @@ def main():
                     help="single-helix workload: events per ia_find_helices call (one step)")
     ap.add_argument("--latency-events", type=int, default=40,
                     help="single-helix workload: single-event calls timed for p50/p99 latency")
-    ap.add_argument("--scratch-gb", type=float, default=8.0)
+    ap.add_argument("--scratch-gb", type=float, default=16.0)
     ap.add_argument("--serve-events", type=int, default=4096)
     ap.add_argument("--rate", type=float, default=20000.0, help="serving: Poisson arrival rate, events/s")
     ap.add_argument("--slots", type=int, default=4, help="serving: concurrent batches")

@@ -992,28 +992,31 @@ __global__ void __launch_bounds__(kWG) k_classify(const HitRec* __restrict__ hit
 }
 
 // Second stage of the classification: the stereo pairs k_classify deferred.
-// A workgroup takes kDeferChunk consecutive flags of one event (thread i
-// reads flags i, i + kWG, ...), lists the deferred ones in LDS with a block
-// scan, and the whole workgroup then works through the list, one pair per
-// lane: the triple's frame, G and the pair quantities (the same functions
-// and inputs as in k_classify, hence the same values), then the per-sign
-// enclosure passes; it writes the class and adds class-1 and class-2 pairs
-// to the triple's bounds.
-constexpr int32_t kDeferChunk = 4096;
+// A workgroup takes `per` x kWG consecutive flags of one event (thread i
+// reads flags i, i + kWG, ...; per <= kDeferPer, smaller for small
+// launches so that they still spread over the device), lists the deferred
+// ones in LDS with a block scan, and the whole workgroup then works through
+// the list, one pair per lane: the triple's frame, G and the pair quantities
+// (the same functions and inputs as in k_classify, hence the same values),
+// then the per-sign enclosure passes; it writes the class and adds class-1
+// and class-2 pairs to the triple's bounds.  Pair indices h * n_tr + t stay
+// below 2^32 (the launcher checks).
+constexpr int32_t kDeferPer = 16;
+constexpr int32_t kDeferChunk = kDeferPer * kWG;
 
 template <bool F32, bool COUNT>
 __global__ void __launch_bounds__(kWG) k_classify_defer(const HitRec* __restrict__ hits, EvView vw,
                                                         const BoxD* __restrict__ parents, Shape sh,
                                                         uint8_t* __restrict__ flags, int32_t* __restrict__ tlb,
-                                                        int32_t* __restrict__ tn2,
+                                                        int32_t* __restrict__ tn2, int32_t per,
                                                         const EventState* __restrict__ ev, float slack32,
                                                         unsigned long long* __restrict__ work) {
   const int e = blockIdx.y;
   if (ev && ev[e].done) return;
   const int32_t n_hits = vw.count(e);
   const uint32_t n_tr = sh.n_parents * sh.m012;
-  const int64_t n_pairs = static_cast<int64_t>(n_tr) * (n_hits > 0 ? n_hits : 0);
-  const int64_t c0 = static_cast<int64_t>(blockIdx.x) * kDeferChunk;
+  const uint32_t n_pairs = n_tr * static_cast<uint32_t>(n_hits > 0 ? n_hits : 0);
+  const uint32_t c0 = blockIdx.x * static_cast<uint32_t>(per * kWG);
   if (c0 >= n_pairs) return;
   hits += vw.beg(e);
   parents += e * vw.par_stride;
@@ -1022,26 +1025,25 @@ __global__ void __launch_bounds__(kWG) k_classify_defer(const HitRec* __restrict
   tn2 += e * vw.tri_stride;
   __shared__ uint16_t s_list[kDeferChunk];
   __shared__ int32_t s_scan[kWG];
-  constexpr int kPer = kDeferChunk / kWG;
   uint32_t mask = 0;
   int32_t mine = 0;
 #pragma unroll
-  for (int k = 0; k < kPer; ++k) {
-    const int64_t p = c0 + k * kWG + threadIdx.x;
-    const bool d = p < n_pairs && flags[p] == kFlagDeferred;
+  for (int k = 0; k < kDeferPer; ++k) {
+    const uint32_t p = c0 + static_cast<uint32_t>(k * kWG) + threadIdx.x;
+    const bool d = k < per && p < n_pairs && flags[p] == kFlagDeferred;
     mask |= d ? (1u << k) : 0u;
     mine += d ? 1 : 0;
   }
   int32_t pos;
   const int32_t total = block_scan_count(mine, &pos, s_scan);
 #pragma unroll
-  for (int k = 0; k < kPer; ++k)
+  for (int k = 0; k < kDeferPer; ++k)
     if (mask & (1u << k)) s_list[pos++] = static_cast<uint16_t>(k * kWG + threadIdx.x);
   __syncthreads();
   int32_t cw[3] = {0, 0, 0};                  // deferred pairs, enclosure passes, inclusion proofs
   for (int32_t i = threadIdx.x; i < total; i += kWG) {
-    const int64_t p = c0 + s_list[i];
-    const uint32_t h = static_cast<uint32_t>(p / n_tr), t = static_cast<uint32_t>(p % n_tr);
+    const uint32_t p = c0 + s_list[i];
+    const uint32_t h = p / n_tr, t = p - h * n_tr;
     const uint32_t tc = t % sh.m012;
     const BoxD& TP = parents[t / sh.m012];
     const Frame f = triple_frame(TP, sh.m, tc / sh.m12, (tc / sh.m[2]) % sh.m[1], tc % sh.m[2]);

@@ -225,10 +225,14 @@ ia_status launch_classify(ia_ctx* c, const HitRec* recs, const ia::EvView& vw, i
     c->marks.push_back({e0, e1, f32, sh.n_boxes, IA_KERNEL_CLASSIFY});
   }
   IA_HIP(c, hipGetLastError());
-  // the pairs left to the enclosure passes, compacted per chunk of flags
+  // the pairs left to the enclosure passes, compacted per chunk of flags:
+  // the largest chunk that still gives about 2048 workgroups
   const int64_t n_pairs = int64_t(n_tr) * std::max(0, max_hits);
+  if (n_pairs >= (int64_t(1) << 32)) return fail(c, IA_ERR_OVERFLOW, "level exceeds 2^32 (triple, hit) pairs");
   if (filt && n_pairs > 0) {
-    const dim3 gd(static_cast<uint32_t>((n_pairs + ia::kDeferChunk - 1) / ia::kDeferChunk), n_ev);
+    int32_t per = ia::kDeferPer;
+    while (per > 1 && (n_pairs * std::max(1, n_ev)) / (int64_t(per) * ia::kWG) < 2048) per /= 2;
+    const dim3 gd(static_cast<uint32_t>((n_pairs + int64_t(per) * ia::kWG - 1) / (int64_t(per) * ia::kWG)), n_ev);
     hipEvent_t d0 = nullptr, d1 = nullptr;
     if (c->profiling) {
       IA_HIP(c, hipEventCreate(&d0));
@@ -237,17 +241,17 @@ ia_status launch_classify(ia_ctx* c, const HitRec* recs, const ia::EvView& vw, i
     }
     if (c->count_work) {
       if (f32)
-        hipLaunchKernelGGL((ia::k_classify_defer<true, true>), gd, b, 0, s, recs, vw, par, sh, flags, tlb, tn2, ev,
-                           slack32, wk);
+        hipLaunchKernelGGL((ia::k_classify_defer<true, true>), gd, b, 0, s, recs, vw, par, sh, flags, tlb, tn2, per,
+                           ev, slack32, wk);
       else
-        hipLaunchKernelGGL((ia::k_classify_defer<false, true>), gd, b, 0, s, recs, vw, par, sh, flags, tlb, tn2, ev,
-                           slack32, wk);
+        hipLaunchKernelGGL((ia::k_classify_defer<false, true>), gd, b, 0, s, recs, vw, par, sh, flags, tlb, tn2, per,
+                           ev, slack32, wk);
     } else if (f32) {
-      hipLaunchKernelGGL((ia::k_classify_defer<true, false>), gd, b, 0, s, recs, vw, par, sh, flags, tlb, tn2, ev,
-                         slack32, nullptr);
+      hipLaunchKernelGGL((ia::k_classify_defer<true, false>), gd, b, 0, s, recs, vw, par, sh, flags, tlb, tn2, per,
+                         ev, slack32, nullptr);
     } else {
-      hipLaunchKernelGGL((ia::k_classify_defer<false, false>), gd, b, 0, s, recs, vw, par, sh, flags, tlb, tn2, ev,
-                         slack32, nullptr);
+      hipLaunchKernelGGL((ia::k_classify_defer<false, false>), gd, b, 0, s, recs, vw, par, sh, flags, tlb, tn2, per,
+                         ev, slack32, nullptr);
     }
     if (c->profiling) {
       IA_HIP(c, hipEventRecord(d1, s));
@@ -831,7 +835,8 @@ ia_status ia_vote_level(ia_ctx* c, const ia_hit* d_hits, int32_t n_hits, const u
                      reinterpret_cast<uint32_t*>(tlb), fill_n, 0u);
   hipLaunchKernelGGL(ia::k_fill_u32, dim3(std::min<uint32_t>((fill_n + 255) / 256, 65535)), dim3(256), 0, s,
                      reinterpret_cast<uint32_t*>(tn2), fill_n, 0u);
-  const ia_status cs = launch_classify(c, recs, vw, 1, n_hits, par, sh, flags, tlb, tn2, nullptr, s, f32, c->slack32);
+  const ia_status cs = launch_classify(c, recs, vw, 1, n_hits, par, sh, flags, tlb, tn2, nullptr, s, f32,
+                                       c->slack32);
   if (cs != IA_OK) return cs;
   const VoteIn in{flags, tlb, tn2, nullptr, 0};
   return launch_vote(c, recs, vw, 1, par, sh, d_votes, nullptr, nullptr, in, nullptr, s, f32, c->slack32);
