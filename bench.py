@@ -77,9 +77,12 @@ FLOP_BOX_STEREO32 = 278
 #    its exclusion test (the FP32 levels' test counted as FP64 too): 688;
 #  - one inclusion proof (bounds at the enclosure's ends): 94;
 #  - one magnitude bound of d^Ax over the triple (67) with its exclusion test (46): 113;
-#  - a deferred pair's triple frame and (z0, tanl) centre ranges: 130.
+#  - a deferred pair's triple frame and (z0, tanl) centre ranges: 130;
+#  - the first stage's outer enclosure of G (sines of the phi0 edges from the
+#    difference identity, then residual_G's interval operations): 68;
+#  - the first stage's stereo pair magnitudes (pair quantities without atan2): 34.
 FLOP_CLS_G, FLOP_CLS_AXIAL, FLOP_CLS_PAIRQ, FLOP_CLS_ENCL, FLOP_CLS_INCL, FLOP_CLS_MAG = 157, 92, 69, 688, 94, 113
-FLOP_CLS_FRAME = 130
+FLOP_CLS_FRAME, FLOP_CLS_GOUT, FLOP_CLS_PAIRMAG = 130, 68, 34
 PEAK_FP64_TFLOPS = 78.6   # MI355X vector FP64: 256 CU x 128 FLOP/clk x 2.4 GHz
 # HBM bytes per launch of the FP64 classification over 1024-event batches of
 # the default workload: rocprofv3 --pmc FETCH_SIZE, then WRITE_SIZE, averaged
@@ -122,8 +125,8 @@ def classify_traffic(workload, events_per_step):
 
 def classify_flops(cw):
     """FP64 flops of the first classification stage."""
-    return (cw["G"] * FLOP_CLS_G + cw["axial"] * FLOP_CLS_AXIAL + cw["pairq"] * FLOP_CLS_PAIRQ
-            + cw["magnitudes"] * FLOP_CLS_MAG)
+    return (cw["G"] * FLOP_CLS_GOUT + cw["axial"] * FLOP_CLS_AXIAL + cw["G_exact"] * (FLOP_CLS_G + FLOP_CLS_AXIAL)
+            + cw["pairq"] * FLOP_CLS_PAIRMAG + cw["magnitudes"] * FLOP_CLS_MAG)
 
 
 def defer_flops(cw):

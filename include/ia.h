@@ -160,16 +160,17 @@ ia_status ia_ctx_profile_kernels(ia_ctx *ctx, int64_t n_launches[6], double tota
 ia_status ia_ctx_set_work_counting(ia_ctx *ctx, int32_t enable);
 
 /* Work of the two classification stages, counted while work counting was
- * enabled, since the last ia_ctx_clear_status: counts[7 p + c] at precision
- * p (0 FP64 levels, 1 FP32 levels).  First stage: c = 0 residual intervals
- * G (Eq. ApoVote over a triple), 1 axial tests, 2 stereo pair quantities,
- * 3 magnitude bounds of d^Ax (each with its exclusion test).  Second stage:
- * c = 4 deferred pairs (each with its triple's frame, G and pair quantities
- * again), 5 interval enclosures of d^Ax (each with its exclusion test),
- * 6 inclusion proofs.  Only pairs of live triples are counted; pairs the
+ * enabled, since the last ia_ctx_clear_status: counts[8 p + c] at precision
+ * p (0 FP64 levels, 1 FP32 levels).  First stage: c = 0 outer enclosures of
+ * the residual G (Eq. ApoVote over a triple), 1 axial tests, 2 exact G for
+ * axial pairs the outer one did not exclude, 3 stereo pair magnitudes,
+ * 4 magnitude bounds of d^Ax (each with its exclusion test).  Second stage:
+ * c = 5 deferred pairs (each with its triple's frame, exact G and pair
+ * quantities), 6 interval enclosures of d^Ax (each with its exclusion test),
+ * 7 inclusion proofs.  Only pairs of live triples are counted; pairs the
  * parent-level test excluded are not.  Synchronises the device.  counts is
- * host memory of 14 entries. */
-ia_status ia_ctx_classify_work(ia_ctx *ctx, int64_t counts[14]);
+ * host memory of 16 entries. */
+ia_status ia_ctx_classify_work(ia_ctx *ctx, int64_t counts[16]);
 
 /* Band widening used by ia_vote_level at IA_FP32 (default 1e-6 m; ia_find_helices
  * takes it from the schedule).  IA_ERR_INVALID outside [0, 1e-3]. */
@@ -225,7 +226,7 @@ size_t ia_ctx_scratch_needed(const ia_schedule *sched, int32_t max_hits);
  *             context's slack; its votes contain the IA_FP64 votes
  *   d_votes   n_parents * prod(split) uint16, written: number of active,
  *             well-formed hits voting for each box
- * Scratch: 96 bytes per hit, and n_parents * prod(split[0..2]) * (n_hits + 8)
+ * Scratch: 112 bytes per hit, and n_parents * prod(split[0..2]) * (n_hits + 8)
  * bytes of (triple, hit) classes and per-triple bounds (IA_ERR_NOMEM when the
  * context's scratch cannot hold them); n_parents * prod(split[0..2]) * n_hits
  * below 2^32 (IA_ERR_OVERFLOW). */

@@ -209,13 +209,13 @@ class Context:
 
     def classify_work(self):
         """Classification work counted (set_work_counting) since the last clear_status(): {"fp64": {...},
-        "fp32": {...}} with counts of residuals G, axial tests, stereo pair
-        quantities and magnitude bounds (first stage), and deferred pairs,
-        d^Ax enclosures and inclusion proofs (second stage)."""
-        a = (C.c_int64 * 14)()
+        "fp32": {...}} with counts of outer residuals G, axial tests, exact G,
+        stereo pair magnitudes and magnitude bounds (first stage), and
+        deferred pairs, d^Ax enclosures and inclusion proofs (second stage)."""
+        a = (C.c_int64 * 16)()
         self._check(self._L.ia_ctx_classify_work(self._h, a))
-        keys = ("G", "axial", "pairq", "magnitudes", "deferred", "enclosures", "inclusions")
-        return {p: {k: int(a[7 * i + j]) for j, k in enumerate(keys)} for i, p in enumerate(("fp64", "fp32"))}
+        keys = ("G", "axial", "G_exact", "pairq", "magnitudes", "deferred", "enclosures", "inclusions")
+        return {p: {k: int(a[8 * i + j]) for j, k in enumerate(keys)} for i, p in enumerate(("fp64", "fp32"))}
 
     def set_fp32_slack(self, slack=1e-6):
         """Band widening of vote_level at FP32 (m)."""

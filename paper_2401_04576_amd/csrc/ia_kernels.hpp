@@ -26,8 +26,9 @@ constexpr int kHistLds = 1024;  // vote histogram bins kept in LDS
 constexpr int kEstLevels = 15;  // estimate stack depth (partials of up to 2^22 boxes)
 constexpr int kMaxTopK = 4096;  // selection size limit
 
-struct HitRec {                 // prepared hit, 96 bytes
+struct HitRec {                 // prepared hit, 112 bytes
   double px, py, tant, sphis, cphis, r, phip, r2lo, r2hi, d, band;
+  double sphp, cphp;            // sin and cos of phip (sin_p, cos_p)
   int32_t use;                  // valid and active
   int32_t axial;
 };
@@ -97,7 +98,11 @@ enum : uint32_t { kStBadHit = 1u, kStVoteOverflow = 2u, kStBadOffsets = 4u };
 constexpr uint32_t kWorkSlots = 64;
 constexpr uint32_t kWorkSlotU64 = 32;
 constexpr uint32_t kWorkClassify = 4;
-enum : uint32_t { kCwG = 0, kCwAxial = 1, kCwPairQ = 2, kCwMag = 3, kCwDefer = 4, kCwPass = 5, kCwIncl = 6, kCwN = 7 };
+enum : uint32_t {
+  kCwG = 0, kCwAxial = 1, kCwGExact = 2, kCwPairQ = 3, kCwMag = 4,    // first stage
+  kCwDefer = 5, kCwPass = 6, kCwIncl = 7,                              // second stage
+  kCwN = 8
+};
 // class flag of a stereo pair whose class k_classify left to k_classify_defer
 constexpr uint8_t kFlagDeferred = 3;
 
@@ -146,6 +151,8 @@ IA_HD void prep_one(const double* h, bool active, HitRec* o, bool* bad) {
   else { r.sphis = tx / r.tant; r.cphis = -ty / r.tant; r.axial = 0; }
   r.r = sqrt(r.px * r.px + r.py * r.py);
   r.phip = atan2_p(r.py, r.px);
+  r.sphp = sin_p(r.phip);
+  r.cphp = cos_p(r.phip);
   double r2 = r.r * r.r;
   r.r2lo = wdn(r2);
   r.r2hi = wup(r2);
@@ -197,6 +204,54 @@ IA_HD Iv residual_G(const Frame& f, const HitRec& h) {
   Iv KT = imul(f.K, T);
   Iv KD1 = iadd(imul(f.K, f.Dd), Iv{1.0, 1.0});
   return iadd(iadd(KT, imul(KD1, rS)), f.Dd);
+}
+
+// An outer enclosure of residual_G for exclusion tests, cheaper per pair.
+// residual_G's operations are kept except the sin enclosure S of
+// [phi0 - phip], which is replaced by an interval holding it: the sines at the
+// two ends come from the difference identity with the triple's sin / cos of
+// its phi0 edges and the hit's sin / cos of phip (each within 0.56 ulp), so
+// they lie within a few ulps of sin_p at those ends, and a margin of 2^-46
+// covers that, sin_encl's 2^-50 and the one-ulp widening of the angles; an
+// extremum is taken as soon as the cosines at the ends change sign within
+// 1e-6 (the phi0 range is narrower than pi, else [-1, 1]).  Every later
+// operation is inclusion-monotone, so the result holds residual_G's: an H
+// test failing for it fails for residual_G too.  GTri holds the per-triple
+// parts.
+struct GTri {
+  Iv D2, KD1;
+  double sa, ca, sb, cb;        // sin, cos of the phi0 edges
+  int32_t wide;
+};
+
+IA_HD GTri g_triple(const Frame& f) {
+  GTri g;
+  g.D2 = isqr(f.Dd);
+  g.KD1 = iadd(imul(f.K, f.Dd), Iv{1.0, 1.0});
+  g.sa = sin_p(f.Fi.lo);
+  g.ca = cos_p(f.Fi.lo);
+  g.sb = sin_p(f.Fi.hi);
+  g.cb = cos_p(f.Fi.hi);
+  g.wide = !(f.Fi.hi - f.Fi.lo <= 3.0);
+  return g;
+}
+
+IA_HD Iv residual_G_outer(const Frame& f, const GTri& g, const HitRec& h) {
+  constexpr double mS = 0x1p-46, mC = 1e-6;
+  Iv S = {-1.0, 1.0};
+  if (!g.wide) {
+    const double s_a = g.sa * h.cphp - g.ca * h.sphp, s_b = g.sb * h.cphp - g.cb * h.sphp;
+    const double c_a = g.ca * h.cphp + g.sa * h.sphp, c_b = g.cb * h.cphp + g.sb * h.sphp;
+    const bool has_max = c_a >= -mC && c_b <= mC;
+    const bool has_min = c_a <= mC && c_b >= -mC;
+    S.hi = has_max ? 1.0 : fmin(1.0, fmax(s_a, s_b) + mS);
+    S.lo = has_min ? -1.0 : fmax(-1.0, fmin(s_a, s_b) - mS);
+  }
+  const Iv rS = imul_pos(S, h.r);
+  const Iv T0 = iadd(g.D2, Iv{h.r2lo, h.r2hi});
+  const Iv T = {0.5 * T0.lo, 0.5 * T0.hi};
+  const Iv KT = imul(f.K, T);
+  return iadd(iadd(KT, imul(g.KD1, rS)), f.Dd);
 }
 
 IA_HD bool h_contains0(Iv G, Iv K, double e, double band) {
@@ -372,21 +427,25 @@ IA_HD bool votes_everywhere(Iv G, Iv K, double E1, double E2, double b) {
 // discriminant from below and `a_hi` bounds A from above.
 struct EMag { double M, eps, disc_lo, a_hi; };
 
-IA_HD bool e_magnitude(const PairQ& q, double R, double tt, double d, Iv Z, Iv L, EMag* out) {
+// magnitudes of the pair quantities that e_magnitude uses; sArc and dphi may
+// be upper bounds of the absolute values
+struct MagIn { double sa, ca, sArc, dphi, RAx, c2, s2, twoRAx2, RpRAx, cAx, sAx; };
+
+IA_HD bool e_magnitude_in(const MagIn& q, double R, double tt, double d, Iv Z, Iv L, EMag* out) {
   const double at = fabs(tt), t2 = at * at;
   const double z = fmax(fabs(Z.lo), fabs(Z.hi)), l = fmax(fabs(L.lo), fabs(L.hi));
-  const double sa = fabs(q.sinA), ca = fabs(q.cosA), S = sa + ca;
-  const double za = z + l * fabs(q.sArc);
+  const double sa = q.sa, ca = q.ca, S = sa + ca;
+  const double za = z + l * q.sArc;
   const double phi1 = (za * sa + (l * d) * ca) / q.RAx;
-  const double phi2 = ((l * R) * za + ((l * za) * (R + 2.0 * d)) * fabs(q.c2) +
-                       (za * za + d * (q.RAx + (l * l) * (q.RpRAx + d))) * fabs(q.s2)) / q.twoRAx2;
+  const double phi2 = ((l * R) * za + ((l * za) * (R + 2.0 * d)) * q.c2 +
+                       (za * za + d * (q.RAx + (l * l) * (q.RpRAx + d))) * q.s2) / q.twoRAx2;
   const double eps = phi1 * at + phi2 * t2;
   const double u2 = 1.0 - ((2.0 * l) * S) * at;
   if (!(u2 >= 0.25)) return false;
   const double delta = d / sqrt(u2);
-  const double zs = (z + l * (R * (fabs(q.dphi) + eps))) + (delta * S) * at;
+  const double zs = (z + l * (R * (q.dphi + eps))) + (delta * S) * at;
   const double ld = l * delta;
-  const double ctau = zs * fabs(q.cAx) + ld * fabs(q.sAx);
+  const double ctau = zs * q.cAx + ld * q.sAx;
   const double Qm = ((2.0 * ctau) * at + (zs * at) * (zs * at)) + (ld * at) * (ld * at);
   const double alo = R - delta;
   if (!(alo > 0.0)) return false;
@@ -398,6 +457,39 @@ IA_HD bool e_magnitude(const PairQ& q, double R, double tt, double d, Iv Z, Iv L
   out->disc_lo = r * (1.0 - 0x1p-29);
   out->a_hi = (R + delta) * (1.0 + 0x1p-29);
   return __builtin_isfinite(out->M) && __builtin_isfinite(out->eps);
+}
+
+IA_HD bool e_magnitude(const PairQ& q, double R, double tt, double d, Iv Z, Iv L, EMag* out) {
+  const MagIn m = {fabs(q.sinA), fabs(q.cosA), fabs(q.sArc), fabs(q.dphi), q.RAx, fabs(q.c2), fabs(q.s2),
+                   q.twoRAx2, q.RpRAx, fabs(q.cAx), fabs(q.sAx)};
+  return e_magnitude_in(m, R, tt, d, Z, L, out);
+}
+
+// The inputs of e_magnitude without the arc angle's atan2: every quantity is
+// computed by pair_quantities' operations (the same values), and |dphi| is
+// bounded by |y| / x when x > 0 (|atan t| <= |t|; atan2_p is within a few ulps
+// of atan), else by pi; |sArc| by R times that.  The widening by 2^-45 covers
+// the few ulps.
+IA_HD MagIn pair_magnitudes(const Frame& f, const HitRec& h) {
+  MagIn m;
+  const double py = f.sig * h.py, cps = f.sig * h.cphis, sps = h.sphis;
+  const double Dx = h.px - f.xc, Dy = py - f.yc;
+  m.RAx = sqrt(Dx * Dx + Dy * Dy);
+  const double cAx = Dx * sps - Dy * cps;
+  const double sAx = Dx * cps + Dy * sps;
+  const double sinA = sAx / m.RAx, cosA = cAx / m.RAx;
+  const double y = Dx * f.cp0 + Dy * f.sp0, x = Dx * f.sp0 - Dy * f.cp0;
+  m.dphi = (x > 0.0 ? fabs(y) / x : kPio2Up * 2.0) * (1.0 + 0x1p-45);
+  m.sArc = (f.R * m.dphi) * (1.0 + 0x1p-45);
+  m.sa = fabs(sinA);
+  m.ca = fabs(cosA);
+  m.c2 = fabs(cosA * cosA - sinA * sinA);
+  m.s2 = fabs(2.0 * sinA * cosA);
+  m.twoRAx2 = 2.0 * (m.RAx * m.RAx);
+  m.RpRAx = f.R + m.RAx;
+  m.cAx = fabs(cAx);
+  m.sAx = fabs(sAx);
+  return m;
 }
 
 // H test of reading 8 over E = [-M, M] widened by the band: false when the
@@ -420,6 +512,12 @@ IA_HD bool h_may_vote_mag(Iv G, Iv K, double M, double band) {
 // of an enclosure's cost; 0 or -1 for undecided) and stereo_pass_class (the
 // enclosure per drift sign).  With `cnt` set, cnt[0] counts the enclosure
 // passes and cnt[1] the inclusion proofs evaluated.
+IA_HD int stereo_quick_class_in(const MagIn& m, Iv G, const Frame& f, const HitRec& h, Iv Z, Iv L) {
+  EMag em;
+  if (e_magnitude_in(m, f.R, h.tant, h.d, Z, L, &em) && !h_may_vote_mag(G, f.K, em.M, h.band)) return 0;
+  return -1;
+}
+
 IA_HD int stereo_quick_class(const PairQ& q, const Frame& f, const HitRec& h, Iv Z, Iv L) {
   EMag em;
   if (e_magnitude(q, f.R, h.tant, h.d, Z, L, &em) && !h_may_vote_mag(Iv{q.Glo, q.Ghi}, f.K, em.M, h.band))
@@ -551,6 +649,22 @@ IA_HD bool stereo_vote32(const PairQ32& q, float R, float sig, Iv32 K, float z0,
 // Two stages as at FP64 levels; the quick stage also gives class 1 to a
 // triple outside the FP32 domain, and its exclusion needs every box inside
 // the domain.
+IA_HD int stereo_quick_class32_in(const MagIn& m, Iv G64, const Frame& f, const HitRec& h, Iv Z, Iv L,
+                                   float slack32) {
+  if (!(f.R <= kR32Max)) return 1;
+  EMag em;
+  if (e_magnitude_in(m, f.R, h.tant, h.d, Z, L, &em) && em.eps <= 0.99 && em.disc_lo > 1e-3 * em.a_hi * em.a_hi) {
+    const Iv32 G = to32(G64);
+    const Iv32 K = to32(f.K);
+    const float bs2 = wup32(ru32(h.band) + 2.0f * slack32);
+    const float m32 = ru32(em.M);
+    const Iv32 Eb = {wdn32(-m32 - bs2), wup32(m32 + bs2)};
+    const Iv32 Hb = isub32(itwice32(G), iadd32(itwice32(Eb), imul32(K, isqr32(Eb))));
+    if (!(Hb.lo <= 0.0f && 0.0f <= Hb.hi)) return 0;
+  }
+  return -1;
+}
+
 IA_HD int stereo_quick_class32(const PairQ& q, const Frame& f, const HitRec& h, Iv Z, Iv L, float slack32) {
   if (!(f.R <= kR32Max)) return 1;
   EMag em;
@@ -603,6 +717,41 @@ IA_HD int triple_vote_class32(const PairQ& q, const Frame& f, const HitRec& h, I
                               int32_t* cnt = nullptr) {
   const int c = stereo_quick_class32(q, f, h, Z, L, slack32);
   return c >= 0 ? c : stereo_pass_class32(q, f, h, Z, L, slack32, cnt);
+}
+
+// The two stages of a (triple, hit) pair's class as the kernels run them.
+// Stage 1 (k_classify): the outer G (residual_G_outer); an axial pair is
+// decided exactly, with the exact G only when the outer one does not already
+// exclude both signs; a stereo pair is excluded by the magnitude bound from
+// pair_magnitudes and the outer G, else deferred (-1).  Outside the FP32
+// domain a stereo pair votes (1); without the proofs (`filter` 0) it is
+// class 2.  cnt[kCwG ..] counts the work when set.
+template <bool F32>
+IA_HD int pair_stage1(const Frame& f, const GTri& g, const HitRec& h, Iv Z, Iv L, int32_t filter, float slack32,
+                      int32_t* cnt) {
+  const Iv Go = residual_G_outer(f, g, h);
+  if (cnt) ++cnt[kCwG];
+  if (h.axial) {
+    if (cnt) ++cnt[kCwAxial];
+    if (!h_contains0(Go, f.K, f.sig * h.d, h.band) && !h_contains0(Go, f.K, f.sig * (-h.d), h.band)) return 0;
+    if (cnt) ++cnt[kCwGExact];
+    const Iv G = residual_G(f, h);
+    return (h_contains0(G, f.K, f.sig * h.d, h.band) || h_contains0(G, f.K, f.sig * (-h.d), h.band)) ? 1 : 0;
+  }
+  if (F32 && !(f.R <= kR32Max)) return 1;
+  if (!filter) return 2;
+  if (cnt) { ++cnt[kCwPairQ]; ++cnt[kCwMag]; }
+  const MagIn m = pair_magnitudes(f, h);
+  return F32 ? stereo_quick_class32_in(m, Go, f, h, Z, L, slack32) : stereo_quick_class_in(m, Go, f, h, Z, L);
+}
+
+// Stage 2 (k_classify_defer): the exact G and pair quantities, then the
+// per-sign enclosure passes.  cnt[0] counts enclosures, cnt[1] inclusion
+// proofs.
+template <bool F32>
+IA_HD int pair_stage2(const Frame& f, const HitRec& h, Iv Z, Iv L, float slack32, int32_t* cnt) {
+  const PairQ q = pair_quantities(f, h, residual_G(f, h));
+  return F32 ? stereo_pass_class32(q, f, h, Z, L, slack32, cnt) : stereo_pass_class(q, f, h, Z, L, cnt);
 }
 
 // (z0, tanl) centre ranges of the boxes of one parent
@@ -939,28 +1088,16 @@ __global__ void __launch_bounds__(kWG) k_classify(const HitRec* __restrict__ hit
   const Frame f = triple_frame(TP, sh.m, tc / sh.m12, (tc / sh.m[2]) % sh.m[1], tc % sh.m[2]);
   Iv Zr, Lr;
   centre_ranges(TP, sh.m, &Zr, &Lr);
+  const GTri gt = g_triple(f);
   int32_t lb = 0, n2 = 0;
-  int32_t cw[kCwDefer] = {0, 0, 0, 0};
+  int32_t cw[kCwDefer] = {0, 0, 0, 0, 0};
   const int32_t h_step = static_cast<int32_t>(gridDim.z) * (kWG / 64);
   for (int32_t h = static_cast<int32_t>(blockIdx.z) * (kWG / 64) + wave; h < n_hits; h += h_step) {
     const HitRec hr = hits[h];
     uint8_t fl = 0;
     if (hr.use && (!pf || pf[h])) {
-      const Iv G = residual_G(f, hr);
-      if constexpr (COUNT) ++cw[kCwG];
-      if (hr.axial) {
-        fl = (h_contains0(G, f.K, f.sig * hr.d, hr.band) || h_contains0(G, f.K, f.sig * (-hr.d), hr.band)) ? 1 : 0;
-        if constexpr (COUNT) ++cw[kCwAxial];
-      } else if (F32 && !(f.R <= kR32Max)) {
-        fl = 1;                              // outside the FP32 domain: the pair votes
-      } else if (!filter) {
-        fl = 2;
-      } else {
-        const PairQ q = pair_quantities(f, hr, G);
-        if constexpr (COUNT) { ++cw[kCwPairQ]; ++cw[kCwMag]; }
-        const int c = F32 ? stereo_quick_class32(q, f, hr, Zr, Lr, slack32) : stereo_quick_class(q, f, hr, Zr, Lr);
-        fl = c >= 0 ? static_cast<uint8_t>(c) : kFlagDeferred;
-      }
+      const int c = pair_stage1<F32>(f, gt, hr, Zr, Lr, filter, slack32, COUNT ? cw : nullptr);
+      fl = c >= 0 ? static_cast<uint8_t>(c) : kFlagDeferred;
     }
     if (live) flags[int64_t(h) * n_tr + t] = fl;
     lb += fl == 1 ? 1 : 0;
@@ -1050,10 +1187,8 @@ __global__ void __launch_bounds__(kWG) k_classify_defer(const HitRec* __restrict
     Iv Zr, Lr;
     centre_ranges(TP, sh.m, &Zr, &Lr);
     const HitRec hr = hits[h];
-    const PairQ q = pair_quantities(f, hr, residual_G(f, hr));
     if constexpr (COUNT) ++cw[0];
-    int32_t* pc = COUNT ? &cw[1] : nullptr;
-    const int c = F32 ? stereo_pass_class32(q, f, hr, Zr, Lr, slack32, pc) : stereo_pass_class(q, f, hr, Zr, Lr, pc);
+    const int c = pair_stage2<F32>(f, hr, Zr, Lr, slack32, COUNT ? &cw[1] : nullptr);
     flags[p] = static_cast<uint8_t>(c);
     if (c == 1) atomicAdd(&tlb[t], 1);
     else if (c == 2) atomicAdd(&tn2[t], 1);

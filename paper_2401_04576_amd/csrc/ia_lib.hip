@@ -22,7 +22,7 @@ static_assert(sizeof(ia_hit) == 64, "ia_hit layout");
 static_assert(sizeof(ia_box) == sizeof(BoxD), "ia_box layout");
 static_assert(sizeof(ia_helix) == sizeof(ia::HelixOut), "ia_helix layout");
 static_assert(sizeof(ia_estimate_t) == sizeof(ia::EstimateOut), "ia_estimate_t layout");
-static_assert(sizeof(HitRec) == 96, "HitRec layout");
+static_assert(sizeof(HitRec) == 112, "HitRec layout");
 
 namespace {
 
@@ -676,7 +676,7 @@ ia_status ia_ctx_work(ia_ctx* c, int64_t* stereo_box_evals, int64_t* staged_pair
   return IA_OK;
 }
 
-ia_status ia_ctx_classify_work(ia_ctx* c, int64_t counts[14]) {
+ia_status ia_ctx_classify_work(ia_ctx* c, int64_t counts[16]) {
   if (!c || !counts) return IA_ERR_INVALID;
   IA_HIP(c, hipSetDevice(c->device));
   IA_HIP(c, hipDeviceSynchronize());

@@ -37,6 +37,8 @@ def lib():
         L.hc_vote_level.restype = C.c_int32
         L.hc_vote_level.argtypes = [P, C.c_int32, P, C.c_int32, P, C.c_int32, C.c_int32, C.c_double, C.c_int32,
                                     C.c_int32, C.c_int32, P, P]
+        L.hc_g_pairs.restype = C.c_int32
+        L.hc_g_pairs.argtypes = [P, C.c_int32, P, P, P]
         L.hc_e_magnitude.restype = C.c_int32
         L.hc_e_magnitude.argtypes = [P, P, P, C.c_uint32, P]
         _lib = L
@@ -68,3 +70,16 @@ def vote_level(hits, parents, split, filter_on, f32=False, slack=1e-6, prune_k=0
                              1 if ties else 0, 1 if parent_filter else 0, votes.ctypes.data, stats.ctypes.data)
     assert rc == 0
     return votes, stats
+
+
+def g_pairs(hits, parent, split):
+    """(G, outer G) intervals of every (triple, hit) pair of one parent's
+    level, shape (triples, hits, 4): G.lo, G.hi, Go.lo, Go.hi."""
+    h = np.ascontiguousarray(hits).view(np.float64).reshape(-1, 8).copy()
+    p = np.atleast_1d(parent)
+    pa = np.ascontiguousarray(np.concatenate([p["lo"], p["hi"]], axis=1)[0], dtype=np.float64)
+    sp = np.ascontiguousarray(split, dtype=np.int32)
+    n_tr = int(np.prod(sp[:3].astype(np.int64)))
+    out = np.zeros((n_tr, h.shape[0], 4))
+    assert lib().hc_g_pairs(h.ctypes.data, h.shape[0], pa.ctypes.data, sp.ctypes.data, out.ctypes.data) == 0
+    return out

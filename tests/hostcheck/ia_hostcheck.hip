@@ -77,23 +77,20 @@ int32_t hc_vote_level(const double* hits, int32_t n_hits, const double* parents,
     const Frame f = triple_frame(P[tp], sh.m, tc / sh.m12, (tc / sh.m[2]) % sh.m[1], tc % sh.m[2]);
     Iv Zr, Lr;
     centre_ranges(P[tp], sh.m, &Zr, &Lr);
+    const GTri gt = g_triple(f);
     int32_t a = 0, c2 = 0;
     for (int32_t i = 0; i < n_hits; ++i) {
       const HitRec& h = rec[i];
       uint8_t fl = 0;
       if (h.use && pmay[size_t(tp) * n_hits + i]) {
-        const Iv G = residual_G(f, h);
-        if (h.axial) {
-          fl = (h_contains0(G, f.K, f.sig * h.d, h.band) || h_contains0(G, f.K, f.sig * (-h.d), h.band)) ? 1 : 0;
-        } else {
+        // the kernels' two stages
+        int c = f32 ? pair_stage1<true>(f, gt, h, Zr, Lr, filter, slack32, nullptr)
+                    : pair_stage1<false>(f, gt, h, Zr, Lr, filter, slack32, nullptr);
+        if (c < 0)
+          c = f32 ? pair_stage2<true>(f, h, Zr, Lr, slack32, nullptr) : pair_stage2<false>(f, h, Zr, Lr, slack32, nullptr);
+        fl = static_cast<uint8_t>(c);
+        if (!h.axial) {
           ++n_pairs;
-          if (f32 && !(f.R <= kR32Max)) fl = 1;
-          else if (!filter) fl = 2;
-          else {
-            const PairQ q = pair_quantities(f, h, G);
-            fl = static_cast<uint8_t>(f32 ? triple_vote_class32(q, f, h, Zr, Lr, slack32)
-                                          : triple_vote_class(q, f, h, Zr, Lr));
-          }
           n_cut += fl == 0;
           n_incl += fl == 1;
         }
@@ -201,6 +198,34 @@ int32_t hc_e_magnitude(const double* hit, const double* parent, const int32_t sp
   out[1] = em.eps;
   out[2] = em.disc_lo;
   return 1;
+}
+
+}  // extern "C"
+
+extern "C" {
+
+// residual_G and residual_G_outer of each (triple, hit) pair of one level:
+// out[4 (t n_hits + i) ..] = G.lo, G.hi, Go.lo, Go.hi (0 for unused hits)
+int32_t hc_g_pairs(const double* hits, int32_t n_hits, const double* parent, const int32_t split[5], double* out) {
+  Shape sh;
+  if (!make_shape(split, 1, &sh)) return 1;
+  std::vector<HitRec> rec(n_hits > 0 ? n_hits : 1);
+  for (int32_t i = 0; i < n_hits; ++i) {
+    bool bad;
+    prep_one(hits + 8 * i, true, &rec[i], &bad);
+  }
+  const BoxD& P = *reinterpret_cast<const BoxD*>(parent);
+  for (uint32_t tc = 0; tc < sh.m012; ++tc) {
+    const Frame f = triple_frame(P, sh.m, tc / sh.m12, (tc / sh.m[2]) % sh.m[1], tc % sh.m[2]);
+    const GTri g = g_triple(f);
+    for (int32_t i = 0; i < n_hits; ++i) {
+      double* o = out + 4 * (size_t(tc) * n_hits + i);
+      if (!rec[i].use) { o[0] = o[1] = o[2] = o[3] = 0.0; continue; }
+      const Iv G = residual_G(f, rec[i]), Go = residual_G_outer(f, g, rec[i]);
+      o[0] = G.lo; o[1] = G.hi; o[2] = Go.lo; o[3] = Go.hi;
+    }
+  }
+  return 0;
 }
 
 }  // extern "C"

@@ -336,11 +336,12 @@ def test_parent_filter_does_not_change_results(ctx):
 
 def test_classification_counters_and_timing(ctx):
     """The classification's work counters and the per-kernel timing record
-    of one ia_vote_level call: one residual G per (triple, used hit), one
-    axial test per axial pair, one set of pair quantities and one magnitude
-    bound per stereo pair in the first stage; in the second, at most two
-    enclosures and as many inclusion proofs per deferred pair; one timed
-    launch each of the two stages and of the vote."""
+    of one ia_vote_level call: one outer residual G per (triple, used hit),
+    one axial test per axial pair (and an exact G for some of them), one set
+    of pair magnitudes and one magnitude bound per stereo pair in the first
+    stage; in the second, at most two enclosures and as many inclusion proofs
+    per deferred pair; one timed launch each of the two stages and of the
+    vote."""
     torch = _torch()
     ev = toymc.config_event(2, 3)
     prep = oracle.prep_hits(ev.hits)
@@ -365,7 +366,7 @@ def test_classification_counters_and_timing(ctx):
     assert kp[("classify_defer", "fp64")][0] == 1
     assert kp[("classify", "fp32")][0] == 0 and kp[("classify", "fp64")][1] > 0
     assert cw["G"] == n_tr * (n_ax + n_st)
-    assert cw["axial"] == n_tr * n_ax
+    assert cw["axial"] == n_tr * n_ax and 0 < cw["G_exact"] < cw["axial"]
     assert cw["pairq"] == n_tr * n_st
     assert cw["magnitudes"] == cw["pairq"]
     assert 0 < cw["deferred"] < cw["pairq"]

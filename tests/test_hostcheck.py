@@ -214,3 +214,29 @@ def test_tie_cut_keeps_selection(orc, cfg, ev_i, f32):
         assert np.array_equal(ti_r, ti_g) and np.array_equal(tv_r, tv_g)
         assert got.max() == ref.max()
         assert st[6] <= st0[6]
+
+
+def test_outer_residual_contains_residual(orc):
+    """The first stage's outer enclosure of G holds residual_G's interval for
+    every pair: boxes at random places (phi0 ranges holding the extrema of
+    the sine and not), widths from 1e-6 to 0.9 rad, hits of several events;
+    and it is not much wider."""
+    rng = np.random.default_rng(21)
+    n_checked, worst = 0, 0.0
+    events = [toymc.config_event(4, i) for i in (3, 7)] + [toymc.config_event(2, 1)]
+    for trial in range(40):
+        lo, hi = H.LO.copy(), H.HI.copy()
+        w = 10 ** rng.uniform(-6, np.log10(0.9))
+        lo[1] = rng.uniform(0, 2 * np.pi)
+        hi[1] = lo[1] + w
+        k = rng.uniform(-0.6, 0.5)
+        lo[2], hi[2] = k, k + 10 ** rng.uniform(-4, -1)
+        box = orc.make_box(lo, hi)
+        ev = events[trial % len(events)]
+        g = hostcheck.g_pairs(ev.hits, box, [2, 3, 2, 1, 1])
+        used = np.any(g != 0, axis=2)
+        assert np.all(g[..., 2][used] <= g[..., 0][used]) and np.all(g[..., 3][used] >= g[..., 1][used])
+        n_checked += int(used.sum())
+        worst = max(worst, float(np.max((g[..., 3] - g[..., 2]) - (g[..., 1] - g[..., 0]))))
+    assert n_checked > 5000
+    assert worst < 1e-12
