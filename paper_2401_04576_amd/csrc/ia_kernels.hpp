@@ -1142,7 +1142,7 @@ constexpr int32_t kDeferPer = 16;
 constexpr int32_t kDeferChunk = kDeferPer * kWG;
 
 template <bool F32, bool COUNT>
-__global__ void __launch_bounds__(kWG) k_classify_defer(const HitRec* __restrict__ hits, EvView vw,
+__global__ void __launch_bounds__(kWG, 3) k_classify_defer(const HitRec* __restrict__ hits, EvView vw,
                                                         const BoxD* __restrict__ parents, Shape sh,
                                                         uint8_t* __restrict__ flags, int32_t* __restrict__ tlb,
                                                         int32_t* __restrict__ tn2, int32_t per,
@@ -1441,25 +1441,27 @@ __global__ void __launch_bounds__(kWG) k_stage(const HitRec* __restrict__ hits, 
 // until all count(> v*) boxes and the first (k - count(> v*)) boxes at v*
 // are collected (at most k workgroups hold boxes above v*).  Then the entries
 // are ordered, the selected boxes written, the histogram cleared and, for
-// level 0, the event stopped when its maximum is below v_min.
+// level 0, the event stopped when its maximum is below v_min.  k <= vw.k
+// boxes are selected (vw.k is the per-event stride of the outputs); the
+// histogram must count at least min(k, n_boxes) boxes.
 __global__ void __launch_bounds__(kWG) k_select_wg(const uint16_t* __restrict__ votes, EvView vw,
                                                    uint32_t* __restrict__ hist, const int32_t* __restrict__ wg_max,
                                                    uint32_t n_wg, int32_t bx, const BoxD* __restrict__ parents,
                                                    Shape sh, BoxD* __restrict__ out_boxes,
                                                    int64_t* __restrict__ out_index, uint16_t* __restrict__ out_votes,
                                                    EventState* __restrict__ ev, int32_t v_min_stop,
-                                                   int32_t* __restrict__ tlb, int32_t* __restrict__ tn2) {
+                                                   int32_t* __restrict__ tlb, int32_t* __restrict__ tn2, int32_t k) {
   const int e = blockIdx.y;
   if (ev && ev[e].done) return;
   const uint32_t n_boxes = sh.n_boxes;
-  const int32_t n_bins = vw.count(e) + 1, k = vw.k;
+  const int32_t n_bins = vw.count(e) + 1;
   votes += int64_t(e) * n_boxes;
   hist += int64_t(e) * vw.hist_stride;
   wg_max += int64_t(e) * vw.wg_stride;
   parents += e * vw.par_stride;
-  out_boxes += int64_t(e) * k;
-  out_index += int64_t(e) * k;
-  out_votes += int64_t(e) * k;
+  out_boxes += int64_t(e) * vw.k;
+  out_index += int64_t(e) * vw.k;
+  out_votes += int64_t(e) * vw.k;
   if (ev) ev += e;
   __shared__ SelInfo si;
   __shared__ int32_t sbuf[kWG / 64];

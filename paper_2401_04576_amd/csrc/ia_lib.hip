@@ -564,10 +564,15 @@ ia_status run_chunk(ia_ctx* c, const double* hits_chunk, const int32_t* h_off_ch
         if (cs != IA_OK) return cs;
       }
       const int32_t vt = vote_tile(c, sh.n_boxes);
-      // the last level's max-vote set feeds the estimate: no tie cut there
-      const int32_t ties = lev < sc->n_refine ? 1 : 0;
-      hipLaunchKernelGGL(ia::k_threshold, dim3(1, E), dim3(ia::kWG), 0, s, tlb, tn2, lbh, vw, sh, K, c->prune, ties,
-                         vt, ev, live, wg_max, rin.live_tri, rin.rec_off, rin.rec_fill, L.rec_stride);
+      // the last level feeds only the estimate, which needs the whole
+      // max-vote set and the first max-vote box: there the selection keeps
+      // one box, so that T is the largest lower bound (a box whose upper
+      // bound is below it cannot reach the maximum), and no tie cut applies
+      const bool last = lev == sc->n_refine;
+      const int32_t k_lev = last ? 1 : K;
+      const int32_t ties = last ? 0 : 1;
+      hipLaunchKernelGGL(ia::k_threshold, dim3(1, E), dim3(ia::kWG), 0, s, tlb, tn2, lbh, vw, sh, k_lev, c->prune,
+                         ties, vt, ev, live, wg_max, rin.live_tri, rin.rec_off, rin.rec_fill, L.rec_stride);
       launch_stage(recs, vw, E, par, sh, flags, rin, ev, s, f32, slack32);
       const VoteIn in{flags, tlb, tn2, live, 1};
       ia_status st = launch_vote_rec(c, vw, E, par, sh, votes, hist, ev, in, rin, wg_max, s, f32);
@@ -580,7 +585,7 @@ ia_status run_chunk(ia_ctx* c, const double* hits_chunk, const int32_t* h_off_ch
       last_bx = bx;
       const uint32_t n_wg = (sh.n_boxes + bx - 1) / bx;
       hipLaunchKernelGGL(ia::k_select_wg, dim3(1, E), dim3(ia::kWG), 0, s, votes, vw, hist, wg_max, n_wg, bx, par,
-                         sh, sel, sel_idx, sel_v, ev, lev == 0 ? std::max(sc->v_min, 0) : 0, tlb, tn2);
+                         sh, sel, sel_idx, sel_v, ev, lev == 0 ? std::max(sc->v_min, 0) : 0, tlb, tn2, k_lev);
       IA_HIP(c, hipGetLastError());
       if (lev == sc->n_refine) break;
       const int32_t k_eff = static_cast<int32_t>(std::min<int64_t>(K, sh.n_boxes));
