@@ -84,14 +84,14 @@ FLOP_BOX_STEREO32 = 278
 FLOP_CLS_G, FLOP_CLS_AXIAL, FLOP_CLS_PAIRQ, FLOP_CLS_ENCL, FLOP_CLS_INCL, FLOP_CLS_MAG = 157, 92, 69, 688, 94, 113
 FLOP_CLS_FRAME, FLOP_CLS_GOUT, FLOP_CLS_PAIRMAG = 130, 68, 34
 PEAK_FP64_TFLOPS = 78.6   # MI355X vector FP64: 256 CU x 128 FLOP/clk x 2.4 GHz
-# HBM bytes per launch of the FP64 classification over 1024-event batches of
-# the default workload: rocprofv3 --pmc FETCH_SIZE, then WRITE_SIZE, averaged
-# over those launches and scaled by 2.0 and 1.0 (what the two counters read
-# for a copy of 1 GiB, bench.py --workload copy).  Valid only for the kernel
-# sources they were measured on (SHA-256 of ia_math.hpp + ia_kernels.hpp).
-TRAFFIC_CLASSIFY = {"workload": "event", "events_per_step": 1024,
-                    "sources_sha256": "475d5b67480e54ed519bebede6c0ce0b52e998e6286b4025a67a637df2594b11",
-                    "fetch_bytes": 44199347, "write_bytes": 75287949}
+# HBM bytes per launch of the default workload's dominant kernel over
+# 1024-event batches: rocprofv3 --pmc FETCH_SIZE, then WRITE_SIZE, averaged
+# over those launches and scaled by what the two counters read for a copy of
+# 1 GiB (bench.py --workload copy).  Valid only for the kernel sources they
+# were measured on (SHA-256 of ia_math.hpp + ia_kernels.hpp).
+TRAFFIC = {"kernel": "k_classify_defer (fp64 levels)", "workload": "event", "events_per_step": 1024,
+           "sources_sha256": "3ec0fcd537c20fd8bd46b1ecae63c532a15103ff9cab827d6df782ddb13e53b5",
+           "fetch_bytes": 97016233, "write_bytes": 268618112}
 PEAK_FP32_TFLOPS = 157.3  # MI355X vector FP32 (non-packed)
 
 
@@ -112,15 +112,15 @@ def kernel_sources_sha256():
     return h.hexdigest()
 
 
-def classify_traffic(workload, events_per_step):
-    """Measured HBM bytes per classification launch, or None when the
-    workload or the kernel sources differ from those of the measurement."""
-    t = TRAFFIC_CLASSIFY
+def measured_traffic(workload, events_per_step):
+    """(kernel, measured HBM bytes per launch), or None when the workload or
+    the kernel sources differ from those of the measurement."""
+    t = TRAFFIC
     if workload != t["workload"] or events_per_step != t["events_per_step"]:
         return None
     if kernel_sources_sha256() != t["sources_sha256"]:
         return None
-    return t["fetch_bytes"] + t["write_bytes"]
+    return t["kernel"], t["fetch_bytes"] + t["write_bytes"]
 
 
 def classify_flops(cw):
@@ -135,7 +135,7 @@ def defer_flops(cw):
             + cw["enclosures"] * FLOP_CLS_ENCL + cw["inclusions"] * FLOP_CLS_INCL)
 
 
-def roofline(kprof, work, cwork, wall, measured_on, traffic_classify=None):
+def roofline(kprof, work, cwork, wall, measured_on, traffic=None):
     """Roofline object of the dominant kernel: of the vote kernel and the
     (triple, hit) classification at FP64 and FP32 levels, the one with the
     largest summed launch time (HIP events around each launch).  Achieved =
@@ -167,7 +167,7 @@ def roofline(kprof, work, cwork, wall, measured_on, traffic_classify=None):
                     "launches": n, "total_ms": ms, **cwork[p]}
     dom = max(parts, key=lambda k: parts[k]["total_ms"])
     d = parts[dom]
-    traffic = traffic_classify if dom == "k_classify (fp64 levels)" else None
+    traffic = traffic[1] if traffic and traffic[0] == dom else None
     return {"bound": "alu", "achieved": d["achieved"], "peak": d["peak"], "unit": "TFLOP/s", "frac": d["frac"],
             "traffic": traffic, "traffic_unit": "bytes per launch (HBM, rocprofv3 FETCH_SIZE + WRITE_SIZE, scaled)",
             "kernel": dom, "avg_launch_ms": d["avg_launch_ms"], "launches": d["launches"],
@@ -442,7 +442,7 @@ def run_event(args):
         "latency": "p50/p99: one event per call, arrival of resident hits to its recorded helix",
         "roofline": roofline(kprof, work, cwork, wall,
                              "repeat of the timed steps: HIP events around each launch, then a work-counting run",
-                             classify_traffic("event", B)),
+                             measured_traffic("event", B)),
     }
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(batches[args.warmup][0], sched_kw, lo, hi, args.cpu_budget)
