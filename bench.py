@@ -291,7 +291,7 @@ def main():
                     help="single-helix workload: single-event calls timed for p50/p99 latency")
     ap.add_argument("--scratch-gb", type=float, default=16.0)
     ap.add_argument("--serve-events", type=int, default=4096)
-    ap.add_argument("--rate", type=float, default=20000.0, help="serving: Poisson arrival rate, events/s")
+    ap.add_argument("--rate", type=float, default=1000.0, help="serving: Poisson arrival rate, events/s")
     ap.add_argument("--slots", type=int, default=4, help="serving: concurrent batches")
     ap.add_argument("--report-events", type=int, default=1000, help="mixed-report: noiseless single-helix events")
     ap.add_argument("--no-autotune", action="store_true", help="skip the vote-tile autotuner")

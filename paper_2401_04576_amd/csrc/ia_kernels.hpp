@@ -2156,7 +2156,17 @@ __global__ void __launch_bounds__(kWG) k_est_partial(const BoxD* __restrict__ pa
   for (int q = 0; q < 5; ++q) { v[q] = 0.0; v[5 + q] = INFINITY; v[10 + q] = -INFINITY; }
   v[15] = 0.0;
   // with wg_max, only tiles whose maximum reaches vmax hold written votes
-  if (i < sh.n_boxes && (!wg_max || wg_max[i / static_cast<uint32_t>(bx)] >= vmax) && votes[i] == vmax) {
+  const bool at_max = i < sh.n_boxes && (!wg_max || wg_max[i / static_cast<uint32_t>(bx)] >= vmax) && votes[i] == vmax;
+  // a chunk without a max-vote box reduces to the identity (sums 0, minima
+  // +inf, maxima -inf, count 0), bit for bit: write it without the tree
+  if (!__syncthreads_or(at_max ? 1 : 0)) {
+    if (threadIdx.x < kEstQ) {
+      const int q = static_cast<int>(threadIdx.x);
+      part[blockIdx.x * kEstQ + q] = (q >= 5 && q < 10) ? INFINITY : ((q >= 10 && q < 15) ? -INFINITY : 0.0);
+    }
+    return;
+  }
+  if (at_max) {
     BoxD box;
     level_box(parents, sh, i, &box);
     for (int j = 0; j < 5; ++j) {
