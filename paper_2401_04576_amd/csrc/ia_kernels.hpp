@@ -1770,34 +1770,21 @@ __global__ void __launch_bounds__(kWG) k_vote(const HitRec* __restrict__ hits, E
 // from k_stage, copied to LDS a chunk at a time, and the triple's frame
 // comes from its TriFrame, so the kernel holds only the per-box arithmetic.
 template <int BX, bool F32>
-__global__ void __launch_bounds__(kWG) k_vote_rec(EvView vw, const BoxD* __restrict__ parents, Shape sh,
-                                                  uint16_t* __restrict__ votes, uint32_t* __restrict__ hist,
+__global__ void __launch_bounds__(kWG) k_vote_rec(EvView vw, const BoxD* __restrict__ parents_all, Shape sh,
+                                                  uint16_t* __restrict__ votes_all, uint32_t* __restrict__ hist_all,
                                                   uint32_t* __restrict__ status, const EventState* __restrict__ ev,
-                                                  const int32_t* __restrict__ tlb, const int32_t* __restrict__ tn2,
-                                                  const int32_t* __restrict__ live_list,
-                                                  const int32_t* __restrict__ rec_off, const void* __restrict__ rec,
-                                                  const TriFrame* __restrict__ tfr, int32_t* __restrict__ wg_max,
+                                                  const int32_t* __restrict__ tlb_all,
+                                                  const int32_t* __restrict__ tn2_all,
+                                                  const int32_t* __restrict__ live_all,
+                                                  const int32_t* __restrict__ live_off, int32_t n_ev,
+                                                  const int32_t* __restrict__ rec_off_all, const void* __restrict__ rec,
+                                                  const TriFrame* __restrict__ tfr_all,
+                                                  int32_t* __restrict__ wg_max_all,
                                                   unsigned long long* __restrict__ work) {
   constexpr int HS = kWG / BX;
   constexpr int NQ = F32 ? 8 : 16;               // doubles of LDS per staged record
   static_assert(BX % 64 == 0 && HS * BX == kWG, "slices are whole waves");
-  const int e = blockIdx.y;
-  if (ev[e].done || !ev[e].rec_ok) return;
-  const int32_t n_hits = vw.count(e), n_bins = n_hits + 1;
-  parents += e * vw.par_stride;
-  votes += int64_t(e) * sh.n_boxes;
-  if (hist) hist += int64_t(e) * vw.hist_stride;
-  tlb += e * vw.tri_stride;
-  tn2 += e * vw.tri_stride;
-  rec_off += e * vw.tri_stride;
-  tfr += e * vw.tri_stride;
-  wg_max += int64_t(e) * vw.wg_stride;
-  live_list += int64_t(e) * vw.wg_stride;
-  const RecD* recd = reinterpret_cast<const RecD*>(rec) + int64_t(e) * vw.rec_stride;
-  const PairQ32* recf = reinterpret_cast<const PairQ32*>(rec) + int64_t(e) * vw.rec_stride;
-  const int32_t T = ev[e].t_prune;
-  const int32_t tcut = ev[e].t_cut;
-  const uint32_t n_items = static_cast<uint32_t>(ev[e].n_live);
+  const uint32_t n_items = static_cast<uint32_t>(live_off[n_ev]);
   __shared__ double sq[NQ][kCap + 16];
   float(*sq32)[kCap + 16] = reinterpret_cast<float(*)[kCap + 16]>(&sq[0][0]);
   __shared__ int8_t sflag[kCap + 16];
@@ -1811,7 +1798,28 @@ __global__ void __launch_bounds__(kWG) k_vote_rec(EvView vw, const BoxD* __restr
   int32_t n_eval = 0;
 
   for (uint32_t item = blockIdx.x; item < n_items; item += gridDim.x) {
-    const uint32_t tile = static_cast<uint32_t>(live_list[item]);
+    // the item's event: the last one whose first item is at or before it
+    int32_t elo = 0, ehi = n_ev - 1;
+    while (elo < ehi) {
+      const int32_t mid = (elo + ehi + 1) >> 1;
+      if (static_cast<uint32_t>(live_off[mid]) <= item) elo = mid;
+      else ehi = mid - 1;
+    }
+    const int e = elo;
+    const int32_t n_hits = vw.count(e), n_bins = n_hits + 1;
+    const BoxD* parents = parents_all + e * vw.par_stride;
+    uint16_t* votes = votes_all + int64_t(e) * sh.n_boxes;
+    uint32_t* hist = hist_all ? hist_all + int64_t(e) * vw.hist_stride : nullptr;
+    const int32_t* tlb = tlb_all + e * vw.tri_stride;
+    const int32_t* tn2 = tn2_all + e * vw.tri_stride;
+    const int32_t* rec_off = rec_off_all + e * vw.tri_stride;
+    const TriFrame* tfr = tfr_all + e * vw.tri_stride;
+    int32_t* wg_max = wg_max_all + int64_t(e) * vw.wg_stride;
+    const RecD* recd = reinterpret_cast<const RecD*>(rec) + int64_t(e) * vw.rec_stride;
+    const PairQ32* recf = reinterpret_cast<const PairQ32*>(rec) + int64_t(e) * vw.rec_stride;
+    const int32_t T = ev[e].t_prune;
+    const int32_t tcut = ev[e].t_cut;
+    const uint32_t tile = static_cast<uint32_t>(live_all[int64_t(e) * vw.wg_stride + (item - live_off[e])]);
     const uint32_t b0 = tile * BX;
     const uint32_t b_last = min(b0 + BX, sh.n_boxes) - 1;
     const uint32_t b = b0 + bl;
@@ -1946,10 +1954,32 @@ __global__ void __launch_bounds__(kWG) k_vote_rec(EvView vw, const BoxD* __restr
     if (tid == 0) {
       int32_t sa = 0;
       for (int w = 0; w < kWG / 64; ++w) sa += sbuf[w];
-      unsigned long long* slot = work + kWorkSlotU64 * ((blockIdx.x + blockIdx.y * 7u) % kWorkSlots);
+      unsigned long long* slot = work + kWorkSlotU64 * (blockIdx.x % kWorkSlots);
       if (sa) atomicAdd(&slot[F32 ? 2 : 0], static_cast<unsigned long long>(sa));
     }
   }
+}
+
+// Offsets of each event's live vote tiles in one list over the batch:
+// live_off[e] = the live tiles of the events before e, live_off[n_ev] = all
+// of them (events that are done, or whose records did not fit, count none),
+// so that the vote kernel's workgroups share the batch's tiles evenly.
+// One workgroup.
+__global__ void __launch_bounds__(kWG) k_live_offsets(const EventState* __restrict__ ev, int32_t n_ev,
+                                                      int32_t* __restrict__ live_off) {
+  __shared__ int32_t sbuf[kWG / 64];
+  const int32_t per = (n_ev + kWG - 1) / kWG;
+  const int32_t a = min(static_cast<int32_t>(threadIdx.x) * per, n_ev), b = min(a + per, n_ev);
+  auto count = [&](int32_t e) { return (ev[e].done || !ev[e].rec_ok) ? 0 : ev[e].n_live; };
+  int32_t c = 0;
+  for (int32_t e = a; e < b; ++e) c += count(e);
+  int32_t pos;
+  const int32_t total = block_scan_count(c, &pos, sbuf);
+  for (int32_t e = a; e < b; ++e) {
+    live_off[e] = pos;
+    pos += count(e);
+  }
+  if (threadIdx.x == 0) live_off[n_ev] = total;
 }
 
 // ---------------------------------------------------------------------------

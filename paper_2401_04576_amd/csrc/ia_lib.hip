@@ -328,6 +328,7 @@ struct RecIn {                    // per-level staged-record buffers
   int32_t* rec_fill;
   void* rec;
   ia::TriFrame* tfr;
+  int32_t* live_off;              // n_ev + 1 offsets of the events' live tiles in one list
 };
 
 void launch_stage(const HitRec* recs, const ia::EvView& vw, int32_t n_ev, const BoxD* par, const Shape& sh,
@@ -343,21 +344,21 @@ void launch_stage(const HitRec* recs, const ia::EvView& vw, int32_t n_ev, const 
 }
 
 template <bool F32>
-void launch_vote_rec_tile(int32_t bx, dim3 g, hipStream_t s, const ia::EvView& vw, const BoxD* par, const Shape& sh,
-                          uint16_t* votes, uint32_t* hist, uint32_t* st, const EventState* ev, const VoteIn& in,
-                          const RecIn& r, int32_t* wg_max, unsigned long long* wk) {
+void launch_vote_rec_tile(int32_t bx, dim3 g, hipStream_t s, const ia::EvView& vw, int32_t n_ev, const BoxD* par,
+                          const Shape& sh, uint16_t* votes, uint32_t* hist, uint32_t* st, const EventState* ev,
+                          const VoteIn& in, const RecIn& r, int32_t* wg_max, unsigned long long* wk) {
   switch (bx) {
     case 256:
       hipLaunchKernelGGL((ia::k_vote_rec<256, F32>), g, dim3(ia::kWG), 0, s, vw, par, sh, votes, hist, st, ev, in.tlb,
-                         in.tn2, in.live_list, r.rec_off, r.rec, r.tfr, wg_max, wk);
+                         in.tn2, in.live_list, r.live_off, n_ev, r.rec_off, r.rec, r.tfr, wg_max, wk);
       break;
     case 128:
       hipLaunchKernelGGL((ia::k_vote_rec<128, F32>), g, dim3(ia::kWG), 0, s, vw, par, sh, votes, hist, st, ev, in.tlb,
-                         in.tn2, in.live_list, r.rec_off, r.rec, r.tfr, wg_max, wk);
+                         in.tn2, in.live_list, r.live_off, n_ev, r.rec_off, r.rec, r.tfr, wg_max, wk);
       break;
     default:
       hipLaunchKernelGGL((ia::k_vote_rec<64, F32>), g, dim3(ia::kWG), 0, s, vw, par, sh, votes, hist, st, ev, in.tlb,
-                         in.tn2, in.live_list, r.rec_off, r.rec, r.tfr, wg_max, wk);
+                         in.tn2, in.live_list, r.live_off, n_ev, r.rec_off, r.rec, r.tfr, wg_max, wk);
       break;
   }
 }
@@ -368,7 +369,10 @@ ia_status launch_vote_rec(ia_ctx* c, const ia::EvView& vw, int32_t n_ev, const B
                           int32_t* wg_max, hipStream_t s, bool f32) {
   const int32_t bx = vote_tile(c, sh.n_boxes);
   const uint32_t n_tiles = (sh.n_boxes + bx - 1) / bx;
-  const uint32_t grid = std::max<uint32_t>(1, std::min<uint32_t>(n_tiles, (kVoteGroups + n_ev - 1) / std::max(1, n_ev)));
+  // the batch's live tiles in one list, shared by all workgroups
+  hipLaunchKernelGGL(ia::k_live_offsets, dim3(1), dim3(ia::kWG), 0, s, ev, n_ev, r.live_off);
+  const uint32_t grid = static_cast<uint32_t>(
+      std::max<int64_t>(1, std::min<int64_t>(int64_t(n_tiles) * std::max(1, n_ev), kVoteGroups)));
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (c->profiling) {
     IA_HIP(c, hipEventCreate(&e0));
@@ -377,9 +381,9 @@ ia_status launch_vote_rec(ia_ctx* c, const ia::EvView& vw, int32_t n_ev, const B
   }
   uint32_t* st = &persistent(c)->status;
   unsigned long long* wk = persistent(c)->work;
-  const dim3 g(grid, n_ev);
-  if (f32) launch_vote_rec_tile<true>(bx, g, s, vw, par, sh, votes, hist, st, ev, in, r, wg_max, wk);
-  else launch_vote_rec_tile<false>(bx, g, s, vw, par, sh, votes, hist, st, ev, in, r, wg_max, wk);
+  const dim3 g(grid, 1);
+  if (f32) launch_vote_rec_tile<true>(bx, g, s, vw, n_ev, par, sh, votes, hist, st, ev, in, r, wg_max, wk);
+  else launch_vote_rec_tile<false>(bx, g, s, vw, n_ev, par, sh, votes, hist, st, ev, in, r, wg_max, wk);
   if (c->profiling) {
     IA_HIP(c, hipEventRecord(e1, s));
     c->marks.push_back({e0, e1, f32, sh.n_boxes, IA_KERNEL_VOTE});
@@ -392,7 +396,7 @@ ia_status launch_vote_rec(ia_ctx* c, const ia::EvView& vw, int32_t n_ev, const B
 // arena): per-event slices of every array, sized for events of max_hits hits
 struct FindLayout {
   size_t off, recs, votes, hist, lbh, selA, selB, range, sel_idx, sel_v, ev, part, flags, tlb, tn2, wg_max, live,
-      live_tri, rec_off, rec_fill, tfr, rec, pflags, total;
+      live_tri, rec_off, rec_fill, tfr, rec, pflags, live_off, total;
   int64_t flag_stride, tri_stride, votes_stride, rec_stride, pflag_stride;
   int32_t hist_stride, wg_stride, part_stride, n_part;
 };
@@ -439,6 +443,7 @@ void layout_find(int64_t max_level_boxes, int64_t max_triples, int32_t top_k, in
   L->tfr = take(sizeof(ia::TriFrame) * size_t(L->tri_stride) * E);
   L->rec = take(sizeof(ia::RecD) * size_t(L->rec_stride) * E);
   L->pflags = take(size_t(L->pflag_stride) * E);
+  L->live_off = take(sizeof(int32_t) * (E + 1));
   L->total = off;
 }
 
@@ -506,7 +511,7 @@ ia_status run_chunk(ia_ctx* c, const double* hits_chunk, const int32_t* h_off_ch
   int32_t* live = reinterpret_cast<int32_t*>(a + L.live);
   const RecIn rin{reinterpret_cast<int32_t*>(a + L.live_tri), reinterpret_cast<int32_t*>(a + L.rec_off),
                   reinterpret_cast<int32_t*>(a + L.rec_fill), a + L.rec,
-                  reinterpret_cast<ia::TriFrame*>(a + L.tfr)};
+                  reinterpret_cast<ia::TriFrame*>(a + L.tfr), reinterpret_cast<int32_t*>(a + L.live_off)};
   if (!dev_off) {
     // chunk-relative hit offsets through a pinned slot whose last copy is done
     const uint32_t slot = c->slot_next++ % kOffSlots;
