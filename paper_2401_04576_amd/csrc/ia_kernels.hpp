@@ -1388,28 +1388,35 @@ __global__ void __launch_bounds__(kWG) k_threshold(const int32_t* __restrict__ t
 // (slots taken in any order: votes do not depend on it).  Every writer of a
 // triple also writes the same TriFrame.  Events with rec_ok == 0 are skipped.
 template <bool F32>
-__global__ void __launch_bounds__(kWG) k_stage(const HitRec* __restrict__ hits, EvView vw,
-                                               const BoxD* __restrict__ parents, Shape sh,
-                                               const uint8_t* __restrict__ flags, const int32_t* __restrict__ live_tri,
-                                               const int32_t* __restrict__ rec_off, int32_t* __restrict__ rec_fill,
-                                               void* __restrict__ rec, TriFrame* __restrict__ tfr,
-                                               const EventState* __restrict__ ev, float slack32) {
-  const int e = blockIdx.y;
-  if (ev[e].done || !ev[e].rec_ok) return;
-  const int32_t n_hits = vw.count(e);
-  if (n_hits <= 0) return;
-  hits += vw.beg(e);
-  parents += e * vw.par_stride;
-  flags += e * vw.flag_stride;
-  live_tri += e * vw.tri_stride;
-  rec_off += e * vw.tri_stride;
-  rec_fill += e * vw.tri_stride;
-  tfr += e * vw.tri_stride;
+__global__ void __launch_bounds__(kWG) k_stage(const HitRec* __restrict__ hits_all, EvView vw,
+                                               const BoxD* __restrict__ parents_all, Shape sh,
+                                               const uint8_t* __restrict__ flags_all,
+                                               const int32_t* __restrict__ live_tri_all,
+                                               const int32_t* __restrict__ rec_off_all,
+                                               int32_t* __restrict__ rec_fill_all, void* __restrict__ rec,
+                                               TriFrame* __restrict__ tfr_all, const int64_t* __restrict__ stage_off,
+                                               int32_t n_ev, float slack32) {
   const uint32_t n_tr = sh.n_parents * sh.m012;
-  const int64_t n_items = static_cast<int64_t>(ev[e].n_live_tri) * n_hits;
+  const int64_t n_items = stage_off[n_ev];
   for (int64_t i = int64_t(blockIdx.x) * kWG + threadIdx.x; i < n_items; i += int64_t(gridDim.x) * kWG) {
-    const uint32_t t = static_cast<uint32_t>(live_tri[i / n_hits]);
-    const int32_t h = static_cast<int32_t>(i % n_hits);
+    // the item's event: the last one whose first item is at or before it
+    int32_t elo = 0, ehi = n_ev - 1;
+    while (elo < ehi) {
+      const int32_t mid = (elo + ehi + 1) >> 1;
+      if (stage_off[mid] <= i) elo = mid;
+      else ehi = mid - 1;
+    }
+    const int e = elo;
+    const int32_t n_hits = vw.count(e);
+    const int64_t il = i - stage_off[e];
+    const HitRec* hits = hits_all + vw.beg(e);
+    const BoxD* parents = parents_all + e * vw.par_stride;
+    const uint8_t* flags = flags_all + e * vw.flag_stride;
+    const int32_t* rec_off = rec_off_all + e * vw.tri_stride;
+    int32_t* rec_fill = rec_fill_all + e * vw.tri_stride;
+    TriFrame* tfr = tfr_all + e * vw.tri_stride;
+    const uint32_t t = static_cast<uint32_t>(live_tri_all[e * vw.tri_stride + il / n_hits]);
+    const int32_t h = static_cast<int32_t>(il % n_hits);
     if (flags[int64_t(h) * n_tr + t] != 2) continue;
     const HitRec hr = hits[h];
     const uint32_t tc = t % sh.m012;
@@ -1960,24 +1967,44 @@ __global__ void __launch_bounds__(kWG) k_vote_rec(EvView vw, const BoxD* __restr
   }
 }
 
-// Offsets of each event's live vote tiles in one list over the batch:
-// live_off[e] = the live tiles of the events before e, live_off[n_ev] = all
-// of them (events that are done, or whose records did not fit, count none),
-// so that the vote kernel's workgroups share the batch's tiles evenly.
-// One workgroup.
-__global__ void __launch_bounds__(kWG) k_live_offsets(const EventState* __restrict__ ev, int32_t n_ev,
-                                                      int32_t* __restrict__ live_off) {
+// Offsets of each event's work items in one list over the batch, so that
+// the workgroups of k_stage and of the vote kernel share the batch's items
+// evenly: live_off[e] counts the live vote tiles of the events before e,
+// stage_off[e] their (live triple, hit) pairs, and entry n_ev the totals.
+// Events that are done, or whose records did not fit, count none.  One
+// workgroup.
+__global__ void __launch_bounds__(kWG) k_live_offsets(const EventState* __restrict__ ev, EvView vw, int32_t n_ev,
+                                                      int32_t* __restrict__ live_off,
+                                                      int64_t* __restrict__ stage_off) {
   __shared__ int32_t sbuf[kWG / 64];
+  __shared__ int64_t s64[kWG];
   const int32_t per = (n_ev + kWG - 1) / kWG;
   const int32_t a = min(static_cast<int32_t>(threadIdx.x) * per, n_ev), b = min(a + per, n_ev);
-  auto count = [&](int32_t e) { return (ev[e].done || !ev[e].rec_ok) ? 0 : ev[e].n_live; };
+  auto skip = [&](int32_t e) { return ev[e].done || !ev[e].rec_ok; };
+  auto tiles = [&](int32_t e) { return skip(e) ? 0 : ev[e].n_live; };
+  auto pairs = [&](int32_t e) {
+    return skip(e) ? int64_t(0) : static_cast<int64_t>(ev[e].n_live_tri) * max(vw.count(e), 0);
+  };
   int32_t c = 0;
-  for (int32_t e = a; e < b; ++e) c += count(e);
+  int64_t c2 = 0;
+  for (int32_t e = a; e < b; ++e) { c += tiles(e); c2 += pairs(e); }
   int32_t pos;
   const int32_t total = block_scan_count(c, &pos, sbuf);
+  // 64-bit exclusive scan of the pair counts (serial over the kWG partials)
+  s64[threadIdx.x] = c2;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int64_t run = 0;
+    for (int w = 0; w < kWG; ++w) { const int64_t x = s64[w]; s64[w] = run; run += x; }
+    stage_off[n_ev] = run;
+  }
+  __syncthreads();
+  int64_t pos2 = s64[threadIdx.x];
   for (int32_t e = a; e < b; ++e) {
     live_off[e] = pos;
-    pos += count(e);
+    pos += tiles(e);
+    stage_off[e] = pos2;
+    pos2 += pairs(e);
   }
   if (threadIdx.x == 0) live_off[n_ev] = total;
 }

@@ -329,18 +329,23 @@ struct RecIn {                    // per-level staged-record buffers
   void* rec;
   ia::TriFrame* tfr;
   int32_t* live_off;              // n_ev + 1 offsets of the events' live tiles in one list
+  int64_t* stage_off;             // n_ev + 1 offsets of the events' (live triple, hit) pairs
 };
 
+// stages the class-2 records of a level; first lays out the batch's stage
+// items and live vote tiles in one list each (k_live_offsets), which the
+// vote kernel then uses too
 void launch_stage(const HitRec* recs, const ia::EvView& vw, int32_t n_ev, const BoxD* par, const Shape& sh,
                   const uint8_t* flags, const RecIn& r, const EventState* ev, hipStream_t s, bool f32,
                   float slack32) {
-  const dim3 g(std::max<uint32_t>(1, (kVoteGroups + n_ev - 1) / std::max(1, n_ev)), n_ev);
+  hipLaunchKernelGGL(ia::k_live_offsets, dim3(1), dim3(ia::kWG), 0, s, ev, vw, n_ev, r.live_off, r.stage_off);
+  const dim3 g(kVoteGroups, 1);
   if (f32)
     hipLaunchKernelGGL((ia::k_stage<true>), g, dim3(ia::kWG), 0, s, recs, vw, par, sh, flags, r.live_tri, r.rec_off,
-                       r.rec_fill, r.rec, r.tfr, ev, slack32);
+                       r.rec_fill, r.rec, r.tfr, r.stage_off, n_ev, slack32);
   else
     hipLaunchKernelGGL((ia::k_stage<false>), g, dim3(ia::kWG), 0, s, recs, vw, par, sh, flags, r.live_tri, r.rec_off,
-                       r.rec_fill, r.rec, r.tfr, ev, slack32);
+                       r.rec_fill, r.rec, r.tfr, r.stage_off, n_ev, slack32);
 }
 
 template <bool F32>
@@ -369,8 +374,8 @@ ia_status launch_vote_rec(ia_ctx* c, const ia::EvView& vw, int32_t n_ev, const B
                           int32_t* wg_max, hipStream_t s, bool f32) {
   const int32_t bx = vote_tile(c, sh.n_boxes);
   const uint32_t n_tiles = (sh.n_boxes + bx - 1) / bx;
-  // the batch's live tiles in one list, shared by all workgroups
-  hipLaunchKernelGGL(ia::k_live_offsets, dim3(1), dim3(ia::kWG), 0, s, ev, n_ev, r.live_off);
+  // the batch's live tiles in one list (laid out by launch_stage), shared by
+  // all workgroups
   const uint32_t grid = static_cast<uint32_t>(
       std::max<int64_t>(1, std::min<int64_t>(int64_t(n_tiles) * std::max(1, n_ev), kVoteGroups)));
   hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -396,7 +401,7 @@ ia_status launch_vote_rec(ia_ctx* c, const ia::EvView& vw, int32_t n_ev, const B
 // arena): per-event slices of every array, sized for events of max_hits hits
 struct FindLayout {
   size_t off, recs, votes, hist, lbh, selA, selB, range, sel_idx, sel_v, ev, part, flags, tlb, tn2, wg_max, live,
-      live_tri, rec_off, rec_fill, tfr, rec, pflags, live_off, total;
+      live_tri, rec_off, rec_fill, tfr, rec, pflags, live_off, stage_off, total;
   int64_t flag_stride, tri_stride, votes_stride, rec_stride, pflag_stride;
   int32_t hist_stride, wg_stride, part_stride, n_part;
 };
@@ -444,6 +449,7 @@ void layout_find(int64_t max_level_boxes, int64_t max_triples, int32_t top_k, in
   L->rec = take(sizeof(ia::RecD) * size_t(L->rec_stride) * E);
   L->pflags = take(size_t(L->pflag_stride) * E);
   L->live_off = take(sizeof(int32_t) * (E + 1));
+  L->stage_off = take(sizeof(int64_t) * (E + 1));
   L->total = off;
 }
 
@@ -511,7 +517,8 @@ ia_status run_chunk(ia_ctx* c, const double* hits_chunk, const int32_t* h_off_ch
   int32_t* live = reinterpret_cast<int32_t*>(a + L.live);
   const RecIn rin{reinterpret_cast<int32_t*>(a + L.live_tri), reinterpret_cast<int32_t*>(a + L.rec_off),
                   reinterpret_cast<int32_t*>(a + L.rec_fill), a + L.rec,
-                  reinterpret_cast<ia::TriFrame*>(a + L.tfr), reinterpret_cast<int32_t*>(a + L.live_off)};
+                  reinterpret_cast<ia::TriFrame*>(a + L.tfr), reinterpret_cast<int32_t*>(a + L.live_off),
+                  reinterpret_cast<int64_t*>(a + L.stage_off)};
   if (!dev_off) {
     // chunk-relative hit offsets through a pinned slot whose last copy is done
     const uint32_t slot = c->slot_next++ % kOffSlots;
