@@ -90,8 +90,8 @@ PEAK_FP64_TFLOPS = 78.6   # MI355X vector FP64: 256 CU x 128 FLOP/clk x 2.4 GHz
 # 1 GiB (bench.py --workload copy).  Valid only for the kernel sources they
 # were measured on (SHA-256 of ia_math.hpp + ia_kernels.hpp).
 TRAFFIC = {"kernel": "k_classify_defer (fp64 levels)", "workload": "event", "events_per_step": 1024,
-           "sources_sha256": "3ec0fcd537c20fd8bd46b1ecae63c532a15103ff9cab827d6df782ddb13e53b5",
-           "fetch_bytes": 97016233, "write_bytes": 268618112}
+           "sources_sha256": "22e8c051463f03f17b9be5058d31a61ed64ab66fb736cd220905dffc1d7f5128",
+           "fetch_bytes": 96959069, "write_bytes": 268526665}
 PEAK_FP32_TFLOPS = 157.3  # MI355X vector FP32 (non-packed)
 
 
