@@ -389,6 +389,95 @@ IA_HD bool e_enclosure(const PairQ& q, double R, double sig, double tt, double t
   return e_enclosure_dom(q, R, sig, tt, t2, ipt(dS), Z, L, out, &eps, &disc, &a);
 }
 
+// The same enclosure in FP32 interval arithmetic (the form the second stage
+// of the classification runs).  Every FP64 input enters as an FP32 interval
+// holding it (thin32, cover32) and every operation rounds outward, so the
+// result still holds the exact d^Ax of the FP64 pair quantities over Z x L,
+// and the same margin 1e-9 |e| + 1e-12 m covers the point evaluation's
+// rounding; FP32 only makes the enclosure wider, by a few 1e-7 of the terms'
+// size.  The inputs are bounded (R <= 2^40, |z0| <= 2^20, |tanl| <= 2^10,
+// |tan tau| <= 16, d <= 2^10, finite pair quantities) so that no
+// intermediate comes near the FP32 range; outside those bounds, or when
+// |eps| may exceed 0.75, no enclosure is returned (the caller then treats
+// the pass as undecided).
+struct EnclIn32 {
+  Iv32 Z, L, sArc, sinA, cosA, RAx, c2, s2, twoRAx2, RpRAx, dphi, cAx, sAx, R, tt, t2, d;
+  bool ok;
+};
+
+IA_HD EnclIn32 encl_in32(const PairQ& q, double R, double tt, double t2, double d, Iv Z, Iv L) {
+  EnclIn32 c;
+  const double qs = q.sArc + q.sinA + q.cosA + q.RAx + q.c2 + q.s2 + q.twoRAx2 + q.RpRAx + q.dphi + q.cAx + q.sAx;
+  c.ok = R <= 0x1p40 && fmax(fabs(Z.lo), fabs(Z.hi)) <= 0x1p20 && fmax(fabs(L.lo), fabs(L.hi)) <= 0x1p10 &&
+         fabs(tt) <= 16.0 && fabs(d) <= 0x1p10 && __builtin_isfinite(qs) && q.RAx > 0.0 && q.twoRAx2 > 0.0;
+  c.Z = cover32(Z);
+  c.L = cover32(L);
+  c.sArc = thin32(q.sArc);
+  c.sinA = thin32(q.sinA);
+  c.cosA = thin32(q.cosA);
+  c.RAx = thin32(q.RAx);
+  c.c2 = thin32(q.c2);
+  c.s2 = thin32(q.s2);
+  c.twoRAx2 = thin32(q.twoRAx2);
+  c.RpRAx = thin32(q.RpRAx);
+  c.dphi = thin32(q.dphi);
+  c.cAx = thin32(q.cAx);
+  c.sAx = thin32(q.sAx);
+  c.R = thin32(R);
+  c.tt = thin32(tt);
+  c.t2 = thin32(t2);
+  c.d = thin32(d);
+  return c;
+}
+
+// `neg` selects the drift sign dS = -d.  Outputs as e_enclosure_dom (exact
+// FP64 images of the FP32 ends; `out` widened by the point margin).
+IA_HD bool e_enclosure32(const EnclIn32& c, bool neg, double sig, Iv* out, Iv* eps_out, Iv* disc_out,
+                         Iv* a_out) {
+  if (!c.ok) return false;
+  const Iv32 DS = neg ? ineg32(c.d) : c.d;
+  const Iv32 ZA = iadd32(c.Z, imul32(c.L, c.sArc));
+  const Iv32 ZAs = imul32(ZA, c.sinA);
+  const Iv32 ZA2 = isqr32(ZA);
+  const Iv32 LZA = imul32(c.L, ZA);
+  const Iv32 LR = imul32(c.L, c.R);
+  const Iv32 L2 = isqr32(c.L);
+  const Iv32 PHI1 = ineg32(idiv_pos32(iadd32(ZAs, imul32(imul32(c.L, DS), c.cosA)), c.RAx));
+  const Iv32 P2a = imul32(LR, ZA);
+  const Iv32 P2b = imul32(imul32(LZA, isub32(c.R, itwice32(DS))), c.c2);
+  const Iv32 inner = iadd32(c.RAx, imul32(L2, isub32(c.RpRAx, DS)));
+  const Iv32 P2c = imul32(iadd32(ZA2, imul32(DS, inner)), c.s2);
+  const Iv32 PHI2 = idiv_pos32(iadd32(isub32(P2a, P2b), P2c), c.twoRAx2);
+  const Iv32 EPS = iadd32(imul32(PHI1, c.tt), imul32(PHI2, c.t2));
+  *eps_out = {EPS.lo, EPS.hi};
+  if (!(fabsf(EPS.lo) <= kSmallTrig32 && fabsf(EPS.hi) <= kSmallTrig32)) return false;
+  Iv32 SE, CE;
+  sincos_encl_small32(EPS, &SE, &CE);
+  const Iv32 SINP = iadd32(imul32(CE, c.sinA), imul32(SE, c.cosA));
+  const Iv32 COSP = isub32(imul32(CE, c.cosA), imul32(SE, c.sinA));
+  const Iv32 U2 = iadd32(iadd32(iadd32(Iv32{1.0f, 1.0f}, imul32(imul32(itwice32(c.L), SINP), c.tt)), imul32(L2, c.t2)),
+                         imul32(isqr32(COSP), c.t2));
+  if (!(U2.lo > 0.0f)) return false;
+  const Iv32 DELTA = idiv_pos32(DS, isqrt32(U2));
+  const Iv32 SPERP = imul32(iadd32(c.dphi, EPS), c.R);
+  const Iv32 ZS = isub32(iadd32(c.Z, imul32(c.L, SPERP)), imul32(imul32(DELTA, COSP), c.tt));
+  const Iv32 LD = imul32(c.L, DELTA);
+  const Iv32 CTAU = isub32(imul32(ZS, c.cAx), imul32(LD, c.sAx));
+  const Iv32 Q = iadd32(iadd32(imul32(itwice32(CTAU), c.tt), isqr32(imul32(ZS, c.tt))), isqr32(imul32(LD, c.tt)));
+  const Iv32 A = iadd32(c.R, DELTA);
+  const Iv32 DISC = isub32(isqr32(A), Q);
+  *disc_out = {DISC.lo, DISC.hi};
+  *a_out = {A.lo, A.hi};
+  if (!(DISC.hi >= 0.0f)) return false;
+  const Iv32 DEN = iadd32(A, isqrt32(DISC));
+  if (!(DEN.lo > 0.0f)) return false;
+  const Iv32 DHAT = isub32(DELTA, idiv_pos32(Q, DEN));
+  const Iv E = sig > 0.0 ? Iv{DHAT.lo, DHAT.hi} : Iv{-static_cast<double>(DHAT.hi), -static_cast<double>(DHAT.lo)};
+  const double m = 1e-9 * fmax(fabs(E.lo), fabs(E.hi)) + 1e-12;
+  *out = {wdn(E.lo - m), wup(E.hi + m)};
+  return __builtin_isfinite(out->lo) && __builtin_isfinite(out->hi);
+}
+
 // Inclusion: a proof that the per-box test votes for every point value e
 // in [E1, E2].  The per-box test (h_contains0, or its FP32 form) votes when
 // its interval T = 2E + K E^2, E = [e - b, e + b] rounded outward, has
@@ -510,7 +599,7 @@ IA_HD bool h_may_vote_mag(Iv G, Iv K, double M, double band) {
 // The class is decided in two stages: stereo_quick_class (the magnitude
 // bound of e, which excludes most pairs that can be excluded at a small part
 // of an enclosure's cost; 0 or -1 for undecided) and stereo_pass_class (the
-// enclosure per drift sign).  With `cnt` set, cnt[0] counts the enclosure
+// FP32 enclosure, e_enclosure32, per drift sign).  With `cnt` set, cnt[0] counts the enclosure
 // passes and cnt[1] the inclusion proofs evaluated.
 IA_HD int stereo_quick_class_in(const MagIn& m, Iv G, const Frame& f, const HitRec& h, Iv Z, Iv L) {
   EMag em;
@@ -528,14 +617,14 @@ IA_HD int stereo_quick_class(const PairQ& q, const Frame& f, const HitRec& h, Iv
 IA_HD int stereo_pass_class(const PairQ& q, const Frame& f, const HitRec& h, Iv Z, Iv L, int32_t* cnt = nullptr) {
   const Iv G = {q.Glo, q.Ghi};
   const double tt = h.tant, t2 = tt * tt;
+  const EnclIn32 c = encl_in32(q, f.R, tt, t2, h.d, Z, L);
   bool may = false;
   // passes 0 and 1: each drift sign.  One loop body, kept rolled, holds the
   // enclosure's registers once.
 #pragma unroll 1
   for (int si = 0; si < 2; ++si) {
-    const Iv DS = ipt(si == 0 ? h.d : -h.d);
     Iv E, EPS, DISC, A;
-    const bool ok = e_enclosure_dom(q, f.R, f.sig, tt, t2, DS, Z, L, &E, &EPS, &DISC, &A);
+    const bool ok = e_enclosure32(c, si != 0, f.sig, &E, &EPS, &DISC, &A);
     if (cnt) ++cnt[0];
     const bool try_incl = ok && DISC.lo > 0.25 * A.lo * A.lo && A.lo > 0.0;
     if (cnt && try_incl) ++cnt[1];
@@ -687,14 +776,14 @@ IA_HD int stereo_pass_class32(const PairQ& q, const Frame& f, const HitRec& h, I
   const float bs = wup32(ru32(h.band) + slack32);
   const float bs2 = wup32(ru32(h.band) + 2.0f * slack32);
   const double tt = h.tant, t2 = tt * tt;
+  const EnclIn32 c = encl_in32(q, f.R, tt, t2, h.d, Z, L);
   bool may = false;
   // passes 0 and 1: each drift sign (one rolled loop body, as in
-  // triple_vote_class)
+  // stereo_pass_class)
 #pragma unroll 1
   for (int si = 0; si < 2; ++si) {
-    const Iv DS = ipt(si == 0 ? h.d : -h.d);
     Iv E, EPS, DISC, A;
-    const bool ok = e_enclosure_dom(q, f.R, f.sig, tt, t2, DS, Z, L, &E, &EPS, &DISC, &A);
+    const bool ok = e_enclosure32(c, si != 0, f.sig, &E, &EPS, &DISC, &A);
     if (cnt) ++cnt[0];
     const bool try_incl = ok && DISC.lo > 0.25 * A.lo * A.lo && A.lo > 0.0;
     if (cnt && try_incl) ++cnt[1];

@@ -262,6 +262,28 @@ IA_HD Iv32 isqr32(Iv32 a) {
 }
 IA_HD Iv32 itwice32(Iv32 a) { return {2.0f * a.lo, 2.0f * a.hi}; }
 IA_HD Iv32 to32(Iv a) { return {rd32(a.lo), ru32(a.hi)}; }
+IA_HD Iv32 ineg32(Iv32 a) { return {-a.hi, -a.lo}; }
+// FP32 interval holding the FP64 value x: x rounded to nearest is within half
+// an FP32 ulp (2^-150 in the subnormal range) of x, and the widening moves
+// each end by at least one ulp
+IA_HD Iv32 thin32(double x) {
+  const float f = static_cast<float>(x);
+  return {wdn32(f), wup32(f)};
+}
+// FP32 interval holding the FP64 interval a (same argument per end)
+IA_HD Iv32 cover32(Iv a) { return {wdn32(static_cast<float>(a.lo)), wup32(static_cast<float>(a.hi))}; }
+// quotients and roots are widened by |x| 2^-21 + 2^-149 (at least four ulps),
+// which holds them whether or not the device rounds them correctly
+IA_HD float wdn32q(float x) { return x - fmaf(fabsf(x), 0x1p-21f, 0x1p-149f); }
+IA_HD float wup32q(float x) { return x + fmaf(fabsf(x), 0x1p-21f, 0x1p-149f); }
+// a / b for b.lo > 0: the extreme quotients, chosen by the signs of a's ends
+IA_HD Iv32 idiv_pos32(Iv32 a, Iv32 b) {
+  const float lo = a.lo / (a.lo >= 0.0f ? b.hi : b.lo);
+  const float hi = a.hi / (a.hi >= 0.0f ? b.lo : b.hi);
+  return {wdn32q(lo), wup32q(hi)};
+}
+// square root of [lo, hi] with hi >= 0; negative parts are clipped
+IA_HD Iv32 isqrt32(Iv32 a) { return {a.lo > 0.0f ? wdn32q(sqrtf(a.lo)) : 0.0f, wup32q(sqrtf(a.hi))}; }
 
 // sin and cos for |x| <= 1: Taylor polynomials of degree 11 and 12 (first
 // omitted terms below 2e-10), Horner with fused multiply-adds
@@ -283,6 +305,20 @@ IA_HD float cos1_32(float x) {
   q = fmaf(q, z, 1.0f / 24.0f);
   q = fmaf(q, z, -0.5f);
   return fmaf(z, q, 1.0f);
+}
+
+// sin and cos enclosures for FP32 intervals inside [-0.75, 0.75], where sin
+// increases and cos decreases with |x|.  On that range the polynomials above
+// are within 4e-12 of sin and cos and their FP32 evaluation within 2e-7 (a
+// few roundings of values below 1); the margin 2^-21 (4.8e-7) covers both.
+constexpr float kSmallTrig32 = 0.75f;
+constexpr float kSmallMargin32 = 0x1p-21f;
+IA_HD void sincos_encl_small32(Iv32 x, Iv32* S, Iv32* C) {
+  *S = {fmaxf(sin1_32(x.lo) - kSmallMargin32, -1.0f), fminf(sin1_32(x.hi) + kSmallMargin32, 1.0f)};
+  const float alo = fabsf(x.lo), ahi = fabsf(x.hi);
+  const bool has0 = x.lo <= 0.0f && x.hi >= 0.0f;
+  const float amin = has0 ? 0.0f : fminf(alo, ahi), amax = fmaxf(alo, ahi);
+  *C = {cos1_32(amax) - kSmallMargin32, has0 ? 1.0f : fminf(cos1_32(amin) + kSmallMargin32, 1.0f)};
 }
 
 }  // namespace ia

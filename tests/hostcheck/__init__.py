@@ -39,6 +39,8 @@ def lib():
                                     C.c_int32, C.c_int32, P, P]
         L.hc_g_pairs.restype = C.c_int32
         L.hc_g_pairs.argtypes = [P, C.c_int32, P, P, P]
+        L.hc_encl_pairs.restype = C.c_int32
+        L.hc_encl_pairs.argtypes = [P, C.c_int32, P, P, P]
         L.hc_e_magnitude.restype = C.c_int32
         L.hc_e_magnitude.argtypes = [P, P, P, C.c_uint32, P]
         _lib = L
@@ -82,4 +84,18 @@ def g_pairs(hits, parent, split):
     n_tr = int(np.prod(sp[:3].astype(np.int64)))
     out = np.zeros((n_tr, h.shape[0], 4))
     assert lib().hc_g_pairs(h.ctypes.data, h.shape[0], pa.ctypes.data, sp.ctypes.data, out.ctypes.data) == 0
+    return out
+
+
+def encl_pairs(hits, parent, split):
+    """FP64 and FP32 enclosures of d^Ax and the range of its values at the
+    box centres, per (triple, hit, drift sign) of one parent's level: shape
+    (triples, hits, 2, 10), rows as in hc_encl_pairs."""
+    h = np.ascontiguousarray(hits).view(np.float64).reshape(-1, 8).copy()
+    p = np.atleast_1d(parent)
+    pa = np.ascontiguousarray(np.concatenate([p["lo"], p["hi"]], axis=1)[0], dtype=np.float64)
+    sp = np.ascontiguousarray(split, dtype=np.int32)
+    n_tr = int(np.prod(sp[:3].astype(np.int64)))
+    out = np.zeros((n_tr, h.shape[0], 2, 10))
+    assert lib().hc_encl_pairs(h.ctypes.data, h.shape[0], pa.ctypes.data, sp.ctypes.data, out.ctypes.data) == 0
     return out

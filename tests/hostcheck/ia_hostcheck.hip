@@ -5,6 +5,7 @@
 // per-box stereo term of the pairs left undecided.
 // Used only by the tests, to compare the device arithmetic with the oracle
 // on many events without a GPU.
+#include <cmath>
 #include <cstdint>
 #include <vector>
 
@@ -223,6 +224,88 @@ int32_t hc_g_pairs(const double* hits, int32_t n_hits, const double* parent, con
       if (!rec[i].use) { o[0] = o[1] = o[2] = o[3] = 0.0; continue; }
       const Iv G = residual_G(f, rec[i]), Go = residual_G_outer(f, g, rec[i]);
       o[0] = G.lo; o[1] = G.hi; o[2] = Go.lo; o[3] = Go.hi;
+    }
+  }
+  return 0;
+}
+
+}  // extern "C"
+
+// d^Ax at one box centre for one drift sign, in stereo_vote's operations;
+// false where the discriminant is negative or the value is not finite
+static bool point_e(const PairQ& q, double R, double sig, double z0, double lam, double tt, double t2, double dS,
+                    double* e) {
+  const double lamR = lam * R, lam2 = lam * lam;
+  const double zA = z0 + lam * q.sArc, zAs = zA * q.sinA, zA2 = zA * zA, lzA = lam * zA;
+  const double Phi1 = -(zAs + (lam * dS) * q.cosA) / q.RAx;
+  const double Phi2n = lamR * zA - (lzA * (R - 2.0 * dS)) * q.c2 + (zA2 + dS * (q.RAx + lam2 * (q.RpRAx - dS))) * q.s2;
+  const double eps = Phi1 * tt + (Phi2n / q.twoRAx2) * t2;
+  double se, ce;
+  sincos_p(eps, &se, &ce);
+  const double sinP = q.sinA * ce + q.cosA * se, cosP = q.cosA * ce - q.sinA * se;
+  const double u = sqrt(((1.0 + ((2.0 * lam) * sinP) * tt) + lam2 * t2) + (cosP * cosP) * t2);
+  const double delta = dS / u;
+  const double zS = (z0 + lam * (R * (q.dphi + eps))) - (delta * cosP) * tt;
+  const double ld = lam * delta;
+  const double ctau = zS * q.cAx - ld * q.sAx;
+  const double a1 = zS * tt, a2 = ld * tt;
+  const double Q = ((2.0 * ctau) * tt + a1 * a1) + a2 * a2;
+  const double A = R + delta, disc = A * A - Q;
+  if (!(disc >= 0.0)) return false;
+  *e = sig * (delta - Q / (A + sqrt(disc)));
+  return std::isfinite(*e);
+}
+
+extern "C" {
+
+// For every (triple, stereo hit) pair of one parent's level and each drift
+// sign: the FP64 and FP32 enclosures of e over the centre rectangle and the
+// range of the point values at the boxes' centres.  Row of 10 per (triple,
+// hit, sign): ok64, E64.lo, E64.hi, ok32, E32.lo, E32.hi, n_points, min, max,
+// stereo (0 for an axial or unused hit).
+int32_t hc_encl_pairs(const double* hits, int32_t n_hits, const double* parent, const int32_t split[5],
+                      double* out) {
+  Shape sh;
+  if (!make_shape(split, 1, &sh)) return 1;
+  std::vector<HitRec> rec(n_hits > 0 ? n_hits : 1);
+  for (int32_t i = 0; i < n_hits; ++i) {
+    bool bad;
+    prep_one(hits + 8 * i, true, &rec[i], &bad);
+  }
+  const BoxD& P = *reinterpret_cast<const BoxD*>(parent);
+  Iv Z, L;
+  centre_ranges(P, sh.m, &Z, &L);
+  for (uint32_t tc = 0; tc < sh.m012; ++tc) {
+    const Frame f = triple_frame(P, sh.m, tc / sh.m12, (tc / sh.m[2]) % sh.m[1], tc % sh.m[2]);
+    for (int32_t i = 0; i < n_hits; ++i) {
+      const HitRec& h = rec[i];
+      const bool stereo = h.use && !h.axial;
+      const PairQ q = pair_quantities(f, h, residual_G(f, h));
+      const double tt = h.tant, t2 = tt * tt;
+      const EnclIn32 c = encl_in32(q, f.R, tt, t2, h.d, Z, L);
+      for (int si = 0; si < 2; ++si) {
+        double* o = out + 10 * ((size_t(tc) * n_hits + i) * 2 + si);
+        for (int k = 0; k < 10; ++k) o[k] = 0.0;
+        if (!stereo) continue;
+        o[9] = 1.0;
+        const double dS = si == 0 ? h.d : -h.d;
+        Iv E = {0.0, 0.0}, EPS, DISC, A;
+        o[0] = e_enclosure_dom(q, f.R, f.sig, tt, t2, ipt(dS), Z, L, &E, &EPS, &DISC, &A) ? 1.0 : 0.0;
+        o[1] = E.lo; o[2] = E.hi;
+        E = {0.0, 0.0};
+        o[3] = e_enclosure32(c, si != 0, f.sig, &E, &EPS, &DISC, &A) ? 1.0 : 0.0;
+        o[4] = E.lo; o[5] = E.hi;
+        double n = 0.0, lo = INFINITY, hi = -INFINITY;
+        for (uint32_t a = 0; a < sh.m[3]; ++a)
+          for (uint32_t b = 0; b < sh.m[4]; ++b) {
+            double zlo, zhi, llo, lhi, e;
+            child_edge(P.lo[3], P.hi[3], sh.m[3], a, &zlo, &zhi);
+            child_edge(P.lo[4], P.hi[4], sh.m[4], b, &llo, &lhi);
+            if (!point_e(q, f.R, f.sig, 0.5 * (zlo + zhi), 0.5 * (llo + lhi), tt, t2, dS, &e)) continue;
+            n += 1.0; lo = std::fmin(lo, e); hi = std::fmax(hi, e);
+          }
+        o[6] = n; o[7] = lo; o[8] = hi;
+      }
     }
   }
   return 0;

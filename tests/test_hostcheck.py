@@ -240,3 +240,31 @@ def test_outer_residual_contains_residual(orc):
         worst = max(worst, float(np.max((g[..., 3] - g[..., 2]) - (g[..., 1] - g[..., 0]))))
     assert n_checked > 5000
     assert worst < 1e-12
+
+
+def test_fp32_enclosure_holds_centre_values(orc):
+    """The second stage's FP32 enclosure of d^Ax (outward FP32 rounding of
+    the FP64 pair quantities) holds d^Ax at every box centre of the triple,
+    for both drift signs, on boxes from 1e-4 of the search domain to half of
+    it around a true helix of several configurations; it exists wherever the
+    FP64 enclosure does and is wider by at most 1e-6 m."""
+    rng = np.random.default_rng(5)
+    n_pairs, worst = 0, 0.0
+    for trial in range(24):
+        cfg = (1, 2, 4, 5)[trial % 4]
+        ev = toymc.config_event(cfg, trial // 4)
+        t = ev.truth[0]
+        w = (H.HI - H.LO) * 10 ** rng.uniform(-4, -0.3)
+        lo = np.maximum(t - w * rng.uniform(0.1, 1, 5), H.LO)
+        hi = np.minimum(t + w * rng.uniform(0.1, 1, 5), H.HI)
+        o = hostcheck.encl_pairs(ev.hits, orc.make_box(lo, hi), [3, 3, 3, 8, 8]).reshape(-1, 10)
+        o = o[o[:, 9] == 1]
+        ok64, ok32, pts = o[:, 0] == 1, o[:, 3] == 1, o[:, 6] > 0
+        assert np.all(ok32[ok64])
+        m = ok32 & pts
+        assert np.all(o[m, 7] >= o[m, 4]) and np.all(o[m, 8] <= o[m, 5])
+        b = ok64 & ok32
+        worst = max(worst, float(np.max((o[b, 5] - o[b, 4]) - (o[b, 2] - o[b, 1]), initial=0.0)))
+        n_pairs += int(m.sum())
+    assert n_pairs > 10000
+    assert worst < 1e-6
