@@ -808,16 +808,44 @@ IA_HD int triple_vote_class32(const PairQ& q, const Frame& f, const HitRec& h, I
   return c >= 0 ? c : stereo_pass_class32(q, f, h, Z, L, slack32, cnt);
 }
 
+// What the parent-level enclosures of d^Ax give the first stage of the child
+// triples' classification (parent_range_excl), per drift sign s: when
+// ok[s] is set, [wlo[s], whi[s]] holds the per-box H test's term
+// 2 E + kappa E^2 for every child box centre (E the point value of d^Ax
+// widened by the band, kappa over the parent); ok[s] is 0 where no range is
+// available (axial hits, FP32 levels, failed enclosures).
+struct ParentE {
+  double wlo[2], whi[2];
+  int32_t ok[2];
+};
+
+// First-stage exclusion of a stereo pair at an FP64 refinement level with
+// the parent's ranges (ParentE), which hold the triple's boxes (its box
+// centres are among the parent's child centres): for both signs the per-box
+// H test fails for any term in [wlo, whi] with the outer G (class 0).  The
+// per-box test computes wdn(2 G.lo - X.hi) and wup(2 G.hi - X.lo) for its
+// term X, which lies inside [wlo, whi] (the same outward-rounded operations
+// on narrower intervals), with G inside the outer G; both roundings are
+// monotone, so the bounds below carry over to every box.
+IA_HD bool parent_range_excl(const ParentE& pe, Iv Go) {
+  for (int si = 0; si < 2; ++si) {
+    if (!pe.ok[si]) return false;
+    if (!(wdn(2.0 * Go.lo - pe.whi[si]) > 0.0 || wup(2.0 * Go.hi - pe.wlo[si]) < 0.0)) return false;
+  }
+  return true;
+}
+
 // The two stages of a (triple, hit) pair's class as the kernels run them.
 // Stage 1 (k_classify): the outer G (residual_G_outer); an axial pair is
 // decided exactly, with the exact G only when the outer one does not already
-// exclude both signs; a stereo pair is excluded by the magnitude bound from
-// pair_magnitudes and the outer G, else deferred (-1).  Outside the FP32
-// domain a stereo pair votes (1); without the proofs (`filter` 0) it is
-// class 2.  cnt[kCwG ..] counts the work when set.
+// exclude both signs; a stereo pair is excluded by parent_range_excl (FP64
+// refinement levels, with the parent's ranges `pe`) or by the magnitude
+// bound from pair_magnitudes and the outer G, else deferred (-1).  Outside
+// the FP32 domain a stereo pair votes (1); without the proofs (`filter` 0)
+// it is class 2.  cnt[kCwG ..] counts the work when set.
 template <bool F32>
 IA_HD int pair_stage1(const Frame& f, const GTri& g, const HitRec& h, Iv Z, Iv L, int32_t filter, float slack32,
-                      int32_t* cnt) {
+                      int32_t* cnt, const ParentE* pe = nullptr) {
   const Iv Go = residual_G_outer(f, g, h);
   if (cnt) ++cnt[kCwG];
   if (h.axial) {
@@ -829,9 +857,11 @@ IA_HD int pair_stage1(const Frame& f, const GTri& g, const HitRec& h, Iv Z, Iv L
   }
   if (F32 && !(f.R <= kR32Max)) return 1;
   if (!filter) return 2;
+  if (!F32 && pe && parent_range_excl(*pe, Go)) return 0;
   if (cnt) { ++cnt[kCwPairQ]; ++cnt[kCwMag]; }
   const MagIn m = pair_magnitudes(f, h);
-  return F32 ? stereo_quick_class32_in(m, Go, f, h, Z, L, slack32) : stereo_quick_class_in(m, Go, f, h, Z, L);
+  if (F32) return stereo_quick_class32_in(m, Go, f, h, Z, L, slack32);
+  return stereo_quick_class_in(m, Go, f, h, Z, L);
 }
 
 // Stage 2 (k_classify_defer): the exact G and pair quantities, then the
@@ -978,9 +1008,13 @@ IA_HD bool e_enclosure_iq(const PairQIv& q, Iv R, double sig, double tt, double 
 }
 
 // false only when the hit can vote for no box of the parent's children
-// (at FP32 levels, under the FP32 definition: out-of-domain boxes vote)
+// (at FP32 levels, under the FP32 definition: out-of-domain boxes vote).
+// At FP64 levels the two drift signs get one enclosure each (inside the
+// combined one, so at least as sharp), written to `pe` when set.
 template <bool F32>
-IA_HD bool parent_may_vote(const BoxD& P, const uint32_t m[5], const HitRec& h, float slack32) {
+IA_HD bool parent_may_vote(const BoxD& P, const uint32_t m[5], const HitRec& h, float slack32,
+                           ParentE* pe = nullptr) {
+  if (pe) pe->ok[0] = pe->ok[1] = 0;
   if (!h.use) return false;
   FrameIv f;
   if (!parent_frame(P, m, &f)) return true;
@@ -998,6 +1032,27 @@ IA_HD bool parent_may_vote(const BoxD& P, const uint32_t m[5], const HitRec& h, 
   centre_ranges(P, m, &Z, &L);
   const double tt = h.tant, t2 = tt * tt;
   Iv E, EPS, DISC, A;
+  if constexpr (!F32) {
+    bool may = false;
+    for (int si = 0; si < 2; ++si) {
+      const double ds = si == 0 ? h.d : -h.d;
+      const bool ok = e_enclosure_iq(q, f.R, f.sig, tt, t2, Iv{ds, ds}, Z, L, &E, &EPS, &DISC, &A);
+      bool in = true;
+      if (ok) {
+        const Iv Eb = {wdn(E.lo - h.band), wup(E.hi + h.band)};
+        const Iv X = iadd(itwice(Eb), imul(f.K, isqr(Eb)));
+        const Iv Hb = isub(itwice(G), X);
+        in = Hb.lo <= 0.0 && 0.0 <= Hb.hi;
+        if (pe) {
+          pe->wlo[si] = X.lo;
+          pe->whi[si] = X.hi;
+          pe->ok[si] = 1;
+        }
+      }
+      may = may || in;
+    }
+    return may;
+  }
   if (!e_enclosure_iq(q, f.R, f.sig, tt, t2, Iv{-h.d, h.d}, Z, L, &E, &EPS, &DISC, &A)) return true;
   if constexpr (F32) {
     if (!(fabs(EPS.lo) <= 0.99 && fabs(EPS.hi) <= 0.99 && DISC.lo > 1e-3 * A.hi * A.hi)) return true;
@@ -1006,11 +1061,8 @@ IA_HD bool parent_may_vote(const BoxD& P, const uint32_t m[5], const HitRec& h, 
     const Iv32 Eb = {wdn32(rd32(E.lo) - bs2), wup32(ru32(E.hi) + bs2)};
     const Iv32 Hb = isub32(itwice32(G32), iadd32(itwice32(Eb), imul32(K32, isqr32(Eb))));
     return Hb.lo <= 0.0f && 0.0f <= Hb.hi;
-  } else {
-    const Iv Eb = {wdn(E.lo - h.band), wup(E.hi + h.band)};
-    const Iv Hb = isub(itwice(G), iadd(itwice(Eb), imul(f.K, isqr(Eb))));
-    return Hb.lo <= 0.0 && 0.0 <= Hb.hi;
   }
+  return true;
 }
 
 // ---------------------------------------------------------------------------
@@ -1156,6 +1208,7 @@ __global__ void __launch_bounds__(kWG) k_classify(const HitRec* __restrict__ hit
                                                   int32_t* __restrict__ tn2, int32_t filter,
                                                   const EventState* __restrict__ ev, float slack32,
                                                   const uint8_t* __restrict__ pflags,
+                                                  const ParentE* __restrict__ pe,
                                                   unsigned long long* __restrict__ work) {
   const int e = blockIdx.y;
   if (ev && ev[e].done) return;
@@ -1174,6 +1227,7 @@ __global__ void __launch_bounds__(kWG) k_classify(const HitRec* __restrict__ hit
   const uint32_t tc = tq % sh.m012;
   const BoxD& TP = parents[tq / sh.m012];
   const uint8_t* pf = pflags ? pflags + e * vw.pflag_stride + int64_t(tq / sh.m012) * n_hits : nullptr;
+  const ParentE* pr = pe ? pe + e * vw.pflag_stride + int64_t(tq / sh.m012) * n_hits : nullptr;
   const Frame f = triple_frame(TP, sh.m, tc / sh.m12, (tc / sh.m[2]) % sh.m[1], tc % sh.m[2]);
   Iv Zr, Lr;
   centre_ranges(TP, sh.m, &Zr, &Lr);
@@ -1185,7 +1239,7 @@ __global__ void __launch_bounds__(kWG) k_classify(const HitRec* __restrict__ hit
     const HitRec hr = hits[h];
     uint8_t fl = 0;
     if (hr.use && (!pf || pf[h])) {
-      const int c = pair_stage1<F32>(f, gt, hr, Zr, Lr, filter, slack32, COUNT ? cw : nullptr);
+      const int c = pair_stage1<F32>(f, gt, hr, Zr, Lr, filter, slack32, COUNT ? cw : nullptr, pr ? &pr[h] : nullptr);
       fl = c >= 0 ? static_cast<uint8_t>(c) : kFlagDeferred;
     }
     if (live) flags[int64_t(h) * n_tr + t] = fl;
@@ -1299,11 +1353,12 @@ __global__ void __launch_bounds__(kWG, 3) k_classify_defer(const HitRec* __restr
 
 // Parent-level exclusion of a refinement level: pflags[p * n_hits + h] = 0
 // when hit h can vote for no child box of parent p (parent_may_vote), else 1.
+// With `pe` set, pe[p * n_hits + h] receives the per-sign ranges of d^Ax.
 template <bool F32>
 __global__ void __launch_bounds__(kWG) k_parent_filter(const HitRec* __restrict__ hits, EvView vw,
                                                        const BoxD* __restrict__ parents, Shape sh,
                                                        uint8_t* __restrict__ pflags, const EventState* __restrict__ ev,
-                                                       float slack32) {
+                                                       float slack32, ParentE* __restrict__ pe) {
   const int e = blockIdx.y;
   if (ev[e].done) return;
   const int32_t n_hits = vw.count(e);
@@ -1311,11 +1366,12 @@ __global__ void __launch_bounds__(kWG) k_parent_filter(const HitRec* __restrict_
   hits += vw.beg(e);
   parents += e * vw.par_stride;
   pflags += e * vw.pflag_stride;
+  if (pe) pe += e * vw.pflag_stride;
   const int64_t n = static_cast<int64_t>(sh.n_parents) * n_hits;
   for (int64_t i = int64_t(blockIdx.x) * kWG + threadIdx.x; i < n; i += int64_t(gridDim.x) * kWG) {
     const uint32_t p = static_cast<uint32_t>(i / n_hits);
     const int32_t h = static_cast<int32_t>(i % n_hits);
-    pflags[i] = parent_may_vote<F32>(parents[p], sh.m, hits[h], slack32) ? 1 : 0;
+    pflags[i] = parent_may_vote<F32>(parents[p], sh.m, hits[h], slack32, pe ? &pe[i] : nullptr) ? 1 : 0;
   }
 }
 

@@ -23,6 +23,7 @@ static_assert(sizeof(ia_box) == sizeof(BoxD), "ia_box layout");
 static_assert(sizeof(ia_helix) == sizeof(ia::HelixOut), "ia_helix layout");
 static_assert(sizeof(ia_estimate_t) == sizeof(ia::EstimateOut), "ia_estimate_t layout");
 static_assert(sizeof(HitRec) == 112, "HitRec layout");
+static_assert(sizeof(ia::ParentE) == 40, "ParentE layout");
 
 namespace {
 
@@ -190,7 +191,7 @@ ia::EvView single_view(int32_t n_hits) {
 ia_status launch_classify(ia_ctx* c, const HitRec* recs, const ia::EvView& vw, int32_t n_ev, int32_t max_hits,
                           const BoxD* par, const Shape& sh, uint8_t* flags, int32_t* tlb, int32_t* tn2,
                           const EventState* ev, hipStream_t s, bool f32, float slack32,
-                          const uint8_t* pflags = nullptr) {
+                          const uint8_t* pflags = nullptr, const ia::ParentE* pe = nullptr) {
   const uint32_t n_tr = sh.n_parents * sh.m012;
   const uint32_t gx = (n_tr + 63) / 64;
   const int64_t base = int64_t(gx) * std::max(1, n_ev);
@@ -209,16 +210,16 @@ ia_status launch_classify(ia_ctx* c, const HitRec* recs, const ia::EvView& vw, i
   if (c->count_work) {
     if (f32)
       hipLaunchKernelGGL((ia::k_classify<true, true>), g, b, 0, s, recs, vw, par, sh, flags, tlb, tn2, filt, ev,
-                         slack32, pflags, wk);
+                         slack32, pflags, pe, wk);
     else
       hipLaunchKernelGGL((ia::k_classify<false, true>), g, b, 0, s, recs, vw, par, sh, flags, tlb, tn2, filt, ev,
-                         slack32, pflags, wk);
+                         slack32, pflags, pe, wk);
   } else if (f32) {
     hipLaunchKernelGGL((ia::k_classify<true, false>), g, b, 0, s, recs, vw, par, sh, flags, tlb, tn2, filt, ev,
-                       slack32, pflags, nullptr);
+                       slack32, pflags, pe, nullptr);
   } else {
     hipLaunchKernelGGL((ia::k_classify<false, false>), g, b, 0, s, recs, vw, par, sh, flags, tlb, tn2, filt, ev,
-                       slack32, pflags, nullptr);
+                       slack32, pflags, pe, nullptr);
   }
   if (c->profiling) {
     IA_HIP(c, hipEventRecord(e1, s));
@@ -401,7 +402,7 @@ ia_status launch_vote_rec(ia_ctx* c, const ia::EvView& vw, int32_t n_ev, const B
 // arena): per-event slices of every array, sized for events of max_hits hits
 struct FindLayout {
   size_t off, recs, votes, hist, lbh, selA, selB, range, sel_idx, sel_v, ev, part, flags, tlb, tn2, wg_max, live,
-      live_tri, rec_off, rec_fill, tfr, rec, pflags, live_off, stage_off, total;
+      live_tri, rec_off, rec_fill, tfr, rec, pflags, pe, live_off, stage_off, total;
   int64_t flag_stride, tri_stride, votes_stride, rec_stride, pflag_stride;
   int32_t hist_stride, wg_stride, part_stride, n_part;
 };
@@ -448,6 +449,7 @@ void layout_find(int64_t max_level_boxes, int64_t max_triples, int32_t top_k, in
   L->tfr = take(sizeof(ia::TriFrame) * size_t(L->tri_stride) * E);
   L->rec = take(sizeof(ia::RecD) * size_t(L->rec_stride) * E);
   L->pflags = take(size_t(L->pflag_stride) * E);
+  L->pe = take(sizeof(ia::ParentE) * size_t(L->pflag_stride) * E);
   L->live_off = take(sizeof(int32_t) * (E + 1));
   L->stage_off = take(sizeof(int64_t) * (E + 1));
   L->total = off;
@@ -510,6 +512,7 @@ ia_status run_chunk(ia_ctx* c, const double* hits_chunk, const int32_t* h_off_ch
   double* part = reinterpret_cast<double*>(a + L.part);
   uint8_t* flags = reinterpret_cast<uint8_t*>(a + L.flags);
   uint8_t* pflags = reinterpret_cast<uint8_t*>(a + L.pflags);
+  ia::ParentE* pe = reinterpret_cast<ia::ParentE*>(a + L.pe);
   int32_t* tlb = reinterpret_cast<int32_t*>(a + L.tlb);
   int32_t* tn2 = reinterpret_cast<int32_t*>(a + L.tn2);
   uint32_t* lbh = reinterpret_cast<uint32_t*>(a + L.lbh);
@@ -565,14 +568,16 @@ ia_status run_chunk(ia_ctx* c, const double* hits_chunk, const int32_t* h_off_ch
         const dim3 gp(static_cast<uint32_t>(std::min<int64_t>((n_pairs + ia::kWG - 1) / ia::kWG, 65535)), E);
         if (f32)
           hipLaunchKernelGGL((ia::k_parent_filter<true>), gp, dim3(ia::kWG), 0, s, recs, vw, par, sh, pflags, ev,
-                             slack32);
+                             slack32, nullptr);
         else
           hipLaunchKernelGGL((ia::k_parent_filter<false>), gp, dim3(ia::kWG), 0, s, recs, vw, par, sh, pflags, ev,
-                             slack32);
+                             slack32, pe);
       }
       {
+        // at FP64 levels the parent's per-sign ranges of d^Ax also decide
+        // many pairs in the first stage
         const ia_status cs = launch_classify(c, recs, vw, E, cmax, par, sh, flags, tlb, tn2, ev, s, f32, slack32,
-                                             use_pf ? pflags : nullptr);
+                                             use_pf ? pflags : nullptr, (use_pf && !f32) ? pe : nullptr);
         if (cs != IA_OK) return cs;
       }
       const int32_t vt = vote_tile(c, sh.n_boxes);

@@ -66,7 +66,7 @@ def vote_level(hits, parents, split, filter_on, f32=False, slack=1e-6, prune_k=0
     sp = np.ascontiguousarray(split, dtype=np.int32)
     nb = pa.shape[0] * int(np.prod(sp.astype(np.int64)))
     votes = np.zeros(nb, dtype=np.uint16)
-    stats = np.zeros(9, dtype=np.int64)
+    stats = np.zeros(10, dtype=np.int64)
     rc = lib().hc_vote_level(h.ctypes.data, h.shape[0], pa.ctypes.data, pa.shape[0], sp.ctypes.data,
                              1 if filter_on else 0, 1 if f32 else 0, float(slack), int(prune_k),
                              1 if ties else 0, 1 if parent_filter else 0, votes.ctypes.data, stats.ctypes.data)

@@ -42,7 +42,8 @@ extern "C" {
 // stats: [0] stereo (triple, hit) pairs, [1] class 0, [2] stereo (box, hit)
 // evaluations, [3] of those that voted, [4] evaluated pairs voting in every
 // box of their triple, [5] class 1, [6] triples evaluated, [7] T,
-// [8] (parent, hit) pairs the parent-level test excluded (with parent_filter)
+// [8] (parent, hit) pairs the parent-level test excluded (with parent_filter),
+// [9] stereo pairs the first stage decided from the parent's ranges of d^Ax
 int32_t hc_vote_level(const double* hits, int32_t n_hits, const double* parents, int32_t n_parents,
                       const int32_t split[5], int32_t filter, int32_t f32, double slack, int32_t prune_k,
                       int32_t ties, int32_t parent_filter, uint16_t* votes, int64_t* stats) {
@@ -58,21 +59,22 @@ int32_t hc_vote_level(const double* hits, int32_t n_hits, const double* parents,
   const int64_t n_triples = int64_t(n_parents) * sh.m012;
   // parent-level exclusion per (parent, hit)
   std::vector<uint8_t> pmay(size_t(n_parents) * size_t(n_hits > 0 ? n_hits : 1), 1);
+  std::vector<ParentE> pe(pmay.size());
   int64_t n_pexcl = 0;
   if (parent_filter && filter) {
 #pragma omp parallel for schedule(dynamic, 1) reduction(+ : n_pexcl)
     for (int32_t p = 0; p < n_parents; ++p)
       for (int32_t i = 0; i < n_hits; ++i) {
         const bool may = f32 ? parent_may_vote<true>(P[p], sh.m, rec[i], slack32)
-                             : parent_may_vote<false>(P[p], sh.m, rec[i], slack32);
+                             : parent_may_vote<false>(P[p], sh.m, rec[i], slack32, &pe[size_t(p) * n_hits + i]);
         pmay[size_t(p) * n_hits + i] = may ? 1 : 0;
         n_pexcl += (!may && rec[i].use) ? 1 : 0;
       }
   }
   std::vector<uint8_t> cls(size_t(n_triples) * size_t(n_hits > 0 ? n_hits : 1));
   std::vector<int32_t> tlb(n_triples), tn2(n_triples);
-  int64_t n_pairs = 0, n_cut = 0, n_incl = 0;
-#pragma omp parallel for schedule(dynamic, 4) reduction(+ : n_pairs, n_cut, n_incl)
+  int64_t n_pairs = 0, n_cut = 0, n_incl = 0, n_prange = 0;
+#pragma omp parallel for schedule(dynamic, 4) reduction(+ : n_pairs, n_cut, n_incl, n_prange)
   for (int64_t t = 0; t < n_triples; ++t) {
     const uint32_t tp = static_cast<uint32_t>(t / sh.m012), tc = static_cast<uint32_t>(t % sh.m012);
     const Frame f = triple_frame(P[tp], sh.m, tc / sh.m12, (tc / sh.m[2]) % sh.m[1], tc % sh.m[2]);
@@ -85,8 +87,11 @@ int32_t hc_vote_level(const double* hits, int32_t n_hits, const double* parents,
       uint8_t fl = 0;
       if (h.use && pmay[size_t(tp) * n_hits + i]) {
         // the kernels' two stages
+        const ParentE* pr = (parent_filter && filter && !f32) ? &pe[size_t(tp) * n_hits + i] : nullptr;
         int c = f32 ? pair_stage1<true>(f, gt, h, Zr, Lr, filter, slack32, nullptr)
-                    : pair_stage1<false>(f, gt, h, Zr, Lr, filter, slack32, nullptr);
+                    : pair_stage1<false>(f, gt, h, Zr, Lr, filter, slack32, nullptr, pr);
+        if (pr && c >= 0 && !h.axial && pair_stage1<false>(f, gt, h, Zr, Lr, filter, slack32, nullptr) < 0)
+          ++n_prange;
         if (c < 0)
           c = f32 ? pair_stage2<true>(f, h, Zr, Lr, slack32, nullptr) : pair_stage2<false>(f, h, Zr, Lr, slack32, nullptr);
         fl = static_cast<uint8_t>(c);
@@ -167,7 +172,7 @@ int32_t hc_vote_level(const double* hits, int32_t n_hits, const double* parents,
   }
   if (stats) {
     stats[0] = n_pairs; stats[1] = n_cut; stats[2] = n_evals; stats[3] = n_yes; stats[4] = n_full;
-    stats[5] = n_incl; stats[6] = n_live; stats[7] = T; stats[8] = n_pexcl;
+    stats[5] = n_incl; stats[6] = n_live; stats[7] = T; stats[8] = n_pexcl; stats[9] = n_prange;
   }
   return 0;
 }

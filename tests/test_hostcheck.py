@@ -148,6 +148,30 @@ def test_parent_exclusion_sound(orc, cfg, ev_i, split, f32):
     assert np.array_equal(ti_r, ti_g) and np.array_equal(tv_r, tv_g)
 
 
+@pytest.mark.parametrize("cfg,ev_i", [(2, 3), (4, 2)])
+def test_parent_ranges_decide_deep_levels(orc, cfg, ev_i):
+    """At FP64 refinement levels the first stage also classifies stereo
+    pairs from the parent's per-sign ranges of d^Ax (exclusion with the
+    outer G, inclusion with the inner G).  Down a refinement chain of the
+    oracle's own top-32 boxes (12^5, then 4^5 three times) the level's votes
+    equal the oracle's, and the parent ranges decide pairs."""
+    ev = toymc.config_event(cfg, ev_i)
+    root = orc.make_box(H.LO, H.HI)
+    v = orc.vote_level(ev.hits, root, [12] * 5)
+    parents, split = np.atleast_1d(root), [12] * 5
+    n_decided = 0
+    for lev in range(1, 4):
+        top, _ = _topk(v, 32)
+        parents = np.array([orc.box_child(parents[int(b) // int(np.prod(split))], split, int(b) % int(np.prod(split)))
+                            for b in top])
+        split = [4] * 5
+        v = orc.vote_level(ev.hits, parents, split)
+        got, st = hostcheck.vote_level(ev.hits, parents, split, True, parent_filter=True)
+        assert np.array_equal(got, v), (lev, np.flatnonzero(got != v)[:10])
+        n_decided += int(st[9])
+    assert n_decided > 0
+
+
 @pytest.mark.parametrize("cfg,ev_i", [(2, 1), (4, 7), (5, 4)])
 def test_magnitude_bound_contains_point_drift(orc, cfg, ev_i):
     """The magnitude bound M of d^Ax over a triple (the classification's
