@@ -90,8 +90,8 @@ PEAK_FP64_TFLOPS = 78.6   # MI355X vector FP64: 256 CU x 128 FLOP/clk x 2.4 GHz
 # 1 GiB (bench.py --workload copy).  Valid only for the kernel sources they
 # were measured on (SHA-256 of ia_math.hpp + ia_kernels.hpp).
 TRAFFIC = {"kernel": "k_classify_defer (fp64 levels)", "workload": "event", "events_per_step": 1024,
-           "sources_sha256": "22e8c051463f03f17b9be5058d31a61ed64ab66fb736cd220905dffc1d7f5128",
-           "fetch_bytes": 96959069, "write_bytes": 268526665}
+           "sources_sha256": "b71e90aa972d0f39e8b5aa40b03c17f09fe31e6d06823c121b96720562441c58",
+           "fetch_bytes": 73465642, "write_bytes": 107593903}
 PEAK_FP32_TFLOPS = 157.3  # MI355X vector FP32 (non-packed)
 
 
