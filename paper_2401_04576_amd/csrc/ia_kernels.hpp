@@ -103,8 +103,14 @@ enum : uint32_t {
   kCwDefer = 5, kCwPass = 6, kCwIncl = 7,                              // second stage
   kCwN = 8
 };
-// class flag of a stereo pair whose class k_classify left to k_classify_defer
+// class flags of a stereo pair whose class k_classify left to
+// k_classify_defer: kFlagDeferred with both drift signs open, + 1 with only
+// dS = +d open, + 2 with only dS = -d open (the other sign casts no vote in
+// any box of the triple)
 constexpr uint8_t kFlagDeferred = 3;
+// drift signs (bit 0: +d, bit 1: -d) of a deferred flag, and the flag of a set
+IA_HD int defer_signs(uint8_t fl) { return fl == kFlagDeferred ? 3 : fl - kFlagDeferred; }
+IA_HD uint8_t defer_flag(int signs) { return static_cast<uint8_t>(signs == 3 ? kFlagDeferred : kFlagDeferred + signs); }
 
 // ---------------------------------------------------------------------------
 // edges of child k of [L, U] split m ways
@@ -614,7 +620,10 @@ IA_HD int stereo_quick_class(const PairQ& q, const Frame& f, const HitRec& h, Iv
   return -1;
 }
 
-IA_HD int stereo_pass_class(const PairQ& q, const Frame& f, const HitRec& h, Iv Z, Iv L, int32_t* cnt = nullptr) {
+// `signs` (bit 0: dS = +d, bit 1: dS = -d): the drift signs left open; a
+// sign outside it casts no vote in any box of the triple and is skipped.
+IA_HD int stereo_pass_class(const PairQ& q, const Frame& f, const HitRec& h, Iv Z, Iv L, int signs = 3,
+                            int32_t* cnt = nullptr) {
   const Iv G = {q.Glo, q.Ghi};
   const double tt = h.tant, t2 = tt * tt;
   const EnclIn32 c = encl_in32(q, f.R, tt, t2, h.d, Z, L);
@@ -623,6 +632,7 @@ IA_HD int stereo_pass_class(const PairQ& q, const Frame& f, const HitRec& h, Iv 
   // enclosure's registers once.
 #pragma unroll 1
   for (int si = 0; si < 2; ++si) {
+    if (!((signs >> si) & 1)) continue;
     Iv E, EPS, DISC, A;
     const bool ok = e_enclosure32(c, si != 0, f.sig, &E, &EPS, &DISC, &A);
     if (cnt) ++cnt[0];
@@ -642,7 +652,7 @@ IA_HD int stereo_pass_class(const PairQ& q, const Frame& f, const HitRec& h, Iv 
 
 IA_HD int triple_vote_class(const PairQ& q, const Frame& f, const HitRec& h, Iv Z, Iv L, int32_t* cnt = nullptr) {
   const int c = stereo_quick_class(q, f, h, Z, L);
-  return c >= 0 ? c : stereo_pass_class(q, f, h, Z, L, cnt);
+  return c >= 0 ? c : stereo_pass_class(q, f, h, Z, L, 3, cnt);
 }
 
 // false only when no box of the triple can get this stereo hit's vote
@@ -770,7 +780,7 @@ IA_HD int stereo_quick_class32(const PairQ& q, const Frame& f, const HitRec& h, 
 }
 
 IA_HD int stereo_pass_class32(const PairQ& q, const Frame& f, const HitRec& h, Iv Z, Iv L, float slack32,
-                              int32_t* cnt = nullptr) {
+                              int signs = 3, int32_t* cnt = nullptr) {
   const Iv32 G = to32(Iv{q.Glo, q.Ghi});
   const Iv32 K = to32(f.K);
   const float bs = wup32(ru32(h.band) + slack32);
@@ -782,6 +792,7 @@ IA_HD int stereo_pass_class32(const PairQ& q, const Frame& f, const HitRec& h, I
   // stereo_pass_class)
 #pragma unroll 1
   for (int si = 0; si < 2; ++si) {
+    if (!((signs >> si) & 1)) continue;
     Iv E, EPS, DISC, A;
     const bool ok = e_enclosure32(c, si != 0, f.sig, &E, &EPS, &DISC, &A);
     if (cnt) ++cnt[0];
@@ -805,11 +816,11 @@ IA_HD int stereo_pass_class32(const PairQ& q, const Frame& f, const HitRec& h, I
 IA_HD int triple_vote_class32(const PairQ& q, const Frame& f, const HitRec& h, Iv Z, Iv L, float slack32,
                               int32_t* cnt = nullptr) {
   const int c = stereo_quick_class32(q, f, h, Z, L, slack32);
-  return c >= 0 ? c : stereo_pass_class32(q, f, h, Z, L, slack32, cnt);
+  return c >= 0 ? c : stereo_pass_class32(q, f, h, Z, L, slack32, 3, cnt);
 }
 
 // What the parent-level enclosures of d^Ax give the first stage of the child
-// triples' classification (parent_range_excl), per drift sign s: when
+// triples' classification (parent_range_signs), per drift sign s: when
 // ok[s] is set, [wlo[s], whi[s]] holds the per-box H test's term
 // 2 E + kappa E^2 for every child box centre (E the point value of d^Ax
 // widened by the band, kappa over the parent); ok[s] is 0 where no range is
@@ -821,28 +832,30 @@ struct ParentE {
 
 // First-stage exclusion of a stereo pair at an FP64 refinement level with
 // the parent's ranges (ParentE), which hold the triple's boxes (its box
-// centres are among the parent's child centres): for both signs the per-box
-// H test fails for any term in [wlo, whi] with the outer G (class 0).  The
+// centres are among the parent's child centres): the set of drift signs for
+// which the per-box H test may pass for a term in [wlo, whi] with the outer
+// G (none: class 0; one: the second stage runs that sign's pass only).  The
 // per-box test computes wdn(2 G.lo - X.hi) and wup(2 G.hi - X.lo) for its
 // term X, which lies inside [wlo, whi] (the same outward-rounded operations
 // on narrower intervals), with G inside the outer G; both roundings are
 // monotone, so the bounds below carry over to every box.
-IA_HD bool parent_range_excl(const ParentE& pe, Iv Go) {
-  for (int si = 0; si < 2; ++si) {
-    if (!pe.ok[si]) return false;
-    if (!(wdn(2.0 * Go.lo - pe.whi[si]) > 0.0 || wup(2.0 * Go.hi - pe.wlo[si]) < 0.0)) return false;
-  }
-  return true;
+IA_HD int parent_range_signs(const ParentE& pe, Iv Go) {
+  int open = 0;
+  for (int si = 0; si < 2; ++si)
+    if (!pe.ok[si] || !(wdn(2.0 * Go.lo - pe.whi[si]) > 0.0 || wup(2.0 * Go.hi - pe.wlo[si]) < 0.0))
+      open |= 1 << si;
+  return open;
 }
 
 // The two stages of a (triple, hit) pair's class as the kernels run them.
 // Stage 1 (k_classify): the outer G (residual_G_outer); an axial pair is
 // decided exactly, with the exact G only when the outer one does not already
-// exclude both signs; a stereo pair is excluded by parent_range_excl (FP64
+// exclude both signs; a stereo pair is excluded by parent_range_signs (FP64
 // refinement levels, with the parent's ranges `pe`) or by the magnitude
-// bound from pair_magnitudes and the outer G, else deferred (-1).  Outside
-// the FP32 domain a stereo pair votes (1); without the proofs (`filter` 0)
-// it is class 2.  cnt[kCwG ..] counts the work when set.
+// bound from pair_magnitudes and the outer G, else deferred: the result is
+// then minus the set of drift signs left open (-3 both, -1 +d, -2 -d).
+// Outside the FP32 domain a stereo pair votes (1); without the proofs
+// (`filter` 0) it is class 2.  cnt[kCwG ..] counts the work when set.
 template <bool F32>
 IA_HD int pair_stage1(const Frame& f, const GTri& g, const HitRec& h, Iv Z, Iv L, int32_t filter, float slack32,
                       int32_t* cnt, const ParentE* pe = nullptr) {
@@ -857,20 +870,22 @@ IA_HD int pair_stage1(const Frame& f, const GTri& g, const HitRec& h, Iv Z, Iv L
   }
   if (F32 && !(f.R <= kR32Max)) return 1;
   if (!filter) return 2;
-  if (!F32 && pe && parent_range_excl(*pe, Go)) return 0;
+  const int signs = (!F32 && pe) ? parent_range_signs(*pe, Go) : 3;
+  if (!signs) return 0;
   if (cnt) { ++cnt[kCwPairQ]; ++cnt[kCwMag]; }
   const MagIn m = pair_magnitudes(f, h);
-  if (F32) return stereo_quick_class32_in(m, Go, f, h, Z, L, slack32);
-  return stereo_quick_class_in(m, Go, f, h, Z, L);
+  const int c = F32 ? stereo_quick_class32_in(m, Go, f, h, Z, L, slack32) : stereo_quick_class_in(m, Go, f, h, Z, L);
+  return c >= 0 ? c : -signs;
 }
 
 // Stage 2 (k_classify_defer): the exact G and pair quantities, then the
-// per-sign enclosure passes.  cnt[0] counts enclosures, cnt[1] inclusion
-// proofs.
+// enclosure passes of the drift signs stage 1 left open.  cnt[0] counts
+// enclosures, cnt[1] inclusion proofs.
 template <bool F32>
-IA_HD int pair_stage2(const Frame& f, const HitRec& h, Iv Z, Iv L, float slack32, int32_t* cnt) {
+IA_HD int pair_stage2(const Frame& f, const HitRec& h, Iv Z, Iv L, float slack32, int signs, int32_t* cnt) {
   const PairQ q = pair_quantities(f, h, residual_G(f, h));
-  return F32 ? stereo_pass_class32(q, f, h, Z, L, slack32, cnt) : stereo_pass_class(q, f, h, Z, L, cnt);
+  return F32 ? stereo_pass_class32(q, f, h, Z, L, slack32, signs, cnt)
+             : stereo_pass_class(q, f, h, Z, L, signs, cnt);
 }
 
 // (z0, tanl) centre ranges of the boxes of one parent
@@ -1193,7 +1208,8 @@ __device__ __forceinline__ int32_t block_sum(int32_t v, int32_t* sbuf) {
 // group z takes hits 4 z + w, 4 z + w + 4 gridDim.z, ...), so the hit of a
 // wave is uniform (axial and stereo work do not diverge) and each thread
 // computes its triple frame once.  flags are hit-major: flags[h * n_tr + t].
-// A stereo pair the quick stage leaves undecided gets kFlagDeferred and is
+// A stereo pair the quick stage leaves undecided gets a deferred flag
+// (kFlagDeferred .. kFlagDeferred + 2, with its open drift signs) and is
 // classified by k_classify_defer, which must run next: the enclosure passes
 // run there on compacted pairs, so that the lanes of a wave whose pairs were
 // decided here do not wait for them.
@@ -1240,7 +1256,7 @@ __global__ void __launch_bounds__(kWG) k_classify(const HitRec* __restrict__ hit
     uint8_t fl = 0;
     if (hr.use && (!pf || pf[h])) {
       const int c = pair_stage1<F32>(f, gt, hr, Zr, Lr, filter, slack32, COUNT ? cw : nullptr, pr ? &pr[h] : nullptr);
-      fl = c >= 0 ? static_cast<uint8_t>(c) : kFlagDeferred;
+      fl = c >= 0 ? static_cast<uint8_t>(c) : defer_flag(-c);
     }
     if (live) flags[int64_t(h) * n_tr + t] = fl;
     lb += fl == 1 ? 1 : 0;
@@ -1310,7 +1326,7 @@ __global__ void __launch_bounds__(kWG, 3) k_classify_defer(const HitRec* __restr
 #pragma unroll
   for (int k = 0; k < kDeferPer; ++k) {
     const uint32_t p = c0 + static_cast<uint32_t>(k * kWG) + threadIdx.x;
-    const bool d = k < per && p < n_pairs && flags[p] == kFlagDeferred;
+    const bool d = k < per && p < n_pairs && flags[p] >= kFlagDeferred;
     mask |= d ? (1u << k) : 0u;
     mine += d ? 1 : 0;
   }
@@ -1330,8 +1346,9 @@ __global__ void __launch_bounds__(kWG, 3) k_classify_defer(const HitRec* __restr
     Iv Zr, Lr;
     centre_ranges(TP, sh.m, &Zr, &Lr);
     const HitRec hr = hits[h];
+    const int signs = defer_signs(flags[p]);
     if constexpr (COUNT) ++cw[0];
-    const int c = pair_stage2<F32>(f, hr, Zr, Lr, slack32, COUNT ? &cw[1] : nullptr);
+    const int c = pair_stage2<F32>(f, hr, Zr, Lr, slack32, signs, COUNT ? &cw[1] : nullptr);
     flags[p] = static_cast<uint8_t>(c);
     if (c == 1) atomicAdd(&tlb[t], 1);
     else if (c == 2) atomicAdd(&tn2[t], 1);

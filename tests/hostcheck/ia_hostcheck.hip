@@ -43,7 +43,8 @@ extern "C" {
 // evaluations, [3] of those that voted, [4] evaluated pairs voting in every
 // box of their triple, [5] class 1, [6] triples evaluated, [7] T,
 // [8] (parent, hit) pairs the parent-level test excluded (with parent_filter),
-// [9] stereo pairs the first stage decided from the parent's ranges of d^Ax
+// [9] stereo pairs the first stage decided, or left with one drift sign,
+// from the parent's ranges of d^Ax
 int32_t hc_vote_level(const double* hits, int32_t n_hits, const double* parents, int32_t n_parents,
                       const int32_t split[5], int32_t filter, int32_t f32, double slack, int32_t prune_k,
                       int32_t ties, int32_t parent_filter, uint16_t* votes, int64_t* stats) {
@@ -90,10 +91,13 @@ int32_t hc_vote_level(const double* hits, int32_t n_hits, const double* parents,
         const ParentE* pr = (parent_filter && filter && !f32) ? &pe[size_t(tp) * n_hits + i] : nullptr;
         int c = f32 ? pair_stage1<true>(f, gt, h, Zr, Lr, filter, slack32, nullptr)
                     : pair_stage1<false>(f, gt, h, Zr, Lr, filter, slack32, nullptr, pr);
-        if (pr && c >= 0 && !h.axial && pair_stage1<false>(f, gt, h, Zr, Lr, filter, slack32, nullptr) < 0)
-          ++n_prange;
+        if (pr && !h.axial) {
+          const int c0 = pair_stage1<false>(f, gt, h, Zr, Lr, filter, slack32, nullptr);
+          if (c0 < 0 && c != c0) ++n_prange;
+        }
         if (c < 0)
-          c = f32 ? pair_stage2<true>(f, h, Zr, Lr, slack32, nullptr) : pair_stage2<false>(f, h, Zr, Lr, slack32, nullptr);
+          c = f32 ? pair_stage2<true>(f, h, Zr, Lr, slack32, -c, nullptr)
+                  : pair_stage2<false>(f, h, Zr, Lr, slack32, -c, nullptr);
         fl = static_cast<uint8_t>(c);
         if (!h.axial) {
           ++n_pairs;
