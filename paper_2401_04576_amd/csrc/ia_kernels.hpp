@@ -1218,7 +1218,7 @@ __device__ __forceinline__ int32_t block_sum(int32_t v, int32_t* sbuf) {
 // per counter per workgroup (a separate instantiation: the counting costs
 // the search a few per cent).
 template <bool F32, bool COUNT>
-__global__ void __launch_bounds__(kWG) k_classify(const HitRec* __restrict__ hits, EvView vw,
+__global__ void __launch_bounds__(kWG, 4) k_classify(const HitRec* __restrict__ hits, EvView vw,
                                                   const BoxD* __restrict__ parents, Shape sh,
                                                   uint8_t* __restrict__ flags, int32_t* __restrict__ tlb,
                                                   int32_t* __restrict__ tn2, int32_t filter,
