@@ -1550,7 +1550,7 @@ __global__ void __launch_bounds__(kWG) k_threshold(const int32_t* __restrict__ t
 // (slots taken in any order: votes do not depend on it).  Every writer of a
 // triple also writes the same TriFrame.  Events with rec_ok == 0 are skipped.
 template <bool F32>
-__global__ void __launch_bounds__(kWG) k_stage(const HitRec* __restrict__ hits_all, EvView vw,
+__global__ void __launch_bounds__(kWG, 4) k_stage(const HitRec* __restrict__ hits_all, EvView vw,
                                                const BoxD* __restrict__ parents_all, Shape sh,
                                                const uint8_t* __restrict__ flags_all,
                                                const int32_t* __restrict__ live_tri_all,
@@ -2321,8 +2321,10 @@ __global__ void __launch_bounds__(kWG) k_select_write(
 // centres (phi0 relative to the first cell's centre, in (-pi, pi]) and half
 // the extent of their union.  Sums are pairwise over the level's boxes in
 // index order on a zero-padded power-of-two array: k_est_partial reduces
-// aligned 256-box chunks (one box per lane, adjacent pairs in LDS), and
-// k_est_final reduces the chunk sums on the same tree.  vmax and the first
+// aligned 256-box chunks (one box per lane, adjacent pairs in LDS; a
+// workgroup takes `per` consecutive chunks in turn, at most kEstPer, fewer
+// for small launches), and k_est_final reduces the chunk sums on the same
+// tree.  vmax and the first
 // max-vote box come from the level's selection (rank 0).
 struct EstimateOut {
   double p[5], err[5];
@@ -2330,6 +2332,7 @@ struct EstimateOut {
 };
 
 constexpr int kEstQ = 16;        // 5 sums, 5 minima, 5 maxima, count
+constexpr int kEstPer = 16;      // chunks per k_est_partial workgroup
 
 __device__ __forceinline__ void tree_step(double (*s)[kWG], int w) {
   // s[q][i] = combine(s[q][2i], s[q][2i + 1]) for i < w / 2
@@ -2358,7 +2361,8 @@ __global__ void __launch_bounds__(kWG) k_est_partial(const BoxD* __restrict__ pa
                                                      const uint16_t* __restrict__ first_votes,
                                                      double* __restrict__ part, EvView vw,
                                                      const EventState* __restrict__ ev,
-                                                     const int32_t* __restrict__ wg_max, int32_t bx) {
+                                                     const int32_t* __restrict__ wg_max, int32_t bx,
+                                                     uint32_t n_part, uint32_t per) {
   const int e = blockIdx.y;
   if (ev && ev[e].done) return;
   parents += e * vw.par_stride;
@@ -2370,47 +2374,53 @@ __global__ void __launch_bounds__(kWG) k_est_partial(const BoxD* __restrict__ pa
   __shared__ double s[kEstQ][kWG];
   const int32_t vmax = first_votes[0];
   const double c0 = 0.5 * (first_box->lo[1] + first_box->hi[1]);
-  const uint32_t i = blockIdx.x * kWG + threadIdx.x;
-  double v[kEstQ];
-  for (int q = 0; q < 5; ++q) { v[q] = 0.0; v[5 + q] = INFINITY; v[10 + q] = -INFINITY; }
-  v[15] = 0.0;
-  // with wg_max, only tiles whose maximum reaches vmax hold written votes
-  const bool at_max = i < sh.n_boxes && (!wg_max || wg_max[i / static_cast<uint32_t>(bx)] >= vmax) && votes[i] == vmax;
-  // a chunk without a max-vote box reduces to the identity (sums 0, minima
-  // +inf, maxima -inf, count 0), bit for bit: write it without the tree
-  if (!__syncthreads_or(at_max ? 1 : 0)) {
-    if (threadIdx.x < kEstQ) {
-      const int q = static_cast<int>(threadIdx.x);
-      part[blockIdx.x * kEstQ + q] = (q >= 5 && q < 10) ? INFINITY : ((q >= 10 && q < 15) ? -INFINITY : 0.0);
-    }
-    return;
-  }
-  if (at_max) {
-    BoxD box;
-    level_box(parents, sh, i, &box);
-    for (int j = 0; j < 5; ++j) {
-      double lo = box.lo[j], hi = box.hi[j];
-      const double c = 0.5 * (lo + hi);
-      if (j == 1) {
-        const double dv = c - c0;
-        double shift = 0.0;
-        if (dv > kPi) shift = -kTwoPi;
-        else if (dv <= -kPi) shift = kTwoPi;
-        v[j] = dv + shift;
-        lo = lo + shift;
-        hi = hi + shift;
-      } else {
-        v[j] = c;
+  const uint32_t ch_end = min(n_part, (blockIdx.x + 1) * per);
+  for (uint32_t ch = blockIdx.x * per; ch < ch_end; ++ch) {
+    const uint32_t i = ch * kWG + threadIdx.x;
+    double v[kEstQ];
+    for (int q = 0; q < 5; ++q) { v[q] = 0.0; v[5 + q] = INFINITY; v[10 + q] = -INFINITY; }
+    v[15] = 0.0;
+    // with wg_max, only tiles whose maximum reaches vmax hold written votes
+    const bool at_max =
+        i < sh.n_boxes && (!wg_max || wg_max[i / static_cast<uint32_t>(bx)] >= vmax) && votes[i] == vmax;
+    // a chunk without a max-vote box reduces to the identity (sums 0,
+    // minima +inf, maxima -inf, count 0), bit for bit: write it without the
+    // tree
+    if (!__syncthreads_or(at_max ? 1 : 0)) {
+      if (threadIdx.x < kEstQ) {
+        const int q = static_cast<int>(threadIdx.x);
+        part[ch * kEstQ + q] = (q >= 5 && q < 10) ? INFINITY : ((q >= 10 && q < 15) ? -INFINITY : 0.0);
       }
-      v[5 + j] = lo;
-      v[10 + j] = hi;
+      continue;
     }
-    v[15] = 1.0;
+    if (at_max) {
+      BoxD box;
+      level_box(parents, sh, i, &box);
+      for (int j = 0; j < 5; ++j) {
+        double lo = box.lo[j], hi = box.hi[j];
+        const double c = 0.5 * (lo + hi);
+        if (j == 1) {
+          const double dv = c - c0;
+          double shift = 0.0;
+          if (dv > kPi) shift = -kTwoPi;
+          else if (dv <= -kPi) shift = kTwoPi;
+          v[j] = dv + shift;
+          lo = lo + shift;
+          hi = hi + shift;
+        } else {
+          v[j] = c;
+        }
+        v[5 + j] = lo;
+        v[10 + j] = hi;
+      }
+      v[15] = 1.0;
+    }
+    for (int q = 0; q < kEstQ; ++q) s[q][threadIdx.x] = v[q];
+    __syncthreads();
+    for (int w = kWG; w > 1; w >>= 1) tree_step(s, w);
+    if (threadIdx.x < kEstQ) part[ch * kEstQ + threadIdx.x] = s[threadIdx.x][0];
+    __syncthreads();                           // s is refilled for the next chunk
   }
-  for (int q = 0; q < kEstQ; ++q) s[q][threadIdx.x] = v[q];
-  __syncthreads();
-  for (int w = kWG; w > 1; w >>= 1) tree_step(s, w);
-  if (threadIdx.x < kEstQ) part[blockIdx.x * kEstQ + threadIdx.x] = s[threadIdx.x][0];
 }
 
 // hit finding (Sec. 3.3): does an active hit vote for the box estimate +- scale x error

@@ -146,6 +146,16 @@ int32_t est_parts(uint32_t n_boxes) {
   return static_cast<int32_t>(p2 / 256);
 }
 
+// chunks per k_est_partial workgroup: enough workgroups (about 2048) to fill
+// the device, at most kEstPer chunks each (n_part is a power of two)
+uint32_t est_per(int32_t n_part, int32_t n_ev) {
+  uint32_t per = 1;
+  while (per < static_cast<uint32_t>(ia::kEstPer) && per < static_cast<uint32_t>(n_part) &&
+         int64_t(n_part) * std::max(1, n_ev) / (2 * per) >= 2048)
+    per <<= 1;
+  return per;
+}
+
 // launches the selection of one level: histogram already in `hist`
 ia_status launch_select(ia_ctx* c, const uint16_t* votes, const Shape& sh, const BoxD* parents,
                         uint32_t* hist, int32_t n_bins, int32_t top_k, int32_t* cnt, uint32_t* tmp_idx,
@@ -612,8 +622,9 @@ ia_status run_chunk(ia_ctx* c, const double* hits_chunk, const int32_t* h_off_ch
       sel = (sel == selA) ? selB : selA;
     }
     const int32_t n_part = est_parts(sh.n_boxes);
-    hipLaunchKernelGGL(ia::k_est_partial, dim3(n_part, E), dim3(ia::kWG), 0, s, par, sh, votes, sel, sel_v, part, vw,
-                       ev, wg_max, last_bx);
+    const uint32_t eper = est_per(n_part, E);
+    hipLaunchKernelGGL(ia::k_est_partial, dim3((n_part + eper - 1) / eper, E), dim3(ia::kWG), 0, s, par, sh, votes,
+                       sel, sel_v, part, vw, ev, wg_max, last_bx, static_cast<uint32_t>(n_part), eper);
     hipLaunchKernelGGL(ia::k_est_final, dim3(1, E), dim3(ia::kWG), 0, s, part, n_part, sel, sel_v,
                        static_cast<ia::EstimateOut*>(nullptr), ev, recs, vw, sc->hitfind_scale, assigned, out, n_out);
     IA_HIP(c, hipGetLastError());
@@ -929,8 +940,9 @@ ia_status ia_estimate(ia_ctx* c, const ia_box* d_parents, int32_t n_parents, con
   ia::EvView vw = single_view(0);
   vw.k = 1;
   vw.part_stride = n_part * ia::kEstQ;
-  hipLaunchKernelGGL(ia::k_est_partial, dim3(n_part, 1), dim3(ia::kWG), 0, s, par, sh, d_votes, first, first_v, part,
-                     vw, nullptr, nullptr, 1);
+  const uint32_t eper = est_per(n_part, 1);
+  hipLaunchKernelGGL(ia::k_est_partial, dim3((n_part + eper - 1) / eper, 1), dim3(ia::kWG), 0, s, par, sh, d_votes,
+                     first, first_v, part, vw, nullptr, nullptr, 1, static_cast<uint32_t>(n_part), eper);
   hipLaunchKernelGGL(ia::k_est_final, dim3(1, 1), dim3(ia::kWG), 0, s, part, n_part, first, first_v,
                      reinterpret_cast<ia::EstimateOut*>(d_out), nullptr, nullptr, vw, 0.0, nullptr, nullptr, nullptr);
   IA_HIP(c, hipGetLastError());
