@@ -1502,15 +1502,23 @@ __global__ void __launch_bounds__(kWG) k_threshold(const int32_t* __restrict__ t
     for (uint32_t t = triple_of(b0); t <= triple_of(b1) && !lv; ++t) lv = triple_live(tlb[t], tn2[t], T, t, tcut);
     return lv;
   };
+  // the first 32 tiles' liveness is kept in a bit mask for the second pass
   int32_t mine = 0;
+  uint32_t lmask = 0;
   for (uint32_t tile = ta; tile < tb; ++tile) {
-    if (tile_live(tile)) ++mine;
-    else wg_max[tile] = -1;
+    const bool lv = tile_live(tile);
+    if (lv) {
+      ++mine;
+      if (tile - ta < 32u) lmask |= 1u << (tile - ta);
+    } else {
+      wg_max[tile] = -1;
+    }
   }
   int32_t pos;
   const int32_t total = block_scan_count(mine, &pos, sbuf);
   for (uint32_t tile = ta; tile < tb; ++tile)
-    if (tile_live(tile)) live_list[pos++] = static_cast<int32_t>(tile);
+    if (tile - ta < 32u ? ((lmask >> (tile - ta)) & 1u) != 0u : tile_live(tile))
+      live_list[pos++] = static_cast<int32_t>(tile);
   int32_t n_lt = 0, n_rec = 0;
   if (live_tri) {
     // triples whose class-2 pairs are evaluated, and their record offsets
