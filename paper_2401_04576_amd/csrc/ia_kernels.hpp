@@ -1947,7 +1947,7 @@ __global__ void __launch_bounds__(kWG) k_vote(const HitRec* __restrict__ hits, E
 // from k_stage, copied to LDS a chunk at a time, and the triple's frame
 // comes from its TriFrame, so the kernel holds only the per-box arithmetic.
 template <int BX, bool F32>
-__global__ void __launch_bounds__(kWG) k_vote_rec(EvView vw, const BoxD* __restrict__ parents_all, Shape sh,
+__global__ void __launch_bounds__(kWG, 4) k_vote_rec(EvView vw, const BoxD* __restrict__ parents_all, Shape sh,
                                                   uint16_t* __restrict__ votes_all, uint32_t* __restrict__ hist_all,
                                                   uint32_t* __restrict__ status, const EventState* __restrict__ ev,
                                                   const int32_t* __restrict__ tlb_all,
