@@ -130,7 +130,9 @@ def classify_flops(cw):
 
 
 def defer_flops(cw):
-    """FP64 flops of the second classification stage."""
+    """Flops of the second classification stage: FP64 frame, G and pair
+    quantities, and the enclosures, which run in FP32 without packed
+    instructions, at the same vector rate as FP64."""
     return (cw["deferred"] * (FLOP_CLS_FRAME + FLOP_CLS_G + FLOP_CLS_PAIRQ)
             + cw["enclosures"] * FLOP_CLS_ENCL + cw["inclusions"] * FLOP_CLS_INCL)
 
@@ -167,9 +169,15 @@ def roofline(kprof, work, cwork, wall, measured_on, traffic=None):
                     "launches": n, "total_ms": ms, **cwork[p]}
     dom = max(parts, key=lambda k: parts[k]["total_ms"])
     d = parts[dom]
-    traffic = traffic[1] if traffic and traffic[0] == dom else None
+    if traffic and traffic[0] == dom:
+        traffic, note = traffic[1], "measured on these kernel sources"
+    else:
+        traffic = None
+        note = ("no counter record for this kernel on these kernel sources and this workload "
+                f"(the last one covers {TRAFFIC['kernel']} on sources {TRAFFIC['sources_sha256'][:12]})")
     return {"bound": "alu", "achieved": d["achieved"], "peak": d["peak"], "unit": "TFLOP/s", "frac": d["frac"],
             "traffic": traffic, "traffic_unit": "bytes per launch (HBM, rocprofv3 FETCH_SIZE + WRITE_SIZE, scaled)",
+            "traffic_note": note,
             "kernel": dom, "avg_launch_ms": d["avg_launch_ms"], "launches": d["launches"],
             "share_of_wall": d["total_ms"] * 1e-3 / wall, "measured_on": measured_on,
             "by_kernel": parts}
