@@ -515,7 +515,9 @@ IA_HD bool votes_everywhere(Iv G, Iv K, double E1, double E2, double b) {
 // (a negative discriminant casts no vote).  Only sums, products, quotients
 // and roots of non-negative numbers remain, except three subtractions held
 // far from cancellation by the checks (u^2 >= 1/4, alo^2 - |Q| >= alo^2 / 4),
-// so the bound's own rounding stays below a few hundred ulps; the result is
+// so the bound's own rounding stays below a few hundred ulps, also with the
+// divisions by R^Ax and 2 R^Ax^2 taken as products with one rounded
+// reciprocal (a few ulps each); the result is
 // widened by 2^-29 relative + 1e-12 m, which also covers the point
 // evaluation's rounding (the margin of e_enclosure_dom).  Returns false when
 // a check fails (no bound).  `eps` bounds |eps|, `disc_lo` bounds the
@@ -523,17 +525,17 @@ IA_HD bool votes_everywhere(Iv G, Iv K, double E1, double E2, double b) {
 struct EMag { double M, eps, disc_lo, a_hi; };
 
 // magnitudes of the pair quantities that e_magnitude uses; sArc and dphi may
-// be upper bounds of the absolute values
-struct MagIn { double sa, ca, sArc, dphi, RAx, c2, s2, twoRAx2, RpRAx, cAx, sAx; };
+// be upper bounds of the absolute values; iRAx is 1 / RAx rounded
+struct MagIn { double sa, ca, sArc, dphi, RAx, c2, s2, iRAx, RpRAx, cAx, sAx; };
 
 IA_HD bool e_magnitude_in(const MagIn& q, double R, double tt, double d, Iv Z, Iv L, EMag* out) {
   const double at = fabs(tt), t2 = at * at;
   const double z = fmax(fabs(Z.lo), fabs(Z.hi)), l = fmax(fabs(L.lo), fabs(L.hi));
   const double sa = q.sa, ca = q.ca, S = sa + ca;
   const double za = z + l * q.sArc;
-  const double phi1 = (za * sa + (l * d) * ca) / q.RAx;
+  const double phi1 = (za * sa + (l * d) * ca) * q.iRAx;
   const double phi2 = ((l * R) * za + ((l * za) * (R + 2.0 * d)) * q.c2 +
-                       (za * za + d * (q.RAx + (l * l) * (q.RpRAx + d))) * q.s2) / q.twoRAx2;
+                       (za * za + d * (q.RAx + (l * l) * (q.RpRAx + d))) * q.s2) * ((0.5 * q.iRAx) * q.iRAx);
   const double eps = phi1 * at + phi2 * t2;
   const double u2 = 1.0 - ((2.0 * l) * S) * at;
   if (!(u2 >= 0.25)) return false;
@@ -556,15 +558,17 @@ IA_HD bool e_magnitude_in(const MagIn& q, double R, double tt, double d, Iv Z, I
 
 IA_HD bool e_magnitude(const PairQ& q, double R, double tt, double d, Iv Z, Iv L, EMag* out) {
   const MagIn m = {fabs(q.sinA), fabs(q.cosA), fabs(q.sArc), fabs(q.dphi), q.RAx, fabs(q.c2), fabs(q.s2),
-                   q.twoRAx2, q.RpRAx, fabs(q.cAx), fabs(q.sAx)};
+                   1.0 / q.RAx, q.RpRAx, fabs(q.cAx), fabs(q.sAx)};
   return e_magnitude_in(m, R, tt, d, Z, L, out);
 }
 
 // The inputs of e_magnitude without the arc angle's atan2: every quantity is
-// computed by pair_quantities' operations (the same values), and |dphi| is
-// bounded by |y| / x when x > 0 (|atan t| <= |t|; atan2_p is within a few ulps
-// of atan), else by pi; |sArc| by R times that.  The widening by 2^-45 covers
-// the few ulps.
+// computed by pair_quantities' operations, except that sinA and cosA are
+// products with one rounded reciprocal of RAx (within a few ulps of its
+// quotients, far inside e_magnitude's widening), and |dphi| is bounded by
+// |y| / x when x > 0 (|atan t| <= |t|; atan2_p is within a few ulps of atan),
+// else by pi; |sArc| by R times that.  The widening by 2^-45 covers the few
+// ulps.
 IA_HD MagIn pair_magnitudes(const Frame& f, const HitRec& h) {
   MagIn m;
   const double py = f.sig * h.py, cps = f.sig * h.cphis, sps = h.sphis;
@@ -572,7 +576,8 @@ IA_HD MagIn pair_magnitudes(const Frame& f, const HitRec& h) {
   m.RAx = sqrt(Dx * Dx + Dy * Dy);
   const double cAx = Dx * sps - Dy * cps;
   const double sAx = Dx * cps + Dy * sps;
-  const double sinA = sAx / m.RAx, cosA = cAx / m.RAx;
+  m.iRAx = 1.0 / m.RAx;
+  const double sinA = sAx * m.iRAx, cosA = cAx * m.iRAx;
   const double y = Dx * f.cp0 + Dy * f.sp0, x = Dx * f.sp0 - Dy * f.cp0;
   m.dphi = (x > 0.0 ? fabs(y) / x : kPio2Up * 2.0) * (1.0 + 0x1p-45);
   m.sArc = (f.R * m.dphi) * (1.0 + 0x1p-45);
@@ -580,7 +585,6 @@ IA_HD MagIn pair_magnitudes(const Frame& f, const HitRec& h) {
   m.ca = fabs(cosA);
   m.c2 = fabs(cosA * cosA - sinA * sinA);
   m.s2 = fabs(2.0 * sinA * cosA);
-  m.twoRAx2 = 2.0 * (m.RAx * m.RAx);
   m.RpRAx = f.R + m.RAx;
   m.cAx = fabs(cAx);
   m.sAx = fabs(sAx);
