@@ -164,12 +164,14 @@ ia_status ia_ctx_set_work_counting(ia_ctx *ctx, int32_t enable);
  * p (0 FP64 levels, 1 FP32 levels).  First stage: c = 0 outer enclosures of
  * the residual G (Eq. ApoVote over a triple), 1 axial tests, 2 exact G for
  * axial pairs the outer one did not exclude, 3 stereo pair magnitudes,
- * 4 magnitude bounds of d^Ax (each with its exclusion test).  Second stage:
- * c = 5 deferred pairs (each with its triple's frame, exact G and pair
- * quantities), 6 interval enclosures of d^Ax (each with its exclusion test),
- * 7 inclusion proofs.  Only pairs of live triples are counted; pairs the
- * parent-level test excluded are not.  Synchronises the device.  counts is
- * host memory of 16 entries. */
+ * 4 magnitude bounds of d^Ax (each with its exclusion test); at FP64
+ * refinement levels, c = 3 and 4 leave out the stereo pairs the parent's
+ * per-sign ranges of d^Ax already excluded.  Second stage: c = 5 deferred
+ * pairs (each with its triple's frame, exact G and pair quantities),
+ * 6 interval enclosures of d^Ax (one per drift sign left open, each with its
+ * exclusion test), 7 inclusion proofs.  Only pairs of live triples are
+ * counted; pairs the parent-level test excluded are not.  Synchronises the
+ * device.  counts is host memory of 16 entries. */
 ia_status ia_ctx_classify_work(ia_ctx *ctx, int64_t counts[16]);
 
 /* Band widening used by ia_vote_level at IA_FP32 (default 1e-6 m; ia_find_helices
