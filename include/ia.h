@@ -77,7 +77,11 @@ typedef struct {
 } ia_estimate_t;
 
 typedef struct {
-  double p[5], err[5];  /* estimate at the last level */
+  double p[5];          /* estimate at the last level, about the origin */
+  double err[5];        /* half the extent of the last level's max-vote boxes, in
+                           the parameters about ref */
+  double ref[2];        /* reference point of the last level ((0, 0) unless the
+                           window schedule moved it) */
   int32_t votes;        /* max vote at the last level */
   int32_t n_assigned;   /* hits assigned to this helix by hit finding */
   int32_t n_argmax;     /* boxes sharing the max vote at the last level */
@@ -86,13 +90,44 @@ typedef struct {
 
 #define IA_MAX_LEVELS 8
 
-/* the search schedule of ia_find_helices */
+/* schedule modes of ia_find_helices */
+enum { IA_SCHED_TOPK = 0, IA_SCHED_WINDOW = 1 };
+
+/* the search schedule of ia_find_helices.
+ *
+ * IA_SCHED_TOPK: level 0 is the grid `bins` over `range`; each later level
+ * splits the first top_k boxes of the previous one, by (votes desc, index
+ * asc), by `split`.
+ *
+ * IA_SCHED_WINDOW (the paper's iterative re-gridding, Sec. 3.3 and Table 1):
+ * every level is one regular grid over a window box, level 0 the grid `bins`
+ * over `range`, level l >= 1 the grid lbins[l] over a window built from ALL
+ * max-vote boxes of level l - 1 (never truncated): their union widened by one
+ * of that level's bins on each side (kappa and tanl clipped to `range`, d0
+ * and z0 too while the reference point is the origin; a phi0 window of a
+ * full turn or more becomes range's).  After level move_level the reference
+ * point of the parametrisation moves to the measurement point closest to the
+ * recovered circle (Sec. 3.3, second and third steps): the hit point (wire at
+ * z = 0) of the active hit with the smallest |G| of Eq. ApoVote's kappa-scaled
+ * form at the estimate, the lowest index on ties; the next window is then
+ * the hull of the max-vote boxes' 32 corners taken to the new reference
+ * point, widened so that it spans all but one bin at each end of the next
+ * grid (kappa and tanl clipped).  top_k and split are not used.
+ *
+ * forward: a hit votes for a box only if it lies ahead of the point of
+ * closest approach (along the direction of travel) for some phi0 of the box
+ * (interval test on cos(phi0 - phi_hit)).  The paper's particles start at the
+ * origin; the test removes the mirror twin (-d0, phi0 + pi, -kappa, z0, -tanl)
+ * that traces the same helix backwards and otherwise ties every helix.  It
+ * applies at every level in IA_SCHED_TOPK and at the levels up to move_level
+ * in IA_SCHED_WINDOW (all levels if move_level < 0), and to the hit finding
+ * of a pass whose last level is one of those. */
 typedef struct {
   ia_box range;           /* level-0 search range */
   int32_t bins[5];        /* level-0 grid */
   int32_t n_refine;       /* refinement levels after level 0 (< IA_MAX_LEVELS) */
-  int32_t top_k;          /* boxes kept per level, by (votes desc, index asc) */
-  int32_t split[5];       /* split of every kept box at the next level */
+  int32_t top_k;          /* IA_SCHED_TOPK: boxes kept per level, by (votes desc, index asc) */
+  int32_t split[5];       /* IA_SCHED_TOPK: split of every kept box at the next level */
   int32_t v_min;          /* stop when the level-0 max vote is below this */
   int32_t n_helix_max;    /* helices searched per event (greedy, hits removed) */
   double hitfind_scale;   /* hit-finding box = estimate +- scale x error (5 in Sec. 3.3) */
@@ -100,6 +135,11 @@ typedef struct {
   double fp32_slack;      /* band widening at FP32 levels, m, in [0, 1e-3]; it must
                            * bound the FP32 error of d^Ax (1e-6 is 100x the largest
                            * error seen on the chamber geometry) */
+  int32_t mode;           /* IA_SCHED_TOPK or IA_SCHED_WINDOW */
+  int32_t forward;        /* 1: forward-hit test (see above), 0: off */
+  int32_t move_level;     /* IA_SCHED_WINDOW: the reference point moves after this
+                           * level (-1: never; else in [0, n_refine)) */
+  int32_t lbins[IA_MAX_LEVELS][5];  /* IA_SCHED_WINDOW: grid of level l >= 1 */
 } ia_schedule;
 
 typedef struct ia_ctx ia_ctx;
@@ -173,6 +213,14 @@ ia_status ia_ctx_set_work_counting(ia_ctx *ctx, int32_t enable);
  * counted; pairs the parent-level test excluded are not.  Synchronises the
  * device.  counts is host memory of 16 entries. */
 ia_status ia_ctx_classify_work(ia_ctx *ctx, int64_t counts[16]);
+
+/* Frame of ia_vote_level (default: forward test off, reference point at the
+ * origin): with forward = 1 a hit votes only where it lies ahead of the
+ * point of closest approach (the test described at ia_schedule), and the
+ * hit points are taken about the reference point (xr, yr) -- the wire point
+ * at z = 0 less (xr, yr) -- so the boxes are perigee parameters about it.
+ * IA_ERR_INVALID for a non-finite reference point. */
+ia_status ia_ctx_set_vote_frame(ia_ctx *ctx, int32_t forward, double xr, double yr);
 
 /* Band widening used by ia_vote_level at IA_FP32 (default 1e-6 m; ia_find_helices
  * takes it from the schedule).  IA_ERR_INVALID outside [0, 1e-3]. */

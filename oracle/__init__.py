@@ -28,16 +28,20 @@ PREP_DTYPE = np.dtype([("valid", "i4"), ("axial", "i4"), ("px", "f8"), ("py", "f
 SCHED_DTYPE = np.dtype([("range", BOX_DTYPE), ("bins", "i4", (5,)), ("n_refine", "i4"),
                         ("top_k", "i4"), ("split", "i4", (5,)), ("v_min", "i4"),
                         ("n_helix_max", "i4"), ("hitfind_scale", "f8"), ("prec", "i4", (8,)),
-                        ("fp32_slack", "f8")], align=True)
+                        ("fp32_slack", "f8"), ("mode", "i4"), ("forward", "i4"),
+                        ("move_level", "i4"), ("lbins", "i4", (8, 5))], align=True)
 FP64, FP32 = 0, 1
-HELIX_DTYPE = np.dtype([("p", "f8", (5,)), ("err", "f8", (5,)), ("votes", "i4"),
+TOPK, WINDOW = 0, 1
+HELIX_DTYPE = np.dtype([("p", "f8", (5,)), ("err", "f8", (5,)), ("ref", "f8", (2,)), ("votes", "i4"),
                         ("n_assigned", "i4"), ("n_argmax", "i4"), ("pad", "i4")])
 MAX_LEVELS, MAX_K, MAX_PASSES = 8, 64, 16
 TRACE_DTYPE = np.dtype([("n_passes", "i4"),
                         ("vmax", "i4", (MAX_PASSES, MAX_LEVELS)),
                         ("n_argmax", "i4", (MAX_PASSES, MAX_LEVELS)),
                         ("selected", BOX_DTYPE, (MAX_PASSES, MAX_LEVELS, MAX_K)),
-                        ("selected_index", "i8", (MAX_PASSES, MAX_LEVELS, MAX_K))], align=True)
+                        ("selected_index", "i8", (MAX_PASSES, MAX_LEVELS, MAX_K)),
+                        ("grid", BOX_DTYPE, (MAX_PASSES, MAX_LEVELS)),
+                        ("ref", "f8", (MAX_PASSES, MAX_LEVELS, 2))], align=True)
 
 CFLAGS = ["-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
           "-fopenmp", "-Wall", "-Wextra"]
@@ -91,6 +95,14 @@ def lib():
         L.or_topk.restype = i32; L.or_topk.argtypes = [_P, i64, i32, _P, _P]
         L.or_estimate.restype = i32
         L.or_estimate.argtypes = [_P, i32, _P, _P, C.c_uint16, _P, _P]
+        L.or_prep_hit_ref.restype = i32; L.or_prep_hit_ref.argtypes = [_P, d, d, _P]
+        L.or_forward.restype = i32; L.or_forward.argtypes = [_P, _P]
+        L.or_frame_shift.restype = None; L.or_frame_shift.argtypes = [_P, d, d, _P]
+        L.or_point_G.restype = d; L.or_point_G.argtypes = [_P, _P]
+        L.or_vote_level_ex.restype = None
+        L.or_vote_level_ex.argtypes = [_P, i32, _P, _P, i32, _P, i32, d, i32, d, d, _P, i32]
+        L.or_estimate_ex.restype = i32
+        L.or_estimate_ex.argtypes = [_P, i32, _P, _P, C.c_uint16, _P, _P, _P, _P]
         L.or_find_helices.restype = i32
         L.or_find_helices.argtypes = [_P, i32, _P, _P, i32, _P, _P, i32]
         _lib = L
@@ -146,12 +158,30 @@ def isqr(a):
     return lo.value, hi.value
 
 
-def prep_hits(hits):
+def prep_hits(hits, ref=(0.0, 0.0)):
     hits = _c(hits, HIT_DTYPE)
     out = np.zeros(hits.shape[0], dtype=PREP_DTYPE)
     for i in range(hits.shape[0]):
-        lib().or_prep_hit(_ptr(hits[i:i + 1]), _ptr(out[i:i + 1]))
+        lib().or_prep_hit_ref(_ptr(hits[i:i + 1]), float(ref[0]), float(ref[1]), _ptr(out[i:i + 1]))
     return out
+
+
+def forward(prep, box):
+    prep = _c(np.atleast_1d(prep), PREP_DTYPE)
+    box = _c(np.atleast_1d(box), BOX_DTYPE)
+    return int(lib().or_forward(_ptr(prep), _ptr(box)))
+
+
+def frame_shift(p, dx, dy):
+    p = _c(p, np.float64)
+    q = np.zeros(5)
+    lib().or_frame_shift(_ptr(p), float(dx), float(dy), _ptr(q))
+    return q
+
+
+def point_G(prep, p):
+    prep = _c(np.atleast_1d(prep), PREP_DTYPE)
+    return float(lib().or_point_G(_ptr(prep), _ptr(_c(p, np.float64))))
 
 
 def make_box(lo, hi):
@@ -193,15 +223,17 @@ def pair_vote(prep, box, debug=False):
     return (int(v), dbg) if debug else int(v)
 
 
-def vote_level(hits, parents, split, active=None, n_threads=0, prec=FP64, slack=1e-6):
+def vote_level(hits, parents, split, active=None, n_threads=0, prec=FP64, slack=1e-6, forward=False,
+               ref=(0.0, 0.0)):
     hits = _c(hits, HIT_DTYPE)
     parents = _c(np.atleast_1d(parents), BOX_DTYPE)
     split = _c(split, np.int32)
     nb = parents.shape[0] * int(np.prod(split.astype(np.int64)))
     votes = np.zeros(nb, dtype=np.uint16)
     act = None if active is None else _c(active, np.uint8)
-    lib().or_vote_level_prec(_ptr(hits), hits.shape[0], _ptr(act), _ptr(parents), parents.shape[0],
-                             _ptr(split), int(prec), C.c_double(slack), _ptr(votes), int(n_threads))
+    lib().or_vote_level_ex(_ptr(hits), hits.shape[0], _ptr(act), _ptr(parents), parents.shape[0],
+                           _ptr(split), int(prec), C.c_double(slack), int(bool(forward)),
+                           float(ref[0]), float(ref[1]), _ptr(votes), int(n_threads))
     return votes
 
 
@@ -268,10 +300,29 @@ def estimate(parents, split, votes, vmax):
     return p, err, int(n)
 
 
+def estimate_ex(parents, split, votes, vmax):
+    """(p, err, n_argmax, union lo, union hi)"""
+    parents = _c(np.atleast_1d(parents), BOX_DTYPE)
+    split = _c(split, np.int32)
+    votes = _c(votes, np.uint16)
+    p, err, ulo, uhi = np.zeros(5), np.zeros(5), np.zeros(5), np.zeros(5)
+    n = lib().or_estimate_ex(_ptr(parents), parents.shape[0], _ptr(split), _ptr(votes), int(vmax),
+                             _ptr(p), _ptr(err), _ptr(ulo), _ptr(uhi))
+    return p, err, int(n), ulo, uhi
+
+
 def make_sched(lo, hi, bins, n_refine=4, top_k=32, split=(4, 4, 4, 4, 4), v_min=10,
-               n_helix_max=1, hitfind_scale=5.0, prec=None, fp32_slack=1e-6):
-    """prec: per-level FP64 / FP32 list (default all FP64)."""
+               n_helix_max=1, hitfind_scale=5.0, prec=None, fp32_slack=1e-6, mode=TOPK, forward=False,
+               move_level=-1, lbins=None):
+    """prec: per-level FP64 / FP32 list (default all FP64).  mode WINDOW: level l >= 1 is
+    a grid of lbins[l] over its window; the reference point moves after move_level."""
     s = np.zeros((), dtype=SCHED_DTYPE)
+    s["mode"] = mode
+    s["forward"] = int(bool(forward))
+    s["move_level"] = move_level
+    if lbins is not None:
+        for l, b in enumerate(lbins):
+            s["lbins"][l] = b
     if prec is not None:
         s["prec"][:len(prec)] = prec
     s["fp32_slack"] = fp32_slack

@@ -38,6 +38,7 @@ static const double PIO2_3 = 0x1.3198a2e037073p-69;
 static const double PI_RN = 0x1.921fb54442d18p+1;      /* pi, rounded (below pi) */
 static const double TWO_PI_RN = 0x1.921fb54442d18p+2;  /* 2 pi, rounded (below 2 pi) */
 static const double PIO2_RN = 0x1.921fb54442d18p+0;
+static const double PIO2_UP = 0x1.921fb54442d19p+0;   /* pi/2 rounded up */
 static const double PIO6_RN = 0x1.0c152382d7366p-1;
 static const double SQRT3_RN = 0x1.bb67ae8584caap+0;
 static const double INV_TWO_PI = 0x1.45f306dc9c883p-3;
@@ -198,15 +199,21 @@ void or_sin_encl(double a, double b, double *lo, double *hi) {
  * hit preparation: the wire point at z = 0 and the stereo direction
  * (Eqs. wirePar_a,b; Eqs. EQSinter_d,e with z_ref = 0)
  * ---------------------------------------------------------------------- */
-int32_t or_prep_hit(const or_hit *h, or_prep *o) {
+int32_t or_prep_hit(const or_hit *h, or_prep *o) { return or_prep_hit_ref(h, 0.0, 0.0, o); }
+
+/* The paper moves the reference point of the parametrisation near the hits
+ * between iterations (Sec. 3.3).  Perigee parameters about a reference point
+ * a are those of the hits translated by -a, so the hit point is taken about
+ * a: (px - xr, py - yr), one rounding each (exact for a = 0). */
+int32_t or_prep_hit_ref(const or_hit *h, double xr, double yr, or_prep *o) {
   memset(o, 0, sizeof *o);
   const double *f = &h->x0;
   for (int i = 0; i < 8; i++) if (!isfinite(f[i])) return 0;
   double dz = h->z1 - h->z0;
   if (dz == 0.0 || h->drift < 0.0 || h->band < 0.0) return 0;
   double tx = (h->x1 - h->x0) / dz, ty = (h->y1 - h->y0) / dz;
-  o->px = h->x0 - h->z0 * tx;
-  o->py = h->y0 - h->z0 * ty;
+  o->px = (h->x0 - h->z0 * tx) - xr;
+  o->py = (h->y0 - h->z0 * ty) - yr;
   o->tant = sqrt(tx * tx + ty * ty);
   if (!isfinite(o->px) || !isfinite(o->py) || !isfinite(o->tant)) return 0;
   /* direction (sin phi_s, -cos phi_s) tan(tau) = (tx, ty) with tan(tau) >= 0 */
@@ -344,6 +351,74 @@ int32_t or_pair_vote(const or_prep *h, const or_box *b, double *dbg) {
     if (H.lo <= 0.0 && 0.0 <= H.hi) vote = 1;
   }
   return vote;
+}
+
+/* ------------------------------------------------------------------------
+ * Forward-hit test.  The paper's particles come from the origin (Sec. 3.2),
+ * so along the direction of travel every hit lies after the point of
+ * closest approach.  Without this, the perigee form holds every helix twice:
+ * (d0, phi0, kappa, z0, tanl) and (-d0, phi0 + pi, -kappa, z0, -tanl) trace
+ * the same points in opposite directions and get the same votes.  The hit
+ * point P is ahead of the point of closest approach d0 (-sin phi0, cos phi0)
+ * when (P - PCA).(cos phi0, sin phi0) = r cos(phi0 - phiP) > 0.  Over the
+ * box's phi0 interval, cos(phi0 - phiP) = sin(phi0 - phiP + pi/2) is
+ * enclosed with the outward sine enclosure (the shifted ends rounded outward,
+ * pi/2 taken below it at the lower end and above it at the upper end); a hit
+ * is ahead for some phi0 of
+ * the box when the enclosure's upper end is positive (a sound test: it can
+ * only answer "ahead" too often).
+ * Parity: pinned by brute force over sampled phi0 and by the twin test.
+ * ---------------------------------------------------------------------- */
+int32_t or_forward(const or_prep *h, const or_box *b) {
+  if (h->r == 0.0) return 1;
+  double lo = or_wdn(or_wdn(b->lo[1] - h->phip) + PIO2_RN);
+  double hi = or_wup(or_wup(b->hi[1] - h->phip) + PIO2_UP);
+  double slo, shi;
+  or_sin_encl(lo, hi, &slo, &shi);
+  return shi > 0.0;
+}
+
+/* ------------------------------------------------------------------------
+ * Change of reference point (Sec. 3.3 moves it between iterations).  The
+ * circle of p about a has centre C = a + (1/kappa + d0) n with
+ * n = (-sin phi0, cos phi0); about b = a + D it is C = b + (1/kappa + d0') n'.
+ * Multiplying by kappa, A = (1 + kappa d0) n - kappa D = (1 + kappa d0') n',
+ * so n' = A / |A|, phi0' = atan2(-A_x, A_y) and
+ *   d0' = (|A|^2 - 1) / (kappa (|A| + 1))
+ *       = (2 d0 + kappa d0^2 - 2 (1 + kappa d0) n.D + kappa |D|^2) / (|A| + 1),
+ * which stays finite as kappa -> 0 (there d0' = d0 - n.D, a line).  The
+ * direction turns by dphi = atan2(kappa u.D, 1 + kappa d0 - kappa n.D) with
+ * u = (cos phi0, sin phi0) from the old point of closest approach to the
+ * new one, over the arc s = dphi / kappa (s = u.D when kappa = 0), and z
+ * grows by tanl s (Eq. HelixEq_c).  kappa and tanl do not change.
+ * Parity: pinned against a direct closest-point computation and by the
+ * round trip a -> b -> a.
+ * ---------------------------------------------------------------------- */
+void or_frame_shift(const double p[5], double dx, double dy, double q[5]) {
+  double d0 = p[0], f0 = p[1], k = p[2], z0 = p[3], l = p[4];
+  double s0 = or_sin(f0), c0 = or_cos(f0);
+  double nD = -s0 * dx + c0 * dy;
+  double uD = c0 * dx + s0 * dy;
+  double one = 1.0 + k * d0;
+  double ax = one * (-s0) - k * dx;
+  double ay = one * c0 - k * dy;
+  double A = sqrt(ax * ax + ay * ay);
+  double num = 2.0 * d0 + k * (d0 * d0) - 2.0 * one * nD + k * (dx * dx + dy * dy);
+  double f1 = or_atan2(-ax, ay);
+  if (f1 < 0.0) f1 += TWO_PI_RN;
+  double arc = uD;
+  if (k != 0.0) arc = or_atan2(k * uD, one - k * nD) / k;
+  q[0] = num / (A + 1.0);
+  q[1] = f1;
+  q[2] = k;
+  q[3] = z0 + l * arc;
+  q[4] = l;
+}
+
+/* G of Eq. ApoVote's kappa-scaled form at one parameter point */
+double or_point_G(const or_prep *h, const double p[5]) {
+  double d0 = p[0], k = p[2];
+  return 0.5 * k * (h->r * h->r + d0 * d0) + (1.0 + k * d0) * (h->r * or_sin(p[1] - h->phip)) + d0;
 }
 
 /* ------------------------------------------------------------------------
@@ -520,7 +595,7 @@ static int64_t prod5(const int32_t m[5]) {
 
 static void vote_prepped(const or_prep *pr, const uint8_t *use, int32_t n_hits,
                          const or_box *parents, int32_t n_parents, const int32_t split[5],
-                         int32_t prec, double slack, uint16_t *votes, int32_t n_threads) {
+                         int32_t prec, double slack, int32_t fwd, uint16_t *votes, int32_t n_threads) {
   int64_t nc = prod5(split), nb = (int64_t)n_parents * nc;
 #ifdef _OPENMP
   int nt = n_threads > 0 ? n_threads : omp_get_max_threads();
@@ -530,8 +605,10 @@ static void vote_prepped(const or_prep *pr, const uint8_t *use, int32_t n_hits,
     or_box box;
     or_box_child(&parents[b / nc], split, b % nc, &box);
     int32_t v = 0;
-    for (int32_t i = 0; i < n_hits; i++)
-      if (use[i]) v += prec == OR_FP32 ? or_pair_vote32(&pr[i], &box, slack, NULL) : or_pair_vote(&pr[i], &box, NULL);
+    for (int32_t i = 0; i < n_hits; i++) {
+      if (!use[i] || (fwd && !or_forward(&pr[i], &box))) continue;
+      v += prec == OR_FP32 ? or_pair_vote32(&pr[i], &box, slack, NULL) : or_pair_vote(&pr[i], &box, NULL);
+    }
     votes[b] = (uint16_t)v;
   }
   (void)n_threads;
@@ -546,11 +623,19 @@ void or_vote_level(const or_hit *hits, int32_t n_hits, const uint8_t *active,
 void or_vote_level_prec(const or_hit *hits, int32_t n_hits, const uint8_t *active,
                         const or_box *parents, int32_t n_parents, const int32_t split[5],
                         int32_t prec, double slack, uint16_t *votes, int32_t n_threads) {
+  or_vote_level_ex(hits, n_hits, active, parents, n_parents, split, prec, slack, 0, 0.0, 0.0, votes,
+                   n_threads);
+}
+
+void or_vote_level_ex(const or_hit *hits, int32_t n_hits, const uint8_t *active,
+                      const or_box *parents, int32_t n_parents, const int32_t split[5],
+                      int32_t prec, double slack, int32_t forward, double xr, double yr,
+                      uint16_t *votes, int32_t n_threads) {
   or_prep *pr = (or_prep *)calloc((size_t)(n_hits > 0 ? n_hits : 1), sizeof *pr);
   uint8_t *use = (uint8_t *)calloc((size_t)(n_hits > 0 ? n_hits : 1), 1);
   for (int32_t i = 0; i < n_hits; i++)
-    use[i] = (uint8_t)(or_prep_hit(&hits[i], &pr[i]) && (!active || active[i]));
-  vote_prepped(pr, use, n_hits, parents, n_parents, split, prec, slack, votes, n_threads);
+    use[i] = (uint8_t)(or_prep_hit_ref(&hits[i], xr, yr, &pr[i]) && (!active || active[i]));
+  vote_prepped(pr, use, n_hits, parents, n_parents, split, prec, slack, forward, votes, n_threads);
   free(pr);
   free(use);
 }
@@ -593,6 +678,13 @@ static double pairwise_sum(double *a, int64_t p2) {
 
 int32_t or_estimate(const or_box *parents, int32_t n_parents, const int32_t split[5],
                     const uint16_t *votes, uint16_t vmax, double p[5], double err[5]) {
+  double ulo[5], uhi[5];
+  return or_estimate_ex(parents, n_parents, split, votes, vmax, p, err, ulo, uhi);
+}
+
+int32_t or_estimate_ex(const or_box *parents, int32_t n_parents, const int32_t split[5],
+                       const uint16_t *votes, uint16_t vmax, double p[5], double err[5],
+                       double ulo[5], double uhi[5]) {
   int64_t nc = prod5(split), nb = (int64_t)n_parents * nc, p2 = 1;
   while (p2 < nb) p2 <<= 1;
   double *acc[5];
@@ -635,25 +727,64 @@ int32_t or_estimate(const or_box *parents, int32_t n_parents, const int32_t spli
     }
     err[j] = 0.5 * (hi_max[j] - lo_min[j]);
   }
+  for (int j = 0; j < 5; j++) { ulo[j] = lo_min[j]; uhi[j] = hi_max[j]; }
   for (int j = 0; j < 5; j++) free(acc[j]);
   return count;
 }
 
 /* ------------------------------------------------------------------------
- * the search for one event (Sec. 3.3): coarse vote, max-cell refinement,
- * estimate, hit finding with the box estimate +- scale x error; repeated on
- * the hits not yet assigned for several helices.
+ * the search for one event (Sec. 3.3): coarse vote, refinement, estimate,
+ * hit finding with the box estimate +- scale x error; repeated on the hits
+ * not yet assigned for several helices.
+ *
+ * OR_TOPK: each level keeps the first top_k boxes by (votes desc, index asc)
+ * and splits each by `split`.
+ *
+ * OR_WINDOW: each level is one regular grid over a window box.  Level 0's
+ * window is the search range.  After a level, the estimate and the union of
+ * ALL its max-vote boxes (never truncated: Sec. 3.3 computes the values and
+ * errors from every selected max cell) give the next window: the union
+ * widened by one of the level's bins on each side (kappa and tanl clipped
+ * to the range; d0 and z0 too while the reference point is the origin; a
+ * phi0 window of a full turn or more becomes the range's).  After level
+ * move_level the reference point moves, as the paper does for its second and
+ * third steps, to the measurement point closest to the recovered circle
+ * (the active hit point with the smallest |G| at the estimate, the lowest
+ * index on ties): every max-vote box's 32 corners are taken to the new
+ * reference point (or_frame_shift) and the next window is their hull
+ * widened so that it spans all but one bin at each end of the next grid
+ * (kappa and tanl clipped).  The forward-hit test applies at the levels up to
+ * move_level (all levels when the reference never moves).  The helix's p is
+ * the last estimate taken back to the origin; its err and the hit finding
+ * stay in the last level's frame.
+ * Parity of the driver: the per-level truth checks and the recovery rates
+ * (A22 tolerances) are pinned on generated events; there is no paper number.
  * ---------------------------------------------------------------------- */
-int32_t or_find_helices(const or_hit *hits, int32_t n_hits, const or_sched *sc,
-                        or_helix *out, int32_t max_out, int32_t *assigned,
-                        or_trace *trace, int32_t n_threads) {
-  int32_t nh1 = n_hits > 0 ? n_hits : 1;
-  or_prep *pr = (or_prep *)calloc((size_t)nh1, sizeof *pr);
-  uint8_t *act = (uint8_t *)calloc((size_t)nh1, 1);
+static uint16_t level_max(const uint16_t *votes, int64_t nb, int64_t *first) {
+  uint16_t vmax = 0;
+  int64_t f = 0;
+  for (int64_t b = 0; b < nb; b++)
+    if (votes[b] > vmax) { vmax = votes[b]; f = b; }
+  *first = f;
+  return vmax;
+}
+
+static void hit_finding(const or_prep *pr, uint8_t *act, int32_t n_hits, const or_box *E, int32_t fwd,
+                        int32_t *assigned, int32_t k, int32_t *na) {
   for (int32_t i = 0; i < n_hits; i++) {
-    act[i] = (uint8_t)or_prep_hit(&hits[i], &pr[i]);
-    if (assigned) assigned[i] = -1;
+    if (!act[i]) continue;
+    if (fwd && !or_forward(&pr[i], E)) continue;
+    if (or_pair_vote(&pr[i], E, NULL)) {
+      act[i] = 0;
+      if (assigned) assigned[i] = k;
+      (*na)++;
+    }
   }
+}
+
+static int32_t find_topk(const or_hit *hits, int32_t n_hits, const or_sched *sc, or_helix *out,
+                         int32_t max_out, int32_t *assigned, or_trace *trace, int32_t n_threads,
+                         or_prep *pr, uint8_t *act) {
   int64_t nb0 = prod5(sc->bins), nbr = (int64_t)sc->top_k * prod5(sc->split);
   int64_t nbmax = nb0 > nbr ? nb0 : nbr;
   uint16_t *votes = (uint16_t *)malloc((size_t)nbmax * sizeof(uint16_t));
@@ -662,8 +793,8 @@ int32_t or_find_helices(const or_hit *hits, int32_t n_hits, const or_sched *sc,
   or_box *nxt = (or_box *)malloc((size_t)(kmax > 1 ? kmax : 1) * sizeof(or_box));
   int64_t *tidx = (int64_t *)malloc((size_t)(kmax > 1 ? kmax : 1) * sizeof(int64_t));
   uint16_t *tv = (uint16_t *)malloc((size_t)(kmax > 1 ? kmax : 1) * sizeof(uint16_t));
-  if (trace) memset(trace, 0, sizeof *trace);
   int32_t nh = 0;
+  (void)hits;
   for (int32_t pass = 0; pass < sc->n_helix_max && nh < max_out; pass++) {
     int32_t n_par = 1, split[5];
     par[0] = sc->range;
@@ -671,7 +802,8 @@ int32_t or_find_helices(const or_hit *hits, int32_t n_hits, const or_sched *sc,
     uint16_t vmax = 0;
     int32_t stop = 0;
     for (int32_t lev = 0; lev <= sc->n_refine; lev++) {
-      vote_prepped(pr, act, n_hits, par, n_par, split, sc->prec[lev], sc->fp32_slack, votes, n_threads);
+      vote_prepped(pr, act, n_hits, par, n_par, split, sc->prec[lev], sc->fp32_slack, sc->forward, votes,
+                   n_threads);
       int64_t nb = (int64_t)n_par * prod5(split);
       int32_t k = or_topk(votes, nb, sc->top_k, tidx, tv);
       vmax = k > 0 ? tv[0] : 0;
@@ -709,18 +841,170 @@ int32_t or_find_helices(const or_hit *hits, int32_t n_hits, const or_sched *sc,
       E.hi[j] = hx.p[j] + w;
     }
     int32_t na = 0;
-    for (int32_t i = 0; i < n_hits; i++) {
-      if (!act[i]) continue;
-      if (or_pair_vote(&pr[i], &E, NULL)) {
-        act[i] = 0;
-        if (assigned) assigned[i] = nh;
-        na++;
-      }
-    }
+    hit_finding(pr, act, n_hits, &E, sc->forward, assigned, nh, &na);
     hx.n_assigned = na;
     out[nh++] = hx;
     if (na == 0) break;
   }
-  free(pr); free(act); free(votes); free(par); free(nxt); free(tidx); free(tv);
+  free(votes); free(par); free(nxt); free(tidx); free(tv);
+  return nh;
+}
+
+/* corner c (bit j: upper end of dimension j) of box b */
+static void box_corner(const or_box *b, int c, double x[5]) {
+  for (int j = 0; j < 5; j++) x[j] = ((c >> j) & 1) ? b->hi[j] : b->lo[j];
+}
+
+static int32_t find_window(const or_hit *hits, int32_t n_hits, const or_sched *sc, or_helix *out,
+                           int32_t max_out, int32_t *assigned, or_trace *trace, int32_t n_threads,
+                           or_prep *pr, uint8_t *act) {
+  int64_t nbmax = prod5(sc->bins);
+  for (int32_t l = 1; l <= sc->n_refine; l++)
+    if (prod5(sc->lbins[l]) > nbmax) nbmax = prod5(sc->lbins[l]);
+  uint16_t *votes = (uint16_t *)malloc((size_t)nbmax * sizeof(uint16_t));
+  int32_t nh = 0;
+  for (int32_t pass = 0; pass < sc->n_helix_max && nh < max_out; pass++) {
+    /* every pass starts about the origin */
+    double ref[2] = {0.0, 0.0};
+    int32_t moved = 0;
+    for (int32_t i = 0; i < n_hits; i++)
+      if (act[i]) or_prep_hit_ref(&hits[i], 0.0, 0.0, &pr[i]);
+    or_box grid = sc->range;
+    int32_t m[5];
+    memcpy(m, sc->bins, sizeof m);
+    uint16_t vmax = 0;
+    int32_t stop = 0, count = 0;
+    double p[5], err[5], ulo[5], uhi[5];
+    for (int32_t lev = 0; lev <= sc->n_refine; lev++) {
+      int32_t fwd = sc->forward && (sc->move_level < 0 || lev <= sc->move_level);
+      vote_prepped(pr, act, n_hits, &grid, 1, m, sc->prec[lev], sc->fp32_slack, fwd, votes, n_threads);
+      int64_t nb = prod5(m), first;
+      vmax = level_max(votes, nb, &first);
+      count = or_estimate_ex(&grid, 1, m, votes, vmax, p, err, ulo, uhi);
+      if (trace && pass < OR_MAX_PASSES && lev < OR_MAX_LEVELS) {
+        trace->n_passes = pass + 1;
+        trace->vmax[pass][lev] = vmax;
+        trace->n_argmax[pass][lev] = count;
+        trace->grid[pass][lev] = grid;
+        trace->ref[pass][lev][0] = ref[0];
+        trace->ref[pass][lev][1] = ref[1];
+        trace->selected_index[pass][lev][0] = first;
+        or_box_child(&grid, m, first, &trace->selected[pass][lev][0]);
+      }
+      if (lev == 0 && vmax < sc->v_min) { stop = 1; break; }
+      if (lev == sc->n_refine) break;
+      const int32_t *mn = sc->lbins[lev + 1];
+      or_box nx;
+      int32_t did_move = 0;
+      if (lev == sc->move_level) {
+        /* the measurement point closest to the recovered circle */
+        int32_t ib = -1;
+        double gb = 0.0;
+        for (int32_t i = 0; i < n_hits; i++) {
+          if (!act[i]) continue;
+          double g = fabs(or_point_G(&pr[i], p));
+          if (ib < 0 || g < gb) { ib = i; gb = g; }
+        }
+        if (ib >= 0) {
+          double dx = pr[ib].px, dy = pr[ib].py;
+          double hl[5], hh[5], cref = 0.0;
+          int32_t seen = 0;
+          for (int64_t b = 0; b < nb; b++) {
+            if (votes[b] != vmax) continue;
+            or_box box;
+            or_box_child(&grid, m, b, &box);
+            for (int c = 0; c < 32; c++) {
+              double x[5], q[5];
+              box_corner(&box, c, x);
+              or_frame_shift(x, dx, dy, q);
+              if (!seen) {
+                cref = q[1];
+                for (int j = 0; j < 5; j++) { hl[j] = q[j]; hh[j] = q[j]; }
+                seen = 1;
+                continue;
+              }
+              double dv = q[1] - cref;
+              if (dv > PI_RN) q[1] -= TWO_PI_RN;
+              else if (dv <= -PI_RN) q[1] += TWO_PI_RN;
+              for (int j = 0; j < 5; j++) { hl[j] = fmin(hl[j], q[j]); hh[j] = fmax(hh[j], q[j]); }
+            }
+          }
+          for (int j = 0; j < 5; j++) {
+            double bin = (hh[j] - hl[j]) / (double)(mn[j] > 2 ? mn[j] - 2 : 1);
+            nx.lo[j] = hl[j] - bin;
+            nx.hi[j] = hh[j] + bin;
+          }
+          ref[0] = ref[0] + dx;
+          ref[1] = ref[1] + dy;
+          moved = 1;
+          did_move = 1;
+          for (int32_t i = 0; i < n_hits; i++)
+            if (act[i]) or_prep_hit_ref(&hits[i], ref[0], ref[1], &pr[i]);
+        }
+      }
+      if (!did_move) {
+        for (int j = 0; j < 5; j++) {
+          double w = (grid.hi[j] - grid.lo[j]) / (double)m[j];
+          nx.lo[j] = ulo[j] - w;
+          nx.hi[j] = uhi[j] + w;
+        }
+        if (!moved) {
+          for (int j = 0; j < 5; j += 3) {
+            nx.lo[j] = fmax(nx.lo[j], sc->range.lo[j]);
+            nx.hi[j] = fmin(nx.hi[j], sc->range.hi[j]);
+          }
+        }
+      }
+      for (int j = 2; j < 5; j += 2) {
+        nx.lo[j] = fmax(nx.lo[j], sc->range.lo[j]);
+        nx.hi[j] = fmin(nx.hi[j], sc->range.hi[j]);
+      }
+      if (nx.hi[1] - nx.lo[1] >= TWO_PI_RN) { nx.lo[1] = sc->range.lo[1]; nx.hi[1] = sc->range.hi[1]; }
+      grid = nx;
+      memcpy(m, mn, sizeof m);
+    }
+    if (stop) break;
+    or_helix hx;
+    memset(&hx, 0, sizeof hx);
+    hx.n_argmax = count;
+    hx.votes = vmax;
+    or_box E;
+    for (int j = 0; j < 5; j++) {
+      double w = sc->hitfind_scale * err[j];
+      E.lo[j] = p[j] - w;
+      E.hi[j] = p[j] + w;
+    }
+    int32_t fwd = sc->forward && (sc->move_level < 0 || sc->n_refine <= sc->move_level);
+    int32_t na = 0;
+    hit_finding(pr, act, n_hits, &E, fwd, assigned, nh, &na);
+    if (moved) or_frame_shift(p, -ref[0], -ref[1], hx.p);
+    else memcpy(hx.p, p, sizeof hx.p);
+    for (int j = 0; j < 5; j++) hx.err[j] = err[j];
+    hx.ref[0] = ref[0];
+    hx.ref[1] = ref[1];
+    hx.n_assigned = na;
+    out[nh++] = hx;
+    if (na == 0) break;
+  }
+  free(votes);
+  return nh;
+}
+
+int32_t or_find_helices(const or_hit *hits, int32_t n_hits, const or_sched *sc,
+                        or_helix *out, int32_t max_out, int32_t *assigned,
+                        or_trace *trace, int32_t n_threads) {
+  int32_t nh1 = n_hits > 0 ? n_hits : 1;
+  or_prep *pr = (or_prep *)calloc((size_t)nh1, sizeof *pr);
+  uint8_t *act = (uint8_t *)calloc((size_t)nh1, 1);
+  for (int32_t i = 0; i < n_hits; i++) {
+    act[i] = (uint8_t)or_prep_hit(&hits[i], &pr[i]);
+    if (assigned) assigned[i] = -1;
+  }
+  if (trace) memset(trace, 0, sizeof *trace);
+  int32_t nh = sc->mode == OR_WINDOW
+                   ? find_window(hits, n_hits, sc, out, max_out, assigned, trace, n_threads, pr, act)
+                   : find_topk(hits, n_hits, sc, out, max_out, assigned, trace, n_threads, pr, act);
+  free(pr);
+  free(act);
   return nh;
 }

@@ -43,6 +43,7 @@ typedef struct {
 
 #define OR_MAX_LEVELS 8
 enum { OR_FP64 = 0, OR_FP32 = 1 };
+enum { OR_TOPK = 0, OR_WINDOW = 1 };
 
 typedef struct {
   or_box range; int32_t bins[5];          /* level-0 regular grid */
@@ -51,10 +52,19 @@ typedef struct {
   double hitfind_scale;                   /* half-width of the hit-finding box in errors */
   int32_t prec[OR_MAX_LEVELS];            /* OR_FP64 or OR_FP32 per level */
   double fp32_slack;                      /* band widening at FP32 levels (m) */
+  int32_t mode;                           /* OR_TOPK: top_k boxes split by split;
+                                             OR_WINDOW: one window box per level */
+  int32_t forward;                        /* forward-hit test at the levels in the
+                                             origin's frame */
+  int32_t move_level;                     /* OR_WINDOW: the reference point moves after
+                                             this level (-1: never) */
+  int32_t lbins[OR_MAX_LEVELS][5];        /* OR_WINDOW: grid of level l >= 1 over its window */
 } or_sched;
 
 typedef struct {
-  double p[5], err[5];
+  double p[5], err[5];   /* p about the origin; err: half extent of the max-vote
+                            boxes, in the frame of the reference point ref */
+  double ref[2];         /* reference point of the last level (0, 0 without a move) */
   int32_t votes, n_assigned, n_argmax, pad;
 } or_helix;
 
@@ -66,6 +76,8 @@ typedef struct {
   int32_t n_argmax[OR_MAX_PASSES][OR_MAX_LEVELS];
   or_box selected[OR_MAX_PASSES][OR_MAX_LEVELS][OR_MAX_K];
   int64_t selected_index[OR_MAX_PASSES][OR_MAX_LEVELS][OR_MAX_K];
+  or_box grid[OR_MAX_PASSES][OR_MAX_LEVELS];   /* OR_WINDOW: the box each level splits */
+  double ref[OR_MAX_PASSES][OR_MAX_LEVELS][2]; /* reference point of each level */
 } or_trace;
 
 /* elementary functions written for the oracle (Cody-Waite + Taylor) */
@@ -82,6 +94,9 @@ void or_imul(double alo, double ahi, double blo, double bhi, double *lo, double 
 void or_isqr(double alo, double ahi, double *lo, double *hi);
 
 int32_t or_prep_hit(const or_hit *h, or_prep *out);
+/* the same with the hit point taken about the reference point (xr, yr):
+ * px, py are the wire point at z = 0 less (xr, yr), r and phip its polar form */
+int32_t or_prep_hit_ref(const or_hit *h, double xr, double yr, or_prep *out);
 void or_box_child(const or_box *parent, const int32_t split[5], int64_t child, or_box *out);
 
 /* d^Ax at the point c for drift sign s (+1 / -1).  Returns 1 and writes
@@ -94,6 +109,21 @@ int32_t or_stereo_e(const or_prep *h, const double c[5], int32_t s, double *e, d
  * either drift sign.  dbg (nullable, 8 doubles): G lo/hi, H+ lo/hi, H- lo/hi,
  * e+, e-. */
 int32_t or_pair_vote(const or_prep *h, const or_box *b, double *dbg);
+
+/* Forward-hit test: 1 when the hit point lies ahead of the point of closest
+ * approach (x cos phi0 + y sin phi0 > 0) for some phi0 of the box, 0 when it
+ * lies behind for every phi0 of the box.  A hit at the reference point is
+ * ahead. */
+int32_t or_forward(const or_prep *h, const or_box *b);
+
+/* perigee parameters p about a reference point -> q about that point moved
+ * by (dx, dy); valid for kappa = 0 (straight lines) */
+void or_frame_shift(const double p[5], double dx, double dy, double q[5]);
+
+/* kappa-scaled residual G (Eq. ApoVote divided by 2 R) of the hit point at
+ * the parameter point p: its magnitude is the distance of the hit point from
+ * the circle to first order */
+double or_point_G(const or_prep *h, const double p[5]);
 
 /* FP32 levels (see the source for the definition): outward and nearest
  * FP64 -> FP32 conversions, FP32 widening, sin/cos on |x| <= 1, d^Ax with
@@ -118,6 +148,13 @@ void or_vote_level_prec(const or_hit *hits, int32_t n_hits, const uint8_t *activ
                         const or_box *parents, int32_t n_parents, const int32_t split[5],
                         int32_t prec, double slack, uint16_t *votes, int32_t n_threads);
 
+/* the same with the forward-hit test on (forward != 0) and the hits taken
+ * about the reference point (xr, yr) */
+void or_vote_level_ex(const or_hit *hits, int32_t n_hits, const uint8_t *active,
+                      const or_box *parents, int32_t n_parents, const int32_t split[5],
+                      int32_t prec, double slack, int32_t forward, double xr, double yr,
+                      uint16_t *votes, int32_t n_threads);
+
 /* the first k boxes by (votes desc, index asc); returns k actually taken */
 int32_t or_topk(const uint16_t *votes, int64_t n_boxes, int32_t k,
                 int64_t *out_index, uint16_t *out_votes);
@@ -125,6 +162,11 @@ int32_t or_topk(const uint16_t *votes, int64_t n_boxes, int32_t k,
 /* estimate from the max-vote boxes of a level (Sec. 3.3) */
 int32_t or_estimate(const or_box *parents, int32_t n_parents, const int32_t split[5],
                     const uint16_t *votes, uint16_t vmax, double p[5], double err[5]);
+/* the same, also writing the union [ulo, uhi] of the max-vote boxes (phi0
+ * taken relative to the first one's centre, as for p) */
+int32_t or_estimate_ex(const or_box *parents, int32_t n_parents, const int32_t split[5],
+                       const uint16_t *votes, uint16_t vmax, double p[5], double err[5],
+                       double ulo[5], double uhi[5]);
 
 /* the whole search for one event; returns the number of helices written.
  * assigned (nullable, n_hits) receives the helix index of each hit or -1. */

@@ -39,16 +39,30 @@ class Box(C.Structure):
     _fields_ = [("lo", C.c_double * 5), ("hi", C.c_double * 5)]
 
 
+SCHED_TOPK, SCHED_WINDOW = 0, 1
+
+
 class Schedule(C.Structure):
     _fields_ = [("range", Box), ("bins", C.c_int32 * 5), ("n_refine", C.c_int32), ("top_k", C.c_int32),
                 ("split", C.c_int32 * 5), ("v_min", C.c_int32), ("n_helix_max", C.c_int32),
                 ("hitfind_scale", C.c_double), ("prec", C.c_int32 * MAX_LEVELS),
-                ("fp32_slack", C.c_double)]
+                ("fp32_slack", C.c_double), ("mode", C.c_int32), ("forward", C.c_int32),
+                ("move_level", C.c_int32), ("lbins", (C.c_int32 * 5) * MAX_LEVELS)]
 
     @classmethod
     def make(cls, lo, hi, bins, n_refine=4, top_k=32, split=(4, 4, 4, 4, 4), v_min=10, n_helix_max=1,
-             hitfind_scale=5.0, prec=None, fp32_slack=1e-6):
+             hitfind_scale=5.0, prec=None, fp32_slack=1e-6, mode=SCHED_TOPK, forward=False, move_level=-1,
+             lbins=None):
+        """mode SCHED_WINDOW: level l >= 1 is the grid lbins[l] over a window built from all max-vote
+        boxes of level l - 1; the reference point moves after move_level (see include/ia.h)."""
         s = cls()
+        s.mode = int(mode)
+        s.forward = int(bool(forward))
+        s.move_level = int(move_level)
+        if lbins is not None:
+            for l, b in enumerate(lbins):
+                for j in range(5):
+                    s.lbins[l][j] = int(b[j])
         for j in range(5):
             s.range.lo[j] = float(lo[j])
             s.range.hi[j] = float(hi[j])
@@ -66,8 +80,8 @@ class Schedule(C.Structure):
         return s
 
 
-HELIX_DTYPE = np.dtype([("p", "f8", (5,)), ("err", "f8", (5,)), ("votes", "i4"), ("n_assigned", "i4"),
-                        ("n_argmax", "i4"), ("status", "i4")])
+HELIX_DTYPE = np.dtype([("p", "f8", (5,)), ("err", "f8", (5,)), ("ref", "f8", (2,)), ("votes", "i4"),
+                        ("n_assigned", "i4"), ("n_argmax", "i4"), ("status", "i4")])
 ESTIMATE_DTYPE = np.dtype([("p", "f8", (5,)), ("err", "f8", (5,)), ("vmax", "i4"), ("n_argmax", "i4")])
 
 _lib = None
@@ -106,6 +120,8 @@ def load():
     L.ia_ctx_profile_kernels.argtypes = [P, C.POINTER(i64), C.POINTER(C.c_double)]
     L.ia_ctx_set_fp32_slack.restype = i32
     L.ia_ctx_set_fp32_slack.argtypes = [P, C.c_double]
+    L.ia_ctx_set_vote_frame.restype = i32
+    L.ia_ctx_set_vote_frame.argtypes = [P, i32, C.c_double, C.c_double]
     L.ia_ctx_clear_status.restype = i32
     L.ia_ctx_clear_status.argtypes = [P]
     L.ia_ctx_set_batch.restype = i32
@@ -220,6 +236,10 @@ class Context:
     def set_fp32_slack(self, slack=1e-6):
         """Band widening of vote_level at FP32 (m)."""
         self._check(self._L.ia_ctx_set_fp32_slack(self._h, float(slack)))
+
+    def set_vote_frame(self, forward=False, ref=(0.0, 0.0)):
+        """forward-hit test and reference point of vote_level"""
+        self._check(self._L.ia_ctx_set_vote_frame(self._h, int(bool(forward)), float(ref[0]), float(ref[1])))
 
     def clear_status(self):
         self._check(self._L.ia_ctx_clear_status(self._h))

@@ -60,7 +60,12 @@ struct EventState {
   int32_t n_rec;                // their class-2 pairs (staged records)
   int32_t rec_ok;               // 1: the records fit the record buffer (else the in-kernel staging runs)
   int32_t t_cut;                // triples after this one with upper bound == t_prune are pruned too
+  int32_t moving;               // window schedule: 1 while the reference point is being moved
+  int32_t moved;                // window schedule: 1 once it moved in this pass
   double p[5], err[5];          // last estimate
+  double ulo[5], uhi[5];        // union of the last level's max-vote boxes (phi0 relative to the first)
+  double ref[2];                // reference point of the current level (origin coordinates)
+  double shift[2];              // move of the reference point under way (the chosen hit point)
 };
 
 // Per-event views of a batch of events launched together: blockIdx.y is the
@@ -82,6 +87,7 @@ struct EvView {
   int32_t max_out;              // helices per event
   int32_t max_hits;             // hits per event the strides are sized for (0: unchecked)
   int64_t n_total;              // hits addressable from the batch's first hit
+  int32_t fwd;                  // 1: forward-hit test at this level
   __device__ int32_t beg(int e) const { return off ? off[e] : 0; }
   __device__ int32_t count(int e) const { return off ? off[e + 1] - off[e] : n_single; }
 };
@@ -137,7 +143,10 @@ IA_HD void level_box(const BoxD* parents, const Shape& sh, uint32_t b, BoxD* out
 
 // ---------------------------------------------------------------------------
 // hit preparation (Eqs. wirePar_a,b and EQSinter_d,e with z_ref = 0)
-IA_HD void prep_one(const double* h, bool active, HitRec* o, bool* bad) {
+// The hit point is taken about the reference point (xr, yr) of the level's
+// parametrisation: the wire point at z = 0 less (xr, yr), one rounding each
+// (exact for the origin).
+IA_HD void prep_one(const double* h, bool active, HitRec* o, bool* bad, double xr = 0.0, double yr = 0.0) {
   HitRec r{};
   bool fin = true;
   for (int i = 0; i < 8; ++i) fin = fin && __builtin_isfinite(h[i]);
@@ -149,8 +158,8 @@ IA_HD void prep_one(const double* h, bool active, HitRec* o, bool* bad) {
   double dz = z1 - z0;
   if (dz == 0.0 || h[6] < 0.0 || h[7] < 0.0) { *bad = true; *o = r; return; }
   double tx = (x1 - x0) / dz, ty = (y1 - y0) / dz;
-  r.px = x0 - z0 * tx;
-  r.py = y0 - z0 * ty;
+  r.px = (x0 - z0 * tx) - xr;
+  r.py = (y0 - z0 * ty) - yr;
   r.tant = sqrt(tx * tx + ty * ty);
   if (!__builtin_isfinite(r.px) || !__builtin_isfinite(r.py) || !__builtin_isfinite(r.tant)) { *bad = true; *o = HitRec{}; return; }
   if (r.tant == 0.0) { r.sphis = 0.0; r.cphis = 1.0; r.axial = 1; }
@@ -210,6 +219,53 @@ IA_HD Iv residual_G(const Frame& f, const HitRec& h) {
   Iv KT = imul(f.K, T);
   Iv KD1 = iadd(imul(f.K, f.Dd), Iv{1.0, 1.0});
   return iadd(iadd(KT, imul(KD1, rS)), f.Dd);
+}
+
+// Forward-hit test over the phi0 interval of a triple: the hit point is ahead
+// of the point of closest approach for some phi0 when the enclosure of
+// cos(phi0 - phiP) = sin(phi0 - phiP + pi/2) reaches above zero (pi/2 taken
+// below it at the lower end, above it at the upper end, the ends rounded
+// outward).  A hit at the reference point is ahead.
+IA_HD bool forward_ok(const Iv& Fi, const HitRec& h) {
+  if (h.r == 0.0) return true;
+  const Iv S = sin_encl(wdn(wdn(Fi.lo - h.phip) + kPio2), wup(wup(Fi.hi - h.phip) + kPio2Up));
+  return S.hi > 0.0;
+}
+
+// Perigee parameters p about a reference point -> q about that point moved by
+// (dx, dy).  With n = (-sin phi0, cos phi0) and u = (cos phi0, sin phi0),
+// A = (1 + kappa d0) n - kappa D is kappa times the vector from the new point
+// to the circle's centre, so phi0' = atan2(-A_x, A_y) and
+// d0' = (2 d0 + kappa d0^2 - 2 (1 + kappa d0) n.D + kappa |D|^2) / (|A| + 1),
+// finite for kappa -> 0; the direction turns by
+// atan2(kappa u.D, 1 + kappa d0 - kappa n.D) over the arc s between the two
+// points of closest approach (s = u.D for kappa = 0), and z0' = z0 + tanl s.
+IA_HD void frame_shift(const double* p, double dx, double dy, double* q) {
+  const double d0 = p[0], f0 = p[1], k = p[2], z0 = p[3], l = p[4];
+  const double s0 = sin_p(f0), c0 = cos_p(f0);
+  const double nD = -s0 * dx + c0 * dy;
+  const double uD = c0 * dx + s0 * dy;
+  const double one = 1.0 + k * d0;
+  const double ax = one * (-s0) - k * dx;
+  const double ay = one * c0 - k * dy;
+  const double A = sqrt(ax * ax + ay * ay);
+  const double num = 2.0 * d0 + k * (d0 * d0) - 2.0 * one * nD + k * (dx * dx + dy * dy);
+  double f1 = atan2_p(-ax, ay);
+  if (f1 < 0.0) f1 += kTwoPi;
+  double arc = uD;
+  if (k != 0.0) arc = atan2_p(k * uD, one - k * nD) / k;
+  q[0] = num / (A + 1.0);
+  q[1] = f1;
+  q[2] = k;
+  q[3] = z0 + l * arc;
+  q[4] = l;
+}
+
+// G of the kappa-scaled Eq. ApoVote at one parameter point: to first order
+// the distance of the hit point from the circle
+IA_HD double point_G(const HitRec& h, const double* p) {
+  const double d0 = p[0], k = p[2];
+  return 0.5 * k * (h.r * h.r + d0 * d0) + (1.0 + k * d0) * (h.r * sin_p(p[1] - h.phip)) + d0;
 }
 
 // An outer enclosure of residual_G for exclusion tests, cheaper per pair.
@@ -1093,7 +1149,8 @@ __global__ void k_prep(const double* __restrict__ hits, const uint8_t* __restric
                        HitRec* __restrict__ out, uint32_t* __restrict__ hist, uint32_t* __restrict__ lbh,
                        int32_t* __restrict__ tlb, int32_t* __restrict__ tn2, uint32_t* __restrict__ status,
                        int64_t* __restrict__ n_bad, EventState* __restrict__ ev, int32_t* __restrict__ n_out,
-                       BoxD* __restrict__ range_dst, BoxD range, int32_t* __restrict__ assigned) {
+                       BoxD* __restrict__ range_dst, BoxD range, int32_t* __restrict__ assigned,
+                       double xr, double yr) {
   const int e = blockIdx.y;
   const int32_t beg = vw.beg(e), n_hits = vw.count(e), n_bins = n_hits + 1;
   const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1125,7 +1182,8 @@ __global__ void k_prep(const double* __restrict__ hits, const uint8_t* __restric
     }
   for (int32_t h = i; h < n_hits; h += stride) {
     bool bad;
-    prep_one(hits + 8 * static_cast<int64_t>(beg + h), active ? active[beg + h] != 0 : true, &out[beg + h], &bad);
+    prep_one(hits + 8 * static_cast<int64_t>(beg + h), active ? active[beg + h] != 0 : true, &out[beg + h], &bad,
+             xr, yr);
     if (assigned) assigned[beg + h] = -1;
     if (bad) {
       atomicOr(status, kStBadHit);
@@ -1258,7 +1316,7 @@ __global__ void __launch_bounds__(kWG, 4) k_classify(const HitRec* __restrict__ 
   for (int32_t h = static_cast<int32_t>(blockIdx.z) * (kWG / 64) + wave; h < n_hits; h += h_step) {
     const HitRec hr = hits[h];
     uint8_t fl = 0;
-    if (hr.use && (!pf || pf[h])) {
+    if (hr.use && (!pf || pf[h]) && (!vw.fwd || forward_ok(f.Fi, hr))) {
       const int c = pair_stage1<F32>(f, gt, hr, Zr, Lr, filter, slack32, COUNT ? cw : nullptr, pr ? &pr[h] : nullptr);
       fl = c >= 0 ? static_cast<uint8_t>(c) : defer_flag(-c);
     }
@@ -2436,12 +2494,13 @@ __global__ void __launch_bounds__(kWG) k_est_partial(const BoxD* __restrict__ pa
 }
 
 // hit finding (Sec. 3.3): does an active hit vote for the box estimate +- scale x error
-IA_HD bool pair_vote_box(const BoxD& b, const HitRec& h) {
+IA_HD bool pair_vote_box(const BoxD& b, const HitRec& h, bool fwd = false) {
   if (!h.use) return false;
   Frame f;
   f.Dd = {b.lo[0], b.hi[0]};
   f.Fi = {b.lo[1], b.hi[1]};
   f.K = {b.lo[2], b.hi[2]};
+  if (fwd && !forward_ok(f.Fi, h)) return false;
   double c0 = 0.5 * (f.Dd.lo + f.Dd.hi), c1 = 0.5 * (f.Fi.lo + f.Fi.hi), kap = 0.5 * (f.K.lo + f.K.hi);
   double sig = 1.0;
   if (kap < 0.0) sig = -1.0;
@@ -2464,20 +2523,24 @@ IA_HD bool pair_vote_box(const BoxD& b, const HitRec& h) {
 
 // helix record: {p[5], err[5], votes, n_assigned, n_argmax, status}
 struct HelixOut {
-  double p[5], err[5];
+  double p[5], err[5], ref[2];
   int32_t votes, n_assigned, n_argmax, status;
 };
 
 // One workgroup: combines the n_part chunk sums (n_part a power of two) on
 // the pairwise tree, writes the estimate; with `hits` set it then runs hit
 // finding for the event and records the helix.
+// With `ev` set and `hits` null it only records the estimate and the union of
+// the max-vote boxes in the event state (a level of the window schedule).
+// Hit finding applies the forward-hit test when fwd is set, in the level's
+// frame; the helix's p is taken back to the origin.
 __global__ void __launch_bounds__(kWG) k_est_final(const double* __restrict__ part, int32_t n_part,
                                                    const BoxD* __restrict__ first_box,
                                                    const uint16_t* __restrict__ first_votes,
                                                    EstimateOut* __restrict__ out, EventState* __restrict__ ev,
                                                    HitRec* __restrict__ hits, EvView vw, double scale,
                                                    int32_t* __restrict__ assigned, HelixOut* __restrict__ hout,
-                                                   int32_t* __restrict__ n_out) {
+                                                   int32_t* __restrict__ n_out, int32_t fwd) {
   const int e = blockIdx.y;
   if (ev && ev[e].done) return;
   part += int64_t(e) * vw.part_stride;
@@ -2548,9 +2611,18 @@ __global__ void __launch_bounds__(kWG) k_est_final(const double* __restrict__ pa
       out->vmax = first_votes[0];
       out->n_argmax = count;
     }
+    if (ev && !hits) {
+      for (int j = 0; j < 5; ++j) {
+        ev->p[j] = sp[j];
+        ev->err[j] = se[j];
+        ev->ulo[j] = s[5 + j][0];
+        ev->uhi[j] = s[10 + j][0];
+      }
+      ev->n_argmax = count;
+    }
   }
   __syncthreads();
-  if (!ev) return;
+  if (!ev || !hits) return;
   // hit finding: every still-active hit voting for estimate +- scale x error
   BoxD E;
   for (int j = 0; j < 5; ++j) {
@@ -2561,7 +2633,7 @@ __global__ void __launch_bounds__(kWG) k_est_final(const double* __restrict__ pa
   const int32_t k = ev->n_out;
   int32_t mine = 0;
   for (int32_t i = t; i < n_hits; i += kWG) {
-    if (pair_vote_box(E, hits[i])) {
+    if (pair_vote_box(E, hits[i], fwd != 0)) {
       hits[i].use = 0;
       if (assigned) assigned[i] = k;
       ++mine;
@@ -2573,7 +2645,11 @@ __global__ void __launch_bounds__(kWG) k_est_final(const double* __restrict__ pa
     const int32_t na = s_assigned;
     if (k < max_out) {
       HelixOut h;
-      for (int j = 0; j < 5; ++j) { h.p[j] = sp[j]; h.err[j] = se[j]; }
+      double p0[5] = {sp[0], sp[1], sp[2], sp[3], sp[4]};
+      if (ev->moved) frame_shift(sp, -ev->ref[0], -ev->ref[1], p0);
+      for (int j = 0; j < 5; ++j) { h.p[j] = p0[j]; h.err[j] = se[j]; }
+      h.ref[0] = ev->ref[0];
+      h.ref[1] = ev->ref[1];
       h.votes = first_votes[0];
       h.n_assigned = na;
       h.n_argmax = s_count;
@@ -2587,6 +2663,227 @@ __global__ void __launch_bounds__(kWG) k_est_final(const double* __restrict__ pa
     if (n_out) *n_out = ev->n_out;
     if (na == 0 || ev->n_out >= max_out) ev->done = 1;
   }
+}
+
+// ---------------------------------------------------------------------------
+// Window schedule (Sec. 3.3, Table 1): every level is one grid over a window
+// box per event.  The kernels below build the next window from all max-vote
+// boxes of a level and move the reference point of the parametrisation.
+
+// Re-prepares every hit of an event about its reference point (reset: about
+// the origin, and the event's frame is reset), keeping each hit's use flag.
+__global__ void __launch_bounds__(kWG) k_reframe(const double* __restrict__ hits, EvView vw,
+                                                 HitRec* __restrict__ out, EventState* __restrict__ ev,
+                                                 int32_t reset) {
+  const int e = blockIdx.y;
+  if (ev[e].done) return;
+  const int32_t beg = vw.beg(e), n_hits = vw.count(e);
+  const double xr = reset ? 0.0 : ev[e].ref[0], yr = reset ? 0.0 : ev[e].ref[1];
+  const int32_t stride = gridDim.x * blockDim.x;
+  for (int32_t h = blockIdx.x * blockDim.x + threadIdx.x; h < n_hits; h += stride) {
+    HitRec r;
+    bool bad;
+    prep_one(hits + 8 * static_cast<int64_t>(beg + h), out[beg + h].use != 0, &r, &bad, xr, yr);
+    out[beg + h] = r;
+  }
+  if (reset && blockIdx.x == 0 && threadIdx.x == 0) {
+    ev[e].ref[0] = 0.0;
+    ev[e].ref[1] = 0.0;
+    ev[e].moved = 0;
+  }
+}
+
+// The measurement point closest to the recovered circle: the active hit with
+// the smallest |G| at the estimate, the lowest index on ties.  One workgroup
+// per event; sets `moving` and `shift` (the hit point in the current frame).
+__global__ void __launch_bounds__(kWG) k_closest(const HitRec* __restrict__ hits, EvView vw,
+                                                 EventState* __restrict__ ev) {
+  const int e = blockIdx.y;
+  if (ev[e].done) return;
+  hits += vw.beg(e);
+  const int32_t n_hits = vw.count(e);
+  double p[5];
+  for (int j = 0; j < 5; ++j) p[j] = ev[e].p[j];
+  double gb = 0.0;
+  int32_t ib = -1;
+  for (int32_t i = threadIdx.x; i < n_hits; i += kWG) {
+    if (!hits[i].use) continue;
+    const double g = fabs(point_G(hits[i], p));
+    if (ib < 0 || g < gb) { gb = g; ib = i; }
+  }
+  __shared__ double sg[kWG];
+  __shared__ int32_t si[kWG];
+  sg[threadIdx.x] = gb;
+  si[threadIdx.x] = ib;
+  __syncthreads();
+  for (int w = kWG / 2; w > 0; w >>= 1) {
+    if (static_cast<int>(threadIdx.x) < w) {
+      const int32_t o = si[threadIdx.x + w];
+      const double go = sg[threadIdx.x + w];
+      const int32_t m = si[threadIdx.x];
+      if (o >= 0 && (m < 0 || go < sg[threadIdx.x] || (go == sg[threadIdx.x] && o < m))) {
+        sg[threadIdx.x] = go;
+        si[threadIdx.x] = o;
+      }
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const int32_t b = si[0];
+    ev[e].moving = b >= 0 ? 1 : 0;
+    if (b >= 0) {
+      ev[e].shift[0] = hits[b].px;
+      ev[e].shift[1] = hits[b].py;
+    }
+  }
+}
+
+// corner c of a box (bit j: upper end of dimension j)
+IA_HD void box_corner(const BoxD& b, int c, double* x) {
+  for (int j = 0; j < 5; ++j) x[j] = ((c >> j) & 1) ? b.hi[j] : b.lo[j];
+}
+
+// Hull of the max-vote boxes' corners taken to the new reference point, in
+// aligned 256-box chunks as k_est_partial (minima at q = 5..9, maxima at
+// q = 10..14 of each chunk's record); phi0 is unwrapped into half a turn of
+// the first max-vote box's first corner.  Minima and maxima do not depend on
+// the order of reduction.
+__global__ void __launch_bounds__(kWG) k_hull_partial(const BoxD* __restrict__ parents, Shape sh,
+                                                      const uint16_t* __restrict__ votes,
+                                                      const BoxD* __restrict__ first_box,
+                                                      const uint16_t* __restrict__ first_votes,
+                                                      double* __restrict__ part, EvView vw,
+                                                      const EventState* __restrict__ ev,
+                                                      const int32_t* __restrict__ wg_max, int32_t bx,
+                                                      uint32_t n_part, uint32_t per) {
+  const int e = blockIdx.y;
+  if (ev[e].done || !ev[e].moving) return;
+  parents += e * vw.par_stride;
+  votes += int64_t(e) * sh.n_boxes;
+  if (wg_max) wg_max += int64_t(e) * vw.wg_stride;
+  first_box += int64_t(e) * vw.k;
+  first_votes += int64_t(e) * vw.k;
+  part += int64_t(e) * vw.part_stride;
+  __shared__ double s[kEstQ][kWG];
+  const int32_t vmax = first_votes[0];
+  const double dx = ev[e].shift[0], dy = ev[e].shift[1];
+  double cref;
+  {
+    double x[5], q[5];
+    box_corner(*first_box, 0, x);
+    frame_shift(x, dx, dy, q);
+    cref = q[1];
+  }
+  const uint32_t ch_end = min(n_part, (blockIdx.x + 1) * per);
+  for (uint32_t ch = blockIdx.x * per; ch < ch_end; ++ch) {
+    const uint32_t i = ch * kWG + threadIdx.x;
+    double v[kEstQ];
+    for (int q = 0; q < 5; ++q) { v[q] = 0.0; v[5 + q] = INFINITY; v[10 + q] = -INFINITY; }
+    v[15] = 0.0;
+    const bool at_max =
+        i < sh.n_boxes && (!wg_max || wg_max[i / static_cast<uint32_t>(bx)] >= vmax) && votes[i] == vmax;
+    if (!__syncthreads_or(at_max ? 1 : 0)) {
+      if (threadIdx.x < kEstQ) {
+        const int q = static_cast<int>(threadIdx.x);
+        part[ch * kEstQ + q] = (q >= 5 && q < 10) ? INFINITY : ((q >= 10 && q < 15) ? -INFINITY : 0.0);
+      }
+      continue;
+    }
+    if (at_max) {
+      BoxD box;
+      level_box(parents, sh, i, &box);
+      for (int c = 0; c < 32; ++c) {
+        double x[5], q[5];
+        box_corner(box, c, x);
+        frame_shift(x, dx, dy, q);
+        const double dv = q[1] - cref;
+        if (dv > kPi) q[1] -= kTwoPi;
+        else if (dv <= -kPi) q[1] += kTwoPi;
+        for (int j = 0; j < 5; ++j) {
+          v[5 + j] = fmin(v[5 + j], q[j]);
+          v[10 + j] = fmax(v[10 + j], q[j]);
+        }
+      }
+    }
+    for (int q = 0; q < kEstQ; ++q) s[q][threadIdx.x] = v[q];
+    __syncthreads();
+    for (int w = kWG; w > 1; w >>= 1) tree_step(s, w);
+    if (threadIdx.x < kEstQ) part[ch * kEstQ + threadIdx.x] = s[threadIdx.x][0];
+    __syncthreads();
+  }
+}
+
+struct Bins5 { int32_t m[5]; };
+
+// Next window of an event from its level's max-vote boxes (one workgroup per
+// event).  After a move (move_now and the event is moving): the hull of the
+// corners reduced from k_hull_partial's records, widened so that it spans all
+// but one bin at each end of the next grid; the reference point advances by
+// the shift.  Otherwise: the union of the max-vote boxes widened by one of
+// the level's bins on each side, d0 and z0 clipped to the range while the
+// frame is the origin's.  Then kappa and tanl are clipped to the range, and a
+// phi0 window of a full turn or more becomes the range's.
+__global__ void __launch_bounds__(kWG) k_window(const double* __restrict__ part, int32_t n_part,
+                                                const BoxD* __restrict__ parents, Shape sh,
+                                                BoxD* __restrict__ win, EventState* __restrict__ ev, EvView vw,
+                                                BoxD range, Bins5 next, int32_t move_now) {
+  const int e = blockIdx.y;
+  EventState& es = ev[e];
+  if (es.done) return;
+  part += int64_t(e) * vw.part_stride;
+  const bool mv = move_now && es.moving;
+  __shared__ double slo[5][kWG], shi[5][kWG];
+  if (mv) {
+    double lo[5], hi[5];
+    for (int j = 0; j < 5; ++j) { lo[j] = INFINITY; hi[j] = -INFINITY; }
+    for (int32_t c = threadIdx.x; c < n_part; c += kWG)
+      for (int j = 0; j < 5; ++j) {
+        lo[j] = fmin(lo[j], part[c * kEstQ + 5 + j]);
+        hi[j] = fmax(hi[j], part[c * kEstQ + 10 + j]);
+      }
+    for (int j = 0; j < 5; ++j) { slo[j][threadIdx.x] = lo[j]; shi[j][threadIdx.x] = hi[j]; }
+    __syncthreads();
+    for (int w = kWG / 2; w > 0; w >>= 1) {
+      if (static_cast<int>(threadIdx.x) < w)
+        for (int j = 0; j < 5; ++j) {
+          slo[j][threadIdx.x] = fmin(slo[j][threadIdx.x], slo[j][threadIdx.x + w]);
+          shi[j][threadIdx.x] = fmax(shi[j][threadIdx.x], shi[j][threadIdx.x + w]);
+        }
+      __syncthreads();
+    }
+  }
+  if (threadIdx.x != 0) return;
+  const BoxD& G = parents[e * vw.par_stride];
+  BoxD nx;
+  if (mv) {
+    for (int j = 0; j < 5; ++j) {
+      const double hl = slo[j][0], hh = shi[j][0];
+      const double bin = (hh - hl) / static_cast<double>(next.m[j] > 2 ? next.m[j] - 2 : 1);
+      nx.lo[j] = hl - bin;
+      nx.hi[j] = hh + bin;
+    }
+    es.ref[0] = es.ref[0] + es.shift[0];
+    es.ref[1] = es.ref[1] + es.shift[1];
+    es.moved = 1;
+  } else {
+    for (int j = 0; j < 5; ++j) {
+      const double w = (G.hi[j] - G.lo[j]) / static_cast<double>(sh.m[j]);
+      nx.lo[j] = es.ulo[j] - w;
+      nx.hi[j] = es.uhi[j] + w;
+    }
+    if (!es.moved)
+      for (int j = 0; j < 5; j += 3) {
+        nx.lo[j] = fmax(nx.lo[j], range.lo[j]);
+        nx.hi[j] = fmin(nx.hi[j], range.hi[j]);
+      }
+  }
+  for (int j = 2; j < 5; j += 2) {
+    nx.lo[j] = fmax(nx.lo[j], range.lo[j]);
+    nx.hi[j] = fmin(nx.hi[j], range.hi[j]);
+  }
+  if (nx.hi[1] - nx.lo[1] >= kTwoPi) { nx.lo[1] = range.lo[1]; nx.hi[1] = range.hi[1]; }
+  win[e] = nx;
+  es.moving = 0;
 }
 
 }  // namespace ia

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -66,6 +67,8 @@ struct ia_ctx {
   int32_t count_work = 0;         // classification launches count their work
   int32_t max_chunk = 65535;      // events per batched launch
   float slack32 = ia::ru32(1e-6);  // band widening of ia_vote_level at FP32
+  int32_t vf_forward = 0;         // ia_vote_level: forward-hit test
+  double vf_xr = 0.0, vf_yr = 0.0;  // ia_vote_level: reference point
   // pinned staging ring for the chunk-relative hit offsets copied to the
   // device; a slot is rewritten only after its previous copy has completed
   int32_t* pinned = nullptr;
@@ -411,7 +414,7 @@ ia_status launch_vote_rec(ia_ctx* c, const ia::EvView& vw, int32_t n_ev, const B
 // scratch layout of one chunk of ia_find_helices (byte offsets into the
 // arena): per-event slices of every array, sized for events of max_hits hits
 struct FindLayout {
-  size_t off, recs, votes, hist, lbh, selA, selB, range, sel_idx, sel_v, ev, part, flags, tlb, tn2, wg_max, live,
+  size_t win, off, recs, votes, hist, lbh, selA, selB, range, sel_idx, sel_v, ev, part, flags, tlb, tn2, wg_max, live,
       live_tri, rec_off, rec_fill, tfr, rec, pflags, pe, live_off, stage_off, total;
   int64_t flag_stride, tri_stride, votes_stride, rec_stride, pflag_stride;
   int32_t hist_stride, wg_stride, part_stride, n_part;
@@ -436,6 +439,7 @@ void layout_find(int64_t max_level_boxes, int64_t max_triples, int32_t top_k, in
     off += align_up(bytes + 1);
     return o;
   };
+  L->win = take(sizeof(BoxD) * E);
   L->off = take(sizeof(int32_t) * (E + 1));
   L->recs = take(sizeof(HitRec) * size_t(std::max<int64_t>(1, n_hits_total)));
   L->votes = take(sizeof(uint16_t) * size_t(L->votes_stride) * E);
@@ -470,8 +474,25 @@ struct SchedShapes {
   int64_t max_boxes, max_triples;
 };
 
+// selection size of a schedule: the window schedule keeps the first
+// max-vote box only (its levels need the maximum and the max-vote set)
+int32_t sched_k(const ia_schedule* sc) { return sc->mode == IA_SCHED_WINDOW ? 1 : sc->top_k; }
+
 bool sched_shapes(const ia_schedule* sc, SchedShapes* S) {
   if (!make_shape(sc->bins, 1, &S->sh0)) return false;
+  S->max_boxes = S->sh0.n_boxes;
+  S->max_triples = S->sh0.m012;
+  if (sc->mode == IA_SCHED_WINDOW) {
+    if (sc->n_refine < 0 || sc->n_refine >= IA_MAX_LEVELS) return false;
+    S->shr = S->sh0;
+    for (int l = 1; l <= sc->n_refine; ++l) {
+      Shape sh;
+      if (!make_shape(sc->lbins[l], 1, &sh)) return false;
+      S->max_boxes = std::max<int64_t>(S->max_boxes, sh.n_boxes);
+      S->max_triples = std::max<int64_t>(S->max_triples, sh.m012);
+    }
+    return true;
+  }
   if (!make_shape(sc->split, std::max(1, sc->top_k), &S->shr)) return false;
   S->max_boxes = std::max<int64_t>(S->sh0.n_boxes, S->shr.n_boxes);
   S->max_triples = std::max<int64_t>(int64_t(S->sh0.n_parents) * S->sh0.m012, int64_t(S->shr.n_parents) * S->shr.m012);
@@ -480,7 +501,20 @@ bool sched_shapes(const ia_schedule* sc, SchedShapes* S) {
 
 ia_status check_sched(ia_ctx* c, const ia_schedule* sc) {
   if (sc->n_refine < 0 || sc->n_refine >= IA_MAX_LEVELS) return fail(c, IA_ERR_INVALID, "n_refine %d", sc->n_refine);
-  if (sc->top_k < 1 || sc->top_k > kMaxTopK) return fail(c, IA_ERR_INVALID, "top_k %d", sc->top_k);
+  if (sc->mode != IA_SCHED_TOPK && sc->mode != IA_SCHED_WINDOW) return fail(c, IA_ERR_INVALID, "mode %d", sc->mode);
+  if (sc->forward != 0 && sc->forward != 1) return fail(c, IA_ERR_INVALID, "forward %d", sc->forward);
+  if (sc->mode == IA_SCHED_WINDOW) {
+    if (sc->move_level < -1 || sc->move_level >= sc->n_refine)
+      return fail(c, IA_ERR_INVALID, "move_level %d outside [-1, n_refine)", sc->move_level);
+    for (int l = 1; l <= sc->n_refine; ++l)
+      for (int j = 0; j < 5; ++j)
+        if (sc->lbins[l][j] < 1) return fail(c, IA_ERR_INVALID, "lbins[%d][%d] = %d < 1", l, j, sc->lbins[l][j]);
+    for (int j = 0; j < 5; ++j)
+      if (!std::isfinite(sc->range.lo[j]) || !std::isfinite(sc->range.hi[j]))
+        return fail(c, IA_ERR_INVALID, "range dimension %d is not finite", j);
+  } else if (sc->top_k < 1 || sc->top_k > kMaxTopK) {
+    return fail(c, IA_ERR_INVALID, "top_k %d", sc->top_k);
+  }
   if (sc->n_helix_max < 0) return fail(c, IA_ERR_INVALID, "n_helix_max %d", sc->n_helix_max);
   if (!(sc->hitfind_scale >= 0.0)) return fail(c, IA_ERR_INVALID, "hitfind_scale");
   for (int j = 0; j < 5; ++j)
@@ -493,6 +527,103 @@ ia_status check_sched(ia_ctx* c, const ia_schedule* sc) {
   return IA_OK;
 }
 
+// The window schedule (ia_schedule, IA_SCHED_WINDOW) for a chunk of E
+// events whose hits are prepared: per pass, every level votes one grid over
+// the event's window (the range at level 0), keeps only the first max-vote
+// box (so that its pruning threshold is the largest lower bound), reduces the
+// estimate and the union of all max-vote boxes, and builds the next window
+// (after move_level: the closest hit, the hull of the moved corners, and the
+// hits re-prepared about the new reference point).  The last level runs hit
+// finding and writes the helix.
+ia_status run_window(ia_ctx* c, const double* hits, ia::EvView vw, int32_t E, int32_t cmax, const SchedShapes& S,
+                     const ia_schedule* sc, float slack32, bool may_overflow, const FindLayout& L, HitRec* recs,
+                     uint16_t* votes, uint32_t* hist, BoxD* sel, BoxD* range, int64_t* sel_idx, uint16_t* sel_v,
+                     EventState* ev, double* part, uint8_t* flags, uint8_t* pflags, ia::ParentE* pe, int32_t* tlb,
+                     int32_t* tn2, uint32_t* lbh, int32_t* wg_max, int32_t* live, const RecIn& rin,
+                     int32_t* assigned, ia::HelixOut* out, int32_t* n_out, hipStream_t s) {
+  BoxD* win = reinterpret_cast<BoxD*>(c->arena + L.win);
+  BoxD rb;
+  std::memcpy(&rb, &sc->range, sizeof rb);
+  const int32_t pg = std::max(1, (cmax + 255) / 256);
+  const int32_t max_per_event = vw.max_out;
+  for (int32_t pass = 0; pass < std::min(sc->n_helix_max, max_per_event); ++pass) {
+    // every pass starts about the origin
+    if (pass > 0 && sc->move_level >= 0)
+      hipLaunchKernelGGL(ia::k_reframe, dim3(pg, E), dim3(ia::kWG), 0, s, hits, vw, recs, ev, 1);
+    const BoxD* par = range;
+    Shape sh = S.sh0;
+    vw.par_stride = 0;
+    for (int32_t lev = 0; lev <= sc->n_refine; ++lev) {
+      const bool f32 = sc->prec[lev] == IA_FP32;
+      vw.fwd = sc->forward && (sc->move_level < 0 || lev <= sc->move_level) ? 1 : 0;
+      const bool use_pf = lev > 0 && use_filter(c) && c->parent_filter;
+      if (use_pf) {
+        const int64_t n_pairs = int64_t(sh.n_parents) * std::max(1, cmax);
+        const dim3 gp(static_cast<uint32_t>(std::min<int64_t>((n_pairs + ia::kWG - 1) / ia::kWG, 65535)), E);
+        if (f32)
+          hipLaunchKernelGGL((ia::k_parent_filter<true>), gp, dim3(ia::kWG), 0, s, recs, vw, par, sh, pflags, ev,
+                             slack32, nullptr);
+        else
+          hipLaunchKernelGGL((ia::k_parent_filter<false>), gp, dim3(ia::kWG), 0, s, recs, vw, par, sh, pflags, ev,
+                             slack32, pe);
+      }
+      {
+        const ia_status cs = launch_classify(c, recs, vw, E, cmax, par, sh, flags, tlb, tn2, ev, s, f32, slack32,
+                                             use_pf ? pflags : nullptr, (use_pf && !f32) ? pe : nullptr);
+        if (cs != IA_OK) return cs;
+      }
+      const int32_t vt = vote_tile(c, sh.n_boxes);
+      hipLaunchKernelGGL(ia::k_threshold, dim3(1, E), dim3(ia::kWG), 0, s, tlb, tn2, lbh, vw, sh, 1, c->prune, 0,
+                         vt, ev, live, wg_max, rin.live_tri, rin.rec_off, rin.rec_fill, L.rec_stride);
+      launch_stage(recs, vw, E, par, sh, flags, rin, ev, s, f32, slack32);
+      const VoteIn in{flags, tlb, tn2, live, 1};
+      ia_status st = launch_vote_rec(c, vw, E, par, sh, votes, hist, ev, in, rin, wg_max, s, f32);
+      if (st != IA_OK) return st;
+      int32_t bx = vt;
+      if (may_overflow) {
+        st = launch_vote(c, recs, vw, E, par, sh, votes, hist, ev, in, wg_max, s, f32, slack32, &bx);
+        if (st != IA_OK) return st;
+      }
+      const uint32_t n_wg = (sh.n_boxes + bx - 1) / bx;
+      hipLaunchKernelGGL(ia::k_select_wg, dim3(1, E), dim3(ia::kWG), 0, s, votes, vw, hist, wg_max, n_wg, bx, par,
+                         sh, sel, sel_idx, sel_v, ev, lev == 0 ? std::max(sc->v_min, 0) : 0, tlb, tn2, 1);
+      const int32_t n_part = est_parts(sh.n_boxes);
+      const uint32_t eper = est_per(n_part, E);
+      const dim3 gpart((n_part + eper - 1) / eper, E);
+      hipLaunchKernelGGL(ia::k_est_partial, gpart, dim3(ia::kWG), 0, s, par, sh, votes, sel, sel_v, part, vw, ev,
+                         wg_max, bx, static_cast<uint32_t>(n_part), eper);
+      if (lev == sc->n_refine) {
+        const int32_t fwd_hf = sc->forward && (sc->move_level < 0 || sc->n_refine <= sc->move_level) ? 1 : 0;
+        hipLaunchKernelGGL(ia::k_est_final, dim3(1, E), dim3(ia::kWG), 0, s, part, n_part, sel, sel_v,
+                           static_cast<ia::EstimateOut*>(nullptr), ev, recs, vw, sc->hitfind_scale, assigned, out,
+                           n_out, fwd_hf);
+        IA_HIP(c, hipGetLastError());
+        break;
+      }
+      hipLaunchKernelGGL(ia::k_est_final, dim3(1, E), dim3(ia::kWG), 0, s, part, n_part, sel, sel_v,
+                         static_cast<ia::EstimateOut*>(nullptr), ev, static_cast<HitRec*>(nullptr), vw, 0.0,
+                         static_cast<int32_t*>(nullptr), static_cast<ia::HelixOut*>(nullptr),
+                         static_cast<int32_t*>(nullptr), 0);
+      const bool mv = lev == sc->move_level;
+      if (mv) {
+        hipLaunchKernelGGL(ia::k_closest, dim3(1, E), dim3(ia::kWG), 0, s, recs, vw, ev);
+        hipLaunchKernelGGL(ia::k_hull_partial, gpart, dim3(ia::kWG), 0, s, par, sh, votes, sel, sel_v, part, vw, ev,
+                           wg_max, bx, static_cast<uint32_t>(n_part), eper);
+      }
+      ia::Bins5 nb;
+      for (int j = 0; j < 5; ++j) nb.m[j] = sc->lbins[lev + 1][j];
+      hipLaunchKernelGGL(ia::k_window, dim3(1, E), dim3(ia::kWG), 0, s, part, n_part, par, sh, win, ev, vw, rb, nb,
+                         mv ? 1 : 0);
+      if (mv) hipLaunchKernelGGL(ia::k_reframe, dim3(pg, E), dim3(ia::kWG), 0, s, hits, vw, recs, ev, 0);
+      IA_HIP(c, hipGetLastError());
+      if (!make_shape(sc->lbins[lev + 1], 1, &sh)) return fail(c, IA_ERR_OVERFLOW, "level %d too large", lev + 1);
+      par = win;
+      vw.par_stride = 1;
+    }
+  }
+  return IA_OK;
+}
+
 // One chunk of E events through every pass and level.  The chunk's CSR
 // offsets (relative to hits_chunk) come from the host (h_off_chunk, copied
 // through the pinned ring) or are already on the device (dev_off, then no
@@ -501,7 +632,7 @@ ia_status run_chunk(ia_ctx* c, const double* hits_chunk, const int32_t* h_off_ch
                     int32_t E, int32_t cmax, int64_t n_tot, const SchedShapes& S, const ia_schedule* sc,
                     float slack32, int64_t rpe, bool may_overflow, ia::HelixOut* out_chunk, int32_t max_per_event,
                     int32_t* n_out_chunk, int32_t* assigned_chunk, hipStream_t s) {
-  const int32_t K = sc->top_k;
+  const int32_t K = sched_k(sc);
   Persistent* ps = persistent(c);
   BoxD rb;
   std::memcpy(&rb, &sc->range, sizeof rb);
@@ -561,7 +692,11 @@ ia_status run_chunk(ia_ctx* c, const double* hits_chunk, const int32_t* h_off_ch
   int32_t* n_out = n_out_chunk;
   const int32_t pg = std::max(1, (cmax + 2 + 255) / 256);
   hipLaunchKernelGGL(ia::k_prep, dim3(pg, E), dim3(256), 0, s, hits, nullptr, vw, recs, hist, lbh, tlb, tn2,
-                     &ps->status, &ps->n_bad, ev, n_out, range, rb, assigned);
+                     &ps->status, &ps->n_bad, ev, n_out, range, rb, assigned, 0.0, 0.0);
+  if (sc->mode == IA_SCHED_WINDOW)
+    return run_window(c, hits, vw, E, cmax, S, sc, slack32, may_overflow, L, recs, votes, hist, selA, range, sel_idx,
+                      sel_v, ev, part, flags, pflags, pe, tlb, tn2, lbh, wg_max, live, rin, assigned, out, n_out, s);
+  vw.fwd = sc->forward;
   for (int32_t pass = 0; pass < std::min(sc->n_helix_max, max_per_event); ++pass) {
     const BoxD* par = range;
     Shape sh = S.sh0;
@@ -626,7 +761,8 @@ ia_status run_chunk(ia_ctx* c, const double* hits_chunk, const int32_t* h_off_ch
     hipLaunchKernelGGL(ia::k_est_partial, dim3((n_part + eper - 1) / eper, E), dim3(ia::kWG), 0, s, par, sh, votes,
                        sel, sel_v, part, vw, ev, wg_max, last_bx, static_cast<uint32_t>(n_part), eper);
     hipLaunchKernelGGL(ia::k_est_final, dim3(1, E), dim3(ia::kWG), 0, s, part, n_part, sel, sel_v,
-                       static_cast<ia::EstimateOut*>(nullptr), ev, recs, vw, sc->hitfind_scale, assigned, out, n_out);
+                       static_cast<ia::EstimateOut*>(nullptr), ev, recs, vw, sc->hitfind_scale, assigned, out, n_out,
+                       sc->forward);
     IA_HIP(c, hipGetLastError());
   }
   return IA_OK;
@@ -812,6 +948,16 @@ ia_status ia_ctx_profile_read(ia_ctx* c, int64_t* n_launches, double* total_ms, 
   return st;
 }
 
+ia_status ia_ctx_set_vote_frame(ia_ctx* c, int32_t forward, double xr, double yr) {
+  if (!c) return IA_ERR_INVALID;
+  if (forward != 0 && forward != 1) return fail(c, IA_ERR_INVALID, "forward %d", forward);
+  if (!std::isfinite(xr) || !std::isfinite(yr)) return fail(c, IA_ERR_INVALID, "reference point not finite");
+  c->vf_forward = forward;
+  c->vf_xr = xr;
+  c->vf_yr = yr;
+  return IA_OK;
+}
+
 ia_status ia_ctx_set_fp32_slack(ia_ctx* c, double slack) {
   if (!c) return IA_ERR_INVALID;
   if (!(slack >= 0.0 && slack <= 1e-3)) return fail(c, IA_ERR_INVALID, "fp32 slack %g outside [0, 1e-3]", slack);
@@ -824,7 +970,7 @@ size_t ia_ctx_scratch_needed(const ia_schedule* sc, int32_t max_hits) {
   SchedShapes S;
   if (!sched_shapes(sc, &S)) return 0;
   FindLayout L;
-  layout_find(S.max_boxes, S.max_triples, std::max(1, sc->top_k), max_hits, 1, max_hits, &L);
+  layout_find(S.max_boxes, S.max_triples, std::max(1, sched_k(sc)), max_hits, 1, max_hits, &L);
   return L.total;
 }
 
@@ -850,7 +996,7 @@ ia_status ia_vote_level(ia_ctx* c, const ia_hit* d_hits, int32_t n_hits, const u
     hipLaunchKernelGGL(ia::k_prep, dim3((n_hits + 255) / 256, 1), dim3(256), 0, s,
                        reinterpret_cast<const double*>(d_hits), d_active, vw, recs, nullptr, nullptr, nullptr, nullptr,
                        &ps->status,
-                       &ps->n_bad, nullptr, nullptr, nullptr, BoxD{}, nullptr);
+                       &ps->n_bad, nullptr, nullptr, nullptr, BoxD{}, nullptr, c->vf_xr, c->vf_yr);
   // classes of the (triple, hit) pairs and per-triple vote bounds
   const int64_t n_tr = int64_t(sh.n_parents) * sh.m012;
   uint8_t* flags = bump<uint8_t>(c, size_t(std::max<int64_t>(1, n_tr * int64_t(n_hits))));
@@ -861,6 +1007,7 @@ ia_status ia_vote_level(ia_ctx* c, const ia_hit* d_hits, int32_t n_hits, const u
                 static_cast<long long>(n_tr * (int64_t(n_hits) + 8)));
   vw.flag_stride = 0;
   vw.tri_stride = 0;
+  vw.fwd = c->vf_forward;
   const BoxD* par = reinterpret_cast<const BoxD*>(d_parents);
   const bool f32 = prec == IA_FP32;
   const uint32_t fill_n = static_cast<uint32_t>(std::min<int64_t>(n_tr, 0x7fffffff));
@@ -944,7 +1091,8 @@ ia_status ia_estimate(ia_ctx* c, const ia_box* d_parents, int32_t n_parents, con
   hipLaunchKernelGGL(ia::k_est_partial, dim3((n_part + eper - 1) / eper, 1), dim3(ia::kWG), 0, s, par, sh, d_votes,
                      first, first_v, part, vw, nullptr, nullptr, 1, static_cast<uint32_t>(n_part), eper);
   hipLaunchKernelGGL(ia::k_est_final, dim3(1, 1), dim3(ia::kWG), 0, s, part, n_part, first, first_v,
-                     reinterpret_cast<ia::EstimateOut*>(d_out), nullptr, nullptr, vw, 0.0, nullptr, nullptr, nullptr);
+                     reinterpret_cast<ia::EstimateOut*>(d_out), nullptr, nullptr, vw, 0.0, nullptr, nullptr, nullptr,
+                     0);
   IA_HIP(c, hipGetLastError());
   return IA_OK;
 }
@@ -971,7 +1119,7 @@ ia_status ia_find_helices(ia_ctx* c, const ia_hit* d_hits, const int32_t* h_off,
   if (S.max_boxes > kMaxEstimateBoxes)
     return fail(c, IA_ERR_OVERFLOW, "a level exceeds %lld boxes", static_cast<long long>(kMaxEstimateBoxes));
   IA_HIP(c, hipSetDevice(c->device));
-  const int32_t K = sc->top_k;
+  const int32_t K = sched_k(sc);
   // events per chunk: as many as the arena holds.  Staged records: room for
   // every (triple, hit) pair when a full chunk fits that way, else kRecCap
   // per event (an event needing more is voted with in-kernel staging)
@@ -1103,10 +1251,10 @@ ia_status ia_find_helices_dev(ia_ctx* c, const ia_hit* d_hits, const int32_t* d_
   const int64_t worst_rec = std::max<int64_t>(1, S.max_triples * int64_t(max_hits));
   int64_t rpe = worst_rec;
   FindLayout L;
-  layout_find(S.max_boxes, S.max_triples, sc->top_k, max_hits, n_events, n_hits_total, &L, rpe);
+  layout_find(S.max_boxes, S.max_triples, sched_k(sc), max_hits, n_events, n_hits_total, &L, rpe);
   if (L.total > c->arena_bytes && kRecCap < worst_rec) {
     rpe = kRecCap;
-    layout_find(S.max_boxes, S.max_triples, sc->top_k, max_hits, n_events, n_hits_total, &L, rpe);
+    layout_find(S.max_boxes, S.max_triples, sched_k(sc), max_hits, n_events, n_hits_total, &L, rpe);
   }
   if (L.total > c->arena_bytes)
     return fail(c, IA_ERR_NOMEM, "scratch too small: need %zu bytes, have %zu", L.total, c->arena_bytes);

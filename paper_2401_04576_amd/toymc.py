@@ -474,3 +474,27 @@ def config_event(config_id, event_index):
         n = int(np.clip(np.floor(np.exp(rng.normal(np.log(120.0), 0.6)) + 0.5), 20, 1000))
         return make_event(rng, n_helix=n_h, sigma=150e-6, noise_frac=f, n_hits=n)
     raise ValueError(f"unknown workload {config_id}")
+
+
+# --------------------------------------------------------------------------
+# search schedules (the keyword arguments of Schedule.make / oracle.make_sched)
+# --------------------------------------------------------------------------
+# the literal schedule of the configs: 16^5, then 4 levels of the top 32 boxes
+# split 4^5 each
+TOPK_KW = dict(bins=[16] * 5, n_refine=4, top_k=32, split=[4] * 5)
+# the window schedule (Sec. 3.3 re-gridding from all max-vote boxes): level 0
+# the 16^5 grid over the range, level 1 a 16^5 window, then the reference
+# point moves to the hit closest to the recovered circle and four 12^5
+# windows follow; the forward-hit test applies before the move
+WINDOW_LBINS = [[16] * 5, [16] * 5, [12] * 5, [12] * 5, [12] * 5, [12] * 5]
+WINDOW_KW = dict(bins=[16] * 5, n_refine=5, mode=1, forward=True, move_level=1, lbins=WINDOW_LBINS)
+# the recovery tolerances on (d0, phi0, kappa, z0, tanl)
+RECOVERY_TOL = (1e-3, 5e-3, 0.01, 10e-3, 0.02)
+
+
+def recovered(p, truth, tol=RECOVERY_TOL):
+    """p within tol of truth in every parameter (phi0 compared on the circle)."""
+    d = np.abs(np.asarray(p, dtype=float) - np.asarray(truth, dtype=float))
+    d[1] = d[1] % (2.0 * np.pi)
+    d[1] = min(d[1], 2.0 * np.pi - d[1])
+    return bool(np.all(d <= np.asarray(tol)))

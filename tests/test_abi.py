@@ -38,11 +38,39 @@ def test_library_exports_every_declared_symbol():
         assert hasattr(L, n)
 
 
-def test_schedule_layout_matches_header():
-    # ia_schedule: ia_box (80) + bins (20) + n_refine, top_k (8) + split (20) + v_min,
-    # n_helix_max (8) + hitfind_scale (8) + prec[8] (32) + fp32_slack (8) = 184
-    assert C.sizeof(ia.Schedule) == 184
-    assert ia.HELIX_DTYPE.itemsize == 96 and ia.ESTIMATE_DTYPE.itemsize == 88
+def _c_layout(tmp_path):
+    """sizeof and field offsets of the ABI structs as the C compiler lays them out"""
+    src = tmp_path / "layout.c"
+    fields = {"ia_schedule": ["range", "bins", "n_refine", "top_k", "split", "v_min", "n_helix_max",
+                              "hitfind_scale", "prec", "fp32_slack", "mode", "forward", "move_level", "lbins"],
+              "ia_helix": ["p", "err", "ref", "votes", "n_assigned", "n_argmax", "status"],
+              "ia_estimate_t": ["p", "err", "vmax", "n_argmax"]}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "ia.h"', "int main(void) {"]
+    for t, fs in fields.items():
+        lines.append(f'  printf("{t} sizeof %zu\\n", sizeof({t}));')
+        for f in fs:
+            lines.append(f'  printf("{t} {f} %zu\\n", offsetof({t}, {f}));')
+    lines.append("  return 0;\n}")
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(src)])
+    out = {}
+    for line in subprocess.check_output([str(exe)], text=True).splitlines():
+        t, f, v = line.split()
+        out[(t, f)] = int(v)
+    return out
+
+
+def test_struct_layouts_match_header(tmp_path):
+    """ctypes / numpy layouts of the binding equal the C compiler's for ia.h"""
+    lay = _c_layout(tmp_path)
+    assert C.sizeof(ia.Schedule) == lay[("ia_schedule", "sizeof")]
+    for name, _ in ia.Schedule._fields_:
+        assert getattr(ia.Schedule, name).offset == lay[("ia_schedule", name)], name
+    for dt, t in ((ia.HELIX_DTYPE, "ia_helix"), (ia.ESTIMATE_DTYPE, "ia_estimate_t")):
+        assert dt.itemsize == lay[(t, "sizeof")]
+        for name in dt.names:
+            assert dt.fields[name][1] == lay[(t, name)], (t, name)
 
 
 def test_host_side_errors_without_device():
