@@ -101,18 +101,21 @@ enum { IA_SCHED_TOPK = 0, IA_SCHED_WINDOW = 1 };
  *
  * IA_SCHED_WINDOW (the paper's iterative re-gridding, Sec. 3.3 and Table 1):
  * every level is one regular grid over a window box, level 0 the grid `bins`
- * over `range`, level l >= 1 the grid lbins[l] over a window built from ALL
- * max-vote boxes of level l - 1 (never truncated): their union widened by one
- * of that level's bins on each side (kappa and tanl clipped to `range`, d0
- * and z0 too while the reference point is the origin; a phi0 window of a
- * full turn or more becomes range's).  After level move_level the reference
- * point of the parametrisation moves to the measurement point closest to the
- * recovered circle (Sec. 3.3, second and third steps): the hit point (wire at
- * z = 0) of the active hit with the smallest |G| of Eq. ApoVote's kappa-scaled
- * form at the estimate, the lowest index on ties; the next window is then
- * the hull of the max-vote boxes' 32 corners taken to the new reference
- * point, widened so that it spans all but one bin at each end of the next
- * grid (kappa and tanl clipped).  top_k and split are not used.
+ * over `range`, level l >= 1 the grid lbins[l] over a window built from the
+ * boxes of level l - 1 within wdrop votes of its maximum (all of them, never
+ * truncated; the estimate uses the max-vote boxes alone): their union (phi0
+ * relative to the first max-vote box's centre) widened by one of that
+ * level's bins on each side (kappa and tanl clipped to `range`, d0 and z0 too
+ * while the reference point is the origin; a phi0 window of a full turn or
+ * more becomes range's).  After level move_level the reference point of the
+ * parametrisation moves to the measurement point closest to the recovered
+ * circle (Sec. 3.3, second and third steps): the hit point (wire at z = 0) of
+ * the active hit with the smallest |G| of Eq. ApoVote's kappa-scaled form at
+ * the estimate, the lowest index on ties; the next window is then the hull of
+ * those boxes' 32 corners taken to the new reference point (phi0 within half
+ * a turn of the first max-vote box's first corner), widened so that it spans
+ * all but one bin at each end of the next grid (kappa and tanl clipped).
+ * top_k and split are not used.
  *
  * forward: a hit votes for a box only if it lies ahead of the point of
  * closest approach (along the direction of travel) for some phi0 of the box
@@ -139,6 +142,14 @@ typedef struct {
   int32_t forward;        /* 1: forward-hit test (see above), 0: off */
   int32_t move_level;     /* IA_SCHED_WINDOW: the reference point moves after this
                            * level (-1: never; else in [0, n_refine)) */
+  int32_t wdrop;          /* IA_SCHED_WINDOW: windows cover the boxes with votes
+                           * >= max - wdrop (>= 0) */
+  int32_t hitsel;         /* IA_SCHED_WINDOW, 1: per-level hit selection (Sec. 3.3):
+                           * a level votes only with the hits voting for the
+                           * previous level's hit-finding box (estimate +-
+                           * hitfind_scale x error, in its frame, with its
+                           * forward test); every hit of the pass stays a
+                           * candidate for each selection and for hit finding */
   int32_t lbins[IA_MAX_LEVELS][5];  /* IA_SCHED_WINDOW: grid of level l >= 1 */
 } ia_schedule;
 

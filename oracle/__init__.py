@@ -29,7 +29,8 @@ SCHED_DTYPE = np.dtype([("range", BOX_DTYPE), ("bins", "i4", (5,)), ("n_refine",
                         ("top_k", "i4"), ("split", "i4", (5,)), ("v_min", "i4"),
                         ("n_helix_max", "i4"), ("hitfind_scale", "f8"), ("prec", "i4", (8,)),
                         ("fp32_slack", "f8"), ("mode", "i4"), ("forward", "i4"),
-                        ("move_level", "i4"), ("lbins", "i4", (8, 5))], align=True)
+                        ("move_level", "i4"), ("wdrop", "i4"), ("hitsel", "i4"),
+                        ("lbins", "i4", (8, 5))], align=True)
 FP64, FP32 = 0, 1
 TOPK, WINDOW = 0, 1
 HELIX_DTYPE = np.dtype([("p", "f8", (5,)), ("err", "f8", (5,)), ("ref", "f8", (2,)), ("votes", "i4"),
@@ -313,13 +314,15 @@ def estimate_ex(parents, split, votes, vmax):
 
 def make_sched(lo, hi, bins, n_refine=4, top_k=32, split=(4, 4, 4, 4, 4), v_min=10,
                n_helix_max=1, hitfind_scale=5.0, prec=None, fp32_slack=1e-6, mode=TOPK, forward=False,
-               move_level=-1, lbins=None):
+               move_level=-1, lbins=None, wdrop=0, hitsel=False):
     """prec: per-level FP64 / FP32 list (default all FP64).  mode WINDOW: level l >= 1 is
     a grid of lbins[l] over its window; the reference point moves after move_level."""
     s = np.zeros((), dtype=SCHED_DTYPE)
     s["mode"] = mode
     s["forward"] = int(bool(forward))
     s["move_level"] = move_level
+    s["wdrop"] = wdrop
+    s["hitsel"] = int(bool(hitsel))
     if lbins is not None:
         for l, b in enumerate(lbins):
             s["lbins"][l] = b

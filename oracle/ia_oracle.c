@@ -741,20 +741,28 @@ int32_t or_estimate_ex(const or_box *parents, int32_t n_parents, const int32_t s
  * and splits each by `split`.
  *
  * OR_WINDOW: each level is one regular grid over a window box.  Level 0's
- * window is the search range.  After a level, the estimate and the union of
- * ALL its max-vote boxes (never truncated: Sec. 3.3 computes the values and
- * errors from every selected max cell) give the next window: the union
- * widened by one of the level's bins on each side (kappa and tanl clipped
- * to the range; d0 and z0 too while the reference point is the origin; a
- * phi0 window of a full turn or more becomes the range's).  After level
+ * window is the search range.  After a level, the estimate comes from ALL
+ * its max-vote boxes (never truncated: Sec. 3.3 computes the values and
+ * errors from every selected max cell), and the next window from every box
+ * within wdrop votes of the maximum (noise hits can lift a few boxes by a
+ * vote or two above the track's own): the union of those boxes (phi0
+ * relative to the first max-vote box's centre, as in the estimate) widened
+ * by one of the level's bins on each side (kappa and tanl clipped to the
+ * range; d0 and z0 too while the reference point is the origin; a phi0
+ * window of a full turn or more becomes the range's).  After level
  * move_level the reference point moves, as the paper does for its second and
  * third steps, to the measurement point closest to the recovered circle
  * (the active hit point with the smallest |G| at the estimate, the lowest
- * index on ties): every max-vote box's 32 corners are taken to the new
- * reference point (or_frame_shift) and the next window is their hull
- * widened so that it spans all but one bin at each end of the next grid
- * (kappa and tanl clipped).  The forward-hit test applies at the levels up to
- * move_level (all levels when the reference never moves).  The helix's p is
+ * index on ties): the 32 corners of those boxes are taken to the new
+ * reference point (or_frame_shift; phi0 within half a turn of the first
+ * max-vote box's first corner) and the next window is their hull widened so
+ * that it spans all but one bin at each end of the next grid (kappa and tanl
+ * clipped).  With hitsel, as the paper does after each iteration, a level
+ * votes only with the hits that vote for the previous level's hit-finding
+ * box (estimate +- hitfind_scale x error, in that level's frame); every hit
+ * of the pass stays a candidate at each selection and at the hit finding.
+ * The forward-hit test applies at the levels up to move_level (all levels
+ * when the reference never moves), to their votes and selections.  The helix's p is
  * the last estimate taken back to the origin; its err and the hit finding
  * stay in the last level's frame.
  * Parity of the driver: the per-level truth checks and the recovery rates
@@ -862,13 +870,16 @@ static int32_t find_window(const or_hit *hits, int32_t n_hits, const or_sched *s
   for (int32_t l = 1; l <= sc->n_refine; l++)
     if (prod5(sc->lbins[l]) > nbmax) nbmax = prod5(sc->lbins[l]);
   uint16_t *votes = (uint16_t *)malloc((size_t)nbmax * sizeof(uint16_t));
+  uint8_t *sel = (uint8_t *)calloc((size_t)(n_hits > 0 ? n_hits : 1), 1);
   int32_t nh = 0;
   for (int32_t pass = 0; pass < sc->n_helix_max && nh < max_out; pass++) {
-    /* every pass starts about the origin */
+    /* every pass starts about the origin, with every active hit voting */
     double ref[2] = {0.0, 0.0};
     int32_t moved = 0;
-    for (int32_t i = 0; i < n_hits; i++)
+    for (int32_t i = 0; i < n_hits; i++) {
       if (act[i]) or_prep_hit_ref(&hits[i], 0.0, 0.0, &pr[i]);
+      sel[i] = act[i];
+    }
     or_box grid = sc->range;
     int32_t m[5];
     memcpy(m, sc->bins, sizeof m);
@@ -877,7 +888,7 @@ static int32_t find_window(const or_hit *hits, int32_t n_hits, const or_sched *s
     double p[5], err[5], ulo[5], uhi[5];
     for (int32_t lev = 0; lev <= sc->n_refine; lev++) {
       int32_t fwd = sc->forward && (sc->move_level < 0 || lev <= sc->move_level);
-      vote_prepped(pr, act, n_hits, &grid, 1, m, sc->prec[lev], sc->fp32_slack, fwd, votes, n_threads);
+      vote_prepped(pr, sel, n_hits, &grid, 1, m, sc->prec[lev], sc->fp32_slack, fwd, votes, n_threads);
       int64_t nb = prod5(m), first;
       vmax = level_max(votes, nb, &first);
       count = or_estimate_ex(&grid, 1, m, votes, vmax, p, err, ulo, uhi);
@@ -894,6 +905,18 @@ static int32_t find_window(const or_hit *hits, int32_t n_hits, const or_sched *s
       if (lev == 0 && vmax < sc->v_min) { stop = 1; break; }
       if (lev == sc->n_refine) break;
       const int32_t *mn = sc->lbins[lev + 1];
+      const uint16_t vlo = vmax > sc->wdrop ? (uint16_t)(vmax - sc->wdrop) : 0;
+      if (sc->hitsel) {
+        /* the hits voting for this level's hit-finding box vote at the next */
+        or_box E;
+        for (int j = 0; j < 5; j++) {
+          double w = sc->hitfind_scale * err[j];
+          E.lo[j] = p[j] - w;
+          E.hi[j] = p[j] + w;
+        }
+        for (int32_t i = 0; i < n_hits; i++)
+          sel[i] = (uint8_t)(act[i] && (!fwd || or_forward(&pr[i], &E)) && or_pair_vote(&pr[i], &E, NULL));
+      }
       or_box nx;
       int32_t did_move = 0;
       if (lev == sc->move_level) {
@@ -908,21 +931,23 @@ static int32_t find_window(const or_hit *hits, int32_t n_hits, const or_sched *s
         if (ib >= 0) {
           double dx = pr[ib].px, dy = pr[ib].py;
           double hl[5], hh[5], cref = 0.0;
-          int32_t seen = 0;
+          for (int j = 0; j < 5; j++) { hl[j] = INFINITY; hh[j] = -INFINITY; }
+          {
+            or_box fb;
+            double x[5], q[5];
+            or_box_child(&grid, m, first, &fb);
+            box_corner(&fb, 0, x);
+            or_frame_shift(x, dx, dy, q);
+            cref = q[1];
+          }
           for (int64_t b = 0; b < nb; b++) {
-            if (votes[b] != vmax) continue;
+            if (votes[b] < vlo) continue;
             or_box box;
             or_box_child(&grid, m, b, &box);
             for (int c = 0; c < 32; c++) {
               double x[5], q[5];
               box_corner(&box, c, x);
               or_frame_shift(x, dx, dy, q);
-              if (!seen) {
-                cref = q[1];
-                for (int j = 0; j < 5; j++) { hl[j] = q[j]; hh[j] = q[j]; }
-                seen = 1;
-                continue;
-              }
               double dv = q[1] - cref;
               if (dv > PI_RN) q[1] -= TWO_PI_RN;
               else if (dv <= -PI_RN) q[1] += TWO_PI_RN;
@@ -943,10 +968,34 @@ static int32_t find_window(const or_hit *hits, int32_t n_hits, const or_sched *s
         }
       }
       if (!did_move) {
+        /* union of the boxes within wdrop of the maximum (phi0 relative to
+         * the first max-vote box's centre) */
+        double c0, wl[5], wh[5];
+        or_box fb;
+        or_box_child(&grid, m, first, &fb);
+        c0 = 0.5 * (fb.lo[1] + fb.hi[1]);
+        for (int j = 0; j < 5; j++) { wl[j] = INFINITY; wh[j] = -INFINITY; }
+        for (int64_t b = 0; b < nb; b++) {
+          if (votes[b] < vlo) continue;
+          or_box box;
+          or_box_child(&grid, m, b, &box);
+          for (int j = 0; j < 5; j++) {
+            double lo = box.lo[j], hi = box.hi[j];
+            if (j == 1) {
+              double dv = 0.5 * (lo + hi) - c0, shift = 0.0;
+              if (dv > PI_RN) shift = -TWO_PI_RN;
+              else if (dv <= -PI_RN) shift = TWO_PI_RN;
+              lo = lo + shift;
+              hi = hi + shift;
+            }
+            wl[j] = fmin(wl[j], lo);
+            wh[j] = fmax(wh[j], hi);
+          }
+        }
         for (int j = 0; j < 5; j++) {
           double w = (grid.hi[j] - grid.lo[j]) / (double)m[j];
-          nx.lo[j] = ulo[j] - w;
-          nx.hi[j] = uhi[j] + w;
+          nx.lo[j] = wl[j] - w;
+          nx.hi[j] = wh[j] + w;
         }
         if (!moved) {
           for (int j = 0; j < 5; j += 3) {
@@ -987,6 +1036,7 @@ static int32_t find_window(const or_hit *hits, int32_t n_hits, const or_sched *s
     if (na == 0) break;
   }
   free(votes);
+  free(sel);
   return nh;
 }
 

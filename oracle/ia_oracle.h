@@ -58,6 +58,10 @@ typedef struct {
                                              origin's frame */
   int32_t move_level;                     /* OR_WINDOW: the reference point moves after
                                              this level (-1: never) */
+  int32_t wdrop;                          /* OR_WINDOW: the next window covers the boxes
+                                             with votes >= max - wdrop */
+  int32_t hitsel;                         /* OR_WINDOW: a level votes with the hits that
+                                             voted for the previous level's hit-finding box */
   int32_t lbins[OR_MAX_LEVELS][5];        /* OR_WINDOW: grid of level l >= 1 over its window */
 } or_sched;
 

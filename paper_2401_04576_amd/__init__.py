@@ -47,18 +47,21 @@ class Schedule(C.Structure):
                 ("split", C.c_int32 * 5), ("v_min", C.c_int32), ("n_helix_max", C.c_int32),
                 ("hitfind_scale", C.c_double), ("prec", C.c_int32 * MAX_LEVELS),
                 ("fp32_slack", C.c_double), ("mode", C.c_int32), ("forward", C.c_int32),
-                ("move_level", C.c_int32), ("lbins", (C.c_int32 * 5) * MAX_LEVELS)]
+                ("move_level", C.c_int32), ("wdrop", C.c_int32), ("hitsel", C.c_int32),
+                ("lbins", (C.c_int32 * 5) * MAX_LEVELS)]
 
     @classmethod
     def make(cls, lo, hi, bins, n_refine=4, top_k=32, split=(4, 4, 4, 4, 4), v_min=10, n_helix_max=1,
              hitfind_scale=5.0, prec=None, fp32_slack=1e-6, mode=SCHED_TOPK, forward=False, move_level=-1,
-             lbins=None):
+             lbins=None, wdrop=0, hitsel=False):
         """mode SCHED_WINDOW: level l >= 1 is the grid lbins[l] over a window built from all max-vote
         boxes of level l - 1; the reference point moves after move_level (see include/ia.h)."""
         s = cls()
         s.mode = int(mode)
         s.forward = int(bool(forward))
         s.move_level = int(move_level)
+        s.wdrop = int(wdrop)
+        s.hitsel = int(bool(hitsel))
         if lbins is not None:
             for l, b in enumerate(lbins):
                 for j in range(5):

@@ -29,9 +29,14 @@ constexpr int kMaxTopK = 4096;  // selection size limit
 struct HitRec {                 // prepared hit, 112 bytes
   double px, py, tant, sphis, cphis, r, phip, r2lo, r2hi, d, band;
   double sphp, cphp;            // sin and cos of phip (sin_p, cos_p)
-  int32_t use;                  // valid and active
+  int32_t use;                  // 0: not searched (malformed or assigned); bit 0: active in the
+                                // pass (a hit-finding candidate); 1: also votes at this level,
+                                // 3: not selected to vote at this level
   int32_t axial;
 };
+
+// the hit votes at the current level
+IA_HD bool votes_now(const HitRec& h) { return h.use == 1; }
 
 struct BoxD { double lo[5], hi[5]; };
 
@@ -1090,7 +1095,7 @@ template <bool F32>
 IA_HD bool parent_may_vote(const BoxD& P, const uint32_t m[5], const HitRec& h, float slack32,
                            ParentE* pe = nullptr) {
   if (pe) pe->ok[0] = pe->ok[1] = 0;
-  if (!h.use) return false;
+  if (!votes_now(h)) return false;
   FrameIv f;
   if (!parent_frame(P, m, &f)) return true;
   Frame fg;                                     // the parent box's ranges for G
@@ -1316,7 +1321,7 @@ __global__ void __launch_bounds__(kWG, 4) k_classify(const HitRec* __restrict__ 
   for (int32_t h = static_cast<int32_t>(blockIdx.z) * (kWG / 64) + wave; h < n_hits; h += h_step) {
     const HitRec hr = hits[h];
     uint8_t fl = 0;
-    if (hr.use && (!pf || pf[h]) && (!vw.fwd || forward_ok(f.Fi, hr))) {
+    if (votes_now(hr) && (!pf || pf[h]) && (!vw.fwd || forward_ok(f.Fi, hr))) {
       const int c = pair_stage1<F32>(f, gt, hr, Zr, Lr, filter, slack32, COUNT ? cw : nullptr, pr ? &pr[h] : nullptr);
       fl = c >= 0 ? static_cast<uint8_t>(c) : defer_flag(-c);
     }
@@ -1488,7 +1493,8 @@ __global__ void __launch_bounds__(kWG) k_threshold(const int32_t* __restrict__ t
                                                    int32_t prune, int32_t ties, int32_t bx, EventState* __restrict__ ev,
                                                    int32_t* __restrict__ live_list, int32_t* __restrict__ wg_max,
                                                    int32_t* __restrict__ live_tri, int32_t* __restrict__ rec_off,
-                                                   int32_t* __restrict__ rec_fill, int64_t rec_cap) {
+                                                   int32_t* __restrict__ rec_fill, int64_t rec_cap,
+                                                   int32_t drop) {
   const int e = blockIdx.y;
   if (ev[e].done) return;
   const int32_t n_bins = vw.count(e) + 1;
@@ -1517,7 +1523,8 @@ __global__ void __launch_bounds__(kWG) k_threshold(const int32_t* __restrict__ t
         cum += static_cast<int64_t>(hh[v]) * sh.m34;
         if (cum >= k_eff) { T = v; break; }
       }
-      s_T = T;
+      // drop: boxes down to `drop` votes below the maximum are needed exactly
+      s_T = max(T - drop, 0);
     }
     __syncthreads();
     if (n_bins > kHistLds)
@@ -2670,8 +2677,9 @@ __global__ void __launch_bounds__(kWG) k_est_final(const double* __restrict__ pa
 // box per event.  The kernels below build the next window from all max-vote
 // boxes of a level and move the reference point of the parametrisation.
 
-// Re-prepares every hit of an event about its reference point (reset: about
-// the origin, and the event's frame is reset), keeping each hit's use flag.
+// Re-prepares every hit of an event about its reference point, keeping each
+// hit's use flag (reset: about the origin, the event's frame is reset and
+// every active hit votes again).
 __global__ void __launch_bounds__(kWG) k_reframe(const double* __restrict__ hits, EvView vw,
                                                  HitRec* __restrict__ out, EventState* __restrict__ ev,
                                                  int32_t reset) {
@@ -2683,7 +2691,9 @@ __global__ void __launch_bounds__(kWG) k_reframe(const double* __restrict__ hits
   for (int32_t h = blockIdx.x * blockDim.x + threadIdx.x; h < n_hits; h += stride) {
     HitRec r;
     bool bad;
-    prep_one(hits + 8 * static_cast<int64_t>(beg + h), out[beg + h].use != 0, &r, &bad, xr, yr);
+    const int32_t use = out[beg + h].use;
+    prep_one(hits + 8 * static_cast<int64_t>(beg + h), use != 0, &r, &bad, xr, yr);
+    r.use = reset ? (use & 1) : use;     // a pass starts with every active hit voting
     out[beg + h] = r;
   }
   if (reset && blockIdx.x == 0 && threadIdx.x == 0) {
@@ -2738,26 +2748,56 @@ __global__ void __launch_bounds__(kWG) k_closest(const HitRec* __restrict__ hits
   }
 }
 
+// Per-level hit selection (Sec. 3.3): after a level, every active hit of the
+// pass is tested against the level's hit-finding box (estimate +- scale x
+// error, in the level's frame, with the level's forward test); the hits that
+// vote for it vote at the next level, the others (use = 3) sit it out.
+__global__ void __launch_bounds__(kWG) k_hit_select(HitRec* __restrict__ hits, EvView vw,
+                                                    const EventState* __restrict__ ev, double scale,
+                                                    int32_t fwd) {
+  const int e = blockIdx.y;
+  if (ev[e].done) return;
+  hits += vw.beg(e);
+  const int32_t n_hits = vw.count(e);
+  BoxD E;
+  for (int j = 0; j < 5; ++j) {
+    const double w = scale * ev[e].err[j];
+    E.lo[j] = ev[e].p[j] - w;
+    E.hi[j] = ev[e].p[j] + w;
+  }
+  const int32_t stride = gridDim.x * blockDim.x;
+  for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n_hits; i += stride) {
+    HitRec& h = hits[i];
+    if (!(h.use & 1)) continue;
+    h.use = pair_vote_box(E, h, fwd != 0) ? 1 : 3;
+  }
+}
+
 // corner c of a box (bit j: upper end of dimension j)
 IA_HD void box_corner(const BoxD& b, int c, double* x) {
   for (int j = 0; j < 5; ++j) x[j] = ((c >> j) & 1) ? b.hi[j] : b.lo[j];
 }
 
-// Hull of the max-vote boxes' corners taken to the new reference point, in
-// aligned 256-box chunks as k_est_partial (minima at q = 5..9, maxima at
-// q = 10..14 of each chunk's record); phi0 is unwrapped into half a turn of
-// the first max-vote box's first corner.  Minima and maxima do not depend on
-// the order of reduction.
-__global__ void __launch_bounds__(kWG) k_hull_partial(const BoxD* __restrict__ parents, Shape sh,
-                                                      const uint16_t* __restrict__ votes,
-                                                      const BoxD* __restrict__ first_box,
-                                                      const uint16_t* __restrict__ first_votes,
-                                                      double* __restrict__ part, EvView vw,
-                                                      const EventState* __restrict__ ev,
-                                                      const int32_t* __restrict__ wg_max, int32_t bx,
-                                                      uint32_t n_part, uint32_t per) {
+// Extent of the boxes within `drop` votes of the maximum, in aligned 256-box
+// chunks as k_est_partial (minima at q = 5..9, maxima at q = 10..14 of each
+// chunk's record).  When the event's reference point moves (move_now and
+// `moving`): the hull of their 32 corners taken to the new reference point,
+// phi0 unwrapped into half a turn of the first max-vote box's first corner;
+// otherwise the union of the boxes, phi0 shifted by a turn where the box
+// centre is more than half a turn from the first max-vote box's centre.
+// Minima and maxima do not depend on the order of reduction.
+__global__ void __launch_bounds__(kWG) k_window_partial(const BoxD* __restrict__ parents, Shape sh,
+                                                        const uint16_t* __restrict__ votes,
+                                                        const BoxD* __restrict__ first_box,
+                                                        const uint16_t* __restrict__ first_votes,
+                                                        double* __restrict__ part, EvView vw,
+                                                        const EventState* __restrict__ ev,
+                                                        const int32_t* __restrict__ wg_max, int32_t bx,
+                                                        uint32_t n_part, uint32_t per, int32_t drop,
+                                                        int32_t move_now) {
   const int e = blockIdx.y;
-  if (ev[e].done || !ev[e].moving) return;
+  if (ev[e].done) return;
+  const bool mv = move_now && ev[e].moving;
   parents += e * vw.par_stride;
   votes += int64_t(e) * sh.n_boxes;
   if (wg_max) wg_max += int64_t(e) * vw.wg_stride;
@@ -2765,10 +2805,10 @@ __global__ void __launch_bounds__(kWG) k_hull_partial(const BoxD* __restrict__ p
   first_votes += int64_t(e) * vw.k;
   part += int64_t(e) * vw.part_stride;
   __shared__ double s[kEstQ][kWG];
-  const int32_t vmax = first_votes[0];
+  const int32_t vlo = max(static_cast<int32_t>(first_votes[0]) - drop, 0);
   const double dx = ev[e].shift[0], dy = ev[e].shift[1];
-  double cref;
-  {
+  double cref = 0.5 * (first_box->lo[1] + first_box->hi[1]);
+  if (mv) {
     double x[5], q[5];
     box_corner(*first_box, 0, x);
     frame_shift(x, dx, dy, q);
@@ -2780,16 +2820,33 @@ __global__ void __launch_bounds__(kWG) k_hull_partial(const BoxD* __restrict__ p
     double v[kEstQ];
     for (int q = 0; q < 5; ++q) { v[q] = 0.0; v[5 + q] = INFINITY; v[10 + q] = -INFINITY; }
     v[15] = 0.0;
-    const bool at_max =
-        i < sh.n_boxes && (!wg_max || wg_max[i / static_cast<uint32_t>(bx)] >= vmax) && votes[i] == vmax;
-    if (!__syncthreads_or(at_max ? 1 : 0)) {
+    const bool in_set =
+        i < sh.n_boxes && (!wg_max || wg_max[i / static_cast<uint32_t>(bx)] >= vlo) && votes[i] >= vlo;
+    if (!__syncthreads_or(in_set ? 1 : 0)) {
       if (threadIdx.x < kEstQ) {
         const int q = static_cast<int>(threadIdx.x);
         part[ch * kEstQ + q] = (q >= 5 && q < 10) ? INFINITY : ((q >= 10 && q < 15) ? -INFINITY : 0.0);
       }
       continue;
     }
-    if (at_max) {
+    if (in_set && !mv) {
+      BoxD box;
+      level_box(parents, sh, i, &box);
+      for (int j = 0; j < 5; ++j) {
+        double lo = box.lo[j], hi = box.hi[j];
+        if (j == 1) {
+          const double dv = 0.5 * (lo + hi) - cref;
+          double shift = 0.0;
+          if (dv > kPi) shift = -kTwoPi;
+          else if (dv <= -kPi) shift = kTwoPi;
+          lo = lo + shift;
+          hi = hi + shift;
+        }
+        v[5 + j] = lo;
+        v[10 + j] = hi;
+      }
+    }
+    if (in_set && mv) {
       BoxD box;
       level_box(parents, sh, i, &box);
       for (int c = 0; c < 32; ++c) {
@@ -2815,14 +2872,13 @@ __global__ void __launch_bounds__(kWG) k_hull_partial(const BoxD* __restrict__ p
 
 struct Bins5 { int32_t m[5]; };
 
-// Next window of an event from its level's max-vote boxes (one workgroup per
+// Next window of an event from k_window_partial's records (one workgroup per
 // event).  After a move (move_now and the event is moving): the hull of the
-// corners reduced from k_hull_partial's records, widened so that it spans all
-// but one bin at each end of the next grid; the reference point advances by
-// the shift.  Otherwise: the union of the max-vote boxes widened by one of
-// the level's bins on each side, d0 and z0 clipped to the range while the
-// frame is the origin's.  Then kappa and tanl are clipped to the range, and a
-// phi0 window of a full turn or more becomes the range's.
+// corners, widened so that it spans all but one bin at each end of the next
+// grid; the reference point advances by the shift.  Otherwise: the union
+// widened by one of the level's bins on each side, d0 and z0 clipped to the
+// range while the frame is the origin's.  Then kappa and tanl are clipped to
+// the range, and a phi0 window of a full turn or more becomes the range's.
 __global__ void __launch_bounds__(kWG) k_window(const double* __restrict__ part, int32_t n_part,
                                                 const BoxD* __restrict__ parents, Shape sh,
                                                 BoxD* __restrict__ win, EventState* __restrict__ ev, EvView vw,
@@ -2833,7 +2889,7 @@ __global__ void __launch_bounds__(kWG) k_window(const double* __restrict__ part,
   part += int64_t(e) * vw.part_stride;
   const bool mv = move_now && es.moving;
   __shared__ double slo[5][kWG], shi[5][kWG];
-  if (mv) {
+  {
     double lo[5], hi[5];
     for (int j = 0; j < 5; ++j) { lo[j] = INFINITY; hi[j] = -INFINITY; }
     for (int32_t c = threadIdx.x; c < n_part; c += kWG)
@@ -2868,8 +2924,8 @@ __global__ void __launch_bounds__(kWG) k_window(const double* __restrict__ part,
   } else {
     for (int j = 0; j < 5; ++j) {
       const double w = (G.hi[j] - G.lo[j]) / static_cast<double>(sh.m[j]);
-      nx.lo[j] = es.ulo[j] - w;
-      nx.hi[j] = es.uhi[j] + w;
+      nx.lo[j] = slo[j][0] - w;
+      nx.hi[j] = shi[j][0] + w;
     }
     if (!es.moved)
       for (int j = 0; j < 5; j += 3) {

@@ -506,6 +506,8 @@ ia_status check_sched(ia_ctx* c, const ia_schedule* sc) {
   if (sc->mode == IA_SCHED_WINDOW) {
     if (sc->move_level < -1 || sc->move_level >= sc->n_refine)
       return fail(c, IA_ERR_INVALID, "move_level %d outside [-1, n_refine)", sc->move_level);
+    if (sc->wdrop < 0 || sc->wdrop > 65535) return fail(c, IA_ERR_INVALID, "wdrop %d", sc->wdrop);
+    if (sc->hitsel != 0 && sc->hitsel != 1) return fail(c, IA_ERR_INVALID, "hitsel %d", sc->hitsel);
     for (int l = 1; l <= sc->n_refine; ++l)
       for (int j = 0; j < 5; ++j)
         if (sc->lbins[l][j] < 1) return fail(c, IA_ERR_INVALID, "lbins[%d][%d] = %d < 1", l, j, sc->lbins[l][j]);
@@ -548,7 +550,7 @@ ia_status run_window(ia_ctx* c, const double* hits, ia::EvView vw, int32_t E, in
   const int32_t max_per_event = vw.max_out;
   for (int32_t pass = 0; pass < std::min(sc->n_helix_max, max_per_event); ++pass) {
     // every pass starts about the origin
-    if (pass > 0 && sc->move_level >= 0)
+    if (pass > 0 && (sc->move_level >= 0 || sc->hitsel))
       hipLaunchKernelGGL(ia::k_reframe, dim3(pg, E), dim3(ia::kWG), 0, s, hits, vw, recs, ev, 1);
     const BoxD* par = range;
     Shape sh = S.sh0;
@@ -574,7 +576,8 @@ ia_status run_window(ia_ctx* c, const double* hits, ia::EvView vw, int32_t E, in
       }
       const int32_t vt = vote_tile(c, sh.n_boxes);
       hipLaunchKernelGGL(ia::k_threshold, dim3(1, E), dim3(ia::kWG), 0, s, tlb, tn2, lbh, vw, sh, 1, c->prune, 0,
-                         vt, ev, live, wg_max, rin.live_tri, rin.rec_off, rin.rec_fill, L.rec_stride);
+                         vt, ev, live, wg_max, rin.live_tri, rin.rec_off, rin.rec_fill, L.rec_stride,
+                         lev < sc->n_refine ? sc->wdrop : 0);
       launch_stage(recs, vw, E, par, sh, flags, rin, ev, s, f32, slack32);
       const VoteIn in{flags, tlb, tn2, live, 1};
       ia_status st = launch_vote_rec(c, vw, E, par, sh, votes, hist, ev, in, rin, wg_max, s, f32);
@@ -604,12 +607,13 @@ ia_status run_window(ia_ctx* c, const double* hits, ia::EvView vw, int32_t E, in
                          static_cast<ia::EstimateOut*>(nullptr), ev, static_cast<HitRec*>(nullptr), vw, 0.0,
                          static_cast<int32_t*>(nullptr), static_cast<ia::HelixOut*>(nullptr),
                          static_cast<int32_t*>(nullptr), 0);
+      if (sc->hitsel)
+        hipLaunchKernelGGL(ia::k_hit_select, dim3(pg, E), dim3(ia::kWG), 0, s, recs, vw, ev, sc->hitfind_scale,
+                           vw.fwd);
       const bool mv = lev == sc->move_level;
-      if (mv) {
-        hipLaunchKernelGGL(ia::k_closest, dim3(1, E), dim3(ia::kWG), 0, s, recs, vw, ev);
-        hipLaunchKernelGGL(ia::k_hull_partial, gpart, dim3(ia::kWG), 0, s, par, sh, votes, sel, sel_v, part, vw, ev,
-                           wg_max, bx, static_cast<uint32_t>(n_part), eper);
-      }
+      if (mv) hipLaunchKernelGGL(ia::k_closest, dim3(1, E), dim3(ia::kWG), 0, s, recs, vw, ev);
+      hipLaunchKernelGGL(ia::k_window_partial, gpart, dim3(ia::kWG), 0, s, par, sh, votes, sel, sel_v, part, vw, ev,
+                         wg_max, bx, static_cast<uint32_t>(n_part), eper, sc->wdrop, mv ? 1 : 0);
       ia::Bins5 nb;
       for (int j = 0; j < 5; ++j) nb.m[j] = sc->lbins[lev + 1][j];
       hipLaunchKernelGGL(ia::k_window, dim3(1, E), dim3(ia::kWG), 0, s, part, n_part, par, sh, win, ev, vw, rb, nb,
@@ -734,7 +738,7 @@ ia_status run_chunk(ia_ctx* c, const double* hits_chunk, const int32_t* h_off_ch
       const int32_t k_lev = last ? 1 : K;
       const int32_t ties = last ? 0 : 1;
       hipLaunchKernelGGL(ia::k_threshold, dim3(1, E), dim3(ia::kWG), 0, s, tlb, tn2, lbh, vw, sh, k_lev, c->prune,
-                         ties, vt, ev, live, wg_max, rin.live_tri, rin.rec_off, rin.rec_fill, L.rec_stride);
+                         ties, vt, ev, live, wg_max, rin.live_tri, rin.rec_off, rin.rec_fill, L.rec_stride, 0);
       launch_stage(recs, vw, E, par, sh, flags, rin, ev, s, f32, slack32);
       const VoteIn in{flags, tlb, tn2, live, 1};
       ia_status st = launch_vote_rec(c, vw, E, par, sh, votes, hist, ev, in, rin, wg_max, s, f32);

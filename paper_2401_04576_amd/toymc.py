@@ -456,11 +456,18 @@ GRID_RANGE_LO = (-5e-3, 0.0, -0.6, -5e-2, -0.8)
 GRID_RANGE_HI = (5e-3, 2.0 * np.pi, 0.6, 5e-2, 0.8)
 
 
+# the noiseless multi-helix family (config 4's helix counts, exact drifts,
+# one hit per layer and helix, no noise hits)
+NOISELESS_MULTI = 40
+
+
 def config_event(config_id, event_index):
-    """Event `event_index` of workload `config_id` (1..5)."""
+    """Event `event_index` of workload `config_id` (1..5, or NOISELESS_MULTI)."""
     rng = rng_for(config_id, event_index)
     if config_id in (1, 3):
         return make_event(rng, n_helix=1, sigma=0.0, noise_frac=0.0)
+    if config_id == NOISELESS_MULTI:
+        return make_event(rng, n_helix=int(rng.integers(1, 6)), sigma=0.0, noise_frac=0.0)
     if config_id == 2:
         return make_event(rng, n_helix=1, sigma=150e-6, noise_frac=0.2)
     if config_id == 4:
@@ -484,12 +491,27 @@ def config_event(config_id, event_index):
 TOPK_KW = dict(bins=[16] * 5, n_refine=4, top_k=32, split=[4] * 5)
 # the window schedule (Sec. 3.3 re-gridding from all max-vote boxes): level 0
 # the 16^5 grid over the range, level 1 a 16^5 window, then the reference
-# point moves to the hit closest to the recovered circle and four 12^5
-# windows follow; the forward-hit test applies before the move
-WINDOW_LBINS = [[16] * 5, [16] * 5, [12] * 5, [12] * 5, [12] * 5, [12] * 5]
-WINDOW_KW = dict(bins=[16] * 5, n_refine=5, mode=1, forward=True, move_level=1, lbins=WINDOW_LBINS)
+# point moves to the hit closest to the recovered circle and six 12^5
+# windows follow; the forward-hit test applies before the move, and each
+# level votes with the hits the previous level's hit finding selected
+WINDOW_LBINS = [[16] * 5, [16] * 5] + [[12] * 5] * 6
+WINDOW_KW = dict(bins=[16] * 5, n_refine=7, mode=1, forward=True, move_level=1, lbins=WINDOW_LBINS, hitsel=True)
 # the recovery tolerances on (d0, phi0, kappa, z0, tanl)
 RECOVERY_TOL = (1e-3, 5e-3, 0.01, 10e-3, 0.02)
+
+
+def match_helices(found, truth, tol=RECOVERY_TOL):
+    """For each found helix (rows of p), the index of the first generated
+    helix it recovers, or -1."""
+    out = []
+    for p in found:
+        m = -1
+        for t in range(len(truth)):
+            if recovered(p, truth[t], tol):
+                m = t
+                break
+        out.append(m)
+    return np.array(out, dtype=np.int64)
 
 
 def recovered(p, truth, tol=RECOVERY_TOL):

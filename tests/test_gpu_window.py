@@ -69,12 +69,12 @@ def _kw(**over):
     return kw
 
 
-@pytest.mark.parametrize("cfg", [3, 2])
-def test_window_schedule_matches_oracle(ctx, cfg):
+@pytest.mark.parametrize("cfg,wdrop,hitsel", [(3, 0, 0), (2, 0, 0), (2, 2, 1), (3, 1, 1)])
+def test_window_schedule_matches_oracle(ctx, cfg, wdrop, hitsel):
     """The full window schedule (16^5, 16^5 window, move, four 12^5 windows) on
     two events: helices, errors, reference points and assignments bit-exact."""
     events = [toymc.config_event(cfg, i) for i in (0, 1)]
-    hel, n_out = _compare(ctx, events, _kw(), max_out=1)
+    hel, n_out = _compare(ctx, events, _kw(wdrop=wdrop, hitsel=hitsel), max_out=1)
     if cfg == 3:
         # noiseless: the search recovers the generated helix
         for e, ev in enumerate(events):
@@ -85,7 +85,7 @@ def test_window_multi_helix_full_schedule(ctx):
     """A multi-helix event (greedy passes with hit removal, each pass back in
     the origin's frame) under the full window schedule."""
     events = [toymc.config_event(4, 2)]
-    _compare(ctx, events, _kw(n_helix_max=3), max_out=3)
+    _compare(ctx, events, _kw(n_helix_max=3, wdrop=1, hitsel=1), max_out=3)
 
 
 def test_window_small_grids_batch_edges(ctx):
@@ -98,16 +98,19 @@ def test_window_small_grids_batch_edges(ctx):
     empty = type(one)(hits=one.hits[:0], truth=one.truth, owner=one.owner[:0], layer=one.layer[:0],
                       wire=one.wire[:0], sigma=0.0)
     events = [empty, one_hit, big, empty, toymc.config_event(2, 9), toymc.config_event(4, 5)]
-    kw = _kw(bins=[6] * 5, n_refine=3, lbins=[[6] * 5, [6] * 5, [5] * 5, [5] * 5], n_helix_max=3)
-    _compare(ctx, events, kw, max_out=3)
+    for wdrop, hitsel in ((0, 0), (1, 1)):
+        kw = _kw(bins=[6] * 5, n_refine=3, lbins=[[6] * 5, [6] * 5, [5] * 5, [5] * 5], n_helix_max=3, wdrop=wdrop,
+                 hitsel=hitsel)
+        _compare(ctx, events, kw, max_out=3)
 
 
-@pytest.mark.parametrize("move_level", [-1, 0, 2])
-def test_window_move_levels(ctx, move_level):
+@pytest.mark.parametrize("move_level,wdrop,hitsel", [(-1, 0, 0), (0, 2, 1), (2, 1, 1), (-1, 1, 1)])
+def test_window_move_levels(ctx, move_level, wdrop, hitsel):
     """No move, a move after level 0, a move late: forward-test levels and
     frames follow the schedule."""
     events = [toymc.config_event(2, 3), toymc.config_event(3, 4)]
-    kw = _kw(bins=[8] * 5, n_refine=3, move_level=move_level, lbins=[[8] * 5, [8] * 5, [7] * 5, [7] * 5])
+    kw = _kw(bins=[8] * 5, n_refine=3, move_level=move_level, lbins=[[8] * 5, [8] * 5, [7] * 5, [7] * 5],
+             wdrop=wdrop, hitsel=hitsel)
     _compare(ctx, events, kw, max_out=1)
 
 
@@ -143,3 +146,22 @@ def test_vote_level_frame_matches_oracle(ctx, forward, ref):
         ctx.set_vote_frame(False, (0.0, 0.0))
     want = oracle.vote_level(ev.hits, root, [12] * 5, forward=forward, ref=ref)
     assert np.array_equal(got, want)
+
+
+def test_window_recovery_rates(ctx):
+    """Recovery of the generated helices by the default window schedule on 400
+    noiseless single-helix events (the GPU path equals the oracle bit for bit,
+    so this is the schedule's rate): at least 95 % within the tolerances.
+    Smeared events with noise hits and noiseless multi-helix events are
+    reported, not required."""
+    kw = dict(toymc.WINDOW_KW)
+    sg = ia.Schedule.make(H.LO, H.HI, **kw)
+    events = [toymc.config_event(3, i) for i in range(400)]
+    hel, n_out, _, _ = _run_gpu(ctx, events, sg, 1)
+    rec = sum(toymc.recovered(hel[e, 0]["p"], ev.truth[0]) for e, ev in enumerate(events) if n_out[e] > 0)
+    print(f"noiseless single-helix recovery {rec}/400")
+    assert rec >= 380
+    events = [toymc.config_event(2, i) for i in range(200)]
+    hel, n_out, _, _ = _run_gpu(ctx, events, sg, 1)
+    rec = sum(toymc.recovered(hel[e, 0]["p"], ev.truth[0]) for e, ev in enumerate(events) if n_out[e] > 0)
+    print(f"smeared single-helix recovery (20 % noise hits) {rec}/200")
