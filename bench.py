@@ -246,6 +246,60 @@ def event_evals(n_valid, helices, n_out, shapes, n_helix_max):
     return ev
 
 
+def window_shapes(sched_kw):
+    """(n_boxes, n_triples) per level of the window schedule (one window per level)."""
+    out = [(int(np.prod(sched_kw["bins"])), int(np.prod(sched_kw["bins"][:3])))]
+    for lev in range(1, sched_kw["n_refine"] + 1):
+        b = sched_kw["lbins"][lev]
+        out.append((int(np.prod(b)), int(np.prod(b[:3]))))
+    return out
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline_level0(events, sched_kw, lo, hi, budget_s=20.0):
+    """The oracle timed on the host: the level-0 vote (every box of the 16^5
+    grid against every hit, with the forward-hit test of the schedule) of the
+    first events of the batch, on all threads, and on one thread over the first
+    1/16 of the boxes.  The oracle evaluates every (box, hit) pair on its own,
+    so its rate is in interval evaluations per second."""
+    import oracle
+    nt = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    grid = oracle.make_box(lo, hi)
+    bins = list(sched_kw["bins"])
+    fwd = bool(sched_kw.get("forward", False))
+    pairs, n_done = 0.0, 0
+    t0 = time.perf_counter()
+    for ev in events:
+        oracle.vote_level(ev.hits, grid, bins, n_threads=nt, forward=fwd)
+        pairs += float(np.prod(bins)) * ev.n_hits
+        n_done += 1
+        if time.perf_counter() - t0 > budget_s * 0.75:
+            break
+    dt = time.perf_counter() - t0
+    # one thread: the first 1/16 of the boxes (the slowest index split by 16)
+    sub = oracle.make_box(lo, hi)
+    sub["hi"][0] = lo[0] + (hi[0] - lo[0]) / 16.0
+    b1 = [1] + bins[1:]
+    t1 = time.perf_counter()
+    oracle.vote_level(events[0].hits, sub, b1, n_threads=1, forward=fwd)
+    dt1 = time.perf_counter() - t1
+    p1 = float(np.prod(b1)) * events[0].n_hits
+    return {"value": pairs / dt, "unit": "box-hit interval evals/s", "cores": nt, "kind": "oracle",
+            "sample": f"level-0 vote of {n_done} event(s) of the timed batch (16^5 boxes x their hits, "
+                      f"{pairs:.3g} pairs) on {nt} threads in {dt:.1f} s",
+            "one_thread": {"value": p1 / dt1, "sample": f"1/16 of event 0's level-0 boxes, {dt1:.1f} s"},
+            "cpu_model": cpu_model()}
+
+
 def _gen(args):
     cfg, i = args
     from paper_2401_04576_amd import toymc
@@ -257,8 +311,15 @@ def generate(cfg, indices):
     if len(indices) < 64:
         return [_gen((cfg, i)) for i in indices]
     import multiprocessing as mp
-    with mp.get_context("fork").Pool(min(16, os.cpu_count() or 1)) as pool:
-        return pool.map(_gen, [(cfg, i) for i in indices], chunksize=16)
+    # close and join (not terminate) the workers, so that none is killed
+    # while a profiler is attached to this process
+    pool = mp.get_context("fork").Pool(min(16, os.cpu_count() or 1))
+    try:
+        out = pool.map(_gen, [(cfg, i) for i in indices], chunksize=16)
+    finally:
+        pool.close()
+        pool.join()
+    return out
 
 
 def cpu_baseline(events, sched_kw, lo, hi, budget_s=20.0):
@@ -291,13 +352,16 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
-    ap.add_argument("--workload", choices=["event", "batch", "serve", "mixed-report", "copy"], default="event")
+    ap.add_argument("--workload", choices=["event", "batch", "serve", "mixed-report", "copy"], default="batch")
+    ap.add_argument("--sched", choices=["window", "topk"], default="window",
+                    help="window: re-gridding from all max-vote boxes with a moved reference point (recovers "
+                         "helices); topk: 16^5 then 4 levels of the top-32 boxes split 4^5 (the literal schedule)")
     ap.add_argument("--batch-events", type=int, default=4096)
     ap.add_argument("--event-batch", type=int, default=1024,
                     help="single-helix workload: events per ia_find_helices call (one step)")
     ap.add_argument("--latency-events", type=int, default=40,
                     help="single-helix workload: single-event calls timed for p50/p99 latency")
-    ap.add_argument("--scratch-gb", type=float, default=16.0)
+    ap.add_argument("--scratch-gb", type=float, default=48.0)
     ap.add_argument("--serve-events", type=int, default=4096)
     ap.add_argument("--rate", type=float, default=1000.0, help="serving: Poisson arrival rate, events/s")
     ap.add_argument("--slots", type=int, default=4, help="serving: concurrent batches")
@@ -462,6 +526,45 @@ def run_event(args):
     print(json.dumps(res), flush=True)
 
 
+def schedule_kw(name, n_helix_max):
+    from paper_2401_04576_amd import toymc
+    kw = dict(toymc.WINDOW_KW if name == "window" else toymc.TOPK_KW)
+    kw.update(v_min=10, n_helix_max=n_helix_max)
+    return kw
+
+
+def schedule_text(name):
+    if name == "window":
+        return ("window schedule: 16^5 grid, a 16^5 window on all max-vote boxes, reference point moved to the "
+                "hit closest to the estimate, six 12^5 windows; forward-hit test before the move; per-level hit "
+                "selection")
+    return "top-k schedule: 16^5 grid then 4 levels of the top-32 boxes split 4^5"
+
+
+def recovery(evs, hel, nout):
+    """Generated helices recovered within the tolerances by a found helix
+    that assigned hits; found helices matching none (fakes)."""
+    from paper_2401_04576_amd import toymc
+    rec = tot = fake = found = 0
+    for e, ev in enumerate(evs):
+        f = hel[e, :int(nout[e])]
+        f = f[f["n_assigned"] > 0]
+        m = toymc.match_helices(f["p"], ev.truth)
+        found += len(f)
+        fake += int((m < 0).sum())
+        rec += len(set(int(x) for x in m if x >= 0))
+        tot += len(ev.truth)
+    return {"recovered": rec, "generated": tot, "rate": rec / max(tot, 1), "found": found, "unmatched": fake}
+
+
+def performed_evals(work, cwork):
+    """Interval evaluations of Eq. ApoVote the library performed: one per
+    live (triple, hit) pair classified over its whole triple, and one per
+    (box, stereo hit) pair evaluated box by box."""
+    e64, _, e32, _ = work
+    return cwork["fp64"]["G"] + cwork["fp32"]["G"] + e64 + e32
+
+
 def run_batch(args):
     """Workload 4: batches of events through one ia_find_helices call each."""
     import torch
@@ -472,7 +575,7 @@ def run_batch(args):
     dev = torch.device("cuda:0")
     lo, hi = np.array(toymc.GRID_RANGE_LO), np.array(toymc.GRID_RANGE_HI)
     nh = 5
-    sched_kw = dict(bins=[16] * 5, n_refine=4, top_k=32, split=[4] * 5, v_min=10, n_helix_max=nh)
+    sched_kw = schedule_kw(args.sched, nh)
     prec = sched_prec(args.prec, sched_kw["n_refine"])
     E = args.batch_events
     n_batches = args.warmup + args.steps
@@ -559,41 +662,69 @@ def run_batch(args):
                 step(args.warmup + k)
         rep_steps = args.steps
     kprof, work, cwork = kernel_measure(ctx, rerun)
-    shapes = level_shapes(sched_kw["bins"], sched_kw["top_k"], sched_kw["split"], sched_kw["n_refine"])
-    evals, found, truth = 0.0, 0, 0
+    # interval evaluations performed in the timed steps: the work counters
+    # over an eager counting repeat of every timed batch (deterministic, so
+    # the same work as the replays)
+    torch.cuda.synchronize()
+    ctx.clear_status()
+    ctx.set_work_counting(True)
+    try:
+        for k in range(args.steps):
+            evs, hits, off, out, n_out, assigned = batches[args.warmup + k]
+            ia.find_helices(ctx, hits, off, sched, max_per_event=nh, stream=stream, out=torch.empty_like(out),
+                            n_out=torch.empty_like(n_out), assigned=torch.empty_like(assigned))
+        torch.cuda.synchronize()
+    finally:
+        ctx.set_work_counting(False)
+    evals = performed_evals(ctx.work(), ctx.classify_work())
+    shapes = window_shapes(sched_kw) if args.sched == "window" else level_shapes(
+        sched_kw["bins"], sched_kw["top_k"], sched_kw["split"], sched_kw["n_refine"])
+    nominal, found, truth = 0.0, 0, 0
+    recs = []
     for k in range(args.steps):
         evs, hits, off, out, n_out, assigned = batches[args.warmup + k]
         hel = ia.decode(out, ia.HELIX_DTYPE).reshape(E, nh)
         nout = n_out.cpu().numpy()
+        recs.append(recovery(evs, hel, nout))
         for e, ev in enumerate(evs):
             n, _ = hit_counts(ev.hits)
-            evals += event_evals(n, hel[e], int(nout[e]), shapes, nh)
+            nominal += event_evals(n, hel[e], int(nout[e]), shapes, nh)
             found += int(nout[e])
             truth += ev.truth.shape[0]
+    rec = {k: sum(r[k] for r in recs) for k in ("recovered", "generated", "found", "unmatched")}
+    rec["rate"] = rec["recovered"] / max(rec["generated"], 1)
     res = {
-        "metric": METRIC, "value": evals / wall, "unit": "box-hit evals/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": wall / args.steps * 1e3, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f64" if args.prec == "fp64" else "f32+f64",
-        "data": "synthetic",
+        "metric": METRIC, "value": evals / wall, "unit": "box-hit interval evals/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": wall / args.steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if args.prec == "fp64" else "f32+f64", "data": "synthetic",
         "config": {"workload": f"batched: {E} events per "
                                + ("replay of one captured ia_find_helices_dev graph" if use_graph
                                   else "ia_find_helices call") + ", 1-5 helices and 20-200 hits "
-                               "per event, 0-30% noise, 150 um smearing, band 3 sigma; 16^5 grid then 4 "
-                               "levels of top-32 split 4^5; up to 5 greedy helix passes; "
-                               + ("FP64" if args.prec == "fp64" else "FP32 at levels 0-2, FP64 at 3-4 and the fit"),
+                               "per event, 0-30% noise, 150 um smearing, band 3 sigma; "
+                               + schedule_text(args.sched) + "; up to 5 greedy helix passes; "
+                               + ("FP64" if args.prec == "fp64" else "FP32 at levels 0-2, FP64 after and the fit"),
                    "events_per_step": E, "helices_found_per_event": found / (E * args.steps),
                    "vote_tiles": {str(k): v for k, v in tuned.items()},
                    "helices_generated_per_event": truth / (E * args.steps)},
+        "value_counts": "interval evaluations of Eq. ApoVote performed: live (triple, hit) pairs classified "
+                        "over their whole triple plus (box, stereo hit) pairs evaluated box by box",
+        "interval_evals_per_step": evals / args.steps,
+        "nominal_box_hit_pairs_per_s": nominal / wall,
+        "nominal_counts": "boxes of every level x the hits active in the pass (each is decided, most in bulk)",
         "events_per_s": E * args.steps / wall,
+        "recovery": rec,
         "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+        "latency": "p50/p99 of the step (one batch of events, resident hits to recorded helices)",
         "roofline": roofline(kprof, work, cwork, wall * rep_steps / args.steps,
                              ("eager repeat of the last timed batch" if use_graph else "repeat of the timed steps")
-                             + ": HIP events around each launch, then a work-counting run"),
+                             + ": HIP events around each launch, then a work-counting run",
+                             measured_traffic("batch", E)),
     }
     if use_graph:
         res["roofline"]["measured_on"] = "eager profiled repeat of the last timed batch"
     if not args.no_cpu_baseline:
-        res["cpu_baseline"] = cpu_baseline(batches[args.warmup][0], sched_kw, lo, hi, args.cpu_budget)
+        res["cpu_baseline"] = cpu_baseline_level0(batches[args.warmup][0], sched_kw, lo, hi, args.cpu_budget)
     ctx.close()
     print(f"[bench] generated {len(events)} events in {t_gen:.1f} s", file=sys.stderr)
     print(json.dumps(res), flush=True)

@@ -117,14 +117,15 @@ enum { IA_SCHED_TOPK = 0, IA_SCHED_WINDOW = 1 };
  * all but one bin at each end of the next grid (kappa and tanl clipped).
  * top_k and split are not used.
  *
- * forward: a hit votes for a box only if it lies ahead of the point of
- * closest approach (along the direction of travel) for some phi0 of the box
- * (interval test on cos(phi0 - phi_hit)).  The paper's particles start at the
- * origin; the test removes the mirror twin (-d0, phi0 + pi, -kappa, z0, -tanl)
- * that traces the same helix backwards and otherwise ties every helix.  It
- * applies at every level in IA_SCHED_TOPK and at the levels up to move_level
- * in IA_SCHED_WINDOW (all levels if move_level < 0), and to the hit finding
- * of a pass whose last level is one of those. */
+ * forward: the paper's particles start at the origin.  About the origin a hit
+ * votes for a box only if it lies ahead of the point of closest approach
+ * (along the direction of travel) for some phi0 of the box (interval test on
+ * cos(phi0 - phi_hit)); this removes the mirror twin (-d0, phi0 + pi, -kappa,
+ * z0, -tanl) that traces the same helix backwards and otherwise ties every
+ * helix.  About a moved reference point a box gets votes only if, for some
+ * phi0 of it, the origin lies behind the point of closest approach.  The
+ * hit-finding box and the per-level hit selection use the first test while
+ * the event's reference point is the origin. */
 typedef struct {
   ia_box range;           /* level-0 search range */
   int32_t bins[5];        /* level-0 grid */
@@ -151,6 +152,11 @@ typedef struct {
                            * forward test); every hit of the pass stays a
                            * candidate for each selection and for hit finding */
   int32_t lbins[IA_MAX_LEVELS][5];  /* IA_SCHED_WINDOW: grid of level l >= 1 */
+  double disk;            /* Eq. ApoVoteDisk (Sec. 3.1), m, >= 0 (0: off): a box
+                           * gets votes only if some circle of it passes within
+                           * `disk` of the origin, the emission point -- the
+                           * vote of a measurement at the origin with drift 0
+                           * and tolerance `disk`, in each level's frame */
 } ia_schedule;
 
 typedef struct ia_ctx ia_ctx;
@@ -227,11 +233,14 @@ ia_status ia_ctx_classify_work(ia_ctx *ctx, int64_t counts[16]);
 
 /* Frame of ia_vote_level (default: forward test off, reference point at the
  * origin): with forward = 1 a hit votes only where it lies ahead of the
- * point of closest approach (the test described at ia_schedule), and the
+ * point of closest approach, with forward = 2 a box gets votes only where the
+ * origin lies behind its point of closest approach (the tests described at
+ * ia_schedule), and the
  * hit points are taken about the reference point (xr, yr) -- the wire point
- * at z = 0 less (xr, yr) -- so the boxes are perigee parameters about it.
- * IA_ERR_INVALID for a non-finite reference point. */
-ia_status ia_ctx_set_vote_frame(ia_ctx *ctx, int32_t forward, double xr, double yr);
+ * at z = 0 less (xr, yr) -- so the boxes are perigee parameters about it;
+ * with disk > 0 the disk condition of ia_schedule applies.  IA_ERR_INVALID
+ * for a non-finite reference point or a negative or non-finite disk. */
+ia_status ia_ctx_set_vote_frame(ia_ctx *ctx, int32_t forward, double xr, double yr, double disk);
 
 /* Band widening used by ia_vote_level at IA_FP32 (default 1e-6 m; ia_find_helices
  * takes it from the schedule).  IA_ERR_INVALID outside [0, 1e-3]. */

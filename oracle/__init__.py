@@ -30,7 +30,7 @@ SCHED_DTYPE = np.dtype([("range", BOX_DTYPE), ("bins", "i4", (5,)), ("n_refine",
                         ("n_helix_max", "i4"), ("hitfind_scale", "f8"), ("prec", "i4", (8,)),
                         ("fp32_slack", "f8"), ("mode", "i4"), ("forward", "i4"),
                         ("move_level", "i4"), ("wdrop", "i4"), ("hitsel", "i4"),
-                        ("lbins", "i4", (8, 5))], align=True)
+                        ("lbins", "i4", (8, 5)), ("disk", "f8")], align=True)
 FP64, FP32 = 0, 1
 TOPK, WINDOW = 0, 1
 HELIX_DTYPE = np.dtype([("p", "f8", (5,)), ("err", "f8", (5,)), ("ref", "f8", (2,)), ("votes", "i4"),
@@ -101,7 +101,9 @@ def lib():
         L.or_frame_shift.restype = None; L.or_frame_shift.argtypes = [_P, d, d, _P]
         L.or_point_G.restype = d; L.or_point_G.argtypes = [_P, _P]
         L.or_vote_level_ex.restype = None
-        L.or_vote_level_ex.argtypes = [_P, i32, _P, _P, i32, _P, i32, d, i32, d, d, _P, i32]
+        L.or_vote_level_ex.argtypes = [_P, i32, _P, _P, i32, _P, i32, d, i32, d, d, d, _P, i32]
+        L.or_disk.restype = i32; L.or_disk.argtypes = [_P, d, d, d]
+        L.or_behind.restype = i32; L.or_behind.argtypes = [_P, d, d]
         L.or_estimate_ex.restype = i32
         L.or_estimate_ex.argtypes = [_P, i32, _P, _P, C.c_uint16, _P, _P, _P, _P]
         L.or_find_helices.restype = i32
@@ -224,8 +226,18 @@ def pair_vote(prep, box, debug=False):
     return (int(v), dbg) if debug else int(v)
 
 
+def disk(box, ref=(0.0, 0.0), radius=5e-3):
+    box = _c(np.atleast_1d(box), BOX_DTYPE)
+    return int(lib().or_disk(_ptr(box), float(ref[0]), float(ref[1]), float(radius)))
+
+
+def behind(box, ref):
+    box = _c(np.atleast_1d(box), BOX_DTYPE)
+    return int(lib().or_behind(_ptr(box), float(ref[0]), float(ref[1])))
+
+
 def vote_level(hits, parents, split, active=None, n_threads=0, prec=FP64, slack=1e-6, forward=False,
-               ref=(0.0, 0.0)):
+               ref=(0.0, 0.0), disk=0.0):
     hits = _c(hits, HIT_DTYPE)
     parents = _c(np.atleast_1d(parents), BOX_DTYPE)
     split = _c(split, np.int32)
@@ -233,8 +245,8 @@ def vote_level(hits, parents, split, active=None, n_threads=0, prec=FP64, slack=
     votes = np.zeros(nb, dtype=np.uint16)
     act = None if active is None else _c(active, np.uint8)
     lib().or_vote_level_ex(_ptr(hits), hits.shape[0], _ptr(act), _ptr(parents), parents.shape[0],
-                           _ptr(split), int(prec), C.c_double(slack), int(bool(forward)),
-                           float(ref[0]), float(ref[1]), _ptr(votes), int(n_threads))
+                           _ptr(split), int(prec), C.c_double(slack), int(forward),
+                           float(ref[0]), float(ref[1]), float(disk), _ptr(votes), int(n_threads))
     return votes
 
 
@@ -314,7 +326,7 @@ def estimate_ex(parents, split, votes, vmax):
 
 def make_sched(lo, hi, bins, n_refine=4, top_k=32, split=(4, 4, 4, 4, 4), v_min=10,
                n_helix_max=1, hitfind_scale=5.0, prec=None, fp32_slack=1e-6, mode=TOPK, forward=False,
-               move_level=-1, lbins=None, wdrop=0, hitsel=False):
+               move_level=-1, lbins=None, wdrop=0, hitsel=False, disk=0.0):
     """prec: per-level FP64 / FP32 list (default all FP64).  mode WINDOW: level l >= 1 is
     a grid of lbins[l] over its window; the reference point moves after move_level."""
     s = np.zeros((), dtype=SCHED_DTYPE)
@@ -323,6 +335,7 @@ def make_sched(lo, hi, bins, n_refine=4, top_k=32, split=(4, 4, 4, 4, 4), v_min=
     s["move_level"] = move_level
     s["wdrop"] = wdrop
     s["hitsel"] = int(bool(hitsel))
+    s["disk"] = disk
     if lbins is not None:
         for l, b in enumerate(lbins):
             s["lbins"][l] = b

@@ -415,6 +415,53 @@ void or_frame_shift(const double p[5], double dx, double dy, double q[5]) {
   q[4] = l;
 }
 
+/* ------------------------------------------------------------------------
+ * The disk condition, Eq. ApoVoteDisk (Sec. 3.1): a voxel is considered only
+ * if some circle of it passes within R_disk of the emission point, the
+ * origin.  That is Eq. ApoVote for a measurement at the origin with drift
+ * distance 0 and tolerance R_disk: an axial hit whose point is the origin
+ * taken about the reference point.  The paper uses it to skip voxels; here
+ * it also keeps the search near the origin after the reference point moves.
+ * Parity: pinned on sampled circles (distance from the origin).
+ * ---------------------------------------------------------------------- */
+int32_t or_disk(const or_box *b, double xr, double yr, double disk) {
+  or_prep h;
+  memset(&h, 0, sizeof h);
+  h.valid = 1;
+  h.axial = 1;
+  h.px = -xr;
+  h.py = -yr;
+  h.tant = 0.0;
+  h.sphis = 0.0;
+  h.cphis = 1.0;
+  h.r = sqrt(h.px * h.px + h.py * h.py);
+  h.phip = h.r == 0.0 ? 0.0 : or_atan2(h.py, h.px);
+  double r2 = h.r * h.r;
+  h.r2lo = or_wdn(r2);
+  h.r2hi = or_wup(r2);
+  h.d = 0.0;
+  h.band = disk;
+  return or_pair_vote(&h, b, NULL);
+}
+
+/* About a moved reference point the forward-hit test no longer applies (the
+ * hits lie on both sides of it), and the mirror twin returns.  The track
+ * still comes from the origin: the origin, seen from the point of closest
+ * approach, lies behind it, r_O cos(phi0 - phi_O) < 0 with phi_O the
+ * direction of the origin from the reference point.  Over the box's phi0
+ * interval the lower end of the enclosure of cos(phi0 - phi_O) =
+ * sin(phi0 - phi_O + pi/2) decides (outward, as in or_forward).
+ * Parity: pinned by brute force over sampled phi0 and by the twin test. */
+int32_t or_behind(const or_box *b, double xr, double yr) {
+  if (xr == 0.0 && yr == 0.0) return 1;
+  double phio = or_atan2(-yr, -xr);
+  double lo = or_wdn(or_wdn(b->lo[1] - phio) + PIO2_RN);
+  double hi = or_wup(or_wup(b->hi[1] - phio) + PIO2_UP);
+  double slo, shi;
+  or_sin_encl(lo, hi, &slo, &shi);
+  return slo < 0.0;
+}
+
 /* G of Eq. ApoVote's kappa-scaled form at one parameter point */
 double or_point_G(const or_prep *h, const double p[5]) {
   double d0 = p[0], k = p[2];
@@ -595,7 +642,8 @@ static int64_t prod5(const int32_t m[5]) {
 
 static void vote_prepped(const or_prep *pr, const uint8_t *use, int32_t n_hits,
                          const or_box *parents, int32_t n_parents, const int32_t split[5],
-                         int32_t prec, double slack, int32_t fwd, uint16_t *votes, int32_t n_threads) {
+                         int32_t prec, double slack, int32_t fwd, double disk, double xr, double yr,
+                         uint16_t *votes, int32_t n_threads) {
   int64_t nc = prod5(split), nb = (int64_t)n_parents * nc;
 #ifdef _OPENMP
   int nt = n_threads > 0 ? n_threads : omp_get_max_threads();
@@ -605,8 +653,12 @@ static void vote_prepped(const or_prep *pr, const uint8_t *use, int32_t n_hits,
     or_box box;
     or_box_child(&parents[b / nc], split, b % nc, &box);
     int32_t v = 0;
+    if ((disk > 0.0 && !or_disk(&box, xr, yr, disk)) || (fwd == 2 && !or_behind(&box, xr, yr))) {
+      votes[b] = 0;
+      continue;
+    }
     for (int32_t i = 0; i < n_hits; i++) {
-      if (!use[i] || (fwd && !or_forward(&pr[i], &box))) continue;
+      if (!use[i] || (fwd == 1 && !or_forward(&pr[i], &box))) continue;
       v += prec == OR_FP32 ? or_pair_vote32(&pr[i], &box, slack, NULL) : or_pair_vote(&pr[i], &box, NULL);
     }
     votes[b] = (uint16_t)v;
@@ -623,19 +675,19 @@ void or_vote_level(const or_hit *hits, int32_t n_hits, const uint8_t *active,
 void or_vote_level_prec(const or_hit *hits, int32_t n_hits, const uint8_t *active,
                         const or_box *parents, int32_t n_parents, const int32_t split[5],
                         int32_t prec, double slack, uint16_t *votes, int32_t n_threads) {
-  or_vote_level_ex(hits, n_hits, active, parents, n_parents, split, prec, slack, 0, 0.0, 0.0, votes,
+  or_vote_level_ex(hits, n_hits, active, parents, n_parents, split, prec, slack, 0, 0.0, 0.0, 0.0, votes,
                    n_threads);
 }
 
 void or_vote_level_ex(const or_hit *hits, int32_t n_hits, const uint8_t *active,
                       const or_box *parents, int32_t n_parents, const int32_t split[5],
                       int32_t prec, double slack, int32_t forward, double xr, double yr,
-                      uint16_t *votes, int32_t n_threads) {
+                      double disk, uint16_t *votes, int32_t n_threads) {
   or_prep *pr = (or_prep *)calloc((size_t)(n_hits > 0 ? n_hits : 1), sizeof *pr);
   uint8_t *use = (uint8_t *)calloc((size_t)(n_hits > 0 ? n_hits : 1), 1);
   for (int32_t i = 0; i < n_hits; i++)
     use[i] = (uint8_t)(or_prep_hit_ref(&hits[i], xr, yr, &pr[i]) && (!active || active[i]));
-  vote_prepped(pr, use, n_hits, parents, n_parents, split, prec, slack, forward, votes, n_threads);
+  vote_prepped(pr, use, n_hits, parents, n_parents, split, prec, slack, forward, disk, xr, yr, votes, n_threads);
   free(pr);
   free(use);
 }
@@ -682,9 +734,20 @@ int32_t or_estimate(const or_box *parents, int32_t n_parents, const int32_t spli
   return or_estimate_ex(parents, n_parents, split, votes, vmax, p, err, ulo, uhi);
 }
 
+static int32_t estimate_masked(const or_box *parents, int32_t n_parents, const int32_t split[5],
+                               const uint16_t *votes, uint16_t vmax, const uint8_t *mask, double p[5],
+                               double err[5], double ulo[5], double uhi[5]);
+
 int32_t or_estimate_ex(const or_box *parents, int32_t n_parents, const int32_t split[5],
                        const uint16_t *votes, uint16_t vmax, double p[5], double err[5],
                        double ulo[5], double uhi[5]) {
+  return estimate_masked(parents, n_parents, split, votes, vmax, NULL, p, err, ulo, uhi);
+}
+
+/* the estimate over the max-vote boxes with mask[b] != 0 (mask NULL: all) */
+static int32_t estimate_masked(const or_box *parents, int32_t n_parents, const int32_t split[5],
+                               const uint16_t *votes, uint16_t vmax, const uint8_t *mask, double p[5],
+                               double err[5], double ulo[5], double uhi[5]) {
   int64_t nc = prod5(split), nb = (int64_t)n_parents * nc, p2 = 1;
   while (p2 < nb) p2 <<= 1;
   double *acc[5];
@@ -693,7 +756,7 @@ int32_t or_estimate_ex(const or_box *parents, int32_t n_parents, const int32_t s
   for (int j = 0; j < 5; j++) { lo_min[j] = INFINITY; hi_max[j] = -INFINITY; }
   int32_t count = 0;
   for (int64_t b = 0; b < nb; b++) {
-    if (votes[b] != vmax) continue;
+    if (votes[b] != vmax || (mask && !mask[b])) continue;
     or_box box;
     or_box_child(&parents[b / nc], split, b % nc, &box);
     if (count == 0) c0 = 0.5 * (box.lo[1] + box.hi[1]);
@@ -742,8 +805,9 @@ int32_t or_estimate_ex(const or_box *parents, int32_t n_parents, const int32_t s
  *
  * OR_WINDOW: each level is one regular grid over a window box.  Level 0's
  * window is the search range.  After a level, the estimate comes from ALL
- * its max-vote boxes (never truncated: Sec. 3.3 computes the values and
- * errors from every selected max cell), and the next window from every box
+ * its max-vote boxes of one phi0 run (never truncated within it: Sec. 3.3
+ * computes the values and errors from every selected max cell; phi_run
+ * below keeps to one track), and the next window from every box of the run
  * within wdrop votes of the maximum (noise hits can lift a few boxes by a
  * vote or two above the track's own): the union of those boxes (phi0
  * relative to the first max-vote box's centre, as in the estimate) widened
@@ -761,8 +825,12 @@ int32_t or_estimate_ex(const or_box *parents, int32_t n_parents, const int32_t s
  * votes only with the hits that vote for the previous level's hit-finding
  * box (estimate +- hitfind_scale x error, in that level's frame); every hit
  * of the pass stays a candidate at each selection and at the hit finding.
- * The forward-hit test applies at the levels up to move_level (all levels
- * when the reference never moves), to their votes and selections.  The helix's p is
+ * With `forward`, the levels about the origin (up to move_level, or all
+ * when the reference point never moves, or does not find a hit) apply the
+ * forward-hit test to their votes, selections and the hit finding; the
+ * levels about a moved reference point apply the direction test or_behind
+ * to every box instead.  With disk > 0 every level applies the disk
+ * condition (or_disk) in its frame.  The helix's p is
  * the last estimate taken back to the origin; its err and the hit finding
  * stay in the last level's frame.
  * Parity of the driver: the per-level truth checks and the recovery rates
@@ -810,8 +878,8 @@ static int32_t find_topk(const or_hit *hits, int32_t n_hits, const or_sched *sc,
     uint16_t vmax = 0;
     int32_t stop = 0;
     for (int32_t lev = 0; lev <= sc->n_refine; lev++) {
-      vote_prepped(pr, act, n_hits, par, n_par, split, sc->prec[lev], sc->fp32_slack, sc->forward, votes,
-                   n_threads);
+      vote_prepped(pr, act, n_hits, par, n_par, split, sc->prec[lev], sc->fp32_slack, sc->forward, sc->disk,
+                   0.0, 0.0, votes, n_threads);
       int64_t nb = (int64_t)n_par * prod5(split);
       int32_t k = or_topk(votes, nb, sc->top_k, tidx, tv);
       vmax = k > 0 ? tv[0] : 0;
@@ -863,6 +931,55 @@ static void box_corner(const or_box *b, int c, double x[5]) {
   for (int j = 0; j < 5; j++) x[j] = ((c >> j) & 1) ? b->hi[j] : b->lo[j];
 }
 
+/* One track at a time: at the coarse levels every helix of an event ties at
+ * the maximum, and their max-vote boxes together would give a meaningless
+ * estimate.  The estimate and the next window therefore use the max-vote
+ * boxes (and the boxes within wdrop of the maximum) whose phi0 bin lies in
+ * the contiguous run of phi0 bins holding max-vote boxes that contains the
+ * first max-vote box's bin (circular when the grid spans a full turn; every
+ * bin when the run covers them all or the grid has more than RUN_MAX_BINS
+ * phi0 bins).  A single helix's max-vote boxes form one such run. */
+#define RUN_MAX_BINS 1024
+
+static void phi_run(const or_box *grid, const int32_t m[5], const uint16_t *votes, int64_t nb, uint16_t vmax,
+                    int64_t first, int32_t *ra, int32_t *rb) {
+  int32_t m1 = m[1];
+  *ra = -1;
+  *rb = -1;
+  if (m1 > RUN_MAX_BINS) return;
+  uint8_t occ[RUN_MAX_BINS];
+  memset(occ, 0, sizeof occ);
+  int64_t s1 = (int64_t)m[2] * m[3] * m[4];
+  for (int64_t b = 0; b < nb; b++)
+    if (votes[b] == vmax) occ[(b / s1) % m1] = 1;
+  int32_t kf = (int32_t)((first / s1) % m1);
+  int32_t circ = grid->hi[1] - grid->lo[1] >= TWO_PI_RN;
+  int32_t a = kf, e = kf, n = 1;
+  while (n < m1) {
+    int32_t k = e + 1;
+    if (k == m1) { if (!circ) break; k = 0; }
+    if (!occ[k]) break;
+    e = k;
+    n++;
+  }
+  while (n < m1) {
+    int32_t k = a - 1;
+    if (k < 0) { if (!circ) break; k = m1 - 1; }
+    if (!occ[k]) break;
+    a = k;
+    n++;
+  }
+  if (n == m1) return;
+  *ra = a;
+  *rb = e;
+}
+
+static int32_t in_run(int64_t b, const int32_t m[5], int32_t ra, int32_t rb) {
+  if (ra < 0) return 1;
+  int32_t k = (int32_t)((b / ((int64_t)m[2] * m[3] * m[4])) % m[1]);
+  return ra <= rb ? (k >= ra && k <= rb) : (k >= ra || k <= rb);
+}
+
 static int32_t find_window(const or_hit *hits, int32_t n_hits, const or_sched *sc, or_helix *out,
                            int32_t max_out, int32_t *assigned, or_trace *trace, int32_t n_threads,
                            or_prep *pr, uint8_t *act) {
@@ -870,6 +987,7 @@ static int32_t find_window(const or_hit *hits, int32_t n_hits, const or_sched *s
   for (int32_t l = 1; l <= sc->n_refine; l++)
     if (prod5(sc->lbins[l]) > nbmax) nbmax = prod5(sc->lbins[l]);
   uint16_t *votes = (uint16_t *)malloc((size_t)nbmax * sizeof(uint16_t));
+  uint8_t *mask = (uint8_t *)malloc((size_t)nbmax);
   uint8_t *sel = (uint8_t *)calloc((size_t)(n_hits > 0 ? n_hits : 1), 1);
   int32_t nh = 0;
   for (int32_t pass = 0; pass < sc->n_helix_max && nh < max_out; pass++) {
@@ -887,11 +1005,17 @@ static int32_t find_window(const or_hit *hits, int32_t n_hits, const or_sched *s
     int32_t stop = 0, count = 0;
     double p[5], err[5], ulo[5], uhi[5];
     for (int32_t lev = 0; lev <= sc->n_refine; lev++) {
-      int32_t fwd = sc->forward && (sc->move_level < 0 || lev <= sc->move_level);
-      vote_prepped(pr, sel, n_hits, &grid, 1, m, sc->prec[lev], sc->fp32_slack, fwd, votes, n_threads);
+      /* about the origin the hits lie ahead; about a moved reference point
+       * the origin lies behind */
+      int32_t fwd = !sc->forward ? 0 : (moved ? 2 : 1);
+      vote_prepped(pr, sel, n_hits, &grid, 1, m, sc->prec[lev], sc->fp32_slack, fwd, sc->disk, ref[0], ref[1],
+                   votes, n_threads);
       int64_t nb = prod5(m), first;
       vmax = level_max(votes, nb, &first);
-      count = or_estimate_ex(&grid, 1, m, votes, vmax, p, err, ulo, uhi);
+      int32_t ra, rb;
+      phi_run(&grid, m, votes, nb, vmax, first, &ra, &rb);
+      for (int64_t b = 0; b < nb; b++) mask[b] = (uint8_t)in_run(b, m, ra, rb);
+      count = estimate_masked(&grid, 1, m, votes, vmax, mask, p, err, ulo, uhi);
       if (trace && pass < OR_MAX_PASSES && lev < OR_MAX_LEVELS) {
         trace->n_passes = pass + 1;
         trace->vmax[pass][lev] = vmax;
@@ -915,7 +1039,7 @@ static int32_t find_window(const or_hit *hits, int32_t n_hits, const or_sched *s
           E.hi[j] = p[j] + w;
         }
         for (int32_t i = 0; i < n_hits; i++)
-          sel[i] = (uint8_t)(act[i] && (!fwd || or_forward(&pr[i], &E)) && or_pair_vote(&pr[i], &E, NULL));
+          sel[i] = (uint8_t)(act[i] && (fwd != 1 || or_forward(&pr[i], &E)) && or_pair_vote(&pr[i], &E, NULL));
       }
       or_box nx;
       int32_t did_move = 0;
@@ -941,7 +1065,7 @@ static int32_t find_window(const or_hit *hits, int32_t n_hits, const or_sched *s
             cref = q[1];
           }
           for (int64_t b = 0; b < nb; b++) {
-            if (votes[b] < vlo) continue;
+            if (votes[b] < vlo || !mask[b]) continue;
             or_box box;
             or_box_child(&grid, m, b, &box);
             for (int c = 0; c < 32; c++) {
@@ -976,7 +1100,7 @@ static int32_t find_window(const or_hit *hits, int32_t n_hits, const or_sched *s
         c0 = 0.5 * (fb.lo[1] + fb.hi[1]);
         for (int j = 0; j < 5; j++) { wl[j] = INFINITY; wh[j] = -INFINITY; }
         for (int64_t b = 0; b < nb; b++) {
-          if (votes[b] < vlo) continue;
+          if (votes[b] < vlo || !mask[b]) continue;
           or_box box;
           or_box_child(&grid, m, b, &box);
           for (int j = 0; j < 5; j++) {
@@ -1023,7 +1147,7 @@ static int32_t find_window(const or_hit *hits, int32_t n_hits, const or_sched *s
       E.lo[j] = p[j] - w;
       E.hi[j] = p[j] + w;
     }
-    int32_t fwd = sc->forward && (sc->move_level < 0 || sc->n_refine <= sc->move_level);
+    int32_t fwd = sc->forward && !moved;
     int32_t na = 0;
     hit_finding(pr, act, n_hits, &E, fwd, assigned, nh, &na);
     if (moved) or_frame_shift(p, -ref[0], -ref[1], hx.p);
@@ -1036,6 +1160,7 @@ static int32_t find_window(const or_hit *hits, int32_t n_hits, const or_sched *s
     if (na == 0) break;
   }
   free(votes);
+  free(mask);
   free(sel);
   return nh;
 }

@@ -63,6 +63,9 @@ typedef struct {
   int32_t hitsel;                         /* OR_WINDOW: a level votes with the hits that
                                              voted for the previous level's hit-finding box */
   int32_t lbins[OR_MAX_LEVELS][5];        /* OR_WINDOW: grid of level l >= 1 over its window */
+  double disk;                            /* Eq. ApoVoteDisk: boxes whose circles all miss the
+                                             disk of this radius about the origin (m) get no
+                                             votes; 0: off */
 } or_sched;
 
 typedef struct {
@@ -152,12 +155,23 @@ void or_vote_level_prec(const or_hit *hits, int32_t n_hits, const uint8_t *activ
                         const or_box *parents, int32_t n_parents, const int32_t split[5],
                         int32_t prec, double slack, uint16_t *votes, int32_t n_threads);
 
-/* the same with the forward-hit test on (forward != 0) and the hits taken
- * about the reference point (xr, yr) */
+/* the same with the forward-hit test (forward = 1) or the direction test
+ * or_behind (forward = 2), the hits taken about the reference point (xr, yr),
+ * and the disk test of Eq. ApoVoteDisk (disk > 0) */
 void or_vote_level_ex(const or_hit *hits, int32_t n_hits, const uint8_t *active,
                       const or_box *parents, int32_t n_parents, const int32_t split[5],
                       int32_t prec, double slack, int32_t forward, double xr, double yr,
-                      uint16_t *votes, int32_t n_threads);
+                      double disk, uint16_t *votes, int32_t n_threads);
+
+/* Eq. ApoVoteDisk for one box in the frame of the reference point (xr, yr):
+ * 1 when some circle of the box passes within `disk` of the origin */
+int32_t or_disk(const or_box *b, double xr, double yr, double disk);
+
+/* Direction test about a moved reference point (xr, yr): 1 when for some
+ * phi0 of the box the origin lies behind the point of closest approach
+ * (the track comes from the origin), 0 when it lies ahead for every phi0.
+ * The origin at the reference point counts as behind. */
+int32_t or_behind(const or_box *b, double xr, double yr);
 
 /* the first k boxes by (votes desc, index asc); returns k actually taken */
 int32_t or_topk(const uint16_t *votes, int64_t n_boxes, int32_t k,

@@ -48,12 +48,12 @@ class Schedule(C.Structure):
                 ("hitfind_scale", C.c_double), ("prec", C.c_int32 * MAX_LEVELS),
                 ("fp32_slack", C.c_double), ("mode", C.c_int32), ("forward", C.c_int32),
                 ("move_level", C.c_int32), ("wdrop", C.c_int32), ("hitsel", C.c_int32),
-                ("lbins", (C.c_int32 * 5) * MAX_LEVELS)]
+                ("lbins", (C.c_int32 * 5) * MAX_LEVELS), ("disk", C.c_double)]
 
     @classmethod
     def make(cls, lo, hi, bins, n_refine=4, top_k=32, split=(4, 4, 4, 4, 4), v_min=10, n_helix_max=1,
              hitfind_scale=5.0, prec=None, fp32_slack=1e-6, mode=SCHED_TOPK, forward=False, move_level=-1,
-             lbins=None, wdrop=0, hitsel=False):
+             lbins=None, wdrop=0, hitsel=False, disk=0.0):
         """mode SCHED_WINDOW: level l >= 1 is the grid lbins[l] over a window built from all max-vote
         boxes of level l - 1; the reference point moves after move_level (see include/ia.h)."""
         s = cls()
@@ -62,6 +62,7 @@ class Schedule(C.Structure):
         s.move_level = int(move_level)
         s.wdrop = int(wdrop)
         s.hitsel = int(bool(hitsel))
+        s.disk = float(disk)
         if lbins is not None:
             for l, b in enumerate(lbins):
                 for j in range(5):
@@ -124,7 +125,7 @@ def load():
     L.ia_ctx_set_fp32_slack.restype = i32
     L.ia_ctx_set_fp32_slack.argtypes = [P, C.c_double]
     L.ia_ctx_set_vote_frame.restype = i32
-    L.ia_ctx_set_vote_frame.argtypes = [P, i32, C.c_double, C.c_double]
+    L.ia_ctx_set_vote_frame.argtypes = [P, i32, C.c_double, C.c_double, C.c_double]
     L.ia_ctx_clear_status.restype = i32
     L.ia_ctx_clear_status.argtypes = [P]
     L.ia_ctx_set_batch.restype = i32
@@ -240,9 +241,10 @@ class Context:
         """Band widening of vote_level at FP32 (m)."""
         self._check(self._L.ia_ctx_set_fp32_slack(self._h, float(slack)))
 
-    def set_vote_frame(self, forward=False, ref=(0.0, 0.0)):
-        """forward-hit test and reference point of vote_level"""
-        self._check(self._L.ia_ctx_set_vote_frame(self._h, int(bool(forward)), float(ref[0]), float(ref[1])))
+    def set_vote_frame(self, forward=False, ref=(0.0, 0.0), disk=0.0):
+        """forward-hit test, reference point and disk condition of vote_level"""
+        self._check(self._L.ia_ctx_set_vote_frame(self._h, int(forward), float(ref[0]), float(ref[1]),
+                                                  float(disk)))
 
     def clear_status(self):
         self._check(self._L.ia_ctx_clear_status(self._h))

@@ -71,7 +71,22 @@ struct EventState {
   double ulo[5], uhi[5];        // union of the last level's max-vote boxes (phi0 relative to the first)
   double ref[2];                // reference point of the current level (origin coordinates)
   double shift[2];              // move of the reference point under way (the chosen hit point)
+  uint32_t occ[32];             // window schedule: phi0 bins holding max-vote boxes (bit mask)
+  int32_t run_a, run_b;         // their run holding the first max-vote box (run_a < 0: all bins)
 };
+
+constexpr uint32_t kRunMaxBins = 1024;   // phi0 bins the run selection handles
+
+// phi0 bin of box b of a level
+IA_HD uint32_t phi_bin(const Shape& sh, uint32_t b) {
+  return ((b % sh.nc) / (sh.m[2] * sh.m[3] * sh.m[4])) % sh.m[1];
+}
+
+IA_HD bool in_run(uint32_t k, int32_t a, int32_t b) {
+  if (a < 0) return true;
+  const int32_t kk = static_cast<int32_t>(k);
+  return a <= b ? (kk >= a && kk <= b) : (kk >= a || kk <= b);
+}
 
 // Per-event views of a batch of events launched together: blockIdx.y is the
 // event.  Event e owns hits [off[e], off[e+1]) of the prepared-hit array
@@ -93,6 +108,8 @@ struct EvView {
   int32_t max_hits;             // hits per event the strides are sized for (0: unchecked)
   int64_t n_total;              // hits addressable from the batch's first hit
   int32_t fwd;                  // 1: forward-hit test at this level
+  double disk;                  // disk condition radius (0: off)
+  double vref[2];               // reference point of the level when there is no event state
   __device__ int32_t beg(int e) const { return off ? off[e] : 0; }
   __device__ int32_t count(int e) const { return off ? off[e + 1] - off[e] : n_single; }
 };
@@ -237,6 +254,18 @@ IA_HD bool forward_ok(const Iv& Fi, const HitRec& h) {
   return S.hi > 0.0;
 }
 
+// Direction test about a moved reference point (xr, yr): for some phi0 of the
+// triple the origin, seen from the point of closest approach, lies behind it
+// (the track comes from the origin): the enclosure of cos(phi0 - phi_O) =
+// sin(phi0 - phi_O + pi/2) reaches below zero, phi_O the direction of the
+// origin from the reference point.
+IA_HD bool behind_ok(const Iv& Fi, double xr, double yr) {
+  if (xr == 0.0 && yr == 0.0) return true;
+  const double phio = atan2_p(-yr, -xr);
+  const Iv S = sin_encl(wdn(wdn(Fi.lo - phio) + kPio2), wup(wup(Fi.hi - phio) + kPio2Up));
+  return S.lo < 0.0;
+}
+
 // Perigee parameters p about a reference point -> q about that point moved by
 // (dx, dy).  With n = (-sin phi0, cos phi0) and u = (cos phi0, sin phi0),
 // A = (1 + kappa d0) n - kappa D is kappa times the vector from the new point
@@ -264,6 +293,29 @@ IA_HD void frame_shift(const double* p, double dx, double dy, double* q) {
   q[2] = k;
   q[3] = z0 + l * arc;
   q[4] = l;
+}
+
+// The disk condition (Eq. ApoVoteDisk): some circle of the triple passes
+// within `disk` of the origin.  It is Eq. ApoVote for a measurement at the
+// origin with drift 0 and tolerance `disk`: an axial hit whose point is the
+// origin taken about the reference point (xr, yr).
+IA_HD HitRec disk_hit(double xr, double yr, double disk) {
+  HitRec h{};
+  h.px = -xr;
+  h.py = -yr;
+  h.tant = 0.0;
+  h.sphis = 0.0;
+  h.cphis = 1.0;
+  h.r = sqrt(h.px * h.px + h.py * h.py);
+  h.phip = h.r == 0.0 ? 0.0 : atan2_p(h.py, h.px);
+  const double r2 = h.r * h.r;
+  h.r2lo = wdn(r2);
+  h.r2hi = wup(r2);
+  h.d = 0.0;
+  h.band = disk;
+  h.use = 1;
+  h.axial = 1;
+  return h;
 }
 
 // G of the kappa-scaled Eq. ApoVote at one parameter point: to first order
@@ -1315,13 +1367,24 @@ __global__ void __launch_bounds__(kWG, 4) k_classify(const HitRec* __restrict__ 
   Iv Zr, Lr;
   centre_ranges(TP, sh.m, &Zr, &Lr);
   const GTri gt = g_triple(f);
+  // the disk condition of the level, once per triple (every hit's pair is
+  // class 0 where it fails)
+  // with the forward test: about the origin each hit must lie ahead (mode
+  // 1); about a moved reference point the origin must lie behind (mode 2)
+  const int fwdm = ev ? (vw.fwd ? (ev[e].moved ? 2 : 1) : 0) : vw.fwd;
+  const double xr = ev ? ev[e].ref[0] : vw.vref[0], yr = ev ? ev[e].ref[1] : vw.vref[1];
+  bool disk_ok = fwdm != 2 || behind_ok(f.Fi, xr, yr);
+  if (disk_ok && vw.disk > 0.0) {
+    const HitRec dh = disk_hit(xr, yr, vw.disk);
+    disk_ok = h_contains0(residual_G(f, dh), f.K, f.sig * dh.d, dh.band);
+  }
   int32_t lb = 0, n2 = 0;
   int32_t cw[kCwDefer] = {0, 0, 0, 0, 0};
   const int32_t h_step = static_cast<int32_t>(gridDim.z) * (kWG / 64);
   for (int32_t h = static_cast<int32_t>(blockIdx.z) * (kWG / 64) + wave; h < n_hits; h += h_step) {
     const HitRec hr = hits[h];
     uint8_t fl = 0;
-    if (votes_now(hr) && (!pf || pf[h]) && (!vw.fwd || forward_ok(f.Fi, hr))) {
+    if (disk_ok && votes_now(hr) && (!pf || pf[h]) && (fwdm != 1 || forward_ok(f.Fi, hr))) {
       const int c = pair_stage1<F32>(f, gt, hr, Zr, Lr, filter, slack32, COUNT ? cw : nullptr, pr ? &pr[h] : nullptr);
       fl = c >= 0 ? static_cast<uint8_t>(c) : defer_flag(-c);
     }
@@ -2439,7 +2502,7 @@ __global__ void __launch_bounds__(kWG) k_est_partial(const BoxD* __restrict__ pa
                                                      double* __restrict__ part, EvView vw,
                                                      const EventState* __restrict__ ev,
                                                      const int32_t* __restrict__ wg_max, int32_t bx,
-                                                     uint32_t n_part, uint32_t per) {
+                                                     uint32_t n_part, uint32_t per, int32_t use_run) {
   const int e = blockIdx.y;
   if (ev && ev[e].done) return;
   parents += e * vw.par_stride;
@@ -2451,6 +2514,7 @@ __global__ void __launch_bounds__(kWG) k_est_partial(const BoxD* __restrict__ pa
   __shared__ double s[kEstQ][kWG];
   const int32_t vmax = first_votes[0];
   const double c0 = 0.5 * (first_box->lo[1] + first_box->hi[1]);
+  const int32_t ra = use_run ? ev[e].run_a : -1, rb = use_run ? ev[e].run_b : -1;
   const uint32_t ch_end = min(n_part, (blockIdx.x + 1) * per);
   for (uint32_t ch = blockIdx.x * per; ch < ch_end; ++ch) {
     const uint32_t i = ch * kWG + threadIdx.x;
@@ -2458,8 +2522,8 @@ __global__ void __launch_bounds__(kWG) k_est_partial(const BoxD* __restrict__ pa
     for (int q = 0; q < 5; ++q) { v[q] = 0.0; v[5 + q] = INFINITY; v[10 + q] = -INFINITY; }
     v[15] = 0.0;
     // with wg_max, only tiles whose maximum reaches vmax hold written votes
-    const bool at_max =
-        i < sh.n_boxes && (!wg_max || wg_max[i / static_cast<uint32_t>(bx)] >= vmax) && votes[i] == vmax;
+    const bool at_max = i < sh.n_boxes && (!wg_max || wg_max[i / static_cast<uint32_t>(bx)] >= vmax) &&
+                        votes[i] == vmax && in_run(phi_bin(sh, i), ra, rb);
     // a chunk without a max-vote box reduces to the identity (sums 0,
     // minima +inf, maxima -inf, count 0), bit for bit: write it without the
     // tree
@@ -2640,7 +2704,7 @@ __global__ void __launch_bounds__(kWG) k_est_final(const double* __restrict__ pa
   const int32_t k = ev->n_out;
   int32_t mine = 0;
   for (int32_t i = t; i < n_hits; i += kWG) {
-    if (pair_vote_box(E, hits[i], fwd != 0)) {
+    if (pair_vote_box(E, hits[i], fwd != 0 && !ev->moved)) {
       hits[i].use = 0;
       if (assigned) assigned[i] = k;
       ++mine;
@@ -2750,8 +2814,9 @@ __global__ void __launch_bounds__(kWG) k_closest(const HitRec* __restrict__ hits
 
 // Per-level hit selection (Sec. 3.3): after a level, every active hit of the
 // pass is tested against the level's hit-finding box (estimate +- scale x
-// error, in the level's frame, with the level's forward test); the hits that
-// vote for it vote at the next level, the others (use = 3) sit it out.
+// error, in the level's frame, with the forward-hit test while the frame is
+// the origin's); the hits that vote for it vote at the next level, the others
+// (use = 3) sit it out.
 __global__ void __launch_bounds__(kWG) k_hit_select(HitRec* __restrict__ hits, EvView vw,
                                                     const EventState* __restrict__ ev, double scale,
                                                     int32_t fwd) {
@@ -2769,7 +2834,7 @@ __global__ void __launch_bounds__(kWG) k_hit_select(HitRec* __restrict__ hits, E
   for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n_hits; i += stride) {
     HitRec& h = hits[i];
     if (!(h.use & 1)) continue;
-    h.use = pair_vote_box(E, h, fwd != 0) ? 1 : 3;
+    h.use = pair_vote_box(E, h, fwd != 0 && !ev[e].moved) ? 1 : 3;
   }
 }
 
@@ -2820,8 +2885,8 @@ __global__ void __launch_bounds__(kWG) k_window_partial(const BoxD* __restrict__
     double v[kEstQ];
     for (int q = 0; q < 5; ++q) { v[q] = 0.0; v[5 + q] = INFINITY; v[10 + q] = -INFINITY; }
     v[15] = 0.0;
-    const bool in_set =
-        i < sh.n_boxes && (!wg_max || wg_max[i / static_cast<uint32_t>(bx)] >= vlo) && votes[i] >= vlo;
+    const bool in_set = i < sh.n_boxes && (!wg_max || wg_max[i / static_cast<uint32_t>(bx)] >= vlo) &&
+                        votes[i] >= vlo && in_run(phi_bin(sh, i), ev[e].run_a, ev[e].run_b);
     if (!__syncthreads_or(in_set ? 1 : 0)) {
       if (threadIdx.x < kEstQ) {
         const int q = static_cast<int>(threadIdx.x);
@@ -2868,6 +2933,66 @@ __global__ void __launch_bounds__(kWG) k_window_partial(const BoxD* __restrict__
     if (threadIdx.x < kEstQ) part[ch * kEstQ + threadIdx.x] = s[threadIdx.x][0];
     __syncthreads();
   }
+}
+
+// phi0 bins holding max-vote boxes: one bit per bin in the event state
+// (chunks as k_est_partial)
+__global__ void __launch_bounds__(kWG) k_phi_occ(const uint16_t* __restrict__ votes, Shape sh,
+                                                 const uint16_t* __restrict__ first_votes, EventState* __restrict__ ev,
+                                                 EvView vw, const int32_t* __restrict__ wg_max, int32_t bx,
+                                                 uint32_t n_part, uint32_t per) {
+  const int e = blockIdx.y;
+  if (ev[e].done || sh.m[1] > kRunMaxBins) return;
+  votes += int64_t(e) * sh.n_boxes;
+  wg_max += int64_t(e) * vw.wg_stride;
+  const int32_t vmax = first_votes[int64_t(e) * vw.k];
+  const uint32_t ch_end = min(n_part, (blockIdx.x + 1) * per);
+  for (uint32_t ch = blockIdx.x * per; ch < ch_end; ++ch) {
+    const uint32_t i = ch * kWG + threadIdx.x;
+    if (i < sh.n_boxes && wg_max[i / static_cast<uint32_t>(bx)] >= vmax && votes[i] == vmax) {
+      const uint32_t k = phi_bin(sh, i);
+      atomicOr(&ev[e].occ[k >> 5], 1u << (k & 31u));
+    }
+  }
+}
+
+// The run of occupied phi0 bins holding the first max-vote box's bin (one
+// thread per event; circular when the level's grid spans a full turn); the
+// bit mask is cleared for the next level.
+__global__ void k_phi_run(const BoxD* __restrict__ parents, Shape sh, const int64_t* __restrict__ first_index,
+                          EventState* __restrict__ ev, EvView vw) {
+  const int e = blockIdx.y;
+  if (threadIdx.x != 0 || ev[e].done) return;
+  EventState& es = ev[e];
+  es.run_a = -1;
+  es.run_b = -1;
+  const int32_t m1 = static_cast<int32_t>(sh.m[1]);
+  if (sh.m[1] <= kRunMaxBins) {
+    const BoxD& G = parents[e * vw.par_stride];
+    const bool circ = G.hi[1] - G.lo[1] >= kTwoPi;
+    auto occ = [&](int32_t k) { return (es.occ[k >> 5] >> (k & 31)) & 1u; };
+    const int32_t kf = static_cast<int32_t>(phi_bin(sh, static_cast<uint32_t>(first_index[int64_t(e) * vw.k])));
+    int32_t a = kf, b = kf, n = 1;
+    while (n < m1) {
+      int32_t k = b + 1;
+      if (k == m1) { if (!circ) break; k = 0; }
+      if (!occ(k)) break;
+      b = k;
+      ++n;
+    }
+    while (n < m1) {
+      int32_t k = a - 1;
+      if (k < 0) { if (!circ) break; k = m1 - 1; }
+      if (!occ(k)) break;
+      a = k;
+      ++n;
+    }
+    if (n < m1) {
+      es.run_a = a;
+      es.run_b = b;
+    }
+  }
+  for (int w = 0; w < 32; ++w) es.occ[w] = 0u;
 }
 
 struct Bins5 { int32_t m[5]; };

@@ -69,6 +69,7 @@ struct ia_ctx {
   float slack32 = ia::ru32(1e-6);  // band widening of ia_vote_level at FP32
   int32_t vf_forward = 0;         // ia_vote_level: forward-hit test
   double vf_xr = 0.0, vf_yr = 0.0;  // ia_vote_level: reference point
+  double vf_disk = 0.0;           // ia_vote_level: disk condition radius
   // pinned staging ring for the chunk-relative hit offsets copied to the
   // device; a slot is rewritten only after its previous copy has completed
   int32_t* pinned = nullptr;
@@ -501,6 +502,7 @@ bool sched_shapes(const ia_schedule* sc, SchedShapes* S) {
 
 ia_status check_sched(ia_ctx* c, const ia_schedule* sc) {
   if (sc->n_refine < 0 || sc->n_refine >= IA_MAX_LEVELS) return fail(c, IA_ERR_INVALID, "n_refine %d", sc->n_refine);
+  if (!(sc->disk >= 0.0) || !std::isfinite(sc->disk)) return fail(c, IA_ERR_INVALID, "disk %g", sc->disk);
   if (sc->mode != IA_SCHED_TOPK && sc->mode != IA_SCHED_WINDOW) return fail(c, IA_ERR_INVALID, "mode %d", sc->mode);
   if (sc->forward != 0 && sc->forward != 1) return fail(c, IA_ERR_INVALID, "forward %d", sc->forward);
   if (sc->mode == IA_SCHED_WINDOW) {
@@ -557,7 +559,7 @@ ia_status run_window(ia_ctx* c, const double* hits, ia::EvView vw, int32_t E, in
     vw.par_stride = 0;
     for (int32_t lev = 0; lev <= sc->n_refine; ++lev) {
       const bool f32 = sc->prec[lev] == IA_FP32;
-      vw.fwd = sc->forward && (sc->move_level < 0 || lev <= sc->move_level) ? 1 : 0;
+      vw.fwd = sc->forward;     // per event: hits ahead about the origin, origin behind after a move
       const bool use_pf = lev > 0 && use_filter(c) && c->parent_filter;
       if (use_pf) {
         const int64_t n_pairs = int64_t(sh.n_parents) * std::max(1, cmax);
@@ -593,10 +595,14 @@ ia_status run_window(ia_ctx* c, const double* hits, ia::EvView vw, int32_t E, in
       const int32_t n_part = est_parts(sh.n_boxes);
       const uint32_t eper = est_per(n_part, E);
       const dim3 gpart((n_part + eper - 1) / eper, E);
+      // one track at a time: the phi0 run of the first max-vote box
+      hipLaunchKernelGGL(ia::k_phi_occ, gpart, dim3(ia::kWG), 0, s, votes, sh, sel_v, ev, vw, wg_max, bx,
+                         static_cast<uint32_t>(n_part), eper);
+      hipLaunchKernelGGL(ia::k_phi_run, dim3(1, E), dim3(64), 0, s, par, sh, sel_idx, ev, vw);
       hipLaunchKernelGGL(ia::k_est_partial, gpart, dim3(ia::kWG), 0, s, par, sh, votes, sel, sel_v, part, vw, ev,
-                         wg_max, bx, static_cast<uint32_t>(n_part), eper);
+                         wg_max, bx, static_cast<uint32_t>(n_part), eper, 1);
       if (lev == sc->n_refine) {
-        const int32_t fwd_hf = sc->forward && (sc->move_level < 0 || sc->n_refine <= sc->move_level) ? 1 : 0;
+        const int32_t fwd_hf = sc->forward;   // applied while the event's frame is the origin's
         hipLaunchKernelGGL(ia::k_est_final, dim3(1, E), dim3(ia::kWG), 0, s, part, n_part, sel, sel_v,
                            static_cast<ia::EstimateOut*>(nullptr), ev, recs, vw, sc->hitfind_scale, assigned, out,
                            n_out, fwd_hf);
@@ -697,6 +703,7 @@ ia_status run_chunk(ia_ctx* c, const double* hits_chunk, const int32_t* h_off_ch
   const int32_t pg = std::max(1, (cmax + 2 + 255) / 256);
   hipLaunchKernelGGL(ia::k_prep, dim3(pg, E), dim3(256), 0, s, hits, nullptr, vw, recs, hist, lbh, tlb, tn2,
                      &ps->status, &ps->n_bad, ev, n_out, range, rb, assigned, 0.0, 0.0);
+  vw.disk = sc->disk;
   if (sc->mode == IA_SCHED_WINDOW)
     return run_window(c, hits, vw, E, cmax, S, sc, slack32, may_overflow, L, recs, votes, hist, selA, range, sel_idx,
                       sel_v, ev, part, flags, pflags, pe, tlb, tn2, lbh, wg_max, live, rin, assigned, out, n_out, s);
@@ -763,7 +770,7 @@ ia_status run_chunk(ia_ctx* c, const double* hits_chunk, const int32_t* h_off_ch
     const int32_t n_part = est_parts(sh.n_boxes);
     const uint32_t eper = est_per(n_part, E);
     hipLaunchKernelGGL(ia::k_est_partial, dim3((n_part + eper - 1) / eper, E), dim3(ia::kWG), 0, s, par, sh, votes,
-                       sel, sel_v, part, vw, ev, wg_max, last_bx, static_cast<uint32_t>(n_part), eper);
+                       sel, sel_v, part, vw, ev, wg_max, last_bx, static_cast<uint32_t>(n_part), eper, 0);
     hipLaunchKernelGGL(ia::k_est_final, dim3(1, E), dim3(ia::kWG), 0, s, part, n_part, sel, sel_v,
                        static_cast<ia::EstimateOut*>(nullptr), ev, recs, vw, sc->hitfind_scale, assigned, out, n_out,
                        sc->forward);
@@ -952,10 +959,12 @@ ia_status ia_ctx_profile_read(ia_ctx* c, int64_t* n_launches, double* total_ms, 
   return st;
 }
 
-ia_status ia_ctx_set_vote_frame(ia_ctx* c, int32_t forward, double xr, double yr) {
+ia_status ia_ctx_set_vote_frame(ia_ctx* c, int32_t forward, double xr, double yr, double disk) {
   if (!c) return IA_ERR_INVALID;
-  if (forward != 0 && forward != 1) return fail(c, IA_ERR_INVALID, "forward %d", forward);
+  if (forward < 0 || forward > 2) return fail(c, IA_ERR_INVALID, "forward %d", forward);
   if (!std::isfinite(xr) || !std::isfinite(yr)) return fail(c, IA_ERR_INVALID, "reference point not finite");
+  if (!(disk >= 0.0) || !std::isfinite(disk)) return fail(c, IA_ERR_INVALID, "disk %g", disk);
+  c->vf_disk = disk;
   c->vf_forward = forward;
   c->vf_xr = xr;
   c->vf_yr = yr;
@@ -1012,6 +1021,9 @@ ia_status ia_vote_level(ia_ctx* c, const ia_hit* d_hits, int32_t n_hits, const u
   vw.flag_stride = 0;
   vw.tri_stride = 0;
   vw.fwd = c->vf_forward;
+  vw.disk = c->vf_disk;
+  vw.vref[0] = c->vf_xr;
+  vw.vref[1] = c->vf_yr;
   const BoxD* par = reinterpret_cast<const BoxD*>(d_parents);
   const bool f32 = prec == IA_FP32;
   const uint32_t fill_n = static_cast<uint32_t>(std::min<int64_t>(n_tr, 0x7fffffff));
@@ -1093,7 +1105,7 @@ ia_status ia_estimate(ia_ctx* c, const ia_box* d_parents, int32_t n_parents, con
   vw.part_stride = n_part * ia::kEstQ;
   const uint32_t eper = est_per(n_part, 1);
   hipLaunchKernelGGL(ia::k_est_partial, dim3((n_part + eper - 1) / eper, 1), dim3(ia::kWG), 0, s, par, sh, d_votes,
-                     first, first_v, part, vw, nullptr, nullptr, 1, static_cast<uint32_t>(n_part), eper);
+                     first, first_v, part, vw, nullptr, nullptr, 1, static_cast<uint32_t>(n_part), eper, 0);
   hipLaunchKernelGGL(ia::k_est_final, dim3(1, 1), dim3(ia::kWG), 0, s, part, n_part, first, first_v,
                      reinterpret_cast<ia::EstimateOut*>(d_out), nullptr, nullptr, vw, 0.0, nullptr, nullptr, nullptr,
                      0);

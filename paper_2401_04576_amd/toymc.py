@@ -492,10 +492,12 @@ TOPK_KW = dict(bins=[16] * 5, n_refine=4, top_k=32, split=[4] * 5)
 # the window schedule (Sec. 3.3 re-gridding from all max-vote boxes): level 0
 # the 16^5 grid over the range, level 1 a 16^5 window, then the reference
 # point moves to the hit closest to the recovered circle and six 12^5
-# windows follow; the forward-hit test applies before the move, and each
-# level votes with the hits the previous level's hit finding selected
+# windows follow; the forward-hit test applies before the move, each level
+# votes with the hits the previous level's hit finding selected, and every
+# level keeps to circles passing within 5 mm of the origin (Eq. ApoVoteDisk)
 WINDOW_LBINS = [[16] * 5, [16] * 5] + [[12] * 5] * 6
-WINDOW_KW = dict(bins=[16] * 5, n_refine=7, mode=1, forward=True, move_level=1, lbins=WINDOW_LBINS, hitsel=True)
+WINDOW_KW = dict(bins=[16] * 5, n_refine=7, mode=1, forward=True, move_level=1, lbins=WINDOW_LBINS, hitsel=True,
+                 disk=5e-3)
 # the recovery tolerances on (d0, phi0, kappa, z0, tanl)
 RECOVERY_TOL = (1e-3, 5e-3, 0.01, 10e-3, 0.02)
 

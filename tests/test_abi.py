@@ -43,7 +43,7 @@ def _c_layout(tmp_path):
     src = tmp_path / "layout.c"
     fields = {"ia_schedule": ["range", "bins", "n_refine", "top_k", "split", "v_min", "n_helix_max",
                               "hitfind_scale", "prec", "fp32_slack", "mode", "forward", "move_level", "wdrop", "hitsel",
-                              "lbins"],
+                              "lbins", "disk"],
               "ia_helix": ["p", "err", "ref", "votes", "n_assigned", "n_argmax", "status"],
               "ia_estimate_t": ["p", "err", "vmax", "n_argmax"]}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "ia.h"', "int main(void) {"]

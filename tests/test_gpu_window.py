@@ -104,13 +104,14 @@ def test_window_small_grids_batch_edges(ctx):
         _compare(ctx, events, kw, max_out=3)
 
 
-@pytest.mark.parametrize("move_level,wdrop,hitsel", [(-1, 0, 0), (0, 2, 1), (2, 1, 1), (-1, 1, 1)])
-def test_window_move_levels(ctx, move_level, wdrop, hitsel):
+@pytest.mark.parametrize("move_level,wdrop,hitsel,disk", [(-1, 0, 0, 0.0), (0, 2, 1, 5e-3), (2, 1, 1, 0.0),
+                                                         (-1, 1, 1, 5e-3)])
+def test_window_move_levels(ctx, move_level, wdrop, hitsel, disk):
     """No move, a move after level 0, a move late: forward-test levels and
     frames follow the schedule."""
     events = [toymc.config_event(2, 3), toymc.config_event(3, 4)]
     kw = _kw(bins=[8] * 5, n_refine=3, move_level=move_level, lbins=[[8] * 5, [8] * 5, [7] * 5, [7] * 5],
-             wdrop=wdrop, hitsel=hitsel)
+             wdrop=wdrop, hitsel=hitsel, disk=disk)
     _compare(ctx, events, kw, max_out=1)
 
 
@@ -123,19 +124,24 @@ def test_window_mixed_precision(ctx):
 def test_topk_forward_matches_oracle(ctx):
     """The forward-hit test in the top-k schedule."""
     events = [toymc.config_event(2, i) for i in (2, 3)]
-    kw = dict(bins=[8] * 5, n_refine=2, top_k=16, split=[2] * 5, forward=True)
-    _compare(ctx, events, kw, max_out=1)
+    for disk in (0.0, 5e-3):
+        kw = dict(bins=[8] * 5, n_refine=2, top_k=16, split=[2] * 5, forward=True, disk=disk)
+        _compare(ctx, events, kw, max_out=1)
 
 
-@pytest.mark.parametrize("forward,ref", [(True, (0.0, 0.0)), (False, (0.31, -0.42)), (True, (-0.2, 0.45))])
-def test_vote_level_frame_matches_oracle(ctx, forward, ref):
-    """ia_vote_level with the forward test and a moved reference point."""
+@pytest.mark.parametrize("forward,ref,disk", [(1, (0.0, 0.0), 0.0), (0, (0.31, -0.42), 0.0),
+                                              (1, (-0.2, 0.45), 0.0), (0, (0.31, -0.42), 5e-3),
+                                              (1, (0.0, 0.0), 2e-3), (2, (0.31, -0.42), 5e-3),
+                                              (2, (-0.2, 0.45), 0.0)])
+def test_vote_level_frame_matches_oracle(ctx, forward, ref, disk):
+    """ia_vote_level with the forward test, a moved reference point and the
+    disk condition."""
     torch = _torch()
     ev = toymc.config_event(2, 4)
     lo, hi = H.LO.copy(), H.HI.copy()
     lo[0], hi[0] = -0.05, 0.05
     root = oracle.make_box(lo, hi)
-    ctx.set_vote_frame(forward, ref)
+    ctx.set_vote_frame(forward, ref, disk)
     try:
         b = np.atleast_1d(root)
         par = torch.from_numpy(np.concatenate([b["lo"], b["hi"]], axis=1).astype(np.float64)).to("cuda:0")
@@ -144,7 +150,7 @@ def test_vote_level_frame_matches_oracle(ctx, forward, ref):
         got = v.cpu().numpy().astype(np.uint16)
     finally:
         ctx.set_vote_frame(False, (0.0, 0.0))
-    want = oracle.vote_level(ev.hits, root, [12] * 5, forward=forward, ref=ref)
+    want = oracle.vote_level(ev.hits, root, [12] * 5, forward=forward, ref=ref, disk=disk)
     assert np.array_equal(got, want)
 
 
