@@ -299,7 +299,7 @@ size_t ia_ctx_scratch_needed(const ia_schedule *sched, int32_t max_hits);
  * Scratch: 112 bytes per hit, and n_parents * prod(split[0..2]) * (n_hits + 8)
  * bytes of (triple, hit) classes and per-triple bounds (IA_ERR_NOMEM when the
  * context's scratch cannot hold them); n_parents * prod(split[0..2]) * n_hits
- * below 2^32 (IA_ERR_OVERFLOW). */
+ * below 2^31 (IA_ERR_OVERFLOW). */
 ia_status ia_vote_level(ia_ctx *ctx, const ia_hit *d_hits, int32_t n_hits, const uint8_t *d_active,
                         const ia_box *d_parents, int32_t n_parents, const int32_t split[5],
                         ia_precision prec, uint16_t *d_votes, void *stream);

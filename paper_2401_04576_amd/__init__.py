@@ -383,6 +383,9 @@ def find_helices(ctx, hits, offsets, sched, max_per_event=16, want_assigned=True
     _check_dev(hits, torch.float64, "hits", ctx.device)
     off = np.ascontiguousarray(np.asarray(offsets, dtype=np.int32))
     n_events = off.shape[0] - 1
+    # the C ABI takes no hit count: the offsets must stay inside `hits`
+    if n_events < 0 or (n_events > 0 and (off[0] < 0 or off[-1] > hits.shape[0] or np.any(np.diff(off) < 0))):
+        raise IAError(1, "offsets must be non-decreasing within [0, hits.shape[0]]")
     dev = hits.device
     if out is None:
         out = torch.zeros(max(1, n_events * max_per_event) * HELIX_DTYPE.itemsize, dtype=torch.uint8, device=dev)

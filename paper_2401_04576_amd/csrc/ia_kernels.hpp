@@ -274,8 +274,10 @@ IA_HD bool behind_ok(const Iv& Fi, double xr, double yr) {
 // finite for kappa -> 0; the direction turns by
 // atan2(kappa u.D, 1 + kappa d0 - kappa n.D) over the arc s between the two
 // points of closest approach (s = u.D for kappa = 0), and z0' = z0 + tanl s.
-IA_HD void frame_shift(const double* p, double dx, double dy, double* q) {
-  const double d0 = p[0], f0 = p[1], k = p[2], z0 = p[3], l = p[4];
+// the transverse part: d0', phi0' and the arc between the two points of
+// closest approach
+IA_HD void frame_shift_t(double d0, double f0, double k, double dx, double dy, double* d1, double* f1o,
+                         double* arc_o) {
   const double s0 = sin_p(f0), c0 = cos_p(f0);
   const double nD = -s0 * dx + c0 * dy;
   const double uD = c0 * dx + s0 * dy;
@@ -288,11 +290,17 @@ IA_HD void frame_shift(const double* p, double dx, double dy, double* q) {
   if (f1 < 0.0) f1 += kTwoPi;
   double arc = uD;
   if (k != 0.0) arc = atan2_p(k * uD, one - k * nD) / k;
-  q[0] = num / (A + 1.0);
-  q[1] = f1;
-  q[2] = k;
-  q[3] = z0 + l * arc;
-  q[4] = l;
+  *d1 = num / (A + 1.0);
+  *f1o = f1;
+  *arc_o = arc;
+}
+
+IA_HD void frame_shift(const double* p, double dx, double dy, double* q) {
+  double arc;
+  frame_shift_t(p[0], p[1], p[2], dx, dy, &q[0], &q[1], &arc);
+  q[2] = p[2];
+  q[3] = p[3] + p[4] * arc;
+  q[4] = p[4];
 }
 
 // The disk condition (Eq. ApoVoteDisk): some circle of the triple passes
@@ -2843,9 +2851,9 @@ IA_HD void box_corner(const BoxD& b, int c, double* x) {
   for (int j = 0; j < 5; ++j) x[j] = ((c >> j) & 1) ? b.hi[j] : b.lo[j];
 }
 
-// Extent of the boxes within `drop` votes of the maximum, in aligned 256-box
-// chunks as k_est_partial (minima at q = 5..9, maxima at q = 10..14 of each
-// chunk's record).  When the event's reference point moves (move_now and
+// Extent of the boxes within `drop` votes of the maximum, over the aligned
+// 256-box chunks of k_est_partial's launch shape, one record per workgroup
+// (minima at q = 5..9, maxima at q = 10..14).  When the event's reference point moves (move_now and
 // `moving`): the hull of their 32 corners taken to the new reference point,
 // phi0 unwrapped into half a turn of the first max-vote box's first corner;
 // otherwise the union of the boxes, phi0 shifted by a turn where the box
@@ -2869,8 +2877,9 @@ __global__ void __launch_bounds__(kWG) k_window_partial(const BoxD* __restrict__
   first_box += int64_t(e) * vw.k;
   first_votes += int64_t(e) * vw.k;
   part += int64_t(e) * vw.part_stride;
-  __shared__ double s[kEstQ][kWG];
+  __shared__ double sw[kWG / 64][10];
   const int32_t vlo = max(static_cast<int32_t>(first_votes[0]) - drop, 0);
+  const int32_t ra = ev[e].run_a, rb = ev[e].run_b;
   const double dx = ev[e].shift[0], dy = ev[e].shift[1];
   double cref = 0.5 * (first_box->lo[1] + first_box->hi[1]);
   if (mv) {
@@ -2879,59 +2888,77 @@ __global__ void __launch_bounds__(kWG) k_window_partial(const BoxD* __restrict__
     frame_shift(x, dx, dy, q);
     cref = q[1];
   }
+  // the window is one parent box: the child widths once (child_edge's values)
+  const BoxD P = parents[0];
+  double w[5];
+  for (int j = 0; j < 5; ++j) w[j] = (P.hi[j] - P.lo[j]) / static_cast<double>(sh.m[j]);
+  const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
+  // each lane keeps running extrema over the workgroup's chunks; one
+  // reduction at the end writes the workgroup's record part[blockIdx.x]
+  double vl[5], vh[5];
+  for (int j = 0; j < 5; ++j) { vl[j] = INFINITY; vh[j] = -INFINITY; }
   const uint32_t ch_end = min(n_part, (blockIdx.x + 1) * per);
   for (uint32_t ch = blockIdx.x * per; ch < ch_end; ++ch) {
     const uint32_t i = ch * kWG + threadIdx.x;
-    double v[kEstQ];
-    for (int q = 0; q < 5; ++q) { v[q] = 0.0; v[5 + q] = INFINITY; v[10 + q] = -INFINITY; }
-    v[15] = 0.0;
     const bool in_set = i < sh.n_boxes && (!wg_max || wg_max[i / static_cast<uint32_t>(bx)] >= vlo) &&
-                        votes[i] >= vlo && in_run(phi_bin(sh, i), ev[e].run_a, ev[e].run_b);
-    if (!__syncthreads_or(in_set ? 1 : 0)) {
-      if (threadIdx.x < kEstQ) {
-        const int q = static_cast<int>(threadIdx.x);
-        part[ch * kEstQ + q] = (q >= 5 && q < 10) ? INFINITY : ((q >= 10 && q < 15) ? -INFINITY : 0.0);
-      }
-      continue;
-    }
-    if (in_set && !mv) {
-      BoxD box;
-      level_box(parents, sh, i, &box);
+                        votes[i] >= vlo && in_run(phi_bin(sh, i), ra, rb);
+    if (in_set) {
+      uint32_t k[5];
+      child_index(sh.m, i % sh.nc, k);
+      double lo[5], hi[5];
       for (int j = 0; j < 5; ++j) {
-        double lo = box.lo[j], hi = box.hi[j];
-        if (j == 1) {
-          const double dv = 0.5 * (lo + hi) - cref;
-          double shift = 0.0;
-          if (dv > kPi) shift = -kTwoPi;
-          else if (dv <= -kPi) shift = kTwoPi;
-          lo = lo + shift;
-          hi = hi + shift;
+        lo[j] = P.lo[j] + static_cast<double>(k[j]) * w[j];
+        hi[j] = (k[j] + 1 == sh.m[j]) ? P.hi[j] : P.lo[j] + static_cast<double>(k[j] + 1) * w[j];
+      }
+      if (!mv) {
+        const double dv = 0.5 * (lo[1] + hi[1]) - cref;
+        double shift = 0.0;
+        if (dv > kPi) shift = -kTwoPi;
+        else if (dv <= -kPi) shift = kTwoPi;
+        lo[1] = lo[1] + shift;
+        hi[1] = hi[1] + shift;
+        for (int j = 0; j < 5; ++j) { vl[j] = fmin(vl[j], lo[j]); vh[j] = fmax(vh[j], hi[j]); }
+      } else {
+        // the 32 corners: the transverse part of each of the 8 (d0, phi0,
+        // kappa) corners once, then z0 + tanl x arc for its 4 (z0, tanl) corners
+        for (int c = 0; c < 8; ++c) {
+          const double d0 = (c & 1) ? hi[0] : lo[0], f0 = (c & 2) ? hi[1] : lo[1], kk = (c & 4) ? hi[2] : lo[2];
+          double d1, f1, arc;
+          frame_shift_t(d0, f0, kk, dx, dy, &d1, &f1, &arc);
+          const double dv = f1 - cref;
+          if (dv > kPi) f1 -= kTwoPi;
+          else if (dv <= -kPi) f1 += kTwoPi;
+          vl[0] = fmin(vl[0], d1); vh[0] = fmax(vh[0], d1);
+          vl[1] = fmin(vl[1], f1); vh[1] = fmax(vh[1], f1);
+          vl[2] = fmin(vl[2], kk); vh[2] = fmax(vh[2], kk);
+          for (int zc = 0; zc < 4; ++zc) {
+            const double z1 = ((zc & 1) ? hi[3] : lo[3]) + ((zc & 2) ? hi[4] : lo[4]) * arc;
+            vl[3] = fmin(vl[3], z1); vh[3] = fmax(vh[3], z1);
+          }
         }
-        v[5 + j] = lo;
-        v[10 + j] = hi;
+        vl[4] = fmin(vl[4], lo[4]);
+        vh[4] = fmax(vh[4], hi[4]);
       }
     }
-    if (in_set && mv) {
-      BoxD box;
-      level_box(parents, sh, i, &box);
-      for (int c = 0; c < 32; ++c) {
-        double x[5], q[5];
-        box_corner(box, c, x);
-        frame_shift(x, dx, dy, q);
-        const double dv = q[1] - cref;
-        if (dv > kPi) q[1] -= kTwoPi;
-        else if (dv <= -kPi) q[1] += kTwoPi;
-        for (int j = 0; j < 5; ++j) {
-          v[5 + j] = fmin(v[5 + j], q[j]);
-          v[10 + j] = fmax(v[10 + j], q[j]);
-        }
-      }
+  }
+  // minima and maxima: across the wave with shuffles, then across waves
+  for (int j = 0; j < 5; ++j)
+    for (int o = 32; o > 0; o >>= 1) {
+      vl[j] = fmin(vl[j], __shfl_xor(vl[j], o, 64));
+      vh[j] = fmax(vh[j], __shfl_xor(vh[j], o, 64));
     }
-    for (int q = 0; q < kEstQ; ++q) s[q][threadIdx.x] = v[q];
-    __syncthreads();
-    for (int w = kWG; w > 1; w >>= 1) tree_step(s, w);
-    if (threadIdx.x < kEstQ) part[ch * kEstQ + threadIdx.x] = s[threadIdx.x][0];
-    __syncthreads();
+  if (lane == 0)
+    for (int j = 0; j < 5; ++j) { sw[wave][j] = vl[j]; sw[wave][5 + j] = vh[j]; }
+  __syncthreads();
+  if (threadIdx.x < kEstQ) {
+    const int q = static_cast<int>(threadIdx.x);
+    double r = 0.0;
+    if (q >= 5 && q < 15) {
+      const int j = q - 5;
+      r = sw[0][j];
+      for (int wv = 1; wv < kWG / 64; ++wv) r = j < 5 ? fmin(r, sw[wv][j]) : fmax(r, sw[wv][j]);
+    }
+    part[blockIdx.x * kEstQ + q] = r;
   }
 }
 
@@ -2945,15 +2972,26 @@ __global__ void __launch_bounds__(kWG) k_phi_occ(const uint16_t* __restrict__ vo
   if (ev[e].done || sh.m[1] > kRunMaxBins) return;
   votes += int64_t(e) * sh.n_boxes;
   wg_max += int64_t(e) * vw.wg_stride;
+  __shared__ uint32_t socc[kRunMaxBins / 32];
+  if (threadIdx.x < kRunMaxBins / 32) socc[threadIdx.x] = 0u;
+  __syncthreads();
   const int32_t vmax = first_votes[int64_t(e) * vw.k];
   const uint32_t ch_end = min(n_part, (blockIdx.x + 1) * per);
   for (uint32_t ch = blockIdx.x * per; ch < ch_end; ++ch) {
     const uint32_t i = ch * kWG + threadIdx.x;
-    if (i < sh.n_boxes && wg_max[i / static_cast<uint32_t>(bx)] >= vmax && votes[i] == vmax) {
-      const uint32_t k = phi_bin(sh, i);
-      atomicOr(&ev[e].occ[k >> 5], 1u << (k & 31u));
+    const bool at = i < sh.n_boxes && wg_max[i / static_cast<uint32_t>(bx)] >= vmax && votes[i] == vmax;
+    const int32_t key = at ? static_cast<int32_t>(phi_bin(sh, i)) : -1;
+    // consecutive boxes mostly share a phi0 bin: one lane sets the wave's
+    // first bin for every lane holding it, the other lanes set their own
+    const unsigned long long m = __ballot(at);
+    if (m) {
+      const int32_t k0 = __shfl(key, __ffsll(static_cast<long long>(m)) - 1, 64);
+      if (key >= 0 && (key != k0 || static_cast<int32_t>(threadIdx.x & 63u) == __ffsll(static_cast<long long>(m)) - 1))
+        atomicOr(&socc[key >> 5], 1u << (key & 31));
     }
   }
+  __syncthreads();
+  if (threadIdx.x < kRunMaxBins / 32 && socc[threadIdx.x]) atomicOr(&ev[e].occ[threadIdx.x], socc[threadIdx.x]);
 }
 
 // The run of occupied phi0 bins holding the first max-vote box's bin (one

@@ -243,7 +243,8 @@ ia_status launch_classify(ia_ctx* c, const HitRec* recs, const ia::EvView& vw, i
   // the pairs left to the enclosure passes, compacted per chunk of flags:
   // the largest chunk that still gives about 2048 workgroups
   const int64_t n_pairs = int64_t(n_tr) * std::max(0, max_hits);
-  if (n_pairs >= (int64_t(1) << 32)) return fail(c, IA_ERR_OVERFLOW, "level exceeds 2^32 (triple, hit) pairs");
+  // pair indices and the per-event record counts and offsets are 32-bit
+  if (n_pairs >= (int64_t(1) << 31)) return fail(c, IA_ERR_OVERFLOW, "level has 2^31 or more (triple, hit) pairs");
   if (filt && n_pairs > 0) {
     int32_t per = ia::kDeferPer;
     while (per > 1 && (n_pairs * std::max(1, n_ev)) / (int64_t(per) * ia::kWG) < 2048) per /= 2;
@@ -622,8 +623,9 @@ ia_status run_window(ia_ctx* c, const double* hits, ia::EvView vw, int32_t E, in
                          wg_max, bx, static_cast<uint32_t>(n_part), eper, sc->wdrop, mv ? 1 : 0);
       ia::Bins5 nb;
       for (int j = 0; j < 5; ++j) nb.m[j] = sc->lbins[lev + 1][j];
-      hipLaunchKernelGGL(ia::k_window, dim3(1, E), dim3(ia::kWG), 0, s, part, n_part, par, sh, win, ev, vw, rb, nb,
-                         mv ? 1 : 0);
+      // k_window_partial wrote one extent record per workgroup
+      hipLaunchKernelGGL(ia::k_window, dim3(1, E), dim3(ia::kWG), 0, s, part, static_cast<int32_t>(gpart.x), par, sh,
+                         win, ev, vw, rb, nb, mv ? 1 : 0);
       if (mv) hipLaunchKernelGGL(ia::k_reframe, dim3(pg, E), dim3(ia::kWG), 0, s, hits, vw, recs, ev, 0);
       IA_HIP(c, hipGetLastError());
       if (!make_shape(sc->lbins[lev + 1], 1, &sh)) return fail(c, IA_ERR_OVERFLOW, "level %d too large", lev + 1);
@@ -1160,6 +1162,13 @@ ia_status ia_find_helices(ia_ctx* c, const ia_hit* d_hits, const int32_t* h_off,
     if (chunk_for(kRecCap, &chunk_cap) && (!fits_worst || chunk_cap > chunk)) {
       rpe = kRecCap;
       chunk = chunk_cap;
+      // as many records per event as the arena holds at that chunk size
+      // (fewer events fall back to the in-kernel staging)
+      for (int64_t r = 2 * kRecCap; r < worst_rec; r *= 2) {
+        int32_t ch2 = 0;
+        if (!chunk_for(r, &ch2) || ch2 < chunk) break;
+        rpe = r;
+      }
     }
   }
   if (chunk == 0) {
@@ -1271,6 +1280,14 @@ ia_status ia_find_helices_dev(ia_ctx* c, const ia_hit* d_hits, const int32_t* d_
   if (L.total > c->arena_bytes && kRecCap < worst_rec) {
     rpe = kRecCap;
     layout_find(S.max_boxes, S.max_triples, sched_k(sc), max_hits, n_events, n_hits_total, &L, rpe);
+    // as many records per event as the arena holds
+    for (int64_t r = 2 * kRecCap; r < worst_rec; r *= 2) {
+      FindLayout L2;
+      layout_find(S.max_boxes, S.max_triples, sched_k(sc), max_hits, n_events, n_hits_total, &L2, r);
+      if (L2.total > c->arena_bytes) break;
+      rpe = r;
+      L = L2;
+    }
   }
   if (L.total > c->arena_bytes)
     return fail(c, IA_ERR_NOMEM, "scratch too small: need %zu bytes, have %zu", L.total, c->arena_bytes);

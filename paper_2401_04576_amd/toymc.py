@@ -494,12 +494,15 @@ TOPK_KW = dict(bins=[16] * 5, n_refine=4, top_k=32, split=[4] * 5)
 # point moves to the hit closest to the recovered circle and six 12^5
 # windows follow; the forward-hit test applies before the move, each level
 # votes with the hits the previous level's hit finding selected, and every
-# level keeps to circles passing within 5 mm of the origin (Eq. ApoVoteDisk)
+# level keeps to circles passing within 5 mm of the origin (Eq. ApoVoteDisk);
+# windows cover the boxes within one vote of the maximum
 WINDOW_LBINS = [[16] * 5, [16] * 5] + [[12] * 5] * 6
 WINDOW_KW = dict(bins=[16] * 5, n_refine=7, mode=1, forward=True, move_level=1, lbins=WINDOW_LBINS, hitsel=True,
-                 disk=5e-3)
+                 disk=5e-3, wdrop=1)
 # the recovery tolerances on (d0, phi0, kappa, z0, tanl)
 RECOVERY_TOL = (1e-3, 5e-3, 0.01, 10e-3, 0.02)
+# the transverse part of them alone (z0 and tanl free)
+TRANSVERSE_TOL = (1e-3, 5e-3, 0.01, np.inf, np.inf)
 
 
 def match_helices(found, truth, tol=RECOVERY_TOL):
