@@ -167,7 +167,8 @@ typedef struct ia_ctx ia_ctx;
 ia_status ia_ctx_create(ia_ctx **out, int32_t device, size_t scratch_bytes);
 void ia_ctx_destroy(ia_ctx *ctx);
 
-/* Message of the last host-side error on this context ("" if none). */
+/* Message of the last host-side error on this context ("" if none); with
+ * ctx NULL, of this thread's last ia_vote_level_noalloc call. */
 const char *ia_last_error(const ia_ctx *ctx);
 
 /* Device-detected conditions since the last clear: flags bit 0 = malformed
@@ -303,6 +304,30 @@ size_t ia_ctx_scratch_needed(const ia_schedule *sched, int32_t max_hits);
 ia_status ia_vote_level(ia_ctx *ctx, const ia_hit *d_hits, int32_t n_hits, const uint8_t *d_active,
                         const ia_box *d_parents, int32_t n_parents, const int32_t split[5],
                         ia_precision prec, uint16_t *d_votes, void *stream);
+
+/* For callers that cannot allocate device memory -- code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc: the same
+ * level as ia_vote_level, without a context.  Its scratch (hit records,
+ * (triple, hit) classes, per-triple bounds, status words) is a fixed array of
+ * IA_NOALLOC_SCRATCH_BYTES in the library's device code, one per device,
+ * held until the process ends; the call allocates nothing and makes no
+ * hipMalloc / hipFree.  Arguments as ia_vote_level; the context settings take
+ * their defaults (classification proofs on, automatic vote tile, no vote
+ * frame, FP32 slack 1e-6 m).
+ *  - IA_ERR_NOMEM when the level needs more scratch than the array holds:
+ *    n_hits x 112 bytes + n_parents x prod(split[0..2]) x (n_hits + 8) bytes
+ *    + about 17 KiB must not exceed IA_NOALLOC_SCRATCH_BYTES.
+ *  - Calls on one device share its array: calls that overlap on one GPU
+ *    (several streams, several threads) race and must be serialised by the
+ *    caller.  Each call clears what must start at zero.
+ *  - Malformed hits never vote; their count is not reported (there is no
+ *    context to hold it).
+ *  - Host-side errors: ia_last_error(NULL) returns this thread's last
+ *    message. */
+#define IA_NOALLOC_SCRATCH_BYTES (64u << 20)
+ia_status ia_vote_level_noalloc(const ia_hit *d_hits, int32_t n_hits, const uint8_t *d_active,
+                                const ia_box *d_parents, int32_t n_parents, const int32_t split[5],
+                                ia_precision prec, uint16_t *d_votes, void *stream);
 
 /* Selection of the max-vote boxes of a level (Sec. 3.3): the first
  * min(top_k, n_boxes) boxes by (votes desc, box index asc), in that order.

@@ -147,6 +147,8 @@ def load():
     L.ia_ctx_scratch_needed.argtypes = [C.POINTER(Schedule), i32]
     L.ia_vote_level.restype = i32
     L.ia_vote_level.argtypes = [P, P, i32, P, P, i32, C.POINTER(i32), i32, P, P]
+    L.ia_vote_level_noalloc.restype = i32
+    L.ia_vote_level_noalloc.argtypes = [P, i32, P, P, i32, C.POINTER(i32), i32, P, P]
     L.ia_refine.restype = i32
     L.ia_refine.argtypes = [P, P, i32, C.POINTER(i32), P, i32, i32, P, P, P, P]
     L.ia_estimate.restype = i32
@@ -337,6 +339,33 @@ def vote_level(ctx, hits, parents, split, votes=None, active=None, prec=FP64, st
     ctx._check(ctx._L.ia_vote_level(ctx._h, _ptr(hits), int(hits.shape[0]), _ptr(active), _ptr(parents),
                                     int(parents.shape[0]), _split(split), int(prec), _ptr(votes),
                                     _stream_handle(stream)))
+    return votes
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20
+
+
+def vote_level_noalloc(hits, parents, split, votes, active=None, prec=FP64, stream=None):
+    """vote_level without a context: the library's scratch is a fixed device
+    array and the call allocates nothing (`votes` is the caller's).  Calls
+    that overlap on one GPU race."""
+    torch = _torch()
+    dev = hits.device.index or 0
+    _check_dev(hits, torch.float64, "hits", dev)
+    _check_dev(parents, torch.float64, "parents", dev)
+    _check_dev(votes, torch.uint16, "votes", dev)
+    nb = parents.shape[0] * int(np.prod([int(s) for s in split]))
+    if votes.numel() < nb:
+        raise IAError(1, "votes too small")
+    if active is not None:
+        _check_dev(active, torch.uint8, "active", dev)
+    L = load()
+    with torch.cuda.device(dev):   # the library uses the current device's array
+        st = L.ia_vote_level_noalloc(_ptr(hits), int(hits.shape[0]), _ptr(active), _ptr(parents),
+                                     int(parents.shape[0]), _split(split), int(prec), _ptr(votes),
+                                     _stream_handle(stream))
+    if st != 0:
+        raise IAError(st, L.ia_last_error(None).decode())
     return votes
 
 

@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <mutex>
 #include <utility>
 #include <vector>
 
@@ -43,6 +44,9 @@ constexpr int64_t kMaxEstimateBoxes = int64_t(ia::kWG) << (ia::kEstLevels - 1);
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
+// messages of ia_vote_level_noalloc (it has no context), per thread
+thread_local char g_noalloc_err[512] = "";
+
 struct Persistent {        // fixed region at the start of the arena
   uint32_t status;
   uint32_t done_counter;
@@ -55,6 +59,7 @@ struct Persistent {        // fixed region at the start of the arena
 
 struct ia_ctx {
   int32_t device = 0;
+  char* errbuf = nullptr;         // when set, error messages go here (no heap use)
   char* arena = nullptr;
   size_t arena_bytes = 0;
   size_t used = 0;
@@ -90,7 +95,8 @@ ia_status fail(ia_ctx* c, ia_status st, const char* fmt, ...) {
   va_start(ap, fmt);
   vsnprintf(buf, sizeof buf, fmt, ap);
   va_end(ap);
-  if (c) c->err = buf;
+  if (c && c->errbuf) std::snprintf(c->errbuf, 512, "%s", buf);
+  else if (c) c->err = buf;
   return st;
 }
 
@@ -828,7 +834,7 @@ void ia_ctx_destroy(ia_ctx* c) {
   delete c;
 }
 
-const char* ia_last_error(const ia_ctx* c) { return c ? c->err.c_str() : "null context"; }
+const char* ia_last_error(const ia_ctx* c) { return c ? c->err.c_str() : g_noalloc_err; }
 
 ia_status ia_ctx_status(ia_ctx* c, uint32_t* flags, int64_t* n_bad) {
   if (!c) return IA_ERR_INVALID;
@@ -989,18 +995,34 @@ size_t ia_ctx_scratch_needed(const ia_schedule* sc, int32_t max_hits) {
   return L.total;
 }
 
-ia_status ia_vote_level(ia_ctx* c, const ia_hit* d_hits, int32_t n_hits, const uint8_t* d_active,
-                        const ia_box* d_parents, int32_t n_parents, const int32_t split[5],
-                        ia_precision prec, uint16_t* d_votes, void* stream) {
-  if (!c) return IA_ERR_INVALID;
+}  // extern "C"
+
+namespace {
+
+// argument checks shared by ia_vote_level and ia_vote_level_noalloc
+ia_status vote_level_args(ia_ctx* c, const ia_hit* d_hits, int32_t n_hits, const ia_box* d_parents,
+                          int32_t n_parents, const int32_t split[5], ia_precision prec, const uint16_t* d_votes,
+                          Shape* sh) {
   if (n_hits < 0 || n_hits > kMaxHits) return fail(c, IA_ERR_INVALID, "n_hits %d outside [0, %d]", n_hits, kMaxHits);
   if (n_hits > 0 && !d_hits) return fail(c, IA_ERR_INVALID, "d_hits is NULL");
   if (!d_parents || !split || !d_votes) return fail(c, IA_ERR_INVALID, "null pointer argument");
   if (n_parents < 1) return fail(c, IA_ERR_INVALID, "n_parents %d < 1", n_parents);
   if (prec != IA_FP64 && prec != IA_FP32) return fail(c, IA_ERR_INVALID, "precision %d unknown", int(prec));
-  Shape sh;
-  if (!make_shape(split, n_parents, &sh)) return fail(c, IA_ERR_OVERFLOW, "level exceeds 2^31 - 1 boxes");
-  IA_HIP(c, hipSetDevice(c->device));
+  if (!make_shape(split, n_parents, sh)) return fail(c, IA_ERR_OVERFLOW, "level exceeds 2^31 - 1 boxes");
+  return IA_OK;
+}
+
+// scratch bytes of one ia_vote_level call: hit records, pair classes, bounds
+size_t vote_level_bytes(const Shape& sh, int32_t n_hits) {
+  const int64_t n_tr = int64_t(sh.n_parents) * sh.m012;
+  return align_up(sizeof(Persistent)) + align_up(sizeof(HitRec) * size_t(std::max(1, n_hits)) + 1) +
+         align_up(size_t(std::max<int64_t>(1, n_tr * int64_t(n_hits))) + 1) + 2 * align_up(4 * size_t(n_tr) + 1);
+}
+
+// one level's votes with the context's arena as scratch
+ia_status vote_level_run(ia_ctx* c, const ia_hit* d_hits, int32_t n_hits, const uint8_t* d_active,
+                         const ia_box* d_parents, const Shape& sh, ia_precision prec, uint16_t* d_votes,
+                         void* stream) {
   reset_bump(c);
   HitRec* recs = bump<HitRec>(c, size_t(std::max(1, n_hits)));
   if (!recs) return fail(c, IA_ERR_NOMEM, "scratch too small for %d hits", n_hits);
@@ -1038,6 +1060,85 @@ ia_status ia_vote_level(ia_ctx* c, const ia_hit* d_hits, int32_t n_hits, const u
   if (cs != IA_OK) return cs;
   const VoteIn in{flags, tlb, tn2, nullptr, 0};
   return launch_vote(c, recs, vw, 1, par, sh, d_votes, nullptr, nullptr, in, nullptr, s, f32, c->slack32);
+}
+
+}  // namespace
+
+extern "C" {
+
+ia_status ia_vote_level(ia_ctx* c, const ia_hit* d_hits, int32_t n_hits, const uint8_t* d_active,
+                        const ia_box* d_parents, int32_t n_parents, const int32_t split[5],
+                        ia_precision prec, uint16_t* d_votes, void* stream) {
+  if (!c) return IA_ERR_INVALID;
+  Shape sh;
+  const ia_status a = vote_level_args(c, d_hits, n_hits, d_parents, n_parents, split, prec, d_votes, &sh);
+  if (a != IA_OK) return a;
+  IA_HIP(c, hipSetDevice(c->device));
+  return vote_level_run(c, d_hits, n_hits, d_active, d_parents, sh, prec, d_votes, stream);
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Scratch of ia_vote_level_noalloc: a fixed array in every device's code
+// object, held until the process ends.  Host code uses only the address
+// hipGetSymbolAddress returns for the current device, never the array's name.
+static __device__ __align__(256) char scratch[IA_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 256;
+std::mutex g_scratch_mu;
+char* g_scratch_at[kMaxDevices] = {};
+// this device's copy of `scratch`, looked up once per device (with that
+// device current); nullptr when the lookup fails
+char* scratch_on(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_at[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return nullptr;
+    g_scratch_at[dev] = static_cast<char*>(p);
+  }
+  return g_scratch_at[dev];
+}
+
+}  // namespace
+
+extern "C" {
+
+ia_status ia_vote_level_noalloc(const ia_hit* d_hits, int32_t n_hits, const uint8_t* d_active,
+                                const ia_box* d_parents, int32_t n_parents, const int32_t split[5],
+                                ia_precision prec, uint16_t* d_votes, void* stream) {
+  // a context on the stack: default settings, the static array as its arena,
+  // messages into a per-thread buffer (nothing is allocated)
+  ia_ctx c;
+  c.errbuf = g_noalloc_err;
+  g_noalloc_err[0] = '\0';
+  Shape sh;
+  const ia_status a = vote_level_args(&c, d_hits, n_hits, d_parents, n_parents, split, prec, d_votes, &sh);
+  if (a != IA_OK) return a;
+  const size_t need = vote_level_bytes(sh, n_hits);
+  if (need > size_t(IA_NOALLOC_SCRATCH_BYTES))
+    return fail(&c, IA_ERR_NOMEM, "the level needs %zu bytes of scratch, above the %zu bytes of the fixed array",
+                need, size_t(IA_NOALLOC_SCRATCH_BYTES));
+  if (int64_t(sh.n_parents) * sh.m012 * int64_t(n_hits) >= (int64_t(1) << 31))
+    return fail(&c, IA_ERR_OVERFLOW, "level has 2^31 or more (triple, hit) pairs");
+  int dev = 0;
+  IA_HIP(&c, hipGetDevice(&dev));
+  char* base = scratch_on(dev);
+  if (!base) return fail(&c, IA_ERR_DEVICE, "hipGetSymbolAddress of the scratch array failed on device %d", dev);
+  c.device = dev;
+  c.arena = base;
+  c.arena_bytes = IA_NOALLOC_SCRATCH_BYTES;
+  // the status words at the start of the array start at zero (a fill kernel,
+  // so that the call can be captured in a graph)
+  hipStream_t s = as_stream(stream);
+  const uint32_t n_words = static_cast<uint32_t>(align_up(sizeof(Persistent)) / 4);
+  hipLaunchKernelGGL(ia::k_fill_u32, dim3((n_words + 255) / 256), dim3(256), 0, s,
+                     reinterpret_cast<uint32_t*>(base), n_words, 0u);
+  IA_HIP(&c, hipGetLastError());
+  return vote_level_run(&c, d_hits, n_hits, d_active, d_parents, sh, prec, d_votes, stream);
 }
 
 ia_status ia_refine(ia_ctx* c, const ia_box* d_parents, int32_t n_parents, const int32_t split[5],
