@@ -31,7 +31,7 @@ SCHED_DTYPE = np.dtype([("range", BOX_DTYPE), ("bins", "i4", (5,)), ("n_refine",
                         ("fp32_slack", "f8"), ("mode", "i4"), ("forward", "i4"),
                         ("move_level", "i4"), ("wdrop", "i4"), ("hitsel", "i4"),
                         ("lbins", "i4", (8, 5)), ("disk", "f8")], align=True)
-FP64, FP32 = 0, 1
+FP64, FP32, FP64X = 0, 1, 2   # FP64X: FP64 with the exact Phi of Eq. CSAXtoPHI_a
 TOPK, WINDOW = 0, 1
 HELIX_DTYPE = np.dtype([("p", "f8", (5,)), ("err", "f8", (5,)), ("ref", "f8", (2,)), ("votes", "i4"),
                         ("n_assigned", "i4"), ("n_argmax", "i4"), ("pad", "i4")])
@@ -79,7 +79,9 @@ def lib():
         L.or_prep_hit.restype = i32; L.or_prep_hit.argtypes = [_P, _P]
         L.or_box_child.restype = None; L.or_box_child.argtypes = [_P, _P, i64, _P]
         L.or_stereo_e.restype = i32; L.or_stereo_e.argtypes = [_P, _P, i32, _P, _P]
+        L.or_stereo_e_x.restype = i32; L.or_stereo_e_x.argtypes = [_P, _P, i32, i32, _P, _P]
         L.or_pair_vote.restype = i32; L.or_pair_vote.argtypes = [_P, _P, _P]
+        L.or_pair_vote_x.restype = i32; L.or_pair_vote_x.argtypes = [_P, _P, i32, _P]
         L.or_vote_level.restype = None
         L.or_vote_level.argtypes = [_P, i32, _P, _P, i32, _P, _P, i32]
         L.or_vote_level_prec.restype = None
@@ -202,12 +204,13 @@ def box_child(parent, split, child):
     return out[0]
 
 
-def stereo_e(prep, c, s, debug=False):
+def stereo_e(prep, c, s, debug=False, exact=False):
+    """d^Ax at the point c for drift sign s; exact: Phi from Eq. CSAXtoPHI_a."""
     prep = _c(np.atleast_1d(prep), PREP_DTYPE)
     c = _c(c, np.float64)
     e = np.zeros(1)
     dbg = np.full(24, np.nan) if debug else None
-    ok = lib().or_stereo_e(_ptr(prep), _ptr(c), int(s), _ptr(e), _ptr(dbg))
+    ok = lib().or_stereo_e_x(_ptr(prep), _ptr(c), int(s), 1 if exact else 0, _ptr(e), _ptr(dbg))
     if debug:
         return bool(ok), float(e[0]), dbg
     return bool(ok), float(e[0])
@@ -218,11 +221,11 @@ STEREO_DEBUG_NAMES = ["R", "xc", "yc", "Dx", "Dy", "RAx", "cAx", "sAx", "sinA", 
                       "ctau", "Q", "dhat"]
 
 
-def pair_vote(prep, box, debug=False):
+def pair_vote(prep, box, debug=False, exact=False):
     prep = _c(np.atleast_1d(prep), PREP_DTYPE)
     box = _c(np.atleast_1d(box), BOX_DTYPE)
     dbg = np.full(8, np.nan) if debug else None
-    v = lib().or_pair_vote(_ptr(prep), _ptr(box), _ptr(dbg))
+    v = lib().or_pair_vote_x(_ptr(prep), _ptr(box), 1 if exact else 0, _ptr(dbg))
     return (int(v), dbg) if debug else int(v)
 
 
@@ -327,7 +330,7 @@ def estimate_ex(parents, split, votes, vmax):
 def make_sched(lo, hi, bins, n_refine=4, top_k=32, split=(4, 4, 4, 4, 4), v_min=10,
                n_helix_max=1, hitfind_scale=5.0, prec=None, fp32_slack=1e-6, mode=TOPK, forward=False,
                move_level=-1, lbins=None, wdrop=0, hitsel=False, disk=0.0):
-    """prec: per-level FP64 / FP32 list (default all FP64).  mode WINDOW: level l >= 1 is
+    """prec: per-level FP64 / FP32 / FP64X list (default all FP64).  mode WINDOW: level l >= 1 is
     a grid of lbins[l] over its window; the reference point moves after move_level."""
     s = np.zeros((), dtype=SCHED_DTYPE)
     s["mode"] = mode

@@ -253,7 +253,38 @@ void or_box_child(const or_box *par, const int32_t m[5], int64_t child, or_box *
  * wire to its mirror image; d^Ax is computed there and returned as
  * e = sgn(kappa) d^Ax, the drift term of the kappa-scaled residual.
  * ---------------------------------------------------------------------- */
+/* the quantities of the stereo point for a given Phi - Phi^Ax = eps
+ * (Eqs. normudi, EQSinter_c, c^tau and s^tau of Appendix A) */
+typedef struct { double sinP, cosP, u, delta, sperp, zS, ld, ctau, stau; } st_point;
+
+static st_point stereo_point(double eps, double sinA, double cosA, double lam, double tt, double t2, double dS,
+                             double R, double dphi, double z0, double cAx, double sAx) {
+  st_point q;
+  double se = or_sin(eps), ce = or_cos(eps);
+  q.sinP = sinA * ce + cosA * se;
+  q.cosP = cosA * ce - sinA * se;
+  q.u = sqrt(((1.0 + ((2.0 * lam) * q.sinP) * tt) + (lam * lam) * t2) + (q.cosP * q.cosP) * t2);
+  q.delta = dS / q.u;
+  q.sperp = R * (dphi + eps);                 /* rho s_perp = Phi + phi_s - phi0 */
+  q.zS = (z0 + lam * q.sperp) - (q.delta * q.cosP) * tt;   /* z_i^St (EQSinter_c) */
+  q.ld = lam * q.delta;
+  q.ctau = q.zS * cAx - q.ld * sAx;           /* c_i^tau */
+  q.stau = -(q.ld * cAx + q.zS * sAx);        /* s_i^tau */
+  return q;
+}
+
 int32_t or_stereo_e(const or_prep *h, const double c[5], int32_t s, double *e, double *dbg) {
+  return or_stereo_e_x(h, c, s, 0, e, dbg);
+}
+
+/* exact = 1: Phi solves Eq. CSAXtoPHI_a, Phi = Phi^Ax + atan2(s^tau tan(tau),
+ * (R^Ax)^2 + c^tau tan(tau)), by OR_PHI_ITERS fixed-point steps started from
+ * the second-order solution ApproxPhi (the map contracts by about
+ * |tan(tau) tanl| R / R^Ax per step, and d^Ax is stationary in Phi at the
+ * closest approach, so its error falls as the square of Phi's).  With the
+ * exact Phi the closest approach does not depend on z_ref, which therefore
+ * stays 0. */
+int32_t or_stereo_e_x(const or_prep *h, const double c[5], int32_t s, int32_t exact, double *e, double *dbg) {
   double kap = c[2], sig = 1.0;
   if (kap < 0.0) sig = -1.0;
   if (kap == 0.0) { kap = 0x1p-30; sig = 1.0; }
@@ -287,15 +318,16 @@ int32_t or_stereo_e(const or_prep *h, const double c[5], int32_t s, double *e, d
   double Phi2 = Phi2n / (2.0 * (RAx * RAx));
   double t2 = tt * tt;
   double eps = Phi1 * tt + Phi2 * t2;         /* Phi_i - Phi_i^Ax (ApproxPhi) */
-  double se = or_sin(eps), ce = or_cos(eps);
-  double sinP = sinA * ce + cosA * se, cosP = cosA * ce - sinA * se;
-  /* norm of the drift direction (normudi) */
-  double u = sqrt(((1.0 + ((2.0 * lam) * sinP) * tt) + (lam * lam) * t2) + (cosP * cosP) * t2);
-  double delta = dS / u;
-  double sperp = R * (dphi + eps);            /* rho s_perp = Phi + phi_s - phi0 */
-  double zS = (z0 + lam * sperp) - (delta * cosP) * tt;   /* z_i^St (EQSinter_c) */
-  double ctau = zS * cAx - (lam * delta) * sAx;           /* c_i^tau */
-  double a1 = zS * tt, a2 = (lam * delta) * tt;
+  if (exact) {
+    double RAx2 = RAx * RAx;
+    for (int k = 0; k < OR_PHI_ITERS; k++) {
+      st_point q = stereo_point(eps, sinA, cosA, lam, tt, t2, dS, R, dphi, z0, cAx, sAx);
+      eps = or_atan2(q.stau * tt, RAx2 + q.ctau * tt);
+    }
+  }
+  st_point q = stereo_point(eps, sinA, cosA, lam, tt, t2, dS, R, dphi, z0, cAx, sAx);
+  double sinP = q.sinP, cosP = q.cosP, u = q.u, delta = q.delta, sperp = q.sperp, zS = q.zS, ctau = q.ctau;
+  double a1 = zS * tt, a2 = q.ld * tt;
   double Q = ((2.0 * ctau) * tt + a1 * a1) + a2 * a2;
   double A = R + delta;
   double disc = A * A - Q;
@@ -334,6 +366,10 @@ static iv pair_G(const or_prep *h, const or_box *b) {
 }
 
 int32_t or_pair_vote(const or_prep *h, const or_box *b, double *dbg) {
+  return or_pair_vote_x(h, b, 0, dbg);
+}
+
+int32_t or_pair_vote_x(const or_prep *h, const or_box *b, int32_t exact, double *dbg) {
   if (!h->valid) return 0;
   iv K = {b->lo[2], b->hi[2]};
   iv G = pair_G(h, b);
@@ -344,7 +380,7 @@ int32_t or_pair_vote(const or_prep *h, const or_box *b, double *dbg) {
   for (int32_t si = 0; si < 2; si++) {
     int32_t s = si == 0 ? 1 : -1;
     double e;
-    if (!or_stereo_e(h, c, s, &e, NULL)) continue;
+    if (!or_stereo_e_x(h, c, s, exact, &e, NULL)) continue;
     iv E = {or_wdn(e - h->band), or_wup(e + h->band)};
     iv H = iv_sub(iv_twice(G), iv_add(iv_twice(E), iv_mul(K, iv_sqr(E))));
     if (dbg) { dbg[2 + 2 * si] = H.lo; dbg[3 + 2 * si] = H.hi; dbg[6 + si] = e; }
@@ -659,7 +695,8 @@ static void vote_prepped(const or_prep *pr, const uint8_t *use, int32_t n_hits,
     }
     for (int32_t i = 0; i < n_hits; i++) {
       if (!use[i] || (fwd == 1 && !or_forward(&pr[i], &box))) continue;
-      v += prec == OR_FP32 ? or_pair_vote32(&pr[i], &box, slack, NULL) : or_pair_vote(&pr[i], &box, NULL);
+      v += prec == OR_FP32 ? or_pair_vote32(&pr[i], &box, slack, NULL)
+                           : or_pair_vote_x(&pr[i], &box, prec == OR_FP64X, NULL);
     }
     votes[b] = (uint16_t)v;
   }
@@ -846,11 +883,11 @@ static uint16_t level_max(const uint16_t *votes, int64_t nb, int64_t *first) {
 }
 
 static void hit_finding(const or_prep *pr, uint8_t *act, int32_t n_hits, const or_box *E, int32_t fwd,
-                        int32_t *assigned, int32_t k, int32_t *na) {
+                        int32_t exact, int32_t *assigned, int32_t k, int32_t *na) {
   for (int32_t i = 0; i < n_hits; i++) {
     if (!act[i]) continue;
     if (fwd && !or_forward(&pr[i], E)) continue;
-    if (or_pair_vote(&pr[i], E, NULL)) {
+    if (or_pair_vote_x(&pr[i], E, exact, NULL)) {
       act[i] = 0;
       if (assigned) assigned[i] = k;
       (*na)++;
@@ -917,7 +954,7 @@ static int32_t find_topk(const or_hit *hits, int32_t n_hits, const or_sched *sc,
       E.hi[j] = hx.p[j] + w;
     }
     int32_t na = 0;
-    hit_finding(pr, act, n_hits, &E, sc->forward, assigned, nh, &na);
+    hit_finding(pr, act, n_hits, &E, sc->forward, sc->prec[sc->n_refine] == OR_FP64X, assigned, nh, &na);
     hx.n_assigned = na;
     out[nh++] = hx;
     if (na == 0) break;
@@ -1039,7 +1076,8 @@ static int32_t find_window(const or_hit *hits, int32_t n_hits, const or_sched *s
           E.hi[j] = p[j] + w;
         }
         for (int32_t i = 0; i < n_hits; i++)
-          sel[i] = (uint8_t)(act[i] && (fwd != 1 || or_forward(&pr[i], &E)) && or_pair_vote(&pr[i], &E, NULL));
+          sel[i] = (uint8_t)(act[i] && (fwd != 1 || or_forward(&pr[i], &E)) &&
+                             or_pair_vote_x(&pr[i], &E, sc->prec[lev] == OR_FP64X, NULL));
       }
       or_box nx;
       int32_t did_move = 0;
@@ -1149,7 +1187,7 @@ static int32_t find_window(const or_hit *hits, int32_t n_hits, const or_sched *s
     }
     int32_t fwd = sc->forward && !moved;
     int32_t na = 0;
-    hit_finding(pr, act, n_hits, &E, fwd, assigned, nh, &na);
+    hit_finding(pr, act, n_hits, &E, fwd, sc->prec[sc->n_refine] == OR_FP64X, assigned, nh, &na);
     if (moved) or_frame_shift(p, -ref[0], -ref[1], hx.p);
     else memcpy(hx.p, p, sizeof hx.p);
     for (int j = 0; j < 5; j++) hx.err[j] = err[j];

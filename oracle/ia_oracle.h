@@ -42,7 +42,10 @@ typedef struct {
 } or_prep;
 
 #define OR_MAX_LEVELS 8
-enum { OR_FP64 = 0, OR_FP32 = 1 };
+/* per-level arithmetic: FP64 with the second-order Phi of Eq. ApproxPhi,
+ * FP32 (see the source), FP64 with the exact Phi of Eq. CSAXtoPHI_a */
+enum { OR_FP64 = 0, OR_FP32 = 1, OR_FP64X = 2 };
+#define OR_PHI_ITERS 3   /* fixed-point steps of Eq. CSAXtoPHI_a at OR_FP64X */
 enum { OR_TOPK = 0, OR_WINDOW = 1 };
 
 typedef struct {
@@ -111,11 +114,16 @@ void or_box_child(const or_box *parent, const int32_t split[5], int64_t child, o
  * Eq. defdiAX_b has a negative argument.  dbg (nullable, 24 doubles) receives
  * intermediates: see the source. */
 int32_t or_stereo_e(const or_prep *h, const double c[5], int32_t s, double *e, double *dbg);
+/* the same with exact = 1: Phi from Eq. CSAXtoPHI_a (OR_PHI_ITERS fixed-point
+ * steps from ApproxPhi) instead of ApproxPhi */
+int32_t or_stereo_e_x(const or_prep *h, const double c[5], int32_t s, int32_t exact, double *e, double *dbg);
 
 /* Eq. ApoVote for one (box, hit): returns 1 when zero lies in the enclosure for
  * either drift sign.  dbg (nullable, 8 doubles): G lo/hi, H+ lo/hi, H- lo/hi,
  * e+, e-. */
 int32_t or_pair_vote(const or_prep *h, const or_box *b, double *dbg);
+/* the same with d^Ax from or_stereo_e_x(.., exact, ..) */
+int32_t or_pair_vote_x(const or_prep *h, const or_box *b, int32_t exact, double *dbg);
 
 /* Forward-hit test: 1 when the hit point lies ahead of the point of closest
  * approach (x cos phi0 + y sin phi0 > 0) for some phi0 of the box, 0 when it
