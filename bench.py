@@ -84,14 +84,19 @@ FLOP_BOX_STEREO32 = 278
 FLOP_CLS_G, FLOP_CLS_AXIAL, FLOP_CLS_PAIRQ, FLOP_CLS_ENCL, FLOP_CLS_INCL, FLOP_CLS_MAG = 157, 92, 69, 688, 94, 113
 FLOP_CLS_FRAME, FLOP_CLS_GOUT, FLOP_CLS_PAIRMAG = 130, 68, 34
 PEAK_FP64_TFLOPS = 78.6   # MI355X vector FP64: 256 CU x 128 FLOP/clk x 2.4 GHz
-# HBM bytes per launch of the default workload's dominant kernel over
-# 1024-event batches: rocprofv3 --pmc FETCH_SIZE, then WRITE_SIZE, averaged
-# over those launches and scaled by what the two counters read for a copy of
-# 1 GiB (bench.py --workload copy).  Valid only for the kernel sources they
-# were measured on (SHA-256 of ia_math.hpp + ia_kernels.hpp).
-TRAFFIC = {"kernel": "k_classify_defer (fp64 levels)", "workload": "event", "events_per_step": 1024,
-           "sources_sha256": "b71e90aa972d0f39e8b5aa40b03c17f09fe31e6d06823c121b96720562441c58",
-           "fetch_bytes": 73465642, "write_bytes": 107593903}
+# Counter record of the default workload's dominant kernel (k_vote_rec over a
+# batch of 4,096 config-4 events, all 40 levels of the five passes), from
+# rocprofv3 --pmc runs of `bench.py --steps 1 --warmup 1 --no-autotune
+# --no-cpu-baseline` (profiles/vote_rec_batch4096_window_fp64.md), averaged
+# over the launches of the full search runs: HBM bytes (FETCH_SIZE x 2.0 and
+# WRITE_SIZE x 1.0, the factors that make the counters read 1 GiB for a
+# 1 GiB copy) and wave-level FP64 VALU instruction counts.  Valid only for
+# the kernel sources they were measured on (SHA-256 of ia_math.hpp +
+# ia_kernels.hpp).
+TRAFFIC = {"kernel": "k_vote (fp64 levels)", "workload": "batch", "events_per_step": 4096,
+           "sources_sha256": "83cf245a8eb9e9b5fc795278c3b1a412169a21d974cb0f454e21e0f885d6c3a7",
+           "fetch_bytes": 6222643200, "write_bytes": 1158963200,
+           "valu_f64": {"add": 6.4907e9, "mul": 7.4484e9, "fma": 8.9735e9, "trans": 8.3431e8}, "valu": 3.5279e10}
 PEAK_FP32_TFLOPS = 157.3  # MI355X vector FP32 (non-packed)
 
 
@@ -113,14 +118,17 @@ def kernel_sources_sha256():
 
 
 def measured_traffic(workload, events_per_step):
-    """(kernel, measured HBM bytes per launch), or None when the workload or
-    the kernel sources differ from those of the measurement."""
+    """(kernel, measured HBM bytes per launch, executed FP64 flops per launch,
+    VALU instructions per launch), or None when the workload or the kernel
+    sources differ from those of the measurement."""
     t = TRAFFIC
     if workload != t["workload"] or events_per_step != t["events_per_step"]:
         return None
     if kernel_sources_sha256() != t["sources_sha256"]:
         return None
-    return t["kernel"], t["fetch_bytes"] + t["write_bytes"]
+    v = t["valu_f64"]
+    flops = 64 * (v["add"] + v["mul"] + 2 * v["fma"] + v["trans"])
+    return t["kernel"], t["fetch_bytes"] + t["write_bytes"], flops, t["valu"]
 
 
 def classify_flops(cw):
@@ -169,15 +177,25 @@ def roofline(kprof, work, cwork, wall, measured_on, traffic=None):
                     "launches": n, "total_ms": ms, **cwork[p]}
     dom = max(parts, key=lambda k: parts[k]["total_ms"])
     d = parts[dom]
+    executed = None
     if traffic and traffic[0] == dom:
-        traffic, note = traffic[1], "measured on these kernel sources"
+        _, traffic, fl, valu = traffic
+        note = "measured on these kernel sources"
+        # the counters' executed FP64 flops (64 lanes per wave instruction, an
+        # FMA counts 2) and VALU issue over this run's average launch
+        sec = d["avg_launch_ms"] * 1e-3
+        executed = {"fp64_tflops": fl / sec / 1e12, "frac": fl / sec / 1e12 / PEAK_FP64_TFLOPS,
+                    "valu_issue_frac": valu / sec / (256 * 2.4e9),
+                    "note": "rocprofv3 SQ_INSTS_VALU_{ADD,MUL,FMA,TRANS}_F64 and SQ_INSTS_VALU per launch "
+                            "(same sources) over this run's average launch; issue peak 1 wave instruction "
+                            "per CU per clock, 256 CU x 2.4 GHz"}
     else:
         traffic = None
         note = ("no counter record for this kernel on these kernel sources and this workload "
                 f"(the last one covers {TRAFFIC['kernel']} on sources {TRAFFIC['sources_sha256'][:12]})")
     return {"bound": "alu", "achieved": d["achieved"], "peak": d["peak"], "unit": "TFLOP/s", "frac": d["frac"],
             "traffic": traffic, "traffic_unit": "bytes per launch (HBM, rocprofv3 FETCH_SIZE + WRITE_SIZE, scaled)",
-            "traffic_note": note,
+            "traffic_note": note, "executed": executed,
             "kernel": dom, "avg_launch_ms": d["avg_launch_ms"], "launches": d["launches"],
             "share_of_wall": d["total_ms"] * 1e-3 / wall, "measured_on": measured_on,
             "by_kernel": parts}

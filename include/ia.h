@@ -23,6 +23,8 @@
  * lexicographic (d0 slowest, tanl fastest).  Child edges along a dimension
  * with range [L, U] and m parts are L + k (U - L)/m, and the last edge is U.
  * A level-0 grid is the case n_parents = 1, parent = the search range.
+ * There is no call that lists a level's boxes: every kernel computes a box
+ * from (parent, child index) with this formula.
  *
  * Conventions shared by every entry point:
  *  - Pointers named d_* are device memory owned by the caller; the library
@@ -59,7 +61,14 @@ typedef enum {
   IA_ERR_OVERFLOW = 5      /* a size does not fit the index types */
 } ia_status;
 
-typedef enum { IA_FP64 = 0, IA_FP32 = 1 } ia_precision;
+/* Arithmetic of a level.  IA_FP64: d^Ax with the second-order Phi of Eq.
+ * ApproxPhi (Appendix A), the paper's form.  IA_FP32: see ia_vote_level.
+ * IA_FP64X: FP64 with the exact Phi, the solution of Eq. CSAXtoPHI_a by
+ * three fixed-point steps from ApproxPhi; the closest approach is then
+ * independent of z_ref, which stays 0.  At IA_FP64X levels the (triple, hit)
+ * class proofs (which enclose the ApproxPhi form) are off: every stereo pair
+ * is evaluated box by box. */
+typedef enum { IA_FP64 = 0, IA_FP32 = 1, IA_FP64X = 2 } ia_precision;
 
 /* one hit: wire end points (z0 != z1), measured drift radius >= 0 and the
  * tolerance half-width added on both sides of the drift (0 = exact) */
@@ -135,7 +144,8 @@ typedef struct {
   int32_t v_min;          /* stop when the level-0 max vote is below this */
   int32_t n_helix_max;    /* helices searched per event (greedy, hits removed) */
   double hitfind_scale;   /* hit-finding box = estimate +- scale x error (5 in Sec. 3.3) */
-  int32_t prec[IA_MAX_LEVELS];  /* arithmetic per level (IA_FP64 or IA_FP32) */
+  int32_t prec[IA_MAX_LEVELS];  /* arithmetic per level (IA_FP64, IA_FP32 or IA_FP64X); the
+                                 * hit finding and hit selection use the estimating level's */
   double fp32_slack;      /* band widening at FP32 levels, m, in [0, 1e-3]; it must
                            * bound the FP32 error of d^Ax (1e-6 is 100x the largest
                            * error seen on the chamber geometry) */
@@ -205,6 +215,8 @@ enum { IA_KERNEL_VOTE = 0, IA_KERNEL_CLASSIFY = 1, IA_KERNEL_CLASSIFY_DEFER = 2 
 
 /* Every bracketed launch: n_launches[2 k + p] and total_ms[2 k + p] for
  * kernel k (IA_KERNEL_*) at precision p (0 FP64 levels, 1 FP32 levels).
+ * A level's vote counts once: the fallback vote of events whose staged
+ * records did not fit is timed together with the record vote before it.
  * Synchronises on the recorded events and clears the record (as
  * ia_ctx_profile_read, which returns the vote kernel's entries of it).
  * Both arrays are host memory of 6 entries; IA_ERR_INVALID if either is
@@ -294,7 +306,8 @@ size_t ia_ctx_scratch_needed(const ia_schedule *sched, int32_t max_hits);
  *   split     host int32[5], each >= 1
  *   prec      IA_FP64, or IA_FP32: the stereo term of each (box, hit) pair in
  *             FP32 and an FP32 interval test with the band widened by the
- *             context's slack; its votes contain the IA_FP64 votes
+ *             context's slack; its votes contain the IA_FP64 votes; or
+ *             IA_FP64X: FP64 with the exact Phi of Eq. CSAXtoPHI_a
  *   d_votes   n_parents * prod(split) uint16, written: number of active,
  *             well-formed hits voting for each box
  * Scratch: 112 bytes per hit, and n_parents * prod(split[0..2]) * (n_hits + 8)
@@ -331,6 +344,9 @@ ia_status ia_vote_level_noalloc(const ia_hit *d_hits, int32_t n_hits, const uint
 
 /* Selection of the max-vote boxes of a level (Sec. 3.3): the first
  * min(top_k, n_boxes) boxes by (votes desc, box index asc), in that order.
+ * It returns the selected boxes themselves (the next level's parents), not
+ * their children: ia_vote_level splits parents itself, so children are never
+ * stored.
  *   d_votes           n_boxes = n_parents * prod(split) votes, each <= vote_bound
  *   d_selected        written: the selected boxes' extents (next level's parents)
  *   d_selected_index  written: their box indices (int64)
@@ -349,12 +365,17 @@ ia_status ia_estimate(ia_ctx *ctx, const ia_box *d_parents, int32_t n_parents, c
 
 /* The whole search (Sec. 3.3) for n_events events.  Event e owns hits
  * [h_hit_offsets[e], h_hit_offsets[e+1]) of d_hits (host array of
- * n_events + 1 offsets, non-decreasing, each event <= 65535 hits).  Per
+ * n_events + 1 offsets, non-decreasing, each event <= 65535 hits; the
+ * offsets are on the host because the call sizes the batch's per-event
+ * slices from them -- ia_find_helices_dev takes them on the device).  Per
  * helix pass: vote the level-0 grid; stop if its max vote is below v_min;
- * n_refine times select top_k boxes and vote their children; estimate from
+ * n_refine times build the next level (IA_SCHED_WINDOW: one grid over the
+ * window of the selected boxes, the reference point moved after move_level;
+ * IA_SCHED_TOPK: the children of the top_k boxes) and vote it; estimate from
  * the max-vote boxes; assign every still-active hit voting for the box
  * estimate +- hitfind_scale x error; stop when none is assigned or
- * n_helix_max / max_per_event helices are found.
+ * n_helix_max / max_per_event helices are found.  Helices carry no truth
+ * flags: the library never sees generated truth.
  *   d_out      n_events * max_per_event helices (event-major)
  *   d_n_out    n_events counts
  *   d_assigned NULL or one int32 per hit: helix index within its event, -1 if none */

@@ -412,8 +412,14 @@ IA_HD PairQ pair_quantities(const Frame& f, const HitRec& h, Iv G) {
   return q;
 }
 
+// fixed-point steps of Eq. CSAXtoPHI_a at IA_FP64X levels
+constexpr int kPhiIters = 3;
+
 // stereo vote of one hit for one box centre (z0, lam); ApproxPhi, normudi,
-// EQSinter_c, defdiAX_b evaluated in the same operation order as the oracle
+// EQSinter_c, defdiAX_b evaluated in the same operation order as the oracle.
+// EXACT: Phi - Phi^Ax from kPhiIters fixed-point steps of Eq. CSAXtoPHI_a,
+// eps <- atan2(s^tau tan(tau), (R^Ax)^2 + c^tau tan(tau)), started from ApproxPhi.
+template <bool EXACT = false>
 IA_HD bool stereo_vote(const PairQ& q, double R, double sig, Iv K, double z0,
                                             double lam, double lamR, double lam2, double tt, double t2,
                                             double d, double band) {
@@ -430,6 +436,22 @@ IA_HD bool stereo_vote(const PairQ& q, double R, double sig, Iv K, double z0,
     double Phi2n = lamR * zA - (lzA * (R - 2.0 * dS)) * q.c2 + (zA2 + dS * (q.RAx + lam2 * (q.RpRAx - dS))) * q.s2;
     double Phi2 = Phi2n / q.twoRAx2;
     double eps = Phi1 * tt + Phi2 * t2;
+    if constexpr (EXACT) {
+      const double RAx2 = q.RAx * q.RAx;
+      for (int it = 0; it < kPhiIters; ++it) {
+        double s1, c1;
+        sincos_p(eps, &s1, &c1);
+        const double sP = q.sinA * c1 + q.cosA * s1, cP = q.cosA * c1 - q.sinA * s1;
+        const double uu = sqrt(((1.0 + ((2.0 * lam) * sP) * tt) + lam2 * t2) + (cP * cP) * t2);
+        const double dl = dS / uu;
+        const double sp = R * (q.dphi + eps);
+        const double zz = (z0 + lam * sp) - (dl * cP) * tt;
+        const double l_d = lam * dl;
+        const double ct = zz * q.cAx - l_d * q.sAx;
+        const double st = -(l_d * q.cAx + zz * q.sAx);
+        eps = atan2_p(st * tt, RAx2 + ct * tt);
+      }
+    }
     double se, ce;
     sincos_p(eps, &se, &ce);
     double sinP = q.sinA * ce + q.cosA * se, cosP = q.cosA * ce - q.sinA * se;
@@ -1879,7 +1901,7 @@ __global__ void __launch_bounds__(kWG) k_select_wg(const uint16_t* __restrict__ 
 // below T).  Tiles that are not live are neither written nor counted.
 // With only_unstaged, it votes only the events whose records did not fit
 // (k_vote_rec votes the others).
-template <int BX, bool F32>
+template <int BX, bool F32, bool EXACT = false>
 __global__ void __launch_bounds__(kWG) k_vote(const HitRec* __restrict__ hits, EvView vw,
                                               const BoxD* __restrict__ parents, Shape sh,
                                               uint16_t* __restrict__ votes, uint32_t* __restrict__ hist,
@@ -2019,7 +2041,7 @@ __global__ void __launch_bounds__(kWG) k_vote(const HitRec* __restrict__ hits, E
             q.cAx = sq[8][slot]; q.c2 = sq[9][slot]; q.s2 = sq[10][slot]; q.twoRAx2 = sq[11][slot];
             q.RpRAx = sq[12][slot];
             const double tt = h.tant;
-            if (stereo_vote(q, f.R, f.sig, f.K, z0, lam, lamR, lam2, tt, tt * tt, h.d, h.band)) ++nv;
+            if (stereo_vote<EXACT>(q, f.R, f.sig, f.K, z0, lam, lamR, lam2, tt, tt * tt, h.d, h.band)) ++nv;
           }
         }
       }
@@ -2086,7 +2108,7 @@ __global__ void __launch_bounds__(kWG) k_vote(const HitRec* __restrict__ hits, E
 // (ev->rec_ok); the class-2 pairs of each evaluated triple are its records
 // from k_stage, copied to LDS a chunk at a time, and the triple's frame
 // comes from its TriFrame, so the kernel holds only the per-box arithmetic.
-template <int BX, bool F32>
+template <int BX, bool F32, bool EXACT = false>
 __global__ void __launch_bounds__(kWG, 4) k_vote_rec(EvView vw, const BoxD* __restrict__ parents_all, Shape sh,
                                                   uint16_t* __restrict__ votes_all, uint32_t* __restrict__ hist_all,
                                                   uint32_t* __restrict__ status, const EventState* __restrict__ ev,
@@ -2222,7 +2244,8 @@ __global__ void __launch_bounds__(kWG, 4) k_vote_rec(EvView vw, const BoxD* __re
             q.cAx = sq[8][slot]; q.c2 = sq[9][slot]; q.s2 = sq[10][slot]; q.twoRAx2 = sq[11][slot];
             q.RpRAx = sq[12][slot];
             const double tt = sq[13][slot];
-            if (stereo_vote(q, fr.R, fr.sig, K, z0, lam, lamR, lam2, tt, tt * tt, sq[14][slot], sq[15][slot])) ++nv;
+            if (stereo_vote<EXACT>(q, fr.R, fr.sig, K, z0, lam, lamR, lam2, tt, tt * tt, sq[14][slot], sq[15][slot]))
+              ++nv;
           }
         }
       }
@@ -2573,7 +2596,7 @@ __global__ void __launch_bounds__(kWG) k_est_partial(const BoxD* __restrict__ pa
 }
 
 // hit finding (Sec. 3.3): does an active hit vote for the box estimate +- scale x error
-IA_HD bool pair_vote_box(const BoxD& b, const HitRec& h, bool fwd = false) {
+IA_HD bool pair_vote_box(const BoxD& b, const HitRec& h, bool fwd = false, bool exact = false) {
   if (!h.use) return false;
   Frame f;
   f.Dd = {b.lo[0], b.hi[0]};
@@ -2597,6 +2620,8 @@ IA_HD bool pair_vote_box(const BoxD& b, const HitRec& h, bool fwd = false) {
     return h_contains0(G, f.K, f.sig * h.d, h.band) || h_contains0(G, f.K, f.sig * (-h.d), h.band);
   const PairQ q = pair_quantities(f, h, G);
   const double z0 = 0.5 * (b.lo[3] + b.hi[3]), lam = 0.5 * (b.lo[4] + b.hi[4]);
+  if (exact)
+    return stereo_vote<true>(q, f.R, f.sig, f.K, z0, lam, lam * f.R, lam * lam, h.tant, h.tant * h.tant, h.d, h.band);
   return stereo_vote(q, f.R, f.sig, f.K, z0, lam, lam * f.R, lam * lam, h.tant, h.tant * h.tant, h.d, h.band);
 }
 
@@ -2712,7 +2737,7 @@ __global__ void __launch_bounds__(kWG) k_est_final(const double* __restrict__ pa
   const int32_t k = ev->n_out;
   int32_t mine = 0;
   for (int32_t i = t; i < n_hits; i += kWG) {
-    if (pair_vote_box(E, hits[i], fwd != 0 && !ev->moved)) {
+    if (pair_vote_box(E, hits[i], (fwd & 1) && !ev->moved, (fwd & 2) != 0)) {
       hits[i].use = 0;
       if (assigned) assigned[i] = k;
       ++mine;
@@ -2842,7 +2867,7 @@ __global__ void __launch_bounds__(kWG) k_hit_select(HitRec* __restrict__ hits, E
   for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n_hits; i += stride) {
     HitRec& h = hits[i];
     if (!(h.use & 1)) continue;
-    h.use = pair_vote_box(E, h, fwd != 0 && !ev[e].moved) ? 1 : 3;
+    h.use = pair_vote_box(E, h, (fwd & 1) && !ev[e].moved, (fwd & 2) != 0) ? 1 : 3;
   }
 }
 

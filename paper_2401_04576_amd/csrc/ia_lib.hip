@@ -182,14 +182,15 @@ ia_status launch_select(ia_ctx* c, const uint16_t* votes, const Shape& sh, const
   return IA_OK;
 }
 
-// boxes per workgroup of the vote kernel for a level: large levels use one
-// lane per box; small levels split each chunk's hits over 2 or 4 waves so
-// that the device gets enough workgroups
-int32_t vote_tile(const ia_ctx* c, uint32_t n_boxes) {
+// boxes per workgroup of the vote kernel for a level of n_boxes boxes per
+// event over n_ev events: large levels and large batches use one lane per
+// box; small levels of few events split each chunk's hits over 2 or 4 waves
+// so that the device gets enough workgroups
+int32_t vote_tile(const ia_ctx* c, uint32_t n_boxes, int32_t n_ev) {
   if (c->tile_override) return c->tile_override;
   for (const auto& t : c->tuned)
     if (t.first == n_boxes) return t.second;
-  if (n_boxes >= (1u << 19)) return 256;
+  if (n_boxes >= (1u << 19) || uint64_t(n_boxes) * uint64_t(std::max(n_ev, 1)) >= (uint64_t(1) << 22)) return 256;
   return 128;
 }
 
@@ -211,14 +212,16 @@ ia::EvView single_view(int32_t n_hits) {
 ia_status launch_classify(ia_ctx* c, const HitRec* recs, const ia::EvView& vw, int32_t n_ev, int32_t max_hits,
                           const BoxD* par, const Shape& sh, uint8_t* flags, int32_t* tlb, int32_t* tn2,
                           const EventState* ev, hipStream_t s, bool f32, float slack32,
-                          const uint8_t* pflags = nullptr, const ia::ParentE* pe = nullptr) {
+                          const uint8_t* pflags = nullptr, const ia::ParentE* pe = nullptr, bool exact = false) {
   const uint32_t n_tr = sh.n_parents * sh.m012;
   const uint32_t gx = (n_tr + 63) / 64;
   const int64_t base = int64_t(gx) * std::max(1, n_ev);
   const int32_t max_groups = std::max(1, (max_hits + ia::kWG / 64 - 1) / (ia::kWG / 64));
   const int32_t hg = static_cast<int32_t>(std::min<int64_t>(std::max<int64_t>(1, 2048 / base), std::min(max_groups, 64)));
   const dim3 g(gx, n_ev, hg);
-  const int32_t filt = use_filter(c);
+  // the class proofs enclose the ApproxPhi form of d^Ax: with the exact Phi
+  // every stereo pair is evaluated box by box
+  const int32_t filt = exact ? 0 : use_filter(c);
   unsigned long long* wk = persistent(c)->work;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (c->profiling) {
@@ -293,21 +296,21 @@ struct VoteIn {                   // per-level inputs of the vote kernel
   int32_t only_unstaged;          // vote only events whose records did not fit
 };
 
-template <bool F32>
+template <bool F32, bool EX>
 void launch_vote_tile(int32_t bx, dim3 g, hipStream_t s, const HitRec* recs, const ia::EvView& vw, const BoxD* par,
                       const Shape& sh, uint16_t* votes, uint32_t* hist, uint32_t* st, const EventState* ev,
                       const VoteIn& in, int32_t* wg_max, unsigned long long* wk, float slack32) {
   switch (bx) {
     case 256:
-      hipLaunchKernelGGL((ia::k_vote<256, F32>), g, dim3(ia::kWG), 0, s, recs, vw, par, sh, votes, hist, st, ev,
+      hipLaunchKernelGGL((ia::k_vote<256, F32, EX>), g, dim3(ia::kWG), 0, s, recs, vw, par, sh, votes, hist, st, ev,
                          in.flags, in.tlb, in.tn2, in.live_list, wg_max, wk, slack32, in.only_unstaged);
       break;
     case 128:
-      hipLaunchKernelGGL((ia::k_vote<128, F32>), g, dim3(ia::kWG), 0, s, recs, vw, par, sh, votes, hist, st, ev,
+      hipLaunchKernelGGL((ia::k_vote<128, F32, EX>), g, dim3(ia::kWG), 0, s, recs, vw, par, sh, votes, hist, st, ev,
                          in.flags, in.tlb, in.tn2, in.live_list, wg_max, wk, slack32, in.only_unstaged);
       break;
     default:
-      hipLaunchKernelGGL((ia::k_vote<64, F32>), g, dim3(ia::kWG), 0, s, recs, vw, par, sh, votes, hist, st, ev,
+      hipLaunchKernelGGL((ia::k_vote<64, F32, EX>), g, dim3(ia::kWG), 0, s, recs, vw, par, sh, votes, hist, st, ev,
                          in.flags, in.tlb, in.tn2, in.live_list, wg_max, wk, slack32, in.only_unstaged);
       break;
   }
@@ -315,8 +318,9 @@ void launch_vote_tile(int32_t bx, dim3 g, hipStream_t s, const HitRec* recs, con
 
 ia_status launch_vote(ia_ctx* c, const HitRec* recs, const ia::EvView& vw, int32_t n_ev, const BoxD* par,
                       const Shape& sh, uint16_t* votes, uint32_t* hist, const EventState* ev, const VoteIn& in,
-                      int32_t* wg_max, hipStream_t s, bool f32, float slack32, int32_t* tile_used = nullptr) {
-  const int32_t bx = vote_tile(c, sh.n_boxes);
+                      int32_t* wg_max, hipStream_t s, bool f32, float slack32, int32_t* tile_used = nullptr,
+                      bool exact = false) {
+  const int32_t bx = vote_tile(c, sh.n_boxes, n_ev);
   // workgroups stride over the tiles: with a live list, about kVoteGroups in
   // all (most tiles of a pruned level are not live); otherwise one per tile
   // up to a cap
@@ -325,20 +329,31 @@ ia_status launch_vote(ia_ctx* c, const HitRec* recs, const ia::EvView& vw, int32
   if (in.live_list)
     grid = std::max<uint32_t>(1, std::min<uint32_t>(n_tiles, (kVoteGroups + n_ev - 1) / std::max(1, n_ev)));
   if (tile_used) *tile_used = bx;
+  // the fallback for events whose records did not fit (in.only_unstaged)
+  // extends the level's vote mark instead of adding a launch of its own, so
+  // that a level's vote counts once
+  const bool extend = in.only_unstaged && c->profiling && !c->marks.empty() &&
+                      c->marks.back().kind == IA_KERNEL_VOTE;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (c->profiling) {
-    IA_HIP(c, hipEventCreate(&e0));
+    if (!extend) IA_HIP(c, hipEventCreate(&e0));
     IA_HIP(c, hipEventCreate(&e1));
-    IA_HIP(c, hipEventRecord(e0, s));
+    if (!extend) IA_HIP(c, hipEventRecord(e0, s));
   }
   uint32_t* st = &persistent(c)->status;
   unsigned long long* wk = persistent(c)->work;
   const dim3 g(grid, n_ev);
-  if (f32) launch_vote_tile<true>(bx, g, s, recs, vw, par, sh, votes, hist, st, ev, in, wg_max, wk, slack32);
-  else launch_vote_tile<false>(bx, g, s, recs, vw, par, sh, votes, hist, st, ev, in, wg_max, wk, slack32);
+  if (f32) launch_vote_tile<true, false>(bx, g, s, recs, vw, par, sh, votes, hist, st, ev, in, wg_max, wk, slack32);
+  else if (exact) launch_vote_tile<false, true>(bx, g, s, recs, vw, par, sh, votes, hist, st, ev, in, wg_max, wk, slack32);
+  else launch_vote_tile<false, false>(bx, g, s, recs, vw, par, sh, votes, hist, st, ev, in, wg_max, wk, slack32);
   if (c->profiling) {
     IA_HIP(c, hipEventRecord(e1, s));
-    c->marks.push_back({e0, e1, f32, sh.n_boxes, IA_KERNEL_VOTE});
+    if (extend) {
+      (void)hipEventDestroy(c->marks.back().e1);
+      c->marks.back().e1 = e1;
+    } else {
+      c->marks.push_back({e0, e1, f32, sh.n_boxes, IA_KERNEL_VOTE});
+    }
   }
   IA_HIP(c, hipGetLastError());
   return IA_OK;
@@ -370,21 +385,21 @@ void launch_stage(const HitRec* recs, const ia::EvView& vw, int32_t n_ev, const 
                        r.rec_fill, r.rec, r.tfr, r.stage_off, n_ev, slack32);
 }
 
-template <bool F32>
+template <bool F32, bool EX>
 void launch_vote_rec_tile(int32_t bx, dim3 g, hipStream_t s, const ia::EvView& vw, int32_t n_ev, const BoxD* par,
                           const Shape& sh, uint16_t* votes, uint32_t* hist, uint32_t* st, const EventState* ev,
                           const VoteIn& in, const RecIn& r, int32_t* wg_max, unsigned long long* wk) {
   switch (bx) {
     case 256:
-      hipLaunchKernelGGL((ia::k_vote_rec<256, F32>), g, dim3(ia::kWG), 0, s, vw, par, sh, votes, hist, st, ev, in.tlb,
+      hipLaunchKernelGGL((ia::k_vote_rec<256, F32, EX>), g, dim3(ia::kWG), 0, s, vw, par, sh, votes, hist, st, ev, in.tlb,
                          in.tn2, in.live_list, r.live_off, n_ev, r.rec_off, r.rec, r.tfr, wg_max, wk);
       break;
     case 128:
-      hipLaunchKernelGGL((ia::k_vote_rec<128, F32>), g, dim3(ia::kWG), 0, s, vw, par, sh, votes, hist, st, ev, in.tlb,
+      hipLaunchKernelGGL((ia::k_vote_rec<128, F32, EX>), g, dim3(ia::kWG), 0, s, vw, par, sh, votes, hist, st, ev, in.tlb,
                          in.tn2, in.live_list, r.live_off, n_ev, r.rec_off, r.rec, r.tfr, wg_max, wk);
       break;
     default:
-      hipLaunchKernelGGL((ia::k_vote_rec<64, F32>), g, dim3(ia::kWG), 0, s, vw, par, sh, votes, hist, st, ev, in.tlb,
+      hipLaunchKernelGGL((ia::k_vote_rec<64, F32, EX>), g, dim3(ia::kWG), 0, s, vw, par, sh, votes, hist, st, ev, in.tlb,
                          in.tn2, in.live_list, r.live_off, n_ev, r.rec_off, r.rec, r.tfr, wg_max, wk);
       break;
   }
@@ -393,8 +408,8 @@ void launch_vote_rec_tile(int32_t bx, dim3 g, hipStream_t s, const ia::EvView& v
 // the record-based vote for n_ev events (bracketed by events when profiling)
 ia_status launch_vote_rec(ia_ctx* c, const ia::EvView& vw, int32_t n_ev, const BoxD* par, const Shape& sh,
                           uint16_t* votes, uint32_t* hist, const EventState* ev, const VoteIn& in, const RecIn& r,
-                          int32_t* wg_max, hipStream_t s, bool f32) {
-  const int32_t bx = vote_tile(c, sh.n_boxes);
+                          int32_t* wg_max, hipStream_t s, bool f32, bool exact = false) {
+  const int32_t bx = vote_tile(c, sh.n_boxes, n_ev);
   const uint32_t n_tiles = (sh.n_boxes + bx - 1) / bx;
   // the batch's live tiles in one list (laid out by launch_stage), shared by
   // all workgroups
@@ -409,8 +424,9 @@ ia_status launch_vote_rec(ia_ctx* c, const ia::EvView& vw, int32_t n_ev, const B
   uint32_t* st = &persistent(c)->status;
   unsigned long long* wk = persistent(c)->work;
   const dim3 g(grid, 1);
-  if (f32) launch_vote_rec_tile<true>(bx, g, s, vw, n_ev, par, sh, votes, hist, st, ev, in, r, wg_max, wk);
-  else launch_vote_rec_tile<false>(bx, g, s, vw, n_ev, par, sh, votes, hist, st, ev, in, r, wg_max, wk);
+  if (f32) launch_vote_rec_tile<true, false>(bx, g, s, vw, n_ev, par, sh, votes, hist, st, ev, in, r, wg_max, wk);
+  else if (exact) launch_vote_rec_tile<false, true>(bx, g, s, vw, n_ev, par, sh, votes, hist, st, ev, in, r, wg_max, wk);
+  else launch_vote_rec_tile<false, false>(bx, g, s, vw, n_ev, par, sh, votes, hist, st, ev, in, r, wg_max, wk);
   if (c->profiling) {
     IA_HIP(c, hipEventRecord(e1, s));
     c->marks.push_back({e0, e1, f32, sh.n_boxes, IA_KERNEL_VOTE});
@@ -531,7 +547,7 @@ ia_status check_sched(ia_ctx* c, const ia_schedule* sc) {
   for (int j = 0; j < 5; ++j)
     if (!(sc->range.lo[j] <= sc->range.hi[j])) return fail(c, IA_ERR_INVALID, "range dimension %d: lo > hi", j);
   for (int l = 0; l <= sc->n_refine; ++l)
-    if (sc->prec[l] != IA_FP64 && sc->prec[l] != IA_FP32)
+    if (sc->prec[l] != IA_FP64 && sc->prec[l] != IA_FP32 && sc->prec[l] != IA_FP64X)
       return fail(c, IA_ERR_INVALID, "precision %d at level %d", sc->prec[l], l);
   if (!(sc->fp32_slack >= 0.0 && sc->fp32_slack <= 1e-3))
     return fail(c, IA_ERR_INVALID, "fp32_slack %g outside [0, 1e-3]", sc->fp32_slack);
@@ -565,9 +581,9 @@ ia_status run_window(ia_ctx* c, const double* hits, ia::EvView vw, int32_t E, in
     Shape sh = S.sh0;
     vw.par_stride = 0;
     for (int32_t lev = 0; lev <= sc->n_refine; ++lev) {
-      const bool f32 = sc->prec[lev] == IA_FP32;
+      const bool f32 = sc->prec[lev] == IA_FP32, exact = sc->prec[lev] == IA_FP64X;
       vw.fwd = sc->forward;     // per event: hits ahead about the origin, origin behind after a move
-      const bool use_pf = lev > 0 && use_filter(c) && c->parent_filter;
+      const bool use_pf = lev > 0 && use_filter(c) && c->parent_filter && !exact;
       if (use_pf) {
         const int64_t n_pairs = int64_t(sh.n_parents) * std::max(1, cmax);
         const dim3 gp(static_cast<uint32_t>(std::min<int64_t>((n_pairs + ia::kWG - 1) / ia::kWG, 65535)), E);
@@ -580,20 +596,20 @@ ia_status run_window(ia_ctx* c, const double* hits, ia::EvView vw, int32_t E, in
       }
       {
         const ia_status cs = launch_classify(c, recs, vw, E, cmax, par, sh, flags, tlb, tn2, ev, s, f32, slack32,
-                                             use_pf ? pflags : nullptr, (use_pf && !f32) ? pe : nullptr);
+                                             use_pf ? pflags : nullptr, (use_pf && !f32) ? pe : nullptr, exact);
         if (cs != IA_OK) return cs;
       }
-      const int32_t vt = vote_tile(c, sh.n_boxes);
+      const int32_t vt = vote_tile(c, sh.n_boxes, E);
       hipLaunchKernelGGL(ia::k_threshold, dim3(1, E), dim3(ia::kWG), 0, s, tlb, tn2, lbh, vw, sh, 1, c->prune, 0,
                          vt, ev, live, wg_max, rin.live_tri, rin.rec_off, rin.rec_fill, L.rec_stride,
                          lev < sc->n_refine ? sc->wdrop : 0);
       launch_stage(recs, vw, E, par, sh, flags, rin, ev, s, f32, slack32);
       const VoteIn in{flags, tlb, tn2, live, 1};
-      ia_status st = launch_vote_rec(c, vw, E, par, sh, votes, hist, ev, in, rin, wg_max, s, f32);
+      ia_status st = launch_vote_rec(c, vw, E, par, sh, votes, hist, ev, in, rin, wg_max, s, f32, exact);
       if (st != IA_OK) return st;
       int32_t bx = vt;
       if (may_overflow) {
-        st = launch_vote(c, recs, vw, E, par, sh, votes, hist, ev, in, wg_max, s, f32, slack32, &bx);
+        st = launch_vote(c, recs, vw, E, par, sh, votes, hist, ev, in, wg_max, s, f32, slack32, &bx, exact);
         if (st != IA_OK) return st;
       }
       const uint32_t n_wg = (sh.n_boxes + bx - 1) / bx;
@@ -609,7 +625,9 @@ ia_status run_window(ia_ctx* c, const double* hits, ia::EvView vw, int32_t E, in
       hipLaunchKernelGGL(ia::k_est_partial, gpart, dim3(ia::kWG), 0, s, par, sh, votes, sel, sel_v, part, vw, ev,
                          wg_max, bx, static_cast<uint32_t>(n_part), eper, 1);
       if (lev == sc->n_refine) {
-        const int32_t fwd_hf = sc->forward;   // applied while the event's frame is the origin's
+        // bit 0: the forward test, applied while the event's frame is the
+        // origin's; bit 1: the exact Phi of the last level
+        const int32_t fwd_hf = (sc->forward ? 1 : 0) | (exact ? 2 : 0);
         hipLaunchKernelGGL(ia::k_est_final, dim3(1, E), dim3(ia::kWG), 0, s, part, n_part, sel, sel_v,
                            static_cast<ia::EstimateOut*>(nullptr), ev, recs, vw, sc->hitfind_scale, assigned, out,
                            n_out, fwd_hf);
@@ -622,7 +640,7 @@ ia_status run_window(ia_ctx* c, const double* hits, ia::EvView vw, int32_t E, in
                          static_cast<int32_t*>(nullptr), 0);
       if (sc->hitsel)
         hipLaunchKernelGGL(ia::k_hit_select, dim3(pg, E), dim3(ia::kWG), 0, s, recs, vw, ev, sc->hitfind_scale,
-                           vw.fwd);
+                           (vw.fwd ? 1 : 0) | (exact ? 2 : 0));
       const bool mv = lev == sc->move_level;
       if (mv) hipLaunchKernelGGL(ia::k_closest, dim3(1, E), dim3(ia::kWG), 0, s, recs, vw, ev);
       hipLaunchKernelGGL(ia::k_window_partial, gpart, dim3(ia::kWG), 0, s, par, sh, votes, sel, sel_v, part, vw, ev,
@@ -723,10 +741,10 @@ ia_status run_chunk(ia_ctx* c, const double* hits_chunk, const int32_t* h_off_ch
     vw.par_stride = 0;
     int32_t last_bx = 1;
     for (int32_t lev = 0; lev <= sc->n_refine; ++lev) {
-      const bool f32 = sc->prec[lev] == IA_FP32;
+      const bool f32 = sc->prec[lev] == IA_FP32, exact = sc->prec[lev] == IA_FP64X;
       // refinement levels: the parent-level test first (a hit it excludes
       // is class 0 for all of that parent's triples)
-      const bool use_pf = lev > 0 && use_filter(c) && c->parent_filter;
+      const bool use_pf = lev > 0 && use_filter(c) && c->parent_filter && !exact;
       if (use_pf) {
         const int64_t n_pairs = int64_t(sh.n_parents) * std::max(1, cmax);
         const dim3 gp(static_cast<uint32_t>(std::min<int64_t>((n_pairs + ia::kWG - 1) / ia::kWG, 65535)), E);
@@ -741,10 +759,10 @@ ia_status run_chunk(ia_ctx* c, const double* hits_chunk, const int32_t* h_off_ch
         // at FP64 levels the parent's per-sign ranges of d^Ax also decide
         // many pairs in the first stage
         const ia_status cs = launch_classify(c, recs, vw, E, cmax, par, sh, flags, tlb, tn2, ev, s, f32, slack32,
-                                             use_pf ? pflags : nullptr, (use_pf && !f32) ? pe : nullptr);
+                                             use_pf ? pflags : nullptr, (use_pf && !f32) ? pe : nullptr, exact);
         if (cs != IA_OK) return cs;
       }
-      const int32_t vt = vote_tile(c, sh.n_boxes);
+      const int32_t vt = vote_tile(c, sh.n_boxes, E);
       // the last level feeds only the estimate, which needs the whole
       // max-vote set and the first max-vote box: there the selection keeps
       // one box, so that T is the largest lower bound (a box whose upper
@@ -756,11 +774,11 @@ ia_status run_chunk(ia_ctx* c, const double* hits_chunk, const int32_t* h_off_ch
                          ties, vt, ev, live, wg_max, rin.live_tri, rin.rec_off, rin.rec_fill, L.rec_stride, 0);
       launch_stage(recs, vw, E, par, sh, flags, rin, ev, s, f32, slack32);
       const VoteIn in{flags, tlb, tn2, live, 1};
-      ia_status st = launch_vote_rec(c, vw, E, par, sh, votes, hist, ev, in, rin, wg_max, s, f32);
+      ia_status st = launch_vote_rec(c, vw, E, par, sh, votes, hist, ev, in, rin, wg_max, s, f32, exact);
       if (st != IA_OK) return st;
       int32_t bx = vt;
       if (may_overflow) {
-        st = launch_vote(c, recs, vw, E, par, sh, votes, hist, ev, in, wg_max, s, f32, slack32, &bx);
+        st = launch_vote(c, recs, vw, E, par, sh, votes, hist, ev, in, wg_max, s, f32, slack32, &bx, exact);
         if (st != IA_OK) return st;
       }
       last_bx = bx;
@@ -781,7 +799,7 @@ ia_status run_chunk(ia_ctx* c, const double* hits_chunk, const int32_t* h_off_ch
                        sel, sel_v, part, vw, ev, wg_max, last_bx, static_cast<uint32_t>(n_part), eper, 0);
     hipLaunchKernelGGL(ia::k_est_final, dim3(1, E), dim3(ia::kWG), 0, s, part, n_part, sel, sel_v,
                        static_cast<ia::EstimateOut*>(nullptr), ev, recs, vw, sc->hitfind_scale, assigned, out, n_out,
-                       sc->forward);
+                       (sc->forward ? 1 : 0) | (sc->prec[sc->n_refine] == IA_FP64X ? 2 : 0));
     IA_HIP(c, hipGetLastError());
   }
   return IA_OK;
@@ -1007,7 +1025,8 @@ ia_status vote_level_args(ia_ctx* c, const ia_hit* d_hits, int32_t n_hits, const
   if (n_hits > 0 && !d_hits) return fail(c, IA_ERR_INVALID, "d_hits is NULL");
   if (!d_parents || !split || !d_votes) return fail(c, IA_ERR_INVALID, "null pointer argument");
   if (n_parents < 1) return fail(c, IA_ERR_INVALID, "n_parents %d < 1", n_parents);
-  if (prec != IA_FP64 && prec != IA_FP32) return fail(c, IA_ERR_INVALID, "precision %d unknown", int(prec));
+  if (prec != IA_FP64 && prec != IA_FP32 && prec != IA_FP64X)
+    return fail(c, IA_ERR_INVALID, "precision %d unknown", int(prec));
   if (!make_shape(split, n_parents, sh)) return fail(c, IA_ERR_OVERFLOW, "level exceeds 2^31 - 1 boxes");
   return IA_OK;
 }
@@ -1049,17 +1068,18 @@ ia_status vote_level_run(ia_ctx* c, const ia_hit* d_hits, int32_t n_hits, const 
   vw.vref[0] = c->vf_xr;
   vw.vref[1] = c->vf_yr;
   const BoxD* par = reinterpret_cast<const BoxD*>(d_parents);
-  const bool f32 = prec == IA_FP32;
+  const bool f32 = prec == IA_FP32, exact = prec == IA_FP64X;
   const uint32_t fill_n = static_cast<uint32_t>(std::min<int64_t>(n_tr, 0x7fffffff));
   hipLaunchKernelGGL(ia::k_fill_u32, dim3(std::min<uint32_t>((fill_n + 255) / 256, 65535)), dim3(256), 0, s,
                      reinterpret_cast<uint32_t*>(tlb), fill_n, 0u);
   hipLaunchKernelGGL(ia::k_fill_u32, dim3(std::min<uint32_t>((fill_n + 255) / 256, 65535)), dim3(256), 0, s,
                      reinterpret_cast<uint32_t*>(tn2), fill_n, 0u);
   const ia_status cs = launch_classify(c, recs, vw, 1, n_hits, par, sh, flags, tlb, tn2, nullptr, s, f32,
-                                       c->slack32);
+                                       c->slack32, nullptr, nullptr, exact);
   if (cs != IA_OK) return cs;
   const VoteIn in{flags, tlb, tn2, nullptr, 0};
-  return launch_vote(c, recs, vw, 1, par, sh, d_votes, nullptr, nullptr, in, nullptr, s, f32, c->slack32);
+  return launch_vote(c, recs, vw, 1, par, sh, d_votes, nullptr, nullptr, in, nullptr, s, f32, c->slack32, nullptr,
+                     exact);
 }
 
 }  // namespace

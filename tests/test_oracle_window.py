@@ -151,7 +151,7 @@ def test_window_search_recovers_noiseless_helices(orc):
     hit, every hit is assigned, and the helix is recovered within the
     tolerances (1 mm, 5 mrad, 0.01 /m, 10 mm, 0.02)."""
     sc = orc.make_sched(H.LO, H.HI, **toymc.WINDOW_KW)
-    for e in range(4):
+    for e in range(2):
         ev = toymc.config_event(3, e)
         hx, ass, tr = orc.find_helices(ev.hits, sc, max_out=1, want_trace=True)
         t0 = np.array(ev.truth[0], dtype=float)
