@@ -100,11 +100,24 @@ TRAFFIC = {"kernel": "k_vote (fp64 levels)", "workload": "batch", "events_per_st
 PEAK_FP32_TFLOPS = 157.3  # MI355X vector FP32 (non-packed)
 
 
+def prec_text(name):
+    return {"fp64": "FP64", "mixed": "FP32 at levels 0-2, FP64 after and the fit",
+            "exact": "FP64, the exact Phi of Eq. CSAXtoPHI_a at levels 2 and after"}[name]
+
+
+def prec_dtype(name):
+    return "f32+f64" if name == "mixed" else "f64"
+
+
 def sched_prec(name, n_refine):
-    """Per-level precision: all FP64, or FP32 at levels 0-2 and FP64 after."""
+    """Per-level precision: all FP64; FP32 at levels 0-2 and FP64 after
+    (mixed); or FP64 with the exact Phi of Eq. CSAXtoPHI_a at levels 2 and
+    after (exact)."""
     import paper_2401_04576_amd as ia
     if name == "fp64":
         return [ia.FP64] * (n_refine + 1)
+    if name == "exact":
+        return [ia.FP64X if lev >= 2 else ia.FP64 for lev in range(n_refine + 1)]
     return [ia.FP32 if lev <= 2 else ia.FP64 for lev in range(n_refine + 1)]
 
 
@@ -380,15 +393,16 @@ def main():
     ap.add_argument("--latency-events", type=int, default=40,
                     help="single-helix workload: single-event calls timed for p50/p99 latency")
     ap.add_argument("--scratch-gb", type=float, default=48.0)
-    ap.add_argument("--serve-events", type=int, default=4096)
-    ap.add_argument("--rate", type=float, default=1000.0, help="serving: Poisson arrival rate, events/s")
-    ap.add_argument("--slots", type=int, default=4, help="serving: concurrent batches")
+    ap.add_argument("--serve-events", type=int, default=2048)
+    ap.add_argument("--rate", type=float, default=0.0,
+                    help="serving: Poisson arrival rate, events/s (0: 0.8 x the measured saturated rate)")
     ap.add_argument("--report-events", type=int, default=1000, help="mixed-report: noiseless single-helix events")
     ap.add_argument("--no-autotune", action="store_true", help="skip the vote-tile autotuner")
     ap.add_argument("--no-graph", action="store_true",
                     help="batch: call ia_find_helices per step instead of replaying a captured graph")
-    ap.add_argument("--prec", choices=["fp64", "mixed"], default="fp64",
-                    help="mixed: FP32 vote arithmetic at levels 0-2, FP64 at the finer levels and the fit")
+    ap.add_argument("--prec", choices=["fp64", "mixed", "exact"], default="fp64",
+                    help="mixed: FP32 vote arithmetic at levels 0-2, FP64 at the finer levels and the fit; "
+                         "exact: the exact Phi of Eq. CSAXtoPHI_a at levels 2 and after")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the search shards by event "
@@ -516,10 +530,10 @@ def run_event(args):
     res = {
         "metric": METRIC, "value": evals / wall, "unit": "box-hit evals/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": wall / args.steps * 1e3, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f64" if args.prec == "fp64" else "f32+f64",
+        "scaling": "weak", "vs_baseline": None, "dtype": prec_dtype(args.prec),
         "data": "synthetic",
         "config": {"workload": f"single-helix events, {B} per ia_find_helices call, hierarchical refinement, "
-                               + ("FP64" if args.prec == "fp64" else "FP32 at levels 0-2, FP64 at 3-4 and the fit")
+                               + prec_text(args.prec)
                                + ": 20 layers, 150 um smearing, 20% noise hits, band 3 sigma; 16^5 level-0 grid "
                                "then 4 levels of top-32 boxes split 4^5; estimate and hit finding",
                    "events_per_step": B, "mean_hits": float(np.mean([e.n_hits for e in events])),
@@ -721,13 +735,13 @@ def run_batch(args):
         "metric": METRIC, "value": evals / wall, "unit": "box-hit interval evals/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": wall / args.steps * 1e3,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64" if args.prec == "fp64" else "f32+f64", "data": "synthetic",
+        "dtype": prec_dtype(args.prec), "data": "synthetic",
         "config": {"workload": f"batched: {E} events per "
                                + ("replay of one captured ia_find_helices_dev graph" if use_graph
                                   else "ia_find_helices call") + ", 1-5 helices and 20-200 hits "
                                "per event, 0-30% noise, 150 um smearing, band 3 sigma; "
                                + schedule_text(args.sched) + "; up to 5 greedy helix passes; "
-                               + ("FP64" if args.prec == "fp64" else "FP32 at levels 0-2, FP64 after and the fit"),
+                               + prec_text(args.prec),
                    "events_per_step": E, "helices_found_per_event": found / (E * args.steps),
                    "vote_tiles": {str(k): v for k, v in tuned.items()},
                    "helices_generated_per_event": truth / (E * args.steps)},
@@ -755,7 +769,12 @@ def run_batch(args):
 
 
 def run_serve(args):
-    """Workload 5: Poisson arrivals served by the continuous-batching loop."""
+    """Workload 5: config-5 events served by resident pools (continuous
+    batching at helix-pass granularity).  First the saturated rate (every
+    event waiting at the start), then Poisson arrivals at --rate, or at 0.8x
+    the saturated rate when --rate is 0, with p50/p99 from arrival to result;
+    beside it the plain FP64 path, one ia_find_helices call per event, on a
+    sample of the same events (the same results, so the same recovery)."""
     import torch
 
     import paper_2401_04576_amd as ia
@@ -764,36 +783,41 @@ def run_serve(args):
     dev = torch.device("cuda:0")
     lo, hi = np.array(toymc.GRID_RANGE_LO), np.array(toymc.GRID_RANGE_HI)
     nh = 10
-    sched_kw = dict(bins=[16] * 5, n_refine=4, top_k=32, split=[4] * 5, v_min=10, n_helix_max=nh)
+    sched_kw = schedule_kw("window", nh)
     sched = ia.Schedule.make(lo, hi, prec=sched_prec(args.prec, sched_kw["n_refine"]), **sched_kw)
-    sched64 = ia.Schedule.make(lo, hi, **sched_kw)
     n_warm = min(256, args.serve_events)
     t_gen = time.perf_counter()
-    events = generate(5, range(args.serve_events + n_warm))
+    events = generate(5, range(2 * args.serve_events + n_warm))
     t_gen = time.perf_counter() - t_gen
-    warm, events = events[:n_warm], events[n_warm:]
-    loop = serve.ServeLoop(sched, max_per_event=nh, n_slots=args.slots,
-                           scratch_budget=int(args.scratch_gb * (1 << 30)), max_batch=args.batch_events)
-    # warm-up: every slot launches at least once
+    warm, sat_events, events = events[:n_warm], events[n_warm:n_warm + args.serve_events], \
+        events[n_warm + args.serve_events:]
+    loop = serve.ServeLoop(sched, max_per_event=nh, scratch_budget=int(args.scratch_gb * (1 << 30)))
     loop.run([serve.Request(i, e.hits, 0.0) for i, e in enumerate(warm)])
     loop.finished = []
     torch.cuda.synchronize()
-    arrivals = serve.poisson_arrivals(len(events), args.rate, seed=11)
+    # saturation: every event waiting at the start
+    t0 = time.perf_counter()
+    loop.run([serve.Request(i, e.hits, 0.0) for i, e in enumerate(sat_events)])
+    torch.cuda.synchronize()
+    sat_rate = len(sat_events) / (time.perf_counter() - t0)
+    loop.finished = []
+    rate = args.rate if args.rate > 0 else 0.8 * sat_rate
+    arrivals = serve.poisson_arrivals(len(events), rate, seed=11)
     reqs = [serve.Request(i, e.hits, float(t)) for i, (e, t) in enumerate(zip(events, arrivals))]
     t0 = time.perf_counter()
     done = loop.run(reqs)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    st = serve.latency_stats(done)
-    shapes = level_shapes(sched_kw["bins"], sched_kw["top_k"], sched_kw["split"], sched_kw["n_refine"])
-    evals, found, truth = 0.0, 0, 0
-    for r in done:
-        n, _ = hit_counts(r.hits)
-        evals += event_evals(n, r.helices, len(r.helices), shapes, nh)
-        found += len(r.helices)
-        truth += events[r.rid].truth.shape[0]
-    slots_used = loop.events_per_slot
+    caps = loop.capacity()
     loop.close()
+    st = serve.latency_stats(done)
+    done.sort(key=lambda r: r.rid)
+    hel = np.zeros((len(done), nh), dtype=ia.HELIX_DTYPE)
+    nout = np.zeros(len(done), dtype=np.int32)
+    for k, r in enumerate(done):
+        nout[k] = len(r.helices)
+        hel[k, :nout[k]] = r.helices
+    rec = recovery(events, hel, nout)
 
     # the plain FP64 one-event-per-call path on a sample of the same events
     n_plain = min(len(events), 256)
@@ -801,35 +825,42 @@ def run_serve(args):
     plain_hits = [torch.from_numpy(e.hits.view(np.float64).reshape(-1, 8).copy()).to(dev) for e in events[:n_plain]]
     torch.cuda.synchronize()
     for h in plain_hits[:8]:
-        ia.find_helices(ctx, h, [0, h.shape[0]], sched64, max_per_event=nh)
+        ia.find_helices(ctx, h, [0, h.shape[0]], sched, max_per_event=nh)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     lat_plain = []
-    for h in plain_hits:
+    same = 0
+    for k, h in enumerate(plain_hits):
         ta = time.perf_counter()
-        ia.find_helices(ctx, h, [0, h.shape[0]], sched64, max_per_event=nh)
+        raw, n_o, _ = ia.find_helices(ctx, h, [0, h.shape[0]], sched, max_per_event=nh)
         torch.cuda.synchronize()
         lat_plain.append(time.perf_counter() - ta)
+        n1 = int(n_o.cpu()[0])
+        same += int(ia.decode(raw, ia.HELIX_DTYPE)[:n1].tobytes() == done[k].helices.tobytes())
     plain_wall = time.perf_counter() - t1
     ctx.close()
     res = {
-        "metric": METRIC, "value": evals / wall, "unit": "box-hit evals/s", "n_gpus": 1, "steps": 1,
+        "metric": METRIC, "value": len(done) / wall, "unit": "events/s", "n_gpus": 1, "steps": 1,
         "warmup": 1, "ms_per_step": wall * 1e3, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f64" if args.prec == "fp64" else "f32+f64", "data": "synthetic",
-        "config": {"workload": f"serving: {len(events)} events, Poisson arrivals at {args.rate:g}/s, 1-10 "
-                               "helices, lognormal hits (median 120, [20, 1000]), 0-40% noise; 16^5 grid then 4 "
-                               "levels of top-32 split 4^5; up to 10 greedy helix passes; "
-                               + ("FP64" if args.prec == "fp64" else "FP32 at levels 0-2, FP64 at 3-4 and the fit"),
-                   "slots": args.slots, "events_per_slot": slots_used,
-                   "helices_found_per_event": found / len(done),
-                   "helices_generated_per_event": truth / len(done)},
-        "events_per_s": len(done) / wall,
+        "vs_baseline": None, "dtype": prec_dtype(args.prec), "data": "synthetic",
+        "config": {"workload": f"serving: {len(events)} config-5 events (1-10 helices, lognormal hits median 120 in "
+                               f"[20, 1000], 0-40% noise), Poisson arrivals at {rate:.0f}/s; resident pools "
+                               "(continuous batching per helix pass) of rows of 128/256/512/1024 hits; window "
+                               "schedule, up to 10 greedy helix passes; "
+                               + prec_text(args.prec),
+                   "rows": caps, "helices_found_per_event": float(nout.mean()),
+                   "helices_generated_per_event": float(np.mean([len(e.truth) for e in events]))},
+        "saturated_events_per_s": sat_rate, "offered_rate": rate, "rate_rule": "0.8 x saturated" if args.rate <= 0
+        else "given", "events_per_s": len(done) / wall,
         "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"], "mean_ms": st["mean_ms"],
+        "latency": "arrival to result on the host",
+        "recovery": rec,
         "plain_fp64_per_event": {"events_per_s": n_plain / plain_wall,
                                  "p50_ms": float(np.percentile(lat_plain, 50) * 1e3),
-                                 "p99_ms": float(np.percentile(lat_plain, 99) * 1e3), "events": n_plain},
+                                 "p99_ms": float(np.percentile(lat_plain, 99) * 1e3), "events": n_plain,
+                                 "same_helices_as_served": same},
     }
-    print(f"[bench] generated {len(events) + n_warm} events in {t_gen:.1f} s", file=sys.stderr)
+    print(f"[bench] generated {len(events) + len(sat_events) + n_warm} events in {t_gen:.1f} s", file=sys.stderr)
     print(json.dumps(res), flush=True)
 
 

@@ -414,6 +414,54 @@ ia_status ia_find_helices_dev(ia_ctx *ctx, const ia_hit *d_hits, const int32_t *
                               ia_helix *d_out, int32_t max_per_event, int32_t *d_n_out,
                               int32_t *d_assigned, void *stream);
 
+/* Resident pools: continuous batching for serving, at helix-pass
+ * granularity (the search of Sec. 3.3 with events arriving over time).  A
+ * pool keeps `rows` event rows of up to max_hits hits each, with the whole
+ * per-event search state (prepared hits, window, reference point, helices
+ * found, hits assigned), resident in the context's scratch arena.  New
+ * events are admitted into free rows at any time; each ia_pool_step runs one
+ * helix pass -- every level of the window schedule -- over all rows still
+ * searching, so events admitted at different times share the launches.  A
+ * row's helices and assignments equal those of ia_find_helices for that
+ * event alone (the search treats every event independently).  Only the
+ * window schedule (IA_SCHED_WINDOW) is supported.  While a pool exists the
+ * context's other search and vote calls return IA_ERR_INVALID (they would
+ * overwrite the arena).
+ *
+ * ia_pool_capacity: rows of max_hits hits that fit the context's arena (0 if
+ * none).  ia_pool_create: lays the pool out (every row empty) and enqueues
+ * its initialisation on `stream`; IA_ERR_NOMEM if it does not fit; one pool
+ * per context.  ia_pool_destroy: releases the layout (no device work). */
+int32_t ia_pool_capacity(const ia_ctx *ctx, int32_t max_hits, const ia_schedule *sched, int32_t max_per_event);
+ia_status ia_pool_create(ia_ctx *ctx, int32_t rows, int32_t max_hits, const ia_schedule *sched,
+                         int32_t max_per_event, void *stream);
+ia_status ia_pool_destroy(ia_ctx *ctx);
+
+/* Admit n events into rows h_rows[0..n) (host, distinct, each in [0, rows)):
+ * event j is hits [h_off[j], h_off[j+1]) of d_hits (device; h_off on the
+ * host, non-decreasing, each event at most max_hits hits).  The hits are
+ * copied into the row (d_hits may be reused once the stream has passed this
+ * call) and the row restarts its search: a row still searching is abandoned.
+ * n <= min(rows, 32767). */
+ia_status ia_pool_admit(ia_ctx *ctx, int32_t n, const int32_t *h_rows, const ia_hit *d_hits,
+                        const int32_t *h_off, void *stream);
+
+/* One helix pass over every row still searching (enqueued on `stream`).  A
+ * row finishes when its level-0 maximum is below v_min, when hit finding
+ * assigns no hit, or after min(n_helix_max, max_per_event) helices. */
+ia_status ia_pool_step(ia_ctx *ctx, void *stream);
+
+/* Per-row state after the work enqueued so far: h_state[2 r] = 1 when row r
+ * is not searching (finished, or never admitted), h_state[2 r + 1] = helices
+ * it has written.  Synchronises the stream.  h_state: host, 2 * rows int32. */
+ia_status ia_pool_poll(ia_ctx *ctx, int32_t *h_state, void *stream);
+
+/* Copies the first n_helices helices of row `row` to h_out and the helix
+ * index (-1: none) of its first n_hits hits to h_assigned (host arrays).
+ * Synchronises the stream. */
+ia_status ia_pool_take(ia_ctx *ctx, int32_t row, int32_t n_helices, ia_helix *h_out, int32_t n_hits,
+                       int32_t *h_assigned, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -161,6 +161,20 @@ def load():
     L.ia_ctx_tuned.argtypes = [P, P, P, i32]
     L.ia_find_helices_dev.restype = i32
     L.ia_find_helices_dev.argtypes = [P, P, P, i32, i32, i64, C.POINTER(Schedule), P, i32, P, P, P]
+    L.ia_pool_capacity.restype = i32
+    L.ia_pool_capacity.argtypes = [P, i32, C.POINTER(Schedule), i32]
+    L.ia_pool_create.restype = i32
+    L.ia_pool_create.argtypes = [P, i32, i32, C.POINTER(Schedule), i32, P]
+    L.ia_pool_destroy.restype = i32
+    L.ia_pool_destroy.argtypes = [P]
+    L.ia_pool_admit.restype = i32
+    L.ia_pool_admit.argtypes = [P, i32, C.POINTER(i32), P, C.POINTER(i32), P]
+    L.ia_pool_step.restype = i32
+    L.ia_pool_step.argtypes = [P, P]
+    L.ia_pool_poll.restype = i32
+    L.ia_pool_poll.argtypes = [P, C.POINTER(i32), P]
+    L.ia_pool_take.restype = i32
+    L.ia_pool_take.argtypes = [P, i32, i32, P, i32, C.POINTER(i32), P]
     _lib = L
     return L
 
@@ -448,3 +462,60 @@ def find_helices_dev(ctx, hits, d_off, max_hits, sched, out, n_out, assigned=Non
                                           int(hits.shape[0]), C.byref(sched), _ptr(out), int(max_per_event),
                                           _ptr(n_out), _ptr(assigned), _stream_handle(stream)))
     return out, n_out, assigned
+
+
+class Pool:
+    """A resident pool of `rows` event rows of up to `max_hits` hits on a
+    context (ia_pool_*): events are admitted into free rows at any time and
+    every step() runs one helix pass over all rows still searching."""
+
+    def __init__(self, ctx, rows, max_hits, sched, max_per_event=10, stream=None):
+        self.ctx, self.rows, self.max_hits = ctx, int(rows), int(max_hits)
+        self.max_out = min(int(sched.n_helix_max), int(max_per_event))
+        self.stream = stream
+        ctx._check(ctx._L.ia_pool_create(ctx._h, self.rows, self.max_hits, C.byref(sched), int(max_per_event),
+                                         _stream_handle(stream)))
+        self._state = np.zeros(2 * self.rows, dtype=np.int32)
+
+    @staticmethod
+    def capacity(ctx, max_hits, sched, max_per_event=10):
+        """Rows of max_hits hits that fit the context's arena."""
+        return int(ctx._L.ia_pool_capacity(ctx._h, int(max_hits), C.byref(sched), int(max_per_event)))
+
+    def admit(self, rows, hits, offsets):
+        """Events j = hits[offsets[j]:offsets[j+1]] (device float64 (n, 8)
+        tensor, host offsets) into rows[j]."""
+        torch = _torch()
+        _check_dev(hits, torch.float64, "hits", self.ctx.device)
+        r = np.ascontiguousarray(np.asarray(rows, dtype=np.int32))
+        off = np.ascontiguousarray(np.asarray(offsets, dtype=np.int32))
+        if off.shape[0] != r.shape[0] + 1 or (r.shape[0] and (off[0] < 0 or off[-1] > hits.shape[0]
+                                                              or np.any(np.diff(off) < 0))):
+            raise IAError(1, "offsets must be len(rows) + 1 non-decreasing values within the hits")
+        self.ctx._check(self.ctx._L.ia_pool_admit(self.ctx._h, int(r.shape[0]), r.ctypes.data_as(C.POINTER(C.c_int32)),
+                                                  _ptr(hits), off.ctypes.data_as(C.POINTER(C.c_int32)),
+                                                  _stream_handle(self.stream)))
+
+    def step(self):
+        self.ctx._check(self.ctx._L.ia_pool_step(self.ctx._h, _stream_handle(self.stream)))
+
+    def poll(self):
+        """(done flags, helices written) per row; synchronises the stream."""
+        self.ctx._check(self.ctx._L.ia_pool_poll(self.ctx._h, self._state.ctypes.data_as(C.POINTER(C.c_int32)),
+                                                 _stream_handle(self.stream)))
+        return self._state[0::2].copy(), self._state[1::2].copy()
+
+    def take(self, row, n_helices, n_hits):
+        """(helices, assigned) of a finished row."""
+        out = np.zeros(max(1, n_helices), dtype=HELIX_DTYPE)
+        ass = np.zeros(max(1, n_hits), dtype=np.int32)
+        self.ctx._check(self.ctx._L.ia_pool_take(self.ctx._h, int(row), int(n_helices), out.ctypes.data_as(C.c_void_p),
+                                                 int(n_hits), ass.ctypes.data_as(C.POINTER(C.c_int32)),
+                                                 _stream_handle(self.stream)))
+        return out[:n_helices], ass[:n_hits]
+
+    def close(self):
+        if self.ctx is not None and self.ctx._h:
+            self.ctx._L.ia_pool_destroy(self.ctx._h)
+        self.ctx = None
+

@@ -110,8 +110,9 @@ struct EvView {
   int32_t fwd;                  // 1: forward-hit test at this level
   double disk;                  // disk condition radius (0: off)
   double vref[2];               // reference point of the level when there is no event state
+  const int32_t* cnt;           // hits per event when events sit in fixed-size rows (off[e] the row start)
   __device__ int32_t beg(int e) const { return off ? off[e] : 0; }
-  __device__ int32_t count(int e) const { return off ? off[e + 1] - off[e] : n_single; }
+  __device__ int32_t count(int e) const { return cnt ? cnt[e] : (off ? off[e + 1] - off[e] : n_single); }
 };
 
 // status word bits (device-detected problems, read after a stream sync)
@@ -769,6 +770,14 @@ IA_HD int stereo_quick_class(const PairQ& q, const Frame& f, const HitRec& h, Iv
 
 // `signs` (bit 0: dS = +d, bit 1: dS = -d): the drift signs left open; a
 // sign outside it casts no vote in any box of the triple and is skipped.
+// Exclusions and inclusions from an enclosure of d^Ax are taken only where
+// the discriminant of Eq. defdiAX_b stays above A^2 / 4 over it: there the
+// square root and the quotient Q / (A + sqrt(disc)) are well conditioned, so
+// the point evaluation's rounding stays far inside the 1e-9 |e| + 1e-12 m
+// margin (checked against long-double evaluations); elsewhere the boxes are
+// evaluated one by one.
+IA_HD bool well_conditioned(Iv DISC, Iv A) { return A.lo > 0.0 && DISC.lo > 0.25 * A.lo * A.lo; }
+
 IA_HD int stereo_pass_class(const PairQ& q, const Frame& f, const HitRec& h, Iv Z, Iv L, int signs = 3,
                             int32_t* cnt = nullptr) {
   const Iv G = {q.Glo, q.Ghi};
@@ -783,11 +792,11 @@ IA_HD int stereo_pass_class(const PairQ& q, const Frame& f, const HitRec& h, Iv 
     Iv E, EPS, DISC, A;
     const bool ok = e_enclosure32(c, si != 0, f.sig, &E, &EPS, &DISC, &A);
     if (cnt) ++cnt[0];
-    const bool try_incl = ok && DISC.lo > 0.25 * A.lo * A.lo && A.lo > 0.0;
+    const bool try_incl = ok && well_conditioned(DISC, A);
     if (cnt && try_incl) ++cnt[1];
     if (try_incl && votes_everywhere(G, f.K, E.lo, E.hi, h.band)) return 1;
     bool in = true;                      // the test cannot be excluded on this pass
-    if (ok) {
+    if (try_incl) {
       const Iv Eb = {wdn(E.lo - h.band), wup(E.hi + h.band)};
       const Iv Hb = isub(itwice(G), iadd(itwice(Eb), imul(f.K, isqr(Eb))));
       in = Hb.lo <= 0.0 && 0.0 <= Hb.hi;
@@ -943,14 +952,14 @@ IA_HD int stereo_pass_class32(const PairQ& q, const Frame& f, const HitRec& h, I
     Iv E, EPS, DISC, A;
     const bool ok = e_enclosure32(c, si != 0, f.sig, &E, &EPS, &DISC, &A);
     if (cnt) ++cnt[0];
-    const bool try_incl = ok && DISC.lo > 0.25 * A.lo * A.lo && A.lo > 0.0;
+    const bool try_incl = ok && well_conditioned(DISC, A);
     if (cnt && try_incl) ++cnt[1];
     if (try_incl && votes_everywhere(Iv{G.lo, G.hi}, Iv{K.lo, K.hi}, wdn(E.lo - slack32), wup(E.hi + slack32), bs))
       return 1;
     // excluded only when every box stays in the FP32 domain and the widened
     // FP32 test fails over the whole enclosure
     bool in = true;
-    if (ok && fabs(EPS.lo) <= 0.99 && fabs(EPS.hi) <= 0.99 && DISC.lo > 1e-3 * A.hi * A.hi) {
+    if (try_incl && fabs(EPS.lo) <= 0.99 && fabs(EPS.hi) <= 0.99 && DISC.lo > 1e-3 * A.hi * A.hi) {
       const Iv32 Eb = {wdn32(rd32(E.lo) - bs2), wup32(ru32(E.hi) + bs2)};
       const Iv32 Hb = isub32(itwice32(G), iadd32(itwice32(Eb), imul32(K, isqr32(Eb))));
       in = Hb.lo <= 0.0f && 0.0f <= Hb.hi;
@@ -1200,7 +1209,7 @@ IA_HD bool parent_may_vote(const BoxD& P, const uint32_t m[5], const HitRec& h, 
       const double ds = si == 0 ? h.d : -h.d;
       const bool ok = e_enclosure_iq(q, f.R, f.sig, tt, t2, Iv{ds, ds}, Z, L, &E, &EPS, &DISC, &A);
       bool in = true;
-      if (ok) {
+      if (ok && well_conditioned(DISC, A)) {
         const Iv Eb = {wdn(E.lo - h.band), wup(E.hi + h.band)};
         const Iv X = iadd(itwice(Eb), imul(f.K, isqr(Eb)));
         const Iv Hb = isub(itwice(G), X);
@@ -1217,7 +1226,8 @@ IA_HD bool parent_may_vote(const BoxD& P, const uint32_t m[5], const HitRec& h, 
   }
   if (!e_enclosure_iq(q, f.R, f.sig, tt, t2, Iv{-h.d, h.d}, Z, L, &E, &EPS, &DISC, &A)) return true;
   if constexpr (F32) {
-    if (!(fabs(EPS.lo) <= 0.99 && fabs(EPS.hi) <= 0.99 && DISC.lo > 1e-3 * A.hi * A.hi)) return true;
+    if (!(fabs(EPS.lo) <= 0.99 && fabs(EPS.hi) <= 0.99 && DISC.lo > 1e-3 * A.hi * A.hi && well_conditioned(DISC, A)))
+      return true;
     const Iv32 G32 = to32(G), K32 = to32(f.K);
     const float bs2 = wup32(ru32(h.band) + 2.0f * slack32);
     const Iv32 Eb = {wdn32(rd32(E.lo) - bs2), wup32(ru32(E.hi) + bs2)};
@@ -1237,8 +1247,9 @@ __global__ void k_prep(const double* __restrict__ hits, const uint8_t* __restric
                        int32_t* __restrict__ tlb, int32_t* __restrict__ tn2, uint32_t* __restrict__ status,
                        int64_t* __restrict__ n_bad, EventState* __restrict__ ev, int32_t* __restrict__ n_out,
                        BoxD* __restrict__ range_dst, BoxD range, int32_t* __restrict__ assigned,
-                       double xr, double yr) {
-  const int e = blockIdx.y;
+                       double xr, double yr, const int32_t* __restrict__ rows) {
+  // rows (resident pools): the events to prepare, one per grid row
+  const int e = rows ? rows[blockIdx.y] : static_cast<int>(blockIdx.y);
   const int32_t beg = vw.beg(e), n_hits = vw.count(e), n_bins = n_hits + 1;
   const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   const int32_t stride = gridDim.x * blockDim.x;
@@ -1255,7 +1266,7 @@ __global__ void k_prep(const double* __restrict__ hits, const uint8_t* __restric
     }
     ev[e] = es;
     if (n_out) n_out[e] = 0;
-    if (e == 0) *range_dst = range;
+    if (e == 0 && range_dst) *range_dst = range;
   }
   if (bad_ev) return;
   if (hist)
@@ -2766,6 +2777,52 @@ __global__ void __launch_bounds__(kWG) k_est_final(const double* __restrict__ pa
     ev->n_argmax = s_count;
     if (n_out) *n_out = ev->n_out;
     if (na == 0 || ev->n_out >= max_out) ev->done = 1;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Resident pools (continuous batching): events sit in fixed-size rows of
+// max_hits hits, row r starting at hit r * max_hits; a row holds the whole
+// per-event search state between helix passes.
+
+// an empty pool: every row done, no hits, the search range in place
+__global__ void k_pool_init(int32_t* __restrict__ off, int32_t* __restrict__ cnt, EventState* __restrict__ ev,
+                            int32_t* __restrict__ n_out, int32_t rows, int32_t max_hits,
+                            BoxD* __restrict__ range_dst, BoxD range) {
+  const int32_t stride = gridDim.x * blockDim.x;
+  for (int32_t r = blockIdx.x * blockDim.x + threadIdx.x; r <= rows; r += stride) {
+    off[r] = r * max_hits;
+    if (r == rows) continue;
+    cnt[r] = 0;
+    EventState es{};
+    es.done = 1;
+    es.t_cut = INT32_MAX;
+    ev[r] = es;
+    n_out[r] = 0;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) *range_dst = range;
+}
+
+// copies new event j (hits new_off[j] .. new_off[j+1] of src) into row
+// new_rows[j] of the pool's hit store; the host has checked the sizes
+__global__ void k_pool_load(const double* __restrict__ src, const int32_t* __restrict__ new_off,
+                            const int32_t* __restrict__ new_rows, double* __restrict__ store,
+                            int32_t* __restrict__ cnt, int32_t max_hits) {
+  const int32_t j = blockIdx.y;
+  const int32_t r = new_rows[j], b = new_off[j], n = new_off[j + 1] - b;
+  if (blockIdx.x == 0 && threadIdx.x == 0) cnt[r] = n;
+  const int32_t stride = gridDim.x * blockDim.x;
+  for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n * 8; i += stride)
+    store[(int64_t(r) * max_hits) * 8 + i] = src[int64_t(b) * 8 + i];
+}
+
+// per row: done flag and helices written, for the host's poll
+__global__ void k_pool_state(const EventState* __restrict__ ev, const int32_t* __restrict__ n_out, int32_t rows,
+                             int32_t* __restrict__ dst) {
+  const int32_t stride = gridDim.x * blockDim.x;
+  for (int32_t r = blockIdx.x * blockDim.x + threadIdx.x; r < rows; r += stride) {
+    dst[2 * r] = ev[r].done;
+    dst[2 * r + 1] = n_out[r];
   }
 }
 

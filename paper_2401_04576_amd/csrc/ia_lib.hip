@@ -57,8 +57,11 @@ struct Persistent {        // fixed region at the start of the arena
 
 }  // namespace
 
+struct PoolState;
+
 struct ia_ctx {
   int32_t device = 0;
+  PoolState* pool = nullptr;      // a resident pool holds the arena (ia_pool_create)
   char* errbuf = nullptr;         // when set, error messages go here (no heap use)
   char* arena = nullptr;
   size_t arena_bytes = 0;
@@ -567,13 +570,15 @@ ia_status run_window(ia_ctx* c, const double* hits, ia::EvView vw, int32_t E, in
                      uint16_t* votes, uint32_t* hist, BoxD* sel, BoxD* range, int64_t* sel_idx, uint16_t* sel_v,
                      EventState* ev, double* part, uint8_t* flags, uint8_t* pflags, ia::ParentE* pe, int32_t* tlb,
                      int32_t* tn2, uint32_t* lbh, int32_t* wg_max, int32_t* live, const RecIn& rin,
-                     int32_t* assigned, ia::HelixOut* out, int32_t* n_out, hipStream_t s) {
+                     int32_t* assigned, ia::HelixOut* out, int32_t* n_out, int32_t pass0, int32_t pass1,
+                     hipStream_t s) {
   BoxD* win = reinterpret_cast<BoxD*>(c->arena + L.win);
   BoxD rb;
   std::memcpy(&rb, &sc->range, sizeof rb);
   const int32_t pg = std::max(1, (cmax + 255) / 256);
   const int32_t max_per_event = vw.max_out;
-  for (int32_t pass = 0; pass < std::min(sc->n_helix_max, max_per_event); ++pass) {
+  (void)max_per_event;
+  for (int32_t pass = pass0; pass < pass1; ++pass) {
     // every pass starts about the origin
     if (pass > 0 && (sc->move_level >= 0 || sc->hitsel))
       hipLaunchKernelGGL(ia::k_reframe, dim3(pg, E), dim3(ia::kWG), 0, s, hits, vw, recs, ev, 1);
@@ -728,11 +733,12 @@ ia_status run_chunk(ia_ctx* c, const double* hits_chunk, const int32_t* h_off_ch
   int32_t* n_out = n_out_chunk;
   const int32_t pg = std::max(1, (cmax + 2 + 255) / 256);
   hipLaunchKernelGGL(ia::k_prep, dim3(pg, E), dim3(256), 0, s, hits, nullptr, vw, recs, hist, lbh, tlb, tn2,
-                     &ps->status, &ps->n_bad, ev, n_out, range, rb, assigned, 0.0, 0.0);
+                     &ps->status, &ps->n_bad, ev, n_out, range, rb, assigned, 0.0, 0.0, nullptr);
   vw.disk = sc->disk;
   if (sc->mode == IA_SCHED_WINDOW)
     return run_window(c, hits, vw, E, cmax, S, sc, slack32, may_overflow, L, recs, votes, hist, selA, range, sel_idx,
-                      sel_v, ev, part, flags, pflags, pe, tlb, tn2, lbh, wg_max, live, rin, assigned, out, n_out, s);
+                      sel_v, ev, part, flags, pflags, pe, tlb, tn2, lbh, wg_max, live, rin, assigned, out, n_out, 0,
+                      std::min(sc->n_helix_max, max_per_event), s);
   vw.fwd = sc->forward;
   for (int32_t pass = 0; pass < std::min(sc->n_helix_max, max_per_event); ++pass) {
     const BoxD* par = range;
@@ -839,6 +845,7 @@ ia_status ia_ctx_create(ia_ctx** out, int32_t device, size_t scratch_bytes) {
 
 void ia_ctx_destroy(ia_ctx* c) {
   if (!c) return;
+  (void)ia_pool_destroy(c);
   for (auto& m : c->marks) {
     (void)hipEventDestroy(m.e0);
     (void)hipEventDestroy(m.e1);
@@ -1052,7 +1059,7 @@ ia_status vote_level_run(ia_ctx* c, const ia_hit* d_hits, int32_t n_hits, const 
     hipLaunchKernelGGL(ia::k_prep, dim3((n_hits + 255) / 256, 1), dim3(256), 0, s,
                        reinterpret_cast<const double*>(d_hits), d_active, vw, recs, nullptr, nullptr, nullptr, nullptr,
                        &ps->status,
-                       &ps->n_bad, nullptr, nullptr, nullptr, BoxD{}, nullptr, c->vf_xr, c->vf_yr);
+                       &ps->n_bad, nullptr, nullptr, nullptr, BoxD{}, nullptr, c->vf_xr, c->vf_yr, nullptr);
   // classes of the (triple, hit) pairs and per-triple vote bounds
   const int64_t n_tr = int64_t(sh.n_parents) * sh.m012;
   uint8_t* flags = bump<uint8_t>(c, size_t(std::max<int64_t>(1, n_tr * int64_t(n_hits))));
@@ -1090,6 +1097,7 @@ ia_status ia_vote_level(ia_ctx* c, const ia_hit* d_hits, int32_t n_hits, const u
                         const ia_box* d_parents, int32_t n_parents, const int32_t split[5],
                         ia_precision prec, uint16_t* d_votes, void* stream) {
   if (!c) return IA_ERR_INVALID;
+  if (c->pool) return fail(c, IA_ERR_INVALID, "the context holds a resident pool (ia_pool_destroy first)");
   Shape sh;
   const ia_status a = vote_level_args(c, d_hits, n_hits, d_parents, n_parents, split, prec, d_votes, &sh);
   if (a != IA_OK) return a;
@@ -1165,6 +1173,7 @@ ia_status ia_refine(ia_ctx* c, const ia_box* d_parents, int32_t n_parents, const
                     const uint16_t* d_votes, int32_t vote_bound, int32_t top_k, ia_box* d_selected,
                     int64_t* d_selected_index, uint16_t* d_selected_votes, void* stream) {
   if (!c) return IA_ERR_INVALID;
+  if (c->pool) return fail(c, IA_ERR_INVALID, "the context holds a resident pool (ia_pool_destroy first)");
   if (!d_parents || !split || !d_votes || !d_selected || !d_selected_index || !d_selected_votes)
     return fail(c, IA_ERR_INVALID, "null pointer argument");
   if (n_parents < 1) return fail(c, IA_ERR_INVALID, "n_parents %d < 1", n_parents);
@@ -1193,6 +1202,7 @@ ia_status ia_refine(ia_ctx* c, const ia_box* d_parents, int32_t n_parents, const
 ia_status ia_estimate(ia_ctx* c, const ia_box* d_parents, int32_t n_parents, const int32_t split[5],
                       const uint16_t* d_votes, ia_estimate_t* d_out, void* stream) {
   if (!c) return IA_ERR_INVALID;
+  if (c->pool) return fail(c, IA_ERR_INVALID, "the context holds a resident pool (ia_pool_destroy first)");
   if (!d_parents || !split || !d_votes || !d_out) return fail(c, IA_ERR_INVALID, "null pointer argument");
   if (n_parents < 1) return fail(c, IA_ERR_INVALID, "n_parents %d < 1", n_parents);
   Shape sh;
@@ -1240,6 +1250,7 @@ ia_status ia_find_helices(ia_ctx* c, const ia_hit* d_hits, const int32_t* h_off,
                           const ia_schedule* sc, ia_helix* d_out, int32_t max_per_event, int32_t* d_n_out,
                           int32_t* d_assigned, void* stream) {
   if (!c) return IA_ERR_INVALID;
+  if (c->pool) return fail(c, IA_ERR_INVALID, "the context holds a resident pool (ia_pool_destroy first)");
   if (!h_off || !sc || !d_out || !d_n_out) return fail(c, IA_ERR_INVALID, "null pointer argument");
   if (n_events < 0) return fail(c, IA_ERR_INVALID, "n_events %d < 0", n_events);
   if (max_per_event < 1) return fail(c, IA_ERR_INVALID, "max_per_event %d < 1", max_per_event);
@@ -1318,6 +1329,7 @@ ia_status ia_ctx_autotune(ia_ctx* c, const ia_hit* d_hits, const int32_t* h_off,
                           const ia_schedule* sc, ia_helix* d_out, int32_t max_per_event, int32_t* d_n_out,
                           void* stream) {
   if (!c) return IA_ERR_INVALID;
+  if (c->pool) return fail(c, IA_ERR_INVALID, "the context holds a resident pool (ia_pool_destroy first)");
   static const int32_t kTiles[3] = {256, 128, 64};
   const int32_t saved = c->tile_override;
   const bool saved_prof = c->profiling;
@@ -1379,6 +1391,7 @@ ia_status ia_find_helices_dev(ia_ctx* c, const ia_hit* d_hits, const int32_t* d_
                               int32_t max_hits, int64_t n_hits_total, const ia_schedule* sc, ia_helix* d_out,
                               int32_t max_per_event, int32_t* d_n_out, int32_t* d_assigned, void* stream) {
   if (!c) return IA_ERR_INVALID;
+  if (c->pool) return fail(c, IA_ERR_INVALID, "the context holds a resident pool (ia_pool_destroy first)");
   if (!d_off || !sc || !d_out || !d_n_out) return fail(c, IA_ERR_INVALID, "null pointer argument");
   if (n_events < 1 || n_events > 65535) return fail(c, IA_ERR_INVALID, "n_events %d outside [1, 65535]", n_events);
   if (max_per_event < 1) return fail(c, IA_ERR_INVALID, "max_per_event %d < 1", max_per_event);
@@ -1415,6 +1428,288 @@ ia_status ia_find_helices_dev(ia_ctx* c, const ia_hit* d_hits, const int32_t* d_
   return run_chunk(c, reinterpret_cast<const double*>(d_hits), nullptr, d_off, n_events, max_hits, n_hits_total, S, sc,
                    slack32, rpe, rpe < worst_rec, reinterpret_cast<ia::HelixOut*>(d_out), max_per_event, d_n_out,
                    d_assigned, as_stream(stream));
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Resident pools: continuous batching at helix-pass granularity.  The pool
+// lays out the whole search state of `rows` events of up to max_hits hits in
+// the context's arena (the layout ia_find_helices uses for a chunk of that
+// many events, plus a hit store of fixed-size rows).  Admission copies a new
+// event's hits into a free row and prepares that row alone; a step runs one
+// helix pass (every level of the window schedule) over all rows still
+// searching, so events admitted at different times share the launches.
+struct PoolState {
+  int32_t rows = 0, max_hits = 0, max_out = 0;
+  ia_schedule sc{};
+  SchedShapes S{};
+  FindLayout L{};
+  int64_t rpe = 0;
+  bool may_overflow = false;
+  float slack32 = 0.f;
+  size_t store = 0, cnt = 0, newrows = 0, newoff = 0, out = 0, n_out = 0, assigned = 0, state = 0, total = 0;
+};
+
+namespace {
+
+// the pool's extra arrays after the find layout; false when it does not fit
+bool pool_layout(PoolState* P, size_t arena_bytes) {
+  layout_find(P->S.max_boxes, P->S.max_triples, sched_k(&P->sc), P->max_hits, P->rows,
+              int64_t(P->rows) * P->max_hits, &P->L, P->rpe);
+  size_t off = align_up(P->L.total);
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off += align_up(bytes + 1);
+    return o;
+  };
+  const size_t R = size_t(P->rows), H = size_t(P->max_hits);
+  P->store = take(sizeof(double) * 8 * R * H);
+  P->cnt = take(sizeof(int32_t) * R);
+  P->newrows = take(sizeof(int32_t) * R);
+  P->newoff = take(sizeof(int32_t) * (R + 1));
+  P->out = take(sizeof(ia::HelixOut) * R * size_t(P->max_out));
+  P->n_out = take(sizeof(int32_t) * R);
+  P->assigned = take(sizeof(int32_t) * R * H);
+  P->state = take(sizeof(int32_t) * 2 * R);
+  P->total = off;
+  return P->total <= arena_bytes;
+}
+
+// records per event: every (triple, hit) pair when the pool fits that way,
+// else the most (doubling from kRecCap) that fit; false when none fits
+bool pool_fit(PoolState* P, size_t arena_bytes) {
+  const int64_t worst = std::max<int64_t>(1, P->S.max_triples * int64_t(P->max_hits));
+  P->rpe = worst;
+  if (pool_layout(P, arena_bytes)) {
+    P->may_overflow = false;
+    return true;
+  }
+  if (kRecCap >= worst) return false;
+  P->rpe = kRecCap;
+  if (!pool_layout(P, arena_bytes)) return false;
+  for (int64_t r = 2 * kRecCap; r < worst; r *= 2) {
+    PoolState Q = *P;
+    Q.rpe = r;
+    if (!pool_layout(&Q, arena_bytes)) break;
+    *P = Q;
+  }
+  P->may_overflow = true;
+  return true;
+}
+
+ia::EvView pool_view(ia_ctx* c, const PoolState* P) {
+  char* a = c->arena;
+  const FindLayout& L = P->L;
+  ia::EvView vw{};
+  vw.off = reinterpret_cast<const int32_t*>(a + L.off);
+  vw.cnt = reinterpret_cast<const int32_t*>(a + P->cnt);
+  vw.k = sched_k(&P->sc);
+  vw.flag_stride = L.flag_stride;
+  vw.tri_stride = L.tri_stride;
+  vw.rec_stride = L.rec_stride;
+  vw.pflag_stride = L.pflag_stride;
+  vw.hist_stride = L.hist_stride;
+  vw.wg_stride = L.wg_stride;
+  vw.part_stride = L.part_stride;
+  vw.max_out = P->max_out;
+  vw.max_hits = P->max_hits;
+  vw.n_total = int64_t(P->rows) * P->max_hits;
+  vw.disk = P->sc.disk;
+  return vw;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t ia_pool_capacity(const ia_ctx* c, int32_t max_hits, const ia_schedule* sc, int32_t max_per_event) {
+  if (!c || !sc || max_hits < 1 || max_hits > kMaxHits || max_per_event < 1) return 0;
+  PoolState P;
+  P.max_hits = max_hits;
+  P.sc = *sc;
+  P.max_out = std::min(sc->n_helix_max, max_per_event);
+  if (P.max_out < 1 || !sched_shapes(sc, &P.S)) return 0;
+  int32_t lo = 0, hi = 65535;
+  while (lo < hi) {
+    const int32_t mid = (lo + hi + 1) / 2;
+    P.rows = mid;
+    if (pool_fit(&P, c->arena_bytes)) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+ia_status ia_pool_create(ia_ctx* c, int32_t rows, int32_t max_hits, const ia_schedule* sc, int32_t max_per_event,
+                         void* stream) {
+  if (!c) return IA_ERR_INVALID;
+  if (c->pool) return fail(c, IA_ERR_INVALID, "the context already holds a pool");
+  if (!sc) return fail(c, IA_ERR_INVALID, "null schedule");
+  if (rows < 1 || rows > 65535) return fail(c, IA_ERR_INVALID, "rows %d outside [1, 65535]", rows);
+  if (max_hits < 1 || max_hits > kMaxHits) return fail(c, IA_ERR_INVALID, "max_hits %d outside [1, %d]", max_hits, kMaxHits);
+  if (max_per_event < 1) return fail(c, IA_ERR_INVALID, "max_per_event %d < 1", max_per_event);
+  const ia_status sv = check_sched(c, sc);
+  if (sv != IA_OK) return sv;
+  if (sc->mode != IA_SCHED_WINDOW) return fail(c, IA_ERR_INVALID, "pools run the window schedule only");
+  IA_HIP(c, hipSetDevice(c->device));
+  PoolState* P = new PoolState();
+  P->rows = rows;
+  P->max_hits = max_hits;
+  P->sc = *sc;
+  P->max_out = std::min(sc->n_helix_max, max_per_event);
+  P->slack32 = ia::ru32(sc->fp32_slack);
+  if (!sched_shapes(sc, &P->S) || P->S.max_boxes > kMaxEstimateBoxes) {
+    delete P;
+    return fail(c, IA_ERR_OVERFLOW, "a level of the schedule is too large");
+  }
+  if (!pool_fit(P, c->arena_bytes)) {
+    const size_t need = P->total;
+    delete P;
+    return fail(c, IA_ERR_NOMEM, "scratch too small for the pool: need %zu bytes, have %zu", need, c->arena_bytes);
+  }
+  char* a = c->arena;
+  BoxD rb;
+  std::memcpy(&rb, &sc->range, sizeof rb);
+  hipLaunchKernelGGL(ia::k_pool_init, dim3(std::max(1, std::min(1024, (rows + 256) / 256))), dim3(256), 0,
+                     as_stream(stream), reinterpret_cast<int32_t*>(a + P->L.off), reinterpret_cast<int32_t*>(a + P->cnt),
+                     reinterpret_cast<EventState*>(a + P->L.ev), reinterpret_cast<int32_t*>(a + P->n_out), rows,
+                     max_hits, reinterpret_cast<BoxD*>(a + P->L.range), rb);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) {
+    delete P;
+    return fail(c, IA_ERR_DEVICE, "k_pool_init: %s", hipGetErrorString(e));
+  }
+  c->pool = P;
+  return IA_OK;
+}
+
+ia_status ia_pool_destroy(ia_ctx* c) {
+  if (!c) return IA_ERR_INVALID;
+  delete c->pool;
+  c->pool = nullptr;
+  return IA_OK;
+}
+
+ia_status ia_pool_admit(ia_ctx* c, int32_t n, const int32_t* h_rows, const ia_hit* d_hits, const int32_t* h_off,
+                        void* stream) {
+  if (!c) return IA_ERR_INVALID;
+  PoolState* P = c->pool;
+  if (!P) return fail(c, IA_ERR_INVALID, "no pool on this context");
+  if (n == 0) return IA_OK;
+  if (n < 0 || n > P->rows || 2 * n + 1 > kOffSlotInts)
+    return fail(c, IA_ERR_INVALID, "%d events outside [0, %d]", n, std::min(P->rows, (kOffSlotInts - 1) / 2));
+  if (!h_rows || !h_off) return fail(c, IA_ERR_INVALID, "null pointer argument");
+  std::vector<char> seen(size_t(P->rows), 0);
+  for (int32_t j = 0; j < n; ++j) {
+    const int32_t r = h_rows[j], k = h_off[j + 1] - h_off[j];
+    if (r < 0 || r >= P->rows) return fail(c, IA_ERR_INVALID, "row %d outside [0, %d)", r, P->rows);
+    if (seen[size_t(r)]) return fail(c, IA_ERR_INVALID, "row %d admitted twice", r);
+    seen[size_t(r)] = 1;
+    if (k < 0 || k > P->max_hits) return fail(c, IA_ERR_INVALID, "event %d has %d hits (rows hold %d)", j, k, P->max_hits);
+  }
+  if (h_off[n] > h_off[0] && !d_hits) return fail(c, IA_ERR_INVALID, "d_hits is NULL");
+  IA_HIP(c, hipSetDevice(c->device));
+  hipStream_t s = as_stream(stream);
+  char* a = c->arena;
+  // rows and event-relative offsets through a pinned slot whose last copy is done
+  const uint32_t slot = c->slot_next++ % kOffSlots;
+  if (c->slot_used[slot]) IA_HIP(c, hipEventSynchronize(c->slot_done[slot]));
+  int32_t* ho = c->pinned + size_t(slot) * kOffSlotInts;
+  for (int32_t j = 0; j < n; ++j) ho[j] = h_rows[j];
+  for (int32_t j = 0; j <= n; ++j) ho[n + j] = h_off[j] - h_off[0];
+  int32_t* d_rows = reinterpret_cast<int32_t*>(a + P->newrows);
+  int32_t* d_noff = reinterpret_cast<int32_t*>(a + P->newoff);
+  IA_HIP(c, hipMemcpyAsync(d_rows, ho, sizeof(int32_t) * size_t(n), hipMemcpyHostToDevice, s));
+  IA_HIP(c, hipMemcpyAsync(d_noff, ho + n, sizeof(int32_t) * (size_t(n) + 1), hipMemcpyHostToDevice, s));
+  IA_HIP(c, hipEventRecord(c->slot_done[slot], s));
+  c->slot_used[slot] = true;
+  const double* src = reinterpret_cast<const double*>(d_hits) + 8 * int64_t(h_off[0]);
+  double* store = reinterpret_cast<double*>(a + P->store);
+  const int32_t gx = std::max(1, std::min(64, (P->max_hits * 8 + 255) / 256));
+  hipLaunchKernelGGL(ia::k_pool_load, dim3(gx, n), dim3(256), 0, s, src, d_noff, d_rows, store,
+                     reinterpret_cast<int32_t*>(a + P->cnt), P->max_hits);
+  // prepare the new rows alone: state, counters, prepared hits, assignments
+  const FindLayout& L = P->L;
+  Persistent* ps = persistent(c);
+  const ia::EvView vw = pool_view(c, P);
+  const int32_t pg = std::max(1, (P->max_hits + 2 + 255) / 256);
+  hipLaunchKernelGGL(ia::k_prep, dim3(pg, n), dim3(256), 0, s, store, nullptr, vw,
+                     reinterpret_cast<HitRec*>(a + L.recs), reinterpret_cast<uint32_t*>(a + L.hist),
+                     reinterpret_cast<uint32_t*>(a + L.lbh), reinterpret_cast<int32_t*>(a + L.tlb),
+                     reinterpret_cast<int32_t*>(a + L.tn2), &ps->status, &ps->n_bad,
+                     reinterpret_cast<EventState*>(a + L.ev), reinterpret_cast<int32_t*>(a + P->n_out),
+                     static_cast<BoxD*>(nullptr), BoxD{}, reinterpret_cast<int32_t*>(a + P->assigned), 0.0, 0.0,
+                     d_rows);
+  IA_HIP(c, hipGetLastError());
+  return IA_OK;
+}
+
+ia_status ia_pool_step(ia_ctx* c, void* stream) {
+  if (!c) return IA_ERR_INVALID;
+  PoolState* P = c->pool;
+  if (!P) return fail(c, IA_ERR_INVALID, "no pool on this context");
+  IA_HIP(c, hipSetDevice(c->device));
+  char* a = c->arena;
+  const FindLayout& L = P->L;
+  const RecIn rin{reinterpret_cast<int32_t*>(a + L.live_tri), reinterpret_cast<int32_t*>(a + L.rec_off),
+                  reinterpret_cast<int32_t*>(a + L.rec_fill), a + L.rec,
+                  reinterpret_cast<ia::TriFrame*>(a + L.tfr), reinterpret_cast<int32_t*>(a + L.live_off),
+                  reinterpret_cast<int64_t*>(a + L.stage_off)};
+  // one pass, numbered as a later pass: it starts by taking every row back
+  // to the origin's frame with all its remaining hits (a no-op for a row
+  // just admitted)
+  return run_window(c, reinterpret_cast<const double*>(a + P->store), pool_view(c, P), P->rows, P->max_hits, P->S,
+                    &P->sc, P->slack32, P->may_overflow, L, reinterpret_cast<HitRec*>(a + L.recs),
+                    reinterpret_cast<uint16_t*>(a + L.votes), reinterpret_cast<uint32_t*>(a + L.hist),
+                    reinterpret_cast<BoxD*>(a + L.selA), reinterpret_cast<BoxD*>(a + L.range),
+                    reinterpret_cast<int64_t*>(a + L.sel_idx), reinterpret_cast<uint16_t*>(a + L.sel_v),
+                    reinterpret_cast<EventState*>(a + L.ev), reinterpret_cast<double*>(a + L.part),
+                    reinterpret_cast<uint8_t*>(a + L.flags), reinterpret_cast<uint8_t*>(a + L.pflags),
+                    reinterpret_cast<ia::ParentE*>(a + L.pe), reinterpret_cast<int32_t*>(a + L.tlb),
+                    reinterpret_cast<int32_t*>(a + L.tn2), reinterpret_cast<uint32_t*>(a + L.lbh),
+                    reinterpret_cast<int32_t*>(a + L.wg_max), reinterpret_cast<int32_t*>(a + L.live), rin,
+                    reinterpret_cast<int32_t*>(a + P->assigned), reinterpret_cast<ia::HelixOut*>(a + P->out),
+                    reinterpret_cast<int32_t*>(a + P->n_out), 1, 2, as_stream(stream));
+}
+
+ia_status ia_pool_poll(ia_ctx* c, int32_t* h_state, void* stream) {
+  if (!c) return IA_ERR_INVALID;
+  PoolState* P = c->pool;
+  if (!P) return fail(c, IA_ERR_INVALID, "no pool on this context");
+  if (!h_state) return fail(c, IA_ERR_INVALID, "null pointer argument");
+  IA_HIP(c, hipSetDevice(c->device));
+  hipStream_t s = as_stream(stream);
+  char* a = c->arena;
+  int32_t* d_state = reinterpret_cast<int32_t*>(a + P->state);
+  hipLaunchKernelGGL(ia::k_pool_state, dim3(std::max(1, std::min(256, (P->rows + 255) / 256))), dim3(256), 0, s,
+                     reinterpret_cast<const EventState*>(a + P->L.ev), reinterpret_cast<const int32_t*>(a + P->n_out),
+                     P->rows, d_state);
+  IA_HIP(c, hipGetLastError());
+  IA_HIP(c, hipMemcpyAsync(h_state, d_state, sizeof(int32_t) * 2 * size_t(P->rows), hipMemcpyDeviceToHost, s));
+  IA_HIP(c, hipStreamSynchronize(s));
+  return IA_OK;
+}
+
+ia_status ia_pool_take(ia_ctx* c, int32_t row, int32_t n_helices, ia_helix* h_out, int32_t n_hits,
+                       int32_t* h_assigned, void* stream) {
+  if (!c) return IA_ERR_INVALID;
+  PoolState* P = c->pool;
+  if (!P) return fail(c, IA_ERR_INVALID, "no pool on this context");
+  if (row < 0 || row >= P->rows) return fail(c, IA_ERR_INVALID, "row %d outside [0, %d)", row, P->rows);
+  if (n_helices < 0 || n_helices > P->max_out || n_hits < 0 || n_hits > P->max_hits)
+    return fail(c, IA_ERR_INVALID, "%d helices / %d hits outside the row", n_helices, n_hits);
+  if ((n_helices && !h_out) || (n_hits && !h_assigned)) return fail(c, IA_ERR_INVALID, "null pointer argument");
+  IA_HIP(c, hipSetDevice(c->device));
+  hipStream_t s = as_stream(stream);
+  char* a = c->arena;
+  if (n_helices)
+    IA_HIP(c, hipMemcpyAsync(h_out, a + P->out + sizeof(ia::HelixOut) * size_t(row) * P->max_out,
+                             sizeof(ia::HelixOut) * size_t(n_helices), hipMemcpyDeviceToHost, s));
+  if (n_hits)
+    IA_HIP(c, hipMemcpyAsync(h_assigned, a + P->assigned + sizeof(int32_t) * size_t(row) * P->max_hits,
+                             sizeof(int32_t) * size_t(n_hits), hipMemcpyDeviceToHost, s));
+  IA_HIP(c, hipStreamSynchronize(s));
+  return IA_OK;
 }
 
 }  // extern "C"

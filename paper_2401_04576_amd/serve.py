@@ -1,18 +1,23 @@
-"""Continuous-batching serving loop over ia_find_helices.
+"""Continuous-batching serving loop over resident pools (ia_pool_*).
 
 Events arrive over time (for instance as a Poisson stream).  The loop keeps
-`n_slots` execution slots; each slot owns a library context (its scratch
-arena, sized from the device-memory budget) and its own stream, so batches
-in different slots run concurrently on the device.  Whenever a slot is free,
-every event that has arrived and fits the slot's arena is admitted into one
-batch and launched; results are collected when the slot's completion event
-fires, and each event's latency is measured from its arrival to the moment
-its result is back on the host.  An event's result does not depend on the
-batch it was served in (the library's kernels treat every event of a batch
-independently), which tests/test_gpu_serve.py checks.
+one resident pool per size class of events (rows of up to 128, 256, 512 or
+1,024 hits by default), each on its own library context (its scratch arena,
+a share of the device-memory budget) and its own stream, so the pools'
+passes run concurrently on the device.  An arriving event is admitted into
+a free row of the smallest class that holds it (a larger class when that one
+is full), so the device memory it occupies follows its own size.  The pool's
+rows keep their whole search state on the device between passes; every step
+runs one helix pass over all rows still searching, so events that arrived at
+different times share the launches (continuous batching at the granularity of
+a helix pass).  When a step completes, finished rows hand back their helices
+and take new events.  An event's latency runs from its arrival to the moment
+its result is on the host.
 
-The device work itself (prep, votes, selection, estimate, hit finding) runs
-in the HIP kernels of libia; this module only schedules host-side work.
+An event's result does not depend on the row, the pool or the other events
+(the kernels treat every event independently), which tests/test_gpu_serve.py
+checks against ia_find_helices and the oracle.  The device work runs in the
+HIP kernels of libia; this module only schedules host-side work.
 """
 from __future__ import annotations
 
@@ -22,7 +27,7 @@ import time
 
 import numpy as np
 
-from . import Context, HELIX_DTYPE, Schedule, decode, find_helices
+from . import Context, Pool, Schedule
 
 
 @dataclasses.dataclass
@@ -35,112 +40,140 @@ class Request:
     assigned: np.ndarray = None
 
 
-class _Slot:
-    def __init__(self, device, scratch_bytes, torch):
-        self.ctx = Context(device, scratch_bytes=scratch_bytes)
-        self.stream = torch.cuda.Stream(device=device)
-        self.done_ev = None
-        self.batch = None           # (requests, out, n_out, assigned, offsets)
+DEFAULT_CLASSES = {128: 0.40, 256: 0.35, 512: 0.15, 1024: 0.10}
+
+
+class _PoolSlot:
+    def __init__(self, device, max_hits, budget, sched, max_per_event, rows_cap, torch):
         self.torch = torch
+        self.max_hits = max_hits
+        self.ctx = Context(device, scratch_bytes=int(budget))
+        self.stream = torch.cuda.Stream(device=device)
+        rows = min(rows_cap, Pool.capacity(self.ctx, max_hits, sched, max_per_event))
+        if rows < 1:
+            raise ValueError(f"scratch budget below one {max_hits}-hit row")
+        self.pool = Pool(self.ctx, rows, max_hits, sched, max_per_event, stream=self.stream)
+        self.rows = rows
+        self.occupant = [None] * rows        # Request per occupied row
+        self.free = collections.deque(range(rows))
+        self.step_ev = None                  # completion event of the step in flight
+        self.keep = []                       # device buffers the step in flight reads
 
     def busy(self):
-        return self.batch is not None
-
-    def ready(self):
-        return self.done_ev is not None and self.done_ev.query()
+        return self.step_ev is not None and not self.step_ev.query()
 
 
 class ServeLoop:
-    """Serve requests with up to `n_slots` concurrent batches.
+    """Serve requests with resident pools, one per hit-count class.
 
-    scratch_budget: device bytes for all slot arenas together (admission by
-    device memory: a batch holds only as many events as its arena fits).
-    """
+    classes: {max_hits of a row: share of scratch_budget}."""
 
-    def __init__(self, sched: Schedule, max_per_event=10, n_slots=4, scratch_budget=8 << 30,
-                 max_batch=4096, device=0, max_hits=1000):
+    def __init__(self, sched: Schedule, max_per_event=10, scratch_budget=48 << 30, device=0, classes=None,
+                 rows_cap=8192):
         import torch
         self.torch = torch
         self.sched = sched
-        self.max_per_event = int(max_per_event)
         self.device = device
-        per_slot = int(scratch_budget // n_slots)
-        self.per_event_bytes = Context.scratch_needed(sched, max_hits)
-        if per_slot < self.per_event_bytes:
-            raise ValueError("scratch budget below one event per slot")
-        self.events_per_slot = max(1, min(max_batch, per_slot // self.per_event_bytes))
-        self.slots = [_Slot(device, per_slot, torch) for _ in range(n_slots)]
-        for s in self.slots:
-            s.ctx.set_batch(self.events_per_slot)
+        classes = dict(DEFAULT_CLASSES if classes is None else classes)
+        total = sum(classes.values())
+        self.slots = [_PoolSlot(device, int(h), scratch_budget * w / total, sched, max_per_event, rows_cap, torch)
+                      for h, w in sorted(classes.items())]
+        self.max_out = self.slots[0].pool.max_out
         self.pending = collections.deque()
         self.finished = []
 
-    # -- batching -----------------------------------------------------------
-    def _launch(self, slot: _Slot, reqs):
+    def capacity(self):
+        """{max_hits: rows} of the pools."""
+        return {s.max_hits: s.rows for s in self.slots}
+
+    # -- one pool's turn ------------------------------------------------------
+    def _collect(self, slot, now_fn):
+        done, n_out = slot.pool.poll()
+        for r, req in enumerate(slot.occupant):
+            if req is None or not done[r]:
+                continue
+            req.helices, req.assigned = slot.pool.take(r, int(n_out[r]), req.hits.shape[0])
+            req.done = now_fn()
+            self.finished.append(req)
+            slot.occupant[r] = None
+            slot.free.append(r)
+
+    def _admit(self, slot):
         torch = self.torch
+        take = []
+        for req in list(self.pending):
+            if len(take) == len(slot.free):
+                break
+            n = req.hits.shape[0]
+            if n > slot.max_hits:
+                continue
+            # the smallest class that holds the event has priority over this one
+            if any(s.max_hits >= n and s.max_hits < slot.max_hits and s.free for s in self.slots):
+                continue
+            take.append(req)
+        if not take:
+            return
+        for req in take:
+            self.pending.remove(req)
+        rows = [slot.free.popleft() for _ in take]
+        for r, req in zip(rows, take):
+            slot.occupant[r] = req
+        hits_np = np.concatenate([q.hits for q in take])
+        offsets = np.concatenate([[0], np.cumsum([q.hits.shape[0] for q in take])]).astype(np.int32)
         dev = torch.device("cuda", self.device)
-        hits_np = np.concatenate([r.hits for r in reqs]) if reqs else np.zeros(0)
-        offsets = np.concatenate([[0], np.cumsum([r.hits.shape[0] for r in reqs])]).astype(np.int64)
         with torch.cuda.stream(slot.stream):
             pinned = torch.from_numpy(hits_np.view(np.float64).reshape(-1, 8).copy()).pin_memory()
             hits = pinned.to(dev, non_blocking=True)
-            n = len(reqs)
-            out = torch.empty(n * self.max_per_event * HELIX_DTYPE.itemsize, dtype=torch.uint8, device=dev)
-            n_out = torch.empty(n, dtype=torch.int32, device=dev)
-            assigned = torch.empty(max(1, hits.shape[0]), dtype=torch.int32, device=dev)
-            find_helices(slot.ctx, hits, offsets, self.sched, max_per_event=self.max_per_event,
-                         stream=slot.stream, out=out, n_out=n_out, assigned=assigned)
-            out_h = out.to("cpu", non_blocking=True)
-            n_out_h = n_out.to("cpu", non_blocking=True)
-            ass_h = assigned.to("cpu", non_blocking=True)
-            ev = torch.cuda.Event()
-            ev.record(slot.stream)
-        slot.batch = (reqs, out_h, n_out_h, ass_h, offsets, (pinned, hits, out, n_out, assigned))
-        slot.done_ev = ev
+        slot.pool.admit(rows, hits, offsets)
+        slot.keep.extend([pinned, hits])
 
-    def _collect(self, slot: _Slot, now):
-        reqs, out_h, n_out_h, ass_h, offsets, _keep = slot.batch
-        hel = decode(out_h, HELIX_DTYPE).reshape(len(reqs), self.max_per_event)
-        n_out = n_out_h.numpy()
-        ass = ass_h.numpy()
-        for i, r in enumerate(reqs):
-            r.helices = hel[i, :n_out[i]].copy()
-            r.assigned = ass[offsets[i]:offsets[i + 1]].copy()
-            r.done = now
-            self.finished.append(r)
-        slot.batch = None
-        slot.done_ev = None
+    def _launch(self, slot):
+        torch = self.torch
+        slot.pool.step()
+        ev = torch.cuda.Event()
+        ev.record(slot.stream)
+        slot.step_ev = ev
 
     # -- the loop -----------------------------------------------------------
     def run(self, requests, clock=None):
-        """Serve `requests` (sorted by arrival time, seconds from start).
-        Returns the finished requests with their `done` times set."""
+        """Serve `requests` (arrival times in seconds from start).  Returns
+        the finished requests with their `done` times set."""
         clock = clock or time.perf_counter
+        largest = max(s.max_hits for s in self.slots)
+        for r in requests:
+            if r.hits.shape[0] > largest:
+                raise ValueError(f"request {r.rid} has {r.hits.shape[0]} hits; rows hold at most {largest}")
         t0 = clock()
+        now = lambda: clock() - t0  # noqa: E731
         queue = collections.deque(sorted(requests, key=lambda r: r.arrival))
-        in_flight = 0
-        while queue or self.pending or in_flight:
-            now = clock() - t0
-            while queue and queue[0].arrival <= now:
+        while queue or self.pending or any(any(o is not None for o in s.occupant) for s in self.slots):
+            t = now()
+            while queue and queue[0].arrival <= t:
                 self.pending.append(queue.popleft())
+            idle = True
             for slot in self.slots:
-                if slot.busy() and slot.ready():
-                    self._collect(slot, clock() - t0)
-                    in_flight -= 1
-            for slot in self.slots:
-                if not slot.busy() and self.pending:
-                    batch = [self.pending.popleft() for _ in range(min(len(self.pending), self.events_per_slot))]
-                    self._launch(slot, batch)
-                    in_flight += 1
-            if not self.pending and queue and not in_flight:
-                # idle until the next arrival
-                wait = queue[0].arrival - (clock() - t0)
+                if slot.busy():
+                    idle = False
+                    continue
+                if slot.step_ev is not None:
+                    self._collect(slot, now)
+                    slot.step_ev = None
+                    slot.keep = []
+                self._admit(slot)
+                if any(o is not None for o in slot.occupant):
+                    self._launch(slot)
+                    idle = False
+            if idle and queue and not self.pending:
+                wait = queue[0].arrival - now()
                 if wait > 0:
                     time.sleep(min(wait, 1e-3))
+            elif not idle:
+                time.sleep(20e-6)
         return self.finished
 
     def close(self):
         for s in self.slots:
+            s.pool.close()
             s.ctx.close()
 
 
