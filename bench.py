@@ -865,7 +865,11 @@ def run_serve(args):
 
 
 def run_mixed_report(args):
-    """FP32 coarse levels against all-FP64 on noiseless single-helix events."""
+    """FP32 coarse levels against all-FP64 on noiseless single-helix events
+    (config 3), under the window schedule: the votes of the level-0 grid and
+    of a 16^5 window around its max-vote boxes both ways (disagreement,
+    superset, maximum and max-vote set agreement), then the whole search
+    both ways (helix differences and recovery)."""
     import torch
 
     import paper_2401_04576_amd as ia
@@ -873,8 +877,7 @@ def run_mixed_report(args):
 
     dev = torch.device("cuda:0")
     lo, hi = np.array(toymc.GRID_RANGE_LO), np.array(toymc.GRID_RANGE_HI)
-    kw = dict(bins=[16] * 5, n_refine=4, top_k=32, split=[4] * 5, v_min=10, n_helix_max=1)
-    n_lev = kw["n_refine"] + 1
+    kw = schedule_kw("window", 1)
     prec_mixed = sched_prec("mixed", kw["n_refine"])
     n = args.report_events
     t_gen = time.perf_counter()
@@ -883,33 +886,36 @@ def run_mixed_report(args):
     ctx = ia.Context(0, scratch_bytes=int(args.scratch_gb * (1 << 30)))
     t0 = time.perf_counter()
 
-    # 1. per level, on the FP64 frontier: FP32 vs FP64 votes and selections
-    diff_boxes = np.zeros(n_lev)
-    tot_boxes = np.zeros(n_lev)
-    superset_ok = np.ones(n_lev, dtype=bool)
-    sel_agree = np.zeros(n_lev)
-    max_agree = np.zeros(n_lev)
+    # 1. two grids per event: the level-0 grid over the range, and a 16^5
+    #    window over the FP64 max-vote boxes widened by one bin
+    names_l = ["level 0 (16^5 over the range)", "16^5 window around the level-0 max-vote boxes"]
+    diff = np.zeros(2)
+    tot = np.zeros(2)
+    superset_ok = [True, True]
+    max_agree = np.zeros(2)
+    set_agree = np.zeros(2)
     root = torch.tensor([list(lo) + list(hi)], dtype=torch.float64, device=dev)
+    m = np.array(kw["bins"])
     for ev in events:
         hits = torch.from_numpy(ev.hits.view(np.float64).reshape(-1, 8).copy()).to(dev)
-        parents, split = root, kw["bins"]
-        for lev in range(n_lev):
-            v64 = ia.vote_level(ctx, hits, parents, split, prec=ia.FP64)
-            if prec_mixed[lev] == ia.FP32:
-                v32 = ia.vote_level(ctx, hits, parents, split, prec=ia.FP32)
-            else:
-                v32 = v64
-            bound = ev.n_hits
-            sel64, idx64, sv64 = ia.refine(ctx, parents, split, v64, bound, kw["top_k"])
-            sel32, idx32, sv32 = ia.refine(ctx, parents, split, v32, bound, kw["top_k"])
-            a64, a32 = v64.cpu().numpy().astype(np.int64), v32.cpu().numpy().astype(np.int64)
-            d = a32 - a64
-            diff_boxes[lev] += np.count_nonzero(d)
-            tot_boxes[lev] += d.size
-            superset_ok[lev] &= bool(d.min() >= 0)
-            sel_agree[lev] += bool(torch.equal(idx64, idx32))
-            max_agree[lev] += bool(a64.max() == a32.max())
-            parents, split = sel64, kw["split"]
+        parents = root
+        for g in range(2):
+            v64 = ia.vote_level(ctx, hits, parents, kw["bins"], prec=ia.FP64).cpu().numpy().astype(np.int64)
+            v32 = ia.vote_level(ctx, hits, parents, kw["bins"], prec=ia.FP32).cpu().numpy().astype(np.int64)
+            d = v32 - v64
+            diff[g] += np.count_nonzero(d)
+            tot[g] += d.size
+            superset_ok[g] &= bool(d.min() >= 0)
+            max_agree[g] += bool(v64.max() == v32.max())
+            set_agree[g] += bool(np.array_equal(np.flatnonzero(v64 == v64.max()), np.flatnonzero(v32 == v32.max())))
+            if g == 0:
+                p = parents.cpu().numpy()[0]
+                plo, phi_ = p[:5], p[5:]
+                w = (phi_ - plo) / m
+                idx = np.array(np.unravel_index(np.flatnonzero(v64 == v64.max()), tuple(m))).T
+                wlo = plo + (idx.min(axis=0) - 1) * w
+                whi = plo + (idx.max(axis=0) + 2) * w
+                parents = torch.tensor([list(wlo) + list(whi)], dtype=torch.float64, device=dev)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
 
@@ -922,12 +928,11 @@ def run_mixed_report(args):
         sched = ia.Schedule.make(lo, hi, prec=prec, **kw)
         raw, n_out, _ = ia.find_helices(ctx, hits, off, sched, max_per_event=1)
         torch.cuda.synchronize()
-        res_h[name] = (ia.decode(raw, ia.HELIX_DTYPE), n_out.cpu().numpy())
+        res_h[name] = (ia.decode(raw, ia.HELIX_DTYPE).reshape(n, 1), n_out.cpu().numpy())
     ctx.close()
     h64, n64 = res_h["fp64"]
     h32, n32 = res_h["mixed"]
     both = (n64 > 0) & (n32 > 0)
-    truth = np.array([e.truth[0] for e in events])
     names = ["d0", "phi0", "kappa", "z0", "tanl"]
 
     def wrap(x):
@@ -937,47 +942,23 @@ def run_mixed_report(args):
         x = np.abs(x)
         return {"mean": float(x.mean()), "rms": float(np.sqrt((x * x).mean())), "max": float(x.max())} if x.size else None
 
-    dpar, d64t, d32t = {}, {}, {}
+    dpar = {}
     for j, nm in enumerate(names):
-        a, b, t = h32["p"][both, j], h64["p"][both, j], truth[both, j]
-        if j == 1:
-            dpar[nm], d64t[nm], d32t[nm] = stats(wrap(a - b)), stats(wrap(b - t)), stats(wrap(a - t))
-        else:
-            dpar[nm], d64t[nm], d32t[nm] = stats(a - b), stats(b - t), stats(a - t)
-
-    # the same helix travelled the other way: (-d0, phi0 + pi, -kappa, z0, -tanl)
-    mirror = truth.copy()
-    mirror[:, 0], mirror[:, 1], mirror[:, 2], mirror[:, 4] = -truth[:, 0], truth[:, 1] + np.pi, -truth[:, 2], -truth[:, 4]
-
-    def inside(h, t):
-        # t inside the hit-finding box (estimate +- 5 error) in every parameter
-        w = 5.0 * h["err"]
-        dd = np.abs(h["p"] - t)
-        dd[:, 1] = np.abs(wrap(h["p"][:, 1] - t[:, 1]))
-        return np.all(dd <= w, axis=1)
-
-    def recovered(h, ok, either=False):
-        r = inside(h, truth)
-        if either:
-            r = r | inside(h, mirror)
-        return float(np.mean(ok & r))
-
+        a, b = h32[both, 0]["p"][:, j], h64[both, 0]["p"][:, j]
+        dpar[nm] = stats(wrap(a - b) if j == 1 else a - b)
+    same = int(sum(h32[e, 0].tobytes() == h64[e, 0].tobytes() for e in range(n) if both[e]))
     res = {
         "metric": METRIC, "value": None, "unit": "report", "n_gpus": 1, "steps": 1, "warmup": 0,
         "ms_per_step": (t1 - t0) * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32+f64", "data": "synthetic",
-        "config": {"workload": f"FP32 at levels 0-2 against all-FP64: {n} noiseless single-helix events, 16^5 "
-                               "grid then 4 levels of top-32 split 4^5, band 0"},
-        "per_level": [{"level": lev, "fp32": bool(prec_mixed[lev] == ia.FP32),
-                       "vote_disagreement": float(diff_boxes[lev] / tot_boxes[lev]),
-                       "fp32_votes_contain_fp64": bool(superset_ok[lev]),
-                       "selection_agreement": float(sel_agree[lev] / n),
-                       "max_agreement": float(max_agree[lev] / n)} for lev in range(n_lev)],
-        "helices_both": int(both.sum()),
-        "abs_fp32_minus_fp64": dpar, "abs_fp64_minus_truth": d64t, "abs_fp32_minus_truth": d32t,
-        "recovery_fp64": recovered(h64, n64 > 0), "recovery_fp32": recovered(h32, n32 > 0),
-        "recovery_either_direction_fp64": recovered(h64, n64 > 0, True),
-        "recovery_either_direction_fp32": recovered(h32, n32 > 0, True),
+        "config": {"workload": f"FP32 at levels 0-2 (the whole predicate in FP32) against all-FP64: {n} noiseless "
+                               "single-helix events, window schedule, band 0"},
+        "grids": [{"grid": names_l[g], "vote_disagreement": float(diff[g] / tot[g]),
+                   "fp32_votes_contain_fp64": bool(superset_ok[g]), "max_agreement": float(max_agree[g] / n),
+                   "max_set_agreement": float(set_agree[g] / n)} for g in range(2)],
+        "helices_both": int(both.sum()), "identical_helices": same,
+        "abs_fp32_minus_fp64": dpar,
+        "recovery_fp64": recovery(events, h64, n64), "recovery_mixed": recovery(events, h32, n32),
     }
     print(f"[bench] generated {n} events in {t_gen:.1f} s", file=sys.stderr)
     print(json.dumps(res), flush=True)

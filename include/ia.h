@@ -146,9 +146,10 @@ typedef struct {
   double hitfind_scale;   /* hit-finding box = estimate +- scale x error (5 in Sec. 3.3) */
   int32_t prec[IA_MAX_LEVELS];  /* arithmetic per level (IA_FP64, IA_FP32 or IA_FP64X); the
                                  * hit finding and hit selection use the estimating level's */
-  double fp32_slack;      /* band widening at FP32 levels, m, in [0, 1e-3]; it must
-                           * bound the FP32 error of d^Ax (1e-6 is 100x the largest
-                           * error seen on the chamber geometry) */
+  double fp32_slack;      /* band widening at FP32 levels, m, in [0, 1e-3], to which
+                           * 2^-24 R is added per box (R the radius at its centre):
+                           * together they bound |e32 - e64| of d^Ax (measured at
+                           * most 6.2e-9 R + 1e-9 m over the search range) */
   int32_t mode;           /* IA_SCHED_TOPK or IA_SCHED_WINDOW */
   int32_t forward;        /* 1: forward-hit test (see above), 0: off */
   int32_t move_level;     /* IA_SCHED_WINDOW: the reference point moves after this
@@ -304,10 +305,12 @@ size_t ia_ctx_scratch_needed(const ia_schedule *sched, int32_t max_hits);
  *   d_active  NULL or n_hits bytes; 0 excludes a hit
  *   d_parents n_parents boxes (lo <= hi in every dimension)
  *   split     host int32[5], each >= 1
- *   prec      IA_FP64, or IA_FP32: the stereo term of each (box, hit) pair in
- *             FP32 and an FP32 interval test with the band widened by the
- *             context's slack; its votes contain the IA_FP64 votes; or
- *             IA_FP64X: FP64 with the exact Phi of Eq. CSAXtoPHI_a
+ *   prec      IA_FP64; or IA_FP32: the whole predicate of each (box, hit)
+ *             pair in FP32 -- G over the box in FP32 intervals, d^Ax at the
+ *             box centre in FP32, the FP32 interval test with the band
+ *             widened by the context's slack + 2^-24 R -- whose votes contain
+ *             the IA_FP64 votes; or IA_FP64X: FP64 with the exact Phi of
+ *             Eq. CSAXtoPHI_a
  *   d_votes   n_parents * prod(split) uint16, written: number of active,
  *             well-formed hits voting for each box
  * Scratch: 112 bytes per hit, and n_parents * prod(split[0..2]) * (n_hits + 8)

@@ -31,7 +31,7 @@ SCHED_DTYPE = np.dtype([("range", BOX_DTYPE), ("bins", "i4", (5,)), ("n_refine",
                         ("fp32_slack", "f8"), ("mode", "i4"), ("forward", "i4"),
                         ("move_level", "i4"), ("wdrop", "i4"), ("hitsel", "i4"),
                         ("lbins", "i4", (8, 5)), ("disk", "f8")], align=True)
-FP64, FP32, FP64X = 0, 1, 2   # FP64X: FP64 with the exact Phi of Eq. CSAXtoPHI_a
+FP64, FP32, FP64X, IV = 0, 1, 2, 3   # FP64X: exact Phi of Eq. CSAXtoPHI_a; IV: sound whole-box d^Ax
 TOPK, WINDOW = 0, 1
 HELIX_DTYPE = np.dtype([("p", "f8", (5,)), ("err", "f8", (5,)), ("ref", "f8", (2,)), ("votes", "i4"),
                         ("n_assigned", "i4"), ("n_argmax", "i4"), ("pad", "i4")])
@@ -82,6 +82,8 @@ def lib():
         L.or_stereo_e_x.restype = i32; L.or_stereo_e_x.argtypes = [_P, _P, i32, i32, _P, _P]
         L.or_pair_vote.restype = i32; L.or_pair_vote.argtypes = [_P, _P, _P]
         L.or_pair_vote_x.restype = i32; L.or_pair_vote_x.argtypes = [_P, _P, i32, _P]
+        L.or_stereo_encl.restype = i32; L.or_stereo_encl.argtypes = [_P, _P, i32, _P, _P]
+        L.or_pair_vote_iv.restype = i32; L.or_pair_vote_iv.argtypes = [_P, _P]
         L.or_vote_level.restype = None
         L.or_vote_level.argtypes = [_P, i32, _P, _P, i32, _P, _P, i32]
         L.or_vote_level_prec.restype = None
@@ -92,6 +94,11 @@ def lib():
         L.or_wdn32.restype = f; L.or_wdn32.argtypes = [f]
         L.or_wup32.restype = f; L.or_wup32.argtypes = [f]
         L.or_sinf1.restype = f; L.or_sinf1.argtypes = [f]
+        L.or_sinf.restype = f; L.or_sinf.argtypes = [f]
+        L.or_cosf.restype = f; L.or_cosf.argtypes = [f]
+        L.or_atan2f.restype = f; L.or_atan2f.argtypes = [f, f]
+        L.or_sin_encl32.restype = None; L.or_sin_encl32.argtypes = [f, f, _P, _P]
+        L.or_pair_G32.restype = None; L.or_pair_G32.argtypes = [_P, _P, _P, _P]
         L.or_cosf1.restype = f; L.or_cosf1.argtypes = [f]
         L.or_stereo_e32.restype = i32; L.or_stereo_e32.argtypes = [_P, _P, i32, _P, _P]
         L.or_pair_vote32.restype = i32; L.or_pair_vote32.argtypes = [_P, _P, d, _P]
@@ -229,6 +236,21 @@ def pair_vote(prep, box, debug=False, exact=False):
     return (int(v), dbg) if debug else int(v)
 
 
+def stereo_encl(prep, box, s):
+    """(ok, lo, hi): enclosure of e = sgn(kappa) d^Ax over the whole box (IV levels)."""
+    prep = _c(np.atleast_1d(prep), PREP_DTYPE)
+    box = _c(np.atleast_1d(box), BOX_DTYPE)
+    lo, hi = np.zeros(1), np.zeros(1)
+    ok = lib().or_stereo_encl(_ptr(prep), _ptr(box), int(s), _ptr(lo), _ptr(hi))
+    return bool(ok), float(lo[0]), float(hi[0])
+
+
+def pair_vote_iv(prep, box):
+    prep = _c(np.atleast_1d(prep), PREP_DTYPE)
+    box = _c(np.atleast_1d(box), BOX_DTYPE)
+    return int(lib().or_pair_vote_iv(_ptr(prep), _ptr(box)))
+
+
 def disk(box, ref=(0.0, 0.0), radius=5e-3):
     box = _c(np.atleast_1d(box), BOX_DTYPE)
     return int(lib().or_disk(_ptr(box), float(ref[0]), float(ref[1]), float(radius)))
@@ -271,6 +293,33 @@ def wup32(x):
 
 def sinf1(x):
     return np.float32(lib().or_sinf1(C.c_float(x)))
+
+
+def sinf(x):
+    return np.float32(lib().or_sinf(C.c_float(x)))
+
+
+def cosf(x):
+    return np.float32(lib().or_cosf(C.c_float(x)))
+
+
+def atan2f(y, x):
+    return np.float32(lib().or_atan2f(C.c_float(y), C.c_float(x)))
+
+
+def sin_encl32(a, b):
+    lo, hi = np.zeros(1, dtype=np.float32), np.zeros(1, dtype=np.float32)
+    lib().or_sin_encl32(C.c_float(a), C.c_float(b), _ptr(lo), _ptr(hi))
+    return lo[0], hi[0]
+
+
+def pair_G32(prep, box):
+    """FP32 interval G of Eq. ApoVote over the box."""
+    prep = _c(np.atleast_1d(prep), PREP_DTYPE)
+    box = _c(np.atleast_1d(box), BOX_DTYPE)
+    lo, hi = np.zeros(1, dtype=np.float32), np.zeros(1, dtype=np.float32)
+    lib().or_pair_G32(_ptr(prep), _ptr(box), _ptr(lo), _ptr(hi))
+    return lo[0], hi[0]
 
 
 def cosf1(x):

@@ -390,6 +390,150 @@ int32_t or_pair_vote_x(const or_prep *h, const or_box *b, int32_t exact, double 
 }
 
 /* ------------------------------------------------------------------------
+ * Sound d^Ax over a whole box (IV levels).  Sec. 3.1 takes d^Ax at the
+ * middle of the voxel, which the paper notes is not an enclosure.  Here
+ * every quantity of Appendix A is enclosed over the whole box in interval
+ * arithmetic (outward rounding as above), in the kappa > 0 frame of the
+ * box (a box whose kappa range holds 0 has no such frame: no enclosure):
+ * the circle centre and radius, R^Ax, c^Ax, s^Ax, sin and cos Phi^Ax,
+ * phi^Ax - phi0 (atan2 enclosed by its values at the corners of its
+ * argument box plus 1e-13, or [-pi, pi] where that box meets the cut), then
+ * Phi itself: Phi - Phi^Ax solves Eq. CSAXtoPHI_a, eps = atan2(s^tau tan
+ * tau, (R^Ax)^2 + c^tau tan tau), so every solution lies in F(EPS) for any
+ * EPS that holds it, F the interval image of the right-hand side.  Starting
+ * from [-pi, pi] (where the denominator must stay positive, else no
+ * enclosure), OR_IV_ITERS steps EPS <- EPS meet F(EPS) keep every solution,
+ * hence the exact closest approach, for every point of the box.  With EPS,
+ * Eqs. normudi, EQSinter_c and defdiAX_b in interval form give d^Ax; the
+ * enclosure is returned for e = sgn(kappa) d^Ax.
+ * Parity: pinned by sampled points of random boxes, whose exact-Phi point
+ * values (themselves pinned against the generator's closest approach) lie
+ * inside, and by the vote containing the mid-voxel vote's hits at the truth.
+ * ---------------------------------------------------------------------- */
+static iv iv_neg(iv a) { iv r = {-a.hi, -a.lo}; return r; }
+static iv iv_mulp(iv a, double x) {
+  double p = a.lo * x, q = a.hi * x;
+  iv r;
+  if (x >= 0.0) { r.lo = or_wdn(p); r.hi = or_wup(q); } else { r.lo = or_wdn(q); r.hi = or_wup(p); }
+  return r;
+}
+/* a / b for b.lo > 0 */
+static iv iv_divpos(iv a, iv b) {
+  double q1 = a.lo / b.lo, q2 = a.lo / b.hi, q3 = a.hi / b.lo, q4 = a.hi / b.hi;
+  iv r = {or_wdn(fmin(fmin(q1, q2), fmin(q3, q4))), or_wup(fmax(fmax(q1, q2), fmax(q3, q4)))};
+  return r;
+}
+static iv iv_sqrt(iv a) { iv r = {a.lo > 0.0 ? or_wdn(sqrt(a.lo)) : 0.0, or_wup(sqrt(a.hi))}; return r; }
+static iv iv_sin(iv a) { iv r; or_sin_encl(a.lo, a.hi, &r.lo, &r.hi); return r; }
+static iv iv_cos(iv a) {
+  iv r;
+  or_sin_encl(or_wdn(a.lo + PIO2_RN), or_wup(a.hi + PIO2_UP), &r.lo, &r.hi);
+  return r;
+}
+static iv iv_atan2(iv y, iv x) {
+  if (x.lo <= 0.0 && y.lo <= 0.0 && y.hi >= 0.0) { iv r = {-2.0 * PIO2_UP, 2.0 * PIO2_UP}; return r; }
+  double a = or_atan2(y.lo, x.lo), b = or_atan2(y.lo, x.hi), c = or_atan2(y.hi, x.lo), d = or_atan2(y.hi, x.hi);
+  iv r = {fmin(fmin(a, b), fmin(c, d)) - 1e-13, fmax(fmax(a, b), fmax(c, d)) + 1e-13};
+  return r;
+}
+
+typedef struct { iv sinP, cosP, u, delta, zS, ld, ctau; } iv_stpoint;
+
+/* the stereo-point quantities for Phi - Phi^Ax in EPS; 0 when u^2 may be <= 0 */
+static int32_t iv_stereo_point(iv EPS, iv SINA, iv COSA, iv LAM, double tt, iv T2, double dS, iv R, iv DPHI,
+                               iv Z0, iv CAX, iv SAX, iv_stpoint *o) {
+  iv SE = iv_sin(EPS), CE = iv_cos(EPS);
+  o->sinP = iv_add(iv_mul(SINA, CE), iv_mul(COSA, SE));
+  o->cosP = iv_sub(iv_mul(COSA, CE), iv_mul(SINA, SE));
+  iv U2 = iv_add(iv_add(iv_add(iv_point(1.0), iv_mulp(iv_mul(iv_twice(LAM), o->sinP), tt)),
+                        iv_mul(iv_sqr(LAM), T2)),
+                 iv_mul(iv_sqr(o->cosP), T2));
+  if (!(U2.lo > 0.0)) return 0;
+  o->u = iv_sqrt(U2);
+  o->delta = iv_divpos(iv_point(dS), o->u);
+  iv SPERP = iv_mul(R, iv_add(DPHI, EPS));
+  o->zS = iv_sub(iv_add(Z0, iv_mul(LAM, SPERP)), iv_mulp(iv_mul(o->delta, o->cosP), tt));
+  o->ld = iv_mul(LAM, o->delta);
+  o->ctau = iv_sub(iv_mul(o->zS, CAX), iv_mul(o->ld, SAX));
+  return 1;
+}
+
+int32_t or_stereo_encl(const or_prep *h, const or_box *b, int32_t s, double *lo, double *hi) {
+  if (!h->valid) return 0;
+  if (b->lo[2] <= 0.0 && b->hi[2] >= 0.0) return 0;            /* kappa of both signs */
+  const double sig = b->lo[2] > 0.0 ? 1.0 : -1.0;
+  const iv K = {b->lo[2], b->hi[2]}, D0 = {b->lo[0], b->hi[0]}, FI = {b->lo[1], b->hi[1]};
+  const double dS = (double)s * h->d;
+  if (h->axial) {                                               /* tan(tau) = 0: d^Ax = d^St */
+    *lo = sig * dS;
+    *hi = sig * dS;
+    return 1;
+  }
+  const iv KP = sig > 0.0 ? K : iv_neg(K), D0P = sig > 0.0 ? D0 : iv_neg(D0);
+  const iv SF = iv_sin(FI), CP0 = iv_cos(FI);
+  const iv SP0 = sig > 0.0 ? SF : iv_neg(SF);
+  const iv R = {or_wdn(1.0 / KP.hi), or_wup(1.0 / KP.lo)};
+  const iv RD = iv_add(R, D0P);
+  const iv XC = iv_neg(iv_mul(RD, SP0)), YC = iv_mul(RD, CP0);
+  const double py = sig * h->py, cps = sig * h->cphis, sps = h->sphis;
+  const iv DX = iv_sub(iv_point(h->px), XC), DY = iv_sub(iv_point(py), YC);
+  const iv RAX2 = iv_add(iv_sqr(DX), iv_sqr(DY));
+  if (!(RAX2.lo > 0.0)) return 0;
+  const iv RAX = iv_sqrt(RAX2);
+  const iv CAX = iv_sub(iv_mulp(DX, sps), iv_mulp(DY, cps));
+  const iv SAX = iv_add(iv_mulp(DX, cps), iv_mulp(DY, sps));
+  const iv SINA = iv_divpos(SAX, RAX), COSA = iv_divpos(CAX, RAX);
+  const iv YY = iv_add(iv_mul(DX, CP0), iv_mul(DY, SP0)), XX = iv_sub(iv_mul(DX, SP0), iv_mul(DY, CP0));
+  const iv DPHI = iv_atan2(YY, XX);
+  const iv Z0 = {b->lo[3], b->hi[3]}, LAM = {b->lo[4], b->hi[4]};
+  const double tt = h->tant;
+  const iv T2 = {or_wdn(tt * tt), or_wup(tt * tt)};
+  /* every solution of Eq. CSAXtoPHI_a over the box */
+  iv EPS = {-2.0 * PIO2_UP, 2.0 * PIO2_UP};
+  iv_stpoint q;
+  for (int k = 0; k < OR_IV_ITERS; k++) {
+    if (!iv_stereo_point(EPS, SINA, COSA, LAM, tt, T2, dS, R, DPHI, Z0, CAX, SAX, &q)) return 0;
+    const iv ST = iv_neg(iv_add(iv_mul(q.ld, CAX), iv_mul(q.zS, SAX)));
+    const iv DEN = iv_add(RAX2, iv_mulp(q.ctau, tt));
+    if (!(DEN.lo > 0.0)) return 0;
+    const iv F = iv_atan2(iv_mulp(ST, tt), DEN);
+    EPS.lo = fmax(EPS.lo, F.lo);
+    EPS.hi = fmin(EPS.hi, F.hi);
+    if (!(EPS.lo <= EPS.hi)) return 0;
+  }
+  if (!iv_stereo_point(EPS, SINA, COSA, LAM, tt, T2, dS, R, DPHI, Z0, CAX, SAX, &q)) return 0;
+  const iv A1 = iv_mulp(q.zS, tt), A2 = iv_mulp(q.ld, tt);
+  const iv Q = iv_add(iv_add(iv_mulp(iv_twice(q.ctau), tt), iv_sqr(A1)), iv_sqr(A2));
+  const iv A = iv_add(R, q.delta);
+  const iv DISC = iv_sub(iv_sqr(A), Q);
+  if (!(DISC.lo > 0.0) || !(A.lo > 0.0)) return 0;
+  const iv DHAT = iv_sub(q.delta, iv_divpos(Q, iv_add(A, iv_sqrt(DISC))));
+  const iv E = sig > 0.0 ? DHAT : iv_neg(DHAT);
+  if (!isfinite(E.lo) || !isfinite(E.hi)) return 0;
+  *lo = E.lo;
+  *hi = E.hi;
+  return 1;
+}
+
+/* the vote of one (box, hit) at an IV level: zero in 2G - 2E - kappa E^2 for
+ * either drift sign, with E the box enclosure of d^Ax widened by the band;
+ * no enclosure: the pair votes */
+int32_t or_pair_vote_iv(const or_prep *h, const or_box *b) {
+  if (!h->valid) return 0;
+  if (h->axial) return or_pair_vote(h, b, NULL);
+  const iv K = {b->lo[2], b->hi[2]};
+  const iv G = pair_G(h, b);
+  for (int32_t si = 0; si < 2; si++) {
+    double lo, hi;
+    if (!or_stereo_encl(h, b, si == 0 ? 1 : -1, &lo, &hi)) return 1;
+    const iv E = {or_wdn(lo - h->band), or_wup(hi + h->band)};
+    const iv H = iv_sub(iv_twice(G), iv_add(iv_twice(E), iv_mul(K, iv_sqr(E))));
+    if (H.lo <= 0.0 && 0.0 <= H.hi) return 1;
+  }
+  return 0;
+}
+
+/* ------------------------------------------------------------------------
  * Forward-hit test.  The paper's particles come from the origin (Sec. 3.2),
  * so along the direction of travel every hit lies after the point of
  * closest approach.  Without this, the perigee form holds every helix twice:
@@ -507,28 +651,52 @@ double or_point_G(const or_prep *h, const double p[5]) {
 /* ------------------------------------------------------------------------
  * FP32 levels of a mixed-precision schedule.
  *
- * The paper computes in FP64 throughout.  A level marked FP32 decides a
- * (box, stereo hit) pair by the following definition:
- *  - what depends on the box only through (d0, phi0, kappa) -- the
- *    enclosure G of Eq. ApoVote and the transverse quantities of d^Ax
- *    (R, R^Ax, c^Ax, s^Ax, sin and cos Phi^Ax, phi^Ax - phi0) -- is computed
- *    in FP64 exactly as in or_pair_vote and or_stereo_e; G and the kappa
- *    interval are then rounded outward to FP32, the point quantities to
- *    nearest;
- *  - the part of d^Ax that depends on the centre (z0, tanl) is evaluated in
- *    FP32, in the operation order of or_stereo_e;
+ * The paper computes in FP64 throughout.  A level marked FP32 evaluates the
+ * whole predicate of a (box, hit) pair in FP32:
+ *  - the box edges enter as FP32 intervals rounded outward, the hit's
+ *    prepared quantities (FP64, once per hit) rounded outward where they are
+ *    intervals (r, r^2, phi_P) and to nearest where they are points;
+ *  - G of Eq. ApoVote (kappa-scaled) is enclosed over the box in FP32
+ *    interval arithmetic with the operations of pair_G and an FP32 sine
+ *    enclosure (or_sinf at the ends, a 2^-20 margin, extrema wherever they
+ *    may lie);
+ *  - d^Ax is the FP32 point evaluation, at the box centre rounded to FP32,
+ *    of or_stereo_e's operations: the transverse quantities with or_sinf,
+ *    or_cosf and or_atan2f, then the (z0, tanl) part (sin and cos of the
+ *    small correction by the degree-11/12 polynomials);
  *  - the vote is the interval test of or_pair_vote in FP32, each result
  *    widened by |x| 2^-23 + 2^-149 (at least one FP32 ulp), with the
- *    tolerance band widened by `slack`, a bound on |e32 - e64|;
- *  - the FP32 evaluation is used only inside the domain where that bound
- *    holds (R <= 2048 m, |Phi - Phi^Ax| <= 1, a positive discriminant, a
- *    finite result); outside it the pair votes.
- * Axial hits are decided exactly as at FP64 levels.  If |e32 - e64| <= slack,
- * every FP32 interval contains the matching FP64 one (the operations are
- * inclusion-monotone and FP32 outward rounding is wider than FP64), so an
- * FP32 level votes for every pair an FP64 level votes for.
+ *    tolerance band widened by `slack` + 2^-24 R, a bound on |e32 - e64|
+ *    (the transverse quantities are of size R and carry FP32 rounding
+ *    2^-24 relative; measured |e32 - e64| <= 6.2e-9 R + 1e-9 m over the
+ *    search range); axial hits take e = +-d (no slack: it is exact);
+ *  - the FP32 evaluation of d^Ax is used only inside the domain where that
+ *    bound holds (R <= 2048 m, |Phi - Phi^Ax| <= 1, a positive
+ *    discriminant, a finite result); outside it the pair votes.
+ * Every FP32 interval contains the matching FP64 one: the inputs are rounded
+ * outward, the operations are inclusion-monotone, an FP32 outward rounding
+ * moves an end at least half an FP32 ulp past the exact value (more than
+ * FP64's two ulps), and the sine margin 2^-20 covers or_sinf's error and the
+ * FP64 enclosure's 2^-50.  With |e32 - e64| <= slack + 2^-24 R, an FP32
+ * level votes for every pair an FP64 level votes for.
  * ---------------------------------------------------------------------- */
 static const double R32_MAX = 2048.0;
+
+/* pi/2 = P1 + P2 + P3 (+ 2e-15): P1 and P2 carry 11 significant bits, so
+ * k P1 and k P2 are exact for |k| < 2^13 */
+#define PIO2F_1 0x1.92p+0f
+#define PIO2F_2 0x1.fb4p-12f
+#define PIO2F_3 0x1.4442d2p-24f
+#define TWO_OVER_PI_F 0x1.45f306p-1f
+#define PI_F 0x1.921fb6p+1f          /* pi rounded to nearest (above) */
+#define PIO2_F 0x1.921fb6p+0f        /* pi/2 rounded to nearest (above) */
+#define TWO_PI_F 0x1.921fb6p+2f
+#define INV_TWO_PI_F 0x1.45f306p-3f
+#define PIO6_F 0x1.0c1524p-1f
+#define SQRT3_F 0x1.bb67aep+0f
+#define TAN_PI12_F 0x1.126146p-2f
+#define SIN_MARGIN_F 0x1p-20f        /* > 4x the error of or_sinf / or_cosf for |x| <= 64 */
+#define EXT_FUZZ_F 0x1p-12f          /* extremum-membership slack (in turns) */
 
 /* the FP32 numbers next to x: largest <= x, smallest >= x */
 float or_rd32(double x) {
@@ -583,82 +751,178 @@ float or_cosf1(float x) {
   return fmaf(z, q, 1.0f);
 }
 
-/* d^Ax at the point c for drift sign s, FP32 part as defined above.
+/* sin and cos of any argument with |x| <= 64: reduction by pi/2 (the
+ * three-part constant above, in FP32), then the polynomials on |r| <= pi/4 */
+static float reduce_f(float x, int *q) {
+  float k = rintf(x * TWO_OVER_PI_F);
+  float r = ((x - k * PIO2F_1) - k * PIO2F_2) - k * PIO2F_3;
+  *q = (int)k & 3;
+  return r;
+}
+float or_sinf(float x) {
+  int q;
+  float r = reduce_f(x, &q);
+  float v = (q & 1) ? or_cosf1(r) : or_sinf1(r);
+  return (q & 2) ? -v : v;
+}
+float or_cosf(float x) {
+  int q;
+  float r = reduce_f(x, &q);
+  float v = (q & 1) ? or_sinf1(r) : or_cosf1(r);
+  return ((q + 1) & 2) ? -v : v;
+}
+
+/* atan on |u| <= tan(pi/12): Taylor series to degree 13 (first omitted term
+ * below 3e-10) */
+static float atan_f(float u) {
+  float z = u * u;
+  float p = 1.0f / 13.0f;
+  p = fmaf(p, z, -1.0f / 11.0f);
+  p = fmaf(p, z, 1.0f / 9.0f);
+  p = fmaf(p, z, -1.0f / 7.0f);
+  p = fmaf(p, z, 1.0f / 5.0f);
+  p = fmaf(p, z, -1.0f / 3.0f);
+  return fmaf(u * z, p, u);
+}
+/* angle of (x, y) in [-pi, pi], the octant reduction of or_atan2 in FP32 */
+float or_atan2f(float y, float x) {
+  float ax = fabsf(x), ay = fabsf(y);
+  if (ax == 0.0f && ay == 0.0f) return 0.0f;
+  int swap = ay > ax;
+  float t = swap ? ax / ay : ay / ax;
+  float a;
+  if (t > TAN_PI12_F) a = PIO6_F + atan_f((t * SQRT3_F - 1.0f) / (t + SQRT3_F));
+  else a = atan_f(t);
+  if (swap) a = PIO2_F - a;
+  if (x < 0.0f) a = PI_F - a;
+  if (y < 0.0f) a = -a;
+  return a;
+}
+
+/* FP32 enclosure of sin over [a, b] (as or_sin_encl) */
+void or_sin_encl32(float a, float b, float *lo, float *hi) {
+  if (b - a >= TWO_PI_F) { *lo = -1.0f; *hi = 1.0f; return; }
+  float va = or_sinf(a), vb = or_sinf(b);
+  float l = fminf(va, vb) - SIN_MARGIN_F, h = fmaxf(va, vb) + SIN_MARGIN_F;
+  if (floorf((b - PIO2_F) * INV_TWO_PI_F + EXT_FUZZ_F) >= ceilf((a - PIO2_F) * INV_TWO_PI_F - EXT_FUZZ_F)) h = 1.0f;
+  if (floorf((b + PIO2_F) * INV_TWO_PI_F + EXT_FUZZ_F) >= ceilf((a + PIO2_F) * INV_TWO_PI_F - EXT_FUZZ_F)) l = -1.0f;
+  *lo = fmaxf(l, -1.0f);
+  *hi = fminf(h, 1.0f);
+}
+
+/* d^Ax at the point c for drift sign s, in FP32 as defined above.
  * Returns 1 and writes e32 = sgn(kappa) d^Ax, or 0 outside the FP32 domain
  * (then the caller votes).  dbg (nullable, 24 floats): as or_stereo_e. */
 int32_t or_stereo_e32(const or_prep *h, const double c[5], int32_t s, float *e, float *dbg) {
-  /* FP64: the transverse frame, as in or_stereo_e */
-  double kap = c[2], sig = 1.0;
-  if (kap < 0.0) sig = -1.0;
-  if (kap == 0.0) { kap = 0x1p-30; sig = 1.0; }
-  double kp = sig * kap, d0p = sig * c[0];
-  double sp0 = sig * or_sin(c[1]), cp0 = or_cos(c[1]);
-  double R = 1.0 / kp;
-  double Rd = R + d0p;
-  double xc = -(Rd * sp0), yc = Rd * cp0;
-  double py = sig * h->py, cps = sig * h->cphis, sps = h->sphis;
-  double Dx = h->px - xc, Dy = py - yc;
-  double RAx = sqrt(Dx * Dx + Dy * Dy);
-  double cAx = Dx * sps - Dy * cps;
-  double sAx = Dx * cps + Dy * sps;
-  double sinA = sAx / RAx, cosA = cAx / RAx;
-  double dphi = or_atan2(Dx * cp0 + Dy * sp0, Dx * sp0 - Dy * cp0);
+  float cf[5];
+  for (int j = 0; j < 5; j++) cf[j] = (float)c[j];   /* the centre, rounded to nearest */
+  float kap = cf[2], sig = 1.0f;
+  if (kap < 0.0f) sig = -1.0f;
+  if (kap == 0.0f) { kap = 0x1p-30f; sig = 1.0f; }
+  const float kp = sig * kap, d0p = sig * cf[0];
+  const float sp0 = sig * or_sinf(cf[1]), cp0 = or_cosf(cf[1]);
+  const float R = 1.0f / kp;
   if (!(R <= R32_MAX)) return 0;
-  /* round to FP32 */
-  const float fR = (float)R, fRAx = (float)RAx, fcAx = (float)cAx, fsAx = (float)sAx;
-  const float fsinA = (float)sinA, fcosA = (float)cosA, fdphi = (float)dphi;
-  const float fsArc = (float)(R * dphi);
-  const float fc2 = (float)(cosA * cosA - sinA * sinA), fs2 = (float)(2.0 * sinA * cosA);
-  const float ftwoRAx2 = (float)(2.0 * (RAx * RAx)), fRpRAx = (float)(R + RAx);
-  const float z0 = (float)c[3], lam = (float)c[4], tt = (float)h->tant;
+  const float Rd = R + d0p;
+  const float xc = -(Rd * sp0), yc = Rd * cp0;
+  const float py = sig * (float)h->py, cps = sig * (float)h->cphis, sps = (float)h->sphis;
+  const float Dx = (float)h->px - xc, Dy = py - yc;
+  const float RAx = sqrtf(Dx * Dx + Dy * Dy);
+  const float cAx = Dx * sps - Dy * cps;
+  const float sAx = Dx * cps + Dy * sps;
+  const float sinA = sAx / RAx, cosA = cAx / RAx;
+  const float dphi = or_atan2f(Dx * cp0 + Dy * sp0, Dx * sp0 - Dy * cp0);
+  const float sArc = R * dphi;
+  const float c2 = cosA * cosA - sinA * sinA, s2 = 2.0f * sinA * cosA;
+  const float twoRAx2 = 2.0f * (RAx * RAx), RpRAx = R + RAx;
+  const float z0 = cf[3], lam = cf[4], tt = (float)h->tant;
   const float dS = (float)s * (float)h->d;
-  /* FP32: the (z0, tanl) part, in the order of or_stereo_e */
-  float zA = z0 + lam * fsArc;
-  float Phi1 = -(zA * fsinA + (lam * dS) * fcosA) / fRAx;
-  float Phi2n = (lam * fR) * zA - ((lam * zA) * (fR - 2.0f * dS)) * fc2
-              + (zA * zA + dS * (fRAx + (lam * lam) * (fRpRAx - dS))) * fs2;
-  float Phi2 = Phi2n / ftwoRAx2;
+  /* the (z0, tanl) part, in the order of or_stereo_e */
+  float zA = z0 + lam * sArc;
+  float Phi1 = -(zA * sinA + (lam * dS) * cosA) / RAx;
+  float Phi2n = (lam * R) * zA - ((lam * zA) * (R - 2.0f * dS)) * c2
+              + (zA * zA + dS * (RAx + (lam * lam) * (RpRAx - dS))) * s2;
+  float Phi2 = Phi2n / twoRAx2;
   float t2 = tt * tt;
   float eps = Phi1 * tt + Phi2 * t2;
   if (!(fabsf(eps) <= 1.0f)) return 0;
   float se = or_sinf1(eps), ce = or_cosf1(eps);
-  float sinP = fsinA * ce + fcosA * se, cosP = fcosA * ce - fsinA * se;
+  float sinP = sinA * ce + cosA * se, cosP = cosA * ce - sinA * se;
   float u = sqrtf(((1.0f + ((2.0f * lam) * sinP) * tt) + (lam * lam) * t2) + (cosP * cosP) * t2);
   float delta = dS / u;
-  float sperp = fR * (fdphi + eps);
+  float sperp = R * (dphi + eps);
   float zS = (z0 + lam * sperp) - (delta * cosP) * tt;
-  float ctau = zS * fcAx - (lam * delta) * fsAx;
+  float ctau = zS * cAx - (lam * delta) * sAx;
   float a1 = zS * tt, a2 = (lam * delta) * tt;
   float Q = ((2.0f * ctau) * tt + a1 * a1) + a2 * a2;
-  float A = fR + delta;
+  float A = R + delta;
   float disc = A * A - Q;
   if (!(disc > 0.0f)) return 0;
   float dhat = delta - Q / (A + sqrtf(disc));
   if (dbg) {
-    float v[24] = {fR, (float)xc, (float)yc, (float)Dx, (float)Dy, fRAx, fcAx, fsAx, fsinA, fcosA, fdphi,
+    float v[24] = {R, xc, yc, Dx, Dy, RAx, cAx, sAx, sinA, cosA, dphi,
                    zA, Phi1, Phi2, eps, sinP, cosP, u, delta, sperp, zS, ctau, Q, dhat};
     memcpy(dbg, v, sizeof v);
   }
-  *e = (float)sig * dhat;
+  *e = sig * dhat;
   return isfinite(*e) ? 1 : 0;
+}
+
+/* G of Eq. ApoVote (kappa-scaled) over the box, in FP32 intervals with the
+ * operations of pair_G */
+static ivf pair_G32(const or_prep *h, const or_box *b) {
+  ivf K = {or_rd32(b->lo[2]), or_ru32(b->hi[2])}, Dd = {or_rd32(b->lo[0]), or_ru32(b->hi[0])};
+  ivf Fi = {or_rd32(b->lo[1]), or_ru32(b->hi[1])};
+  ivf P = {or_rd32(h->phip), or_ru32(h->phip)};
+  ivf Ar = {or_wdn32(Fi.lo - P.hi), or_wup32(Fi.hi - P.lo)};
+  ivf S;
+  or_sin_encl32(Ar.lo, Ar.hi, &S.lo, &S.hi);
+  ivf r = {or_rd32(h->r), or_ru32(h->r)};
+  ivf rS = ivf_mul(S, r);
+  ivf D2 = ivf_sqr(Dd);
+  ivf T0 = ivf_add(D2, (ivf){or_rd32(h->r2lo), or_ru32(h->r2hi)});
+  ivf T = {0.5f * T0.lo, 0.5f * T0.hi};
+  ivf KT = ivf_mul(K, T);
+  ivf KD1 = ivf_add(ivf_mul(K, Dd), (ivf){1.0f, 1.0f});
+  return ivf_add(ivf_add(KT, ivf_mul(KD1, rS)), Dd);
+}
+
+void or_pair_G32(const or_prep *h, const or_box *b, float *lo, float *hi) {
+  ivf G = pair_G32(h, b);
+  *lo = G.lo;
+  *hi = G.hi;
 }
 
 /* the vote of one (box, hit) at an FP32 level; dbg (nullable, 8 floats):
  * G lo/hi, H+ lo/hi, H- lo/hi, e+, e- */
 int32_t or_pair_vote32(const or_prep *h, const or_box *b, double slack, float *dbg) {
   if (!h->valid) return 0;
-  if (h->axial) return or_pair_vote(h, b, NULL);
-  const iv G64 = pair_G(h, b);
-  ivf G = {or_rd32(G64.lo), or_ru32(G64.hi)};
-  ivf K = {or_rd32(b->lo[2]), or_ru32(b->hi[2])};
-  const float bs = or_wup32(or_ru32(h->band) + or_ru32(slack));
-  double c[5];
-  for (int j = 0; j < 5; j++) c[j] = 0.5 * (b->lo[j] + b->hi[j]);
+  const ivf G = pair_G32(h, b);
+  const ivf K = {or_rd32(b->lo[2]), or_ru32(b->hi[2])};
   int32_t vote = 0;
   if (dbg) { dbg[0] = G.lo; dbg[1] = G.hi; for (int j = 2; j < 8; j++) dbg[j] = NAN; }
+  if (h->axial) {
+    /* e = sgn(kappa) (+-d) exactly: its FP32 interval needs no slack */
+    const double kc = 0.5 * (b->lo[2] + b->hi[2]);
+    const float sig = (float)kc < 0.0f ? -1.0f : 1.0f;
+    const float blo = or_ru32(h->band);
+    for (int32_t si = 0; si < 2; si++) {
+      const double e = (double)sig * (si == 0 ? h->d : -h->d);
+      ivf E = {or_wdn32(or_rd32(e) - blo), or_wup32(or_ru32(e) + blo)};
+      ivf H = ivf_sub(ivf_twice(G), ivf_add(ivf_twice(E), ivf_mul(K, ivf_sqr(E))));
+      if (dbg) { dbg[2 + 2 * si] = H.lo; dbg[3 + 2 * si] = H.hi; dbg[6 + si] = (float)e; }
+      if (H.lo <= 0.0f && 0.0f <= H.hi) vote = 1;
+    }
+    return vote;
+  }
+  double c[5];
+  for (int j = 0; j < 5; j++) c[j] = 0.5 * (b->lo[j] + b->hi[j]);
+  float dbg24[24];
   for (int32_t si = 0; si < 2; si++) {
     float e;
-    if (!or_stereo_e32(h, c, si == 0 ? 1 : -1, &e, NULL)) { vote = 1; continue; }
+    if (!or_stereo_e32(h, c, si == 0 ? 1 : -1, &e, dbg24)) { vote = 1; continue; }
+    /* the band widened by slack + 2^-24 R (R = dbg24[0], the centre's radius) */
+    const float bs = or_wup32(or_wup32(or_ru32(h->band) + or_ru32(slack)) + dbg24[0] * 0x1p-24f);
     ivf E = {or_wdn32(e - bs), or_wup32(e + bs)};
     ivf H = ivf_sub(ivf_twice(G), ivf_add(ivf_twice(E), ivf_mul(K, ivf_sqr(E))));
     if (dbg) { dbg[2 + 2 * si] = H.lo; dbg[3 + 2 * si] = H.hi; dbg[6 + si] = e; }
@@ -696,6 +960,7 @@ static void vote_prepped(const or_prep *pr, const uint8_t *use, int32_t n_hits,
     for (int32_t i = 0; i < n_hits; i++) {
       if (!use[i] || (fwd == 1 && !or_forward(&pr[i], &box))) continue;
       v += prec == OR_FP32 ? or_pair_vote32(&pr[i], &box, slack, NULL)
+         : prec == OR_IV   ? or_pair_vote_iv(&pr[i], &box)
                            : or_pair_vote_x(&pr[i], &box, prec == OR_FP64X, NULL);
     }
     votes[b] = (uint16_t)v;

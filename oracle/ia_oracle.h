@@ -43,9 +43,11 @@ typedef struct {
 
 #define OR_MAX_LEVELS 8
 /* per-level arithmetic: FP64 with the second-order Phi of Eq. ApproxPhi,
- * FP32 (see the source), FP64 with the exact Phi of Eq. CSAXtoPHI_a */
-enum { OR_FP64 = 0, OR_FP32 = 1, OR_FP64X = 2 };
+ * FP32 (see the source), FP64 with the exact Phi of Eq. CSAXtoPHI_a, or the
+ * sound enclosure of d^Ax over the whole box (OR_IV) */
+enum { OR_FP64 = 0, OR_FP32 = 1, OR_FP64X = 2, OR_IV = 3 };
 #define OR_PHI_ITERS 3   /* fixed-point steps of Eq. CSAXtoPHI_a at OR_FP64X */
+#define OR_IV_ITERS 6    /* interval fixed-point steps of Eq. CSAXtoPHI_a at OR_IV */
 enum { OR_TOPK = 0, OR_WINDOW = 1 };
 
 typedef struct {
@@ -124,6 +126,11 @@ int32_t or_stereo_e_x(const or_prep *h, const double c[5], int32_t s, int32_t ex
 int32_t or_pair_vote(const or_prep *h, const or_box *b, double *dbg);
 /* the same with d^Ax from or_stereo_e_x(.., exact, ..) */
 int32_t or_pair_vote_x(const or_prep *h, const or_box *b, int32_t exact, double *dbg);
+/* IV levels: an enclosure of e = sgn(kappa) d^Ax over the whole box for drift
+ * sign s (1), or 0 when none (kappa of both signs, a bound that fails); and
+ * the vote with it */
+int32_t or_stereo_encl(const or_prep *h, const or_box *b, int32_t s, double *lo, double *hi);
+int32_t or_pair_vote_iv(const or_prep *h, const or_box *b);
 
 /* Forward-hit test: 1 when the hit point lies ahead of the point of closest
  * approach (x cos phi0 + y sin phi0 > 0) for some phi0 of the box, 0 when it
@@ -141,9 +148,9 @@ void or_frame_shift(const double p[5], double dx, double dy, double q[5]);
 double or_point_G(const or_prep *h, const double p[5]);
 
 /* FP32 levels (see the source for the definition): outward and nearest
- * FP64 -> FP32 conversions, FP32 widening, sin/cos on |x| <= 1, d^Ax with
- * its (z0, tanl) part in FP32 (returns 0 outside the FP32 domain), and the
- * vote of one (box, hit) with the band widened by slack. */
+ * FP64 -> FP32 conversions, FP32 widening, sin/cos on |x| <= 1, d^Ax in
+ * FP32 (returns 0 outside the FP32 domain), and the vote of one (box, hit)
+ * in FP32 with the band widened by slack. */
 float or_rd32(double x);
 float or_ru32(double x);
 float or_wdn32(float x);
@@ -151,6 +158,13 @@ float or_wup32(float x);
 float or_sinf1(float x);
 float or_cosf1(float x);
 int32_t or_stereo_e32(const or_prep *h, const double c[5], int32_t s, float *e, float *dbg);
+/* FP32 sin, cos (|x| <= 64), atan2, the FP32 sine enclosure and G of
+ * Eq. ApoVote over a box in FP32 intervals */
+float or_sinf(float x);
+float or_cosf(float x);
+float or_atan2f(float y, float x);
+void or_sin_encl32(float a, float b, float *lo, float *hi);
+void or_pair_G32(const or_prep *h, const or_box *b, float *lo, float *hi);
 int32_t or_pair_vote32(const or_prep *h, const or_box *b, double slack, float *dbg);
 
 /* votes[parent * prod(split) + child] for every child box of every parent.

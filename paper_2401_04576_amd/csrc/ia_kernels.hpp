@@ -844,6 +844,96 @@ IA_HD PairQ32 pair_q32(const PairQ& q, const HitRec& h, float slack32) {
   return r;
 }
 
+// FP32 levels evaluate the whole predicate in FP32: the box's (d0, phi0,
+// kappa) ranges rounded outward, its centre rounded to nearest, G of Eq.
+// ApoVote in FP32 intervals with the FP32 sine enclosure, the transverse
+// quantities of d^Ax in FP32 (sinf32, cosf32, atan2f32), and the band
+// widened by slack + 2^-24 R, a bound on |e32 - e64| (the transverse
+// quantities are of size R with FP32 rounding).  No class proofs run at
+// such levels; the per-box test is stereo_vote32 on these quantities.
+struct Frame32 {
+  Iv32 K, Dd, Fi;
+  float sig, R, xc, yc, sp0, cp0;
+};
+
+IA_HD Frame32 frame32_of(const Frame& f) {
+  Frame32 g;
+  g.Dd = {rd32(f.Dd.lo), ru32(f.Dd.hi)};
+  g.Fi = {rd32(f.Fi.lo), ru32(f.Fi.hi)};
+  g.K = {rd32(f.K.lo), ru32(f.K.hi)};
+  const float c0 = static_cast<float>(0.5 * (f.Dd.lo + f.Dd.hi)), c1 = static_cast<float>(0.5 * (f.Fi.lo + f.Fi.hi));
+  float kap = static_cast<float>(0.5 * (f.K.lo + f.K.hi)), sig = 1.0f;
+  if (kap < 0.0f) sig = -1.0f;
+  if (kap == 0.0f) { kap = 0x1p-30f; sig = 1.0f; }
+  const float kp = sig * kap, d0p = sig * c0;
+  g.sp0 = sig * sinf32(c1);
+  g.cp0 = cosf32(c1);
+  g.R = 1.0f / kp;
+  const float Rd = g.R + d0p;
+  g.xc = -(Rd * g.sp0);
+  g.yc = Rd * g.cp0;
+  g.sig = sig;
+  return g;
+}
+
+IA_HD Iv32 residual_G32(const Frame32& f, const HitRec& h) {
+  const Iv32 P = {rd32(h.phip), ru32(h.phip)};
+  const Iv32 Ar = {wdn32(f.Fi.lo - P.hi), wup32(f.Fi.hi - P.lo)};
+  const Iv32 S = sin_encl32(Ar.lo, Ar.hi);
+  const Iv32 r = {rd32(h.r), ru32(h.r)};
+  const Iv32 rS = imul32(S, r);
+  const Iv32 D2 = isqr32(f.Dd);
+  const Iv32 T0 = iadd32(D2, Iv32{rd32(h.r2lo), ru32(h.r2hi)});
+  const Iv32 T = {0.5f * T0.lo, 0.5f * T0.hi};
+  const Iv32 KT = imul32(f.K, T);
+  const Iv32 KD1 = iadd32(imul32(f.K, f.Dd), Iv32{1.0f, 1.0f});
+  return iadd32(iadd32(KT, imul32(KD1, rS)), f.Dd);
+}
+
+// an axial pair at an FP32 level: e = +-d exactly, no slack
+IA_HD int axial_class32(const Frame32& f, const HitRec& h) {
+  const Iv32 G = residual_G32(f, h);
+  const float b = ru32(h.band);
+  for (int si = 0; si < 2; ++si) {
+    const double e = static_cast<double>(f.sig) * (si == 0 ? h.d : -h.d);
+    const Iv32 E = {wdn32(rd32(e) - b), wup32(ru32(e) + b)};
+    const Iv32 H = isub32(itwice32(G), iadd32(itwice32(E), imul32(f.K, isqr32(E))));
+    if (H.lo <= 0.0f && 0.0f <= H.hi) return 1;
+  }
+  return 0;
+}
+
+// the staged record of a stereo pair at an FP32 level
+IA_HD PairQ32 pair_q32_f32(const Frame32& f, const HitRec& h, float slack32) {
+  PairQ32 r;
+  const Iv32 G = residual_G32(f, h);
+  const float py = f.sig * static_cast<float>(h.py), cps = f.sig * static_cast<float>(h.cphis);
+  const float sps = static_cast<float>(h.sphis);
+  const float Dx = static_cast<float>(h.px) - f.xc, Dy = py - f.yc;
+  const float RAx = sqrtf(Dx * Dx + Dy * Dy);
+  const float cAx = Dx * sps - Dy * cps;
+  const float sAx = Dx * cps + Dy * sps;
+  const float sinA = sAx / RAx, cosA = cAx / RAx;
+  const float dphi = atan2f32(Dx * f.cp0 + Dy * f.sp0, Dx * f.sp0 - Dy * f.cp0);
+  r.Glo = G.lo;
+  r.Ghi = G.hi;
+  r.sArc = f.R * dphi;
+  r.dphi = dphi;
+  r.RAx = RAx;
+  r.sinA = sinA;
+  r.cosA = cosA;
+  r.sAx = sAx;
+  r.cAx = cAx;
+  r.c2 = cosA * cosA - sinA * sinA;
+  r.s2 = 2.0f * sinA * cosA;
+  r.twoRAx2 = 2.0f * (RAx * RAx);
+  r.RpRAx = f.R + RAx;
+  r.tt = static_cast<float>(h.tant);
+  r.d = static_cast<float>(h.d);
+  r.bs = wup32(wup32(ru32(h.band) + slack32) + f.R * 0x1p-24f);
+  return r;
+}
+
 // a staged (triple, stereo hit) record at FP64 levels: the pair quantities
 // and the hit's tan(tau), drift and band (128 bytes)
 struct RecD {
@@ -1015,6 +1105,14 @@ IA_HD int parent_range_signs(const ParentE& pe, Iv Go) {
 template <bool F32>
 IA_HD int pair_stage1(const Frame& f, const GTri& g, const HitRec& h, Iv Z, Iv L, int32_t filter, float slack32,
                       int32_t* cnt, const ParentE* pe = nullptr) {
+  if constexpr (F32) {
+    // FP32 levels: no class proofs; an axial pair's class is exact, a
+    // stereo pair outside the FP32 domain votes in every box
+    const Frame32 g32 = frame32_of(f);
+    if (cnt) ++cnt[kCwG];
+    if (h.axial) return axial_class32(g32, h);
+    return g32.R <= static_cast<float>(kR32Max) ? 2 : 1;
+  }
   const Iv Go = residual_G_outer(f, g, h);
   if (cnt) ++cnt[kCwG];
   if (h.axial) {
@@ -1764,12 +1862,14 @@ __global__ void __launch_bounds__(kWG, 4) k_stage(const HitRec* __restrict__ hit
     const HitRec hr = hits[h];
     const uint32_t tc = t % sh.m012;
     const Frame f = triple_frame(parents[t / sh.m012], sh.m, tc / sh.m12, (tc / sh.m[2]) % sh.m[1], tc % sh.m[2]);
-    const Iv G = residual_G(f, hr);
-    const PairQ q = pair_quantities(f, hr, G);
     const int64_t slot = int64_t(e) * vw.rec_stride + rec_off[t] + atomicAdd(&rec_fill[t], 1);
     if constexpr (F32) {
-      reinterpret_cast<PairQ32*>(rec)[slot] = pair_q32(q, hr, slack32);
+      const Frame32 g32 = frame32_of(f);
+      reinterpret_cast<PairQ32*>(rec)[slot] = pair_q32_f32(g32, hr, slack32);
+      tfr[t] = TriFrame{static_cast<double>(g32.R), static_cast<double>(g32.sig), f.K.lo, f.K.hi};
     } else {
+      const Iv G = residual_G(f, hr);
+      const PairQ q = pair_quantities(f, hr, G);
       RecD r;
       r.q[0] = q.Glo; r.q[1] = q.Ghi; r.q[2] = q.sArc; r.q[3] = q.dphi; r.q[4] = q.RAx; r.q[5] = q.sinA;
       r.q[6] = q.cosA; r.q[7] = q.sAx; r.q[8] = q.cAx; r.q[9] = q.c2; r.q[10] = q.s2; r.q[11] = q.twoRAx2;
@@ -1778,8 +1878,8 @@ __global__ void __launch_bounds__(kWG, 4) k_stage(const HitRec* __restrict__ hit
       r.d = hr.d;
       r.band = hr.band;
       reinterpret_cast<RecD*>(rec)[slot] = r;
+      tfr[t] = TriFrame{f.R, f.sig, f.K.lo, f.K.hi};
     }
-    tfr[t] = TriFrame{f.R, f.sig, f.K.lo, f.K.hi};
   }
 }
 
@@ -1994,8 +2094,14 @@ __global__ void __launch_bounds__(kWG) k_vote(const HitRec* __restrict__ hits, E
       child_edge(P.lo[4], P.hi[4], sh.m[4], k[4], &llo, &lhi);
       const double z0 = 0.5 * (zlo + zhi), lam = 0.5 * (llo + lhi);
       const double lamR = lam * f.R, lam2 = lam * lam;
-      // FP32 images of the lane's box (used at FP32 levels only)
-      const float R32 = static_cast<float>(f.R), sig32 = static_cast<float>(f.sig);
+      // FP32 images of the lane's box (used at FP32 levels only): the FP32
+      // frame's radius and sign, kappa rounded outward
+      float R32 = 0.0f, sig32 = 0.0f;
+      if constexpr (F32) {
+        const Frame32 g32 = frame32_of(f);
+        R32 = g32.R;
+        sig32 = g32.sig;
+      }
       const Iv32 K32 = to32(f.K);
       const float z032 = static_cast<float>(z0), lam32 = static_cast<float>(lam);
       const float lamR32 = lam32 * R32, lam232 = lam32 * lam32;
@@ -2014,17 +2120,17 @@ __global__ void __launch_bounds__(kWG) k_vote(const HitRec* __restrict__ hits, E
           const uint32_t tc = t % sh.m012;
           const uint32_t t0 = tc / sh.m12, t1 = (tc / sh.m[2]) % sh.m[1], t2 = tc % sh.m[2];
           const Frame ft = triple_frame(parents[t / sh.m012], sh.m, t0, t1, t2);
-          const Iv G = residual_G(ft, h);
-          const PairQ q = pair_quantities(ft, h, G);
           ++n_staged;
           sflag[slot] = 2;
           if constexpr (F32) {
-            const PairQ32 rq = pair_q32(q, h, slack32);
+            const PairQ32 rq = pair_q32_f32(frame32_of(ft), h, slack32);
             sq32[0][slot] = rq.Glo; sq32[1][slot] = rq.Ghi; sq32[2][slot] = rq.sArc; sq32[3][slot] = rq.dphi;
             sq32[4][slot] = rq.RAx; sq32[5][slot] = rq.sinA; sq32[6][slot] = rq.cosA; sq32[7][slot] = rq.sAx;
             sq32[8][slot] = rq.cAx; sq32[9][slot] = rq.c2; sq32[10][slot] = rq.s2; sq32[11][slot] = rq.twoRAx2;
             sq32[12][slot] = rq.RpRAx; sq32[13][slot] = rq.tt; sq32[14][slot] = rq.d; sq32[15][slot] = rq.bs;
           } else {
+            const Iv G = residual_G(ft, h);
+            const PairQ q = pair_quantities(ft, h, G);
             sq[0][slot] = q.Glo; sq[1][slot] = q.Ghi; sq[2][slot] = q.sArc; sq[3][slot] = q.dphi;
             sq[4][slot] = q.RAx; sq[5][slot] = q.sinA; sq[6][slot] = q.cosA; sq[7][slot] = q.sAx;
             sq[8][slot] = q.cAx; sq[9][slot] = q.c2; sq[10][slot] = q.s2; sq[11][slot] = q.twoRAx2;

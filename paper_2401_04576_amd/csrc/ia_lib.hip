@@ -222,9 +222,10 @@ ia_status launch_classify(ia_ctx* c, const HitRec* recs, const ia::EvView& vw, i
   const int32_t max_groups = std::max(1, (max_hits + ia::kWG / 64 - 1) / (ia::kWG / 64));
   const int32_t hg = static_cast<int32_t>(std::min<int64_t>(std::max<int64_t>(1, 2048 / base), std::min(max_groups, 64)));
   const dim3 g(gx, n_ev, hg);
-  // the class proofs enclose the ApproxPhi form of d^Ax: with the exact Phi
-  // every stereo pair is evaluated box by box
-  const int32_t filt = exact ? 0 : use_filter(c);
+  // the class proofs enclose the FP64 ApproxPhi form of d^Ax: with the
+  // exact Phi, and at FP32 levels (the whole predicate in FP32), every
+  // stereo pair is evaluated box by box
+  const int32_t filt = (exact || f32) ? 0 : use_filter(c);
   unsigned long long* wk = persistent(c)->work;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (c->profiling) {
@@ -588,7 +589,7 @@ ia_status run_window(ia_ctx* c, const double* hits, ia::EvView vw, int32_t E, in
     for (int32_t lev = 0; lev <= sc->n_refine; ++lev) {
       const bool f32 = sc->prec[lev] == IA_FP32, exact = sc->prec[lev] == IA_FP64X;
       vw.fwd = sc->forward;     // per event: hits ahead about the origin, origin behind after a move
-      const bool use_pf = lev > 0 && use_filter(c) && c->parent_filter && !exact;
+      const bool use_pf = lev > 0 && use_filter(c) && c->parent_filter && !exact && !f32;
       if (use_pf) {
         const int64_t n_pairs = int64_t(sh.n_parents) * std::max(1, cmax);
         const dim3 gp(static_cast<uint32_t>(std::min<int64_t>((n_pairs + ia::kWG - 1) / ia::kWG, 65535)), E);
@@ -750,7 +751,7 @@ ia_status run_chunk(ia_ctx* c, const double* hits_chunk, const int32_t* h_off_ch
       const bool f32 = sc->prec[lev] == IA_FP32, exact = sc->prec[lev] == IA_FP64X;
       // refinement levels: the parent-level test first (a hit it excludes
       // is class 0 for all of that parent's triples)
-      const bool use_pf = lev > 0 && use_filter(c) && c->parent_filter && !exact;
+      const bool use_pf = lev > 0 && use_filter(c) && c->parent_filter && !exact && !f32;
       if (use_pf) {
         const int64_t n_pairs = int64_t(sh.n_parents) * std::max(1, cmax);
         const dim3 gp(static_cast<uint32_t>(std::min<int64_t>((n_pairs + ia::kWG - 1) / ia::kWG, 65535)), E);

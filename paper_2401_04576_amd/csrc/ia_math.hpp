@@ -321,4 +321,74 @@ IA_HD void sincos_encl_small32(Iv32 x, Iv32* S, Iv32* C) {
   *C = {cos1_32(amax) - kSmallMargin32, has0 ? 1.0f : fminf(cos1_32(amin) + kSmallMargin32, 1.0f)};
 }
 
+// FP32 levels evaluate the whole predicate in FP32: sin and cos of any
+// argument with |x| <= 64 by reduction with a three-part pi/2 (11, 11 and 24
+// significant bits: k P1 and k P2 exact for |k| < 2^13) and the polynomials
+// above on |r| <= pi/4; atan2 by the octant reduction of atan2_p with a
+// degree-13 Taylor series on |u| <= tan(pi/12); the FP32 sine enclosure with
+// a 2^-20 margin (more than 4x the error of sinf32 there).
+constexpr float kPio2F1 = 0x1.92p+0f;
+constexpr float kPio2F2 = 0x1.fb4p-12f;
+constexpr float kPio2F3 = 0x1.4442d2p-24f;
+constexpr float kTwoOverPiF = 0x1.45f306p-1f;
+constexpr float kPiF = 0x1.921fb6p+1f;
+constexpr float kPio2F = 0x1.921fb6p+0f;
+constexpr float kTwoPiF = 0x1.921fb6p+2f;
+constexpr float kInvTwoPiF = 0x1.45f306p-3f;
+constexpr float kPio6F = 0x1.0c1524p-1f;
+constexpr float kSqrt3F = 0x1.bb67aep+0f;
+constexpr float kTanPi12F = 0x1.126146p-2f;
+constexpr float kSinMarginF = 0x1p-20f;
+constexpr float kExtFuzzF = 0x1p-12f;
+
+IA_HD float reduce_f32(float x, int* q) {
+  const float k = rintf(x * kTwoOverPiF);
+  const float r = ((x - k * kPio2F1) - k * kPio2F2) - k * kPio2F3;
+  *q = static_cast<int>(k) & 3;
+  return r;
+}
+IA_HD float sinf32(float x) {
+  int q;
+  const float r = reduce_f32(x, &q);
+  const float v = (q & 1) ? cos1_32(r) : sin1_32(r);
+  return (q & 2) ? -v : v;
+}
+IA_HD float cosf32(float x) {
+  int q;
+  const float r = reduce_f32(x, &q);
+  const float v = (q & 1) ? sin1_32(r) : cos1_32(r);
+  return ((q + 1) & 2) ? -v : v;
+}
+IA_HD float atan_f32(float u) {
+  const float z = u * u;
+  float p = 1.0f / 13.0f;
+  p = fmaf(p, z, -1.0f / 11.0f);
+  p = fmaf(p, z, 1.0f / 9.0f);
+  p = fmaf(p, z, -1.0f / 7.0f);
+  p = fmaf(p, z, 1.0f / 5.0f);
+  p = fmaf(p, z, -1.0f / 3.0f);
+  return fmaf(u * z, p, u);
+}
+IA_HD float atan2f32(float y, float x) {
+  const float ax = fabsf(x), ay = fabsf(y);
+  if (ax == 0.0f && ay == 0.0f) return 0.0f;
+  const bool swap = ay > ax;
+  const float t = swap ? ax / ay : ay / ax;
+  float a;
+  if (t > kTanPi12F) a = kPio6F + atan_f32((t * kSqrt3F - 1.0f) / (t + kSqrt3F));
+  else a = atan_f32(t);
+  if (swap) a = kPio2F - a;
+  if (x < 0.0f) a = kPiF - a;
+  if (y < 0.0f) a = -a;
+  return a;
+}
+IA_HD Iv32 sin_encl32(float a, float b) {
+  if (b - a >= kTwoPiF) return {-1.0f, 1.0f};
+  const float va = sinf32(a), vb = sinf32(b);
+  float l = fminf(va, vb) - kSinMarginF, h = fmaxf(va, vb) + kSinMarginF;
+  if (floorf((b - kPio2F) * kInvTwoPiF + kExtFuzzF) >= ceilf((a - kPio2F) * kInvTwoPiF - kExtFuzzF)) h = 1.0f;
+  if (floorf((b + kPio2F) * kInvTwoPiF + kExtFuzzF) >= ceilf((a + kPio2F) * kInvTwoPiF - kExtFuzzF)) l = -1.0f;
+  return {fmaxf(l, -1.0f), fminf(h, 1.0f)};
+}
+
 }  // namespace ia

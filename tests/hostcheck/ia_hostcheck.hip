@@ -62,7 +62,8 @@ int32_t hc_vote_level(const double* hits, int32_t n_hits, const double* parents,
   std::vector<uint8_t> pmay(size_t(n_parents) * size_t(n_hits > 0 ? n_hits : 1), 1);
   std::vector<ParentE> pe(pmay.size());
   int64_t n_pexcl = 0;
-  if (parent_filter && filter) {
+  // (the library runs no class proofs at FP32 levels)
+  if (parent_filter && filter && !f32) {
 #pragma omp parallel for schedule(dynamic, 1) reduction(+ : n_pexcl)
     for (int32_t p = 0; p < n_parents; ++p)
       for (int32_t i = 0; i < n_hits; ++i) {
@@ -144,14 +145,15 @@ int32_t hc_vote_level(const double* hits, int32_t n_hits, const double* parents,
     if (tn2[t] > 0 && triple_live(tlb[t], tn2[t], T, static_cast<uint32_t>(t), tcut)) {
       ++n_live;
       const Frame f = triple_frame(P[tp], sh.m, tc / sh.m12, (tc / sh.m[2]) % sh.m[1], tc % sh.m[2]);
-      const float R32 = static_cast<float>(f.R), sig32 = static_cast<float>(f.sig);
+      const Frame32 g32 = frame32_of(f);
+      const float R32 = g32.R, sig32 = g32.sig;
       const Iv32 K32 = to32(f.K);
       for (int32_t i = 0; i < n_hits; ++i) {
         if (cls[size_t(t) * n_hits + i] != 2) continue;
         const HitRec& h = rec[i];
         const Iv G = residual_G(f, h);
         const PairQ q = pair_quantities(f, h, G);
-        const PairQ32 q32 = pair_q32(q, h, slack32);
+        const PairQ32 q32 = pair_q32_f32(g32, h, slack32);
         int64_t yes_here = 0;
         for (uint32_t l = 0; l < sh.m34; ++l) {
           const uint32_t k3 = l / sh.m[4], k4 = l % sh.m[4];
