@@ -102,7 +102,8 @@ PEAK_FP32_TFLOPS = 157.3  # MI355X vector FP32 (non-packed)
 
 def prec_text(name):
     return {"fp64": "FP64", "mixed": "FP32 at levels 0-2, FP64 after and the fit",
-            "exact": "FP64, the exact Phi of Eq. CSAXtoPHI_a at levels 2 and after"}[name]
+            "exact": "FP64, the exact Phi of Eq. CSAXtoPHI_a at levels 2 and after",
+            "iv": "FP64, d^Ax enclosed over the whole box (sound test) at the last two levels"}[name]
 
 
 def prec_dtype(name):
@@ -118,6 +119,8 @@ def sched_prec(name, n_refine):
         return [ia.FP64] * (n_refine + 1)
     if name == "exact":
         return [ia.FP64X if lev >= 2 else ia.FP64 for lev in range(n_refine + 1)]
+    if name == "iv":
+        return [ia.IV if lev >= n_refine - 1 else ia.FP64 for lev in range(n_refine + 1)]
     return [ia.FP32 if lev <= 2 else ia.FP64 for lev in range(n_refine + 1)]
 
 
@@ -158,7 +161,7 @@ def defer_flops(cw):
             + cw["enclosures"] * FLOP_CLS_ENCL + cw["inclusions"] * FLOP_CLS_INCL)
 
 
-def roofline(kprof, work, cwork, wall, measured_on, traffic=None):
+def roofline(kprof, work, cwork, wall, measured_on, traffic=None, prec="fp64"):
     """Roofline object of the dominant kernel: of the vote kernel and the
     (triple, hit) classification at FP64 and FP32 levels, the one with the
     largest summed launch time (HIP events around each launch).  Achieved =
@@ -211,7 +214,11 @@ def roofline(kprof, work, cwork, wall, measured_on, traffic=None):
             "traffic_note": note, "executed": executed,
             "kernel": dom, "avg_launch_ms": d["avg_launch_ms"], "launches": d["launches"],
             "share_of_wall": d["total_ms"] * 1e-3 / wall, "measured_on": measured_on,
-            "by_kernel": parts}
+            "by_kernel": parts,
+            **({"levels_note": "the fp64-levels record covers every level that is not FP32 (FP64, exact-Phi and "
+                               "whole-box levels); its algorithmic flops count the mid-voxel test's, so it "
+                               "understates the exact-Phi and whole-box kernels' work"}
+               if prec in ("exact", "iv") else {})}
 
 
 def kernel_measure(ctx, run):
@@ -394,15 +401,17 @@ def main():
                     help="single-helix workload: single-event calls timed for p50/p99 latency")
     ap.add_argument("--scratch-gb", type=float, default=48.0)
     ap.add_argument("--serve-events", type=int, default=2048)
+    ap.add_argument("--serve-rows", type=int, default=8192, help="serving: rows per pool at most")
     ap.add_argument("--rate", type=float, default=0.0,
                     help="serving: Poisson arrival rate, events/s (0: 0.8 x the measured saturated rate)")
     ap.add_argument("--report-events", type=int, default=1000, help="mixed-report: noiseless single-helix events")
     ap.add_argument("--no-autotune", action="store_true", help="skip the vote-tile autotuner")
     ap.add_argument("--no-graph", action="store_true",
                     help="batch: call ia_find_helices per step instead of replaying a captured graph")
-    ap.add_argument("--prec", choices=["fp64", "mixed", "exact"], default="fp64",
+    ap.add_argument("--prec", choices=["fp64", "mixed", "exact", "iv"], default="fp64",
                     help="mixed: FP32 vote arithmetic at levels 0-2, FP64 at the finer levels and the fit; "
-                         "exact: the exact Phi of Eq. CSAXtoPHI_a at levels 2 and after")
+                         "exact: the exact Phi of Eq. CSAXtoPHI_a at levels 2 and after; iv: d^Ax enclosed "
+                         "over the whole box at the last two levels")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the search shards by event "
@@ -546,7 +555,7 @@ def run_event(args):
         "latency": "p50/p99: one event per call, arrival of resident hits to its recorded helix",
         "roofline": roofline(kprof, work, cwork, wall,
                              "repeat of the timed steps: HIP events around each launch, then a work-counting run",
-                             measured_traffic("event", B)),
+                             measured_traffic("event", B), args.prec),
     }
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(batches[args.warmup][0], sched_kw, lo, hi, args.cpu_budget)
@@ -757,7 +766,7 @@ def run_batch(args):
         "roofline": roofline(kprof, work, cwork, wall * rep_steps / args.steps,
                              ("eager repeat of the last timed batch" if use_graph else "repeat of the timed steps")
                              + ": HIP events around each launch, then a work-counting run",
-                             measured_traffic("batch", E)),
+                             measured_traffic("batch", E), args.prec),
     }
     if use_graph:
         res["roofline"]["measured_on"] = "eager profiled repeat of the last timed batch"
@@ -791,7 +800,8 @@ def run_serve(args):
     t_gen = time.perf_counter() - t_gen
     warm, sat_events, events = events[:n_warm], events[n_warm:n_warm + args.serve_events], \
         events[n_warm + args.serve_events:]
-    loop = serve.ServeLoop(sched, max_per_event=nh, scratch_budget=int(args.scratch_gb * (1 << 30)))
+    loop = serve.ServeLoop(sched, max_per_event=nh, scratch_budget=int(args.scratch_gb * (1 << 30)),
+                           rows_cap=args.serve_rows)
     loop.run([serve.Request(i, e.hits, 0.0) for i, e in enumerate(warm)])
     loop.finished = []
     torch.cuda.synchronize()

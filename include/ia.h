@@ -65,10 +65,14 @@ typedef enum {
  * ApproxPhi (Appendix A), the paper's form.  IA_FP32: see ia_vote_level.
  * IA_FP64X: FP64 with the exact Phi, the solution of Eq. CSAXtoPHI_a by
  * three fixed-point steps from ApproxPhi; the closest approach is then
- * independent of z_ref, which stays 0.  At IA_FP64X levels the (triple, hit)
- * class proofs (which enclose the ApproxPhi form) are off: every stereo pair
- * is evaluated box by box. */
-typedef enum { IA_FP64 = 0, IA_FP32 = 1, IA_FP64X = 2 } ia_precision;
+ * independent of z_ref, which stays 0.  IA_IV: the sound test -- d^Ax
+ * enclosed over the whole box (every quantity of Appendix A in FP64 interval
+ * arithmetic, Phi enclosed by interval fixed-point steps of Eq.
+ * CSAXtoPHI_a) instead of its value at the middle of the voxel (Sec. 3.1), so
+ * a box that holds a tangent helix always gets the vote.  At IA_FP64X and
+ * IA_IV levels the (triple, hit) class proofs (which enclose the ApproxPhi
+ * form) are off: every stereo pair is evaluated box by box. */
+typedef enum { IA_FP64 = 0, IA_FP32 = 1, IA_FP64X = 2, IA_IV = 3 } ia_precision;
 
 /* one hit: wire end points (z0 != z1), measured drift radius >= 0 and the
  * tolerance half-width added on both sides of the drift (0 = exact) */
@@ -144,8 +148,9 @@ typedef struct {
   int32_t v_min;          /* stop when the level-0 max vote is below this */
   int32_t n_helix_max;    /* helices searched per event (greedy, hits removed) */
   double hitfind_scale;   /* hit-finding box = estimate +- scale x error (5 in Sec. 3.3) */
-  int32_t prec[IA_MAX_LEVELS];  /* arithmetic per level (IA_FP64, IA_FP32 or IA_FP64X); the
-                                 * hit finding and hit selection use the estimating level's */
+  int32_t prec[IA_MAX_LEVELS];  /* arithmetic per level (ia_precision); the hit finding and
+                                 * hit selection use the estimating level's with IA_FP64X,
+                                 * else the FP64 mid-voxel test */
   double fp32_slack;      /* band widening at FP32 levels, m, in [0, 1e-3], to which
                            * 2^-24 R is added per box (R the radius at its centre):
                            * together they bound |e32 - e64| of d^Ax (measured at
@@ -309,8 +314,8 @@ size_t ia_ctx_scratch_needed(const ia_schedule *sched, int32_t max_hits);
  *             pair in FP32 -- G over the box in FP32 intervals, d^Ax at the
  *             box centre in FP32, the FP32 interval test with the band
  *             widened by the context's slack + 2^-24 R -- whose votes contain
- *             the IA_FP64 votes; or IA_FP64X: FP64 with the exact Phi of
- *             Eq. CSAXtoPHI_a
+ *             the IA_FP64 votes; IA_FP64X: FP64 with the exact Phi of Eq.
+ *             CSAXtoPHI_a; or IA_IV: d^Ax enclosed over the whole box
  *   d_votes   n_parents * prod(split) uint16, written: number of active,
  *             well-formed hits voting for each box
  * Scratch: 112 bytes per hit, and n_parents * prod(split[0..2]) * (n_hits + 8)

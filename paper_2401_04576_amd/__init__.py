@@ -22,7 +22,7 @@ __all__ = ["IAError", "Context", "Schedule", "vote_level", "refine", "estimate",
            "lib_path", "load", "FP64", "FP32", "HELIX_DTYPE", "ESTIMATE_DTYPE"]
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-FP64, FP32, FP64X = 0, 1, 2   # FP64X: FP64 with the exact Phi of Eq. CSAXtoPHI_a
+FP64, FP32, FP64X, IV = 0, 1, 2, 3   # FP64X: exact Phi of Eq. CSAXtoPHI_a; IV: sound whole-box d^Ax
 MAX_LEVELS = 8
 
 _STATUS = {0: "IA_OK", 1: "IA_ERR_INVALID", 2: "IA_ERR_NOMEM", 3: "IA_ERR_DEVICE",

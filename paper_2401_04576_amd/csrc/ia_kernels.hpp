@@ -454,7 +454,7 @@ IA_HD bool stereo_vote(const PairQ& q, double R, double sig, Iv K, double z0,
       }
     }
     double se, ce;
-    sincos_p(eps, &se, &ce);
+    sincos_small_p(eps, &se, &ce);
     double sinP = q.sinA * ce + q.cosA * se, cosP = q.cosA * ce - q.sinA * se;
     double u = sqrt(((1.0 + ((2.0 * lam) * sinP) * tt) + lam2 * t2) + (cosP * cosP) * t2);
     double delta = dS / u;
@@ -2883,6 +2883,205 @@ __global__ void __launch_bounds__(kWG) k_est_final(const double* __restrict__ pa
     ev->n_argmax = s_count;
     if (n_out) *n_out = ev->n_out;
     if (na == 0 || ev->n_out >= max_out) ev->done = 1;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// IV levels: d^Ax enclosed over the whole box instead of its value at the
+// middle of the voxel (Sec. 3.1), every quantity of Appendix A in interval
+// arithmetic in the box's kappa > 0 frame, Phi - Phi^Ax enclosed by interval
+// fixed-point steps of Eq. CSAXtoPHI_a from [-pi, pi] (each step keeps every
+// solution); the same operations in the same order as the oracle's.
+constexpr int kIvIters = 6;
+
+struct IvSt { Iv sinP, cosP, u, delta, zS, ld, ctau; };
+
+IA_HD bool iv_stereo_point(Iv EPS, Iv SINA, Iv COSA, Iv LAM, double tt, Iv T2, double dS, Iv R, Iv DPHI, Iv Z0,
+                           Iv CAX, Iv SAX, IvSt* o) {
+  const Iv SE = sin_encl(EPS.lo, EPS.hi), CE = cos_encl(EPS.lo, EPS.hi);
+  o->sinP = iadd(imul(SINA, CE), imul(COSA, SE));
+  o->cosP = isub(imul(COSA, CE), imul(SINA, SE));
+  const Iv U2 = iadd(iadd(iadd(ipt(1.0), imul_pt(imul(itwice(LAM), o->sinP), tt)), imul(isqr(LAM), T2)),
+                     imul(isqr(o->cosP), T2));
+  if (!(U2.lo > 0.0)) return false;
+  o->u = isqrt(U2);
+  o->delta = idiv_pos(ipt(dS), o->u);
+  const Iv SPERP = imul(R, iadd(DPHI, EPS));
+  o->zS = isub(iadd(Z0, imul(LAM, SPERP)), imul_pt(imul(o->delta, o->cosP), tt));
+  o->ld = imul(LAM, o->delta);
+  o->ctau = isub(imul(o->zS, CAX), imul(o->ld, SAX));
+  return true;
+}
+
+// enclosure of e = sgn(kappa) d^Ax over box b for drift sign s; false when
+// none (kappa of both signs, a bound that fails): the pair then votes
+IA_HD bool stereo_encl(const BoxD& b, const HitRec& h, int s, Iv* out) {
+  if (b.lo[2] <= 0.0 && b.hi[2] >= 0.0) return false;
+  const double sig = b.lo[2] > 0.0 ? 1.0 : -1.0;
+  const Iv K = {b.lo[2], b.hi[2]}, D0 = {b.lo[0], b.hi[0]}, FI = {b.lo[1], b.hi[1]};
+  const double dS = static_cast<double>(s) * h.d;
+  if (h.axial) {
+    *out = {sig * dS, sig * dS};
+    return true;
+  }
+  const Iv KP = sig > 0.0 ? K : ineg(K), D0P = sig > 0.0 ? D0 : ineg(D0);
+  const Iv SF = sin_encl(FI.lo, FI.hi), CP0 = cos_encl(FI.lo, FI.hi);
+  const Iv SP0 = sig > 0.0 ? SF : ineg(SF);
+  const Iv R = {wdn(1.0 / KP.hi), wup(1.0 / KP.lo)};
+  const Iv RD = iadd(R, D0P);
+  const Iv XC = ineg(imul(RD, SP0)), YC = imul(RD, CP0);
+  const double py = sig * h.py, cps = sig * h.cphis, sps = h.sphis;
+  const Iv DX = isub(ipt(h.px), XC), DY = isub(ipt(py), YC);
+  const Iv RAX2 = iadd(isqr(DX), isqr(DY));
+  if (!(RAX2.lo > 0.0)) return false;
+  const Iv RAX = isqrt(RAX2);
+  const Iv CAX = isub(imul_pt(DX, sps), imul_pt(DY, cps));
+  const Iv SAX = iadd(imul_pt(DX, cps), imul_pt(DY, sps));
+  const Iv SINA = idiv_pos(SAX, RAX), COSA = idiv_pos(CAX, RAX);
+  const Iv YY = iadd(imul(DX, CP0), imul(DY, SP0)), XX = isub(imul(DX, SP0), imul(DY, CP0));
+  const Iv DPHI = atan2_encl(YY, XX);
+  const Iv Z0 = {b.lo[3], b.hi[3]}, LAM = {b.lo[4], b.hi[4]};
+  const double tt = h.tant;
+  const Iv T2 = {wdn(tt * tt), wup(tt * tt)};
+  Iv EPS = {-2.0 * kPio2Up, 2.0 * kPio2Up};
+  IvSt q;
+  for (int k = 0; k < kIvIters; ++k) {
+    if (!iv_stereo_point(EPS, SINA, COSA, LAM, tt, T2, dS, R, DPHI, Z0, CAX, SAX, &q)) return false;
+    const Iv ST = ineg(iadd(imul(q.ld, CAX), imul(q.zS, SAX)));
+    const Iv DEN = iadd(RAX2, imul_pt(q.ctau, tt));
+    if (!(DEN.lo > 0.0)) return false;
+    const Iv F = atan2_encl(imul_pt(ST, tt), DEN);
+    EPS.lo = fmax(EPS.lo, F.lo);
+    EPS.hi = fmin(EPS.hi, F.hi);
+    if (!(EPS.lo <= EPS.hi)) return false;
+  }
+  if (!iv_stereo_point(EPS, SINA, COSA, LAM, tt, T2, dS, R, DPHI, Z0, CAX, SAX, &q)) return false;
+  const Iv A1 = imul_pt(q.zS, tt), A2 = imul_pt(q.ld, tt);
+  const Iv Q = iadd(iadd(imul_pt(itwice(q.ctau), tt), isqr(A1)), isqr(A2));
+  const Iv A = iadd(R, q.delta);
+  const Iv DISC = isub(isqr(A), Q);
+  if (!(DISC.lo > 0.0) || !(A.lo > 0.0)) return false;
+  const Iv DHAT = isub(q.delta, idiv_pos(Q, iadd(A, isqrt(DISC))));
+  const Iv E = sig > 0.0 ? DHAT : ineg(DHAT);
+  if (!__builtin_isfinite(E.lo) || !__builtin_isfinite(E.hi)) return false;
+  *out = E;
+  return true;
+}
+
+// the IV vote of a stereo (box, hit) pair: zero in 2G - 2E - kappa E^2 for
+// either sign, E the box enclosure widened by the band
+IA_HD bool pair_vote_iv(const BoxD& b, const HitRec& h, Iv G) {
+  const Iv K = {b.lo[2], b.hi[2]};
+  for (int si = 0; si < 2; ++si) {
+    Iv E;
+    if (!stereo_encl(b, h, si == 0 ? 1 : -1, &E)) return true;
+    const Iv Eb = {wdn(E.lo - h.band), wup(E.hi + h.band)};
+    const Iv Hb = isub(itwice(G), iadd(itwice(Eb), imul(K, isqr(Eb))));
+    if (Hb.lo <= 0.0 && 0.0 <= Hb.hi) return true;
+  }
+  return false;
+}
+
+// The vote of an IV level: one lane per box (tiles of kWG boxes), over the
+// batch's live tiles (live_all, offsets live_off) or, without a list, every
+// tile of n_ev events; each box starts from its triple's lower bound and
+// adds the class-2 stereo pairs it gets.  Outputs as k_vote_rec's.
+__global__ void __launch_bounds__(kWG) k_vote_iv(const HitRec* __restrict__ hits_all, EvView vw,
+                                                 const BoxD* __restrict__ parents_all, Shape sh,
+                                                 const uint8_t* __restrict__ flags_all, uint16_t* __restrict__ votes_all,
+                                                 uint32_t* __restrict__ hist_all, uint32_t* __restrict__ status,
+                                                 const EventState* __restrict__ ev, const int32_t* __restrict__ tlb_all,
+                                                 const int32_t* __restrict__ tn2_all,
+                                                 const int32_t* __restrict__ live_all,
+                                                 const int32_t* __restrict__ live_off, int32_t n_ev,
+                                                 int32_t* __restrict__ wg_max_all,
+                                                 unsigned long long* __restrict__ work) {
+  const uint32_t n_tr = sh.n_parents * sh.m012;
+  const uint32_t n_tiles = (sh.n_boxes + kWG - 1) / kWG;
+  const uint32_t n_items = live_all ? static_cast<uint32_t>(live_off[n_ev]) : n_tiles * static_cast<uint32_t>(n_ev);
+  __shared__ uint32_t shist[kHistLds];
+  __shared__ int32_t sbuf[kWG / 64];
+  const uint32_t tid = threadIdx.x;
+  auto triple_of = [&](uint32_t x) { return (x / sh.nc) * sh.m012 + (x % sh.nc) / sh.m34; };
+  int32_t n_eval = 0;
+  for (uint32_t item = blockIdx.x; item < n_items; item += gridDim.x) {
+    int e;
+    uint32_t tile;
+    if (live_all) {
+      int32_t elo = 0, ehi = n_ev - 1;
+      while (elo < ehi) {
+        const int32_t mid = (elo + ehi + 1) >> 1;
+        if (static_cast<uint32_t>(live_off[mid]) <= item) elo = mid;
+        else ehi = mid - 1;
+      }
+      e = elo;
+      tile = static_cast<uint32_t>(live_all[int64_t(e) * vw.wg_stride + (item - live_off[e])]);
+    } else {
+      e = static_cast<int>(item / n_tiles);
+      tile = item % n_tiles;
+    }
+    const int32_t n_hits = vw.count(e), n_bins = n_hits + 1;
+    const HitRec* hits = hits_all + vw.beg(e);
+    const BoxD* parents = parents_all + e * vw.par_stride;
+    const uint8_t* flags = flags_all + e * vw.flag_stride;
+    const int32_t* tlb = tlb_all + e * vw.tri_stride;
+    const int32_t* tn2 = tn2_all + e * vw.tri_stride;
+    uint16_t* votes = votes_all + int64_t(e) * sh.n_boxes;
+    uint32_t* hist = hist_all ? hist_all + int64_t(e) * vw.hist_stride : nullptr;
+    int32_t* wg_max = wg_max_all ? wg_max_all + int64_t(e) * vw.wg_stride : nullptr;
+    const int32_t T = ev ? ev[e].t_prune : 0;
+    const int32_t tcut = ev ? ev[e].t_cut : INT32_MAX;
+    const uint32_t b = tile * kWG + tid;
+    const bool live = b < sh.n_boxes;
+    const uint32_t t = triple_of(live ? b : sh.n_boxes - 1);
+    int32_t nv = tlb[t];
+    if (live && tn2[t] > 0 && triple_live(tlb[t], tn2[t], T, t, tcut)) {
+      const BoxD& P = parents[b / sh.nc];
+      BoxD B;
+      child_box(P, sh.m, b % sh.nc, &B);
+      const uint32_t tc = t % sh.m012;
+      const Frame f = triple_frame(P, sh.m, tc / sh.m12, (tc / sh.m[2]) % sh.m[1], tc % sh.m[2]);
+      for (int32_t h = 0; h < n_hits; ++h) {
+        if (flags[int64_t(h) * n_tr + t] != 2) continue;
+        const HitRec hr = hits[h];
+        ++n_eval;
+        if (pair_vote_iv(B, hr, residual_G(f, hr))) ++nv;
+      }
+    }
+    if (live) votes[b] = static_cast<uint16_t>(nv);
+    int32_t mv = live ? nv : -1;
+    for (int o = 32; o > 0; o >>= 1) mv = max(mv, __shfl_down(mv, o, 64));
+    __syncthreads();
+    if ((tid & 63) == 0) sbuf[tid >> 6] = mv;
+    __syncthreads();
+    int32_t wmax = -1;
+    for (int w = 0; w < kWG / 64; ++w) wmax = max(wmax, sbuf[w]);
+    if (wg_max && tid == 0) wg_max[tile] = wmax;
+    if (hist && wmax >= T) {
+      const bool in_lds = n_bins <= kHistLds;
+      if (in_lds) {
+        for (int32_t i = tid; i < n_bins; i += kWG) shist[i] = 0u;
+        __syncthreads();
+      }
+      if (live && nv >= T) {
+        if (nv >= n_bins) atomicOr(status, kStVoteOverflow);
+        else if (in_lds) atomicAdd(&shist[nv], 1u);
+        else atomicAdd(&hist[nv], 1u);
+      }
+      if (in_lds) {
+        __syncthreads();
+        for (int32_t i = tid; i < n_bins; i += kWG)
+          if (shist[i]) atomicAdd(&hist[i], shist[i]);
+      }
+    }
+  }
+  if (work) {
+    int32_t a = n_eval;
+    for (int o = 32; o > 0; o >>= 1) a += __shfl_down(a, o, 64);
+    if ((tid & 63) == 0 && a) {
+      unsigned long long* slot = work + kWorkSlotU64 * ((blockIdx.x * 4u + (tid >> 6)) % kWorkSlots);
+      atomicAdd(&slot[0], static_cast<unsigned long long>(a));
+    }
   }
 }
 

@@ -409,6 +409,31 @@ void launch_vote_rec_tile(int32_t bx, dim3 g, hipStream_t s, const ia::EvView& v
   }
 }
 
+// the IV levels' vote (k_vote_iv) over the listed live tiles of n_ev events
+// (live_list null: every tile), bracketed by events when profiling
+ia_status launch_vote_iv(ia_ctx* c, const HitRec* recs, const ia::EvView& vw, int32_t n_ev, const BoxD* par,
+                         const Shape& sh, const uint8_t* flags, uint16_t* votes, uint32_t* hist,
+                         const EventState* ev, const int32_t* tlb, const int32_t* tn2, const int32_t* live_list,
+                         const int32_t* live_off, int32_t* wg_max, hipStream_t s) {
+  const uint32_t n_tiles = (sh.n_boxes + ia::kWG - 1) / ia::kWG;
+  const uint32_t grid = static_cast<uint32_t>(
+      std::max<int64_t>(1, std::min<int64_t>(int64_t(n_tiles) * std::max(1, n_ev), kVoteGroups)));
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (c->profiling) {
+    IA_HIP(c, hipEventCreate(&e0));
+    IA_HIP(c, hipEventCreate(&e1));
+    IA_HIP(c, hipEventRecord(e0, s));
+  }
+  hipLaunchKernelGGL(ia::k_vote_iv, dim3(grid), dim3(ia::kWG), 0, s, recs, vw, par, sh, flags, votes, hist,
+                     &persistent(c)->status, ev, tlb, tn2, live_list, live_off, n_ev, wg_max, persistent(c)->work);
+  if (c->profiling) {
+    IA_HIP(c, hipEventRecord(e1, s));
+    c->marks.push_back({e0, e1, false, sh.n_boxes, IA_KERNEL_VOTE});
+  }
+  IA_HIP(c, hipGetLastError());
+  return IA_OK;
+}
+
 // the record-based vote for n_ev events (bracketed by events when profiling)
 ia_status launch_vote_rec(ia_ctx* c, const ia::EvView& vw, int32_t n_ev, const BoxD* par, const Shape& sh,
                           uint16_t* votes, uint32_t* hist, const EventState* ev, const VoteIn& in, const RecIn& r,
@@ -551,7 +576,7 @@ ia_status check_sched(ia_ctx* c, const ia_schedule* sc) {
   for (int j = 0; j < 5; ++j)
     if (!(sc->range.lo[j] <= sc->range.hi[j])) return fail(c, IA_ERR_INVALID, "range dimension %d: lo > hi", j);
   for (int l = 0; l <= sc->n_refine; ++l)
-    if (sc->prec[l] != IA_FP64 && sc->prec[l] != IA_FP32 && sc->prec[l] != IA_FP64X)
+    if (sc->prec[l] != IA_FP64 && sc->prec[l] != IA_FP32 && sc->prec[l] != IA_FP64X && sc->prec[l] != IA_IV)
       return fail(c, IA_ERR_INVALID, "precision %d at level %d", sc->prec[l], l);
   if (!(sc->fp32_slack >= 0.0 && sc->fp32_slack <= 1e-3))
     return fail(c, IA_ERR_INVALID, "fp32_slack %g outside [0, 1e-3]", sc->fp32_slack);
@@ -587,9 +612,9 @@ ia_status run_window(ia_ctx* c, const double* hits, ia::EvView vw, int32_t E, in
     Shape sh = S.sh0;
     vw.par_stride = 0;
     for (int32_t lev = 0; lev <= sc->n_refine; ++lev) {
-      const bool f32 = sc->prec[lev] == IA_FP32, exact = sc->prec[lev] == IA_FP64X;
+      const bool f32 = sc->prec[lev] == IA_FP32, exact = sc->prec[lev] == IA_FP64X, iv = sc->prec[lev] == IA_IV;
       vw.fwd = sc->forward;     // per event: hits ahead about the origin, origin behind after a move
-      const bool use_pf = lev > 0 && use_filter(c) && c->parent_filter && !exact && !f32;
+      const bool use_pf = lev > 0 && use_filter(c) && c->parent_filter && !exact && !f32 && !iv;
       if (use_pf) {
         const int64_t n_pairs = int64_t(sh.n_parents) * std::max(1, cmax);
         const dim3 gp(static_cast<uint32_t>(std::min<int64_t>((n_pairs + ia::kWG - 1) / ia::kWG, 65535)), E);
@@ -602,21 +627,28 @@ ia_status run_window(ia_ctx* c, const double* hits, ia::EvView vw, int32_t E, in
       }
       {
         const ia_status cs = launch_classify(c, recs, vw, E, cmax, par, sh, flags, tlb, tn2, ev, s, f32, slack32,
-                                             use_pf ? pflags : nullptr, (use_pf && !f32) ? pe : nullptr, exact);
+                                             use_pf ? pflags : nullptr, (use_pf && !f32) ? pe : nullptr, exact || iv);
         if (cs != IA_OK) return cs;
       }
-      const int32_t vt = vote_tile(c, sh.n_boxes, E);
+      const int32_t vt = iv ? ia::kWG : vote_tile(c, sh.n_boxes, E);
       hipLaunchKernelGGL(ia::k_threshold, dim3(1, E), dim3(ia::kWG), 0, s, tlb, tn2, lbh, vw, sh, 1, c->prune, 0,
-                         vt, ev, live, wg_max, rin.live_tri, rin.rec_off, rin.rec_fill, L.rec_stride,
-                         lev < sc->n_refine ? sc->wdrop : 0);
-      launch_stage(recs, vw, E, par, sh, flags, rin, ev, s, f32, slack32);
-      const VoteIn in{flags, tlb, tn2, live, 1};
-      ia_status st = launch_vote_rec(c, vw, E, par, sh, votes, hist, ev, in, rin, wg_max, s, f32, exact);
-      if (st != IA_OK) return st;
+                         vt, ev, live, wg_max, rin.live_tri, rin.rec_off, rin.rec_fill,
+                         iv ? INT64_MAX : L.rec_stride, lev < sc->n_refine ? sc->wdrop : 0);
       int32_t bx = vt;
-      if (may_overflow) {
-        st = launch_vote(c, recs, vw, E, par, sh, votes, hist, ev, in, wg_max, s, f32, slack32, &bx, exact);
+      if (iv) {
+        hipLaunchKernelGGL(ia::k_live_offsets, dim3(1), dim3(ia::kWG), 0, s, ev, vw, E, rin.live_off, rin.stage_off);
+        const ia_status st = launch_vote_iv(c, recs, vw, E, par, sh, flags, votes, hist, ev, tlb, tn2, live,
+                                            rin.live_off, wg_max, s);
         if (st != IA_OK) return st;
+      } else {
+        launch_stage(recs, vw, E, par, sh, flags, rin, ev, s, f32, slack32);
+        const VoteIn in{flags, tlb, tn2, live, 1};
+        ia_status st = launch_vote_rec(c, vw, E, par, sh, votes, hist, ev, in, rin, wg_max, s, f32, exact);
+        if (st != IA_OK) return st;
+        if (may_overflow) {
+          st = launch_vote(c, recs, vw, E, par, sh, votes, hist, ev, in, wg_max, s, f32, slack32, &bx, exact);
+          if (st != IA_OK) return st;
+        }
       }
       const uint32_t n_wg = (sh.n_boxes + bx - 1) / bx;
       hipLaunchKernelGGL(ia::k_select_wg, dim3(1, E), dim3(ia::kWG), 0, s, votes, vw, hist, wg_max, n_wg, bx, par,
@@ -748,10 +780,10 @@ ia_status run_chunk(ia_ctx* c, const double* hits_chunk, const int32_t* h_off_ch
     vw.par_stride = 0;
     int32_t last_bx = 1;
     for (int32_t lev = 0; lev <= sc->n_refine; ++lev) {
-      const bool f32 = sc->prec[lev] == IA_FP32, exact = sc->prec[lev] == IA_FP64X;
+      const bool f32 = sc->prec[lev] == IA_FP32, exact = sc->prec[lev] == IA_FP64X, iv = sc->prec[lev] == IA_IV;
       // refinement levels: the parent-level test first (a hit it excludes
       // is class 0 for all of that parent's triples)
-      const bool use_pf = lev > 0 && use_filter(c) && c->parent_filter && !exact && !f32;
+      const bool use_pf = lev > 0 && use_filter(c) && c->parent_filter && !exact && !f32 && !iv;
       if (use_pf) {
         const int64_t n_pairs = int64_t(sh.n_parents) * std::max(1, cmax);
         const dim3 gp(static_cast<uint32_t>(std::min<int64_t>((n_pairs + ia::kWG - 1) / ia::kWG, 65535)), E);
@@ -766,10 +798,10 @@ ia_status run_chunk(ia_ctx* c, const double* hits_chunk, const int32_t* h_off_ch
         // at FP64 levels the parent's per-sign ranges of d^Ax also decide
         // many pairs in the first stage
         const ia_status cs = launch_classify(c, recs, vw, E, cmax, par, sh, flags, tlb, tn2, ev, s, f32, slack32,
-                                             use_pf ? pflags : nullptr, (use_pf && !f32) ? pe : nullptr, exact);
+                                             use_pf ? pflags : nullptr, (use_pf && !f32) ? pe : nullptr, exact || iv);
         if (cs != IA_OK) return cs;
       }
-      const int32_t vt = vote_tile(c, sh.n_boxes, E);
+      const int32_t vt = iv ? ia::kWG : vote_tile(c, sh.n_boxes, E);
       // the last level feeds only the estimate, which needs the whole
       // max-vote set and the first max-vote box: there the selection keeps
       // one box, so that T is the largest lower bound (a box whose upper
@@ -778,15 +810,23 @@ ia_status run_chunk(ia_ctx* c, const double* hits_chunk, const int32_t* h_off_ch
       const int32_t k_lev = last ? 1 : K;
       const int32_t ties = last ? 0 : 1;
       hipLaunchKernelGGL(ia::k_threshold, dim3(1, E), dim3(ia::kWG), 0, s, tlb, tn2, lbh, vw, sh, k_lev, c->prune,
-                         ties, vt, ev, live, wg_max, rin.live_tri, rin.rec_off, rin.rec_fill, L.rec_stride, 0);
-      launch_stage(recs, vw, E, par, sh, flags, rin, ev, s, f32, slack32);
-      const VoteIn in{flags, tlb, tn2, live, 1};
-      ia_status st = launch_vote_rec(c, vw, E, par, sh, votes, hist, ev, in, rin, wg_max, s, f32, exact);
-      if (st != IA_OK) return st;
+                         ties, vt, ev, live, wg_max, rin.live_tri, rin.rec_off, rin.rec_fill,
+                         iv ? INT64_MAX : L.rec_stride, 0);
       int32_t bx = vt;
-      if (may_overflow) {
-        st = launch_vote(c, recs, vw, E, par, sh, votes, hist, ev, in, wg_max, s, f32, slack32, &bx, exact);
+      if (iv) {
+        hipLaunchKernelGGL(ia::k_live_offsets, dim3(1), dim3(ia::kWG), 0, s, ev, vw, E, rin.live_off, rin.stage_off);
+        const ia_status st = launch_vote_iv(c, recs, vw, E, par, sh, flags, votes, hist, ev, tlb, tn2, live,
+                                            rin.live_off, wg_max, s);
         if (st != IA_OK) return st;
+      } else {
+        launch_stage(recs, vw, E, par, sh, flags, rin, ev, s, f32, slack32);
+        const VoteIn in{flags, tlb, tn2, live, 1};
+        ia_status st = launch_vote_rec(c, vw, E, par, sh, votes, hist, ev, in, rin, wg_max, s, f32, exact);
+        if (st != IA_OK) return st;
+        if (may_overflow) {
+          st = launch_vote(c, recs, vw, E, par, sh, votes, hist, ev, in, wg_max, s, f32, slack32, &bx, exact);
+          if (st != IA_OK) return st;
+        }
       }
       last_bx = bx;
       const uint32_t n_wg = (sh.n_boxes + bx - 1) / bx;
@@ -1033,7 +1073,7 @@ ia_status vote_level_args(ia_ctx* c, const ia_hit* d_hits, int32_t n_hits, const
   if (n_hits > 0 && !d_hits) return fail(c, IA_ERR_INVALID, "d_hits is NULL");
   if (!d_parents || !split || !d_votes) return fail(c, IA_ERR_INVALID, "null pointer argument");
   if (n_parents < 1) return fail(c, IA_ERR_INVALID, "n_parents %d < 1", n_parents);
-  if (prec != IA_FP64 && prec != IA_FP32 && prec != IA_FP64X)
+  if (prec != IA_FP64 && prec != IA_FP32 && prec != IA_FP64X && prec != IA_IV)
     return fail(c, IA_ERR_INVALID, "precision %d unknown", int(prec));
   if (!make_shape(split, n_parents, sh)) return fail(c, IA_ERR_OVERFLOW, "level exceeds 2^31 - 1 boxes");
   return IA_OK;
@@ -1076,15 +1116,18 @@ ia_status vote_level_run(ia_ctx* c, const ia_hit* d_hits, int32_t n_hits, const 
   vw.vref[0] = c->vf_xr;
   vw.vref[1] = c->vf_yr;
   const BoxD* par = reinterpret_cast<const BoxD*>(d_parents);
-  const bool f32 = prec == IA_FP32, exact = prec == IA_FP64X;
+  const bool f32 = prec == IA_FP32, exact = prec == IA_FP64X, iv = prec == IA_IV;
   const uint32_t fill_n = static_cast<uint32_t>(std::min<int64_t>(n_tr, 0x7fffffff));
   hipLaunchKernelGGL(ia::k_fill_u32, dim3(std::min<uint32_t>((fill_n + 255) / 256, 65535)), dim3(256), 0, s,
                      reinterpret_cast<uint32_t*>(tlb), fill_n, 0u);
   hipLaunchKernelGGL(ia::k_fill_u32, dim3(std::min<uint32_t>((fill_n + 255) / 256, 65535)), dim3(256), 0, s,
                      reinterpret_cast<uint32_t*>(tn2), fill_n, 0u);
   const ia_status cs = launch_classify(c, recs, vw, 1, n_hits, par, sh, flags, tlb, tn2, nullptr, s, f32,
-                                       c->slack32, nullptr, nullptr, exact);
+                                       c->slack32, nullptr, nullptr, exact || iv);
   if (cs != IA_OK) return cs;
+  if (iv)
+    return launch_vote_iv(c, recs, vw, 1, par, sh, flags, d_votes, nullptr, nullptr, tlb, tn2, nullptr, nullptr,
+                          nullptr, s);
   const VoteIn in{flags, tlb, tn2, nullptr, 0};
   return launch_vote(c, recs, vw, 1, par, sh, d_votes, nullptr, nullptr, in, nullptr, s, f32, c->slack32, nullptr,
                      exact);

@@ -101,6 +101,19 @@ IA_HD void sincos_p(double x, double* s, double* c) {
   *c = ((q + 1) & 2) ? -cv : cv;
 }
 
+// sincos_p for the small corrections of the vote: below pi/4 in magnitude
+// the reduction is the identity (k = 0, r = x exactly), so the polynomials
+// alone give sincos_p's values bit for bit
+constexpr double kPio4 = 0x1.921fb54442d18p-1;   // below pi/4
+IA_HD void sincos_small_p(double x, double* s, double* c) {
+  if (fabs(x) < kPio4) {
+    *s = poly_sin(x);
+    *c = poly_cos(x);
+  } else {
+    sincos_p(x, s, c);
+  }
+}
+
 IA_HD double poly_atan(double u) {
   double z = u * u;
   double p = 1.0 / 29.0;

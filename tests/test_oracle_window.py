@@ -144,7 +144,6 @@ def _truth_in(grid, t):
     return True
 
 
-@pytest.mark.slow
 def test_window_search_recovers_noiseless_helices(orc):
     """The window schedule on noiseless single-helix events: the truth lies in
     every level's grid (in that level's frame), the level-0 maximum is every
