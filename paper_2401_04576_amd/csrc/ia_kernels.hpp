@@ -23,6 +23,7 @@ namespace ia {
 constexpr int kWG = 256;        // lanes per workgroup (4 waves of 64)
 constexpr int kCap = 256;       // (triple, hit) records staged per chunk
 constexpr int kHistLds = 1024;  // vote histogram bins kept in LDS
+constexpr int kHistLdsRec = 512; // the same in k_vote_rec, whose staged records take more LDS
 constexpr int kEstLevels = 15;  // estimate stack depth (partials of up to 2^22 boxes)
 constexpr int kMaxTopK = 4096;  // selection size limit
 
@@ -385,12 +386,13 @@ IA_HD Iv residual_G_outer(const Frame& f, const GTri& g, const HitRec& h) {
 IA_HD bool h_contains0(Iv G, Iv K, double e, double band) {
   Iv E = {wdn(e - band), wup(e + band)};
   Iv Hv = isub(itwice(G), iadd(itwice(E), imul(K, isqr(E))));
-  return Hv.lo <= 0.0 && 0.0 <= Hv.hi;
+  return (Hv.lo <= 0.0) & (0.0 <= Hv.hi);
 }
 
 // per (triple, stereo hit) quantities that do not depend on (z0, tanl)
 struct PairQ {
   double Glo, Ghi, sArc, dphi, RAx, sinA, cosA, sAx, cAx, c2, s2, twoRAx2, RpRAx;
+  double rRAx, r2RAx2;   // recip_v of RAx and of twoRAx2 (the per-box quotients' divisors)
 };
 
 IA_HD PairQ pair_quantities(const Frame& f, const HitRec& h, Iv G) {
@@ -410,6 +412,8 @@ IA_HD PairQ pair_quantities(const Frame& f, const HitRec& h, Iv G) {
   q.s2 = 2.0 * q.sinA * q.cosA;
   q.twoRAx2 = 2.0 * (q.RAx * q.RAx);
   q.RpRAx = f.R + q.RAx;
+  q.rRAx = recip_v(q.RAx);
+  q.r2RAx2 = recip_v(q.twoRAx2);
   return q;
 }
 
@@ -420,10 +424,17 @@ constexpr int kPhiIters = 3;
 // EQSinter_c, defdiAX_b evaluated in the same operation order as the oracle.
 // EXACT: Phi - Phi^Ax from kPhiIters fixed-point steps of Eq. CSAXtoPHI_a,
 // eps <- atan2(s^tau tan(tau), (R^Ax)^2 + c^tau tan(tau)), started from ApproxPhi.
-template <bool EXACT = false>
-IA_HD bool stereo_vote(const PairQ& q, double R, double sig, Iv K, double z0,
-                                            double lam, double lamR, double lam2, double tt, double t2,
-                                            double d, double band) {
+//
+// FAST (device only): the same operations with three primitives replaced by
+// forms that give the same bits on a stated range (ia_math.hpp): the two
+// quotients by per-pair divisors (div_fast, reciprocals staged in PairQ),
+// the square roots (sqrt_fast) and sin/cos of the correction without the
+// range reduction.  It has no branches, so the two drift signs interleave;
+// each replaced step clears *ok when its input is outside its range, and the
+// caller then evaluates the box again in the plain form.
+template <bool EXACT, bool FAST>
+IA_HD bool stereo_vote_t(const PairQ& q, double R, double sig, Iv K, double z0, double lam, double lamR,
+                         double lam2, double tt, double t2, double d, double band, bool* ok) {
   double zA = z0 + lam * q.sArc;
   double zAs = zA * q.sinA;
   double zA2 = zA * zA;
@@ -433,9 +444,16 @@ IA_HD bool stereo_vote(const PairQ& q, double R, double sig, Iv K, double z0,
 #pragma unroll
   for (int si = 0; si < 2; ++si) {
     double dS = si == 0 ? d : -d;
-    double Phi1 = -(zAs + (lam * dS) * q.cosA) / q.RAx;
-    double Phi2n = lamR * zA - (lzA * (R - 2.0 * dS)) * q.c2 + (zA2 + dS * (q.RAx + lam2 * (q.RpRAx - dS))) * q.s2;
-    double Phi2 = Phi2n / q.twoRAx2;
+    double Phi1, Phi2;
+    const double Phi2n =
+        lamR * zA - (lzA * (R - 2.0 * dS)) * q.c2 + (zA2 + dS * (q.RAx + lam2 * (q.RpRAx - dS))) * q.s2;
+    if constexpr (FAST) {
+      Phi1 = div_fast(-(zAs + (lam * dS) * q.cosA), q.RAx, q.rRAx, ok);
+      Phi2 = div_fast(Phi2n, q.twoRAx2, q.r2RAx2, ok);
+    } else {
+      Phi1 = -(zAs + (lam * dS) * q.cosA) / q.RAx;
+      Phi2 = Phi2n / q.twoRAx2;
+    }
     double eps = Phi1 * tt + Phi2 * t2;
     if constexpr (EXACT) {
       const double RAx2 = q.RAx * q.RAx;
@@ -454,9 +472,20 @@ IA_HD bool stereo_vote(const PairQ& q, double R, double sig, Iv K, double z0,
       }
     }
     double se, ce;
-    sincos_small_p(eps, &se, &ce);
+    if constexpr (FAST) {
+      // |eps| < pi/4: the reduction of sincos_p is the identity
+      const double aeps = fabs(eps);
+      *ok = *ok & (aeps < kPio4);
+      se = poly_sin(eps);
+      ce = poly_cos(eps);
+    } else {
+      sincos_p(eps, &se, &ce);
+    }
     double sinP = q.sinA * ce + q.cosA * se, cosP = q.cosA * ce - q.sinA * se;
-    double u = sqrt(((1.0 + ((2.0 * lam) * sinP) * tt) + lam2 * t2) + (cosP * cosP) * t2);
+    const double u2 = ((1.0 + ((2.0 * lam) * sinP) * tt) + lam2 * t2) + (cosP * cosP) * t2;
+    double u;
+    if constexpr (FAST) u = sqrt_fast(u2, ok);
+    else u = sqrt(u2);
     double delta = dS / u;
     double sperp = R * (q.dphi + eps);
     double zS = (z0 + lam * sperp) - (delta * cosP) * tt;
@@ -466,13 +495,34 @@ IA_HD bool stereo_vote(const PairQ& q, double R, double sig, Iv K, double z0,
     double Q = ((2.0 * ctau) * tt + a1 * a1) + a2 * a2;
     double A = R + delta;
     double disc = A * A - Q;
-    if (disc >= 0.0) {
+    if constexpr (FAST) {
+      // a negative (or NaN) discriminant casts no vote whatever its root
+      bool ok_d = true;
+      const double dhat = delta - Q / (A + sqrt_fast(disc, &ok_d));
+      *ok = *ok & (ok_d | !(disc >= 0.0));
+      const double e = sig * dhat;
+      const bool fin = __builtin_isfinite(e), hit = h_contains0(G, K, e, band);
+      vote = vote | ((disc >= 0.0) & fin & hit);
+    } else if (disc >= 0.0) {
       double dhat = delta - Q / (A + sqrt(disc));
       double e = sig * dhat;
       if (__builtin_isfinite(e) && h_contains0(G, K, e, band)) vote = true;
     }
   }
   return vote;
+}
+
+template <bool EXACT = false>
+IA_HD bool stereo_vote(const PairQ& q, double R, double sig, Iv K, double z0, double lam, double lamR,
+                       double lam2, double tt, double t2, double d, double band) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  if constexpr (!EXACT) {
+    bool ok = true;
+    const bool v = stereo_vote_t<false, true>(q, R, sig, K, z0, lam, lamR, lam2, tt, t2, d, band, &ok);
+    if (ok) return v;
+  }
+#endif
+  return stereo_vote_t<EXACT, false>(q, R, sig, K, z0, lam, lamR, lam2, tt, t2, d, band, nullptr);
 }
 
 // ---------------------------------------------------------------------------
@@ -2041,9 +2091,9 @@ __global__ void __launch_bounds__(kWG) k_vote(const HitRec* __restrict__ hits, E
   const uint32_t n_tr = sh.n_parents * sh.m012;
   const uint32_t n_tiles = (sh.n_boxes + BX - 1) / BX;
   const uint32_t n_items = live_list ? static_cast<uint32_t>(ev[e].n_live) : n_tiles;
-  __shared__ double sq[13][kCap + 16];
+  __shared__ double sq[14][kCap + 16];
   // FP32 levels stage 16 floats per pair in the same storage
-  static_assert(sizeof(PairQ32) == 16 * sizeof(float) && 16 * 4 <= 13 * 8, "FP32 staging fits");
+  static_assert(sizeof(PairQ32) == 16 * sizeof(float) && 16 * 4 <= 14 * 8, "FP32 staging fits");
   float(*sq32)[kCap + 16] = reinterpret_cast<float(*)[kCap + 16]>(&sq[0][0]);
   __shared__ int8_t sflag[kCap + 16];
   __shared__ int8_t stlive[kWG];
@@ -2134,7 +2184,7 @@ __global__ void __launch_bounds__(kWG) k_vote(const HitRec* __restrict__ hits, E
             sq[0][slot] = q.Glo; sq[1][slot] = q.Ghi; sq[2][slot] = q.sArc; sq[3][slot] = q.dphi;
             sq[4][slot] = q.RAx; sq[5][slot] = q.sinA; sq[6][slot] = q.cosA; sq[7][slot] = q.sAx;
             sq[8][slot] = q.cAx; sq[9][slot] = q.c2; sq[10][slot] = q.s2; sq[11][slot] = q.twoRAx2;
-            sq[12][slot] = q.RpRAx;
+            sq[12][slot] = q.rRAx; sq[13][slot] = q.r2RAx2;
           }
         }
         __syncthreads();
@@ -2156,7 +2206,8 @@ __global__ void __launch_bounds__(kWG) k_vote(const HitRec* __restrict__ hits, E
             q.Glo = sq[0][slot]; q.Ghi = sq[1][slot]; q.sArc = sq[2][slot]; q.dphi = sq[3][slot];
             q.RAx = sq[4][slot]; q.sinA = sq[5][slot]; q.cosA = sq[6][slot]; q.sAx = sq[7][slot];
             q.cAx = sq[8][slot]; q.c2 = sq[9][slot]; q.s2 = sq[10][slot]; q.twoRAx2 = sq[11][slot];
-            q.RpRAx = sq[12][slot];
+            q.rRAx = sq[12][slot]; q.r2RAx2 = sq[13][slot];
+            q.RpRAx = f.R + q.RAx;             // as pair_quantities forms it, same frame
             const double tt = h.tant;
             if (stereo_vote<EXACT>(q, f.R, f.sig, f.K, z0, lam, lamR, lam2, tt, tt * tt, h.d, h.band)) ++nv;
           }
@@ -2238,14 +2289,14 @@ __global__ void __launch_bounds__(kWG, 4) k_vote_rec(EvView vw, const BoxD* __re
                                                   int32_t* __restrict__ wg_max_all,
                                                   unsigned long long* __restrict__ work) {
   constexpr int HS = kWG / BX;
-  constexpr int NQ = F32 ? 8 : 16;               // doubles of LDS per staged record
+  constexpr int NQ = F32 ? 8 : 17;               // doubles of LDS per staged record
   static_assert(BX % 64 == 0 && HS * BX == kWG, "slices are whole waves");
   const uint32_t n_items = static_cast<uint32_t>(live_off[n_ev]);
   __shared__ double sq[NQ][kCap + 16];
   float(*sq32)[kCap + 16] = reinterpret_cast<float(*)[kCap + 16]>(&sq[0][0]);
   __shared__ int8_t sflag[kCap + 16];
   __shared__ int8_t stlive[kWG];
-  __shared__ uint32_t shist[kHistLds];
+  __shared__ uint32_t shist[kHistLdsRec];
   __shared__ int32_t sred[HS][BX];
   __shared__ int32_t sbuf[kWG / 64];
   const uint32_t tid = threadIdx.x;
@@ -2338,8 +2389,10 @@ __global__ void __launch_bounds__(kWG, 4) k_vote_rec(EvView vw, const BoxD* __re
             sq32[12][slot] = q.RpRAx; sq32[13][slot] = q.tt; sq32[14][slot] = q.d; sq32[15][slot] = q.bs;
           } else {
             const RecD& q = recd[ri];
-            for (int c = 0; c < 13; ++c) sq[c][slot] = q.q[c];
-            sq[13][slot] = q.tt; sq[14][slot] = q.d; sq[15][slot] = q.band;
+            for (int c = 0; c < 12; ++c) sq[c][slot] = q.q[c];
+            sq[12][slot] = recip_v(q.q[4]);     // RAx
+            sq[13][slot] = recip_v(q.q[11]);    // twoRAx2
+            sq[14][slot] = q.tt; sq[15][slot] = q.d; sq[16][slot] = q.band;
           }
         }
         __syncthreads();
@@ -2359,9 +2412,10 @@ __global__ void __launch_bounds__(kWG, 4) k_vote_rec(EvView vw, const BoxD* __re
             q.Glo = sq[0][slot]; q.Ghi = sq[1][slot]; q.sArc = sq[2][slot]; q.dphi = sq[3][slot];
             q.RAx = sq[4][slot]; q.sinA = sq[5][slot]; q.cosA = sq[6][slot]; q.sAx = sq[7][slot];
             q.cAx = sq[8][slot]; q.c2 = sq[9][slot]; q.s2 = sq[10][slot]; q.twoRAx2 = sq[11][slot];
-            q.RpRAx = sq[12][slot];
-            const double tt = sq[13][slot];
-            if (stereo_vote<EXACT>(q, fr.R, fr.sig, K, z0, lam, lamR, lam2, tt, tt * tt, sq[14][slot], sq[15][slot]))
+            q.rRAx = sq[12][slot]; q.r2RAx2 = sq[13][slot];
+            q.RpRAx = fr.R + q.RAx;            // as k_stage's pair_quantities forms it
+            const double tt = sq[14][slot];
+            if (stereo_vote<EXACT>(q, fr.R, fr.sig, K, z0, lam, lamR, lam2, tt, tt * tt, sq[15][slot], sq[16][slot]))
               ++nv;
           }
         }
@@ -2385,7 +2439,7 @@ __global__ void __launch_bounds__(kWG, 4) k_vote_rec(EvView vw, const BoxD* __re
     for (int w = 0; w < kWG / 64; ++w) wmax = max(wmax, sbuf[w]);
     if (tid == 0) wg_max[tile] = wmax;
     if (hist && wmax >= T) {
-      const bool in_lds = n_bins <= kHistLds;
+      const bool in_lds = n_bins <= kHistLdsRec;
       if (in_lds) {
         for (int32_t i = tid; i < n_bins; i += kWG) shist[i] = 0u;
         __syncthreads();

@@ -42,29 +42,106 @@ constexpr double kExtFuzz = 0x1p-40;     // extremum-membership slack
 IA_HD double wdn(double x) { return x - fma(fabs(x), 0x1p-52, 0x1p-1074); }
 IA_HD double wup(double x) { return x + fma(fabs(x), 0x1p-52, 0x1p-1074); }
 
+// Horner step p z + c as one three-address fused multiply-add.  The
+// compiler's two-address form (the accumulator tied to the destination)
+// copies the coefficient, which stays live in a register, into the
+// destination first; written as v_fma_f64 it needs no copy.  The result is
+// the same correctly rounded fma.
+IA_HD double horner(double p, double z, double c) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  double r;
+  asm("v_fma_f64 %0, %1, %2, %3" : "=v"(r) : "v"(p), "v"(z), "s"(c));
+  return r;
+#else
+  return fma(p, z, c);
+#endif
+}
+
+// Square root and division forms for the per-box vote (device only).
+//
+// sqrt_fast: on 2^-767 <= x <= DBL_MAX the compiler's IEEE square root is a
+// reciprocal-square-root start followed by two coupled Newton steps on
+// (sqrt x, 1 / (2 sqrt x)) in fused multiply-adds (Markstein's scheme); its
+// range scaling and its selects for 0 and infinity are identities there.
+// This is that sequence without them, so the bits are the same; outside the
+// range it clears *ok (the caller then takes sqrt).
+IA_HD double sqrt_fast(double x, bool* ok) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  *ok = *ok & (x >= 0x1p-767) & (x <= 0x1.fffffffffffffp+1023);   // no short-circuit branches
+  const double g = __builtin_amdgcn_rsq(x);
+  double s = x * g, h = 0.5 * g;
+  const double r = fma(-h, s, 0.5);
+  s = fma(s, r, s);
+  h = fma(h, r, h);
+  double d = fma(-s, s, x);
+  s = fma(d, h, s);
+  d = fma(-s, s, x);
+  return fma(d, h, s);
+#else
+  (void)ok;
+  return sqrt(x);
+#endif
+}
+
+// Division by a value that many quotients share.  The compiler's IEEE
+// quotient n / d is: r = rcp(d) refined by two Newton steps, q = n r, then
+// q + r (n - d q) in fused multiply-adds, wrapped in a range scaling and a
+// special-case fix-up that are both identities when d lies in
+// [2^-300, 2^300] and the quotient in [2^-500, 2^500] (then n is finite,
+// nonzero and far from both ends of the exponent range).  recip_v gives that
+// r once per divisor (NaN outside the range); div_fast finishes one quotient
+// from it with the same operations, so the bits are those of n / d, and
+// clears *ok when the estimate q is outside the range (which covers n = 0,
+// an infinite or NaN n, and a NaN r).  On the host r is unused.
+IA_HD double recip_v(double d) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  if (!(d >= 0x1p-300 && d <= 0x1p300)) return __builtin_nan("");
+  double r = __builtin_amdgcn_rcp(d);
+  double e = fma(-d, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-d, r, 1.0);
+  return fma(r, e, r);
+#else
+  return 1.0 / d;
+#endif
+}
+
+IA_HD double div_fast(double n, double d, double r, bool* ok) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  const double q = n * r;
+  const double aq = fabs(q);
+  *ok = *ok & (aq >= 0x1p-500) & (aq <= 0x1p500);
+  return fma(fma(-d, q, n), r, q);
+#else
+  (void)r;
+  (void)ok;
+  return n / d;
+#endif
+}
+
 IA_HD double poly_sin(double r) {
   double z = r * r;
   double p = 1.0 / 355687428096000.0;      // 1/17!
-  p = fma(p, z, -1.0 / 1307674368000.0);   // 1/15!
-  p = fma(p, z, 1.0 / 6227020800.0);       // 1/13!
-  p = fma(p, z, -1.0 / 39916800.0);        // 1/11!
-  p = fma(p, z, 1.0 / 362880.0);           // 1/9!
-  p = fma(p, z, -1.0 / 5040.0);            // 1/7!
-  p = fma(p, z, 1.0 / 120.0);              // 1/5!
-  p = fma(p, z, -1.0 / 6.0);               // 1/3!
+  p = horner(p, z, -1.0 / 1307674368000.0);   // 1/15!
+  p = horner(p, z, 1.0 / 6227020800.0);       // 1/13!
+  p = horner(p, z, -1.0 / 39916800.0);        // 1/11!
+  p = horner(p, z, 1.0 / 362880.0);           // 1/9!
+  p = horner(p, z, -1.0 / 5040.0);            // 1/7!
+  p = horner(p, z, 1.0 / 120.0);              // 1/5!
+  p = horner(p, z, -1.0 / 6.0);               // 1/3!
   return fma(r * z, p, r);
 }
 
 IA_HD double poly_cos(double r) {
   double z = r * r;
   double q = 1.0 / 20922789888000.0;       // 1/16!
-  q = fma(q, z, -1.0 / 87178291200.0);     // 1/14!
-  q = fma(q, z, 1.0 / 479001600.0);        // 1/12!
-  q = fma(q, z, -1.0 / 3628800.0);         // 1/10!
-  q = fma(q, z, 1.0 / 40320.0);            // 1/8!
-  q = fma(q, z, -1.0 / 720.0);             // 1/6!
-  q = fma(q, z, 1.0 / 24.0);               // 1/4!
-  q = fma(q, z, -0.5);                     // 1/2!
+  q = horner(q, z, -1.0 / 87178291200.0);     // 1/14!
+  q = horner(q, z, 1.0 / 479001600.0);        // 1/12!
+  q = horner(q, z, -1.0 / 3628800.0);         // 1/10!
+  q = horner(q, z, 1.0 / 40320.0);            // 1/8!
+  q = horner(q, z, -1.0 / 720.0);             // 1/6!
+  q = horner(q, z, 1.0 / 24.0);               // 1/4!
+  q = horner(q, z, -0.5);                     // 1/2!
   return fma(z, q, 1.0);
 }
 
@@ -101,35 +178,26 @@ IA_HD void sincos_p(double x, double* s, double* c) {
   *c = ((q + 1) & 2) ? -cv : cv;
 }
 
-// sincos_p for the small corrections of the vote: below pi/4 in magnitude
-// the reduction is the identity (k = 0, r = x exactly), so the polynomials
-// alone give sincos_p's values bit for bit
+// below pi/4 in magnitude the reduction of sincos_p is the identity (k = 0,
+// r = x exactly), so the polynomials alone give sincos_p's values bit for bit
 constexpr double kPio4 = 0x1.921fb54442d18p-1;   // below pi/4
-IA_HD void sincos_small_p(double x, double* s, double* c) {
-  if (fabs(x) < kPio4) {
-    *s = poly_sin(x);
-    *c = poly_cos(x);
-  } else {
-    sincos_p(x, s, c);
-  }
-}
 
 IA_HD double poly_atan(double u) {
   double z = u * u;
   double p = 1.0 / 29.0;
-  p = fma(p, z, -1.0 / 27.0);
-  p = fma(p, z, 1.0 / 25.0);
-  p = fma(p, z, -1.0 / 23.0);
-  p = fma(p, z, 1.0 / 21.0);
-  p = fma(p, z, -1.0 / 19.0);
-  p = fma(p, z, 1.0 / 17.0);
-  p = fma(p, z, -1.0 / 15.0);
-  p = fma(p, z, 1.0 / 13.0);
-  p = fma(p, z, -1.0 / 11.0);
-  p = fma(p, z, 1.0 / 9.0);
-  p = fma(p, z, -1.0 / 7.0);
-  p = fma(p, z, 1.0 / 5.0);
-  p = fma(p, z, -1.0 / 3.0);
+  p = horner(p, z, -1.0 / 27.0);
+  p = horner(p, z, 1.0 / 25.0);
+  p = horner(p, z, -1.0 / 23.0);
+  p = horner(p, z, 1.0 / 21.0);
+  p = horner(p, z, -1.0 / 19.0);
+  p = horner(p, z, 1.0 / 17.0);
+  p = horner(p, z, -1.0 / 15.0);
+  p = horner(p, z, 1.0 / 13.0);
+  p = horner(p, z, -1.0 / 11.0);
+  p = horner(p, z, 1.0 / 9.0);
+  p = horner(p, z, -1.0 / 7.0);
+  p = horner(p, z, 1.0 / 5.0);
+  p = horner(p, z, -1.0 / 3.0);
   return fma(u * z, p, u);
 }
 
@@ -196,22 +264,22 @@ constexpr double kSmallMargin = 0x1p-40;
 IA_HD double sin_small(double x) {
   const double z = x * x;
   double p = 1.0 / 6227020800.0;
-  p = fma(p, z, -1.0 / 39916800.0);
-  p = fma(p, z, 1.0 / 362880.0);
-  p = fma(p, z, -1.0 / 5040.0);
-  p = fma(p, z, 1.0 / 120.0);
-  p = fma(p, z, -1.0 / 6.0);
+  p = horner(p, z, -1.0 / 39916800.0);
+  p = horner(p, z, 1.0 / 362880.0);
+  p = horner(p, z, -1.0 / 5040.0);
+  p = horner(p, z, 1.0 / 120.0);
+  p = horner(p, z, -1.0 / 6.0);
   return fma(x * z, p, x);
 }
 IA_HD double cos_small(double x) {
   const double z = x * x;
   double q = -1.0 / 87178291200.0;
-  q = fma(q, z, 1.0 / 479001600.0);
-  q = fma(q, z, -1.0 / 3628800.0);
-  q = fma(q, z, 1.0 / 40320.0);
-  q = fma(q, z, -1.0 / 720.0);
-  q = fma(q, z, 1.0 / 24.0);
-  q = fma(q, z, -0.5);
+  q = horner(q, z, 1.0 / 479001600.0);
+  q = horner(q, z, -1.0 / 3628800.0);
+  q = horner(q, z, 1.0 / 40320.0);
+  q = horner(q, z, -1.0 / 720.0);
+  q = horner(q, z, 1.0 / 24.0);
+  q = horner(q, z, -0.5);
   return fma(z, q, 1.0);
 }
 IA_HD void sincos_encl_small(Iv x, Iv* S, Iv* C) {
