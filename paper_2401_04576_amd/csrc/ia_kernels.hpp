@@ -1872,12 +1872,17 @@ __global__ void __launch_bounds__(kWG) k_threshold(const int32_t* __restrict__ t
   }
 }
 
-// Staged records of a level: one thread per (listed triple, hit); each
-// class-2 pair computes its triple's frame, G and the pair quantities
-// (FP64, or their FP32 images at FP32 levels) and writes them, with the
-// hit's tan(tau), drift and band, to a slot of its triple's record range
-// (slots taken in any order: votes do not depend on it).  Every writer of a
-// triple also writes the same TriFrame.  Events with rec_ok == 0 are skipped.
+// Staged records of a level.  Items are (hit, listed triple) pairs; a
+// workgroup takes kStageBatch x kWG consecutive items, keeps the class-2
+// ones in an LDS list (most pairs are decided, so computing in place would
+// leave most lanes of a wave idle), then computes one record per listed
+// pair with all its lanes: the triple's frame, G and the pair quantities
+// (FP64, or their FP32 images at FP32 levels), written with the hit's
+// tan(tau), drift and band to a slot of its triple's record range (slots
+// taken in any order: votes do not depend on it).  Every writer of a triple
+// also writes the same TriFrame.  Events with rec_ok == 0 are skipped.
+constexpr int kStageBatch = 4;
+
 template <bool F32>
 __global__ void __launch_bounds__(kWG, 4) k_stage(const HitRec* __restrict__ hits_all, EvView vw,
                                                const BoxD* __restrict__ parents_all, Shape sh,
@@ -1889,47 +1894,88 @@ __global__ void __launch_bounds__(kWG, 4) k_stage(const HitRec* __restrict__ hit
                                                int32_t n_ev, float slack32) {
   const uint32_t n_tr = sh.n_parents * sh.m012;
   const int64_t n_items = stage_off[n_ev];
-  for (int64_t i = int64_t(blockIdx.x) * kWG + threadIdx.x; i < n_items; i += int64_t(gridDim.x) * kWG) {
-    // the item's event: the last one whose first item is at or before it
-    int32_t elo = 0, ehi = n_ev - 1;
-    while (elo < ehi) {
-      const int32_t mid = (elo + ehi + 1) >> 1;
-      if (stage_off[mid] <= i) elo = mid;
-      else ehi = mid - 1;
+  __shared__ int64_t slist[kStageBatch * kWG];
+  __shared__ int32_t sev[kStageBatch * kWG];
+  __shared__ int32_t scount;
+  const int64_t span = int64_t(kStageBatch) * kWG;
+  for (int64_t base = int64_t(blockIdx.x) * span; base < n_items; base += int64_t(gridDim.x) * span) {
+    if (threadIdx.x == 0) scount = 0;
+    // the event of the batch's first item: the last one whose first item is
+    // at or before it (the same for every thread); later items step forward
+    int32_t e_base = 0;
+    {
+      int32_t elo = 0, ehi = n_ev - 1;
+      while (elo < ehi) {
+        const int32_t mid = (elo + ehi + 1) >> 1;
+        if (stage_off[mid] <= base) elo = mid;
+        else ehi = mid - 1;
+      }
+      e_base = elo;
     }
-    const int e = elo;
-    const int32_t n_hits = vw.count(e);
-    const int64_t il = i - stage_off[e];
-    const HitRec* hits = hits_all + vw.beg(e);
-    const BoxD* parents = parents_all + e * vw.par_stride;
-    const uint8_t* flags = flags_all + e * vw.flag_stride;
-    const int32_t* rec_off = rec_off_all + e * vw.tri_stride;
-    int32_t* rec_fill = rec_fill_all + e * vw.tri_stride;
-    TriFrame* tfr = tfr_all + e * vw.tri_stride;
-    const uint32_t t = static_cast<uint32_t>(live_tri_all[e * vw.tri_stride + il / n_hits]);
-    const int32_t h = static_cast<int32_t>(il % n_hits);
-    if (flags[int64_t(h) * n_tr + t] != 2) continue;
-    const HitRec hr = hits[h];
-    const uint32_t tc = t % sh.m012;
-    const Frame f = triple_frame(parents[t / sh.m012], sh.m, tc / sh.m12, (tc / sh.m[2]) % sh.m[1], tc % sh.m[2]);
-    const int64_t slot = int64_t(e) * vw.rec_stride + rec_off[t] + atomicAdd(&rec_fill[t], 1);
-    if constexpr (F32) {
-      const Frame32 g32 = frame32_of(f);
-      reinterpret_cast<PairQ32*>(rec)[slot] = pair_q32_f32(g32, hr, slack32);
-      tfr[t] = TriFrame{static_cast<double>(g32.R), static_cast<double>(g32.sig), f.K.lo, f.K.hi};
-    } else {
-      const Iv G = residual_G(f, hr);
-      const PairQ q = pair_quantities(f, hr, G);
-      RecD r;
-      r.q[0] = q.Glo; r.q[1] = q.Ghi; r.q[2] = q.sArc; r.q[3] = q.dphi; r.q[4] = q.RAx; r.q[5] = q.sinA;
-      r.q[6] = q.cosA; r.q[7] = q.sAx; r.q[8] = q.cAx; r.q[9] = q.c2; r.q[10] = q.s2; r.q[11] = q.twoRAx2;
-      r.q[12] = q.RpRAx;
-      r.tt = hr.tant;
-      r.d = hr.d;
-      r.band = hr.band;
-      reinterpret_cast<RecD*>(rec)[slot] = r;
-      tfr[t] = TriFrame{f.R, f.sig, f.K.lo, f.K.hi};
+    __syncthreads();
+    int32_t e = e_base;
+    for (int r = 0; r < kStageBatch; ++r) {
+      const int64_t i = base + int64_t(r) * kWG + threadIdx.x;
+      bool keep = false;
+      if (i < n_items) {
+        while (e + 1 < n_ev && stage_off[e + 1] <= i) ++e;
+        // hit-major within the event: neighbouring lanes read neighbouring
+        // live triples' flags of one hit (flags are [hit][triple])
+        const int64_t n_lt = (stage_off[e + 1] - stage_off[e]) / vw.count(e);
+        const int64_t il = i - stage_off[e];
+        const uint32_t t = static_cast<uint32_t>(live_tri_all[e * vw.tri_stride + il % n_lt]);
+        const int32_t h = static_cast<int32_t>(il / n_lt);
+        keep = flags_all[e * vw.flag_stride + int64_t(h) * n_tr + t] == 2;
+      }
+      // wave-level compaction: one LDS atomic per wave
+      const unsigned long long m = __ballot(keep);
+      const uint32_t lane = threadIdx.x & 63u;
+      int32_t wbase = 0;
+      if (lane == 0 && m) wbase = atomicAdd(&scount, __popcll(m));
+      wbase = __shfl(wbase, 0, 64);
+      if (keep) {
+        const int32_t pos = wbase + __popcll(m & ((1ull << lane) - 1ull));
+        slist[pos] = i;
+        sev[pos] = e;
+      }
     }
+    __syncthreads();
+    const int32_t n = scount;
+    for (int32_t j = threadIdx.x; j < n; j += kWG) {
+      const int64_t i = slist[j];
+      const int e = sev[j];
+      const int64_t n_lt = (stage_off[e + 1] - stage_off[e]) / vw.count(e);
+      const int64_t il = i - stage_off[e];
+      const HitRec* hits = hits_all + vw.beg(e);
+      const BoxD* parents = parents_all + e * vw.par_stride;
+      const int32_t* rec_off = rec_off_all + e * vw.tri_stride;
+      int32_t* rec_fill = rec_fill_all + e * vw.tri_stride;
+      TriFrame* tfr = tfr_all + e * vw.tri_stride;
+      const uint32_t t = static_cast<uint32_t>(live_tri_all[e * vw.tri_stride + il % n_lt]);
+      const int32_t h = static_cast<int32_t>(il / n_lt);
+      const HitRec hr = hits[h];
+      const uint32_t tc = t % sh.m012;
+      const Frame f = triple_frame(parents[t / sh.m012], sh.m, tc / sh.m12, (tc / sh.m[2]) % sh.m[1], tc % sh.m[2]);
+      const int64_t slot = int64_t(e) * vw.rec_stride + rec_off[t] + atomicAdd(&rec_fill[t], 1);
+      if constexpr (F32) {
+        const Frame32 g32 = frame32_of(f);
+        reinterpret_cast<PairQ32*>(rec)[slot] = pair_q32_f32(g32, hr, slack32);
+        tfr[t] = TriFrame{static_cast<double>(g32.R), static_cast<double>(g32.sig), f.K.lo, f.K.hi};
+      } else {
+        const Iv G = residual_G(f, hr);
+        const PairQ q = pair_quantities(f, hr, G);
+        RecD r;
+        r.q[0] = q.Glo; r.q[1] = q.Ghi; r.q[2] = q.sArc; r.q[3] = q.dphi; r.q[4] = q.RAx; r.q[5] = q.sinA;
+        r.q[6] = q.cosA; r.q[7] = q.sAx; r.q[8] = q.cAx; r.q[9] = q.c2; r.q[10] = q.s2; r.q[11] = q.twoRAx2;
+        r.q[12] = q.RpRAx;
+        r.tt = hr.tant;
+        r.d = hr.d;
+        r.band = hr.band;
+        reinterpret_cast<RecD*>(rec)[slot] = r;
+        tfr[t] = TriFrame{f.R, f.sig, f.K.lo, f.K.hi};
+      }
+    }
+    __syncthreads();                     // the list is rebuilt for the next batch
   }
 }
 
@@ -2675,6 +2721,33 @@ struct EstimateOut {
 
 constexpr int kEstQ = 16;        // 5 sums, 5 minima, 5 maxima, count
 constexpr int kEstPer = 16;      // chunks per k_est_partial workgroup
+static_assert(kEstPer <= 32, "chunks_reaching keeps one bit per chunk of a workgroup");
+
+// Which of a workgroup's 256-box chunks [c0, c1) (at most 32) can hold a
+// box with `vlo` votes or more: bit ch - c0 is clear when the chunk lies past
+// the level's boxes or every vote tile it overlaps (tiles of bx boxes, bx =
+// 64, 128 or 256) has its maximum below vlo.  The tile maxima are read once,
+// spread over the workgroup's threads, so the chunks' own loop needs no
+// further global read to skip a chunk.  Call from every thread; the result
+// is the same for all.
+__device__ uint32_t chunks_reaching(const int32_t* wg_max, int32_t bx, uint32_t c0, uint32_t c1, uint32_t n_boxes,
+                                    int32_t vlo, uint32_t* smask) {
+  const uint32_t b0 = c0 * static_cast<uint32_t>(kWG);
+  if (threadIdx.x == 0) *smask = 0u;
+  __syncthreads();
+  if (b0 < n_boxes) {
+    const uint32_t b1 = min(c1 * static_cast<uint32_t>(kWG), n_boxes) - 1;
+    if (!wg_max) {
+      if (threadIdx.x == 0) *smask = (b1 / kWG - c0 == 31) ? 0xffffffffu : ((2u << (b1 / kWG - c0)) - 1u);
+    } else {
+      const uint32_t ub = static_cast<uint32_t>(bx);
+      for (uint32_t t = b0 / ub + threadIdx.x; t <= b1 / ub; t += kWG)
+        if (wg_max[t] >= vlo) atomicOr(smask, 1u << ((t * ub) / kWG - c0));
+    }
+  }
+  __syncthreads();
+  return *smask;
+}
 
 __device__ __forceinline__ void tree_step(double (*s)[kWG], int w) {
   // s[q][i] = combine(s[q][2i], s[q][2i + 1]) for i < w / 2
@@ -2718,18 +2791,21 @@ __global__ void __launch_bounds__(kWG) k_est_partial(const BoxD* __restrict__ pa
   const double c0 = 0.5 * (first_box->lo[1] + first_box->hi[1]);
   const int32_t ra = use_run ? ev[e].run_a : -1, rb = use_run ? ev[e].run_b : -1;
   const uint32_t ch_end = min(n_part, (blockIdx.x + 1) * per);
+  __shared__ uint32_t smask;
+  const uint32_t reach = chunks_reaching(wg_max, bx, blockIdx.x * per, ch_end, sh.n_boxes, vmax, &smask);
   for (uint32_t ch = blockIdx.x * per; ch < ch_end; ++ch) {
     const uint32_t i = ch * kWG + threadIdx.x;
     double v[kEstQ];
     for (int q = 0; q < 5; ++q) { v[q] = 0.0; v[5 + q] = INFINITY; v[10 + q] = -INFINITY; }
     v[15] = 0.0;
     // with wg_max, only tiles whose maximum reaches vmax hold written votes
-    const bool at_max = i < sh.n_boxes && (!wg_max || wg_max[i / static_cast<uint32_t>(bx)] >= vmax) &&
+    const bool may = (reach >> (ch - blockIdx.x * per)) & 1u;
+    const bool at_max = may && i < sh.n_boxes && (!wg_max || wg_max[i / static_cast<uint32_t>(bx)] >= vmax) &&
                         votes[i] == vmax && in_run(phi_bin(sh, i), ra, rb);
     // a chunk without a max-vote box reduces to the identity (sums 0,
     // minima +inf, maxima -inf, count 0), bit for bit: write it without the
     // tree
-    if (!__syncthreads_or(at_max ? 1 : 0)) {
+    if (!may || !__syncthreads_or(at_max ? 1 : 0)) {
       if (threadIdx.x < kEstQ) {
         const int q = static_cast<int>(threadIdx.x);
         part[ch * kEstQ + q] = (q >= 5 && q < 10) ? INFINITY : ((q >= 10 && q < 15) ? -INFINITY : 0.0);
@@ -3338,11 +3414,46 @@ __global__ void __launch_bounds__(kWG) k_window_partial(const BoxD* __restrict__
   // reduction at the end writes the workgroup's record part[blockIdx.x]
   double vl[5], vh[5];
   for (int j = 0; j < 5; ++j) { vl[j] = INFINITY; vh[j] = -INFINITY; }
+  // moving window: the transverse corners of each (d0, phi0, kappa) triple
+  // of a chunk, shifted once into the new frame (d1, phi1, arc) and shared
+  // by the triple's boxes (the boxes of a triple differ only in z0, tanl)
+  __shared__ double scorner[kWG][3];
+  const uint32_t m34 = sh.m[3] * sh.m[4];
+  const bool table = mv && (static_cast<uint32_t>(kWG) / m34 + 2) * 8 <= static_cast<uint32_t>(kWG);
   const uint32_t ch_end = min(n_part, (blockIdx.x + 1) * per);
+  __shared__ uint32_t smask;
+  const uint32_t reach = chunks_reaching(wg_max, bx, blockIdx.x * per, ch_end, sh.n_boxes, vlo, &smask);
   for (uint32_t ch = blockIdx.x * per; ch < ch_end; ++ch) {
+    if (!((reach >> (ch - blockIdx.x * per)) & 1u)) continue;
     const uint32_t i = ch * kWG + threadIdx.x;
     const bool in_set = i < sh.n_boxes && (!wg_max || wg_max[i / static_cast<uint32_t>(bx)] >= vlo) &&
                         votes[i] >= vlo && in_run(phi_bin(sh, i), ra, rb);
+    const uint32_t t_first = (ch * kWG) / m34;
+    if (table) {
+      if (!__syncthreads_or(in_set ? 1 : 0)) continue;
+      const uint32_t t_last = (min(ch * kWG + kWG, sh.n_boxes) - 1) / m34;
+      const uint32_t n_c = (t_last - t_first + 1) * 8;
+      for (uint32_t cidx = threadIdx.x; cidx < n_c; cidx += kWG) {
+        uint32_t kt[5];
+        child_index(sh.m, ((t_first + cidx / 8) * m34) % sh.nc, kt);
+        const int c = static_cast<int>(cidx % 8);
+        double cl[3];
+        for (int j = 0; j < 3; ++j) {
+          const bool up = (c >> j) & 1;
+          const uint32_t kk = kt[j] + (up ? 1u : 0u);
+          cl[j] = (up && kk == sh.m[j]) ? P.hi[j] : P.lo[j] + static_cast<double>(kk) * w[j];
+        }
+        double d1, f1, arc;
+        frame_shift_t(cl[0], cl[1], cl[2], dx, dy, &d1, &f1, &arc);
+        const double dv = f1 - cref;
+        if (dv > kPi) f1 -= kTwoPi;
+        else if (dv <= -kPi) f1 += kTwoPi;
+        scorner[cidx][0] = d1;
+        scorner[cidx][1] = f1;
+        scorner[cidx][2] = arc;
+      }
+      __syncthreads();
+    }
     if (in_set) {
       uint32_t k[5];
       child_index(sh.m, i % sh.nc, k);
@@ -3362,13 +3473,21 @@ __global__ void __launch_bounds__(kWG) k_window_partial(const BoxD* __restrict__
       } else {
         // the 32 corners: the transverse part of each of the 8 (d0, phi0,
         // kappa) corners once, then z0 + tanl x arc for its 4 (z0, tanl) corners
+        const uint32_t tl = i / m34 - t_first;
         for (int c = 0; c < 8; ++c) {
-          const double d0 = (c & 1) ? hi[0] : lo[0], f0 = (c & 2) ? hi[1] : lo[1], kk = (c & 4) ? hi[2] : lo[2];
+          const double kk = (c & 4) ? hi[2] : lo[2];
           double d1, f1, arc;
-          frame_shift_t(d0, f0, kk, dx, dy, &d1, &f1, &arc);
-          const double dv = f1 - cref;
-          if (dv > kPi) f1 -= kTwoPi;
-          else if (dv <= -kPi) f1 += kTwoPi;
+          if (table) {
+            d1 = scorner[tl * 8 + c][0];
+            f1 = scorner[tl * 8 + c][1];
+            arc = scorner[tl * 8 + c][2];
+          } else {
+            const double d0 = (c & 1) ? hi[0] : lo[0], f0 = (c & 2) ? hi[1] : lo[1];
+            frame_shift_t(d0, f0, kk, dx, dy, &d1, &f1, &arc);
+            const double dv = f1 - cref;
+            if (dv > kPi) f1 -= kTwoPi;
+            else if (dv <= -kPi) f1 += kTwoPi;
+          }
           vl[0] = fmin(vl[0], d1); vh[0] = fmax(vh[0], d1);
           vl[1] = fmin(vl[1], f1); vh[1] = fmax(vh[1], f1);
           vl[2] = fmin(vl[2], kk); vh[2] = fmax(vh[2], kk);
@@ -3418,7 +3537,10 @@ __global__ void __launch_bounds__(kWG) k_phi_occ(const uint16_t* __restrict__ vo
   __syncthreads();
   const int32_t vmax = first_votes[int64_t(e) * vw.k];
   const uint32_t ch_end = min(n_part, (blockIdx.x + 1) * per);
+  __shared__ uint32_t smask;
+  const uint32_t reach = chunks_reaching(wg_max, bx, blockIdx.x * per, ch_end, sh.n_boxes, vmax, &smask);
   for (uint32_t ch = blockIdx.x * per; ch < ch_end; ++ch) {
+    if (!((reach >> (ch - blockIdx.x * per)) & 1u)) continue;
     const uint32_t i = ch * kWG + threadIdx.x;
     const bool at = i < sh.n_boxes && wg_max[i / static_cast<uint32_t>(bx)] >= vmax && votes[i] == vmax;
     const int32_t key = at ? static_cast<int32_t>(phi_bin(sh, i)) : -1;
