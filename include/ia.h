@@ -278,14 +278,19 @@ ia_status ia_ctx_set_vote_tile(ia_ctx *ctx, int32_t boxes_per_workgroup);
  * it. */
 ia_status ia_ctx_set_prefilter(ia_ctx *ctx, int32_t mode);
 
-/* Pruning in ia_find_helices (enabled by default): per level, each triple's
- * votes are bounded from below by its pairs proved to vote everywhere and
- * from above by adding the pairs left undecided; a triple whose upper bound
- * is below the k-th largest lower bound over boxes holds no box the
- * selection can take, so its boxes are not evaluated.  Selections,
- * estimates and helices do not depend on it; only the internal vote array of
- * a level differs (pruned boxes hold their lower bound). */
-ia_status ia_ctx_set_pruning(ia_ctx *ctx, int32_t enable);
+/* Pruning in ia_find_helices: per level, each triple's votes are bounded
+ * from below by its pairs proved to vote everywhere and from above by adding
+ * the pairs left undecided; a triple whose upper bound is below the k-th
+ * largest lower bound over boxes holds no box the selection can take, so its
+ * boxes are not evaluated.  mode 0: off; 1: that threshold; 2 (default):
+ * under the window schedule each level first votes the few triples with the
+ * largest upper bounds (a probe), and the largest vote found there, when it
+ * is above the largest lower bound, takes that bound's place in the
+ * threshold (the maximum is at least both).  Selections, estimates and
+ * helices do not depend on the mode; only the internal vote array of a level
+ * differs (pruned boxes hold their lower bound).  IA_ERR_INVALID for another
+ * mode. */
+ia_status ia_ctx_set_pruning(ia_ctx *ctx, int32_t mode);
 
 /* Parent-level exclusion in ia_find_helices (enabled by default): at each
  * refinement level, an interval enclosure over all of a parent's children

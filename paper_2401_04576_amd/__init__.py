@@ -273,9 +273,12 @@ class Context:
         """Maximum events per batched launch of find_helices."""
         self._check(self._L.ia_ctx_set_batch(self._h, int(max_events)))
 
-    def set_pruning(self, enable=True):
-        """find_helices: skip triples whose vote upper bound cannot reach the selection."""
-        self._check(self._L.ia_ctx_set_pruning(self._h, 1 if enable else 0))
+    def set_pruning(self, enable=True, probe=True):
+        """find_helices: skip triples whose vote upper bound cannot reach the
+        selection; with `probe` (window schedule) the threshold is raised by
+        the largest vote among the triples with the largest upper bounds,
+        voted first."""
+        self._check(self._L.ia_ctx_set_pruning(self._h, (2 if probe else 1) if enable else 0))
 
     def autotune(self, hits, offsets, sched, max_per_event=16, stream=None):
         """Pick the vote tile per level size by timing a sample batch; returns {level boxes: tile}."""

@@ -1740,13 +1740,25 @@ IA_HD bool triple_live(int32_t lb, int32_t n2, int32_t T, uint32_t t, int32_t tc
 // of them (votes desc, index asc); a triple after t_cut whose upper bound is
 // T is pruned too.  The maximum is unchanged (it is at least T).
 // ev->t_cut = INT32_MAX without ties.
+//
+// Probe (probe = 1, one-box selections, before the level's vote): T is the
+// kProbeTriples-th largest upper bound over the triples with class-2 pairs
+// (no triple when fewer hold such pairs), no drop, and every tile's wg_max is
+// set to -1, so that after a vote of the listed tiles (without histogram) the
+// largest wg_max is the largest vote v1 found among them, or -1.  After a
+// probe (probe = 2): v1 is read from wg_max first, and T = max(T, v1) - drop.
+// A box with at least vmax - drop votes has at least max(T, v1) - drop
+// (vmax >= T and vmax >= v1), so its triple is still evaluated: selections
+// and maxima are those of the plain threshold.
+constexpr int32_t kProbeTriples = 8;
+
 __global__ void __launch_bounds__(kWG) k_threshold(const int32_t* __restrict__ tlb, const int32_t* __restrict__ tn2,
                                                    uint32_t* __restrict__ lbh, EvView vw, Shape sh, int32_t k,
                                                    int32_t prune, int32_t ties, int32_t bx, EventState* __restrict__ ev,
                                                    int32_t* __restrict__ live_list, int32_t* __restrict__ wg_max,
                                                    int32_t* __restrict__ live_tri, int32_t* __restrict__ rec_off,
                                                    int32_t* __restrict__ rec_fill, int64_t rec_cap,
-                                                   int32_t drop) {
+                                                   int32_t drop, int32_t probe) {
   const int e = blockIdx.y;
   if (ev[e].done) return;
   const int32_t n_bins = vw.count(e) + 1;
@@ -1759,24 +1771,51 @@ __global__ void __launch_bounds__(kWG) k_threshold(const int32_t* __restrict__ t
   __shared__ int32_t s_T;
   __shared__ int32_t sbuf[kWG / 64];
   const uint32_t tid = threadIdx.x;
+  const uint32_t n_tiles = (sh.n_boxes + static_cast<uint32_t>(bx) - 1) / static_cast<uint32_t>(bx);
+  int32_t v1 = -1;
+  if (prune && probe == 2) {
+    // the largest vote the probe found (its tiles' maxima; -1 elsewhere)
+    for (uint32_t tile = tid; tile < n_tiles; tile += kWG) v1 = max(v1, wg_max[tile]);
+    for (int o = 32; o > 0; o >>= 1) v1 = max(v1, __shfl_down(v1, o, 64));
+    if ((tid & 63) == 0) sbuf[tid >> 6] = v1;
+    __syncthreads();
+    v1 = -1;
+    for (int w = 0; w < kWG / 64; ++w) v1 = max(v1, sbuf[w]);
+    __syncthreads();
+  }
   if (prune) {
     uint32_t* hh = sh_h;
     if (n_bins > kHistLds) hh = lbh + int64_t(e) * vw.hist_stride;
     else
       for (int32_t b = tid; b < n_bins; b += kWG) sh_h[b] = 0u;
     __syncthreads();
-    for (uint32_t t = tid; t < n_tr; t += kWG) atomicAdd(&hh[min(tlb[t], n_bins - 1)], 1u);
+    if (probe == 1) {
+      for (uint32_t t = tid; t < n_tr; t += kWG)
+        if (tn2[t] > 0) atomicAdd(&hh[min(tlb[t] + tn2[t], n_bins - 1)], 1u);
+    } else {
+      for (uint32_t t = tid; t < n_tr; t += kWG) atomicAdd(&hh[min(tlb[t], n_bins - 1)], 1u);
+    }
     __syncthreads();
     if (tid == 0) {
-      const int64_t k_eff = min(static_cast<int64_t>(k), static_cast<int64_t>(sh.n_boxes));
-      int64_t cum = 0;
-      int32_t T = 0;
-      for (int32_t v = n_bins - 1; v >= 0; --v) {
-        cum += static_cast<int64_t>(hh[v]) * sh.m34;
-        if (cum >= k_eff) { T = v; break; }
+      if (probe == 1) {
+        int64_t cum = 0;
+        int32_t T = n_bins;               // no triple when fewer than kProbeTriples hold class-2 pairs
+        for (int32_t v = n_bins - 1; v >= 0; --v) {
+          cum += static_cast<int64_t>(hh[v]);
+          if (cum >= kProbeTriples) { T = v; break; }
+        }
+        s_T = T;
+      } else {
+        const int64_t k_eff = min(static_cast<int64_t>(k), static_cast<int64_t>(sh.n_boxes));
+        int64_t cum = 0;
+        int32_t T = 0;
+        for (int32_t v = n_bins - 1; v >= 0; --v) {
+          cum += static_cast<int64_t>(hh[v]) * sh.m34;
+          if (cum >= k_eff) { T = v; break; }
+        }
+        // drop: boxes down to `drop` votes below the maximum are needed exactly
+        s_T = max(max(T, v1) - drop, 0);
       }
-      // drop: boxes down to `drop` votes below the maximum are needed exactly
-      s_T = max(T - drop, 0);
     }
     __syncthreads();
     if (n_bins > kHistLds)
@@ -1813,7 +1852,6 @@ __global__ void __launch_bounds__(kWG) k_threshold(const int32_t* __restrict__ t
   // live tiles, compacted in index order: each thread takes a contiguous run
   // of tiles, counts its live ones, and one block scan places them
   auto triple_of = [&](uint32_t x) { return (x / sh.nc) * sh.m012 + (x % sh.nc) / sh.m34; };
-  const uint32_t n_tiles = (sh.n_boxes + static_cast<uint32_t>(bx) - 1) / static_cast<uint32_t>(bx);
   const uint32_t per = (n_tiles + kWG - 1) / kWG;
   const uint32_t ta = min(tid * per, n_tiles), tb = min(ta + per, n_tiles);
   auto tile_live = [&](uint32_t tile) {
@@ -1831,9 +1869,8 @@ __global__ void __launch_bounds__(kWG) k_threshold(const int32_t* __restrict__ t
     if (lv) {
       ++mine;
       if (tile - ta < 32u) lmask |= 1u << (tile - ta);
-    } else {
-      wg_max[tile] = -1;
     }
+    if (!lv || probe == 1) wg_max[tile] = -1;
   }
   int32_t pos;
   const int32_t total = block_scan_count(mine, &pos, sbuf);

@@ -70,7 +70,7 @@ struct ia_ctx {
   bool profiling = false;
   int32_t tile_override = 0;
   int32_t filter_mode = -1;       // -1: automatic, 0: off, 1: on
-  int32_t prune = 1;              // ia_find_helices: skip triples that cannot reach the selection
+  int32_t prune = 2;              // ia_find_helices: skip triples that cannot reach the selection (2: with a probe)
   int32_t parent_filter = 1;      // ia_find_helices: parent-level exclusion at refinement levels
   int32_t count_work = 0;         // classification launches count their work
   int32_t max_chunk = 65535;      // events per batched launch
@@ -631,9 +631,20 @@ ia_status run_window(ia_ctx* c, const double* hits, ia::EvView vw, int32_t E, in
         if (cs != IA_OK) return cs;
       }
       const int32_t vt = iv ? ia::kWG : vote_tile(c, sh.n_boxes, E);
+      // probe: vote the triples with the largest upper bounds first; the
+      // largest vote found raises the level's pruning threshold
+      const bool probe = c->prune == 2 && !iv;
+      if (probe) {
+        hipLaunchKernelGGL(ia::k_threshold, dim3(1, E), dim3(ia::kWG), 0, s, tlb, tn2, lbh, vw, sh, 1, 1, 0, vt, ev,
+                           live, wg_max, rin.live_tri, rin.rec_off, rin.rec_fill, L.rec_stride, 0, 1);
+        launch_stage(recs, vw, E, par, sh, flags, rin, ev, s, f32, slack32);
+        const VoteIn pin{flags, tlb, tn2, live, 1};
+        const ia_status st = launch_vote_rec(c, vw, E, par, sh, votes, nullptr, ev, pin, rin, wg_max, s, f32, exact);
+        if (st != IA_OK) return st;
+      }
       hipLaunchKernelGGL(ia::k_threshold, dim3(1, E), dim3(ia::kWG), 0, s, tlb, tn2, lbh, vw, sh, 1, c->prune, 0,
                          vt, ev, live, wg_max, rin.live_tri, rin.rec_off, rin.rec_fill,
-                         iv ? INT64_MAX : L.rec_stride, lev < sc->n_refine ? sc->wdrop : 0);
+                         iv ? INT64_MAX : L.rec_stride, lev < sc->n_refine ? sc->wdrop : 0, probe ? 2 : 0);
       int32_t bx = vt;
       if (iv) {
         hipLaunchKernelGGL(ia::k_live_offsets, dim3(1), dim3(ia::kWG), 0, s, ev, vw, E, rin.live_off, rin.stage_off);
@@ -811,7 +822,7 @@ ia_status run_chunk(ia_ctx* c, const double* hits_chunk, const int32_t* h_off_ch
       const int32_t ties = last ? 0 : 1;
       hipLaunchKernelGGL(ia::k_threshold, dim3(1, E), dim3(ia::kWG), 0, s, tlb, tn2, lbh, vw, sh, k_lev, c->prune,
                          ties, vt, ev, live, wg_max, rin.live_tri, rin.rec_off, rin.rec_fill,
-                         iv ? INT64_MAX : L.rec_stride, 0);
+                         iv ? INT64_MAX : L.rec_stride, 0, 0);
       int32_t bx = vt;
       if (iv) {
         hipLaunchKernelGGL(ia::k_live_offsets, dim3(1), dim3(ia::kWG), 0, s, ev, vw, E, rin.live_off, rin.stage_off);
@@ -977,7 +988,8 @@ ia_status ia_ctx_set_prefilter(ia_ctx* c, int32_t mode) {
 
 ia_status ia_ctx_set_pruning(ia_ctx* c, int32_t enable) {
   if (!c) return IA_ERR_INVALID;
-  c->prune = enable != 0 ? 1 : 0;
+  if (enable < 0 || enable > 2) return fail(c, IA_ERR_INVALID, "pruning mode %d outside 0..2", enable);
+  c->prune = enable;
   return IA_OK;
 }
 

@@ -88,6 +88,31 @@ def test_window_multi_helix_full_schedule(ctx):
     _compare(ctx, events, _kw(n_helix_max=3, wdrop=1, hitsel=1), max_out=3)
 
 
+def test_window_pruning_modes_agree(ctx):
+    """Pruning off, by the largest lower bound, and with the probe pass (the
+    default): identical helices and assignments on a batch of multi-helix
+    events under the full window schedule, and the probe's threshold leaves
+    fewer per-box evaluations."""
+    events = [toymc.config_event(4, i) for i in range(30, 36)]
+    sched = ia.Schedule.make(H.LO, H.HI, **_kw(n_helix_max=3, wdrop=1, hitsel=1))
+    res, evals = {}, {}
+    try:
+        for mode in ("probe", "lower", "off"):
+            ctx.set_pruning(mode != "off", probe=mode == "probe")
+            ctx.clear_status()
+            res[mode] = _run_gpu(ctx, events, sched, 3)
+            evals[mode] = ctx.work()[0]
+    finally:
+        ctx.set_pruning(True)
+    hel, n_out, assigned, _ = res["probe"]
+    for mode in ("lower", "off"):
+        h2, n2, a2, _ = res[mode]
+        assert np.array_equal(n_out, n2) and np.array_equal(assigned, a2), mode
+        for e in range(len(events)):
+            assert hel[e, :n_out[e]].tobytes() == h2[e, :n2[e]].tobytes(), (mode, e)
+    assert evals["probe"] < evals["lower"] < evals["off"], evals
+
+
 def test_window_small_grids_batch_edges(ctx):
     """Empty events, a one-hit event and a large event next to ordinary ones in
     one batch (small window grids so that the oracle runs quickly)."""
