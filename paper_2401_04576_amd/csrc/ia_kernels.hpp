@@ -1743,7 +1743,8 @@ IA_HD bool triple_live(int32_t lb, int32_t n2, int32_t T, uint32_t t, int32_t tc
 //
 // Probe (probe = 1, one-box selections, before the level's vote): T is the
 // kProbeTriples-th largest upper bound over the triples with class-2 pairs
-// (no triple when fewer hold such pairs), no drop, and every tile's wg_max is
+// (no triple when fewer hold such pairs), cut among the triples at T in index
+// order so that kProbeTriples are voted, no drop, and every tile's wg_max is
 // set to -1, so that after a vote of the listed tiles (without histogram) the
 // largest wg_max is the largest vote v1 found among them, or -1.  After a
 // probe (probe = 2): v1 is read from wg_max first, and T = max(T, v1) - drop.
@@ -1844,6 +1845,31 @@ __global__ void __launch_bounds__(kWG) k_threshold(const int32_t* __restrict__ t
         if (tlb[t] < T) continue;
         cum += sh.m34;
         if (cum >= k_eff) { s_cut = static_cast<int32_t>(t); break; }
+      }
+    }
+    __syncthreads();
+  }
+  if (prune && probe == 1 && T < n_bins) {
+    // the probe's tie cut: exactly kProbeTriples triples with class-2 pairs,
+    // those whose upper bound is above T, then those at T in index order
+    const uint32_t pt = (n_tr + kWG - 1) / kWG;
+    const uint32_t ra = min(tid * pt, n_tr), rb = min(ra + pt, n_tr);
+    int32_t ca = 0, ct = 0;
+    for (uint32_t t = ra; t < rb; ++t)
+      if (tn2[t] > 0) {
+        const int32_t ub = tlb[t] + tn2[t];
+        ca += ub > T ? 1 : 0;
+        ct += ub == T ? 1 : 0;
+      }
+    int32_t ba, bt;
+    const int32_t n_above = block_scan_count(ca, &ba, sbuf);
+    block_scan_count(ct, &bt, sbuf);
+    const int32_t need = kProbeTriples - n_above;   // >= 1: fewer than kProbeTriples lie above T
+    if (bt < need && bt + ct >= need) {
+      int32_t cum = bt;
+      for (uint32_t t = ra; t < rb; ++t) {
+        if (tn2[t] == 0 || tlb[t] + tn2[t] != T) continue;
+        if (++cum == need) { s_cut = static_cast<int32_t>(t); break; }
       }
     }
     __syncthreads();
