@@ -3431,9 +3431,10 @@ IA_HD void box_corner(const BoxD& b, int c, double* x) {
   for (int j = 0; j < 5; ++j) x[j] = ((c >> j) & 1) ? b.hi[j] : b.lo[j];
 }
 
-// Extent of the boxes within `drop` votes of the maximum, over the aligned
-// 256-box chunks of k_est_partial's launch shape, one record per workgroup
-// (minima at q = 5..9, maxima at q = 10..14).  When the event's reference point moves (move_now and
+// Extent of the boxes within `drop` votes of the maximum, over the level's
+// live vote tiles (live_list, ev->n_live; every box with votes written lies
+// in one): gridDim.x workgroups per event take every gridDim.x-th live tile,
+// and each writes one record (minima at q = 5..9, maxima at q = 10..14).  When the event's reference point moves (move_now and
 // `moving`): the hull of their 32 corners taken to the new reference point,
 // phi0 unwrapped into half a turn of the first max-vote box's first corner;
 // otherwise the union of the boxes, phi0 shifted by a turn where the box
@@ -3445,15 +3446,17 @@ __global__ void __launch_bounds__(kWG) k_window_partial(const BoxD* __restrict__
                                                         const uint16_t* __restrict__ first_votes,
                                                         double* __restrict__ part, EvView vw,
                                                         const EventState* __restrict__ ev,
-                                                        const int32_t* __restrict__ wg_max, int32_t bx,
-                                                        uint32_t n_part, uint32_t per, int32_t drop,
-                                                        int32_t move_now) {
+                                                        const int32_t* __restrict__ wg_max,
+                                                        const int32_t* __restrict__ live_list, int32_t bx,
+                                                        int32_t drop, int32_t move_now) {
   const int e = blockIdx.y;
   if (ev[e].done) return;
   const bool mv = move_now && ev[e].moving;
   parents += e * vw.par_stride;
   votes += int64_t(e) * sh.n_boxes;
-  if (wg_max) wg_max += int64_t(e) * vw.wg_stride;
+  wg_max += int64_t(e) * vw.wg_stride;
+  live_list += int64_t(e) * vw.wg_stride;
+  const int32_t n_live = ev[e].n_live;
   first_box += int64_t(e) * vw.k;
   first_votes += int64_t(e) * vw.k;
   part += int64_t(e) * vw.part_stride;
@@ -3478,23 +3481,22 @@ __global__ void __launch_bounds__(kWG) k_window_partial(const BoxD* __restrict__
   double vl[5], vh[5];
   for (int j = 0; j < 5; ++j) { vl[j] = INFINITY; vh[j] = -INFINITY; }
   // moving window: the transverse corners of each (d0, phi0, kappa) triple
-  // of a chunk, shifted once into the new frame (d1, phi1, arc) and shared
+  // of a tile, shifted once into the new frame (d1, phi1, arc) and shared
   // by the triple's boxes (the boxes of a triple differ only in z0, tanl)
   __shared__ double scorner[kWG][3];
   const uint32_t m34 = sh.m[3] * sh.m[4];
-  const bool table = mv && (static_cast<uint32_t>(kWG) / m34 + 2) * 8 <= static_cast<uint32_t>(kWG);
-  const uint32_t ch_end = min(n_part, (blockIdx.x + 1) * per);
-  __shared__ uint32_t smask;
-  const uint32_t reach = chunks_reaching(wg_max, bx, blockIdx.x * per, ch_end, sh.n_boxes, vlo, &smask);
-  for (uint32_t ch = blockIdx.x * per; ch < ch_end; ++ch) {
-    if (!((reach >> (ch - blockIdx.x * per)) & 1u)) continue;
-    const uint32_t i = ch * kWG + threadIdx.x;
-    const bool in_set = i < sh.n_boxes && (!wg_max || wg_max[i / static_cast<uint32_t>(bx)] >= vlo) &&
-                        votes[i] >= vlo && in_run(phi_bin(sh, i), ra, rb);
-    const uint32_t t_first = (ch * kWG) / m34;
+  const uint32_t ubx = static_cast<uint32_t>(bx);
+  const bool table = mv && (ubx / m34 + 2) * 8 <= static_cast<uint32_t>(kWG);
+  for (int32_t li = blockIdx.x; li < n_live; li += gridDim.x) {
+    const uint32_t tile = static_cast<uint32_t>(live_list[li]);
+    if (wg_max[tile] < vlo) continue;   // uniform over the workgroup
+    const uint32_t b0 = tile * ubx;
+    const uint32_t i = b0 + threadIdx.x;
+    const bool in_set = threadIdx.x < ubx && i < sh.n_boxes && votes[i] >= vlo && in_run(phi_bin(sh, i), ra, rb);
+    const uint32_t t_first = b0 / m34;
     if (table) {
       if (!__syncthreads_or(in_set ? 1 : 0)) continue;
-      const uint32_t t_last = (min(ch * kWG + kWG, sh.n_boxes) - 1) / m34;
+      const uint32_t t_last = (min(b0 + ubx, sh.n_boxes) - 1) / m34;
       const uint32_t n_c = (t_last - t_first + 1) * 8;
       for (uint32_t cidx = threadIdx.x; cidx < n_c; cidx += kWG) {
         uint32_t kt[5];

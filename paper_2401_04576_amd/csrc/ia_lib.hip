@@ -38,6 +38,7 @@ constexpr int32_t kSelMaxGroups = 1024;
 constexpr int kOffSlots = 8;             // pinned offset-staging slots
 constexpr int32_t kOffSlotInts = 65536;  // events + 1 per slot
 constexpr uint32_t kVoteGroups = 2048;   // vote workgroups per launch over live tiles
+constexpr int32_t kWinGroups = 32;       // k_window_partial workgroups per event
 constexpr int64_t kRecCap = 32768;       // staged records per event when the arena cannot hold all pairs
 // k_estimate: 256 lanes x segments of at most 2^(kEstLevels - 1) boxes
 constexpr int64_t kMaxEstimateBoxes = int64_t(ia::kWG) << (ia::kEstLevels - 1);
@@ -692,13 +693,15 @@ ia_status run_window(ia_ctx* c, const double* hits, ia::EvView vw, int32_t E, in
                            (vw.fwd ? 1 : 0) | (exact ? 2 : 0));
       const bool mv = lev == sc->move_level;
       if (mv) hipLaunchKernelGGL(ia::k_closest, dim3(1, E), dim3(ia::kWG), 0, s, recs, vw, ev);
-      hipLaunchKernelGGL(ia::k_window_partial, gpart, dim3(ia::kWG), 0, s, par, sh, votes, sel, sel_v, part, vw, ev,
-                         wg_max, bx, static_cast<uint32_t>(n_part), eper, sc->wdrop, mv ? 1 : 0);
+      // the window's extent over the live tiles: kWinGroups workgroups per
+      // event (at most the part records the arena holds), one record each
+      const int32_t n_win = std::min(kWinGroups, L.n_part);
+      hipLaunchKernelGGL(ia::k_window_partial, dim3(n_win, E), dim3(ia::kWG), 0, s, par, sh, votes, sel, sel_v, part,
+                         vw, ev, wg_max, live, bx, sc->wdrop, mv ? 1 : 0);
       ia::Bins5 nb;
       for (int j = 0; j < 5; ++j) nb.m[j] = sc->lbins[lev + 1][j];
-      // k_window_partial wrote one extent record per workgroup
-      hipLaunchKernelGGL(ia::k_window, dim3(1, E), dim3(ia::kWG), 0, s, part, static_cast<int32_t>(gpart.x), par, sh,
-                         win, ev, vw, rb, nb, mv ? 1 : 0);
+      hipLaunchKernelGGL(ia::k_window, dim3(1, E), dim3(ia::kWG), 0, s, part, n_win, par, sh, win, ev, vw, rb, nb,
+                         mv ? 1 : 0);
       if (mv) hipLaunchKernelGGL(ia::k_reframe, dim3(pg, E), dim3(ia::kWG), 0, s, hits, vw, recs, ev, 0);
       IA_HIP(c, hipGetLastError());
       if (!make_shape(sc->lbins[lev + 1], 1, &sh)) return fail(c, IA_ERR_OVERFLOW, "level %d too large", lev + 1);
