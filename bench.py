@@ -85,18 +85,18 @@ FLOP_CLS_G, FLOP_CLS_AXIAL, FLOP_CLS_PAIRQ, FLOP_CLS_ENCL, FLOP_CLS_INCL, FLOP_C
 FLOP_CLS_FRAME, FLOP_CLS_GOUT, FLOP_CLS_PAIRMAG = 130, 68, 34
 PEAK_FP64_TFLOPS = 78.6   # MI355X vector FP64: 256 CU x 128 FLOP/clk x 2.4 GHz
 # Counter record of the default workload's dominant kernel (k_vote_rec over a
-# batch of 4,096 config-4 events, all 40 levels of the five passes), from
-# rocprofv3 --pmc runs of `bench.py --steps 1 --warmup 1 --no-autotune
-# --no-cpu-baseline` (profiles/vote_rec_batch4096_window_fp64.md), averaged
-# over the launches of the full search runs: HBM bytes (FETCH_SIZE x 2.0 and
-# WRITE_SIZE x 1.0, the factors that make the counters read 1 GiB for a
-# 1 GiB copy) and wave-level FP64 VALU instruction counts.  Valid only for
-# the kernel sources they were measured on (SHA-256 of ia_math.hpp +
-# ia_kernels.hpp).
+# batch of 4,096 config-4 events, all 80 launches of the five full search
+# runs: a probe and a vote per level), from rocprofv3 --pmc runs of
+# `bench.py --steps 1 --warmup 1 --no-autotune --no-cpu-baseline`
+# (profiles/vote_rec_batch4096_window_fp64.md), averaged per launch: HBM
+# bytes (FETCH_SIZE x 2.0 and WRITE_SIZE x 1.0, the factors that make the
+# counters read 1 GiB for a 1 GiB copy) and wave-level FP64 VALU instruction
+# counts.  Valid only for the kernel sources they were measured on (SHA-256
+# of ia_math.hpp + ia_kernels.hpp).
 TRAFFIC = {"kernel": "k_vote (fp64 levels)", "workload": "batch", "events_per_step": 4096,
-           "sources_sha256": "83cf245a8eb9e9b5fc795278c3b1a412169a21d974cb0f454e21e0f885d6c3a7",
-           "fetch_bytes": 6222643200, "write_bytes": 1158963200,
-           "valu_f64": {"add": 6.4907e9, "mul": 7.4484e9, "fma": 8.9735e9, "trans": 8.3431e8}, "valu": 3.5279e10}
+           "sources_sha256": "e3644d9738b1fba6fa208f5d7feaf6c2e73ca6e04c9a816e518c964f6459152d",
+           "fetch_bytes": 1575792640, "write_bytes": 312985600,
+           "valu_f64": {"add": 1.5146e9, "mul": 1.6998e9, "fma": 1.9141e9, "trans": 1.3995e8}, "valu": 7.0387e9}
 PEAK_FP32_TFLOPS = 157.3  # MI355X vector FP32 (non-packed)
 
 
@@ -401,7 +401,7 @@ def main():
                     help="single-helix workload: single-event calls timed for p50/p99 latency")
     ap.add_argument("--scratch-gb", type=float, default=48.0)
     ap.add_argument("--serve-events", type=int, default=2048)
-    ap.add_argument("--serve-rows", type=int, default=8192, help="serving: rows per pool at most")
+    ap.add_argument("--serve-rows", type=int, default=256, help="serving: rows per pool at most")
     ap.add_argument("--rate", type=float, default=0.0,
                     help="serving: Poisson arrival rate, events/s (0: 0.8 x the measured saturated rate)")
     ap.add_argument("--report-events", type=int, default=1000, help="mixed-report: noiseless single-helix events")
