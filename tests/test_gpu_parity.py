@@ -109,6 +109,35 @@ def test_ragged_shapes_bit_exact(ctx, split, n_par, tile, prefilter):
     assert np.array_equal(got, ref)
 
 
+def test_far_boxes_take_the_plain_path_bit_exact(ctx):
+    """Box centres far outside the physical (z0, tanl) range, where the
+    correction eps of Eq. ApproxPhi exceeds pi/4 for many (box, hit) pairs:
+    there the kernels' per-box evaluation leaves its branch-free form (whose
+    sin/cos skip the range reduction) for the plain one.  Votes must still
+    match the oracle bit for bit.  The host first checks, with the oracle's
+    own intermediate values, that such pairs occur."""
+    ev = toymc.config_event(2, 4)
+    lo = np.array(H.LO, dtype=float)
+    hi = np.array(H.HI, dtype=float)
+    lo[3], hi[3], lo[4], hi[4] = -100.0, 100.0, -8.0, 8.0
+    root = oracle.make_box(lo, hi)
+    split = [5, 5, 5, 8, 8]
+    pr = oracle.prep_hits(ev.hits)
+    stereo = np.flatnonzero((pr["axial"] == 0) & (pr["valid"] == 1))
+    rng = np.random.default_rng(7)
+    i_eps = oracle.STEREO_DEBUG_NAMES.index("eps")
+    n_big = 0
+    for _ in range(200):
+        c = lo + (hi - lo) * rng.random(5)
+        for h in rng.choice(stereo, size=3, replace=False):
+            ok, _, dbg = oracle.stereo_e(pr[h], c, 1, debug=True)
+            n_big += np.isfinite(dbg[i_eps]) and abs(dbg[i_eps]) >= np.pi / 4
+    assert n_big > 40, n_big
+    ref = oracle.vote_level(ev.hits, root, split)
+    got = _gpu_votes(ctx, ev.hits, root, split)
+    assert np.array_equal(got, ref)
+
+
 def test_edge_cases_hits(ctx):
     torch = _torch()
     root = oracle.make_box(H.LO, H.HI)
