@@ -2840,7 +2840,9 @@ __global__ void __launch_bounds__(kWG) k_est_partial(const BoxD* __restrict__ pa
                                                      double* __restrict__ part, EvView vw,
                                                      const EventState* __restrict__ ev,
                                                      const int32_t* __restrict__ wg_max, int32_t bx,
-                                                     uint32_t n_part, uint32_t per, int32_t use_run) {
+                                                     uint32_t n_part, uint32_t per, int32_t use_run,
+                                                     const int32_t* __restrict__ live_list,
+                                                     uint32_t* __restrict__ emask, int32_t emask_stride) {
   const int e = blockIdx.y;
   if (ev && ev[e].done) return;
   parents += e * vw.par_stride;
@@ -2853,27 +2855,24 @@ __global__ void __launch_bounds__(kWG) k_est_partial(const BoxD* __restrict__ pa
   const int32_t vmax = first_votes[0];
   const double c0 = 0.5 * (first_box->lo[1] + first_box->hi[1]);
   const int32_t ra = use_run ? ev[e].run_a : -1, rb = use_run ? ev[e].run_b : -1;
-  const uint32_t ch_end = min(n_part, (blockIdx.x + 1) * per);
-  __shared__ uint32_t smask;
-  const uint32_t reach = chunks_reaching(wg_max, bx, blockIdx.x * per, ch_end, sh.n_boxes, vmax, &smask);
-  for (uint32_t ch = blockIdx.x * per; ch < ch_end; ++ch) {
+  // one chunk: its record on the pairwise tree of its 256 lanes; a chunk
+  // without a max-vote box reduces to the identity (sums 0, minima +inf,
+  // maxima -inf, count 0), bit for bit, written without the tree (dense) or
+  // left to k_est_final as a clear bit of emask (sparse)
+  auto chunk = [&](uint32_t ch, bool may) {
     const uint32_t i = ch * kWG + threadIdx.x;
     double v[kEstQ];
     for (int q = 0; q < 5; ++q) { v[q] = 0.0; v[5 + q] = INFINITY; v[10 + q] = -INFINITY; }
     v[15] = 0.0;
     // with wg_max, only tiles whose maximum reaches vmax hold written votes
-    const bool may = (reach >> (ch - blockIdx.x * per)) & 1u;
     const bool at_max = may && i < sh.n_boxes && (!wg_max || wg_max[i / static_cast<uint32_t>(bx)] >= vmax) &&
                         votes[i] == vmax && in_run(phi_bin(sh, i), ra, rb);
-    // a chunk without a max-vote box reduces to the identity (sums 0,
-    // minima +inf, maxima -inf, count 0), bit for bit: write it without the
-    // tree
     if (!may || !__syncthreads_or(at_max ? 1 : 0)) {
-      if (threadIdx.x < kEstQ) {
+      if (!emask && threadIdx.x < kEstQ) {
         const int q = static_cast<int>(threadIdx.x);
         part[ch * kEstQ + q] = (q >= 5 && q < 10) ? INFINITY : ((q >= 10 && q < 15) ? -INFINITY : 0.0);
       }
-      continue;
+      return;
     }
     if (at_max) {
       BoxD box;
@@ -2901,8 +2900,30 @@ __global__ void __launch_bounds__(kWG) k_est_partial(const BoxD* __restrict__ pa
     __syncthreads();
     for (int w = kWG; w > 1; w >>= 1) tree_step(s, w);
     if (threadIdx.x < kEstQ) part[ch * kEstQ + threadIdx.x] = s[threadIdx.x][0];
+    if (emask && threadIdx.x == 0) atomicOr(&emask[ch >> 5], 1u << (ch & 31u));
     __syncthreads();                           // s is refilled for the next chunk
+  };
+  if (emask) {
+    // sparse: only chunks holding a live tile (every box with written votes
+    // lies in one), each taken by the workgroup of its first live tile
+    emask += int64_t(e) * emask_stride;
+    live_list += int64_t(e) * vw.wg_stride;
+    const int32_t n_live = ev[e].n_live;
+    const uint32_t ub = static_cast<uint32_t>(bx), per_ch = static_cast<uint32_t>(kWG) / ub;
+    for (int32_t li = blockIdx.x; li < n_live; li += gridDim.x) {
+      const uint32_t ch = static_cast<uint32_t>(live_list[li]) / per_ch;
+      if (li > 0 && static_cast<uint32_t>(live_list[li - 1]) / per_ch == ch) continue;
+      int32_t mx = -1;
+      for (uint32_t t = ch * per_ch; t < min((ch + 1) * per_ch, (sh.n_boxes + ub - 1) / ub); ++t)
+        mx = max(mx, wg_max[t]);
+      chunk(ch, mx >= vmax);
+    }
+    return;
   }
+  const uint32_t ch_end = min(n_part, (blockIdx.x + 1) * per);
+  __shared__ uint32_t smask;
+  const uint32_t reach = chunks_reaching(wg_max, bx, blockIdx.x * per, ch_end, sh.n_boxes, vmax, &smask);
+  for (uint32_t ch = blockIdx.x * per; ch < ch_end; ++ch) chunk(ch, (reach >> (ch - blockIdx.x * per)) & 1u);
 }
 
 // hit finding (Sec. 3.3): does an active hit vote for the box estimate +- scale x error
@@ -2954,10 +2975,15 @@ __global__ void __launch_bounds__(kWG) k_est_final(const double* __restrict__ pa
                                                    EstimateOut* __restrict__ out, EventState* __restrict__ ev,
                                                    HitRec* __restrict__ hits, EvView vw, double scale,
                                                    int32_t* __restrict__ assigned, HelixOut* __restrict__ hout,
-                                                   int32_t* __restrict__ n_out, int32_t fwd) {
+                                                   int32_t* __restrict__ n_out, int32_t fwd,
+                                                   uint32_t* __restrict__ emask, int32_t emask_stride) {
   const int e = blockIdx.y;
   if (ev && ev[e].done) return;
   part += int64_t(e) * vw.part_stride;
+  if (emask) emask += int64_t(e) * emask_stride;
+  // with emask, a chunk whose bit is clear holds the identity (k_est_partial
+  // wrote no record for it): the same values enter the tree, unread
+  auto has = [&](int32_t i) { return !emask || ((emask[i >> 5] >> (i & 31)) & 1u); };
   first_box += int64_t(e) * vw.k;
   first_votes += int64_t(e) * vw.k;
   if (ev) ev += e;
@@ -2980,7 +3006,7 @@ __global__ void __launch_bounds__(kWG) k_est_final(const double* __restrict__ pa
       const int32_t beg = t * seg;
       if (q < 5 || q == 15) {
         for (int32_t i = 0; i < seg; ++i) {
-          double v = part[(beg + i) * kEstQ + q];
+          double v = has(beg + i) ? part[(beg + i) * kEstQ + q] : 0.0;
           int32_t c = i, lvl = 0;
           while (c & 1) { v = stack[t][lvl] + v; c >>= 1; ++lvl; }
           stack[t][lvl] = v;
@@ -2991,6 +3017,7 @@ __global__ void __launch_bounds__(kWG) k_est_final(const double* __restrict__ pa
       } else {
         acc = q < 10 ? INFINITY : -INFINITY;
         for (int32_t i = 0; i < seg; ++i) {
+          if (!has(beg + i)) continue;         // fmin(acc, +inf) = acc, fmax(acc, -inf) = acc
           const double v = part[(beg + i) * kEstQ + q];
           acc = q < 10 ? fmin(acc, v) : fmax(acc, v);
         }
@@ -3001,6 +3028,8 @@ __global__ void __launch_bounds__(kWG) k_est_final(const double* __restrict__ pa
     s[q][t] = acc;
   }
   __syncthreads();
+  if (emask)                                   // cleared for the next level
+    for (int32_t w = t; w < (n_part + 31) / 32; w += kWG) emask[w] = 0u;
   for (int w = kWG; w > 1; w >>= 1) tree_step(s, w);
   if (t == 0) {
     const double c0 = 0.5 * (first_box->lo[1] + first_box->hi[1]);

@@ -469,9 +469,9 @@ ia_status launch_vote_rec(ia_ctx* c, const ia::EvView& vw, int32_t n_ev, const B
 // arena): per-event slices of every array, sized for events of max_hits hits
 struct FindLayout {
   size_t win, off, recs, votes, hist, lbh, selA, selB, range, sel_idx, sel_v, ev, part, flags, tlb, tn2, wg_max, live,
-      live_tri, rec_off, rec_fill, tfr, rec, pflags, pe, live_off, stage_off, total;
+      live_tri, rec_off, rec_fill, tfr, rec, pflags, pe, live_off, stage_off, emask, total;
   int64_t flag_stride, tri_stride, votes_stride, rec_stride, pflag_stride;
-  int32_t hist_stride, wg_stride, part_stride, n_part;
+  int32_t hist_stride, wg_stride, part_stride, n_part, emask_stride;
 };
 
 // rec_per_event: staged records per event (0: every (triple, hit) pair)
@@ -486,6 +486,7 @@ void layout_find(int64_t max_level_boxes, int64_t max_triples, int32_t top_k, in
   L->rec_stride = rec_per_event > 0 ? rec_per_event : std::max<int64_t>(1, max_triples * int64_t(std::max(0, max_hits)));
   L->wg_stride = static_cast<int32_t>((max_level_boxes + 63) / 64);
   L->part_stride = ia::kEstQ * L->n_part;
+  L->emask_stride = (L->n_part + 31) / 32;
   const size_t E = size_t(std::max(1, n_ev));
   size_t off = align_up(sizeof(Persistent));
   auto take = [&](size_t bytes) {
@@ -506,6 +507,7 @@ void layout_find(int64_t max_level_boxes, int64_t max_triples, int32_t top_k, in
   L->sel_v = take(sizeof(uint16_t) * size_t(top_k) * E);
   L->ev = take(sizeof(EventState) * E);
   L->part = take(sizeof(double) * size_t(L->part_stride) * E);
+  L->emask = take(sizeof(uint32_t) * size_t(L->emask_stride) * E);
   L->flags = take(size_t(L->flag_stride) * E);
   L->tlb = take(sizeof(int32_t) * size_t(L->tri_stride) * E);
   L->tn2 = take(sizeof(int32_t) * size_t(L->tri_stride) * E);
@@ -600,6 +602,14 @@ ia_status run_window(ia_ctx* c, const double* hits, ia::EvView vw, int32_t E, in
                      int32_t* assigned, ia::HelixOut* out, int32_t* n_out, int32_t pass0, int32_t pass1,
                      hipStream_t s) {
   BoxD* win = reinterpret_cast<BoxD*>(c->arena + L.win);
+  // chunk masks of the sparse estimate: zero on entry, and k_est_final
+  // clears what it read
+  uint32_t* emask = reinterpret_cast<uint32_t*>(c->arena + L.emask);
+  {
+    const uint32_t n_words = static_cast<uint32_t>(L.emask_stride) * static_cast<uint32_t>(E);
+    hipLaunchKernelGGL(ia::k_fill_u32, dim3(std::min<uint32_t>((n_words + 255) / 256, 65535)), dim3(256), 0, s, emask,
+                       n_words, 0u);
+  }
   BoxD rb;
   std::memcpy(&rb, &sc->range, sizeof rb);
   const int32_t pg = std::max(1, (cmax + 255) / 256);
@@ -672,22 +682,25 @@ ia_status run_window(ia_ctx* c, const double* hits, ia::EvView vw, int32_t E, in
       hipLaunchKernelGGL(ia::k_phi_occ, gpart, dim3(ia::kWG), 0, s, votes, sh, sel_v, ev, vw, wg_max, bx,
                          static_cast<uint32_t>(n_part), eper);
       hipLaunchKernelGGL(ia::k_phi_run, dim3(1, E), dim3(64), 0, s, par, sh, sel_idx, ev, vw);
-      hipLaunchKernelGGL(ia::k_est_partial, gpart, dim3(ia::kWG), 0, s, par, sh, votes, sel, sel_v, part, vw, ev,
-                         wg_max, bx, static_cast<uint32_t>(n_part), eper, 1);
+      // the max-vote boxes' sums, over the chunks of the live tiles only
+      // (sparse: the other chunks are the identity, marked by clear bits)
+      hipLaunchKernelGGL(ia::k_est_partial, dim3(std::min(kWinGroups, n_part), E), dim3(ia::kWG), 0, s, par, sh,
+                         votes, sel, sel_v, part, vw, ev, wg_max, bx, static_cast<uint32_t>(n_part), eper, 1, live,
+                         emask, L.emask_stride);
       if (lev == sc->n_refine) {
         // bit 0: the forward test, applied while the event's frame is the
         // origin's; bit 1: the exact Phi of the last level
         const int32_t fwd_hf = (sc->forward ? 1 : 0) | (exact ? 2 : 0);
         hipLaunchKernelGGL(ia::k_est_final, dim3(1, E), dim3(ia::kWG), 0, s, part, n_part, sel, sel_v,
                            static_cast<ia::EstimateOut*>(nullptr), ev, recs, vw, sc->hitfind_scale, assigned, out,
-                           n_out, fwd_hf);
+                           n_out, fwd_hf, emask, L.emask_stride);
         IA_HIP(c, hipGetLastError());
         break;
       }
       hipLaunchKernelGGL(ia::k_est_final, dim3(1, E), dim3(ia::kWG), 0, s, part, n_part, sel, sel_v,
                          static_cast<ia::EstimateOut*>(nullptr), ev, static_cast<HitRec*>(nullptr), vw, 0.0,
                          static_cast<int32_t*>(nullptr), static_cast<ia::HelixOut*>(nullptr),
-                         static_cast<int32_t*>(nullptr), 0);
+                         static_cast<int32_t*>(nullptr), 0, emask, L.emask_stride);
       if (sc->hitsel)
         hipLaunchKernelGGL(ia::k_hit_select, dim3(pg, E), dim3(ia::kWG), 0, s, recs, vw, ev, sc->hitfind_scale,
                            (vw.fwd ? 1 : 0) | (exact ? 2 : 0));
@@ -857,10 +870,12 @@ ia_status run_chunk(ia_ctx* c, const double* hits_chunk, const int32_t* h_off_ch
     const int32_t n_part = est_parts(sh.n_boxes);
     const uint32_t eper = est_per(n_part, E);
     hipLaunchKernelGGL(ia::k_est_partial, dim3((n_part + eper - 1) / eper, E), dim3(ia::kWG), 0, s, par, sh, votes,
-                       sel, sel_v, part, vw, ev, wg_max, last_bx, static_cast<uint32_t>(n_part), eper, 0);
+                       sel, sel_v, part, vw, ev, wg_max, last_bx, static_cast<uint32_t>(n_part), eper, 0,
+                       static_cast<const int32_t*>(nullptr), static_cast<uint32_t*>(nullptr), 0);
     hipLaunchKernelGGL(ia::k_est_final, dim3(1, E), dim3(ia::kWG), 0, s, part, n_part, sel, sel_v,
                        static_cast<ia::EstimateOut*>(nullptr), ev, recs, vw, sc->hitfind_scale, assigned, out, n_out,
-                       (sc->forward ? 1 : 0) | (sc->prec[sc->n_refine] == IA_FP64X ? 2 : 0));
+                       (sc->forward ? 1 : 0) | (sc->prec[sc->n_refine] == IA_FP64X ? 2 : 0),
+                       static_cast<uint32_t*>(nullptr), 0);
     IA_HIP(c, hipGetLastError());
   }
   return IA_OK;
@@ -1297,10 +1312,11 @@ ia_status ia_estimate(ia_ctx* c, const ia_box* d_parents, int32_t n_parents, con
   vw.part_stride = n_part * ia::kEstQ;
   const uint32_t eper = est_per(n_part, 1);
   hipLaunchKernelGGL(ia::k_est_partial, dim3((n_part + eper - 1) / eper, 1), dim3(ia::kWG), 0, s, par, sh, d_votes,
-                     first, first_v, part, vw, nullptr, nullptr, 1, static_cast<uint32_t>(n_part), eper, 0);
+                     first, first_v, part, vw, nullptr, nullptr, 1, static_cast<uint32_t>(n_part), eper, 0,
+                     static_cast<const int32_t*>(nullptr), static_cast<uint32_t*>(nullptr), 0);
   hipLaunchKernelGGL(ia::k_est_final, dim3(1, 1), dim3(ia::kWG), 0, s, part, n_part, first, first_v,
                      reinterpret_cast<ia::EstimateOut*>(d_out), nullptr, nullptr, vw, 0.0, nullptr, nullptr, nullptr,
-                     0);
+                     0, static_cast<uint32_t*>(nullptr), 0);
   IA_HIP(c, hipGetLastError());
   return IA_OK;
 }
