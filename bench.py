@@ -94,8 +94,8 @@ PEAK_FP64_TFLOPS = 78.6   # MI355X vector FP64: 256 CU x 128 FLOP/clk x 2.4 GHz
 # counts.  Valid only for the kernel sources they were measured on (SHA-256
 # of ia_math.hpp + ia_kernels.hpp).
 TRAFFIC = {"kernel": "k_vote (fp64 levels)", "workload": "batch", "events_per_step": 4096,
-           "sources_sha256": "e3644d9738b1fba6fa208f5d7feaf6c2e73ca6e04c9a816e518c964f6459152d",
-           "fetch_bytes": 1575792640, "write_bytes": 312985600,
+           "sources_sha256": "37f5391d9071fd2a640f7dbd67df82fe1fef7f9dfb233a3c7b32922129a1a58e",
+           "fetch_bytes": 1575669760, "write_bytes": 312975360,
            "valu_f64": {"add": 1.5146e9, "mul": 1.6998e9, "fma": 1.9141e9, "trans": 1.3995e8}, "valu": 7.0387e9}
 PEAK_FP32_TFLOPS = 157.3  # MI355X vector FP32 (non-packed)
 
