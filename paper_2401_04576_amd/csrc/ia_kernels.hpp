@@ -389,11 +389,36 @@ IA_HD bool h_contains0(Iv G, Iv K, double e, double band) {
   return (Hv.lo <= 0.0) & (0.0 <= Hv.hi);
 }
 
+// h_contains0 with the same result in fewer operations, for the branch-free
+// per-box evaluation.  With S = E^2 and S.lo >= 0 (otherwise *ok is
+// cleared), the smallest of the four products K x S is K.lo S.lo for
+// K.lo >= 0 and K.lo S.hi otherwise, and the largest K.hi S.hi for
+// K.hi >= 0 and K.hi S.lo otherwise (rounding to nearest is monotone), so
+// two products give imul's end points.  The last outward roundings are
+// folded into the comparisons: wdn(x) <= 0 exactly when x <= 2^-1074, and
+// wup(x) >= 0 exactly when x >= -2^-1074.  *sq_ok tells whether S.lo >= 0
+// held (the result stands only then).
+IA_HD bool h_contains0_fast(Iv G, Iv K, double e, double band, bool* sq_ok) {
+  const Iv E = {wdn(e - band), wup(e + band)};
+  const Iv S = isqr(E);
+  *sq_ok = S.lo >= 0.0;
+  const Iv KS = {wdn(K.lo * (K.lo >= 0.0 ? S.lo : S.hi)), wup(K.hi * (K.hi >= 0.0 ? S.hi : S.lo))};
+  const Iv T = iadd(itwice(E), KS);
+  const double lo = 2.0 * G.lo - T.hi, hi = 2.0 * G.hi - T.lo;
+  return (lo <= 0x1p-1074) & (hi >= -0x1p-1074);
+}
+
 // per (triple, stereo hit) quantities that do not depend on (z0, tanl)
 struct PairQ {
   double Glo, Ghi, sArc, dphi, RAx, sinA, cosA, sAx, cAx, c2, s2, twoRAx2, RpRAx;
-  double rRAx, r2RAx2;   // recip_v of RAx and of twoRAx2 (the per-box quotients' divisors)
+  // recip_v of RAx and of twoRAx2 (the per-box quotients' divisors); r2RAx2
+  // is NaN too when the drift is outside [2^-200, 2^200] (drift_ok), so that
+  // the branch-free per-box form, which divides by the drift's range, is
+  // left for the plain one
+  double rRAx, r2RAx2;
 };
+
+IA_HD bool drift_ok(double d) { return d >= 0x1p-200 && d <= 0x1p200; }
 
 IA_HD PairQ pair_quantities(const Frame& f, const HitRec& h, Iv G) {
   PairQ q;
@@ -413,7 +438,7 @@ IA_HD PairQ pair_quantities(const Frame& f, const HitRec& h, Iv G) {
   q.twoRAx2 = 2.0 * (q.RAx * q.RAx);
   q.RpRAx = f.R + q.RAx;
   q.rRAx = recip_v(q.RAx);
-  q.r2RAx2 = recip_v(q.twoRAx2);
+  q.r2RAx2 = drift_ok(h.d) ? recip_v(q.twoRAx2) : __builtin_nan("");
   return q;
 }
 
@@ -483,10 +508,17 @@ IA_HD bool stereo_vote_t(const PairQ& q, double R, double sig, Iv K, double z0, 
     }
     double sinP = q.sinA * ce + q.cosA * se, cosP = q.cosA * ce - q.sinA * se;
     const double u2 = ((1.0 + ((2.0 * lam) * sinP) * tt) + lam2 * t2) + (cosP * cosP) * t2;
-    double u;
-    if constexpr (FAST) u = sqrt_fast(u2, ok);
-    else u = sqrt(u2);
-    double delta = dS / u;
+    double u, delta;
+    if constexpr (FAST) {
+      // u in [2^-300, 2^300] and |dS| in [2^-200, 2^200] (the record's
+      // r2RAx2 is NaN otherwise, which failed the Phi2 check): the quotient's
+      // range holds, so div_exact gives dS / u
+      u = sqrt_fast(u2, ok, 0x1p-600, 0x1p600);
+      delta = div_exact(dS, u, rcp_newton(u));
+    } else {
+      u = sqrt(u2);
+      delta = dS / u;
+    }
     double sperp = R * (q.dphi + eps);
     double zS = (z0 + lam * sperp) - (delta * cosP) * tt;
     double ld = lam * delta;
@@ -501,8 +533,11 @@ IA_HD bool stereo_vote_t(const PairQ& q, double R, double sig, Iv K, double z0, 
       const double dhat = delta - Q / (A + sqrt_fast(disc, &ok_d));
       *ok = *ok & (ok_d | !(disc >= 0.0));
       const double e = sig * dhat;
-      const bool fin = __builtin_isfinite(e), hit = h_contains0(G, K, e, band);
-      vote = vote | ((disc >= 0.0) & fin & hit);
+      bool sq_ok;
+      const bool fin = __builtin_isfinite(e), hit = h_contains0_fast(G, K, e, band, &sq_ok);
+      const bool used = (disc >= 0.0) & fin;   // the H test decides only then
+      *ok = *ok & (sq_ok | !used);
+      vote = vote | (used & hit);
     } else if (disc >= 0.0) {
       double dhat = delta - Q / (A + sqrt(disc));
       double e = sig * dhat;
@@ -2500,7 +2535,7 @@ __global__ void __launch_bounds__(kWG, 4) k_vote_rec(EvView vw, const BoxD* __re
             const RecD& q = recd[ri];
             for (int c = 0; c < 12; ++c) sq[c][slot] = q.q[c];
             sq[12][slot] = recip_v(q.q[4]);     // RAx
-            sq[13][slot] = recip_v(q.q[11]);    // twoRAx2
+            sq[13][slot] = drift_ok(q.d) ? recip_v(q.q[11]) : __builtin_nan("");   // twoRAx2, as pair_quantities
             sq[14][slot] = q.tt; sq[15][slot] = q.d; sq[16][slot] = q.band;
           }
         }

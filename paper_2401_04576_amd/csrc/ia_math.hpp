@@ -65,9 +65,10 @@ IA_HD double horner(double p, double z, double c) {
 // range scaling and its selects for 0 and infinity are identities there.
 // This is that sequence without them, so the bits are the same; outside the
 // range it clears *ok (the caller then takes sqrt).
-IA_HD double sqrt_fast(double x, bool* ok) {
+// lo, hi: a narrower range the caller needs (within the one above).
+IA_HD double sqrt_fast(double x, bool* ok, double lo = 0x1p-767, double hi = 0x1.fffffffffffffp+1023) {
 #if defined(__HIP_DEVICE_COMPILE__)
-  *ok = *ok & (x >= 0x1p-767) & (x <= 0x1.fffffffffffffp+1023);   // no short-circuit branches
+  *ok = *ok & (x >= lo) & (x <= hi);   // no short-circuit branches
   const double g = __builtin_amdgcn_rsq(x);
   double s = x * g, h = 0.5 * g;
   const double r = fma(-h, s, 0.5);
@@ -103,6 +104,31 @@ IA_HD double recip_v(double d) {
   return fma(r, e, r);
 #else
   return 1.0 / d;
+#endif
+}
+
+// The same reciprocal without the range check, for a divisor the caller
+// keeps in [2^-300, 2^300]; with a dividend of magnitude in [2^-200, 2^200]
+// the quotient lies in [2^-500, 2^500], and div_exact finishes it as n / d.
+IA_HD double rcp_newton(double d) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  double r = __builtin_amdgcn_rcp(d);
+  double e = fma(-d, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-d, r, 1.0);
+  return fma(r, e, r);
+#else
+  return 1.0 / d;
+#endif
+}
+
+IA_HD double div_exact(double n, double d, double r) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  const double q = n * r;
+  return fma(fma(-d, q, n), r, q);
+#else
+  (void)r;
+  return n / d;
 #endif
 }
 
