@@ -94,9 +94,9 @@ PEAK_FP64_TFLOPS = 78.6   # MI355X vector FP64: 256 CU x 128 FLOP/clk x 2.4 GHz
 # counts.  Valid only for the kernel sources they were measured on (SHA-256
 # of ia_math.hpp + ia_kernels.hpp).
 TRAFFIC = {"kernel": "k_vote (fp64 levels)", "workload": "batch", "events_per_step": 4096,
-           "sources_sha256": "37f5391d9071fd2a640f7dbd67df82fe1fef7f9dfb233a3c7b32922129a1a58e",
-           "fetch_bytes": 1575669760, "write_bytes": 312975360,
-           "valu_f64": {"add": 1.5146e9, "mul": 1.6998e9, "fma": 1.9141e9, "trans": 1.3995e8}, "valu": 7.0387e9}
+           "sources_sha256": "7050beb9d1639ab1f6cfbfc8dae9bcacc97ac8a69834c27a5df588f08e3a95bf",
+           "fetch_bytes": 1572413440, "write_bytes": 312913920,
+           "valu_f64": {"add": 1.4518e9, "mul": 1.6378e9, "fma": 1.8546e9, "trans": 1.4068e8}, "valu": 6.768e9}
 PEAK_FP32_TFLOPS = 157.3  # MI355X vector FP32 (non-packed)
 
 
