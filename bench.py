@@ -91,12 +91,12 @@ PEAK_FP64_TFLOPS = 78.6   # MI355X vector FP64: 256 CU x 128 FLOP/clk x 2.4 GHz
 # (profiles/vote_rec_batch4096_window_fp64.md), averaged per launch: HBM
 # bytes (FETCH_SIZE x 2.0 and WRITE_SIZE x 1.0, the factors that make the
 # counters read 1 GiB for a 1 GiB copy) and wave-level FP64 VALU instruction
-# counts.  Valid only for the kernel sources they were measured on (SHA-256
-# of ia_math.hpp + ia_kernels.hpp).
+# counts.  Valid only for the kernel sources and launch shapes they were
+# measured on (SHA-256 of ia_math.hpp + ia_kernels.hpp + ia_lib.hip).
 TRAFFIC = {"kernel": "k_vote (fp64 levels)", "workload": "batch", "events_per_step": 4096,
-           "sources_sha256": "7050beb9d1639ab1f6cfbfc8dae9bcacc97ac8a69834c27a5df588f08e3a95bf",
-           "fetch_bytes": 1572413440, "write_bytes": 312913920,
-           "valu_f64": {"add": 1.4518e9, "mul": 1.6378e9, "fma": 1.8546e9, "trans": 1.4068e8}, "valu": 6.768e9}
+           "sources_sha256": "7381a64019efad127c5073258bf67efa49867b9e23d942c287d44584cc99d6fc",
+           "fetch_bytes": 1576341325, "write_bytes": 356884496,
+           "valu_f64": {"add": 1.4518e9, "mul": 1.6378e9, "fma": 1.8546e9, "trans": 1.4068e8}, "valu": 6.7779e9}
 PEAK_FP32_TFLOPS = 157.3  # MI355X vector FP32 (non-packed)
 
 
@@ -127,7 +127,8 @@ def sched_prec(name, n_refine):
 def kernel_sources_sha256():
     import hashlib
     h = hashlib.sha256()
-    for f in ("ia_math.hpp", "ia_kernels.hpp"):
+    # the kernels and their launch shapes (grid sizes live in ia_lib.hip)
+    for f in ("ia_math.hpp", "ia_kernels.hpp", "ia_lib.hip"):
         with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2401_04576_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()

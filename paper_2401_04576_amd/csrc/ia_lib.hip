@@ -37,7 +37,11 @@ constexpr int64_t kSelChunkMin = 4096;
 constexpr int32_t kSelMaxGroups = 1024;
 constexpr int kOffSlots = 8;             // pinned offset-staging slots
 constexpr int32_t kOffSlotInts = 65536;  // events + 1 per slot
-constexpr uint32_t kVoteGroups = 2048;   // vote workgroups per launch over live tiles
+// vote and staging workgroups per launch over the live items: 16 per resident
+// slot (4 per CU on 256 CUs), so that the dispatcher, which starts a new
+// workgroup as soon as one ends, balances tiles of very different record
+// counts
+constexpr uint32_t kVoteGroups = 16384;
 constexpr int32_t kWinGroups = 32;       // k_window_partial workgroups per event
 constexpr int64_t kRecCap = 32768;       // staged records per event when the arena cannot hold all pairs
 // k_estimate: 256 lanes x segments of at most 2^(kEstLevels - 1) boxes
