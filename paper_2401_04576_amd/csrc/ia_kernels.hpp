@@ -1560,8 +1560,10 @@ __device__ __forceinline__ int32_t block_sum(int32_t v, int32_t* sbuf) {
 // magnitude bounds; live triples only) is added to `work` with one atomic
 // per counter per workgroup (a separate instantiation: the counting costs
 // the search a few per cent).
+// Waves per SIMD: 5 at FP64 (at most 96 VGPRs, with eight 8-byte spills in
+// the hit loop; 5 % faster than 4 waves at 113 VGPRs), 4 at FP32.
 template <bool F32, bool COUNT>
-__global__ void __launch_bounds__(kWG, 4) k_classify(const HitRec* __restrict__ hits, EvView vw,
+__global__ void __launch_bounds__(kWG, F32 ? 4 : 5) k_classify(const HitRec* __restrict__ hits, EvView vw,
                                                   const BoxD* __restrict__ parents, Shape sh,
                                                   uint8_t* __restrict__ flags, int32_t* __restrict__ tlb,
                                                   int32_t* __restrict__ tn2, int32_t filter,
@@ -1650,12 +1652,13 @@ __global__ void __launch_bounds__(kWG, 4) k_classify(const HitRec* __restrict__ 
 // (the same functions and inputs as in k_classify, hence the same values),
 // then the per-sign enclosure passes; it writes the class and adds class-1
 // and class-2 pairs to the triple's bounds.  Pair indices h * n_tr + t stay
-// below 2^32 (the launcher checks).
+// below 2^32 (the launcher checks).  Waves per SIMD: 4 at FP64 (128 VGPRs,
+// no spills), 3 at FP32 (whose enclosures would spill at 128).
 constexpr int32_t kDeferPer = 16;
 constexpr int32_t kDeferChunk = kDeferPer * kWG;
 
 template <bool F32, bool COUNT>
-__global__ void __launch_bounds__(kWG, 3) k_classify_defer(const HitRec* __restrict__ hits, EvView vw,
+__global__ void __launch_bounds__(kWG, F32 ? 3 : 4) k_classify_defer(const HitRec* __restrict__ hits, EvView vw,
                                                         const BoxD* __restrict__ parents, Shape sh,
                                                         uint8_t* __restrict__ flags, int32_t* __restrict__ tlb,
                                                         int32_t* __restrict__ tn2, int32_t per,
