@@ -385,7 +385,16 @@ void launch_stage(const HitRec* recs, const ia::EvView& vw, int32_t n_ev, const 
                   const uint8_t* flags, const RecIn& r, const EventState* ev, hipStream_t s, bool f32,
                   float slack32) {
   hipLaunchKernelGGL(ia::k_live_offsets, dim3(1), dim3(ia::kWG), 0, s, ev, vw, n_ev, r.live_off, r.stage_off);
-  const dim3 g(kVoteGroups, 1);
+  // no more workgroups than the level's items could fill: at most n_ev x
+  // triples x max_hits (live triple, hit) items, kStageBatch x kWG each, so
+  // that small batches do not start thousands of empty workgroups
+  int64_t groups = kVoteGroups;
+  if (vw.max_hits > 0) {
+    const int64_t items = int64_t(std::max(1, n_ev)) * sh.n_parents * sh.m012 * vw.max_hits;
+    const int64_t per = int64_t(ia::kStageBatch) * ia::kWG;
+    groups = std::max<int64_t>(1, std::min<int64_t>(kVoteGroups, (items + per - 1) / per));
+  }
+  const dim3 g(static_cast<uint32_t>(groups), 1);
   if (f32)
     hipLaunchKernelGGL((ia::k_stage<true>), g, dim3(ia::kWG), 0, s, recs, vw, par, sh, flags, r.live_tri, r.rec_off,
                        r.rec_fill, r.rec, r.tfr, r.stage_off, n_ev, slack32);
