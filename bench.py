@@ -94,8 +94,8 @@ PEAK_FP64_TFLOPS = 78.6   # MI355X vector FP64: 256 CU x 128 FLOP/clk x 2.4 GHz
 # counts.  Valid only for the kernel sources and launch shapes they were
 # measured on (SHA-256 of ia_math.hpp + ia_kernels.hpp + ia_lib.hip).
 TRAFFIC = {"kernel": "k_vote (fp64 levels)", "workload": "batch", "events_per_step": 4096,
-           "sources_sha256": "9c9bab1339ac24acee6a45fc47d867adc72fa3c49b84476fcc28621730b3b04a",
-           "fetch_bytes": 1579495673, "write_bytes": 358319573,
+           "sources_sha256": "f2fc53e9e838d5ede522355626d95e39504c71b2a0ffc45986de82344029d303",
+           "fetch_bytes": 1579480468, "write_bytes": 358304629,
            "valu_f64": {"add": 1.4518e9, "mul": 1.6378e9, "fma": 1.8546e9, "trans": 1.4068e8}, "valu": 6.7779e9}
 PEAK_FP32_TFLOPS = 157.3  # MI355X vector FP32 (non-packed)
 

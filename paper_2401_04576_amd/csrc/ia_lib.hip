@@ -42,7 +42,15 @@ constexpr int32_t kOffSlotInts = 65536;  // events + 1 per slot
 // workgroup as soon as one ends, balances tiles of very different record
 // counts
 constexpr uint32_t kVoteGroups = 16384;
-constexpr int32_t kWinGroups = 32;       // k_window_partial workgroups per event
+// workgroups per event of the window-extent and estimate scans over the live
+// tiles.  The window scan takes about kWinTotal workgroups over the batch,
+// between 8 and 32 per event: in a large batch most of its workgroups do
+// little more than start (8 per event run 4,096 events 23 % faster than 32),
+// while a single event needs 32 to spread its tiles.  The estimate's chunk
+// trees keep 32 per event busy.
+constexpr int32_t kWinTotal = 32768;
+constexpr int32_t kWinGroupsMin = 8, kWinGroupsMax = 32;
+constexpr int32_t kEstGroups = 32;
 constexpr int64_t kRecCap = 32768;       // staged records per event when the arena cannot hold all pairs
 // k_estimate: 256 lanes x segments of at most 2^(kEstLevels - 1) boxes
 constexpr int64_t kMaxEstimateBoxes = int64_t(ia::kWG) << (ia::kEstLevels - 1);
@@ -697,7 +705,7 @@ ia_status run_window(ia_ctx* c, const double* hits, ia::EvView vw, int32_t E, in
       hipLaunchKernelGGL(ia::k_phi_run, dim3(1, E), dim3(64), 0, s, par, sh, sel_idx, ev, vw);
       // the max-vote boxes' sums, over the chunks of the live tiles only
       // (sparse: the other chunks are the identity, marked by clear bits)
-      hipLaunchKernelGGL(ia::k_est_partial, dim3(std::min(kWinGroups, n_part), E), dim3(ia::kWG), 0, s, par, sh,
+      hipLaunchKernelGGL(ia::k_est_partial, dim3(std::min(kEstGroups, n_part), E), dim3(ia::kWG), 0, s, par, sh,
                          votes, sel, sel_v, part, vw, ev, wg_max, bx, static_cast<uint32_t>(n_part), eper, 1, live,
                          emask, L.emask_stride);
       if (lev == sc->n_refine) {
@@ -719,9 +727,10 @@ ia_status run_window(ia_ctx* c, const double* hits, ia::EvView vw, int32_t E, in
                            (vw.fwd ? 1 : 0) | (exact ? 2 : 0));
       const bool mv = lev == sc->move_level;
       if (mv) hipLaunchKernelGGL(ia::k_closest, dim3(1, E), dim3(ia::kWG), 0, s, recs, vw, ev);
-      // the window's extent over the live tiles: kWinGroups workgroups per
+      // the window's extent over the live tiles: 8 to 32 workgroups per
       // event (at most the part records the arena holds), one record each
-      const int32_t n_win = std::min(kWinGroups, L.n_part);
+      const int32_t n_win = std::min(std::max(kWinGroupsMin, std::min(kWinGroupsMax, kWinTotal / std::max(1, E))),
+                                     L.n_part);
       hipLaunchKernelGGL(ia::k_window_partial, dim3(n_win, E), dim3(ia::kWG), 0, s, par, sh, votes, sel, sel_v, part,
                          vw, ev, wg_max, live, bx, sc->wdrop, mv ? 1 : 0);
       ia::Bins5 nb;
